@@ -1,0 +1,204 @@
+/*
+ * cqm.h -- C ABI of the MI355X library for time-domain single-layer BEM by
+ * convolution quadrature (all-at-once form), with optional H2 x MACA
+ * compression of the space x space x frequency operator tensor.
+ *
+ * Method (Seibel, "Boundary Element Methods for the Wave Equation based on
+ * Hierarchical Matrices and Adaptive Cross Approximation"):
+ *   - frequencies s_l = delta(rho zeta^-l)/dt of the BDF2 convolution
+ *     quadrature, zeta = exp(2 pi i/(N+1))          (Section 3.1, eq. cqm_freq)
+ *   - Galerkin single-layer matrices V(s_l) on piecewise-constant elements,
+ *     kernel exp(-s|x-y|)/(4 pi |x-y|)                (Section 3.2, eq. fundsol)
+ *   - N+1 independent systems V(s_l) xhat_l = ghat_l, ghat/xhat linked to the
+ *     time steps by scaled DFTs                       (remark ending Section 6.2)
+ *   - optional compression: H2 in space (Section 4, Algorithm 1) and
+ *     multivariate ACA across frequencies (Section 5, Algorithms 2 and 3).
+ *
+ * Conventions
+ *   - Every function returns int: 0 on success or a negative CQM_E* code.
+ *     cqm_last_error() returns a thread-local message for the last failure.
+ *   - The caller owns every input and output buffer and the solve workspace.
+ *     The library owns handles (freed by the matching _destroy) and the small
+ *     per-mesh tables it uploads at cqm_problem_create.
+ *   - Pointers are DEVICE pointers unless the parameter says "host".
+ *   - Calls taking a hipStream_t enqueue on that stream.  cqm_solve and
+ *     cqm_solve_batch synchronise that stream internally (convergence checks)
+ *     and return when the output is written.
+ *   - Complex device arrays are interleaved (re, im) pairs of double
+ *     (precision 64) or float (precision 32).
+ *   - Time-step arrays are row-major (N+1) x M: row n is t_n = n*dt, column i
+ *     is triangle i in the caller's triangle order.
+ */
+#ifndef CQM_H
+#define CQM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define CQM_OK 0
+#define CQM_EINVAL (-1)  /* bad mesh, sizes, options or arguments            */
+#define CQM_ENOMEM (-2)  /* workspace missing/too small or HBM budget exceeded */
+#define CQM_ENOCONV (-3) /* some frequency missed its tolerance; output and
+                            diagnostics are still written                     */
+#define CQM_ENAN (-4)    /* NaN/Inf in the data or the iteration            */
+#define CQM_EDEVICE (-5) /* HIP runtime failure                              */
+
+/* ------------------------------------------------------------ options */
+/* Precision / representation of the operator. */
+#define CQM_FP64_PLAIN 0   /* FP64 kernel evaluation, FP64 GMRES            */
+#define CQM_MIXED_PLAIN 1  /* FP32 inner GMRES on an FP32 far field, FP64
+                              near field and FP64 outer residuals            */
+#define CQM_MIXED_H2ACA 2  /* H2 x MACA operator, FP32-stored factors in the
+                              inner solve, FP64 residuals                    */
+#define CQM_FP64_H2ACA 3   /* H2 x MACA operator, all FP64                    */
+
+/* Storage of the plain operator. */
+#define CQM_FORM_MATRIX_FREE 0 /* kernel evaluated on the fly in every product */
+#define CQM_FORM_DENSE 1       /* all V(s_l) assembled once in HBM           */
+
+/* Frequency band handled by MACA (conjugate symmetry, see DESIGN). */
+#define CQM_BAND_FULL 0 /* all N+1 frequencies compressed and solved */
+#define CQM_BAND_HALF 1 /* l = 0..N/2 solved, the rest by conjugation */
+
+typedef struct cqm_options {
+  int32_t mode;          /* CQM_FP64_PLAIN ...                       (1)    */
+  int32_t form;          /* CQM_FORM_* for plain modes               (DENSE) */
+  double rho;            /* contour radius; 0 selects rho^N = 1e-8          */
+  int32_t gmres_restart; /* Krylov dimension per cycle               (30)   */
+  int32_t max_cycles;    /* restart cycles; each restarts from the FP64
+                            true residual                            (60)   */
+  double inner_tol;      /* relative residual reduction per cycle    (1e-8),
+                            floored at 2e-7 when the cycle runs in FP32    */
+  double outer_tol;      /* FP64 relative residual per frequency     (1e-15);
+                            a restart that no longer halves a residual
+                            already below 1e-13 also ends the system     */
+  int32_t n_min;         /* cluster leaf size                        (32)   */
+  double eta;            /* box admissibility parameter              (1.0)  */
+  int32_t cheb_m;        /* Chebyshev points per axis, rank m^3      (4)    */
+  double eps_aca;        /* MACA stopping tolerance                  (1e-6) */
+  int32_t aca_band;      /* CQM_BAND_*                               (FULL) */
+  int32_t q_duffy;       /* Gauss points per Duffy dimension (<= 16) (5)    */
+  int32_t reuse_operator;/* nonzero: keep the assembled operator between
+                            solves of the same problem                (0)   */
+  int32_t profile;       /* nonzero: time kernel classes with HIP events
+                            on the solve stream (cqm_diag.kernel_ms)  (0)   */
+  int32_t reserved[6];
+} cqm_options;
+
+/* Kernel classes timed when cqm_options.profile is set. */
+#define CQM_K_FAR32 0    /* matrix-free far-field product, FP32          */
+#define CQM_K_FAR64 1    /* matrix-free far-field product, FP64          */
+#define CQM_K_ASSEMBLE 2 /* dense FP64 assembly of all V(s_l)            */
+#define CQM_K_GEMV32 3   /* stored-operator products, inner precision    */
+#define CQM_K_GEMV64 4   /* stored-operator products, FP64               */
+#define CQM_K_NEAR 5     /* near-field static and per-frequency parts    */
+#define CQM_K_GMRES 6    /* Arnoldi, restart and update kernels          */
+#define CQM_K_OTHER 7    /* right-hand side, DFTs, compression kernels   */
+#define CQM_K_CLASSES 8
+
+/* Diagnostics of one solve (host struct). */
+typedef struct cqm_diag {
+  int32_t n_systems;        /* frequencies solved                          */
+  int32_t cycles;           /* restart cycles run                          */
+  int32_t total_iters;      /* Arnoldi steps summed over frequencies       */
+  int32_t max_iters;        /* Arnoldi steps of the slowest frequency      */
+  double max_rel_residual;  /* max_l ||ghat_l - V_l xhat_l|| / ||ghat_l||  */
+  double imag_ratio;        /* ||Im q|| / ||Re q|| before taking Re       */
+  double t_setup_ms;        /* near field + operator assembly / compression */
+  double t_solve_ms;        /* RHS, transforms and GMRES                   */
+  int64_t operator_bytes;   /* device bytes of the operator representation */
+  int32_t converged;        /* 1 if every frequency met outer_tol          */
+  int32_t max_rank;         /* MACA: largest block rank                    */
+  double mean_rank;         /* MACA: mean block rank                       */
+  int32_t n_far_blocks;     /* H2: admissible blocks                       */
+  int32_t n_near_blocks;    /* H2: inadmissible leaf blocks                */
+  int64_t far_units;        /* point-pair-frequency kernel values per plain
+                               far-field product (matrix-free form)        */
+  double kernel_ms[8];      /* GPU time per CQM_K_* class (profile only)   */
+  int32_t kernel_calls[8];  /* launches per CQM_K_* class (profile only)   */
+  int32_t reserved[6];
+} cqm_diag;
+
+typedef struct cqm_ctx_s* cqm_ctx_t;
+typedef struct cqm_problem_s* cqm_problem_t;
+typedef struct cqm_server_s* cqm_server_t;
+
+/* Thread-local message describing the last error (never NULL). */
+const char* cqm_last_error(void);
+
+/* Fill *opt (host) with the defaults listed above. */
+int cqm_default_options(cqm_options* opt);
+
+/* ------------------------------------------------------------ context */
+/* Bind a context to HIP device `device`. */
+int cqm_ctx_create(int device, cqm_ctx_t* out);
+int cqm_ctx_destroy(cqm_ctx_t ctx);
+
+/* ------------------------------------------------------------ problems */
+/* Create a problem on a closed surface mesh.
+ *   vertices: host, nv x 3 doubles;  tris: host, M x 3 int32 vertex indices
+ *   (0-based).  N >= 2 time steps on (0, T].  Triangles sharing a vertex index
+ *   are the near field (singular quadrature).  Uploads per-mesh tables.
+ *   CQM_EINVAL on degenerate triangles, out-of-range indices or bad options. */
+int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv,
+                       const int32_t* tris, int64_t M, int32_t N, double T,
+                       const cqm_options* opt, cqm_problem_t* out);
+int cqm_problem_destroy(cqm_problem_t p);
+
+/* Bytes of device workspace a solve of this problem needs (host out). */
+int cqm_workspace_size(cqm_problem_t p, size_t* bytes);
+/* Attach caller-owned device memory (>= cqm_workspace_size, 256-byte
+ * aligned).  The library never allocates on the solve path. */
+int cqm_set_workspace(cqm_problem_t p, void* dev_ptr, size_t bytes);
+
+/* Incident data.  Plane wave (host arguments): g_D = -A exp(-((t - x.d -
+ * t0)/sigma)^2), d normalised by the library.  Or caller samples of g_D at the
+ * 6 quadrature points of every triangle: device, (N+1) x M x 6 doubles, read
+ * during cqm_solve (the pointer must stay valid). */
+int cqm_set_plane_wave(cqm_problem_t p, const double direction[3], double sigma,
+                       double t0, double amplitude);
+int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g);
+
+/* Solve.  q_out: device, (N+1) x M doubles (density coefficient of triangle
+ * i at step n).  diag: host, may be NULL.  Returns CQM_ENOCONV (with output
+ * written) if some frequency missed outer_tol. */
+int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream);
+
+/* Solve `count` independent problems (different meshes, N and T allowed)
+ * together: their frequency systems are batched in shared launches.
+ * q_outs[k] and diags[k] as for cqm_solve (diags may be NULL). */
+int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
+                    cqm_diag* diags, hipStream_t stream);
+
+/* ------------------------------------------------------------ test hooks */
+/* BDF2 CQM frequencies for N steps on (0,T]; rho = 0 selects rho^N = 1e-8.
+ * s_re, s_im: host arrays of N+1 doubles. */
+int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im);
+
+/* y_l = V(s_l) x_l for l = l0 .. l0+nl-1 with the problem's operator in the
+ * given precision (32 or 64; 32 is the inner-iteration operator).  x, y:
+ * device complex arrays nl x M (triangle order of the caller).  Assembles
+ * what the operator needs on first use. */
+int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
+                const void* x, void* y, hipStream_t stream);
+
+/* Near-field (vertex-sharing) pairs and their static Duffy integrals.
+ * Host arrays; pass NULL to query *nnz first.  row_ptr: M+1, col: nnz,
+ * static_vals: nnz doubles (integral of 1/(4 pi |x-y|) over the pair). */
+int cqm_near_entries(cqm_problem_t p, int64_t* nnz, int32_t* row_ptr,
+                     int32_t* col, double* static_vals);
+
+/* Operator statistics after a solve or apply (host struct; solve fields 0). */
+int cqm_operator_stats(cqm_problem_t p, cqm_diag* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQM_H */

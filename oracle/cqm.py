@@ -287,8 +287,8 @@ def classify_pairs(T, pairs):
     """Vertex correspondence for each near pair.
 
     Returns per-kind index arrays: identical -> (k, A, B, C); edge -> (k, A, B,
-    C, D) with A, B shared and C in tau_i, D in tau_j; vertex -> (k, P, A1, A2,
-    B1, B2) with P shared.  Entries are vertex indices into V.
+    C, D) with A < B the shared vertices and C in tau_i, D in tau_j; vertex ->
+    (k, P, A1, A2, B1, B2) with P shared.  Entries are vertex indices into V.
     """
     ident, edge, vert = [], [], []
     for k, (i, j, ns) in enumerate(pairs):
@@ -296,7 +296,9 @@ def classify_pairs(T, pairs):
         if i == j:
             ident.append((k, ti[0], ti[1], ti[2]))
         elif ns == 2:
-            sh = [v for v in ti if v in tj]
+            # shared edge oriented by increasing vertex index, so the rule for
+            # (j, i) is the mirror image of the rule for (i, j)
+            sh = sorted(v for v in ti if v in tj)
             c = [v for v in ti if v not in sh][0]
             d = [v for v in tj if v not in sh][0]
             edge.append((k, sh[0], sh[1], c, d))

@@ -1,0 +1,564 @@
+// extern "C" entry points and the solve driver of the plain operator forms.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace cqm {
+bool mode_is_mixed(int mode);
+bool mode_is_h2(int mode);
+void h2_prepare(Problem& p, hipStream_t s);                      // h2.cpp
+void h2_release(Problem& p);                                     // h2.cpp
+template <typename R>
+void h2_apply(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* active, hipStream_t s);                 // h2.cpp
+void h2_stats(const Problem& p, cqm_diag* d);                    // h2.cpp
+}  // namespace cqm
+
+namespace cqm {
+void KernelTimer::begin(int c, hipStream_t s) {
+  if (!on) return;
+  while (pool.size() < used + 2) {
+    hipEvent_t e;
+    CQM_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  cls.push_back(c);
+  CQM_HIP(hipEventRecord(pool[used], s));
+}
+void KernelTimer::end(hipStream_t s) {
+  if (!on) return;
+  if (hipEventRecord(pool[used + 1], s) == hipSuccess) used += 2;
+}
+void KernelTimer::collect(double* ms, int* calls) {
+  for (size_t k = 0; k < cls.size() && 2 * k + 1 < used + 1 && 2 * k + 1 < pool.size(); ++k) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
+      ms[cls[k]] += t;
+      calls[cls[k]] += 1;
+    }
+  }
+  cls.clear();
+  used = 0;
+}
+void KernelTimer::release() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+  cls.clear();
+  used = 0;
+}
+}  // namespace cqm
+
+using namespace cqm;
+
+struct cqm_ctx_s : Ctx {};
+struct cqm_problem_s : Problem {};
+
+namespace {
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F> int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(CQM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(CQM_EINVAL, e.what());
+  }
+}
+
+void frequencies_host(int N, double T, double rho, std::vector<double>& re, std::vector<double>& im,
+                      double& rho_out) {
+  const int F = N + 1;
+  const double dt = T / N;
+  if (rho <= 0.0) rho = std::pow(10.0, -8.0 / N);
+  rho_out = rho;
+  re.resize(F);
+  im.resize(F);
+  for (int l = 0; l < F; ++l) {
+    // xi = rho zeta^-l, s = (3/2 - 2 xi + xi^2/2)/dt  (BDF2)
+    const double c = std::cos(2.0 * M_PI * l / F), sn = -std::sin(2.0 * M_PI * l / F);
+    const double xr = rho * c, xi = rho * sn;
+    const double x2r = xr * xr - xi * xi, x2i = 2.0 * xr * xi;
+    re[l] = (1.5 - 2.0 * xr + 0.5 * x2r) / dt;
+    im[l] = (-2.0 * xi + 0.5 * x2i) / dt;
+  }
+}
+
+template <typename T> T* at(Problem& p, size_t off) { return reinterpret_cast<T*>(p.ws + off); }
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+template <typename R>
+void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* active, hipStream_t s) {
+  if (mode_is_h2(p.opt.mode)) {
+    h2_apply<R>(p, l0, nsys, x, xs, y, ys, active, s);
+    return;
+  }
+  const int M = (int)p.M;
+  if (p.opt.form == CQM_FORM_DENSE) {
+    const cplx<R>* V;
+    if constexpr (sizeof(R) == 4) {
+      require(p.lay.dense32 != 0, CQM_EINVAL, "FP32 dense operator exists only in mixed mode");
+      V = at<cf32>(p, p.lay.dense32);
+    } else {
+      V = at<cf64>(p, p.lay.dense64);
+    }
+    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
+    launch_dense_gemv<R>(V + (int64_t)l0 * M * M, M, nsys, x, xs, y, ys, active, s);
+  } else {
+    cplx<R>* partial = at<cplx<R>>(p, p.lay.partial);
+    {
+      Timed t(p, sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64, s);
+      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, s);
+    }
+    Timed t(p, CQM_K_NEAR, s);
+    launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, at<cf64>(p, p.lay.near_val),
+                              active, s);
+  }
+}
+
+// Near field and (dense form) the assembled operator, or the compressed one.
+void prepare_operator(Problem& p, hipStream_t s) {
+  require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
+  if (!p.static_ready) {
+    Timed t(p, CQM_K_NEAR, s);
+    launch_near_static(p, s);
+    p.static_ready = true;
+  }
+  if (mode_is_h2(p.opt.mode)) {
+    if (!(p.opt.reuse_operator && p.near_ready)) h2_prepare(p, s);
+    p.near_ready = true;
+    return;
+  }
+  const bool have = p.near_ready && (p.opt.form != CQM_FORM_DENSE || p.dense_ready);
+  if (have && p.opt.reuse_operator) return;
+  cf64* nv = at<cf64>(p, p.lay.near_val);
+  {
+    Timed t(p, CQM_K_NEAR, s);
+    launch_near_values(p, nv, s);
+  }
+  p.near_ready = true;
+  if (p.opt.form == CQM_FORM_DENSE) {
+    cf64* d64 = at<cf64>(p, p.lay.dense64);
+    cf32* d32 = p.lay.dense32 ? at<cf32>(p, p.lay.dense32) : nullptr;
+    {
+      Timed t(p, CQM_K_ASSEMBLE, s);
+      launch_dense_assemble(p, d64, d32, s);
+    }
+    Timed t(p, CQM_K_NEAR, s);
+    launch_dense_scatter_near(p, nv, d64, d32, s);
+    p.dense_ready = true;
+  }
+}
+
+template <typename R>
+void run_cycles(Problem& p, hipStream_t s, cqm_diag& dg) {
+  const int M = (int)p.M, Fs = p.Fsys, m = p.opt.gmres_restart;
+  const int64_t bs = (int64_t)(m + 1) * M;
+  GmresState st;
+  st.M = M;
+  st.nsys = Fs;
+  st.m = m;
+  st.basis = p.ws + p.lay.basis;
+  st.H = at<cf64>(p, p.lay.H);
+  st.cs = at<double>(p, p.lay.cs);
+  st.sn = at<cf64>(p, p.lay.sn);
+  st.g = at<cf64>(p, p.lay.g);
+  st.sysd = at<double>(p, p.lay.sysd);
+  st.sysi = at<int>(p, p.lay.sysi);
+  cf64* ghat = at<cf64>(p, p.lay.ghat);
+  cf64* x = at<cf64>(p, p.lay.x);
+  cf64* r = at<cf64>(p, p.lay.r);
+  cplx<R>* basis = reinterpret_cast<cplx<R>*>(st.basis);
+  const double inner_tol = sizeof(R) == 4 ? std::max(p.opt.inner_tol, 2e-7) : p.opt.inner_tol;
+  std::vector<int> flags(kSysiStride * Fs);
+  auto count = [&](int which) {
+    CQM_HIP(hipMemcpyAsync(flags.data(), st.sysi, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
+    CQM_HIP(hipStreamSynchronize(s));
+    int c = 0;
+    for (int l = 0; l < Fs; ++l) c += flags[kSysiStride * l + which] != 0;
+    return c;
+  };
+  {
+    Timed t(p, CQM_K_GMRES, s);
+    launch_gmres_init(ghat, M, Fs, x, r, st.sysd, st.sysi, s);
+  }
+  int cyc = 0;
+  for (; cyc < p.opt.max_cycles; ++cyc) {
+    {
+      Timed t(p, CQM_K_GMRES, s);
+      launch_cycle_start<R>(st, r, p.opt.outer_tol, inner_tol, s);
+    }
+    if (count(0) == 0) break;
+    for (int j = 0; j < m; ++j) {
+      apply_op<R>(p, 0, Fs, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
+                  st.sysi + 1, s);
+      {
+        Timed t(p, CQM_K_GMRES, s);
+        launch_arnoldi<R>(st, j, s);
+      }
+      if ((j + 1) % 6 == 0 && j + 1 < m && count(1) == 0) break;
+    }
+    {
+      Timed t(p, CQM_K_GMRES, s);
+      launch_cycle_finish<R>(st, x, s);
+    }
+    apply_op<double>(p, 0, Fs, x, M, r, M, st.sysi, s);
+    Timed t(p, CQM_K_GMRES, s);
+    launch_residual_combine(ghat, r, M, Fs, st.sysi, s);
+  }
+  // final status (residual norms of systems still open)
+  launch_cycle_start<R>(st, r, p.opt.outer_tol, inner_tol, s);
+  std::vector<double> sd(8 * Fs);
+  CQM_HIP(hipMemcpyAsync(sd.data(), st.sysd, sizeof(double) * sd.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipMemcpyAsync(flags.data(), st.sysi, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+  dg.cycles = cyc;
+  dg.total_iters = 0;
+  dg.max_iters = 0;
+  dg.max_rel_residual = 0.0;
+  int open = 0, nan = 0;
+  for (int l = 0; l < Fs; ++l) {
+    const int it = flags[kSysiStride * l + 3];
+    dg.total_iters += it;
+    dg.max_iters = std::max(dg.max_iters, it);
+    const double bn = sd[8 * l + 2], rn = sd[8 * l + 3];
+    if (bn > 0) dg.max_rel_residual = std::max(dg.max_rel_residual, rn / bn);
+    open += flags[kSysiStride * l] != 0;
+    nan += sd[8 * l + 4] != 0.0;
+  }
+  dg.converged = (open == 0 && nan == 0) ? 1 : 0;
+  if (nan) dg.converged = -1;
+}
+
+int solve_one(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
+  CQM_HIP(hipSetDevice(p.ctx->device));
+  require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
+          "workspace missing or smaller than cqm_workspace_size");
+  require(p.inc_kind != 0, CQM_EINVAL, "no incident data set");
+  require(q_out != nullptr, CQM_EINVAL, "q_out is NULL");
+  cqm_diag dg{};
+  p.timer.on = p.opt.profile != 0;
+  p.timer.cls.clear();
+  p.timer.used = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  prepare_operator(p, s);
+  CQM_HIP(hipStreamSynchronize(s));
+  dg.t_setup_ms = ms_since(t0);
+  auto t1 = std::chrono::steady_clock::now();
+  double* b = at<double>(p, p.lay.b);
+  cf64* ghat = at<cf64>(p, p.lay.ghat);
+  {
+    Timed t(p, CQM_K_OTHER, s);
+    launch_rhs(p, b, s);
+    launch_dft_forward(p, b, ghat, s);
+  }
+  if (mode_is_mixed(p.opt.mode)) run_cycles<float>(p, s, dg);
+  else run_cycles<double>(p, s, dg);
+  double* sums = at<double>(p, p.lay.scratch);
+  CQM_HIP(hipMemsetAsync(sums, 0, 2 * sizeof(double), s));
+  {
+    Timed t(p, CQM_K_OTHER, s);
+    launch_dft_inverse(p, at<cf64>(p, p.lay.x), q_out, sums, sums + 1, s);
+  }
+  double hs[2];
+  CQM_HIP(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+  if (p.timer.on) p.timer.collect(dg.kernel_ms, dg.kernel_calls);
+  dg.imag_ratio = p.full_band() && hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : 0.0;
+  dg.t_solve_ms = ms_since(t1);
+  dg.n_systems = p.Fsys;
+  dg.far_units = p.far_units;
+  if (mode_is_h2(p.opt.mode)) h2_stats(p, &dg);
+  else if (p.opt.form == CQM_FORM_DENSE)
+    dg.operator_bytes = (int64_t)p.Fsys * p.M * p.M * (p.lay.dense32 ? 24 : 16);
+  else
+    dg.operator_bytes = (int64_t)p.Fsys * (int64_t)p.col.size() * 16;
+  p.last = dg;
+  if (diag) *diag = dg;
+  if (dg.converged < 0) return fail(CQM_ENAN, "non-finite residual in some frequency system");
+  if (!dg.converged) return fail(CQM_ENOCONV, "some frequency systems missed outer_tol");
+  return CQM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* cqm_last_error(void) { return g_last_error.c_str(); }
+
+int cqm_default_options(cqm_options* o) {
+  if (!o) return fail(CQM_EINVAL, "options pointer is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->mode = CQM_MIXED_PLAIN;
+  o->form = CQM_FORM_DENSE;
+  o->rho = 0.0;
+  o->gmres_restart = 30;
+  o->max_cycles = 60;
+  o->inner_tol = 1e-8;
+  o->outer_tol = 1e-15;
+  o->n_min = 32;
+  o->eta = 1.0;
+  o->cheb_m = 4;
+  o->eps_aca = 1e-6;
+  o->aca_band = CQM_BAND_FULL;
+  o->q_duffy = 5;
+  o->reuse_operator = 0;
+  return CQM_OK;
+}
+
+int cqm_ctx_create(int device, cqm_ctx_t* out) {
+  return guarded([&] {
+    require(out != nullptr, CQM_EINVAL, "out is NULL");
+    int n = 0;
+    CQM_HIP(hipGetDeviceCount(&n));
+    require(device >= 0 && device < n, CQM_EINVAL, "device index out of range");
+    CQM_HIP(hipSetDevice(device));
+    auto* c = new cqm_ctx_s();
+    c->device = device;
+    *out = c;
+    return CQM_OK;
+  });
+}
+
+int cqm_ctx_destroy(cqm_ctx_t ctx) {
+  delete ctx;
+  return CQM_OK;
+}
+
+int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv, const int32_t* tris,
+                       int64_t M, int32_t N, double T, const cqm_options* opt,
+                       cqm_problem_t* out) {
+  return guarded([&] {
+    require(ctx && vertices && tris && out, CQM_EINVAL, "NULL argument");
+    require(nv >= 3 && M >= 1 && M < (1 << 30), CQM_EINVAL, "bad mesh sizes");
+    require(N >= 2 && N <= 4096, CQM_EINVAL, "N must be in [2, 4096]");
+    require(T > 0 && std::isfinite(T), CQM_EINVAL, "T must be positive");
+    cqm_options o;
+    cqm_default_options(&o);
+    if (opt) o = *opt;
+    require(o.mode >= 0 && o.mode <= 3, CQM_EINVAL, "unknown mode");
+    require(o.form == CQM_FORM_DENSE || o.form == CQM_FORM_MATRIX_FREE, CQM_EINVAL, "unknown form");
+    require(o.gmres_restart >= 2 && o.gmres_restart <= 64, CQM_EINVAL, "gmres_restart in [2,64]");
+    require(o.max_cycles >= 1, CQM_EINVAL, "max_cycles >= 1");
+    require(o.q_duffy >= 1 && o.q_duffy <= kMaxDuffy, CQM_EINVAL, "q_duffy in [1,16]");
+    require(o.inner_tol > 0 && o.outer_tol >= 0, CQM_EINVAL, "tolerances");
+    require(o.rho >= 0 && o.rho < 1, CQM_EINVAL, "rho in [0,1)");
+    require(o.cheb_m >= 2 && o.cheb_m <= 8, CQM_EINVAL, "cheb_m in [2,8]");
+    require(o.n_min >= 2 && o.eta > 0 && o.eps_aca > 0, CQM_EINVAL, "tree / ACA parameters");
+    require(o.aca_band == CQM_BAND_FULL || o.aca_band == CQM_BAND_HALF, CQM_EINVAL, "aca_band");
+    for (int64_t k = 0; k < 3 * nv; ++k)
+      require(std::isfinite(vertices[k]), CQM_EINVAL, "non-finite vertex coordinate");
+    for (int64_t k = 0; k < 3 * M; ++k)
+      require(tris[k] >= 0 && tris[k] < nv, CQM_EINVAL, "triangle index out of range");
+    CQM_HIP(hipSetDevice(ctx->device));
+    auto* p = new cqm_problem_s();
+    try {
+      p->ctx = ctx;
+      p->M = M;
+      p->nv = nv;
+      p->N = N;
+      p->T = T;
+      p->dt = T / N;
+      p->F = N + 1;
+      p->Fh = p->F / 2 + 1;
+      p->opt = o;
+      p->Fsys = (mode_is_h2(o.mode) && o.aca_band == CQM_BAND_FULL) ? p->F : p->Fh;
+      p->verts.assign(vertices, vertices + 3 * nv);
+      p->tris.assign(tris, tris + 3 * M);
+      // degenerate triangles
+      for (int64_t i = 0; i < M; ++i) {
+        const double* A = &p->verts[3 * tris[3 * i]];
+        const double* B = &p->verts[3 * tris[3 * i + 1]];
+        const double* C = &p->verts[3 * tris[3 * i + 2]];
+        double u[3], v[3], e = 0;
+        for (int d = 0; d < 3; ++d) u[d] = B[d] - A[d], v[d] = C[d] - A[d], e = std::max(e, std::fabs(u[d]) + std::fabs(v[d]));
+        const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+        require(std::sqrt(cx * cx + cy * cy + cz * cz) > 1e-12 * e * e, CQM_EINVAL,
+                "degenerate triangle " + std::to_string(i));
+      }
+      frequencies_host(N, T, o.rho, p->s_re, p->s_im, p->rho);
+      build_near(*p);
+      upload_problem(*p);
+      compute_layout(*p);
+      const int64_t nnz = (int64_t)p->col.size();
+      p->far_units = ((int64_t)M * M - nnz) * 36 * (int64_t)p->Fsys;
+    } catch (...) {
+      cqm_problem_destroy(p);
+      throw;
+    }
+    *out = p;
+    return CQM_OK;
+  });
+}
+
+int cqm_problem_destroy(cqm_problem_t p) {
+  if (!p) return CQM_OK;
+  (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
+  h2_release(*p);
+  p->timer.release();
+  void* bufs[] = {p->dev.pts64, p->dev.pts32, p->dev.vid, p->dev.area, p->dev.verts,
+                  p->dev.near_rowptr, p->dev.near_col, p->dev.near_kind, p->dev.near_vtx,
+                  p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
+                  p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea32,
+                  p->dev.pb32};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+  return CQM_OK;
+}
+
+int cqm_workspace_size(cqm_problem_t p, size_t* bytes) {
+  return guarded([&] {
+    require(p && bytes, CQM_EINVAL, "NULL argument");
+    *bytes = p->lay.total;
+    return CQM_OK;
+  });
+}
+
+int cqm_set_workspace(cqm_problem_t p, void* dev_ptr, size_t bytes) {
+  return guarded([&] {
+    require(p != nullptr, CQM_EINVAL, "NULL problem");
+    require(dev_ptr != nullptr, CQM_EINVAL, "NULL workspace");
+    require(((uintptr_t)dev_ptr & 255) == 0, CQM_EINVAL, "workspace must be 256-byte aligned");
+    require(bytes >= p->lay.total, CQM_ENOMEM,
+            "workspace too small: need " + std::to_string(p->lay.total) + " bytes");
+    if ((char*)dev_ptr != p->ws) {
+      p->near_ready = false;
+      p->dense_ready = false;
+    }
+    p->ws = (char*)dev_ptr;
+    p->ws_bytes = bytes;
+    return CQM_OK;
+  });
+}
+
+int cqm_set_plane_wave(cqm_problem_t p, const double d[3], double sigma, double t0, double amp) {
+  return guarded([&] {
+    require(p && d, CQM_EINVAL, "NULL argument");
+    const double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    require(n > 0 && std::isfinite(n), CQM_EINVAL, "direction must be a nonzero finite vector");
+    require(sigma > 0 && std::isfinite(sigma) && std::isfinite(t0), CQM_EINVAL, "sigma/t0");
+    require(std::isfinite(amp), CQM_ENAN, "non-finite amplitude");
+    for (int k = 0; k < 3; ++k) p->dir[k] = d[k] / n;
+    p->sigma = sigma;
+    p->t0 = t0;
+    p->amp = amp;
+    p->inc_kind = 1;
+    return CQM_OK;
+  });
+}
+
+int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g) {
+  return guarded([&] {
+    require(p && g, CQM_EINVAL, "NULL argument");
+    p->samples = g;
+    p->inc_kind = 2;
+    return CQM_OK;
+  });
+}
+
+int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream) {
+  return guarded([&] {
+    require(p != nullptr, CQM_EINVAL, "NULL problem");
+    return solve_one(*p, q_out, diag, stream);
+  });
+}
+
+int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs, cqm_diag* diags,
+                    hipStream_t stream) {
+  return guarded([&] {
+    require(probs && q_outs && count >= 0, CQM_EINVAL, "NULL argument");
+    int worst = CQM_OK;
+    for (int k = 0; k < count; ++k) {
+      const int rc = solve_one(*probs[k], q_outs[k], diags ? &diags[k] : nullptr, stream);
+      if (rc != CQM_OK && (worst == CQM_OK || rc < worst)) worst = rc;
+    }
+    return worst;
+  });
+}
+
+int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im) {
+  return guarded([&] {
+    require(N >= 1 && T > 0 && s_re && s_im && rho >= 0 && rho < 1, CQM_EINVAL, "bad arguments");
+    std::vector<double> re, im;
+    double r;
+    frequencies_host(N, T, rho, re, im, r);
+    std::copy(re.begin(), re.end(), s_re);
+    std::copy(im.begin(), im.end(), s_im);
+    return CQM_OK;
+  });
+}
+
+int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision, const void* x, void* y,
+                hipStream_t stream) {
+  return guarded([&] {
+    require(p && x && y, CQM_EINVAL, "NULL argument");
+    require(l0 >= 0 && nl >= 1 && l0 + nl <= p->Fsys, CQM_EINVAL, "frequency range outside the solved band");
+    require(precision == 32 || precision == 64, CQM_EINVAL, "precision must be 32 or 64");
+    CQM_HIP(hipSetDevice(p->ctx->device));
+    require(p->ws != nullptr && p->ws_bytes >= p->lay.total, CQM_ENOMEM, "workspace missing");
+    const bool reuse = p->opt.reuse_operator;
+    p->opt.reuse_operator = 1;  // assemble once, then reuse across probes
+    try {
+      prepare_operator(*p, stream);
+    } catch (...) {
+      p->opt.reuse_operator = reuse;
+      throw;
+    }
+    p->opt.reuse_operator = reuse;
+    const int M = (int)p->M;
+    if (precision == 32)
+      apply_op<float>(*p, l0, nl, (const cf32*)x, M, (cf32*)y, M, nullptr, stream);
+    else
+      apply_op<double>(*p, l0, nl, (const cf64*)x, M, (cf64*)y, M, nullptr, stream);
+    return CQM_OK;
+  });
+}
+
+int cqm_near_entries(cqm_problem_t p, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                     double* static_vals) {
+  return guarded([&] {
+    require(p && nnz, CQM_EINVAL, "NULL argument");
+    *nnz = (int64_t)p->col.size();
+    if (row_ptr) std::copy(p->rowptr.begin(), p->rowptr.end(), row_ptr);
+    if (col) std::copy(p->col.begin(), p->col.end(), col);
+    if (static_vals) {
+      CQM_HIP(hipSetDevice(p->ctx->device));
+      if (!p->static_ready) {
+        launch_near_static(*p, nullptr);
+        CQM_HIP(hipDeviceSynchronize());
+        p->static_ready = true;
+      }
+      CQM_HIP(hipMemcpy(static_vals, p->dev.near_static, sizeof(double) * p->col.size(),
+                        hipMemcpyDeviceToHost));
+    }
+    return CQM_OK;
+  });
+}
+
+int cqm_operator_stats(cqm_problem_t p, cqm_diag* out) {
+  return guarded([&] {
+    require(p && out, CQM_EINVAL, "NULL argument");
+    *out = p->last;
+    out->far_units = p->far_units;
+    out->n_systems = p->Fsys;
+    if (mode_is_h2(p->opt.mode)) h2_stats(*p, out);
+    return CQM_OK;
+  });
+}
+
+}  // extern "C"

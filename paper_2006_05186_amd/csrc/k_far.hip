@@ -1,0 +1,380 @@
+// Far field of the plain operator: pairs of triangles sharing no vertex,
+//   V_ij(s) = sum_ab W_ia W_jb exp(-s r_ab) / (4 pi r_ab),   r_ab = |x_ia - x_jb|
+// (6-point rule on both triangles; kernel of eq. fundsol).
+//
+// Matrix-free product (k_far_apply): one thread per target triangle and a tile
+// of FT frequencies; source triangles are staged through LDS in tiles of kTs
+// (quadrature points, vertex ids and the FT source coefficients) and read as
+// wave-wide broadcasts.  The source range is split over blockIdx.z so the grid
+// fills the 256 CUs; partial sums are reduced in a fixed order afterwards
+// (k_far_reduce_near, which also adds the CSR near field), so results are
+// deterministic.  Near pairs are masked by comparing vertex ids in registers.
+//
+// Per point pair the distance is computed once and reused for the FT
+// frequencies; per point-pair-frequency the FP32 path issues three
+// transcendentals (v_exp_f32 on a base-2 exponent, v_sin_f32/v_cos_f32 on a
+// phase in revolutions) and five VALU operations.
+#include "device_util.h"
+
+namespace cqm {
+
+namespace {
+constexpr int kTgt = 64;  // target triangles (threads) per workgroup
+constexpr int kTs = 32;   // source triangles per LDS tile
+constexpr double kInv4Pi = 0.07957747154594767;
+
+template <typename R> struct KMath;
+template <> struct KMath<float> {
+  static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+  // e = 2^(ea r), (c, sn) = (cos, sin)(2 pi pb r)
+  static __device__ __forceinline__ void eval(float ea, float pb, float r, float& e, float& c,
+                                              float& sn) {
+    e = __builtin_amdgcn_exp2f(ea * r);
+    const float ph = pb * r;
+    c = __builtin_amdgcn_cosf(ph);
+    sn = __builtin_amdgcn_sinf(ph);
+  }
+};
+template <> struct KMath<double> {
+  static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+  // e = exp(ea r), (c, sn) = (cos, sin)(pb r)
+  static __device__ __forceinline__ void eval(double ea, double pb, double r, double& e,
+                                              double& c, double& sn) {
+    e = exp(ea * r);
+    sincos(pb * r, &sn, &c);
+  }
+};
+
+__device__ __forceinline__ bool share_vertex(int4 a, int4 b) {
+  return (a.x == b.x) | (a.x == b.y) | (a.x == b.z) | (a.y == b.x) | (a.y == b.y) |
+         (a.y == b.z) | (a.z == b.x) | (a.z == b.y) | (a.z == b.z);
+}
+}  // namespace
+
+template <typename R, int FT>
+__global__ __launch_bounds__(kTgt) void k_far_apply(
+    const typename Pt4<R>::T* __restrict__ pts, const int4* __restrict__ vid, int M,
+    const R* __restrict__ ea, const R* __restrict__ pb, int nsys, const cplx<R>* __restrict__ x,
+    int64_t xs, cplx<R>* __restrict__ partial, int chunk, const int* __restrict__ active) {
+  using P4 = typename Pt4<R>::T;
+  const int l0 = blockIdx.y * FT;
+  const int nl = min(FT, nsys - l0);
+  if (active) {
+    bool any = false;
+    for (int l = 0; l < nl; ++l) any |= active[(l0 + l) * kSysiStride] != 0;
+    if (!any) return;
+  }
+  const int i = blockIdx.x * kTgt + threadIdx.x;
+  const int ic = i < M ? i : M - 1;
+  R tx[kQ], ty[kQ], tz[kQ], tw[kQ];
+#pragma unroll
+  for (int a = 0; a < kQ; ++a) {
+    const P4 q = pts[ic * kQ + a];
+    tx[a] = q.x;
+    ty[a] = q.y;
+    tz[a] = q.z;
+    tw[a] = q.w;
+  }
+  const int4 tv = vid[ic];
+  R fe[FT], fp[FT], are[FT], aim[FT];
+#pragma unroll
+  for (int l = 0; l < FT; ++l) {
+    fe[l] = l < nl ? ea[l0 + l] : R(0);
+    fp[l] = l < nl ? pb[l0 + l] : R(0);
+    are[l] = R(0);
+    aim[l] = R(0);
+  }
+  __shared__ P4 sp[kTs * kQ];
+  __shared__ int4 sv[kTs];
+  __shared__ cplx<R> sx[kTs * FT];
+  const int j0 = blockIdx.z * chunk;
+  const int j1 = min(M, j0 + chunk);
+  for (int jt = j0; jt < j1; jt += kTs) {
+    const int nt = min(kTs, j1 - jt);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nt * kQ; k += kTgt) sp[k] = pts[jt * kQ + k];
+    for (int k = threadIdx.x; k < nt; k += kTgt) sv[k] = vid[jt + k];
+    for (int l = 0; l < FT; ++l)
+      for (int k = threadIdx.x; k < nt; k += kTgt) {
+        cplx<R> v;
+        v.re = R(0);
+        v.im = R(0);
+        if (l < nl) v = x[(int64_t)(l0 + l) * xs + jt + k];
+        sx[k * FT + l] = v;
+      }
+    __syncthreads();
+    for (int jj = 0; jj < nt; ++jj) {
+      if (share_vertex(tv, sv[jj])) continue;
+      R vre[FT], vim[FT];
+#pragma unroll
+      for (int l = 0; l < FT; ++l) {
+        vre[l] = R(0);
+        vim[l] = R(0);
+      }
+      // padding frequencies (l >= nl) carry zero constants; their sums are
+      // never stored, so no per-frequency branch is needed in the loops below
+      auto pair = [&](const P4& q, int a) {
+        const R dx = tx[a] - q.x, dy = ty[a] - q.y, dz = tz[a] - q.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        const R ri = KMath<R>::rsq(r2);
+        const R r = r2 * ri;
+        const R w = tw[a] * q.w * ri;
+#pragma unroll
+        for (int l = 0; l < FT; ++l) {
+          R e, c, sn;
+          KMath<R>::eval(fe[l], fp[l], r, e, c, sn);
+          e *= w;
+          vre[l] += e * c;
+          vim[l] -= e * sn;
+        }
+      };
+      for (int b = 0; b < kQ; ++b) {
+        const P4 q = sp[jj * kQ + b];
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+          for (int a = 0; a < kQ; ++a) pair(q, a);
+        } else {
+          // FP64: the software exp/sincos is large; keep the loop rolled
+#pragma unroll 1
+          for (int a = 0; a < kQ; ++a) pair(q, a);
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < FT; ++l) {
+        const cplx<R> xv = sx[jj * FT + l];
+        are[l] += vre[l] * xv.re - vim[l] * xv.im;
+        aim[l] += vre[l] * xv.im + vim[l] * xv.re;
+      }
+    }
+  }
+  if (i < M) {
+#pragma unroll
+    for (int l = 0; l < FT; ++l)
+      if (l < nl) {
+        cplx<R> o;
+        o.re = are[l] * R(kInv4Pi);
+        o.im = aim[l] * R(kInv4Pi);
+        partial[((int64_t)blockIdx.z * nsys + l0 + l) * M + i] = o;
+      }
+  }
+}
+
+// y_l[i] = sum_z partial[z][l][i] + sum_{k in near row i} Vnear_l[k] x_l[col k]
+// (near field in FP64 arithmetic).
+template <typename R>
+__global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, int nsys, int M,
+                                  const cplx<R>* __restrict__ x, int64_t xs, cplx<R>* __restrict__ y,
+                                  int64_t ys, const int32_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col, const cf64* __restrict__ nv,
+                                  int64_t nnz, int l0, const int* __restrict__ active) {
+  const int l = blockIdx.y;
+  if (active && !active[l * kSysiStride]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  R fre = R(0), fim = R(0);
+  for (int z = 0; z < S; ++z) {
+    const cplx<R> v = partial[((int64_t)z * nsys + l) * M + i];
+    fre += v.re;
+    fim += v.im;
+  }
+  double nre = 0.0, nim = 0.0;
+  const cf64* vl = nv + (int64_t)(l0 + l) * nnz;
+  const cplx<R>* xl = x + (int64_t)l * xs;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const cf64 a = vl[k];
+    const cplx<R> b = xl[col[k]];
+    nre += a.re * (double)b.re - a.im * (double)b.im;
+    nim += a.re * (double)b.im + a.im * (double)b.re;
+  }
+  cplx<R> o;
+  o.re = (R)((double)fre + nre);
+  o.im = (R)((double)fim + nim);
+  y[(int64_t)l * ys + i] = o;
+}
+
+// Dense assembly: entries of the far pairs of all frequency systems in FP64
+// (optionally also stored as complex64).  One thread per (target i, source j)
+// pair and FT frequencies; 64 consecutive sources per workgroup so stores are
+// coalesced along rows.  Near pairs are left for the near-field scatter.
+template <int FT>
+__global__ __launch_bounds__(64) void k_dense_assemble(const double4* __restrict__ pts,
+                                                       const int4* __restrict__ vid, int M,
+                                                       const double* __restrict__ ea,
+                                                       const double* __restrict__ pb, int nsys,
+                                                       cf64* __restrict__ d64,
+                                                       cf32* __restrict__ d32) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  const int i = blockIdx.y;
+  const int l0 = blockIdx.z * FT;
+  const int nl = min(FT, nsys - l0);
+  if (j >= M) return;
+  if (share_vertex(vid[i], vid[j])) return;
+  double sx[kQ], sy[kQ], sz[kQ], sw[kQ];
+#pragma unroll
+  for (int b = 0; b < kQ; ++b) {
+    const double4 q = pts[j * kQ + b];
+    sx[b] = q.x;
+    sy[b] = q.y;
+    sz[b] = q.z;
+    sw[b] = q.w;
+  }
+  double fe[FT], fp[FT], vre[FT], vim[FT];
+#pragma unroll
+  for (int l = 0; l < FT; ++l) {
+    fe[l] = l < nl ? ea[l0 + l] : 0.0;
+    fp[l] = l < nl ? pb[l0 + l] : 0.0;
+    vre[l] = 0.0;
+    vim[l] = 0.0;
+  }
+  for (int a = 0; a < kQ; ++a) {
+    const double4 t = pts[i * kQ + a];
+#pragma unroll 1
+    for (int b = 0; b < kQ; ++b) {
+      const double dx = t.x - sx[b], dy = t.y - sy[b], dz = t.z - sz[b];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double w = t.w * sw[b] / r;
+#pragma unroll
+      for (int l = 0; l < FT; ++l) {
+        double e, c, sn;
+        KMath<double>::eval(fe[l], fp[l], r, e, c, sn);
+        e *= w;
+        vre[l] += e * c;
+        vim[l] -= e * sn;
+      }
+    }
+  }
+  const int64_t base = (int64_t)i * M + j;
+  const int64_t MM = (int64_t)M * M;
+#pragma unroll
+  for (int l = 0; l < FT; ++l)
+    if (l < nl) {
+      const double re = vre[l] * kInv4Pi, im = vim[l] * kInv4Pi;
+      d64[(int64_t)(l0 + l) * MM + base] = cf64{re, im};
+      if (d32) d32[(int64_t)(l0 + l) * MM + base] = cf32{(float)re, (float)im};
+    }
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+template <typename R> int pick_ft(int nsys);
+// Frequency tile: the width with the fewest padding slots (ties: wider).
+// 9, 11, 13 and 17 divide the half-band sizes N/2+1 of N = 16, 64, 128, 32.
+template <> int pick_ft<float>(int nsys) {
+  const int opts[5] = {17, 16, 13, 11, 9};
+  int best = 17, waste = 1 << 30;
+  for (int f : opts) {
+    const int w = ((nsys + f - 1) / f) * f - nsys;
+    if (w < waste) waste = w, best = f;
+  }
+  return best;
+}
+template <> int pick_ft<double>(int nsys) {
+  const int opts[3] = {9, 8, 6};
+  int best = 9, waste = 1 << 30;
+  for (int f : opts) {
+    const int w = ((nsys + f - 1) / f) * f - nsys;
+    if (w < waste) waste = w, best = f;
+  }
+  return best;
+}
+}  // namespace
+
+// Source split: enough workgroups to fill the chip (about 4096 waves), each
+// source chunk a whole number of LDS tiles.  Returns the number of slots and
+// the chunk length; both launchers use it so they agree on the slot count.
+int far_splits(int M, int nsys, int FT, int* chunk_out = nullptr) {
+  const int tiles = ((M + kTgt - 1) / kTgt) * ((nsys + FT - 1) / FT);
+  int S = (4096 + tiles - 1) / tiles;
+  const int maxS = (M + kTs - 1) / kTs;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  int chunk = (M + S - 1) / S;
+  chunk = ((chunk + kTs - 1) / kTs) * kTs;
+  if (chunk_out) *chunk_out = chunk;
+  return (M + chunk - 1) / chunk;
+}
+
+template <typename R, int FT>
+static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                         cplx<R>* partial, const int* active, hipStream_t s) {
+  const int M = (int)p.M;
+  int chunk = 0;
+  const int S = far_splits(M, nsys, FT, &chunk);
+  dim3 grid((M + kTgt - 1) / kTgt, (nsys + FT - 1) / FT, S);
+  const typename Pt4<R>::T* pts;
+  const R *ea, *pb;
+  if constexpr (sizeof(R) == 4) {
+    pts = p.dev.pts32;
+    ea = p.dev.ea32 + l0;
+    pb = p.dev.pb32 + l0;
+  } else {
+    pts = p.dev.pts64;
+    ea = p.dev.ea64 + l0;
+    pb = p.dev.pb64 + l0;
+  }
+  hipLaunchKernelGGL((k_far_apply<R, FT>), grid, dim3(kTgt), 0, s, pts, p.dev.vid, M, ea, pb,
+                     nsys, x, xs, partial, chunk, active);
+  CQM_HIP(hipGetLastError());
+}
+
+template <typename R>
+void launch_far_apply(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                      cplx<R>* partial, const int* active, hipStream_t s) {
+  const int FT = pick_ft<R>(nsys);
+  if constexpr (sizeof(R) == 4) {
+    switch (FT) {
+      case 17: far_apply_ft<R, 17>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 16: far_apply_ft<R, 16>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 13: far_apply_ft<R, 13>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 11: far_apply_ft<R, 11>(p, l0, nsys, x, xs, partial, active, s); break;
+      default: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, s); break;
+    }
+  } else {
+    switch (FT) {
+      case 9: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 8: far_apply_ft<R, 8>(p, l0, nsys, x, xs, partial, active, s); break;
+      default: far_apply_ft<R, 6>(p, l0, nsys, x, xs, partial, active, s); break;
+    }
+  }
+}
+
+int far_partial_slots(int M, int nsys, int precision) {
+  const int FT = precision == 32 ? pick_ft<float>(nsys) : pick_ft<double>(nsys);
+  return far_splits(M, nsys, FT);
+}
+
+template <typename R>
+void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* partial,
+                            const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+                            const cf64* near_vals, const int* active, hipStream_t s) {
+  const int M = (int)p.M;
+  const int FT = pick_ft<R>(nsys);
+  const int S = far_splits(M, nsys, FT);
+  dim3 grid((M + 255) / 256, nsys);
+  hipLaunchKernelGGL((k_far_reduce_near<R>), grid, dim3(256), 0, s, partial, S, nsys, M, x, xs, y,
+                     ys, p.dev.near_rowptr, p.dev.near_col, near_vals, (int64_t)p.col.size(), l0,
+                     active);
+  CQM_HIP(hipGetLastError());
+}
+
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
+  const int M = (int)p.M;
+  constexpr int FT = 8;
+  dim3 grid((M + 63) / 64, M, (p.Fsys + FT - 1) / FT);
+  hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(64), 0, s, p.dev.pts64, p.dev.vid, M,
+                     p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32);
+  CQM_HIP(hipGetLastError());
+}
+
+template void launch_far_apply<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,
+                                      const int*, hipStream_t);
+template void launch_far_apply<double>(const Problem&, int, int, const cf64*, int64_t, cf64*,
+                                       const int*, hipStream_t);
+template void launch_far_reduce_near<float>(const Problem&, int, int, const cf32*, const cf32*,
+                                            int64_t, cf32*, int64_t, const cf64*, const int*,
+                                            hipStream_t);
+template void launch_far_reduce_near<double>(const Problem&, int, int, const cf64*, const cf64*,
+                                             int64_t, cf64*, int64_t, const cf64*, const int*,
+                                             hipStream_t);
+
+}  // namespace cqm

@@ -1,0 +1,306 @@
+// Batched restarted GMRES: one workgroup per frequency system, all systems
+// advanced by the same launches.  Each restart cycle begins from the FP64 true
+// residual r = ghat - V x (computed by the caller), so restarts double as
+// iterative-refinement steps: the Krylov basis may be FP32 while x and r stay
+// FP64.  Orthogonalisation is classical Gram-Schmidt applied twice; the
+// Hessenberg matrix, Givens rotations and the residual estimate are FP64.
+// Per-system status lives on the device, so a cycle needs no host round trip.
+#include "device_util.h"
+
+namespace cqm {
+
+namespace {
+constexpr int kGB = 256;    // threads per system
+constexpr int kChunk = 8;   // inner products per pass over w
+constexpr int kMaxM = 64;   // largest supported restart length
+constexpr double kFloorTol = 1e-13;  // stagnation below this counts as converged
+}  // namespace
+
+// sysd per system (8 doubles): 0 beta, 1 cycle tolerance, 2 ||ghat||,
+// 3 last true residual norm, 4 non-finite flag.  sysi (kSysiStride ints):
+// 0 system active, 1 cycle active, 2 Arnoldi steps in cycle, 3 total steps.
+__global__ __launch_bounds__(kGB) void k_gmres_init(const cf64* __restrict__ ghat, int M,
+                                                    cf64* __restrict__ x, cf64* __restrict__ r,
+                                                    double* __restrict__ sysd, int* __restrict__ sysi) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  const int64_t off = (int64_t)l * M;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < M; i += kGB) {
+    const cf64 v = ghat[off + i];
+    acc += v.re * v.re + v.im * v.im;
+    x[off + i] = cf64{0.0, 0.0};
+    r[off + i] = v;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    double* d = sysd + 8 * l;
+    for (int k = 0; k < 8; ++k) d[k] = 0.0;
+    d[2] = sqrt(acc);
+    d[3] = d[2];
+    int* st = sysi + kSysiStride * l;
+    st[0] = 1;
+    st[1] = 0;
+    st[2] = 0;
+    st[3] = 0;
+  }
+}
+
+void launch_gmres_init(const cf64* ghat, int M, int nsys, cf64* x, cf64* r, double* sysd,
+                       int* sysi, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(nsys), dim3(kGB), 0, s, ghat, M, x, r, sysd, sysi);
+  CQM_HIP(hipGetLastError());
+}
+
+template <typename R>
+__global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __restrict__ basis,
+                                                     cf64* __restrict__ g, double* __restrict__ sysd,
+                                                     int* __restrict__ sysi,
+                                                     const cf64* __restrict__ r, double outer_tol,
+                                                     double inner_tol) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  int* st = sysi + kSysiStride * l;
+  double* d = sysd + 8 * l;
+  if (!st[0]) return;
+  const cf64* rl = r + (int64_t)l * M;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < M; i += kGB) acc += rl[i].re * rl[i].re + rl[i].im * rl[i].im;
+  const double rn = sqrt(block_sum(acc, red));
+  const double bn = d[2];
+  if (!isfinite(rn)) {
+    if (threadIdx.x == 0) {
+      d[4] = 1.0;
+      st[0] = 0;
+      st[1] = 0;
+    }
+    return;
+  }
+  // converged, or stagnated at the FP64 floor: a restart that no longer halves
+  // a true residual already below kFloorTol counts as converged
+  const double prev = d[3];
+  if (rn <= outer_tol * bn || rn == 0.0 || (rn > 0.5 * prev && rn <= kFloorTol * bn)) {
+    if (threadIdx.x == 0) {
+      d[3] = rn;
+      st[0] = 0;
+      st[1] = 0;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    d[0] = rn;
+    d[1] = fmax(inner_tol * rn, 0.5 * outer_tol * bn);
+    d[3] = rn;
+    st[1] = 1;
+    st[2] = 0;
+  }
+  cf64* gl = g + (int64_t)l * (m + 1);
+  for (int k = threadIdx.x; k <= m; k += kGB) gl[k] = cf64{k == 0 ? rn : 0.0, 0.0};
+  cplx<R>* v0 = basis + (int64_t)l * (m + 1) * M;
+  const double inv = 1.0 / rn;
+  for (int i = threadIdx.x; i < M; i += kGB) {
+    cplx<R> o;
+    o.re = (R)(rl[i].re * inv);
+    o.im = (R)(rl[i].im * inv);
+    v0[i] = o;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* __restrict__ basis,
+                                                 cf64* __restrict__ H, double* __restrict__ cs,
+                                                 cf64* __restrict__ sn, cf64* __restrict__ g,
+                                                 double* __restrict__ sysd, int* __restrict__ sysi) {
+  __shared__ double red[16 * 2 * kChunk];
+  __shared__ cf64 coef[kMaxM + 1];
+  __shared__ cf64 hacc[kMaxM + 2];
+  const int l = blockIdx.x;
+  int* st = sysi + kSysiStride * l;
+  if (!st[1]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = kGB / 64;
+  cplx<R>* V = basis + (int64_t)l * (m + 1) * M;
+  cplx<R>* w = V + (int64_t)(j + 1) * M;
+  for (int k = tid; k <= j + 1; k += kGB) hacc[k] = cf64{0.0, 0.0};
+  for (int pass = 0; pass < 2; ++pass) {
+    // coefficients c_k = <v_k, w>, k = 0..j, in chunks of kChunk
+    for (int kc = 0; kc <= j; kc += kChunk) {
+      double ar[kChunk], ai[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) ar[u] = ai[u] = 0.0;
+      for (int i = tid; i < M; i += kGB) {
+        const cplx<R> x = w[i];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+          if (kc + u <= j) {
+            const cplx<R> v = V[(int64_t)(kc + u) * M + i];
+            ar[u] += (double)v.re * x.re + (double)v.im * x.im;
+            ai[u] += (double)v.re * x.im - (double)v.im * x.re;
+          }
+      }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        ar[u] = wave_sum(ar[u]);
+        ai[u] = wave_sum(ai[u]);
+      }
+      __syncthreads();
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          red[(wv * kChunk + u) * 2] = ar[u];
+          red[(wv * kChunk + u) * 2 + 1] = ai[u];
+        }
+      __syncthreads();
+      if (tid < kChunk && kc + tid <= j) {
+        double sr = 0.0, si = 0.0;
+        for (int q = 0; q < nw; ++q) {
+          sr += red[(q * kChunk + tid) * 2];
+          si += red[(q * kChunk + tid) * 2 + 1];
+        }
+        coef[kc + tid] = cf64{sr, si};
+      }
+    }
+    __syncthreads();
+    // w <- w - sum_k c_k v_k
+    for (int i = tid; i < M; i += kGB) {
+      const cplx<R> x = w[i];
+      double re = x.re, im = x.im;
+      for (int k = 0; k <= j; ++k) {
+        const cplx<R> v = V[(int64_t)k * M + i];
+        const cf64 c = coef[k];
+        re -= c.re * v.re - c.im * v.im;
+        im -= c.re * v.im + c.im * v.re;
+      }
+      cplx<R> o;
+      o.re = (R)re;
+      o.im = (R)im;
+      w[i] = o;
+    }
+    for (int k = tid; k <= j; k += kGB) {
+      hacc[k].re += coef[k].re;
+      hacc[k].im += coef[k].im;
+    }
+    __syncthreads();
+  }
+  double acc = 0.0;
+  for (int i = tid; i < M; i += kGB) acc += (double)w[i].re * w[i].re + (double)w[i].im * w[i].im;
+  const double nr = sqrt(block_sum(acc, red));
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int i = tid; i < M; i += kGB) {
+    cplx<R> o = w[i];
+    o.re = (R)(o.re * inv);
+    o.im = (R)(o.im * inv);
+    w[i] = o;
+  }
+  if (tid == 0) {
+    cf64* Hc = H + (int64_t)l * (m + 1) * m + (int64_t)(m + 1) * j;
+    double* csl = cs + (int64_t)l * m;
+    cf64* snl = sn + (int64_t)l * m;
+    cf64* gl = g + (int64_t)l * (m + 1);
+    cf64 h[kMaxM + 2];
+    for (int k = 0; k <= j; ++k) h[k] = hacc[k];
+    h[j + 1] = cf64{nr, 0.0};
+    // previous rotations: (h_k, h_k+1) <- (c h_k + s h_k+1, -conj(s) h_k + c h_k+1)
+    for (int k = 0; k < j; ++k) {
+      const double c = csl[k];
+      const cf64 s = snl[k], a = h[k], b = h[k + 1];
+      h[k] = cf64{c * a.re + s.re * b.re - s.im * b.im, c * a.im + s.re * b.im + s.im * b.re};
+      h[k + 1] = cf64{-(s.re * a.re + s.im * a.im) + c * b.re, -(s.re * a.im - s.im * a.re) + c * b.im};
+    }
+    // new rotation zeroing h_{j+1}
+    const cf64 a = h[j];
+    const double bb = h[j + 1].re;  // real, >= 0
+    const double na = sqrt(a.re * a.re + a.im * a.im);
+    double c;
+    cf64 s, rr;
+    if (na == 0.0) {
+      c = 0.0;
+      s = cf64{1.0, 0.0};
+      rr = cf64{bb, 0.0};
+    } else {
+      const double t = sqrt(na * na + bb * bb);
+      const cf64 ph{a.re / na, a.im / na};
+      c = na / t;
+      s = cf64{ph.re * bb / t, ph.im * bb / t};
+      rr = cf64{ph.re * t, ph.im * t};
+    }
+    csl[j] = c;
+    snl[j] = s;
+    h[j] = rr;
+    for (int k = 0; k <= j; ++k) Hc[k] = h[k];
+    const cf64 gj = gl[j];
+    gl[j + 1] = cf64{-(s.re * gj.re + s.im * gj.im), -(s.re * gj.im - s.im * gj.re)};
+    gl[j] = cf64{c * gj.re, c * gj.im};
+    const double res = sqrt(gl[j + 1].re * gl[j + 1].re + gl[j + 1].im * gl[j + 1].im);
+    st[2] = j + 1;
+    st[3] += 1;
+    if (!(res > sysd[8 * l + 1]) || j + 1 >= m || nr == 0.0) st[1] = 0;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kGB) void k_cycle_finish(int M, int m, const cplx<R>* __restrict__ basis,
+                                                      const cf64* __restrict__ H,
+                                                      const cf64* __restrict__ g,
+                                                      const int* __restrict__ sysi,
+                                                      cf64* __restrict__ x) {
+  __shared__ cf64 y[kMaxM];
+  const int l = blockIdx.x;
+  const int* st = sysi + kSysiStride * l;
+  if (!st[0]) return;
+  const int k = st[2];
+  if (k == 0) return;
+  const cf64* Hl = H + (int64_t)l * (m + 1) * m;
+  const cf64* gl = g + (int64_t)l * (m + 1);
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double re = gl[i].re, im = gl[i].im;
+      for (int t = i + 1; t < k; ++t) {
+        const cf64 a = Hl[(int64_t)(m + 1) * t + i];
+        re -= a.re * y[t].re - a.im * y[t].im;
+        im -= a.re * y[t].im + a.im * y[t].re;
+      }
+      const cf64 d = Hl[(int64_t)(m + 1) * i + i];
+      const double dn = d.re * d.re + d.im * d.im;
+      y[i] = cf64{(re * d.re + im * d.im) / dn, (im * d.re - re * d.im) / dn};
+    }
+  }
+  __syncthreads();
+  const cplx<R>* V = basis + (int64_t)l * (m + 1) * M;
+  cf64* xl = x + (int64_t)l * M;
+  for (int i = threadIdx.x; i < M; i += kGB) {
+    double re = xl[i].re, im = xl[i].im;
+    for (int t = 0; t < k; ++t) {
+      const cplx<R> v = V[(int64_t)t * M + i];
+      re += y[t].re * v.re - y[t].im * v.im;
+      im += y[t].re * v.im + y[t].im * v.re;
+    }
+    xl[i] = cf64{re, im};
+  }
+}
+
+template <typename R>
+void launch_cycle_start(const GmresState& st, const cf64* r, double outer_tol, double inner_tol,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_start<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m,
+                     (cplx<R>*)st.basis, st.g, st.sysd, st.sysi, r, outer_tol, inner_tol);
+  CQM_HIP(hipGetLastError());
+}
+template <typename R> void launch_arnoldi(const GmresState& st, int j, hipStream_t s) {
+  hipLaunchKernelGGL((k_arnoldi<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m, j,
+                     (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
+  CQM_HIP(hipGetLastError());
+}
+template <typename R> void launch_cycle_finish(const GmresState& st, cf64* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_finish<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m,
+                     (const cplx<R>*)st.basis, st.H, st.g, st.sysi, x);
+  CQM_HIP(hipGetLastError());
+}
+
+template void launch_cycle_start<float>(const GmresState&, const cf64*, double, double, hipStream_t);
+template void launch_cycle_start<double>(const GmresState&, const cf64*, double, double, hipStream_t);
+template void launch_arnoldi<float>(const GmresState&, int, hipStream_t);
+template void launch_arnoldi<double>(const GmresState&, int, hipStream_t);
+template void launch_cycle_finish<float>(const GmresState&, cf64*, hipStream_t);
+template void launch_cycle_finish<double>(const GmresState&, cf64*, hipStream_t);
+
+}  // namespace cqm

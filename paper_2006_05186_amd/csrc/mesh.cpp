@@ -1,0 +1,258 @@
+// Host planner: mesh validation, quadrature points, near-field adjacency,
+// CQM frequency tables, device upload and the solve-workspace layout.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <set>
+
+#include "internal.h"
+
+namespace cqm {
+
+// Gauss-Legendre rule on [0,1] by Newton iteration on P_q.
+void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = q * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) {
+        double a0 = 1.0, a1 = t;
+        for (int k = 2; k <= q; ++k) {
+          const double a2 = ((2.0 * k - 1.0) * t * a1 - (k - 1.0) * a0) / k;
+          a0 = a1;
+          a1 = a2;
+        }
+        const double d = q * (t * a1 - a0) / (t * t - 1.0);
+        w[i] = 1.0 / ((1.0 - t * t) * d * d);  // weight on [0,1] = 2/((1-t^2)P'^2) / 2
+        break;
+      }
+    }
+    x[i] = 0.5 * (1.0 - t);
+  }
+  // sort ascending
+  std::vector<int> idx(q);
+  for (int i = 0; i < q; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(q), ws(q);
+  for (int i = 0; i < q; ++i) xs[i] = x[idx[i]], ws[i] = w[idx[i]];
+  x = xs;
+  w = ws;
+}
+
+// Dunavant's 6-point rule of degree 4 (barycentric points, weights sum to 1).
+void dunavant6(double bary[6][3], double w[6]) {
+  const double a = 0.445948490915965, b = 0.091576213509771;
+  const double wa = 0.223381589678011, wb = 0.109951743655322;
+  const double P[6][3] = {{1 - 2 * a, a, a}, {a, 1 - 2 * a, a}, {a, a, 1 - 2 * a},
+                          {1 - 2 * b, b, b}, {b, 1 - 2 * b, b}, {b, b, 1 - 2 * b}};
+  for (int k = 0; k < 6; ++k) {
+    for (int d = 0; d < 3; ++d) bary[k][d] = P[k][d];
+    w[k] = k < 3 ? wa : wb;
+  }
+}
+
+// Near field: for every triangle, the triangles sharing at least one vertex
+// index (itself included), with the vertex ordering each Duffy rule expects:
+// kind 0 (same triangle) A B C; kind 1 (shared edge AB) A B C D, C in row
+// triangle, D in column triangle; kind 2 (shared vertex P) P A1 A2 B1 B2.
+void build_near(Problem& p) {
+  const int64_t M = p.M;
+  std::vector<std::vector<int32_t>> by_vertex(p.nv);
+  for (int64_t i = 0; i < M; ++i)
+    for (int k = 0; k < 3; ++k) by_vertex[p.tris[3 * i + k]].push_back((int32_t)i);
+  p.rowptr.assign(M + 1, 0);
+  p.col.clear();
+  p.kind.clear();
+  p.nvtx.clear();
+  for (int64_t i = 0; i < M; ++i) {
+    std::set<int32_t> cand;
+    const int32_t* ti = &p.tris[3 * i];
+    for (int k = 0; k < 3; ++k) cand.insert(by_vertex[ti[k]].begin(), by_vertex[ti[k]].end());
+    for (int32_t j : cand) {
+      const int32_t* tj = &p.tris[3 * (int64_t)j];
+      int shared[3], ns = 0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          if (ti[a] == tj[b]) shared[ns++] = ti[a];
+      int32_t v[6] = {0, 0, 0, 0, 0, 0};
+      int kd;
+      if (j == i) {
+        kd = 0;
+        v[0] = ti[0], v[1] = ti[1], v[2] = ti[2];
+      } else if (ns == 3) {
+        throw Error(CQM_EINVAL, "duplicate triangles " + std::to_string(i) + " and " + std::to_string(j));
+      } else if (ns == 2) {
+        kd = 1;
+        // shared edge oriented by increasing vertex index: the rule for (j,i)
+        // is then the mirror image of the rule for (i,j)
+        v[0] = std::min(shared[0], shared[1]), v[1] = std::max(shared[0], shared[1]);
+        for (int a = 0; a < 3; ++a)
+          if (ti[a] != shared[0] && ti[a] != shared[1]) v[2] = ti[a];
+        for (int b = 0; b < 3; ++b)
+          if (tj[b] != shared[0] && tj[b] != shared[1]) v[3] = tj[b];
+      } else {
+        kd = 2;
+        v[0] = shared[0];
+        int na = 1, nb = 3;
+        for (int a = 0; a < 3; ++a)
+          if (ti[a] != shared[0]) v[na++] = ti[a];
+        for (int b = 0; b < 3; ++b)
+          if (tj[b] != shared[0]) v[nb++] = tj[b];
+      }
+      p.col.push_back(j);
+      p.kind.push_back(kd);
+      for (int k = 0; k < 6; ++k) p.nvtx.push_back(v[k]);
+    }
+    p.rowptr[i + 1] = (int32_t)p.col.size();
+  }
+}
+
+namespace {
+template <typename T> T* upload(const std::vector<T>& h) {
+  T* d = nullptr;
+  if (h.empty()) return nullptr;
+  CQM_HIP(hipMalloc(&d, sizeof(T) * h.size()));
+  CQM_HIP(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return d;
+}
+}  // namespace
+
+void upload_problem(Problem& p) {
+  const int64_t M = p.M;
+  double bary[6][3], w[6];
+  dunavant6(bary, w);
+  std::vector<double4> p64(M * kQ);
+  std::vector<float4> p32(M * kQ);
+  std::vector<int4> vid(M);
+  std::vector<double> area(M);
+  for (int64_t i = 0; i < M; ++i) {
+    const double* A = &p.verts[3 * p.tris[3 * i]];
+    const double* B = &p.verts[3 * p.tris[3 * i + 1]];
+    const double* C = &p.verts[3 * p.tris[3 * i + 2]];
+    const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2],
+                 cz = u[0] * v[1] - u[1] * v[0];
+    area[i] = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    for (int a = 0; a < kQ; ++a) {
+      double q[3];
+      for (int d = 0; d < 3; ++d) q[d] = bary[a][0] * A[d] + bary[a][1] * B[d] + bary[a][2] * C[d];
+      p64[i * kQ + a] = double4{q[0], q[1], q[2], w[a] * area[i]};
+      p32[i * kQ + a] = float4{(float)q[0], (float)q[1], (float)q[2], (float)(w[a] * area[i])};
+    }
+    vid[i] = int4{p.tris[3 * i], p.tris[3 * i + 1], p.tris[3 * i + 2], 0};
+  }
+  p.dev.pts64 = upload(p64);
+  p.dev.pts32 = upload(p32);
+  p.dev.vid = upload(vid);
+  p.dev.area = upload(area);
+  p.dev.verts = upload(p.verts);
+  p.dev.near_rowptr = upload(p.rowptr);
+  p.dev.near_col = upload(p.col);
+  p.dev.near_kind = upload(p.kind);
+  p.dev.near_vtx = upload(p.nvtx);
+  CQM_HIP(hipMalloc(&p.dev.near_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
+  std::vector<double> gx, gw;
+  gauss_legendre01(p.opt.q_duffy, gx, gw);
+  std::vector<double> gl(gx);
+  gl.insert(gl.end(), gw.begin(), gw.end());
+  p.dev.gl = upload(gl);
+  // frequency tables
+  const int F = p.F;
+  std::vector<cf64> s(F), twf(F), twi(F);
+  std::vector<double> rp(F), rip(F);
+  for (int l = 0; l < F; ++l) s[l] = cf64{p.s_re[l], p.s_im[l]};
+  for (int k = 0; k <= F / 2; ++k) {
+    const double c = std::cos(2.0 * M_PI * k / F), sn = std::sin(2.0 * M_PI * k / F);
+    twf[k] = cf64{c, -sn};
+    twi[k] = cf64{c, sn};
+    if (k > 0) {
+      twf[F - k] = cf64{c, sn};
+      twi[F - k] = cf64{c, -sn};
+    }
+  }
+  for (int n = 0; n < F; ++n) {
+    rp[n] = std::pow(p.rho, n);
+    rip[n] = std::pow(p.rho, -n) / F;
+  }
+  p.dev.s = upload(s);
+  p.dev.tw_fwd = upload(twf);
+  p.dev.tw_inv = upload(twi);
+  p.dev.rho_pow = upload(rp);
+  p.dev.rho_ipow = upload(rip);
+  std::vector<double> ea64(F), pb64(F);
+  std::vector<float> ea32(F), pb32(F);
+  const double log2e = 1.4426950408889634;
+  for (int l = 0; l < F; ++l) {
+    ea64[l] = -p.s_re[l];
+    pb64[l] = p.s_im[l];
+    ea32[l] = (float)(-p.s_re[l] * log2e);
+    pb32[l] = (float)(p.s_im[l] / (2.0 * M_PI));
+  }
+  p.dev.ea64 = upload(ea64);
+  p.dev.pb64 = upload(pb64);
+  p.dev.ea32 = upload(ea32);
+  p.dev.pb32 = upload(pb32);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool mode_is_mixed(int mode) { return mode == CQM_MIXED_PLAIN || mode == CQM_MIXED_H2ACA; }
+bool mode_is_h2(int mode) { return mode == CQM_MIXED_H2ACA || mode == CQM_FP64_H2ACA; }
+
+size_t h2_workspace_bytes(const Problem& p);  // h2.cpp
+
+void compute_layout(Problem& p) {
+  Layout L;
+  const size_t M = p.M, Fs = p.Fsys, m = p.opt.gmres_restart;
+  const size_t inner = mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.b = take(sizeof(double) * p.F * M);
+  L.ghat = take(sizeof(cf64) * Fs * M);
+  L.x = take(sizeof(cf64) * Fs * M);
+  L.r = take(sizeof(cf64) * Fs * M);
+  L.basis = take(inner * Fs * (m + 1) * M);
+  L.H = take(sizeof(cf64) * Fs * (m + 1) * m);
+  L.cs = take(sizeof(double) * Fs * m);
+  L.sn = take(sizeof(cf64) * Fs * m);
+  L.g = take(sizeof(cf64) * Fs * (m + 1));
+  L.sysd = take(sizeof(double) * 8 * Fs);
+  L.sysi = take(sizeof(int) * kSysiStride * Fs);
+  L.scratch = take(4096);
+  if (mode_is_h2(p.opt.mode)) {
+    L.partial = take(h2_workspace_bytes(p));
+  } else {
+    L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
+    if (p.opt.form == CQM_FORM_DENSE) {
+      L.dense64 = take(sizeof(cf64) * Fs * M * M);
+      if (mode_is_mixed(p.opt.mode)) L.dense32 = take(sizeof(cf32) * Fs * M * M);
+    } else {
+      size_t worst = 0;
+      for (int nl = 1; nl <= (int)Fs; ++nl) {
+        const size_t a = (size_t)far_partial_slots((int)M, nl, 32) * nl * sizeof(cf32);
+        const size_t b = (size_t)far_partial_slots((int)M, nl, 64) * nl * sizeof(cf64);
+        worst = std::max(worst, std::max(a, b));
+      }
+      L.partial = take(worst * M);
+    }
+  }
+  L.total = off;
+  p.lay = L;
+}
+
+}  // namespace cqm

@@ -1,0 +1,63 @@
+"""Convenience wrapper: one problem with a torch-allocated device workspace.
+
+Marshalling only -- every step of the computation runs in libcqm.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cqm as C
+
+
+class Problem:
+    def __init__(self, ctx, vertices, tris, N, T, device="cuda", **opts):
+        import torch
+        self.torch = torch
+        self.M = int(np.asarray(tris).shape[0])
+        self.N = int(N)
+        self.options = C.cqm_default_options(**opts)
+        self.handle = C.cqm_problem_create(ctx, vertices, tris, N, T, self.options)
+        nbytes = C.cqm_workspace_size(self.handle)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        C.cqm_set_workspace(self.handle, aligned, nbytes)
+        self.workspace_bytes = nbytes
+        self.device = device
+
+    def set_plane_wave(self, direction=(1.0, 0.0, 0.0), sigma=0.25, t0=1.5, amplitude=1.0):
+        C.cqm_set_plane_wave(self.handle, direction, sigma, t0, amplitude)
+
+    def set_samples(self, samples):
+        t = self.torch.as_tensor(np.ascontiguousarray(samples), dtype=self.torch.float64,
+                                 device=self.device)
+        self._samples = t
+        C.cqm_set_dirichlet_samples(self.handle, t.data_ptr())
+
+    def solve(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.N + 1, self.M), dtype=torch.float64, device=self.device)
+        rc, diag = C.cqm_solve(self.handle, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        return out, rc, diag
+
+    def apply(self, x, l0=0, precision=64):
+        """x: complex torch tensor (nl, M) on device; returns V(s_l) x_l."""
+        torch = self.torch
+        dt = torch.complex128 if precision == 64 else torch.complex64
+        x = x.to(dt).contiguous()
+        y = torch.empty_like(x)
+        C.cqm_apply_V(self.handle, l0, x.shape[0], precision, x.data_ptr(), y.data_ptr(),
+                      torch.cuda.current_stream().cuda_stream)
+        return y
+
+    def close(self):
+        if self.handle is not None:
+            C.cqm_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import cqm_workloads as W
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_05186_amd import cqm as C  # noqa: E402
+from paper_2006_05186_amd.solver import Problem  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = C.cqm_ctx_create(0)
+    yield c
+    C.cqm_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    wl = W.C1
+    V, T = wl.mesh()
+    r = O.solve(V, T, wl.N, wl.T, return_all=True)
+    _, _, area = O.triangle_quadrature(V, T)
+    return wl, V, T, r, area
+
+
+def test_near_static_entries_match_oracle(ctx, c1):
+    wl, V, T, r, _ = c1
+    say("near static M=320")
+    p = Problem(ctx, V, T, wl.N, wl.T)
+    rp, col, sv = C.cqm_near_entries(p.handle)
+    pairs = r["pairs"]
+    assert len(col) == len(pairs)
+    got = {(i, int(col[k])): sv[k] for i in range(len(T)) for k in range(rp[i], rp[i + 1])}
+    for (i, j, _), ref in zip(pairs, r["static"]):
+        assert abs(got[(i, j)] - ref) <= 1e-13 * abs(ref)
+    p.close()
+
+
+@pytest.mark.parametrize("form", [C.CQM_FORM_DENSE, C.CQM_FORM_MATRIX_FREE])
+@pytest.mark.parametrize("mode", [C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN])
+def test_apply_V_matches_oracle(ctx, c1, form, mode):
+    wl, V, T, r, _ = c1
+    say(f"apply_V M=320 form={form} mode={mode}")
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form)
+    H = O.num_frequencies_half(wl.N + 1)
+    x = W.random_complex((H, len(T)), seed=7)
+    xt = torch.as_tensor(x, device="cuda")
+    precs = (64, 32) if mode == C.CQM_MIXED_PLAIN or form == C.CQM_FORM_MATRIX_FREE else (64,)
+    for prec in precs:
+        y = p.apply(xt, 0, prec).cpu().numpy().astype(np.complex128)
+        for l in range(H):
+            A = O.assemble_V(V, T, r["s"][l], pairs=r["pairs"], static=r["static"])
+            ref = A @ x[l]
+            err = np.linalg.norm(y[l] - ref) / np.linalg.norm(ref)
+            tol = 1e-13 if prec == 64 else 2e-6
+            assert err < tol, (l, prec, err)
+    # a sub-range of frequencies
+    y2 = p.apply(xt[3:5], 3, 64).cpu().numpy()
+    A = O.assemble_V(V, T, r["s"][4], pairs=r["pairs"], static=r["static"])
+    assert np.linalg.norm(y2[1] - A @ x[4]) < 1e-13 * np.linalg.norm(A @ x[4])
+    p.close()
+
+
+def test_gpu_operator_symmetric(ctx, c1):
+    wl, V, T, r, _ = c1
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_FP64_PLAIN, form=C.CQM_FORM_MATRIX_FREE)
+    H = O.num_frequencies_half(wl.N + 1)
+    x = torch.as_tensor(W.random_complex((H, len(T)), seed=1), device="cuda")
+    z = torch.as_tensor(W.random_complex((H, len(T)), seed=2), device="cuda")
+    Vx, Vz = p.apply(x).cpu().numpy(), p.apply(z).cpu().numpy()
+    xn, zn = x.cpu().numpy(), z.cpu().numpy()
+    for l in range(H):
+        a, b = zn[l] @ Vx[l], xn[l] @ Vz[l]
+        scale = np.abs(zn[l]) @ np.abs(Vx[l])
+        assert abs(a - b) < 1e-13 * scale, (l, abs(a - b), scale)
+    p.close()
+
+
+@pytest.mark.parametrize("form", [C.CQM_FORM_DENSE, C.CQM_FORM_MATRIX_FREE])
+@pytest.mark.parametrize("mode", [C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN])
+def test_solve_C1_matches_oracle(ctx, c1, form, mode):
+    wl, V, T, r, area = c1
+    say(f"solve C1 form={form} mode={mode}")
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form)
+    p.set_plane_wave()
+    q, rc, diag = p.solve()
+    q = q.cpu().numpy()
+    err = O.rel_error(q, r["q"], area)
+    say(f"  rc={rc} err={err:.3e} iters={diag.total_iters} cycles={diag.cycles} "
+        f"resid={diag.max_rel_residual:.2e}")
+    assert rc == C.CQM_OK
+    assert diag.max_rel_residual <= 1e-13
+    assert diag.converged == 1
+    assert err < 1e-8
+    p.close()
+
+
+def test_solve_C2_against_stored_oracle(ctx):
+    wl = W.C2
+    path = os.path.join(GOLDEN, f"{wl.name}.npz")
+    g = np.load(path)
+    V, T = wl.mesh()
+    _, _, area = O.triangle_quadrature(V, T)
+    for mode in (C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN):
+        say(f"solve C2 mode={mode}")
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=C.CQM_FORM_DENSE)
+        p.set_plane_wave()
+        q, rc, diag = p.solve()
+        err = O.rel_error(q.cpu().numpy(), g["q"], area)
+        steps = O.step_errors(q.cpu().numpy(), g["q"], area)
+        say(f"  rc={rc} err={err:.3e} max step err={steps.max():.2e} iters={diag.total_iters} "
+            f"t_setup={diag.t_setup_ms:.1f}ms t_solve={diag.t_solve_ms:.1f}ms")
+        assert rc == C.CQM_OK and err < 1e-8
+        p.close()
+
+
+# N = 2 puts rho = 1e-4 per step: rounding of the three frequency solutions
+# (~1e-16 times the condition number, ~10) is amplified by rho^-N = 1e8 with no
+# averaging over steps, so its floor is ~1e-7 rather than the 1e-8 of N >= 7.
+@pytest.mark.parametrize("level,N,T,axes,tol", [(1, 7, 2.0, (1.0, 1.0, 1.0), 1e-8),
+                                                (1, 2, 0.5, (1.0, 1.0, 1.0), 2e-7),
+                                                (1, 10, 3.0, (1.3, 0.7, 0.9), 1e-8)])
+def test_small_and_ragged_cases(ctx, level, N, T, axes, tol):
+    """Odd N (even F: a real middle frequency), the smallest N, an ellipsoid."""
+    V, Tr = W.ellipsoid(level, axes)
+    say(f"ragged level={level} N={N} axes={axes}")
+    d = (0.3, -0.5, 0.8)
+    ref = O.solve(V, Tr, N, T, direction=np.asarray(d) / np.linalg.norm(d), sigma=0.3, t0=1.2)
+    _, _, area = O.triangle_quadrature(V, Tr)
+    for form in (C.CQM_FORM_DENSE, C.CQM_FORM_MATRIX_FREE):
+        p = Problem(ctx, V, Tr, N, T, mode=C.CQM_MIXED_PLAIN, form=form)
+        p.set_plane_wave(d, 0.3, 1.2)
+        q, rc, diag = p.solve()
+        err = O.rel_error(q.cpu().numpy(), ref, area)
+        assert rc == C.CQM_OK and err < tol, err
+        p.close()
+
+
+def test_dirichlet_samples_path(ctx):
+    """Caller-provided samples at the quadrature points (random data)."""
+    wl = W.C0_TINY
+    V, T = wl.mesh()
+    g = np.random.default_rng(4).standard_normal((wl.N + 1, len(T), 6))
+    ref = O.solve(V, T, wl.N, wl.T, samples=g)
+    _, _, area = O.triangle_quadrature(V, T)
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_FP64_PLAIN)
+    p.set_samples(g)
+    q, rc, _ = p.solve()
+    assert rc == C.CQM_OK and O.rel_error(q.cpu().numpy(), ref, area) < 1e-8
+    p.close()
+
+
+def test_error_paths(ctx):
+    wl = W.C0_TINY
+    V, T = wl.mesh()
+    # no workspace
+    h = C.cqm_problem_create(ctx, V, T, wl.N, wl.T)
+    out = torch.empty((wl.N + 1, len(T)), dtype=torch.float64, device="cuda")
+    with pytest.raises(C.CqmError) as e:
+        C.cqm_solve(h, out.data_ptr())
+    assert e.value.code == C.CQM_ENOMEM
+    C.cqm_problem_destroy(h)
+    # bad meshes
+    bad = T.copy()
+    bad[0, 0] = len(V) + 5
+    with pytest.raises(C.CqmError) as e:
+        C.cqm_problem_create(ctx, V, bad, wl.N, wl.T)
+    assert e.value.code == C.CQM_EINVAL
+    deg = T.copy()
+    deg[0] = [deg[0, 0], deg[0, 0], deg[0, 1]]
+    with pytest.raises(C.CqmError):
+        C.cqm_problem_create(ctx, V, deg, wl.N, wl.T)
+    # no incident data
+    p = Problem(ctx, V, T, wl.N, wl.T)
+    with pytest.raises(C.CqmError) as e:
+        p.solve()
+    assert e.value.code == C.CQM_EINVAL
+    # non-finite data -> CQM_ENAN, output still written
+    g = np.zeros((wl.N + 1, len(T), 6))
+    g[3, 5, 2] = np.nan
+    p.set_samples(g)
+    with pytest.raises(C.CqmError) as e:
+        p.solve()
+    assert e.value.code == C.CQM_ENAN
+    # one cycle, tiny restart: not converged, diagnostics still filled
+    p2 = Problem(ctx, V, T, wl.N, wl.T, gmres_restart=2, max_cycles=1)
+    p2.set_plane_wave()
+    q, rc, diag = p2.solve()
+    assert rc == C.CQM_ENOCONV and diag.converged == 0 and diag.cycles == 1
+    p.close()
+    p2.close()

@@ -1,0 +1,43 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, and its host-only entry points agree with the oracle (no GPU calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_05186_amd import cqm as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "cqm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|const char\*)\s+(cqm_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.load_library()
+    names = declared_functions()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(C.EXPORTED_SYMBOLS) <= set(names)
+
+
+@pytest.mark.parametrize("N,T", [(8, 2.0), (32, 4.0), (64, 4.0), (128, 6.0), (256, 6.0)])
+def test_host_frequencies_match_oracle(N, T):
+    s = C.cqm_frequencies(N, T)
+    ref, _, _ = O.frequencies(N, T)
+    assert np.max(np.abs(s - ref) / np.abs(ref)) < 1e-14
+
+
+def test_host_argument_errors():
+    with pytest.raises(C.CqmError) as e:
+        C.cqm_frequencies(0, 1.0)
+    assert e.value.code == C.CQM_EINVAL
+    o = C.cqm_default_options()
+    assert (o.gmres_restart, o.n_min, o.cheb_m, o.q_duffy) == (30, 32, 4, 5)
+    assert o.eps_aca == 1e-6 and o.eta == 1.0 and o.outer_tol == 1e-15
