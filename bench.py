@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Benchmark: time-domain CQM-BEM solves per second on one MI355X.
+
+A step is one complete solve of the hot path on a synthetic workload: near
+field (Duffy static part + per-frequency remainder), operator evaluation for
+all frequency systems, right-hand side, forward scaled DFT, batched GMRES with
+FP64 refinement, inverse scaled DFT -- everything from the mesh to the
+time-domain density, with inputs already resident on the device.
+
+Prints ONE JSON line.  Default workload: unit-sphere icosphere with 1280
+triangles, N = 64 steps on T = 4 (33 frequency systems), Gaussian plane wave.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import cqm_workloads as W  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+# Algorithmic flops of one point-pair-frequency kernel value
+# exp(-s r)/(4 pi r) accumulated with a real weight: three transcendental
+# evaluations (exp, sin, cos; one flop each), three multiplies (sigma r,
+# omega r, weight) and two fused multiply-adds (4 flops).
+FLOPS_PER_UNIT = 10
+
+WORKLOADS = {"C1": W.C1, "C2": W.C2, "C3": W.C3}
+KCLS = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "gmres", "other"]
+
+
+def area_of(V, T):
+    P = V[T]
+    return 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+
+
+def rel_err(q, ref, area):
+    return float(np.sqrt(np.sum(area * (q - ref) ** 2) / np.sum(area * ref ** 2)))
+
+
+def run_variant(C, Problem, ctx, wl, mode, form, steps, warmup, torch):
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form, profile=1)
+    p.set_plane_wave(wl.wave.direction, wl.wave.sigma, wl.wave.t0, wl.wave.amplitude)
+    out = torch.empty((wl.N + 1, len(T)), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        p.solve(out)
+    torch.cuda.synchronize()
+    lat, diags = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        _, rc, d = p.solve(out)
+        lat.append(time.perf_counter() - s0)
+        if rc != C.CQM_OK:
+            raise RuntimeError(f"solve did not converge (rc={rc})")
+        diags.append(d.as_dict())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    q = out.cpu().numpy()
+    p.close()
+    return dict(elapsed=el, lat=lat, diags=diags, q=q, V=V, T=T,
+                workspace=p.workspace_bytes)
+
+
+def summarise_kernels(diags):
+    ms = np.zeros(len(KCLS))
+    calls = np.zeros(len(KCLS), dtype=int)
+    for d in diags:
+        ms += np.asarray(d["kernel_ms"])
+        calls += np.asarray(d["kernel_calls"])
+    return ms, calls
+
+
+def roofline(diags, wl_units, form, mode):
+    """Dominant kernel class over the timed steps and its roofline fraction."""
+    ms, calls = summarise_kernels(diags)
+    k = int(np.argmax(ms))
+    name = KCLS[k]
+    avg_ms = ms[k] / max(calls[k], 1)
+    out = {"kernel": name, "avg_ms": avg_ms, "launches": int(calls[k]),
+           "share": float(ms[k] / ms.sum())}
+    if name in ("far32", "far64", "assemble"):
+        # every launch evaluates the far field of all frequency systems that
+        # are still open; the assembly launch covers all of them exactly
+        units = wl_units if name == "assemble" else None
+        if units is None:
+            return out | {"bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s",
+                          "frac": None, "traffic": None}
+        ach = units * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if name in ("far64", "assemble") else PEAK_FP32_TFLOPS
+        return out | {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                      "frac": ach / peak, "traffic": None, "units_per_launch": units,
+                      "flops_per_unit": FLOPS_PER_UNIT}
+    return out | {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": None, "traffic": None}
+
+
+def cpu_baseline(wl, sample_freqs=2):
+    """The oracle on the host: near field, right-hand side, both DFTs, and the
+    dense assembly + LU of `sample_freqs` of the frequency systems; the
+    per-frequency part is scaled to all systems of one solve."""
+    import scipy.linalg as sla
+
+    import oracle as O
+    V, T = wl.mesh()
+    F = wl.N + 1
+    H = O.num_frequencies_half(F)
+    t0 = time.perf_counter()
+    s, rho, dt = O.frequencies(wl.N, wl.T)
+    b = O.rhs(V, T, wl.N, wl.T)
+    ghat = O.forward_dft(b, rho, H)
+    pairs = O.near_pairs(T)
+    static = O.near_static(V, T, pairs, 5)
+    t_fixed = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    xh = np.zeros((H, len(T)), dtype=complex)
+    for l in range(sample_freqs):
+        A = O.assemble_V(V, T, s[l], pairs=pairs, static=static)
+        xh[l] = sla.lu_solve(sla.lu_factor(A), ghat[l])
+    t_freq = (time.perf_counter() - t1) / sample_freqs
+    t2 = time.perf_counter()
+    O.inverse_dft(xh, rho, F)
+    t_fixed += time.perf_counter() - t2
+    t_solve = t_fixed + H * t_freq
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_freqs} of {H} frequency systems (dense assembly + LU) plus the "
+                      f"near field, right-hand side and both DFTs; per-frequency time scaled "
+                      f"x{H}", "seconds_per_solve": t_solve}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs "
+              f"is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2006_05186_amd import cqm as C
+    from paper_2006_05186_amd.solver import Problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = WORKLOADS[args.workload]
+    ctx = C.cqm_ctx_create(0)
+    main_mode, main_form = C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE
+    r = run_variant(C, Problem, ctx, wl, main_mode, main_form, args.steps, args.warmup, torch)
+    K = args.steps
+    value = K / r["elapsed"]
+    lat_ms = np.asarray(r["lat"]) * 1e3
+    d0 = r["diags"][-1]
+    units = d0["far_units"]
+    rl = roofline(r["diags"], units, main_form, main_mode)
+    out = {
+        "metric": "time-domain CQM-BEM solves/s + p50/p99 latency; kernel entries/s vs VALU peak",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["elapsed"] / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": wl.name, "triangles": len(r["T"]), "N": wl.N, "T": wl.T,
+                   "frequency_systems": wl.N // 2 + 1, "mode": "mixed", "form": "dense",
+                   "pulse": {"direction": wl.wave.direction, "sigma": wl.wave.sigma,
+                             "t0": wl.wave.t0}},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "dominant_kernel": {k: v for k, v in rl.items()
+                            if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "solver": {"total_iters": d0["total_iters"], "max_iters": d0["max_iters"],
+                   "cycles": d0["cycles"], "max_rel_residual": d0["max_rel_residual"],
+                   "t_setup_ms": d0["t_setup_ms"], "t_solve_ms": d0["t_solve_ms"],
+                   "workspace_GB": r["workspace"] / 1e9},
+        "kernel_ms_per_step": dict(zip(KCLS, (summarise_kernels(r["diags"])[0] / K).round(4).tolist())),
+    }
+    golden = os.path.join(ROOT, "tests", "golden", f"{wl.name}.npz")
+    if os.path.exists(golden):
+        ref = np.load(golden)["q"]
+        out["error_vs_oracle"] = rel_err(r["q"], ref, area_of(r["V"], r["T"]))
+    if not args.no_variants:
+        var = {}
+        for name, mode, form, steps in (("fp64_dense", C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE, 10),
+                                        ("mixed_matrix_free", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE, 5),
+                                        ("fp64_matrix_free", C.CQM_FP64_PLAIN, C.CQM_FORM_MATRIX_FREE, 3)):
+            rv = run_variant(C, Problem, ctx, wl, mode, form, steps, 1, torch)
+            ms, calls = summarise_kernels(rv["diags"])
+            v = {"solves_per_s": steps / rv["elapsed"]}
+            for kn in ("far32", "far64"):
+                k = KCLS.index(kn)
+                if calls[k]:
+                    v[f"{kn}_avg_ms"] = ms[k] / calls[k]
+            if os.path.exists(golden):
+                v["error_vs_oracle"] = rel_err(rv["q"], ref, area_of(rv["V"], rv["T"]))
+            var[name] = v
+        # kernel evaluation rate of the matrix-free FP32 far product (all
+        # frequency systems active): one cqm_apply_V probe, timed by events
+        V, T = wl.mesh()
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE)
+        H = wl.N // 2 + 1
+        x = torch.as_tensor(W.random_complex((H, len(T)), seed=3), device="cuda").to(torch.complex64)
+        for _ in range(2):
+            p.apply(x, 0, 32)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(st)
+        for _ in range(reps):
+            p.apply(x, 0, 32)
+        e1.record(st)
+        torch.cuda.synchronize()
+        t_apply = e0.elapsed_time(e1) / reps * 1e-3
+        u = C.cqm_operator_stats(p.handle).far_units
+        var["far32_apply_probe"] = {"ms": t_apply * 1e3, "units_per_s": u / t_apply,
+                                    "entries_per_s": u / 36 / t_apply,
+                                    "tflops": u * FLOPS_PER_UNIT / t_apply / 1e12,
+                                    "frac_fp32_peak": u * FLOPS_PER_UNIT / t_apply / 1e12 / PEAK_FP32_TFLOPS}
+        p.close()
+        out["variants"] = var
+    C.cqm_ctx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,9 +95,10 @@ typedef struct cqm_options {
 /* Kernel classes timed when cqm_options.profile is set. */
 #define CQM_K_FAR32 0    /* matrix-free far-field product, FP32          */
 #define CQM_K_FAR64 1    /* matrix-free far-field product, FP64          */
-#define CQM_K_ASSEMBLE 2 /* dense FP64 assembly of all V(s_l)            */
-#define CQM_K_GEMV32 3   /* stored-operator products, inner precision    */
-#define CQM_K_GEMV64 4   /* stored-operator products, FP64               */
+#define CQM_K_ASSEMBLE 2 /* dense FP64 assembly of all V(s_l), or MACA  */
+#define CQM_K_GEMV32 3   /* stored or compressed operator products, inner
+                            precision                                    */
+#define CQM_K_GEMV64 4   /* stored or compressed operator products, FP64 */
 #define CQM_K_NEAR 5     /* near-field static and per-frequency parts    */
 #define CQM_K_GMRES 6    /* Arnoldi, restart and update kernels          */
 #define CQM_K_OTHER 7    /* right-hand side, DFTs, compression kernels   */

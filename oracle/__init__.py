@@ -12,3 +12,4 @@ follows. The arithmetic is plain NumPy/SciPy in float64/complex128, with no
 blocking or reordering beyond what the definitions state.
 """
 from .cqm import *  # noqa: F401,F403
+from .compress import *  # noqa: F401,F403

@@ -105,6 +105,7 @@ template <typename R>
 void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
               const int* active, hipStream_t s) {
   if (mode_is_h2(p.opt.mode)) {
+    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
     h2_apply<R>(p, l0, nsys, x, xs, y, ys, active, s);
     return;
   }
@@ -140,7 +141,10 @@ void prepare_operator(Problem& p, hipStream_t s) {
     p.static_ready = true;
   }
   if (mode_is_h2(p.opt.mode)) {
-    if (!(p.opt.reuse_operator && p.near_ready)) h2_prepare(p, s);
+    if (!(p.opt.reuse_operator && p.near_ready)) {
+      Timed t(p, CQM_K_ASSEMBLE, s);
+      h2_prepare(p, s);
+    }
     p.near_ready = true;
     return;
   }

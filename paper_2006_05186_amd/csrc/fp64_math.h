@@ -1,0 +1,74 @@
+// FP64 exponential and sine/cosine for the bounded arguments of the kernel
+// exp(-s r) (r at most a few surface diameters, Re s > 0).
+//
+// Published methods (Cody & Waite, "Software Manual for the Elementary
+// Functions", 1980): additive argument reduction by a multi-part constant so
+// that k*C_hi is exact, then a truncated Taylor series on the reduced
+// interval, evaluated by Horner's rule with fused multiply-adds.
+//   exp:    x = k ln2 + r, |r| <= ln2/2, degree 13 (truncation < 5e-18 relative)
+//   sincos: t = k pi/2 + r, |r| <= pi/4, degrees 17 / 18 (truncation < 1e-19)
+// The split constants are ln2 and pi/2 cut into 32/33-bit leading parts and
+// remainders (computed in extended precision); k*hi is exact for |k| < 2^20.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cqm {
+
+__device__ __forceinline__ double exp_nonpos(double x) {
+  // x <= 0 expected; results below the normal range flush to zero
+  if (x < -708.0) return 0.0;
+  const double k = rint(x * 1.4426950408889634);
+  double r = fma(-k, 0.6931471803691238, x);
+  r = fma(-k, 1.9082149292705877e-10, r);
+  double p = 1.6059043836821613e-10;  // 1/13!
+  p = fma(p, r, 2.08767569878681e-09);   // 1/12!
+  p = fma(p, r, 2.505210838544172e-08);  // 1/11!
+  p = fma(p, r, 2.755731922398589e-07);  // 1/10!
+  p = fma(p, r, 2.7557319223985893e-06); // 1/9!
+  p = fma(p, r, 2.48015873015873e-05);   // 1/8!
+  p = fma(p, r, 0.0001984126984126984);  // 1/7!
+  p = fma(p, r, 0.001388888888888889);   // 1/6!
+  p = fma(p, r, 0.008333333333333333);   // 1/5!
+  p = fma(p, r, 0.041666666666666664);   // 1/4!
+  p = fma(p, r, 0.16666666666666666);    // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ void sincos_bounded(double t, double* s, double* c) {
+  const double k = rint(t * 0.6366197723675814);
+  double r = fma(-k, 1.5707963267341256, t);
+  r = fma(-k, 6.077100506303966e-11, r);
+  r = fma(-k, 2.0222662487959506e-21, r);
+  const double r2 = r * r;
+  // sin r = r (1 - r2/3! + r2^2/5! - ...), through r^17
+  double ps = 2.8114572543455206e-15;        // 1/17!
+  ps = fma(ps, r2, -7.647163731819816e-13);  // -1/15!
+  ps = fma(ps, r2, 1.6059043836821613e-10);  // 1/13!
+  ps = fma(ps, r2, -2.505210838544172e-08);  // -1/11!
+  ps = fma(ps, r2, 2.7557319223985893e-06);  // 1/9!
+  ps = fma(ps, r2, -0.0001984126984126984);  // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);    // 1/5!
+  ps = fma(ps, r2, -0.16666666666666666);    // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  // cos r = 1 - r2/2! + r2^2/4! - ..., through r^18
+  double pc = -1.5619206968586225e-16;       // -1/18!
+  pc = fma(pc, r2, 4.779477332387385e-14);   // 1/16!
+  pc = fma(pc, r2, -1.1470745597729725e-11); // -1/14!
+  pc = fma(pc, r2, 2.08767569878681e-09);    // 1/12!
+  pc = fma(pc, r2, -2.755731922398589e-07);  // -1/10!
+  pc = fma(pc, r2, 2.48015873015873e-05);    // 1/8!
+  pc = fma(pc, r2, -0.001388888888888889);   // -1/6!
+  pc = fma(pc, r2, 0.041666666666666664);    // 1/4!
+  pc = fma(pc, r2, -0.5);                    // -1/2!
+  const double cr = fma(pc, r2, 1.0);
+  const int q = ((int)k) & 3;
+  const double a = (q & 1) ? cr : sr;
+  const double b = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -a : a;
+  *c = ((q + 1) & 2) ? -b : b;
+}
+
+}  // namespace cqm

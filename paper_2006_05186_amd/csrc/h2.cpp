@@ -1,16 +1,203 @@
-// Compressed operator: H2 in space x MACA across frequencies (placeholder
-// until the compressed path is built; the modes are rejected at solve time).
-#include "internal.h"
+// Compressed operator driver: structure and tables at problem creation,
+// MACA of all blocks on the GPU when the operator is prepared, products for
+// the GMRES iterations.
+#include <algorithm>
+#include <numeric>
+
+#include "h2_internal.h"
 
 namespace cqm {
-size_t h2_workspace_bytes(const Problem&) { return 0; }
-void h2_prepare(Problem&, hipStream_t) { throw Error(CQM_EINVAL, "compressed modes are not available in this build"); }
-void h2_release(Problem&) {}
+bool mode_is_mixed(int mode);
+
+namespace {
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T> T* up(const std::vector<T>& h) {
+  if (h.empty()) return nullptr;
+  T* d = nullptr;
+  CQM_HIP(hipMalloc(&d, sizeof(T) * h.size()));
+  CQM_HIP(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return d;
+}
+template <typename T> void release(T*& d) {
+  if (d) (void)hipFree(d);
+  d = nullptr;
+}
+
+void setup_structure(Problem& p) {
+  if (!p.h2) p.h2 = new H2Operator();
+  H2Operator& h = *p.h2;
+  if (h.built) return;
+  require(p.opt.cheb_m <= 4, CQM_EINVAL, "compressed modes support cheb_m <= 4 (rank <= 64)");
+  h2_build_structure(p, h);
+  h.store_fp64 = mode_is_mixed(p.opt.mode) ? 0 : 1;
+  const int ncl = (int)h.cl.size(), nleaf = (int)h.leaves.size();
+  // level lists followed by the leaves in leaf order
+  std::vector<int> lvl;
+  h.level_off.assign(h.nlevels + 1, 0);
+  for (int lv = 0; lv < h.nlevels; ++lv) {
+    h.level_off[lv] = (int)lvl.size();
+    lvl.insert(lvl.end(), h.by_level[lv].begin(), h.by_level[lv].end());
+  }
+  h.level_off[h.nlevels] = (int)lvl.size();
+  lvl.insert(lvl.end(), h.leaves.begin(), h.leaves.end());
+  // core blocks per row cluster (CSR over clusters)
+  std::vector<int> crow(ncl + 1, 0), clist;
+  for (int c = 0; c < ncl; ++c) {
+    clist.insert(clist.end(), h.core_by_row[c].begin(), h.core_by_row[c].end());
+    crow[c + 1] = (int)clist.size();
+  }
+  // expanded-far and near blocks per leaf of their row cluster
+  std::vector<std::vector<LeafTask>> per_leaf(nleaf);
+  std::vector<int> leaf_begin(nleaf);
+  for (int k = 0; k < nleaf; ++k) leaf_begin[k] = h.cl[h.leaves[k]].begin;
+  for (int b = 0; b < (int)h.blocks.size(); ++b) {
+    const BlockDesc& B = h.blocks[b];
+    if (B.kind == kFarCore) continue;
+    const Cluster& R = h.cl[B.r];
+    int k = (int)(std::lower_bound(leaf_begin.begin(), leaf_begin.end(), R.begin) - leaf_begin.begin());
+    for (; k < nleaf && leaf_begin[k] < R.end; ++k) per_leaf[k].push_back(LeafTask{b, leaf_begin[k] - R.begin});
+  }
+  std::vector<int> trow(nleaf + 1, 0);
+  std::vector<LeafTask> tasks;
+  for (int k = 0; k < nleaf; ++k) {
+    tasks.insert(tasks.end(), per_leaf[k].begin(), per_leaf[k].end());
+    trow[k + 1] = (int)tasks.size();
+  }
+  // cluster table: begin, end, parent, leaf_id; then two sons per cluster
+  std::vector<int> clt(6 * ncl);
+  for (int c = 0; c < ncl; ++c) {
+    clt[4 * c] = h.cl[c].begin;
+    clt[4 * c + 1] = h.cl[c].end;
+    clt[4 * c + 2] = h.cl[c].parent;
+    clt[4 * c + 3] = h.cl[c].leaf_id;
+    clt[4 * ncl + 2 * c] = h.cl[c].son[0];
+    clt[4 * ncl + 2 * c + 1] = h.cl[c].son[1];
+  }
+  std::vector<float> U32(h.Uleaf.begin(), h.Uleaf.end()), E32(h.E.begin(), h.E.end());
+  h.perm_d = up(h.perm);
+  h.nodes_d = up(h.nodes);
+  h.U_d = up(h.Uleaf);
+  h.U32_d = up(U32);
+  h.uleaf_off_d = up(h.uleaf_off);
+  h.E_d = up(h.E);
+  h.E32_d = up(E32);
+  h.Ufull_d = up(h.Ufull);
+  h.ufull_off_d = up(h.ufull_off);
+  h.cl_d = up(clt);
+  h.blocks_d = up(h.blocks);
+  h.ranks.assign(h.blocks.size(), 0);
+  h.ranks_d = up(h.ranks);
+  h.core_rowptr_d = up(crow);
+  h.core_list_d = up(clist.empty() ? std::vector<int>{0} : clist);
+  h.task_rowptr_d = up(trow);
+  h.tasks_d = up(tasks.empty() ? std::vector<LeafTask>{LeafTask{0, 0}} : tasks);
+  h.level_cl_d = up(lvl);
+  h.built = true;
+}
+
+void set_views(Problem& p) {
+  H2Operator& h = *p.h2;
+  require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached");
+  char* base = p.ws + p.lay.partial;
+  h.cstore_d = base + h.off_cstore;
+  h.dvec_d = (cf64*)(base + h.off_dvec);
+  h.stage_d = (cf64*)(base + h.off_stage);
+  h.xhat_d = base + h.off_xhat;
+  h.yhat_d = base + h.off_yhat;
+  h.xp_d = base + h.off_xp;
+  h.yp_d = base + h.off_yp;
+}
+}  // namespace
+
+size_t h2_workspace_bytes(const Problem& pc) {
+  Problem& p = const_cast<Problem&>(pc);
+  setup_structure(p);
+  H2Operator& h = *p.h2;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += align256(b);
+    return o;
+  };
+  h.off_cstore = take((size_t)h.cstore_elems * (h.store_fp64 ? sizeof(cf64) : sizeof(cf32)));
+  h.off_dvec = take((size_t)h.dvec_elems * sizeof(cf64));
+  h.off_stage = take((size_t)h.stage_elems * sizeof(cf64));
+  h.off_xhat = take(h2_apply_scratch_bytes(h, p.Fsys));
+  h.off_yhat = take(h2_apply_scratch_bytes(h, p.Fsys));
+  h.off_xp = take(h2_perm_scratch_bytes(h, p.Fsys));
+  h.off_yp = take(h2_perm_scratch_bytes(h, p.Fsys));
+  h.total = off;
+  return off;
+}
+
+void h2_prepare(Problem& p, hipStream_t s) {
+  setup_structure(p);
+  set_views(p);
+  H2Operator& h = *p.h2;
+  for (auto& bt : h.batches) {
+    const int nb = bt.second - bt.first;
+    if (nb <= 0) continue;
+    launch_maca(p, h, bt.first, nb, s);
+    launch_maca_finalize_batch(p, h, bt.first, nb, s);
+  }
+  CQM_HIP(hipMemcpyAsync(h.ranks.data(), h.ranks_d, sizeof(int) * h.ranks.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+  h.max_rank = 0;
+  double sum = 0.0;
+  int64_t bytes = 0;
+  const size_t es = h.store_fp64 ? sizeof(cf64) : sizeof(cf32);
+  for (size_t b = 0; b < h.blocks.size(); ++b) {
+    h.max_rank = std::max(h.max_rank, h.ranks[b]);
+    sum += h.ranks[b];
+    bytes += (int64_t)h.ranks[b] * ((int64_t)h.blocks[b].arows * h.blocks[b].acols * es + (int64_t)h.nsys * 16);
+  }
+  bytes += (int64_t)(h.Uleaf.size() + h.E.size()) * 8;
+  h.mean_rank = h.blocks.empty() ? 0.0 : sum / h.blocks.size();
+  h.bytes = bytes;
+}
+
 template <typename R>
-void h2_apply(Problem&, int, int, const cplx<R>*, int64_t, cplx<R>*, int64_t, const int*, hipStream_t) {
-  throw Error(CQM_EINVAL, "compressed modes are not available in this build");
+void h2_apply(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* /*active*/, hipStream_t s) {
+  set_views(p);
+  launch_h2_apply<R>(p, *p.h2, l0, nsys, x, xs, y, ys, nullptr, s);
 }
 template void h2_apply<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
 template void h2_apply<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);
-void h2_stats(const Problem&, cqm_diag*) {}
+
+void h2_stats(const Problem& p, cqm_diag* d) {
+  if (!p.h2) return;
+  const H2Operator& h = *p.h2;
+  d->max_rank = h.max_rank;
+  d->mean_rank = h.mean_rank;
+  d->n_far_blocks = h.n_far;
+  d->n_near_blocks = h.n_near;
+  d->operator_bytes = h.bytes;
+}
+
+void h2_release(Problem& p) {
+  if (!p.h2) return;
+  H2Operator& h = *p.h2;
+  release(h.perm_d);
+  release(h.nodes_d);
+  release(h.U_d);
+  release(h.U32_d);
+  release(h.uleaf_off_d);
+  release(h.E_d);
+  release(h.E32_d);
+  release(h.Ufull_d);
+  release(h.ufull_off_d);
+  release(h.cl_d);
+  release(h.blocks_d);
+  release(h.ranks_d);
+  release(h.core_rowptr_d);
+  release(h.core_list_d);
+  release(h.task_rowptr_d);
+  release(h.tasks_d);
+  release(h.level_cl_d);
+  delete p.h2;
+  p.h2 = nullptr;
+}
+
 }  // namespace cqm

@@ -15,6 +15,7 @@
 // transcendentals (v_exp_f32 on a base-2 exponent, v_sin_f32/v_cos_f32 on a
 // phase in revolutions) and five VALU operations.
 #include "device_util.h"
+#include "fp64_math.h"
 
 namespace cqm {
 
@@ -37,11 +38,11 @@ template <> struct KMath<float> {
 };
 template <> struct KMath<double> {
   static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-  // e = exp(ea r), (c, sn) = (cos, sin)(pb r)
+  // e = exp(ea r) (ea <= 0), (c, sn) = (cos, sin)(pb r)
   static __device__ __forceinline__ void eval(double ea, double pb, double r, double& e,
                                               double& c, double& sn) {
-    e = exp(ea * r);
-    sincos(pb * r, &sn, &c);
+    e = exp_nonpos(ea * r);
+    sincos_bounded(pb * r, &sn, &c);
   }
 };
 
@@ -192,66 +193,96 @@ __global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, in
   y[(int64_t)l * ys + i] = o;
 }
 
-// Dense assembly: entries of the far pairs of all frequency systems in FP64
-// (optionally also stored as complex64).  One thread per (target i, source j)
-// pair and FT frequencies; 64 consecutive sources per workgroup so stores are
-// coalesced along rows.  Near pairs are left for the near-field scatter.
+// Dense assembly of the far pairs of all frequency systems, FP64 entries (and
+// an optional complex64 copy).  V(s) is symmetric, so only tiles I <= J of a
+// 16 x 16 tiling are evaluated: each thread computes one pair (i, j), i <= j,
+// for FT frequencies, stores it along rows (coalesced) and, through an LDS
+// transpose, stores the mirrored entry (j, i) along rows as well.  Near pairs
+// are left for the near-field scatter.
+constexpr int kAt = 16;
 template <int FT>
-__global__ __launch_bounds__(64) void k_dense_assemble(const double4* __restrict__ pts,
-                                                       const int4* __restrict__ vid, int M,
-                                                       const double* __restrict__ ea,
-                                                       const double* __restrict__ pb, int nsys,
-                                                       cf64* __restrict__ d64,
-                                                       cf32* __restrict__ d32) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  const int i = blockIdx.y;
-  const int l0 = blockIdx.z * FT;
+__global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __restrict__ pts,
+                                                              const int4* __restrict__ vid, int M,
+                                                              const double* __restrict__ ea,
+                                                              const double* __restrict__ pb,
+                                                              int nsys, cf64* __restrict__ d64,
+                                                              cf32* __restrict__ d32) {
+  // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I
+  const long long kk = blockIdx.x;
+  long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
+  while (J * (J + 1) / 2 > kk) --J;
+  while ((J + 1) * (J + 2) / 2 <= kk) ++J;
+  const int I = (int)(kk - J * (J + 1) / 2);
+  const int tx = threadIdx.x % kAt, ty = threadIdx.x / kAt;
+  const int i = I * kAt + ty, j = (int)J * kAt + tx;
+  const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
-  if (j >= M) return;
-  if (share_vertex(vid[i], vid[j])) return;
-  double sx[kQ], sy[kQ], sz[kQ], sw[kQ];
+  __shared__ cf64 tile[FT][kAt][kAt + 1];
+  bool live = i < M && j < M && (I != J || i <= j);
+  if (live) live = !share_vertex(vid[i], vid[j]);
+  double vre[FT], vim[FT];
 #pragma unroll
-  for (int b = 0; b < kQ; ++b) {
-    const double4 q = pts[j * kQ + b];
-    sx[b] = q.x;
-    sy[b] = q.y;
-    sz[b] = q.z;
-    sw[b] = q.w;
-  }
-  double fe[FT], fp[FT], vre[FT], vim[FT];
+  for (int l = 0; l < FT; ++l) vre[l] = vim[l] = 0.0;
+  if (live) {
+    double sx[kQ], sy[kQ], sz[kQ], sw[kQ];
 #pragma unroll
-  for (int l = 0; l < FT; ++l) {
-    fe[l] = l < nl ? ea[l0 + l] : 0.0;
-    fp[l] = l < nl ? pb[l0 + l] : 0.0;
-    vre[l] = 0.0;
-    vim[l] = 0.0;
-  }
-  for (int a = 0; a < kQ; ++a) {
-    const double4 t = pts[i * kQ + a];
-#pragma unroll 1
     for (int b = 0; b < kQ; ++b) {
-      const double dx = t.x - sx[b], dy = t.y - sy[b], dz = t.z - sz[b];
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double w = t.w * sw[b] / r;
+      const double4 q = pts[j * kQ + b];
+      sx[b] = q.x;
+      sy[b] = q.y;
+      sz[b] = q.z;
+      sw[b] = q.w;
+    }
+    double fe[FT], fp[FT];
 #pragma unroll
-      for (int l = 0; l < FT; ++l) {
-        double e, c, sn;
-        KMath<double>::eval(fe[l], fp[l], r, e, c, sn);
-        e *= w;
-        vre[l] += e * c;
-        vim[l] -= e * sn;
+    for (int l = 0; l < FT; ++l) {
+      fe[l] = l < nl ? ea[l0 + l] : 0.0;
+      fp[l] = l < nl ? pb[l0 + l] : 0.0;
+    }
+    for (int a = 0; a < kQ; ++a) {
+      const double4 t = pts[i * kQ + a];
+#pragma unroll 1
+      for (int b = 0; b < kQ; ++b) {
+        const double dx = t.x - sx[b], dy = t.y - sy[b], dz = t.z - sz[b];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double w = t.w * sw[b] / r;
+#pragma unroll
+        for (int l = 0; l < FT; ++l) {
+          double e, c, sn;
+          KMath<double>::eval(fe[l], fp[l], r, e, c, sn);
+          e *= w;
+          vre[l] += e * c;
+          vim[l] -= e * sn;
+        }
       }
     }
   }
-  const int64_t base = (int64_t)i * M + j;
   const int64_t MM = (int64_t)M * M;
 #pragma unroll
-  for (int l = 0; l < FT; ++l)
-    if (l < nl) {
-      const double re = vre[l] * kInv4Pi, im = vim[l] * kInv4Pi;
-      d64[(int64_t)(l0 + l) * MM + base] = cf64{re, im};
-      if (d32) d32[(int64_t)(l0 + l) * MM + base] = cf32{(float)re, (float)im};
+  for (int l = 0; l < FT; ++l) {
+    const double re = vre[l] * kInv4Pi, im = vim[l] * kInv4Pi;
+    tile[l][ty][tx] = cf64{re, im};
+    if (live && l < nl) {
+      const int64_t o = (int64_t)(l0 + l) * MM + (int64_t)i * M + j;
+      d64[o] = cf64{re, im};
+      if (d32) d32[o] = cf32{(float)re, (float)im};
     }
+  }
+  __syncthreads();
+  // mirrored entries: thread (ty, tx) writes (j', i') = (J*16+ty, I*16+tx)
+  const int jm = (int)J * kAt + ty, im_ = I * kAt + tx;
+  bool live_m = jm < M && im_ < M && (I != J || im_ < jm);
+  if (live_m) live_m = !share_vertex(vid[im_], vid[jm]);
+  if (live_m) {
+#pragma unroll
+    for (int l = 0; l < FT; ++l)
+      if (l < nl) {
+        const cf64 v = tile[l][tx][ty];
+        const int64_t o = (int64_t)(l0 + l) * MM + (int64_t)jm * M + im_;
+        d64[o] = v;
+        if (d32) d32[o] = cf32{(float)v.re, (float)v.im};
+      }
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -357,13 +388,27 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
   CQM_HIP(hipGetLastError());
 }
 
-void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
+template <int FT>
+static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
   const int M = (int)p.M;
-  constexpr int FT = 8;
-  dim3 grid((M + 63) / 64, M, (p.Fsys + FT - 1) / FT);
-  hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(64), 0, s, p.dev.pts64, p.dev.vid, M,
-                     p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32);
+  const int nt = (M + kAt - 1) / kAt;
+  dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
+  hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64, p.dev.vid,
+                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32);
   CQM_HIP(hipGetLastError());
+}
+
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
+  // frequency tile with the fewest padding slots (11 | 33, 13 | 65, 9 | 9)
+  const int opts[3] = {13, 11, 9};
+  int FT = 13, waste = 1 << 30;
+  for (int f : opts) {
+    const int w = ((p.Fsys + f - 1) / f) * f - p.Fsys;
+    if (w < waste) waste = w, FT = f;
+  }
+  if (FT == 13) dense_assemble_ft<13>(p, d64, d32, s);
+  else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, s);
+  else dense_assemble_ft<9>(p, d64, d32, s);
 }
 
 template void launch_far_apply<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,

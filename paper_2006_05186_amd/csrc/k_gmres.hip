@@ -10,8 +10,8 @@
 namespace cqm {
 
 namespace {
-constexpr int kGB = 256;    // threads per system
-constexpr int kChunk = 8;   // inner products per pass over w
+constexpr int kGB = 1024;   // threads per system (16 waves)
+constexpr int kChunk = 16;  // inner products per pass over w (one pass for j < 16)
 constexpr int kMaxM = 64;   // largest supported restart length
 constexpr double kFloorTol = 1e-13;  // stagnation below this counts as converged
 }  // namespace
@@ -106,29 +106,45 @@ __global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __re
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* __restrict__ basis,
-                                                 cf64* __restrict__ H, double* __restrict__ cs,
-                                                 cf64* __restrict__ sn, cf64* __restrict__ g,
-                                                 double* __restrict__ sysd, int* __restrict__ sysi) {
-  __shared__ double red[16 * 2 * kChunk];
+// One Arnoldi step of every open system.  Classical Gram-Schmidt with the
+// DGKS criterion: a second pass is made only if the first one removed more
+// than about 30% of the norm of w (||w'||^2 < 0.49 ||w||^2, with ||w'||^2
+// accumulated while w is updated).  BS threads per system.
+template <typename R, int BS>
+__global__ __launch_bounds__(BS) void k_arnoldi(int M, int m, int j, cplx<R>* __restrict__ basis,
+                                                cf64* __restrict__ H, double* __restrict__ cs,
+                                                cf64* __restrict__ sn, cf64* __restrict__ g,
+                                                double* __restrict__ sysd, int* __restrict__ sysi) {
+  constexpr int NW = BS / 64;
+  __shared__ double red[NW * (2 * kChunk + 1)];
   __shared__ cf64 coef[kMaxM + 1];
   __shared__ cf64 hacc[kMaxM + 2];
+  __shared__ double rc_s[kMaxM];  // previous rotations, prefetched for thread 0
+  __shared__ cf64 rs_s[kMaxM];
+  __shared__ cf64 g_j;
   const int l = blockIdx.x;
   int* st = sysi + kSysiStride * l;
   if (!st[1]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = kGB / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   cplx<R>* V = basis + (int64_t)l * (m + 1) * M;
   cplx<R>* w = V + (int64_t)(j + 1) * M;
-  for (int k = tid; k <= j + 1; k += kGB) hacc[k] = cf64{0.0, 0.0};
+  for (int k = tid; k <= j + 1; k += BS) hacc[k] = cf64{0.0, 0.0};
+  for (int k = tid; k < j; k += BS) {
+    rc_s[k] = cs[(int64_t)l * m + k];
+    rs_s[k] = sn[(int64_t)l * m + k];
+  }
+  if (tid == 0) g_j = g[(int64_t)l * (m + 1) + j];
+  double nrm2 = 0.0;  // ||w||^2 after the last update
   for (int pass = 0; pass < 2; ++pass) {
-    // coefficients c_k = <v_k, w>, k = 0..j, in chunks of kChunk
+    double w2 = 0.0;  // ||w||^2 before this pass
     for (int kc = 0; kc <= j; kc += kChunk) {
       double ar[kChunk], ai[kChunk];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) ar[u] = ai[u] = 0.0;
-      for (int i = tid; i < M; i += kGB) {
+      double ww = 0.0;
+      for (int i = tid; i < M; i += BS) {
         const cplx<R> x = w[i];
+        if (kc == 0) ww += (double)x.re * x.re + (double)x.im * x.im;
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
           if (kc + u <= j) {
@@ -142,26 +158,35 @@ __global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* _
         ar[u] = wave_sum(ar[u]);
         ai[u] = wave_sum(ai[u]);
       }
+      ww = wave_sum(ww);
       __syncthreads();
-      if (lane == 0)
+      if (lane == 0) {
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
           red[(wv * kChunk + u) * 2] = ar[u];
           red[(wv * kChunk + u) * 2 + 1] = ai[u];
         }
+        red[NW * 2 * kChunk + wv] = ww;
+      }
       __syncthreads();
       if (tid < kChunk && kc + tid <= j) {
         double sr = 0.0, si = 0.0;
-        for (int q = 0; q < nw; ++q) {
+        for (int q = 0; q < NW; ++q) {
           sr += red[(q * kChunk + tid) * 2];
           si += red[(q * kChunk + tid) * 2 + 1];
         }
         coef[kc + tid] = cf64{sr, si};
       }
+      if (kc == 0) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += red[NW * 2 * kChunk + q];
+        w2 = t;
+      }
     }
     __syncthreads();
-    // w <- w - sum_k c_k v_k
-    for (int i = tid; i < M; i += kGB) {
+    // w <- w - sum_k c_k v_k, accumulating ||w||^2 of the result
+    double acc = 0.0;
+    for (int i = tid; i < M; i += BS) {
       const cplx<R> x = w[i];
       double re = x.re, im = x.im;
       for (int k = 0; k <= j; ++k) {
@@ -174,18 +199,24 @@ __global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* _
       o.re = (R)re;
       o.im = (R)im;
       w[i] = o;
+      acc += (double)o.re * o.re + (double)o.im * o.im;
     }
-    for (int k = tid; k <= j; k += kGB) {
+    for (int k = tid; k <= j; k += BS) {
       hacc[k].re += coef[k].re;
       hacc[k].im += coef[k].im;
     }
+    acc = wave_sum(acc);
+    __syncthreads();
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    nrm2 = 0.0;
+    for (int q = 0; q < NW; ++q) nrm2 += red[q];
+    if (nrm2 >= 0.49 * w2) break;  // block-uniform decision
     __syncthreads();
   }
-  double acc = 0.0;
-  for (int i = tid; i < M; i += kGB) acc += (double)w[i].re * w[i].re + (double)w[i].im * w[i].im;
-  const double nr = sqrt(block_sum(acc, red));
+  const double nr = sqrt(nrm2);
   const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-  for (int i = tid; i < M; i += kGB) {
+  for (int i = tid; i < M; i += BS) {
     cplx<R> o = w[i];
     o.re = (R)(o.re * inv);
     o.im = (R)(o.im * inv);
@@ -201,8 +232,8 @@ __global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* _
     h[j + 1] = cf64{nr, 0.0};
     // previous rotations: (h_k, h_k+1) <- (c h_k + s h_k+1, -conj(s) h_k + c h_k+1)
     for (int k = 0; k < j; ++k) {
-      const double c = csl[k];
-      const cf64 s = snl[k], a = h[k], b = h[k + 1];
+      const double c = rc_s[k];
+      const cf64 s = rs_s[k], a = h[k], b = h[k + 1];
       h[k] = cf64{c * a.re + s.re * b.re - s.im * b.im, c * a.im + s.re * b.im + s.im * b.re};
       h[k + 1] = cf64{-(s.re * a.re + s.im * a.im) + c * b.re, -(s.re * a.im - s.im * a.re) + c * b.im};
     }
@@ -227,7 +258,7 @@ __global__ __launch_bounds__(kGB) void k_arnoldi(int M, int m, int j, cplx<R>* _
     snl[j] = s;
     h[j] = rr;
     for (int k = 0; k <= j; ++k) Hc[k] = h[k];
-    const cf64 gj = gl[j];
+    const cf64 gj = g_j;
     gl[j + 1] = cf64{-(s.re * gj.re + s.im * gj.im), -(s.re * gj.im - s.im * gj.re)};
     gl[j] = cf64{c * gj.re, c * gj.im};
     const double res = sqrt(gl[j + 1].re * gl[j + 1].re + gl[j + 1].im * gl[j + 1].im);
@@ -285,9 +316,15 @@ void launch_cycle_start(const GmresState& st, const cf64* r, double outer_tol, d
                      (cplx<R>*)st.basis, st.g, st.sysd, st.sysi, r, outer_tol, inner_tol);
   CQM_HIP(hipGetLastError());
 }
+// Threads per system: latency of the block reductions dominates for short
+// vectors, memory parallelism for long ones.
 template <typename R> void launch_arnoldi(const GmresState& st, int j, hipStream_t s) {
-  hipLaunchKernelGGL((k_arnoldi<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m, j,
-                     (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
+  if (st.M < 3072)
+    hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(st.nsys), dim3(256), 0, s, st.M, st.m, j,
+                       (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
+  else
+    hipLaunchKernelGGL((k_arnoldi<R, 1024>), dim3(st.nsys), dim3(1024), 0, s, st.M, st.m, j,
+                       (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
   CQM_HIP(hipGetLastError());
 }
 template <typename R> void launch_cycle_finish(const GmresState& st, cf64* x, hipStream_t s) {

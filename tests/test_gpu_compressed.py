@@ -1,0 +1,81 @@
+"""GPU parity of the compressed operator (H2 x MACA) against the oracle's
+compressed operator, and of the compressed solve against the oracle's solve
+with the same compressed operator."""
+import sys
+
+import numpy as np
+import pytest
+
+import cqm_workloads as W
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_05186_amd import cqm as C  # noqa: E402
+from paper_2006_05186_amd.solver import Problem  # noqa: E402
+
+N, TEND, NMIN, ETA, M_CHEB = 16, 2.0, 8, 1.0, 3
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = C.cqm_ctx_create(0)
+    yield c
+    C.cqm_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def case():
+    V, T = W.icosphere(2)
+    s, _, _ = O.frequencies(N, TEND)
+    dense = O.dense_tensor(V, T, s)
+    return V, T, s, dense
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-10])
+def test_compressed_operator_matches_oracle(ctx, case, eps):
+    V, T, s, dense = case
+    say(f"compressed apply eps={eps}")
+    op = O.build_compressed(V, T, s, NMIN, ETA, M_CHEB, eps, dense=dense)
+    x = W.random_complex((len(s), len(T)), seed=11)
+    ref = O.compressed_matvec(op, x)
+    exact = np.stack([dense[:, :, l] @ x[l] for l in range(len(s))])
+    for mode, tol in ((C.CQM_FP64_H2ACA, 1e-12), (C.CQM_MIXED_H2ACA, 1e-6)):
+        p = Problem(ctx, V, T, N, TEND, mode=mode, n_min=NMIN, eta=ETA, cheb_m=M_CHEB, eps_aca=eps)
+        y = p.apply(torch.as_tensor(x, device="cuda"), 0, 64).cpu().numpy()
+        st = C.cqm_operator_stats(p.handle)
+        ranks = sorted(b["rank"] for b in op["blocks"])
+        say(f"  mode={mode} blocks far/near {st.n_far_blocks}/{st.n_near_blocks} "
+            f"(oracle {len(op['far'])}/{len(op['near'])}) max rank {st.max_rank} (oracle {ranks[-1]})")
+        assert (st.n_far_blocks, st.n_near_blocks) == (len(op["far"]), len(op["near"]))
+        # same algorithm: agreement far below the approximation error, up to
+        # pivot choices that floating-point near-ties may flip (bounded by eps)
+        for l in range(len(s)):
+            e_or = np.linalg.norm(y[l] - ref[l]) / np.linalg.norm(ref[l])
+            e_ex = np.linalg.norm(y[l] - exact[l]) / np.linalg.norm(exact[l])
+            assert e_or < max(tol, 10 * eps), (mode, l, e_or)
+            assert e_ex < 1e-3, (mode, l, e_ex)
+        p.close()
+
+
+def test_compressed_solve_matches_oracle_compressed_solve(ctx, case):
+    V, T, s, dense = case
+    eps = 1e-10
+    say("compressed solve vs oracle compressed solve")
+    qref, im_ref, _ = O.solve_compressed(V, T, N, TEND, NMIN, ETA, M_CHEB, eps)
+    _, _, area = O.triangle_quadrature(V, T)
+    for mode in (C.CQM_FP64_H2ACA, C.CQM_MIXED_H2ACA):
+        p = Problem(ctx, V, T, N, TEND, mode=mode, n_min=NMIN, eta=ETA, cheb_m=M_CHEB, eps_aca=eps)
+        p.set_plane_wave()
+        q, rc, d = p.solve()
+        err = O.rel_error(q.cpu().numpy(), qref, area)
+        say(f"  mode={mode} rc={rc} err vs oracle compressed {err:.2e} imag {d.imag_ratio:.1e} "
+            f"(oracle {im_ref:.1e})")
+        assert rc == C.CQM_OK and err < 1e-6
+        p.close()
