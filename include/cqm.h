@@ -199,6 +199,59 @@ int cqm_near_entries(cqm_problem_t p, int64_t* nnz, int32_t* row_ptr,
 /* Operator statistics after a solve or apply (host struct; solve fields 0). */
 int cqm_operator_stats(cqm_problem_t p, cqm_diag* out);
 
+/* ------------------------------------------------------------ serving */
+/* A server admits solve requests as they arrive, keeps every admitted
+ * request's frequency-system states on the device and advances all of them
+ * together, one GMRES restart cycle at a time; requests join and leave at
+ * cycle boundaries (continuous batching).  Device memory comes from one arena
+ * of hbm_budget bytes allocated at creation: a request is admitted when its
+ * state (and, on a cache miss, its operator) fits, otherwise it waits; a
+ * request that can never fit is rejected with CQM_ENOMEM.  Requests with the
+ * same mesh, N and T share one operator (operator cache). */
+typedef struct cqm_server_opts {
+  int32_t max_active;      /* requests advanced together                 (16) */
+  int32_t cache_operators; /* share operators of identical mesh, N, T     (1) */
+  int32_t reserved[6];
+  cqm_options solver;      /* options of every request (mode, form, tolerances) */
+} cqm_server_opts;
+
+typedef struct cqm_request {
+  const double* vertices;  /* host, nv x 3 (copied at submit) */
+  int64_t nv;
+  const int32_t* tris;     /* host, M x 3 (copied at submit) */
+  int64_t M;
+  int32_t N;
+  double T;
+  double direction[3];     /* plane wave g_D = -A exp(-((t - x.d - t0)/sigma)^2) */
+  double sigma, t0, amplitude;
+} cqm_request;
+
+typedef struct cqm_server_stats {
+  int64_t submitted, completed, rejected, active, queued, peak_active;
+  int64_t arena_bytes, peak_arena_bytes, operators_built, operator_cache_hits, cycles;
+  int64_t reserved[5];
+} cqm_server_stats_t;
+
+/* Default server options (host). */
+int cqm_server_default_options(cqm_server_opts* opts);
+/* Start a server on ctx's device with an arena of hbm_budget bytes. */
+int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* opts,
+                      cqm_server_t* out);
+/* Queue a request (mesh copied); *ticket identifies it.  Returns at once. */
+int cqm_server_submit(cqm_server_t s, const cqm_request* req, uint64_t* ticket);
+/* *done: 0 queued or running, 1 finished (return value: the request's
+ * CQM_OK / CQM_ENOCONV / CQM_ENAN), -1 rejected (return value CQM_ENOMEM or
+ * CQM_EINVAL).  When finished, q_out (host, (N+1) x M doubles, may be NULL),
+ * diag (may be NULL) and latency_ms (submit to completion, may be NULL) are
+ * written.  A finished ticket stays readable until the server is destroyed. */
+int cqm_server_poll(cqm_server_t s, uint64_t ticket, int32_t* done, double* q_out,
+                    cqm_diag* diag, double* latency_ms);
+/* Block until every submitted request has finished or been rejected. */
+int cqm_server_drain(cqm_server_t s);
+int cqm_server_stats(cqm_server_t s, cqm_server_stats_t* out);
+/* Drain, stop the worker and release the arena. */
+int cqm_server_destroy(cqm_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,9 @@ __all__ = [
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
     "cqm_frequencies", "cqm_apply_V", "cqm_near_entries", "cqm_operator_stats",
-    "EXPORTED_SYMBOLS",
+    "cqm_server_opts", "cqm_request", "cqm_server_stats_t", "cqm_server_default_options",
+    "cqm_server_create", "cqm_server_submit", "cqm_server_poll", "cqm_server_drain",
+    "cqm_server_stats", "cqm_server_destroy", "EXPORTED_SYMBOLS",
 ]
 
 CQM_OK, CQM_EINVAL, CQM_ENOMEM, CQM_ENOCONV, CQM_ENAN, CQM_EDEVICE = 0, -1, -2, -3, -4, -5
@@ -34,6 +36,8 @@ EXPORTED_SYMBOLS = [
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
     "cqm_frequencies", "cqm_apply_V", "cqm_near_entries", "cqm_operator_stats",
+    "cqm_server_default_options", "cqm_server_create", "cqm_server_submit", "cqm_server_poll",
+    "cqm_server_drain", "cqm_server_stats", "cqm_server_destroy",
 ]
 
 
@@ -75,6 +79,28 @@ class cqm_diag(ctypes.Structure):
         return out
 
 
+class cqm_server_opts(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("cache_operators", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6), ("solver", cqm_options)]
+
+
+class cqm_request(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_void_p), ("nv", ctypes.c_int64), ("tris", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int32), ("T", ctypes.c_double),
+                ("direction", ctypes.c_double * 3), ("sigma", ctypes.c_double),
+                ("t0", ctypes.c_double), ("amplitude", ctypes.c_double)]
+
+
+class cqm_server_stats_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "completed", "rejected", "active", "queued", "peak_active", "arena_bytes",
+        "peak_arena_bytes", "operators_built", "operator_cache_hits", "cycles")] + \
+        [("reserved", ctypes.c_int64 * 5)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 
 
@@ -111,6 +137,16 @@ def load_library():
         "cqm_apply_V": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_near_entries": (ctypes.c_int, [P, ctypes.POINTER(I64), P, P, P]),
         "cqm_operator_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_diag)]),
+        "cqm_server_default_options": (ctypes.c_int, [ctypes.POINTER(cqm_server_opts)]),
+        "cqm_server_create": (ctypes.c_int, [P, ctypes.c_size_t, ctypes.POINTER(cqm_server_opts),
+                                             ctypes.POINTER(P)]),
+        "cqm_server_submit": (ctypes.c_int, [P, ctypes.POINTER(cqm_request),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+        "cqm_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(I32), P,
+                                           ctypes.POINTER(cqm_diag), ctypes.POINTER(D)]),
+        "cqm_server_drain": (ctypes.c_int, [P]),
+        "cqm_server_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_server_stats_t)]),
+        "cqm_server_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -249,3 +285,61 @@ def cqm_problem_create(ctx, vertices, tris, N, T, options=None):  # noqa: F811
     h = _create(ctx, vertices, tris, N, T, options)
     _M_of[h.value] = int(np.asarray(tris).shape[0])
     return h
+
+
+def cqm_server_default_options(**solver):
+    o = cqm_server_opts()
+    _check(load_library().cqm_server_default_options(ctypes.byref(o)))
+    for k, v in solver.items():
+        if k in ("max_active", "cache_operators"):
+            setattr(o, k, v)
+        else:
+            setattr(o.solver, k, v)
+    return o
+
+
+def cqm_server_create(ctx, hbm_budget, opts=None):
+    h = ctypes.c_void_p()
+    o = opts if opts is not None else cqm_server_default_options()
+    _check(load_library().cqm_server_create(ctx, int(hbm_budget), ctypes.byref(o), ctypes.byref(h)))
+    return h
+
+
+def cqm_server_submit(server, vertices, tris, N, T, direction=(1.0, 0.0, 0.0), sigma=0.25,
+                      t0=1.5, amplitude=1.0):
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    Tr = np.ascontiguousarray(tris, dtype=np.int32)
+    r = cqm_request(V.ctypes.data, V.shape[0], Tr.ctypes.data, Tr.shape[0], int(N), float(T),
+                    (ctypes.c_double * 3)(*[float(x) for x in direction]), float(sigma),
+                    float(t0), float(amplitude))
+    t = ctypes.c_uint64()
+    _check(load_library().cqm_server_submit(server, ctypes.byref(r), ctypes.byref(t)))
+    return t.value
+
+
+def cqm_server_poll(server, ticket, out=None):
+    """Returns (done, rc, diag, latency_ms); `out` (float64 numpy, (N+1)*M)
+    receives the density when done == 1."""
+    done = ctypes.c_int32()
+    d = cqm_diag()
+    lat = ctypes.c_double()
+    ptr = out.ctypes.data if out is not None else None
+    rc = load_library().cqm_server_poll(server, ctypes.c_uint64(ticket), ctypes.byref(done), ptr,
+                                        ctypes.byref(d), ctypes.byref(lat))
+    if done.value == 0:
+        _check(rc)
+    return done.value, rc, d, lat.value
+
+
+def cqm_server_drain(server):
+    return _check(load_library().cqm_server_drain(server))
+
+
+def cqm_server_stats(server):
+    s = cqm_server_stats_t()
+    _check(load_library().cqm_server_stats(server, ctypes.byref(s)))
+    return s
+
+
+def cqm_server_destroy(server):
+    return _check(load_library().cqm_server_destroy(server))

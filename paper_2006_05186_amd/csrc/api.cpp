@@ -8,14 +8,8 @@
 #include "internal.h"
 
 namespace cqm {
-bool mode_is_mixed(int mode);
-bool mode_is_h2(int mode);
-void h2_prepare(Problem& p, hipStream_t s);                      // h2.cpp
-void h2_release(Problem& p);                                     // h2.cpp
-template <typename R>
-void h2_apply(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
-              const int* active, hipStream_t s);                 // h2.cpp
-void h2_stats(const Problem& p, cqm_diag* d);                    // h2.cpp
+void h2_release(Problem& p);                 // h2.cpp
+void h2_stats(const Problem& p, cqm_diag* d);
 }  // namespace cqm
 
 namespace cqm {
@@ -54,8 +48,6 @@ void KernelTimer::release() {
 
 using namespace cqm;
 
-struct cqm_ctx_s : Ctx {};
-struct cqm_problem_s : Problem {};
 
 namespace {
 thread_local std::string g_last_error = "no error";
@@ -95,208 +87,10 @@ void frequencies_host(int N, double T, double rho, std::vector<double>& re, std:
   }
 }
 
-template <typename T> T* at(Problem& p, size_t off) { return reinterpret_cast<T*>(p.ws + off); }
-
-double ms_since(std::chrono::steady_clock::time_point t0) {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-}
-
-template <typename R>
-void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
-              const int* active, hipStream_t s) {
-  if (mode_is_h2(p.opt.mode)) {
-    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
-    h2_apply<R>(p, l0, nsys, x, xs, y, ys, active, s);
-    return;
-  }
-  const int M = (int)p.M;
-  if (p.opt.form == CQM_FORM_DENSE) {
-    const cplx<R>* V;
-    if constexpr (sizeof(R) == 4) {
-      require(p.lay.dense32 != 0, CQM_EINVAL, "FP32 dense operator exists only in mixed mode");
-      V = at<cf32>(p, p.lay.dense32);
-    } else {
-      V = at<cf64>(p, p.lay.dense64);
-    }
-    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
-    launch_dense_gemv<R>(V + (int64_t)l0 * M * M, M, nsys, x, xs, y, ys, active, s);
-  } else {
-    cplx<R>* partial = at<cplx<R>>(p, p.lay.partial);
-    {
-      Timed t(p, sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64, s);
-      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, s);
-    }
-    Timed t(p, CQM_K_NEAR, s);
-    launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, at<cf64>(p, p.lay.near_val),
-                              active, s);
-  }
-}
-
-// Near field and (dense form) the assembled operator, or the compressed one.
-void prepare_operator(Problem& p, hipStream_t s) {
-  require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
-  if (!p.static_ready) {
-    Timed t(p, CQM_K_NEAR, s);
-    launch_near_static(p, s);
-    p.static_ready = true;
-  }
-  if (mode_is_h2(p.opt.mode)) {
-    if (!(p.opt.reuse_operator && p.near_ready)) {
-      Timed t(p, CQM_K_ASSEMBLE, s);
-      h2_prepare(p, s);
-    }
-    p.near_ready = true;
-    return;
-  }
-  const bool have = p.near_ready && (p.opt.form != CQM_FORM_DENSE || p.dense_ready);
-  if (have && p.opt.reuse_operator) return;
-  cf64* nv = at<cf64>(p, p.lay.near_val);
-  {
-    Timed t(p, CQM_K_NEAR, s);
-    launch_near_values(p, nv, s);
-  }
-  p.near_ready = true;
-  if (p.opt.form == CQM_FORM_DENSE) {
-    cf64* d64 = at<cf64>(p, p.lay.dense64);
-    cf32* d32 = p.lay.dense32 ? at<cf32>(p, p.lay.dense32) : nullptr;
-    {
-      Timed t(p, CQM_K_ASSEMBLE, s);
-      launch_dense_assemble(p, d64, d32, s);
-    }
-    Timed t(p, CQM_K_NEAR, s);
-    launch_dense_scatter_near(p, nv, d64, d32, s);
-    p.dense_ready = true;
-  }
-}
-
-template <typename R>
-void run_cycles(Problem& p, hipStream_t s, cqm_diag& dg) {
-  const int M = (int)p.M, Fs = p.Fsys, m = p.opt.gmres_restart;
-  const int64_t bs = (int64_t)(m + 1) * M;
-  GmresState st;
-  st.M = M;
-  st.nsys = Fs;
-  st.m = m;
-  st.basis = p.ws + p.lay.basis;
-  st.H = at<cf64>(p, p.lay.H);
-  st.cs = at<double>(p, p.lay.cs);
-  st.sn = at<cf64>(p, p.lay.sn);
-  st.g = at<cf64>(p, p.lay.g);
-  st.sysd = at<double>(p, p.lay.sysd);
-  st.sysi = at<int>(p, p.lay.sysi);
-  cf64* ghat = at<cf64>(p, p.lay.ghat);
-  cf64* x = at<cf64>(p, p.lay.x);
-  cf64* r = at<cf64>(p, p.lay.r);
-  cplx<R>* basis = reinterpret_cast<cplx<R>*>(st.basis);
-  const double inner_tol = sizeof(R) == 4 ? std::max(p.opt.inner_tol, 2e-7) : p.opt.inner_tol;
-  std::vector<int> flags(kSysiStride * Fs);
-  auto count = [&](int which) {
-    CQM_HIP(hipMemcpyAsync(flags.data(), st.sysi, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
-    CQM_HIP(hipStreamSynchronize(s));
-    int c = 0;
-    for (int l = 0; l < Fs; ++l) c += flags[kSysiStride * l + which] != 0;
-    return c;
-  };
-  {
-    Timed t(p, CQM_K_GMRES, s);
-    launch_gmres_init(ghat, M, Fs, x, r, st.sysd, st.sysi, s);
-  }
-  int cyc = 0;
-  for (; cyc < p.opt.max_cycles; ++cyc) {
-    {
-      Timed t(p, CQM_K_GMRES, s);
-      launch_cycle_start<R>(st, r, p.opt.outer_tol, inner_tol, s);
-    }
-    if (count(0) == 0) break;
-    for (int j = 0; j < m; ++j) {
-      apply_op<R>(p, 0, Fs, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
-                  st.sysi + 1, s);
-      {
-        Timed t(p, CQM_K_GMRES, s);
-        launch_arnoldi<R>(st, j, s);
-      }
-      if ((j + 1) % 6 == 0 && j + 1 < m && count(1) == 0) break;
-    }
-    {
-      Timed t(p, CQM_K_GMRES, s);
-      launch_cycle_finish<R>(st, x, s);
-    }
-    apply_op<double>(p, 0, Fs, x, M, r, M, st.sysi, s);
-    Timed t(p, CQM_K_GMRES, s);
-    launch_residual_combine(ghat, r, M, Fs, st.sysi, s);
-  }
-  // final status (residual norms of systems still open)
-  launch_cycle_start<R>(st, r, p.opt.outer_tol, inner_tol, s);
-  std::vector<double> sd(8 * Fs);
-  CQM_HIP(hipMemcpyAsync(sd.data(), st.sysd, sizeof(double) * sd.size(), hipMemcpyDeviceToHost, s));
-  CQM_HIP(hipMemcpyAsync(flags.data(), st.sysi, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
-  CQM_HIP(hipStreamSynchronize(s));
-  dg.cycles = cyc;
-  dg.total_iters = 0;
-  dg.max_iters = 0;
-  dg.max_rel_residual = 0.0;
-  int open = 0, nan = 0;
-  for (int l = 0; l < Fs; ++l) {
-    const int it = flags[kSysiStride * l + 3];
-    dg.total_iters += it;
-    dg.max_iters = std::max(dg.max_iters, it);
-    const double bn = sd[8 * l + 2], rn = sd[8 * l + 3];
-    if (bn > 0) dg.max_rel_residual = std::max(dg.max_rel_residual, rn / bn);
-    open += flags[kSysiStride * l] != 0;
-    nan += sd[8 * l + 4] != 0.0;
-  }
-  dg.converged = (open == 0 && nan == 0) ? 1 : 0;
-  if (nan) dg.converged = -1;
-}
-
-int solve_one(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
-  CQM_HIP(hipSetDevice(p.ctx->device));
-  require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
-          "workspace missing or smaller than cqm_workspace_size");
-  require(p.inc_kind != 0, CQM_EINVAL, "no incident data set");
-  require(q_out != nullptr, CQM_EINVAL, "q_out is NULL");
-  cqm_diag dg{};
-  p.timer.on = p.opt.profile != 0;
-  p.timer.cls.clear();
-  p.timer.used = 0;
-  auto t0 = std::chrono::steady_clock::now();
-  prepare_operator(p, s);
-  CQM_HIP(hipStreamSynchronize(s));
-  dg.t_setup_ms = ms_since(t0);
-  auto t1 = std::chrono::steady_clock::now();
-  double* b = at<double>(p, p.lay.b);
-  cf64* ghat = at<cf64>(p, p.lay.ghat);
-  {
-    Timed t(p, CQM_K_OTHER, s);
-    launch_rhs(p, b, s);
-    launch_dft_forward(p, b, ghat, s);
-  }
-  if (mode_is_mixed(p.opt.mode)) run_cycles<float>(p, s, dg);
-  else run_cycles<double>(p, s, dg);
-  double* sums = at<double>(p, p.lay.scratch);
-  CQM_HIP(hipMemsetAsync(sums, 0, 2 * sizeof(double), s));
-  {
-    Timed t(p, CQM_K_OTHER, s);
-    launch_dft_inverse(p, at<cf64>(p, p.lay.x), q_out, sums, sums + 1, s);
-  }
-  double hs[2];
-  CQM_HIP(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, s));
-  CQM_HIP(hipStreamSynchronize(s));
-  if (p.timer.on) p.timer.collect(dg.kernel_ms, dg.kernel_calls);
-  dg.imag_ratio = p.full_band() && hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : 0.0;
-  dg.t_solve_ms = ms_since(t1);
-  dg.n_systems = p.Fsys;
-  dg.far_units = p.far_units;
-  if (mode_is_h2(p.opt.mode)) h2_stats(p, &dg);
-  else if (p.opt.form == CQM_FORM_DENSE)
-    dg.operator_bytes = (int64_t)p.Fsys * p.M * p.M * (p.lay.dense32 ? 24 : 16);
-  else
-    dg.operator_bytes = (int64_t)p.Fsys * (int64_t)p.col.size() * 16;
-  p.last = dg;
-  if (diag) *diag = dg;
-  if (dg.converged < 0) return fail(CQM_ENAN, "non-finite residual in some frequency system");
-  if (!dg.converged) return fail(CQM_ENOCONV, "some frequency systems missed outer_tol");
-  return CQM_OK;
+int finish(int rc) {
+  if (rc == CQM_ENAN) return fail(rc, "non-finite residual in some frequency system");
+  if (rc == CQM_ENOCONV) return fail(rc, "some frequency systems missed outer_tol");
+  return rc;
 }
 }  // namespace
 
@@ -446,6 +240,8 @@ int cqm_set_workspace(cqm_problem_t p, void* dev_ptr, size_t bytes) {
     }
     p->ws = (char*)dev_ptr;
     p->ws_bytes = bytes;
+    p->own.p = p;
+    p->own.base = p->ws;
     return CQM_OK;
   });
 }
@@ -457,11 +253,11 @@ int cqm_set_plane_wave(cqm_problem_t p, const double d[3], double sigma, double 
     require(n > 0 && std::isfinite(n), CQM_EINVAL, "direction must be a nonzero finite vector");
     require(sigma > 0 && std::isfinite(sigma) && std::isfinite(t0), CQM_EINVAL, "sigma/t0");
     require(std::isfinite(amp), CQM_ENAN, "non-finite amplitude");
-    for (int k = 0; k < 3; ++k) p->dir[k] = d[k] / n;
-    p->sigma = sigma;
-    p->t0 = t0;
-    p->amp = amp;
-    p->inc_kind = 1;
+    for (int k = 0; k < 3; ++k) p->inc.dir[k] = d[k] / n;
+    p->inc.sigma = sigma;
+    p->inc.t0 = t0;
+    p->inc.amp = amp;
+    p->inc.kind = 1;
     return CQM_OK;
   });
 }
@@ -469,8 +265,8 @@ int cqm_set_plane_wave(cqm_problem_t p, const double d[3], double sigma, double 
 int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g) {
   return guarded([&] {
     require(p && g, CQM_EINVAL, "NULL argument");
-    p->samples = g;
-    p->inc_kind = 2;
+    p->inc.samples = g;
+    p->inc.kind = 2;
     return CQM_OK;
   });
 }
@@ -478,7 +274,14 @@ int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g) {
 int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream) {
   return guarded([&] {
     require(p != nullptr, CQM_EINVAL, "NULL problem");
-    return solve_one(*p, q_out, diag, stream);
+    p->own.p = p;
+    p->own.base = p->ws;
+    p->own.inc = p->inc;
+    p->own.q_out = q_out;
+    std::vector<SolveState*> S{&p->own};
+    solve_states(S, stream);
+    if (diag) *diag = p->own.diag;
+    return finish(diag_status(p->own.diag));
   });
 }
 
@@ -486,12 +289,26 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs, cqm_di
                     hipStream_t stream) {
   return guarded([&] {
     require(probs && q_outs && count >= 0, CQM_EINVAL, "NULL argument");
+    std::vector<SolveState*> S;
+    for (int k = 0; k < count; ++k) {
+      require(probs[k] != nullptr, CQM_EINVAL, "NULL problem in batch");
+      for (int j = 0; j < k; ++j)
+        require(probs[j] != probs[k], CQM_EINVAL, "a problem appears twice in the batch");
+      Problem& p = *probs[k];
+      p.own.p = &p;
+      p.own.base = p.ws;
+      p.own.inc = p.inc;
+      p.own.q_out = q_outs[k];
+      S.push_back(&p.own);
+    }
+    solve_states(S, stream);
     int worst = CQM_OK;
     for (int k = 0; k < count; ++k) {
-      const int rc = solve_one(*probs[k], q_outs[k], diags ? &diags[k] : nullptr, stream);
+      if (diags) diags[k] = probs[k]->own.diag;
+      const int rc = diag_status(probs[k]->own.diag);
       if (rc != CQM_OK && (worst == CQM_OK || rc < worst)) worst = rc;
     }
-    return worst;
+    return finish(worst);
   });
 }
 

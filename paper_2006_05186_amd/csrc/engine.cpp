@@ -1,0 +1,359 @@
+// Solve driver: operator preparation, right-hand sides and transforms, and
+// the batched restarted-GMRES engine with FP64 refinement over any set of
+// solve states (one problem, an uneven batch, or the serving loop's active
+// requests).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace cqm {
+void h2_prepare(Problem& p, hipStream_t s);
+template <typename R>
+void h2_apply(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* active, hipStream_t s);
+void h2_stats(const Problem& p, cqm_diag* d);
+
+namespace {
+template <typename T> T* wsp(Problem& p, size_t off) { return reinterpret_cast<T*>(p.ws + off); }
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+template <typename T> void ensure(T*& ptr, size_t& cap, size_t n) {
+  if (n <= cap && ptr) return;
+  if (ptr) CQM_HIP(hipFree(ptr));
+  ptr = nullptr;
+  const size_t c = std::max<size_t>(n, 2 * cap);
+  CQM_HIP(hipMalloc(&ptr, sizeof(T) * c));
+  cap = c;
+}
+bool dense_form(const Problem& p) { return !mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE; }
+}  // namespace
+
+template <typename R>
+void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* active, hipStream_t s) {
+  if (mode_is_h2(p.opt.mode)) {
+    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
+    h2_apply<R>(p, l0, nsys, x, xs, y, ys, active, s);
+    return;
+  }
+  const int M = (int)p.M;
+  if (p.opt.form == CQM_FORM_DENSE) {
+    const cplx<R>* V;
+    if constexpr (sizeof(R) == 4) {
+      require(p.lay.dense32 != 0, CQM_EINVAL, "FP32 dense operator exists only in mixed mode");
+      V = wsp<cf32>(p, p.lay.dense32);
+    } else {
+      V = wsp<cf64>(p, p.lay.dense64);
+    }
+    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
+    launch_dense_gemv<R>(V + (int64_t)l0 * M * M, M, nsys, x, xs, y, ys, active, s);
+  } else {
+    cplx<R>* partial = wsp<cplx<R>>(p, p.lay.partial);
+    {
+      Timed t(p, sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64, s);
+      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, s);
+    }
+    Timed t(p, CQM_K_NEAR, s);
+    launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, wsp<cf64>(p, p.lay.near_val),
+                              active, s);
+  }
+}
+template void apply_op<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
+template void apply_op<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);
+
+// Near field and (dense form) the assembled operator, or the compressed one.
+void prepare_operator(Problem& p, hipStream_t s) {
+  require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
+  if (!p.static_ready) {
+    Timed t(p, CQM_K_NEAR, s);
+    launch_near_static(p, s);
+    p.static_ready = true;
+  }
+  if (mode_is_h2(p.opt.mode)) {
+    if (!(p.opt.reuse_operator && p.near_ready)) {
+      Timed t(p, CQM_K_ASSEMBLE, s);
+      h2_prepare(p, s);
+    }
+    p.near_ready = true;
+    return;
+  }
+  const bool have = p.near_ready && (p.opt.form != CQM_FORM_DENSE || p.dense_ready);
+  if (have && p.opt.reuse_operator) return;
+  cf64* nv = wsp<cf64>(p, p.lay.near_val);
+  {
+    Timed t(p, CQM_K_NEAR, s);
+    launch_near_values(p, nv, s);
+  }
+  p.near_ready = true;
+  if (p.opt.form == CQM_FORM_DENSE) {
+    cf64* d64 = wsp<cf64>(p, p.lay.dense64);
+    cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
+    {
+      Timed t(p, CQM_K_ASSEMBLE, s);
+      launch_dense_assemble(p, d64, d32, s);
+    }
+    Timed t(p, CQM_K_NEAR, s);
+    launch_dense_scatter_near(p, nv, d64, d32, s);
+    p.dense_ready = true;
+  }
+}
+
+// Operator (optionally), right-hand side and forward transform of one state.
+void pre_solve(SolveState& st, hipStream_t s, bool prepare) {
+  Problem& p = *st.p;
+  CQM_HIP(hipSetDevice(p.ctx->device));
+  require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
+          "workspace missing or smaller than cqm_workspace_size");
+  require(st.inc.kind != 0, CQM_EINVAL, "no incident data set");
+  require(st.q_out != nullptr, CQM_EINVAL, "q_out is NULL");
+  st.diag = cqm_diag{};
+  if (prepare) {
+    auto t0 = std::chrono::steady_clock::now();
+    prepare_operator(p, s);
+    CQM_HIP(hipStreamSynchronize(s));
+    st.diag.t_setup_ms = ms_since(t0);
+  }
+  Timed t(p, CQM_K_OTHER, s);
+  launch_rhs(p, st.inc, st.at<double>(st.b), s);
+  launch_dft_forward(p, st.at<double>(st.b), st.at<cf64>(st.ghat), s);
+}
+
+// Inverse transform and operator diagnostics of one state.
+void post_solve(SolveState& st, hipStream_t s) {
+  Problem& p = *st.p;
+  cqm_diag& dg = st.diag;
+  double* sums = st.at<double>(st.scratch);
+  CQM_HIP(hipMemsetAsync(sums, 0, 2 * sizeof(double), s));
+  {
+    Timed t(p, CQM_K_OTHER, s);
+    launch_dft_inverse(p, st.at<cf64>(st.x), st.q_out, sums, sums + 1, s);
+  }
+  double hs[2];
+  CQM_HIP(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+  dg.imag_ratio = p.full_band() && hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : 0.0;
+  dg.n_systems = p.Fsys;
+  dg.far_units = p.far_units;
+  if (mode_is_h2(p.opt.mode)) h2_stats(p, &dg);
+  else if (p.opt.form == CQM_FORM_DENSE)
+    dg.operator_bytes = (int64_t)p.Fsys * p.M * p.M * (p.lay.dense32 ? 24 : 16);
+  else
+    dg.operator_bytes = (int64_t)p.Fsys * (int64_t)p.col.size() * 16;
+}
+
+int diag_status(const cqm_diag& dg) {
+  if (dg.converged < 0) return CQM_ENAN;
+  if (!dg.converged) return CQM_ENOCONV;
+  return CQM_OK;
+}
+
+// ------------------------------------------------------------ engine
+void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
+  S_ = S;
+  hd_.clear();
+  rows_.clear();
+  maxM_ = 0;
+  if (S_.empty()) return;
+  m_ = S_[0]->p->opt.gmres_restart;
+  mixed = mode_is_mixed(S_[0]->p->opt.mode);
+  for (size_t k = 0; k < S_.size(); ++k) {
+    SolveState* st = S_[k];
+    Problem& p = *st->p;
+    require(p.opt.gmres_restart == m_, CQM_EINVAL, "batched problems must share gmres_restart");
+    require(mode_is_mixed(p.opt.mode) == mixed, CQM_EINVAL, "batched problems must share precision");
+    const int M = (int)p.M;
+    maxM_ = std::max(maxM_, M);
+    st->first = (int)hd_.size();
+    const size_t isz = mixed ? sizeof(cf32) : sizeof(cf64);
+    for (int l = 0; l < p.Fsys; ++l) {
+      SysDesc d{};
+      d.M = M;
+      d.m = m_;
+      d.prob = (int)k;
+      d.l = l;
+      d.basis = st->base + st->basis + isz * (size_t)l * (m_ + 1) * M;
+      d.H = st->at<cf64>(st->H) + (size_t)l * (m_ + 1) * m_;
+      d.cs = st->at<double>(st->cs) + (size_t)l * m_;
+      d.sn = st->at<cf64>(st->sn) + (size_t)l * m_;
+      d.g = st->at<cf64>(st->g) + (size_t)l * (m_ + 1);
+      d.sysd = st->at<double>(st->sysd) + 8 * l;
+      d.sysi = st->at<int>(st->sysi) + kSysiStride * l;
+      d.x = st->at<cf64>(st->x) + (size_t)l * M;
+      d.r = st->at<cf64>(st->r) + (size_t)l * M;
+      d.ghat = st->at<cf64>(st->ghat) + (size_t)l * M;
+      if (dense_form(p)) {
+        d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * M * M;
+        d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * M * M) : nullptr;
+        for (int r0 = 0; r0 < M; r0 += 4) rows_.push_back(RowBlock{(int)hd_.size(), r0});
+      }
+      hd_.push_back(d);
+    }
+  }
+  const int n = (int)hd_.size();
+  ensure(ctx.eb.desc, ctx.eb.desc_cap, hd_.size());
+  ensure(ctx.eb.map, ctx.eb.map_cap, std::max<size_t>(1, rows_.size()));
+  ensure(ctx.eb.status, ctx.eb.status_cap, (size_t)kSysiStride * n);
+  CQM_HIP(hipMemcpyAsync(ctx.eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
+  if (!rows_.empty())
+    CQM_HIP(hipMemcpyAsync(ctx.eb.map, rows_.data(), sizeof(RowBlock) * rows_.size(),
+                           hipMemcpyHostToDevice, s));
+  flags_.assign((size_t)kSysiStride * n, 0);
+}
+
+void Engine::init(int k, hipStream_t s) {
+  SolveState* st = S_[k];
+  Timed t(*S_[0]->p, CQM_K_GMRES, s);
+  launch_gmres_init(ctx.eb.desc + st->first, st->p->Fsys, s);
+}
+
+void Engine::status(hipStream_t s) {
+  const int n = (int)hd_.size();
+  if (!n) return;
+  launch_gather_status(ctx.eb.desc, n, ctx.eb.status, s);
+  CQM_HIP(hipMemcpyAsync(flags_.data(), ctx.eb.status, sizeof(int) * flags_.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+}
+
+bool Engine::state_done(int k) const {
+  const SolveState* st = S_[k];
+  for (int l = 0; l < st->p->Fsys; ++l)
+    if (flags_[(size_t)kSysiStride * (st->first + l)]) return false;
+  return true;
+}
+
+int Engine::cycle(hipStream_t s) { return mixed ? cycle_t<float>(s) : cycle_t<double>(s); }
+
+// One restart cycle of every open system: start from the FP64 residual, up
+// to m Arnoldi steps, update x, new FP64 residual.  Returns the number of
+// systems that were open at the start (0: nothing was done).
+template <typename R> int Engine::cycle_t(hipStream_t s) {
+  const int n = (int)hd_.size();
+  if (!n) return 0;
+  Problem& p0 = *S_[0]->p;
+  const SysDesc* sd = ctx.eb.desc;
+  const double outer_tol = p0.opt.outer_tol;
+  const double inner_tol = sizeof(R) == 4 ? std::max(p0.opt.inner_tol, 2e-7) : p0.opt.inner_tol;
+  auto count = [&](int which) {
+    status(s);
+    int c = 0;
+    for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + which] != 0;
+    return c;
+  };
+  {
+    Timed t(p0, CQM_K_GMRES, s);
+    launch_cycle_start<R>(sd, n, outer_tol, inner_tol, s);
+  }
+  const int open = count(0);
+  if (open == 0) return 0;
+  for (int j = 0; j < m_; ++j) {
+    if (!rows_.empty()) {
+      Timed t(p0, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
+      launch_dense_gemv_desc<R>(sd, ctx.eb.map, (int)rows_.size(), 0, j, s);
+    }
+    for (SolveState* st : S_) {
+      Problem& p = *st->p;
+      if (dense_form(p)) continue;
+      const int M = (int)p.M;
+      const int64_t bs = (int64_t)(m_ + 1) * M;
+      cplx<R>* basis = reinterpret_cast<cplx<R>*>(st->base + st->basis);
+      apply_op<R>(p, 0, p.Fsys, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
+                  st->at<int>(st->sysi) + 1, s);
+    }
+    {
+      Timed t(p0, CQM_K_GMRES, s);
+      launch_arnoldi<R>(sd, n, maxM_, j, s);
+    }
+    if ((j + 1) % 6 == 0 && j + 1 < m_ && count(1) == 0) break;
+  }
+  {
+    Timed t(p0, CQM_K_GMRES, s);
+    launch_cycle_finish<R>(sd, n, s);
+  }
+  if (!rows_.empty()) {
+    Timed t(p0, CQM_K_GEMV64, s);
+    launch_dense_gemv_desc<double>(sd, ctx.eb.map, (int)rows_.size(), 1, 0, s);
+  }
+  for (SolveState* st : S_) {
+    Problem& p = *st->p;
+    if (dense_form(p)) continue;
+    const int M = (int)p.M;
+    apply_op<double>(p, 0, p.Fsys, st->at<cf64>(st->x), M, st->at<cf64>(st->r), M,
+                     st->at<int>(st->sysi), s);
+  }
+  {
+    Timed t(p0, CQM_K_GMRES, s);
+    launch_residual_combine(sd, n, s);
+  }
+  ++cycles_run;
+  return open;
+}
+template int Engine::cycle_t<float>(hipStream_t);
+template int Engine::cycle_t<double>(hipStream_t);
+
+// Closing status pass for state k: residual norms refreshed by one more
+// cycle start (systems still open keep their flags) and the diagnostics.
+void Engine::finish_diag(int k, hipStream_t s) {
+  SolveState* st = S_[k];
+  Problem& p = *st->p;
+  const SysDesc* sd = ctx.eb.desc + st->first;
+  const double outer_tol = p.opt.outer_tol;
+  if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
+  else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);
+  std::vector<double> sdv(8 * (size_t)p.Fsys);
+  std::vector<int> fl((size_t)kSysiStride * p.Fsys);
+  CQM_HIP(hipMemcpyAsync(sdv.data(), st->at<double>(st->sysd), sizeof(double) * sdv.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipMemcpyAsync(fl.data(), st->at<int>(st->sysi), sizeof(int) * fl.size(), hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipStreamSynchronize(s));
+  cqm_diag& d = st->diag;
+  d.cycles = cycles_run;
+  d.total_iters = d.max_iters = 0;
+  d.max_rel_residual = 0.0;
+  int open = 0, nan = 0;
+  for (int l = 0; l < p.Fsys; ++l) {
+    const int* f = &fl[(size_t)kSysiStride * l];
+    d.total_iters += f[3];
+    d.max_iters = std::max(d.max_iters, f[3]);
+    const double bn = sdv[8 * l + 2], rn = sdv[8 * l + 3];
+    if (bn > 0) d.max_rel_residual = std::max(d.max_rel_residual, rn / bn);
+    open += f[0] != 0;
+    nan += sdv[8 * l + 4] != 0.0;
+  }
+  d.converged = nan ? -1 : (open == 0 ? 1 : 0);
+}
+
+// Full solves of a set of states; states with the same inner precision share
+// the engine's launches.
+void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
+  for (int g = 0; g < 2; ++g) {
+    std::vector<SolveState*> G;
+    for (SolveState* st : S)
+      if ((mode_is_mixed(st->p->opt.mode) ? 1 : 0) == g) G.push_back(st);
+    if (G.empty()) continue;
+    Problem& p0 = *G[0]->p;
+    p0.timer.on = p0.opt.profile != 0;
+    p0.timer.cls.clear();
+    p0.timer.used = 0;
+    for (size_t k = 1; k < G.size(); ++k)
+      if (G[k]->p != &p0) G[k]->p->timer.on = false;
+    for (SolveState* st : G) pre_solve(*st, s, true);
+    auto t1 = std::chrono::steady_clock::now();
+    Engine E(*p0.ctx);
+    E.set(G, s);
+    for (size_t k = 0; k < G.size(); ++k) E.init((int)k, s);
+    for (int c = 0; c < p0.opt.max_cycles; ++c)
+      if (E.cycle(s) == 0) break;
+    for (size_t k = 0; k < G.size(); ++k) E.finish_diag((int)k, s);
+    for (SolveState* st : G) post_solve(*st, s);
+    const double el = ms_since(t1);
+    if (p0.timer.on) p0.timer.collect(G[0]->diag.kernel_ms, G[0]->diag.kernel_calls);
+    for (SolveState* st : G) {
+      st->diag.t_solve_ms = el;
+      st->p->last = st->diag;
+    }
+  }
+}
+
+}  // namespace cqm

@@ -58,8 +58,41 @@ template <typename R> struct FreqTab {
 };
 
 // ------------------------------------------------------------ problem state
+// GMRES (k_gmres.hip).  One descriptor per frequency system.
+struct SysDesc {
+  int M, m;               // length, restart length
+  int prob, l;            // problem index (in a batch) and frequency index
+  void* basis;            // (m+1) x M, inner precision
+  cf64* H;                // (m+1) x m, column-major
+  double* cs;             // m
+  cf64* sn;               // m
+  cf64* g;                // m+1
+  double* sysd;           // 8 doubles of status
+  int* sysi;              // kSysiStride ints of status
+  cf64* x;                // M, FP64 solution
+  cf64* r;                // M, FP64 residual
+  const cf64* ghat;       // M, right-hand side
+  const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
+  const cf64* V64;        // dense operator slice in FP64 (dense form) or null
+};
+struct RowBlock {
+  int sys, row0;
+};
+
+
+// Device tables of the batched GMRES engine (library-owned, grow-only).
+struct EngineBufs {
+  SysDesc* desc = nullptr;
+  size_t desc_cap = 0;
+  RowBlock* map = nullptr;
+  size_t map_cap = 0;
+  int* status = nullptr;
+  size_t status_cap = 0;
+};
+
 struct Ctx {
   int device = 0;
+  EngineBufs eb;
 };
 
 // Device tables of one mesh (owned by the problem, uploaded at create).
@@ -88,13 +121,34 @@ struct MeshDev {
 
 // Offsets (bytes) of the solve workspace.
 struct Layout {
-  size_t b = 0, ghat = 0, x = 0, r = 0, basis = 0, H = 0, cs = 0, sn = 0, g = 0;
-  size_t sysd = 0, sysi = 0, partial = 0, near_val = 0, dense64 = 0, dense32 = 0;
-  size_t scratch = 0, total = 0;
-  int nsplit = 1;
+  size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, total = 0;
 };
 
 struct H2Operator;  // compressed representation (h2.cpp)
+struct Problem;
+
+// Incident Dirichlet data of one right-hand side.
+struct Incident {
+  int kind = 0;  // 0 none, 1 plane wave, 2 samples at the quadrature points
+  double dir[3] = {1, 0, 0}, sigma = 0.25, t0 = 1.5, amp = 1.0;
+  const double* samples = nullptr;  // device, (N+1) x M x 6
+};
+
+// Per-right-hand-side solve state: data samples, transforms, Krylov basis,
+// Hessenberg data and status of every frequency system.  Offsets are bytes
+// from `base`.  A problem owns one in its workspace; the serving loop adds
+// more that share the problem's operator.
+struct SolveState {
+  Problem* p = nullptr;
+  char* base = nullptr;
+  size_t b = 0, ghat = 0, x = 0, r = 0, basis = 0, H = 0, cs = 0, sn = 0, g = 0, sysd = 0,
+         sysi = 0, scratch = 0, total = 0;
+  Incident inc;
+  double* q_out = nullptr;
+  cqm_diag diag{};
+  int first = 0;  // index of its first system in the engine's descriptor list
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+};
 
 // Optional per-class kernel timing with HIP events recorded on the launch
 // stream (enabled by cqm_options.profile).
@@ -123,10 +177,9 @@ struct Problem {
   std::vector<double> static_host;
   bool static_host_valid = false;
   MeshDev dev;
-  // incident data
-  int inc_kind = 0;  // 0 none, 1 plane wave, 2 samples
-  double dir[3] = {1, 0, 0}, sigma = 0.25, t0 = 1.5, amp = 1.0;
-  const double* samples = nullptr;
+  // incident data and the problem's own solve state
+  Incident inc;
+  SolveState own;
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -141,13 +194,11 @@ struct Problem {
 
 // ------------------------------------------------------------ launchers
 // tables / transforms (k_transform.hip)
-void launch_rhs(const Problem& p, double* b, hipStream_t s);
+void launch_rhs(const Problem& p, const Incident& inc, double* b, hipStream_t s);
 void launch_dft_forward(const Problem& p, const double* b, cf64* ghat, hipStream_t s);
 void launch_dft_inverse(const Problem& p, const cf64* xhat, double* q, double* imag_sq,
                         double* real_sq, hipStream_t s);
 void launch_vec_norms(const cf64* v, int64_t stride, int M, int nsys, double* out, hipStream_t s);
-void launch_residual_combine(const cf64* ghat, cf64* r, int M, int nsys, const int* active,
-                             hipStream_t s);
 
 // near field (k_near.hip)
 void launch_near_static(const Problem& p, hipStream_t s);
@@ -171,26 +222,19 @@ template <typename R>
 void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int64_t xs,
                        cplx<R>* y, int64_t ys, const int* active, hipStream_t s);
 
-// GMRES (k_gmres.hip)
-struct GmresState {
-  int M, nsys, m;
-  void* basis;      // [nsys][m+1][M] inner precision
-  cf64* H;          // [nsys][(m+1)*m]
-  double* cs;       // [nsys][m]
-  cf64* sn;         // [nsys][m]
-  cf64* g;          // [nsys][m+1]
-  double* sysd;     // [nsys][8] doubles: 0 beta, 1 tol_abs, 2 bnorm, 3 rnorm
-  int* sysi;        // [nsys][4] ints: 0 sys_active, 1 cyc_active, 2 jdone, 3 iters
-};
-void launch_gmres_init(const cf64* ghat, int M, int nsys, cf64* x, cf64* r, double* sysd,
-                       int* sysi, hipStream_t s);
+void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s);
+void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
+void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s);
 template <typename R>
-void launch_cycle_start(const GmresState& st, const cf64* r, double outer_tol, double inner_tol,
-                        hipStream_t s);
+void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s);
+template <typename R> void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, hipStream_t s);
+template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s);
+// dense products over descriptors (k_dense.hip): which = 0 inner product
+// basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
+// residual product x -> r of open systems.  rowmap: (system, first row).
 template <typename R>
-void launch_arnoldi(const GmresState& st, int j, hipStream_t s);
-template <typename R>
-void launch_cycle_finish(const GmresState& st, cf64* x, hipStream_t s);
+void launch_dense_gemv_desc(const SysDesc* sd, const RowBlock* map, int nblocks, int which, int j,
+                            hipStream_t s);
 
 // ------------------------------------------------------------ host helpers
 void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w);
@@ -198,6 +242,42 @@ void dunavant6(double bary[6][3], double w[6]);
 void build_near(Problem& p);
 void upload_problem(Problem& p);
 void compute_layout(Problem& p);
+size_t state_layout(const Problem& p, SolveState& st);  // offsets of a state; returns bytes
+bool mode_is_mixed(int mode);
+bool mode_is_h2(int mode);
+
+// solve driver (engine.cpp)
+template <typename R>
+void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+              const int* active, hipStream_t s);
+void prepare_operator(Problem& p, hipStream_t s);
+void pre_solve(SolveState& st, hipStream_t s, bool prepare);
+void post_solve(SolveState& st, hipStream_t s);
+int diag_status(const cqm_diag& dg);  // CQM_OK / CQM_ENOCONV / CQM_ENAN
+void solve_states(std::vector<SolveState*>& S, hipStream_t s);  // full solves, grouped by precision
+
+// One restart cycle at a time over a changing set of states (same inner
+// precision): used by the batch solve and by the serving loop.
+class Engine {
+ public:
+  explicit Engine(Ctx& c) : ctx(c) {}
+  void set(const std::vector<SolveState*>& S, hipStream_t s);  // rebuild descriptors
+  void init(int k, hipStream_t s);                              // x = 0, r = ghat of state k
+  int cycle(hipStream_t s);                                     // returns systems still open
+  void status(hipStream_t s);                                   // refresh host flags
+  bool state_done(int k) const;                                 // every system of state k closed
+  void finish_diag(int k, hipStream_t s);                       // fill diag of state k
+  int cycles_run = 0;
+  bool mixed = true;
+ private:
+  template <typename R> int cycle_t(hipStream_t s);
+  Ctx& ctx;
+  std::vector<SolveState*> S_;
+  std::vector<SysDesc> hd_;
+  std::vector<RowBlock> rows_;
+  std::vector<int> flags_;
+  int maxM_ = 0, m_ = 30;
+};
 
 // RAII helper: times the launches issued in its scope as one class.
 struct Timed {
@@ -208,3 +288,7 @@ struct Timed {
 };
 
 }  // namespace cqm
+
+// Opaque handle types of the C ABI.
+struct cqm_ctx_s : cqm::Ctx {};
+struct cqm_problem_s : cqm::Problem {};

@@ -10,7 +10,6 @@
 namespace cqm {
 
 namespace {
-constexpr int kGB = 1024;   // threads per system (16 waves)
 constexpr int kChunk = 16;  // inner products per pass over w (one pass for j < 16)
 constexpr int kMaxM = 64;   // largest supported restart length
 constexpr double kFloorTol = 1e-13;  // stagnation below this counts as converged
@@ -19,53 +18,42 @@ constexpr double kFloorTol = 1e-13;  // stagnation below this counts as converge
 // sysd per system (8 doubles): 0 beta, 1 cycle tolerance, 2 ||ghat||,
 // 3 last true residual norm, 4 non-finite flag.  sysi (kSysiStride ints):
 // 0 system active, 1 cycle active, 2 Arnoldi steps in cycle, 3 total steps.
-__global__ __launch_bounds__(kGB) void k_gmres_init(const cf64* __restrict__ ghat, int M,
-                                                    cf64* __restrict__ x, cf64* __restrict__ r,
-                                                    double* __restrict__ sysd, int* __restrict__ sysi) {
+// Every kernel takes the system descriptors; workgroup k serves system k, so
+// systems of different lengths and problems share the launches.
+__global__ __launch_bounds__(256) void k_gmres_init(const SysDesc* __restrict__ sd) {
   __shared__ double red[16];
-  const int l = blockIdx.x;
-  const int64_t off = (int64_t)l * M;
+  const SysDesc D = sd[blockIdx.x];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < M; i += kGB) {
-    const cf64 v = ghat[off + i];
+  for (int i = threadIdx.x; i < D.M; i += 256) {
+    const cf64 v = D.ghat[i];
     acc += v.re * v.re + v.im * v.im;
-    x[off + i] = cf64{0.0, 0.0};
-    r[off + i] = v;
+    D.x[i] = cf64{0.0, 0.0};
+    D.r[i] = v;
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    double* d = sysd + 8 * l;
-    for (int k = 0; k < 8; ++k) d[k] = 0.0;
-    d[2] = sqrt(acc);
-    d[3] = d[2];
-    int* st = sysi + kSysiStride * l;
-    st[0] = 1;
-    st[1] = 0;
-    st[2] = 0;
-    st[3] = 0;
+    for (int k = 0; k < 8; ++k) D.sysd[k] = 0.0;
+    D.sysd[2] = sqrt(acc);
+    D.sysd[3] = D.sysd[2];
+    D.sysi[0] = 1;
+    D.sysi[1] = 0;
+    D.sysi[2] = 0;
+    D.sysi[3] = 0;
   }
 }
 
-void launch_gmres_init(const cf64* ghat, int M, int nsys, cf64* x, cf64* r, double* sysd,
-                       int* sysi, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_init, dim3(nsys), dim3(kGB), 0, s, ghat, M, x, r, sysd, sysi);
-  CQM_HIP(hipGetLastError());
-}
-
 template <typename R>
-__global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __restrict__ basis,
-                                                     cf64* __restrict__ g, double* __restrict__ sysd,
-                                                     int* __restrict__ sysi,
-                                                     const cf64* __restrict__ r, double outer_tol,
+__global__ __launch_bounds__(256) void k_cycle_start(const SysDesc* __restrict__ sd, double outer_tol,
                                                      double inner_tol) {
   __shared__ double red[16];
-  const int l = blockIdx.x;
-  int* st = sysi + kSysiStride * l;
-  double* d = sysd + 8 * l;
+  const SysDesc D = sd[blockIdx.x];
+  int* st = D.sysi;
+  double* d = D.sysd;
   if (!st[0]) return;
-  const cf64* rl = r + (int64_t)l * M;
+  const int M = D.M, m = D.m;
+  const cf64* rl = D.r;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < M; i += kGB) acc += rl[i].re * rl[i].re + rl[i].im * rl[i].im;
+  for (int i = threadIdx.x; i < M; i += 256) acc += rl[i].re * rl[i].re + rl[i].im * rl[i].im;
   const double rn = sqrt(block_sum(acc, red));
   const double bn = d[2];
   if (!isfinite(rn)) {
@@ -87,6 +75,7 @@ __global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __re
     }
     return;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     d[0] = rn;
     d[1] = fmax(inner_tol * rn, 0.5 * outer_tol * bn);
@@ -94,11 +83,10 @@ __global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __re
     st[1] = 1;
     st[2] = 0;
   }
-  cf64* gl = g + (int64_t)l * (m + 1);
-  for (int k = threadIdx.x; k <= m; k += kGB) gl[k] = cf64{k == 0 ? rn : 0.0, 0.0};
-  cplx<R>* v0 = basis + (int64_t)l * (m + 1) * M;
+  for (int k = threadIdx.x; k <= m; k += 256) D.g[k] = cf64{k == 0 ? rn : 0.0, 0.0};
+  cplx<R>* v0 = (cplx<R>*)D.basis;
   const double inv = 1.0 / rn;
-  for (int i = threadIdx.x; i < M; i += kGB) {
+  for (int i = threadIdx.x; i < M; i += 256) {
     cplx<R> o;
     o.re = (R)(rl[i].re * inv);
     o.im = (R)(rl[i].im * inv);
@@ -106,15 +94,28 @@ __global__ __launch_bounds__(kGB) void k_cycle_start(int M, int m, cplx<R>* __re
   }
 }
 
+// r <- ghat - r for open systems (r holds V x on entry).
+__global__ __launch_bounds__(256) void k_residual_combine(const SysDesc* __restrict__ sd) {
+  const SysDesc D = sd[blockIdx.x];
+  if (!D.sysi[0]) return;
+  for (int i = threadIdx.x; i < D.M; i += 256)
+    D.r[i] = cf64{D.ghat[i].re - D.r[i].re, D.ghat[i].im - D.r[i].im};
+}
+
+// status of every system into one array (one host copy per check)
+__global__ void k_gather_status(const SysDesc* __restrict__ sd, int n, int* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int* st = sd[k].sysi;
+  for (int q = 0; q < kSysiStride; ++q) out[k * kSysiStride + q] = st[q];
+}
+
 // One Arnoldi step of every open system.  Classical Gram-Schmidt with the
 // DGKS criterion: a second pass is made only if the first one removed more
 // than about 30% of the norm of w (||w'||^2 < 0.49 ||w||^2, with ||w'||^2
 // accumulated while w is updated).  BS threads per system.
 template <typename R, int BS>
-__global__ __launch_bounds__(BS) void k_arnoldi(int M, int m, int j, cplx<R>* __restrict__ basis,
-                                                cf64* __restrict__ H, double* __restrict__ cs,
-                                                cf64* __restrict__ sn, cf64* __restrict__ g,
-                                                double* __restrict__ sysd, int* __restrict__ sysi) {
+__global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, int j) {
   constexpr int NW = BS / 64;
   __shared__ double red[NW * (2 * kChunk + 1)];
   __shared__ cf64 coef[kMaxM + 1];
@@ -122,18 +123,19 @@ __global__ __launch_bounds__(BS) void k_arnoldi(int M, int m, int j, cplx<R>* __
   __shared__ double rc_s[kMaxM];  // previous rotations, prefetched for thread 0
   __shared__ cf64 rs_s[kMaxM];
   __shared__ cf64 g_j;
-  const int l = blockIdx.x;
-  int* st = sysi + kSysiStride * l;
+  const SysDesc D = sd[blockIdx.x];
+  int* st = D.sysi;
   if (!st[1]) return;
+  const int M = D.M, m = D.m;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  cplx<R>* V = basis + (int64_t)l * (m + 1) * M;
+  cplx<R>* V = (cplx<R>*)D.basis;
   cplx<R>* w = V + (int64_t)(j + 1) * M;
   for (int k = tid; k <= j + 1; k += BS) hacc[k] = cf64{0.0, 0.0};
   for (int k = tid; k < j; k += BS) {
-    rc_s[k] = cs[(int64_t)l * m + k];
-    rs_s[k] = sn[(int64_t)l * m + k];
+    rc_s[k] = D.cs[k];
+    rs_s[k] = D.sn[k];
   }
-  if (tid == 0) g_j = g[(int64_t)l * (m + 1) + j];
+  if (tid == 0) g_j = D.g[j];
   double nrm2 = 0.0;  // ||w||^2 after the last update
   for (int pass = 0; pass < 2; ++pass) {
     double w2 = 0.0;  // ||w||^2 before this pass
@@ -223,10 +225,10 @@ __global__ __launch_bounds__(BS) void k_arnoldi(int M, int m, int j, cplx<R>* __
     w[i] = o;
   }
   if (tid == 0) {
-    cf64* Hc = H + (int64_t)l * (m + 1) * m + (int64_t)(m + 1) * j;
-    double* csl = cs + (int64_t)l * m;
-    cf64* snl = sn + (int64_t)l * m;
-    cf64* gl = g + (int64_t)l * (m + 1);
+    cf64* Hc = D.H + (int64_t)(m + 1) * j;
+    double* csl = D.cs;
+    cf64* snl = D.sn;
+    cf64* gl = D.g;
     cf64 h[kMaxM + 2];
     for (int k = 0; k <= j; ++k) h[k] = hacc[k];
     h[j + 1] = cf64{nr, 0.0};
@@ -264,24 +266,21 @@ __global__ __launch_bounds__(BS) void k_arnoldi(int M, int m, int j, cplx<R>* __
     const double res = sqrt(gl[j + 1].re * gl[j + 1].re + gl[j + 1].im * gl[j + 1].im);
     st[2] = j + 1;
     st[3] += 1;
-    if (!(res > sysd[8 * l + 1]) || j + 1 >= m || nr == 0.0) st[1] = 0;
+    if (!(res > D.sysd[1]) || j + 1 >= m || nr == 0.0) st[1] = 0;
   }
 }
 
 template <typename R>
-__global__ __launch_bounds__(kGB) void k_cycle_finish(int M, int m, const cplx<R>* __restrict__ basis,
-                                                      const cf64* __restrict__ H,
-                                                      const cf64* __restrict__ g,
-                                                      const int* __restrict__ sysi,
-                                                      cf64* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_cycle_finish(const SysDesc* __restrict__ sd) {
   __shared__ cf64 y[kMaxM];
-  const int l = blockIdx.x;
-  const int* st = sysi + kSysiStride * l;
+  const SysDesc D = sd[blockIdx.x];
+  const int* st = D.sysi;
   if (!st[0]) return;
   const int k = st[2];
   if (k == 0) return;
-  const cf64* Hl = H + (int64_t)l * (m + 1) * m;
-  const cf64* gl = g + (int64_t)l * (m + 1);
+  const int M = D.M, m = D.m;
+  const cf64* Hl = D.H;
+  const cf64* gl = D.g;
   if (threadIdx.x == 0) {
     for (int i = k - 1; i >= 0; --i) {
       double re = gl[i].re, im = gl[i].im;
@@ -296,9 +295,9 @@ __global__ __launch_bounds__(kGB) void k_cycle_finish(int M, int m, const cplx<R
     }
   }
   __syncthreads();
-  const cplx<R>* V = basis + (int64_t)l * (m + 1) * M;
-  cf64* xl = x + (int64_t)l * M;
-  for (int i = threadIdx.x; i < M; i += kGB) {
+  const cplx<R>* V = (const cplx<R>*)D.basis;
+  cf64* xl = D.x;
+  for (int i = threadIdx.x; i < M; i += 256) {
     double re = xl[i].re, im = xl[i].im;
     for (int t = 0; t < k; ++t) {
       const cplx<R> v = V[(int64_t)t * M + i];
@@ -309,35 +308,42 @@ __global__ __launch_bounds__(kGB) void k_cycle_finish(int M, int m, const cplx<R
   }
 }
 
+void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(n), dim3(256), 0, s, sd);
+  CQM_HIP(hipGetLastError());
+}
+void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_combine, dim3(n), dim3(256), 0, s, sd);
+  CQM_HIP(hipGetLastError());
+}
+void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_status, dim3((n + 255) / 256), dim3(256), 0, s, sd, n, out);
+  CQM_HIP(hipGetLastError());
+}
 template <typename R>
-void launch_cycle_start(const GmresState& st, const cf64* r, double outer_tol, double inner_tol,
-                        hipStream_t s) {
-  hipLaunchKernelGGL((k_cycle_start<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m,
-                     (cplx<R>*)st.basis, st.g, st.sysd, st.sysi, r, outer_tol, inner_tol);
+void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_start<R>), dim3(n), dim3(256), 0, s, sd, outer_tol, inner_tol);
   CQM_HIP(hipGetLastError());
 }
 // Threads per system: latency of the block reductions dominates for short
 // vectors, memory parallelism for long ones.
-template <typename R> void launch_arnoldi(const GmresState& st, int j, hipStream_t s) {
-  if (st.M < 3072)
-    hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(st.nsys), dim3(256), 0, s, st.M, st.m, j,
-                       (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
+template <typename R> void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, hipStream_t s) {
+  if (maxM < 3072)
+    hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(n), dim3(256), 0, s, sd, j);
   else
-    hipLaunchKernelGGL((k_arnoldi<R, 1024>), dim3(st.nsys), dim3(1024), 0, s, st.M, st.m, j,
-                       (cplx<R>*)st.basis, st.H, st.cs, st.sn, st.g, st.sysd, st.sysi);
+    hipLaunchKernelGGL((k_arnoldi<R, 1024>), dim3(n), dim3(1024), 0, s, sd, j);
   CQM_HIP(hipGetLastError());
 }
-template <typename R> void launch_cycle_finish(const GmresState& st, cf64* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_cycle_finish<R>), dim3(st.nsys), dim3(kGB), 0, s, st.M, st.m,
-                     (const cplx<R>*)st.basis, st.H, st.g, st.sysi, x);
+template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_finish<R>), dim3(n), dim3(256), 0, s, sd);
   CQM_HIP(hipGetLastError());
 }
 
-template void launch_cycle_start<float>(const GmresState&, const cf64*, double, double, hipStream_t);
-template void launch_cycle_start<double>(const GmresState&, const cf64*, double, double, hipStream_t);
-template void launch_arnoldi<float>(const GmresState&, int, hipStream_t);
-template void launch_arnoldi<double>(const GmresState&, int, hipStream_t);
-template void launch_cycle_finish<float>(const GmresState&, cf64*, hipStream_t);
-template void launch_cycle_finish<double>(const GmresState&, cf64*, hipStream_t);
+template void launch_cycle_start<float>(const SysDesc*, int, double, double, hipStream_t);
+template void launch_cycle_start<double>(const SysDesc*, int, double, double, hipStream_t);
+template void launch_arnoldi<float>(const SysDesc*, int, int, int, hipStream_t);
+template void launch_arnoldi<double>(const SysDesc*, int, int, int, hipStream_t);
+template void launch_cycle_finish<float>(const SysDesc*, int, hipStream_t);
+template void launch_cycle_finish<double>(const SysDesc*, int, hipStream_t);
 
 }  // namespace cqm

@@ -29,11 +29,11 @@ __global__ void k_rhs(const double4* __restrict__ pts, int M, int F, double dt, 
   b[(int64_t)n * M + i] = acc;
 }
 
-void launch_rhs(const Problem& p, double* b, hipStream_t s) {
+void launch_rhs(const Problem& p, const Incident& inc, double* b, hipStream_t s) {
   dim3 grid((p.M + 255) / 256, p.F);
-  const double* smp = p.inc_kind == 2 ? p.samples : nullptr;
-  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, p.dev.pts64, (int)p.M, p.F, p.dt, p.dir[0],
-                     p.dir[1], p.dir[2], p.sigma, p.t0, p.amp, smp, b);
+  const double* smp = inc.kind == 2 ? inc.samples : nullptr;
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, p.dev.pts64, (int)p.M, p.F, p.dt, inc.dir[0],
+                     inc.dir[1], inc.dir[2], inc.sigma, inc.t0, inc.amp, smp, b);
   CQM_HIP(hipGetLastError());
 }
 
@@ -139,24 +139,6 @@ __global__ void k_vec_norms(const cf64* __restrict__ v, int64_t stride, int M,
 
 void launch_vec_norms(const cf64* v, int64_t stride, int M, int nsys, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_vec_norms, dim3(nsys), dim3(256), 0, s, v, stride, M, out);
-  CQM_HIP(hipGetLastError());
-}
-
-// r <- ghat - r for active systems (r holds V x on entry).
-__global__ void k_residual_combine(const cf64* __restrict__ ghat, cf64* __restrict__ r, int M,
-                                   const int* __restrict__ active) {
-  const int l = blockIdx.y;
-  if (active && !active[l * kSysiStride]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const int64_t k = (int64_t)l * M + i;
-  r[k] = cf64{ghat[k].re - r[k].re, ghat[k].im - r[k].im};
-}
-
-void launch_residual_combine(const cf64* ghat, cf64* r, int M, int nsys, const int* active,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_combine, dim3((M + 255) / 256, nsys), dim3(256), 0, s, ghat, r,
-                     M, active);
   CQM_HIP(hipGetLastError());
 }
 

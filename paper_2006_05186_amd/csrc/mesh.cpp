@@ -212,8 +212,7 @@ bool mode_is_h2(int mode) { return mode == CQM_MIXED_H2ACA || mode == CQM_FP64_H
 
 size_t h2_workspace_bytes(const Problem& p);  // h2.cpp
 
-void compute_layout(Problem& p) {
-  Layout L;
+size_t state_layout(const Problem& p, SolveState& st) {
   const size_t M = p.M, Fs = p.Fsys, m = p.opt.gmres_restart;
   const size_t inner = mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64);
   size_t off = 0;
@@ -222,18 +221,34 @@ void compute_layout(Problem& p) {
     off += align256(bytes);
     return o;
   };
-  L.b = take(sizeof(double) * p.F * M);
-  L.ghat = take(sizeof(cf64) * Fs * M);
-  L.x = take(sizeof(cf64) * Fs * M);
-  L.r = take(sizeof(cf64) * Fs * M);
-  L.basis = take(inner * Fs * (m + 1) * M);
-  L.H = take(sizeof(cf64) * Fs * (m + 1) * m);
-  L.cs = take(sizeof(double) * Fs * m);
-  L.sn = take(sizeof(cf64) * Fs * m);
-  L.g = take(sizeof(cf64) * Fs * (m + 1));
-  L.sysd = take(sizeof(double) * 8 * Fs);
-  L.sysi = take(sizeof(int) * kSysiStride * Fs);
-  L.scratch = take(4096);
+  st.b = take(sizeof(double) * p.F * M);
+  st.ghat = take(sizeof(cf64) * Fs * M);
+  st.x = take(sizeof(cf64) * Fs * M);
+  st.r = take(sizeof(cf64) * Fs * M);
+  st.basis = take(inner * Fs * (m + 1) * M);
+  st.H = take(sizeof(cf64) * Fs * (m + 1) * m);
+  st.cs = take(sizeof(double) * Fs * m);
+  st.sn = take(sizeof(cf64) * Fs * m);
+  st.g = take(sizeof(cf64) * Fs * (m + 1));
+  st.sysd = take(sizeof(double) * 8 * Fs);
+  st.sysi = take(sizeof(int) * kSysiStride * Fs);
+  st.scratch = take(4096);
+  st.total = off;
+  return off;
+}
+
+void compute_layout(Problem& p) {
+  Layout L;
+  const size_t M = p.M, Fs = p.Fsys;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  // the problem's own solve state first, then the operator
+  p.own.p = &p;
+  off = state_layout(p, p.own);
   if (mode_is_h2(p.opt.mode)) {
     L.partial = take(h2_workspace_bytes(p));
   } else {

@@ -1,0 +1,457 @@
+// Serving loop: continuous batching of solve requests on one GPU.
+//
+// A worker thread owns a HIP stream and an arena (one allocation of the HBM
+// budget, first-fit free list).  At every GMRES restart-cycle boundary it
+// retires finished requests (inverse transform, copy to host, free state) and
+// admits queued ones whose state -- and operator, unless cached -- fits the
+// arena; then it runs one cycle of the engine over every admitted request.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "internal.h"
+
+namespace cqm {
+void h2_release(Problem& p);
+}
+using namespace cqm;
+
+namespace {
+using clk = std::chrono::steady_clock;
+
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0, peak = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(char* b, size_t n) {
+    base = b;
+    size = n;
+    free_.clear();
+    free_[0] = n;
+  }
+  // first fit, 256-byte granularity; returns size_t(-1) when nothing fits
+  size_t alloc(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        used += n;
+        peak = std::max(peak, used);
+        return off;
+      }
+    return size_t(-1);
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct OpEntry {
+  uint64_t key = 0;
+  Problem* prob = nullptr;
+  size_t off = 0, bytes = 0;
+  int users = 0;
+  bool ready = false;
+  clk::time_point last;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  std::vector<double> verts;
+  std::vector<int32_t> tris;
+  int N = 0;
+  double T = 0;
+  Incident inc;
+  clk::time_point t_submit, t_done;
+  int state = 0;  // 0 queued, 1 active, 2 done, 3 rejected
+  int rc = CQM_OK;
+  std::vector<double> q;
+  cqm_diag diag{};
+  OpEntry* op = nullptr;
+  SolveState st;
+  size_t off = 0, bytes = 0;
+  int cycles = 0;
+};
+
+uint64_t fnv(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t k = 0; k < n; ++k) h = (h ^ p[k]) * 1099511628211ull;
+  return h;
+}
+}  // namespace
+
+struct cqm_server_s {
+  cqm_ctx_t ctx = nullptr;
+  cqm_server_opts opts{};
+  hipStream_t stream = nullptr;
+  char* arena_mem = nullptr;
+  Arena arena;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::thread worker;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;
+  std::map<uint64_t, std::unique_ptr<Request>> all;
+  std::vector<std::unique_ptr<OpEntry>> cache;
+  cqm_server_stats_t st{};
+  std::string worker_error;
+
+  // ---------------------------------------------------------------- worker
+  OpEntry* find_or_build(Request& r, bool* cannot_fit) {
+    *cannot_fit = false;
+    uint64_t key = fnv(r.verts.data(), r.verts.size() * sizeof(double));
+    key = fnv(r.tris.data(), r.tris.size() * sizeof(int32_t), key);
+    key = fnv(&r.N, sizeof(r.N), key);
+    key = fnv(&r.T, sizeof(r.T), key);
+    if (opts.cache_operators)
+      for (auto& e : cache)
+        if (e->key == key && e->ready) {
+          ++st.operator_cache_hits;
+          return e.get();
+        }
+    cqm_problem_t h = nullptr;
+    int rc = cqm_problem_create(ctx_handle(), r.verts.data(), (int64_t)r.verts.size() / 3, r.tris.data(),
+                                (int64_t)r.tris.size() / 3, r.N, r.T, &opts.solver, &h);
+    if (rc != CQM_OK) throw Error(rc, cqm_last_error());
+    Problem* p = h;
+    const size_t need = p->lay.total;
+    size_t off = arena.alloc(need);
+    while (off == size_t(-1) && evict_one()) off = arena.alloc(need);
+    if (off == size_t(-1)) {
+      *cannot_fit = need > arena.size;
+      cqm_problem_destroy(h);
+      return nullptr;
+    }
+    p->ws = arena.base + off;
+    p->ws_bytes = need;
+    p->own.p = p;
+    p->own.base = p->ws;
+    auto e = std::make_unique<OpEntry>();
+    e->key = key;
+    e->prob = p;
+    e->off = off;
+    e->bytes = need;
+    cache.push_back(std::move(e));
+    ++st.operators_built;
+    return cache.back().get();
+  }
+  bool evict_one() {  // least recently used operator without users
+    int best = -1;
+    for (int k = 0; k < (int)cache.size(); ++k)
+      if (cache[k]->users == 0 && (best < 0 || cache[k]->last < cache[best]->last)) best = k;
+    if (best < 0) return false;
+    arena.release(cache[best]->off, cache[best]->bytes);
+    cqm_problem_destroy(static_cast<cqm_problem_t>(cache[best]->prob));
+    cache.erase(cache.begin() + best);
+    return true;
+  }
+  cqm_ctx_t ctx_handle() { return ctx; }
+
+  // admit from the queue; returns true if the active set changed
+  bool admit() {
+    bool changed = false;
+    while ((int)active.size() < opts.max_active) {
+      Request* r;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (queue.empty()) break;
+        r = queue.front();
+      }
+      bool never = false;
+      OpEntry* op = nullptr;
+      try {
+        op = find_or_build(*r, &never);
+      } catch (const Error& e) {
+        reject(r, e.code);
+        continue;
+      }
+      if (!op) {
+        if (never || active.empty()) reject(r, CQM_ENOMEM);
+        break;  // wait for memory
+      }
+      Problem& p = *op->prob;
+      SolveState& s = r->st;
+      s = SolveState{};
+      s.p = &p;
+      const size_t sbytes = state_layout(p, s);
+      const size_t need = sbytes + sizeof(double) * (size_t)(r->N + 1) * p.M;
+      size_t off = arena.alloc(need);
+      if (off == size_t(-1)) {
+        if (active.empty()) {
+          // nothing will free up: drop idle operators other than this one
+          op->users++;
+          while (off == size_t(-1) && evict_one()) off = arena.alloc(need);
+          op->users--;
+        }
+        if (off == size_t(-1)) {
+          if (active.empty()) reject(r, CQM_ENOMEM);
+          break;
+        }
+      }
+      r->off = off;
+      r->bytes = need;
+      s.base = arena.base + off;
+      s.inc = r->inc;
+      s.q_out = reinterpret_cast<double*>(s.base + sbytes);
+      op->users++;
+      op->last = clk::now();
+      r->op = op;
+      pre_solve(s, stream, !op->ready);
+      op->ready = true;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        queue.pop_front();
+        r->state = 1;
+      }
+      active.push_back(r);
+      changed = true;
+      st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
+    }
+    return changed;
+  }
+  void reject(Request* r, int code) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!queue.empty() && queue.front() == r) queue.pop_front();
+    r->state = 3;
+    r->rc = code;
+    r->t_done = clk::now();
+    ++st.rejected;
+    cv_done.notify_all();
+  }
+  void retire(Engine& E, int k) {
+    Request* r = active[k];
+    E.finish_diag(k, stream);
+    post_solve(r->st, stream);
+    r->q.resize((size_t)(r->N + 1) * r->st.p->M);
+    CQM_HIP(hipMemcpyAsync(r->q.data(), r->st.q_out, sizeof(double) * r->q.size(), hipMemcpyDeviceToHost, stream));
+    CQM_HIP(hipStreamSynchronize(stream));
+    r->diag = r->st.diag;
+    r->diag.cycles = r->cycles;
+    arena.release(r->off, r->bytes);
+    r->op->users--;
+    r->op->last = clk::now();
+    if (!opts.cache_operators && r->op->users == 0) {
+      for (int q = 0; q < (int)cache.size(); ++q)
+        if (cache[q].get() == r->op) {
+          arena.release(cache[q]->off, cache[q]->bytes);
+          cqm_problem_destroy(static_cast<cqm_problem_t>(cache[q]->prob));
+          cache.erase(cache.begin() + q);
+          break;
+        }
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    r->rc = diag_status(r->diag);
+    r->state = 2;
+    r->t_done = clk::now();
+    ++st.completed;
+    cv_done.notify_all();
+  }
+
+  void run() {
+    try {
+      CQM_HIP(hipSetDevice(ctx->device));
+      Engine E(*ctx);
+      bool dirty = true;
+      for (;;) {
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+          if (stop && queue.empty() && active.empty()) break;
+        }
+        const size_t before = active.size();
+        if (admit()) dirty = true;
+        if (active.empty()) {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait_for(lk, std::chrono::milliseconds(1));
+          continue;
+        }
+        if (dirty) {
+          std::vector<SolveState*> S;
+          for (Request* r : active) S.push_back(&r->st);
+          E.set(S, stream);
+          for (size_t k = before; k < active.size(); ++k) E.init((int)k, stream);
+          dirty = false;
+        }
+        E.cycle(stream);
+        ++st.cycles;
+        E.status(stream);
+        for (Request* r : active) r->cycles++;
+        // retire finished (or out-of-cycles) requests, highest index first
+        for (int k = (int)active.size() - 1; k >= 0; --k) {
+          Request* r = active[k];
+          if (E.state_done(k) || r->cycles >= r->st.p->opt.max_cycles) {
+            retire(E, k);
+            active.erase(active.begin() + k);
+            dirty = true;
+          }
+        }
+        if (dirty && !active.empty()) {
+          // keep the survivors' descriptors valid for the next cycle
+          std::vector<SolveState*> S;
+          for (Request* r : active) S.push_back(&r->st);
+          E.set(S, stream);
+          dirty = false;
+        }
+      }
+    } catch (const std::exception& e) {
+      std::lock_guard<std::mutex> lk(mu);
+      worker_error = e.what();
+      for (Request* r : queue) {
+        r->state = 3;
+        r->rc = CQM_EDEVICE;
+      }
+      queue.clear();
+      for (Request* r : active) {
+        r->state = 3;
+        r->rc = CQM_EDEVICE;
+      }
+      active.clear();
+      cv_done.notify_all();
+    }
+  }
+};
+
+namespace {
+thread_local std::string g_srv_err;
+}
+
+extern "C" {
+
+int cqm_server_default_options(cqm_server_opts* o) {
+  if (!o) return CQM_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->max_active = 16;
+  o->cache_operators = 1;
+  cqm_default_options(&o->solver);
+  o->solver.reuse_operator = 1;
+  return CQM_OK;
+}
+
+int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* opts, cqm_server_t* out) {
+  if (!ctx || !out || hbm_budget < (1u << 20)) return CQM_EINVAL;
+  auto* s = new cqm_server_s();
+  s->ctx = ctx;
+  if (opts) s->opts = *opts;
+  else cqm_server_default_options(&s->opts);
+  s->opts.solver.reuse_operator = 1;
+  s->opts.solver.profile = 0;
+  if (s->opts.max_active < 1) s->opts.max_active = 1;
+  if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&s->arena_mem, hbm_budget) != hipSuccess) {
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return CQM_ENOMEM;
+  }
+  s->arena.init(s->arena_mem, hbm_budget);
+  s->worker = std::thread([s] { s->run(); });
+  *out = s;
+  return CQM_OK;
+}
+
+int cqm_server_submit(cqm_server_t s, const cqm_request* q, uint64_t* ticket) {
+  if (!s || !q || !ticket || !q->vertices || !q->tris || q->nv < 3 || q->M < 1 || q->N < 2 || !(q->T > 0))
+    return CQM_EINVAL;
+  auto r = std::make_unique<Request>();
+  r->verts.assign(q->vertices, q->vertices + 3 * q->nv);
+  r->tris.assign(q->tris, q->tris + 3 * q->M);
+  r->N = q->N;
+  r->T = q->T;
+  const double n = std::sqrt(q->direction[0] * q->direction[0] + q->direction[1] * q->direction[1] +
+                             q->direction[2] * q->direction[2]);
+  if (!(n > 0) || !(q->sigma > 0)) return CQM_EINVAL;
+  r->inc.kind = 1;
+  for (int k = 0; k < 3; ++k) r->inc.dir[k] = q->direction[k] / n;
+  r->inc.sigma = q->sigma;
+  r->inc.t0 = q->t0;
+  r->inc.amp = q->amplitude;
+  r->t_submit = clk::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->ticket = s->next_ticket++;
+  *ticket = r->ticket;
+  s->queue.push_back(r.get());
+  s->all[r->ticket] = std::move(r);
+  ++s->st.submitted;
+  s->cv.notify_all();
+  return CQM_OK;
+}
+
+int cqm_server_poll(cqm_server_t s, uint64_t ticket, int32_t* done, double* q_out, cqm_diag* diag,
+                    double* latency_ms) {
+  if (!s || !done) return CQM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return CQM_EINVAL;
+  Request& r = *it->second;
+  if (r.state < 2) {
+    *done = 0;
+    return CQM_OK;
+  }
+  *done = r.state == 2 ? 1 : -1;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+  if (r.state == 2) {
+    if (q_out) std::memcpy(q_out, r.q.data(), sizeof(double) * r.q.size());
+    if (diag) *diag = r.diag;
+  }
+  return r.rc;
+}
+
+int cqm_server_drain(cqm_server_t s) {
+  if (!s) return CQM_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->active.empty() && (int64_t)(s->st.completed + s->st.rejected) == s->st.submitted; });
+  return s->worker_error.empty() ? CQM_OK : CQM_EDEVICE;
+}
+
+int cqm_server_stats(cqm_server_t s, cqm_server_stats_t* out) {
+  if (!s || !out) return CQM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  out->active = (int64_t)s->active.size();
+  out->queued = (int64_t)s->queue.size();
+  out->arena_bytes = (int64_t)s->arena.size;
+  out->peak_arena_bytes = (int64_t)s->arena.peak;
+  return CQM_OK;
+}
+
+int cqm_server_destroy(cqm_server_t s) {
+  if (!s) return CQM_OK;
+  cqm_server_drain(s);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->ctx->device);
+  for (auto& e : s->cache) cqm_problem_destroy(static_cast<cqm_problem_t>(e->prob));
+  s->cache.clear();
+  if (s->arena_mem) (void)hipFree(s->arena_mem);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return CQM_OK;
+}
+
+}  // extern "C"

@@ -61,3 +61,53 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(problems, stream=None):
+    """Solve several Problem objects together (cqm_solve_batch).  Returns the
+    list of (q, diag) and the aggregate return code."""
+    import torch
+    outs = [torch.empty((p.N + 1, p.M), dtype=torch.float64, device=p.device) for p in problems]
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc, diags = C.cqm_solve_batch([p.handle for p in problems], [o.data_ptr() for o in outs], st)
+    return list(zip(outs, diags)), rc
+
+
+class Server:
+    """Serving loop on one GPU (cqm_server_*): submit requests as they arrive,
+    poll for results.  Marshalling only."""
+
+    def __init__(self, ctx, hbm_budget, max_active=16, cache_operators=1, **solver):
+        self.opts = C.cqm_server_default_options(max_active=max_active,
+                                                 cache_operators=cache_operators, **solver)
+        self.handle = C.cqm_server_create(ctx, hbm_budget, self.opts)
+        self.shapes = {}
+
+    def submit(self, vertices, tris, N, T, direction=(1.0, 0.0, 0.0), sigma=0.25, t0=1.5,
+               amplitude=1.0):
+        t = C.cqm_server_submit(self.handle, vertices, tris, N, T, direction, sigma, t0, amplitude)
+        self.shapes[t] = (int(N) + 1, int(np.asarray(tris).shape[0]))
+        return t
+
+    def poll(self, ticket):
+        """(done, rc, q or None, diag, latency_ms)."""
+        out = np.empty(self.shapes[ticket])
+        done, rc, d, lat = C.cqm_server_poll(self.handle, ticket, out)
+        return done, rc, (out if done == 1 else None), d, lat
+
+    def drain(self):
+        C.cqm_server_drain(self.handle)
+
+    def stats(self):
+        return C.cqm_server_stats(self.handle).as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            C.cqm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,74 @@
+"""Uneven batch: problems of different meshes, step counts and pulses solved
+in shared launches match the same problems solved alone and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import cqm_workloads as W
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_05186_amd import cqm as C  # noqa: E402
+from paper_2006_05186_amd.solver import Problem, solve_batch  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = C.cqm_ctx_create(0)
+    yield c
+    C.cqm_ctx_destroy(c)
+
+
+def test_uneven_batch_matches_alone_and_oracle(ctx):
+    mix = W.problem_mix(6, seed=7, levels=(1, 2), steps=(8, 16), T=2.0)
+    say("batch of " + ", ".join(f"{w.name}(M={w.M},N={w.N})" for w in mix))
+    probs, alone = [], []
+    for w in mix:
+        V, T = w.mesh()
+        for store in (probs, alone):
+            p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
+            p.set_plane_wave(w.wave.direction, w.wave.sigma, w.wave.t0)
+            store.append(p)
+    res, rc = solve_batch(probs)
+    assert rc == C.CQM_OK
+    for w, (q, d), p in zip(mix, res, alone):
+        qa, rca, _ = p.solve()
+        V, T = w.mesh()
+        _, _, area = O.triangle_quadrature(V, T)
+        ref = O.solve(V, T, w.N, w.T, direction=w.wave.direction, sigma=w.wave.sigma, t0=w.wave.t0)
+        e_alone = O.rel_error(q.cpu().numpy(), qa.cpu().numpy(), area)
+        e_or = O.rel_error(q.cpu().numpy(), ref, area)
+        say(f"  {w.name}: vs alone {e_alone:.2e} vs oracle {e_or:.2e} iters {d.total_iters}")
+        assert rca == C.CQM_OK and e_alone < 1e-9 and e_or < 1e-8
+    for p in probs + alone:
+        p.close()
+
+
+def test_batch_mixing_forms_and_precisions(ctx):
+    """Dense, matrix-free and FP64 problems in one call (grouped by precision)."""
+    V1, T1 = W.icosphere(1)
+    V2, T2 = W.ellipsoid(1, (1.2, 0.8, 1.0))
+    specs = [(V1, T1, 8, C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE),
+             (V2, T2, 10, C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE),
+             (V1, T1, 6, C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE)]
+    probs = []
+    for V, T, N, mode, form in specs:
+        p = Problem(ctx, V, T, N, 2.0, mode=mode, form=form)
+        p.set_plane_wave()
+        probs.append(p)
+    res, rc = solve_batch(probs)
+    assert rc == C.CQM_OK
+    for (V, T, N, _, _), (q, d) in zip(specs, res):
+        _, _, area = O.triangle_quadrature(V, T)
+        ref = O.solve(V, T, N, 2.0)
+        assert O.rel_error(q.cpu().numpy(), ref, area) < 1e-8
+    for p in probs:
+        p.close()
