@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_PER_UNIT = 10
 
 WORKLOADS = {"C1": W.C1, "C2": W.C2, "C3": W.C3}
-KCLS = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "gmres", "other"]
+KCLS = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
 
 
 def area_of(V, T):
@@ -46,9 +46,9 @@ def rel_err(q, ref, area):
     return float(np.sqrt(np.sum(area * (q - ref) ** 2) / np.sum(area * ref ** 2)))
 
 
-def run_variant(C, Problem, ctx, wl, mode, form, steps, warmup, torch):
+def run_variant(C, Problem, ctx, wl, mode, form, steps, warmup, torch, profile=0):
     V, T = wl.mesh()
-    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form, profile=1)
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form, profile=profile)
     p.set_plane_wave(wl.wave.direction, wl.wave.sigma, wl.wave.t0, wl.wave.amplitude)
     out = torch.empty((wl.N + 1, len(T)), dtype=torch.float64, device="cuda")
     for _ in range(warmup):
@@ -80,28 +80,59 @@ def summarise_kernels(diags):
     return ms, calls
 
 
-def roofline(diags, wl_units, form, mode):
-    """Dominant kernel class over the timed steps and its roofline fraction."""
+def roofline(diags):
+    """Dominant kernel class over the timed steps and where it stands against
+    its roofline.  Durations are the HIP-event times of every launch in the
+    timed steps (recorded on the solve stream); the algorithmic work is what
+    the kernels counted themselves: kernel values for the evaluation kernels
+    (x FLOPS_PER_UNIT), bytes for the bandwidth-bound products and the
+    Arnoldi step."""
     ms, calls = summarise_kernels(diags)
+    work = np.zeros(len(KCLS))
+    for d in diags:
+        work += np.asarray(d["kernel_work"])
     k = int(np.argmax(ms))
     name = KCLS[k]
-    avg_ms = ms[k] / max(calls[k], 1)
-    out = {"kernel": name, "avg_ms": avg_ms, "launches": int(calls[k]),
-           "share": float(ms[k] / ms.sum())}
+    n = max(int(calls[k]), 1)
+    avg_ms = ms[k] / n
+    out = {"kernel": name, "avg_launch_ms": avg_ms, "launches": int(calls[k]),
+           "share_of_kernel_time": float(ms[k] / ms.sum()),
+           "work_per_launch": work[k] / n}
     if name in ("far32", "far64", "assemble"):
-        # every launch evaluates the far field of all frequency systems that
-        # are still open; the assembly launch covers all of them exactly
-        units = wl_units if name == "assemble" else None
-        if units is None:
-            return out | {"bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s",
-                          "frac": None, "traffic": None}
-        ach = units * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if name in ("far64", "assemble") else PEAK_FP32_TFLOPS
+        ach = work[k] / n * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP32_TFLOPS if name == "far32" else PEAK_FP64_TFLOPS
         return out | {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                      "frac": ach / peak, "traffic": None, "units_per_launch": units,
+                      "frac": ach / peak, "traffic": None, "work_unit": "kernel values",
                       "flops_per_unit": FLOPS_PER_UNIT}
+    if name in ("gemv32", "gemv64", "arnoldi"):
+        ach = work[k] / n / (avg_ms * 1e-3) / 1e9
+        return out | {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": ach / PEAK_HBM_GBS, "traffic": traffic_per_launch(name),
+                      "work_unit": "bytes"}
     return out | {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                   "frac": None, "traffic": None}
+
+
+def traffic_per_launch(cls):
+    """HBM bytes per launch of the class's kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
+    or None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{cls}_sphere1280_N64.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            key, _, val = line.partition(":")
+            kv[key.strip()] = val.strip()
+    try:
+        src = os.path.join(ROOT, kv["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["source_sha256_16"]:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, sample_freqs=2):
@@ -138,6 +169,73 @@ def cpu_baseline(wl, sample_freqs=2):
                       f"x{H}", "seconds_per_solve": t_solve}
 
 
+def run_batch48(C, torch, ctx):
+    """Uneven batch: 48 seeded problems (spheres/ellipsoids of 80..5120
+    triangles, N in {16,32,64,128}, random direction and pulse width) solved
+    by one cqm_solve_batch call; dense stored operators up to 1280 triangles,
+    matrix-free products for 5120."""
+    from paper_2006_05186_amd.solver import Problem, solve_batch
+    mix = W.problem_mix(48)
+    probs = []
+    for w in mix:
+        V, T = w.mesh()
+        form = C.CQM_FORM_DENSE if len(T) <= 1280 else C.CQM_FORM_MATRIX_FREE
+        p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=form)
+        p.set_plane_wave(w.wave.direction, w.wave.sigma, w.wave.t0)
+        probs.append(p)
+    solve_batch(probs)  # warm-up (kernels, descriptor buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, rc = solve_batch(probs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters = sum(d.total_iters for _, d in res)
+    for p in probs:
+        p.close()
+    return {"problems": len(mix), "makespan_s": el, "solves_per_s": len(mix) / el, "rc": rc,
+            "triangles": sorted({w.M for w in mix}), "steps": sorted({w.N for w in mix}),
+            "total_arnoldi_steps": iters}
+
+
+def run_serving(C, torch, ctx, rate, duration):
+    """Poisson stream of solve requests on the 5120-triangle sphere (N = 128,
+    T = 6, random direction and pulse per request) served by the continuous-
+    batching loop with the operator cache (dense mixed form)."""
+    from paper_2006_05186_amd.solver import Server
+    wl = W.C3
+    V, T = wl.mesh()
+    arrivals = W.poisson_arrivals(rate, duration)
+    rng = np.random.default_rng(W.DEFAULT_SEED + 1)
+    srv = Server(ctx, 96 << 30, max_active=16, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
+    # the first request builds the cached operator; it is timed like the rest
+    tickets = []
+    t0 = time.perf_counter()
+    for a in arrivals:
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        sigma = float(rng.uniform(0.2, 0.4))
+        tickets.append(srv.submit(V, T, wl.N, wl.T, W.random_direction(rng), sigma, 1.0 + 2 * sigma))
+    lat, rcs = {}, []
+    while len(lat) < len(tickets):
+        for t in tickets:
+            if t not in lat:
+                done, rc, _, d, l = srv.poll(t)
+                if done:
+                    lat[t] = l
+                    rcs.append(rc)
+        time.sleep(0.001)
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    L = np.asarray(list(lat.values()))
+    return {"workload": wl.name, "rate_per_s": rate, "duration_s": duration, "requests": len(tickets),
+            "solves_per_s": len(tickets) / el, "p50_ms": float(np.percentile(L, 50)),
+            "p99_ms": float(np.percentile(L, 99)), "max_ms": float(L.max()),
+            "all_ok": all(r == C.CQM_OK for r in rcs), "peak_active": st["peak_active"],
+            "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +244,8 @@ def main():
     ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs "
@@ -165,8 +265,13 @@ def main():
     value = K / r["elapsed"]
     lat_ms = np.asarray(r["lat"]) * 1e3
     d0 = r["diags"][-1]
-    units = d0["far_units"]
-    rl = roofline(r["diags"], units, main_form, main_mode)
+    # Kernel durations come from HIP events recorded around every launch on
+    # the solve stream; the event records cost about a tenth of a step, so
+    # they run in a second pass of the same workload right after the timed
+    # steps rather than inside them.
+    KP = min(K, 10)
+    rp = run_variant(C, Problem, ctx, wl, main_mode, main_form, KP, 1, torch, profile=1)
+    rl = roofline(rp["diags"])
     out = {
         "metric": "time-domain CQM-BEM solves/s + p50/p99 latency; kernel entries/s vs VALU peak",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -180,12 +285,13 @@ def main():
                        "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "dominant_kernel": {k: v for k, v in rl.items()
-                            if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+                            if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+        | {"profiled_steps": KP, "profiled_ms_per_step": 1e3 * rp["elapsed"] / KP},
         "solver": {"total_iters": d0["total_iters"], "max_iters": d0["max_iters"],
                    "cycles": d0["cycles"], "max_rel_residual": d0["max_rel_residual"],
                    "t_setup_ms": d0["t_setup_ms"], "t_solve_ms": d0["t_solve_ms"],
                    "workspace_GB": r["workspace"] / 1e9},
-        "kernel_ms_per_step": dict(zip(KCLS, (summarise_kernels(r["diags"])[0] / K).round(4).tolist())),
+        "kernel_ms_per_step": dict(zip(KCLS, (summarise_kernels(rp["diags"])[0] / KP).round(4).tolist())),
     }
     golden = os.path.join(ROOT, "tests", "golden", f"{wl.name}.npz")
     if os.path.exists(golden):
@@ -196,7 +302,7 @@ def main():
         for name, mode, form, steps in (("fp64_dense", C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE, 10),
                                         ("mixed_matrix_free", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE, 5),
                                         ("fp64_matrix_free", C.CQM_FP64_PLAIN, C.CQM_FORM_MATRIX_FREE, 3)):
-            rv = run_variant(C, Problem, ctx, wl, mode, form, steps, 1, torch)
+            rv = run_variant(C, Problem, ctx, wl, mode, form, steps, 1, torch, profile=1)
             ms, calls = summarise_kernels(rv["diags"])
             v = {"solves_per_s": steps / rv["elapsed"]}
             for kn in ("far32", "far64"):
@@ -231,6 +337,9 @@ def main():
                                     "frac_fp32_peak": u * FLOPS_PER_UNIT / t_apply / 1e12 / PEAK_FP32_TFLOPS}
         p.close()
         out["variants"] = var
+    if not args.no_variants:
+        out["batch48"] = run_batch48(C, torch, ctx)
+        out["serving"] = run_serving(C, torch, ctx, rate=args.serve_rate, duration=args.serve_seconds)
     C.cqm_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -89,8 +89,17 @@ typedef struct cqm_options {
                             solves of the same problem                (0)   */
   int32_t profile;       /* nonzero: time kernel classes with HIP events
                             on the solve stream (cqm_diag.kernel_ms)  (0)   */
-  int32_t reserved[6];
+  int32_t arnoldi_layout;/* CQM_ARNOLDI_*: workgroups per system in the
+                            Arnoldi step                             (AUTO) */
+  int32_t reserved[5];
 } cqm_options;
+
+/* Arnoldi step layouts (cqm_options.arnoldi_layout).  AUTO splits when a
+   batch has fewer systems than the GPU has compute units (256). */
+#define CQM_ARNOLDI_AUTO 0   /* choose by the number of systems            */
+#define CQM_ARNOLDI_GROUP 1  /* one workgroup per system, one launch      */
+#define CQM_ARNOLDI_SPLIT 2  /* ceil(M/256) workgroups per system, three
+                                launches (dots, update, finish)           */
 
 /* Kernel classes timed when cqm_options.profile is set. */
 #define CQM_K_FAR32 0    /* matrix-free far-field product, FP32          */
@@ -100,8 +109,9 @@ typedef struct cqm_options {
                             precision                                    */
 #define CQM_K_GEMV64 4   /* stored or compressed operator products, FP64 */
 #define CQM_K_NEAR 5     /* near-field static and per-frequency parts    */
-#define CQM_K_GMRES 6    /* Arnoldi, restart and update kernels          */
-#define CQM_K_OTHER 7    /* right-hand side, DFTs, compression kernels   */
+#define CQM_K_ARNOLDI 6  /* Arnoldi step: orthogonalisation, Givens      */
+#define CQM_K_OTHER 7    /* right-hand side, DFTs, GMRES restart/update
+                            bookkeeping, compression kernels             */
 #define CQM_K_CLASSES 8
 
 /* Diagnostics of one solve (host struct). */
@@ -124,6 +134,12 @@ typedef struct cqm_diag {
                                far-field product (matrix-free form)        */
   double kernel_ms[8];      /* GPU time per CQM_K_* class (profile only)   */
   int32_t kernel_calls[8];  /* launches per CQM_K_* class (profile only)   */
+  double kernel_work[8];    /* algorithmic work per CQM_K_* class, counted
+                               by the kernels (profile only): FAR32, FAR64
+                               and ASSEMBLE in point-pair-frequency kernel
+                               values evaluated; GEMV32, GEMV64 and ARNOLDI
+                               in bytes the algorithm must move (operator
+                               rows once, Krylov vectors per pass); others 0 */
   int32_t reserved[6];
 } cqm_diag;
 

@@ -15,6 +15,7 @@ __all__ = [
     "CQM_OK", "CQM_EINVAL", "CQM_ENOMEM", "CQM_ENOCONV", "CQM_ENAN", "CQM_EDEVICE",
     "CQM_FP64_PLAIN", "CQM_MIXED_PLAIN", "CQM_MIXED_H2ACA", "CQM_FP64_H2ACA",
     "CQM_FORM_MATRIX_FREE", "CQM_FORM_DENSE", "CQM_BAND_FULL", "CQM_BAND_HALF", "KERNEL_CLASSES",
+    "CQM_ARNOLDI_AUTO", "CQM_ARNOLDI_GROUP", "CQM_ARNOLDI_SPLIT",
     "CqmError", "cqm_options", "cqm_diag", "library_path", "load_library",
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
@@ -29,7 +30,8 @@ CQM_OK, CQM_EINVAL, CQM_ENOMEM, CQM_ENOCONV, CQM_ENAN, CQM_EDEVICE = 0, -1, -2, 
 CQM_FP64_PLAIN, CQM_MIXED_PLAIN, CQM_MIXED_H2ACA, CQM_FP64_H2ACA = 0, 1, 2, 3
 CQM_FORM_MATRIX_FREE, CQM_FORM_DENSE = 0, 1
 CQM_BAND_FULL, CQM_BAND_HALF = 0, 1
-KERNEL_CLASSES = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "gmres", "other"]
+CQM_ARNOLDI_AUTO, CQM_ARNOLDI_GROUP, CQM_ARNOLDI_SPLIT = 0, 1, 2
+KERNEL_CLASSES = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
 
 EXPORTED_SYMBOLS = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
@@ -55,7 +57,7 @@ class cqm_options(ctypes.Structure):
         ("n_min", ctypes.c_int32), ("eta", ctypes.c_double), ("cheb_m", ctypes.c_int32),
         ("eps_aca", ctypes.c_double), ("aca_band", ctypes.c_int32), ("q_duffy", ctypes.c_int32),
         ("reuse_operator", ctypes.c_int32), ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("arnoldi_layout", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -69,13 +71,15 @@ class cqm_diag(ctypes.Structure):
         ("max_rank", ctypes.c_int32), ("mean_rank", ctypes.c_double),
         ("n_far_blocks", ctypes.c_int32), ("n_near_blocks", ctypes.c_int32),
         ("far_units", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
-        ("kernel_calls", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32 * 6),
+        ("kernel_calls", ctypes.c_int32 * 8), ("kernel_work", ctypes.c_double * 8),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
     def as_dict(self):
         out = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
         out["kernel_ms"] = list(self.kernel_ms)
         out["kernel_calls"] = list(self.kernel_calls)
+        out["kernel_work"] = list(self.kernel_work)
         return out
 
 

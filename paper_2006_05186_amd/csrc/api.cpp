@@ -27,7 +27,19 @@ void KernelTimer::end(hipStream_t s) {
   if (!on) return;
   if (hipEventRecord(pool[used + 1], s) == hipSuccess) used += 2;
 }
-void KernelTimer::collect(double* ms, int* calls) {
+void KernelTimer::reset(hipStream_t s) {
+  cls.clear();
+  used = 0;
+  if (!on) return;
+  if (!work_d) CQM_HIP(hipMalloc(&work_d, sizeof(unsigned long long) * CQM_K_CLASSES));
+  CQM_HIP(hipMemsetAsync(work_d, 0, sizeof(unsigned long long) * CQM_K_CLASSES, s));
+}
+void KernelTimer::collect(double* ms, int* calls, double* work) {
+  if (work_d && work) {
+    unsigned long long w[CQM_K_CLASSES];
+    CQM_HIP(hipMemcpy(w, work_d, sizeof(w), hipMemcpyDeviceToHost));
+    for (int c = 0; c < CQM_K_CLASSES; ++c) work[c] += (double)w[c];
+  }
   for (size_t k = 0; k < cls.size() && 2 * k + 1 < used + 1 && 2 * k + 1 < pool.size(); ++k) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
@@ -39,6 +51,8 @@ void KernelTimer::collect(double* ms, int* calls) {
   used = 0;
 }
 void KernelTimer::release() {
+  if (work_d) (void)hipFree(work_d);
+  work_d = nullptr;
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   pool.clear();
   cls.clear();
@@ -133,6 +147,12 @@ int cqm_ctx_create(int device, cqm_ctx_t* out) {
 }
 
 int cqm_ctx_destroy(cqm_ctx_t ctx) {
+  if (!ctx) return CQM_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->eb.desc) (void)hipFree(ctx->eb.desc);
+  if (ctx->eb.map) (void)hipFree(ctx->eb.map);
+  if (ctx->eb.groups) (void)hipFree(ctx->eb.groups);
+  if (ctx->eb.status) (void)hipFree(ctx->eb.status);
   delete ctx;
   return CQM_OK;
 }
@@ -158,6 +178,8 @@ int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv, const 
     require(o.cheb_m >= 2 && o.cheb_m <= 8, CQM_EINVAL, "cheb_m in [2,8]");
     require(o.n_min >= 2 && o.eta > 0 && o.eps_aca > 0, CQM_EINVAL, "tree / ACA parameters");
     require(o.aca_band == CQM_BAND_FULL || o.aca_band == CQM_BAND_HALF, CQM_EINVAL, "aca_band");
+    require(o.arnoldi_layout >= CQM_ARNOLDI_AUTO && o.arnoldi_layout <= CQM_ARNOLDI_SPLIT, CQM_EINVAL,
+            "arnoldi_layout");
     for (int64_t k = 0; k < 3 * nv; ++k)
       require(std::isfinite(vertices[k]), CQM_EINVAL, "non-finite vertex coordinate");
     for (int64_t k = 0; k < 3 * M; ++k)
@@ -209,7 +231,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
   h2_release(*p);
   p->timer.release();
   void* bufs[] = {p->dev.pts64, p->dev.pts32, p->dev.vid, p->dev.area, p->dev.verts,
-                  p->dev.near_rowptr, p->dev.near_col, p->dev.near_kind, p->dev.near_vtx,
+                  p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
                   p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea32,
                   p->dev.pb32};

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <map>
 
 #include "internal.h"
 
@@ -53,8 +54,9 @@ void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R
   } else {
     cplx<R>* partial = wsp<cplx<R>>(p, p.lay.partial);
     {
-      Timed t(p, sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64, s);
-      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, s);
+      const int c = sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64;
+      Timed t(p, c, s);
+      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, p.timer.ctr(c), s);
     }
     Timed t(p, CQM_K_NEAR, s);
     launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, wsp<cf64>(p, p.lay.near_val),
@@ -93,7 +95,7 @@ void prepare_operator(Problem& p, hipStream_t s) {
     cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
     {
       Timed t(p, CQM_K_ASSEMBLE, s);
-      launch_dense_assemble(p, d64, d32, s);
+      launch_dense_assemble(p, d64, d32, p.timer.ctr(CQM_K_ASSEMBLE), s);
     }
     Timed t(p, CQM_K_NEAR, s);
     launch_dense_scatter_near(p, nv, d64, d32, s);
@@ -151,10 +153,16 @@ int diag_status(const cqm_diag& dg) {
 }
 
 // ------------------------------------------------------------ engine
+// Systems per batch below which the Arnoldi step is split over row slices
+// (256 compute units: one workgroup per system leaves most of them idle).
+constexpr int kSplitBelow = 256;
+
 void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   S_ = S;
   hd_.clear();
   rows_.clear();
+  groups_.clear();
+  std::map<const void*, int> slot;
   maxM_ = 0;
   if (S_.empty()) return;
   m_ = S_[0]->p->opt.gmres_restart;
@@ -184,28 +192,50 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
       d.x = st->at<cf64>(st->x) + (size_t)l * M;
       d.r = st->at<cf64>(st->r) + (size_t)l * M;
       d.ghat = st->at<cf64>(st->ghat) + (size_t)l * M;
+      d.part = st->at<double>(st->part) + (size_t)l * ((M + kArnRows - 1) / kArnRows) * (4 * (m_ + 1) + 2);
       if (dense_form(p)) {
         d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * M * M;
         d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * M * M) : nullptr;
-        for (int r0 = 0; r0 < M; r0 += 4) rows_.push_back(RowBlock{(int)hd_.size(), r0});
+        // join the group of systems on the same operator slice, if any
+        auto it = slot.find(d.V64);
+        if (it == slot.end() || groups_[it->second].n == kMaxGroup) {
+          GemvGroup g{};
+          g.n = 0;
+          slot[d.V64] = (int)groups_.size();
+          groups_.push_back(g);
+          for (int r0 = 0; r0 < M; r0 += 4) rows_.push_back(RowBlock{(int)groups_.size() - 1, r0});
+          it = slot.find(d.V64);
+        }
+        GemvGroup& g = groups_[it->second];
+        g.sys[g.n++] = (int)hd_.size();
       }
       hd_.push_back(d);
     }
   }
+  grouped_ = false;
+  for (const GemvGroup& g : groups_) grouped_ |= g.n > 1;
   const int n = (int)hd_.size();
+  // split the Arnoldi step over row slices when one workgroup per system
+  // would leave most compute units idle
+  const int lay = S_[0]->p->opt.arnoldi_layout;
+  split_ = lay == CQM_ARNOLDI_SPLIT || (lay == CQM_ARNOLDI_AUTO && n < kSplitBelow);
   ensure(ctx.eb.desc, ctx.eb.desc_cap, hd_.size());
   ensure(ctx.eb.map, ctx.eb.map_cap, std::max<size_t>(1, rows_.size()));
+  ensure(ctx.eb.groups, ctx.eb.groups_cap, std::max<size_t>(1, groups_.size()));
   ensure(ctx.eb.status, ctx.eb.status_cap, (size_t)kSysiStride * n);
   CQM_HIP(hipMemcpyAsync(ctx.eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
-  if (!rows_.empty())
+  if (!rows_.empty()) {
     CQM_HIP(hipMemcpyAsync(ctx.eb.map, rows_.data(), sizeof(RowBlock) * rows_.size(),
                            hipMemcpyHostToDevice, s));
+    CQM_HIP(hipMemcpyAsync(ctx.eb.groups, groups_.data(), sizeof(GemvGroup) * groups_.size(),
+                           hipMemcpyHostToDevice, s));
+  }
   flags_.assign((size_t)kSysiStride * n, 0);
 }
 
 void Engine::init(int k, hipStream_t s) {
   SolveState* st = S_[k];
-  Timed t(*S_[0]->p, CQM_K_GMRES, s);
+  Timed t(*S_[0]->p, CQM_K_OTHER, s);
   launch_gmres_init(ctx.eb.desc + st->first, st->p->Fsys, s);
 }
 
@@ -243,15 +273,17 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     return c;
   };
   {
-    Timed t(p0, CQM_K_GMRES, s);
+    Timed t(p0, CQM_K_OTHER, s);
     launch_cycle_start<R>(sd, n, outer_tol, inner_tol, s);
   }
   const int open = count(0);
   if (open == 0) return 0;
   for (int j = 0; j < m_; ++j) {
     if (!rows_.empty()) {
-      Timed t(p0, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
-      launch_dense_gemv_desc<R>(sd, ctx.eb.map, (int)rows_.size(), 0, j, s);
+      const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
+      Timed t(p0, c, s);
+      launch_dense_gemv_desc<R>(sd, ctx.eb.groups, ctx.eb.map, (int)rows_.size(), 0, j, grouped_,
+                                p0.timer.ctr(c), s);
     }
     for (SolveState* st : S_) {
       Problem& p = *st->p;
@@ -263,18 +295,19 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
                   st->at<int>(st->sysi) + 1, s);
     }
     {
-      Timed t(p0, CQM_K_GMRES, s);
-      launch_arnoldi<R>(sd, n, maxM_, j, s);
+      Timed t(p0, CQM_K_ARNOLDI, s);
+      launch_arnoldi<R>(sd, n, maxM_, j, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
     }
     if ((j + 1) % 6 == 0 && j + 1 < m_ && count(1) == 0) break;
   }
   {
-    Timed t(p0, CQM_K_GMRES, s);
+    Timed t(p0, CQM_K_OTHER, s);
     launch_cycle_finish<R>(sd, n, s);
   }
   if (!rows_.empty()) {
     Timed t(p0, CQM_K_GEMV64, s);
-    launch_dense_gemv_desc<double>(sd, ctx.eb.map, (int)rows_.size(), 1, 0, s);
+    launch_dense_gemv_desc<double>(sd, ctx.eb.groups, ctx.eb.map, (int)rows_.size(), 1, 0, grouped_,
+                                   p0.timer.ctr(CQM_K_GEMV64), s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -284,7 +317,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
                      st->at<int>(st->sysi), s);
   }
   {
-    Timed t(p0, CQM_K_GMRES, s);
+    Timed t(p0, CQM_K_OTHER, s);
     launch_residual_combine(sd, n, s);
   }
   ++cycles_run;
@@ -334,8 +367,7 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
     if (G.empty()) continue;
     Problem& p0 = *G[0]->p;
     p0.timer.on = p0.opt.profile != 0;
-    p0.timer.cls.clear();
-    p0.timer.used = 0;
+    p0.timer.reset(s);
     for (size_t k = 1; k < G.size(); ++k)
       if (G[k]->p != &p0) G[k]->p->timer.on = false;
     for (SolveState* st : G) pre_solve(*st, s, true);
@@ -348,7 +380,7 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
     for (size_t k = 0; k < G.size(); ++k) E.finish_diag((int)k, s);
     for (SolveState* st : G) post_solve(*st, s);
     const double el = ms_since(t1);
-    if (p0.timer.on) p0.timer.collect(G[0]->diag.kernel_ms, G[0]->diag.kernel_calls);
+    if (p0.timer.on) p0.timer.collect(G[0]->diag.kernel_ms, G[0]->diag.kernel_calls, G[0]->diag.kernel_work);
     for (SolveState* st : G) {
       st->diag.t_solve_ms = el;
       st->p->last = st->diag;

@@ -74,9 +74,19 @@ struct SysDesc {
   const cf64* ghat;       // M, right-hand side
   const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
   const cf64* V64;        // dense operator slice in FP64 (dense form) or null
+  double* part;           // split Arnoldi: per row slice 4 (m+1) + 2 partial sums
 };
+// Rows per workgroup (one per thread) of the split Arnoldi step.
+constexpr int kArnRows = 256;
 struct RowBlock {
-  int sys, row0;
+  int group, row0;
+};
+// Systems that share one stored operator slice (same mesh, N, T and
+// frequency): their products read each row of the slice once.
+constexpr int kMaxGroup = 8;
+struct GemvGroup {
+  int n;
+  int sys[kMaxGroup];
 };
 
 
@@ -86,6 +96,8 @@ struct EngineBufs {
   size_t desc_cap = 0;
   RowBlock* map = nullptr;
   size_t map_cap = 0;
+  GemvGroup* groups = nullptr;
+  size_t groups_cap = 0;
   int* status = nullptr;
   size_t status_cap = 0;
 };
@@ -104,6 +116,7 @@ struct MeshDev {
   double* verts = nullptr;    // nv*3
   int32_t* near_rowptr = nullptr;
   int32_t* near_col = nullptr;
+  int32_t* near_row = nullptr;    // row of each near pair
   int32_t* near_kind = nullptr;   // 0 identical, 1 edge, 2 vertex
   int32_t* near_vtx = nullptr;    // nnz*6 vertex ids ordered per kind
   double* near_static = nullptr;  // nnz
@@ -142,7 +155,7 @@ struct SolveState {
   Problem* p = nullptr;
   char* base = nullptr;
   size_t b = 0, ghat = 0, x = 0, r = 0, basis = 0, H = 0, cs = 0, sn = 0, g = 0, sysd = 0,
-         sysi = 0, scratch = 0, total = 0;
+         sysi = 0, part = 0, scratch = 0, total = 0;
   Incident inc;
   double* q_out = nullptr;
   cqm_diag diag{};
@@ -151,15 +164,20 @@ struct SolveState {
 };
 
 // Optional per-class kernel timing with HIP events recorded on the launch
-// stream (enabled by cqm_options.profile).
+// stream, and per-class algorithmic work counted by the kernels themselves
+// (one device atomic per workgroup), both enabled by cqm_options.profile.
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;
   std::vector<int> cls;  // class of each recorded pair
   size_t used = 0;       // events used (2 per launch)
+  unsigned long long* work_d = nullptr;  // CQM_K_CLASSES device counters
   void begin(int c, hipStream_t s);
   void end(hipStream_t s);
-  void collect(double* ms, int* calls);  // after the stream is synchronised
+  void reset(hipStream_t s);             // clear events and counters
+  unsigned long long* ctr(int c) const { return on && work_d ? work_d + c : nullptr; }
+  // after the stream is synchronised
+  void collect(double* ms, int* calls, double* work);
   void release();
 };
 
@@ -209,12 +227,13 @@ void launch_dense_scatter_near(const Problem& p, const cf64* vals, cf64* d64, cf
 // far field (k_far.hip)
 template <typename R>
 void launch_far_apply(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                      cplx<R>* partial, const int* active, hipStream_t s);
+                      cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s);
 template <typename R>
 void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* partial,
                             const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
                             const cf64* near_vals, const int* active, hipStream_t s);
-void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s);
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
+                           hipStream_t s);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product
 
 // dense products (k_dense.hip)
@@ -227,13 +246,16 @@ void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
 void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s);
 template <typename R>
 void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s);
-template <typename R> void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, hipStream_t s);
+template <typename R>
+void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, unsigned long long* ctr,
+                    hipStream_t s);
 template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s);
 // dense products over descriptors (k_dense.hip): which = 0 inner product
 // basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
 // residual product x -> r of open systems.  rowmap: (system, first row).
 template <typename R>
-void launch_dense_gemv_desc(const SysDesc* sd, const RowBlock* map, int nblocks, int which, int j,
+void launch_dense_gemv_desc(const SysDesc* sd, const GemvGroup* groups, const RowBlock* map,
+                            int nblocks, int which, int j, bool grouped, unsigned long long* ctr,
                             hipStream_t s);
 
 // ------------------------------------------------------------ host helpers
@@ -275,6 +297,9 @@ class Engine {
   std::vector<SolveState*> S_;
   std::vector<SysDesc> hd_;
   std::vector<RowBlock> rows_;
+  std::vector<GemvGroup> groups_;
+  bool grouped_ = false;  // some operator slice is shared by several systems
+  bool split_ = false;    // Arnoldi step split over row slices
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
 };

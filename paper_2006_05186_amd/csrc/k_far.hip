@@ -56,14 +56,16 @@ template <typename R, int FT>
 __global__ __launch_bounds__(kTgt) void k_far_apply(
     const typename Pt4<R>::T* __restrict__ pts, const int4* __restrict__ vid, int M,
     const R* __restrict__ ea, const R* __restrict__ pb, int nsys, const cplx<R>* __restrict__ x,
-    int64_t xs, cplx<R>* __restrict__ partial, int chunk, const int* __restrict__ active) {
+    int64_t xs, cplx<R>* __restrict__ partial, int chunk, const int* __restrict__ active,
+    unsigned long long* ctr) {
   using P4 = typename Pt4<R>::T;
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
+  int nact = nl;  // systems of the tile that asked for the product
   if (active) {
-    bool any = false;
-    for (int l = 0; l < nl; ++l) any |= active[(l0 + l) * kSysiStride] != 0;
-    if (!any) return;
+    nact = 0;
+    for (int l = 0; l < nl; ++l) nact += active[(l0 + l) * kSysiStride] != 0;
+    if (!nact) return;
   }
   const int i = blockIdx.x * kTgt + threadIdx.x;
   const int ic = i < M ? i : M - 1;
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
   __shared__ cplx<R> sx[kTs * FT];
   const int j0 = blockIdx.z * chunk;
   const int j1 = min(M, j0 + chunk);
+  int pairs_done = 0;  // non-near source triangles of this target (work count)
   for (int jt = j0; jt < j1; jt += kTs) {
     const int nt = min(kTs, j1 - jt);
     __syncthreads();
@@ -106,6 +109,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     __syncthreads();
     for (int jj = 0; jj < nt; ++jj) {
       if (share_vertex(tv, sv[jj])) continue;
+      ++pairs_done;
       R vre[FT], vim[FT];
 #pragma unroll
       for (int l = 0; l < FT; ++l) {
@@ -147,6 +151,14 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
         aim[l] += vre[l] * xv.im + vim[l] * xv.re;
       }
     }
+  }
+  if (ctr) {
+    // point-pair-frequency kernel values of the far pairs handled here, for
+    // the systems that asked for them (closed systems sharing the tile are
+    // evaluated too but are not useful work)
+    unsigned long long u = i < M ? (unsigned long long)pairs_done * kQ * kQ * nact : 0ull;
+    u = wave_sum(u);
+    if ((threadIdx.x & 63) == 0) atomicAdd(ctr, u);
   }
   if (i < M) {
 #pragma unroll
@@ -206,7 +218,8 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
                                                               const double* __restrict__ ea,
                                                               const double* __restrict__ pb,
                                                               int nsys, cf64* __restrict__ d64,
-                                                              cf32* __restrict__ d32) {
+                                                              cf32* __restrict__ d32,
+                                                              unsigned long long* ctr) {
   // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I
   const long long kk = blockIdx.x;
   long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
@@ -220,6 +233,12 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
   __shared__ cf64 tile[FT][kAt][kAt + 1];
   bool live = i < M && j < M && (I != J || i <= j);
   if (live) live = !share_vertex(vid[i], vid[j]);
+  if (ctr) {
+    // point-pair-frequency kernel values evaluated by this tile
+    unsigned long long u = live ? (unsigned long long)kQ * kQ * nl : 0ull;
+    u = wave_sum(u);
+    if ((threadIdx.x & 63) == 0) atomicAdd(ctr, u);
+  }
   double vre[FT], vim[FT];
 #pragma unroll
   for (int l = 0; l < FT; ++l) vre[l] = vim[l] = 0.0;
@@ -327,7 +346,7 @@ int far_splits(int M, int nsys, int FT, int* chunk_out = nullptr) {
 
 template <typename R, int FT>
 static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                         cplx<R>* partial, const int* active, hipStream_t s) {
+                         cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s) {
   const int M = (int)p.M;
   int chunk = 0;
   const int S = far_splits(M, nsys, FT, &chunk);
@@ -344,27 +363,27 @@ static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, i
     pb = p.dev.pb64 + l0;
   }
   hipLaunchKernelGGL((k_far_apply<R, FT>), grid, dim3(kTgt), 0, s, pts, p.dev.vid, M, ea, pb,
-                     nsys, x, xs, partial, chunk, active);
+                     nsys, x, xs, partial, chunk, active, ctr);
   CQM_HIP(hipGetLastError());
 }
 
 template <typename R>
 void launch_far_apply(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                      cplx<R>* partial, const int* active, hipStream_t s) {
+                      cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s) {
   const int FT = pick_ft<R>(nsys);
   if constexpr (sizeof(R) == 4) {
     switch (FT) {
-      case 17: far_apply_ft<R, 17>(p, l0, nsys, x, xs, partial, active, s); break;
-      case 16: far_apply_ft<R, 16>(p, l0, nsys, x, xs, partial, active, s); break;
-      case 13: far_apply_ft<R, 13>(p, l0, nsys, x, xs, partial, active, s); break;
-      case 11: far_apply_ft<R, 11>(p, l0, nsys, x, xs, partial, active, s); break;
-      default: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 17: far_apply_ft<R, 17>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      case 16: far_apply_ft<R, 16>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      case 13: far_apply_ft<R, 13>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      case 11: far_apply_ft<R, 11>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      default: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
     }
   } else {
     switch (FT) {
-      case 9: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, s); break;
-      case 8: far_apply_ft<R, 8>(p, l0, nsys, x, xs, partial, active, s); break;
-      default: far_apply_ft<R, 6>(p, l0, nsys, x, xs, partial, active, s); break;
+      case 9: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      case 8: far_apply_ft<R, 8>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+      default: far_apply_ft<R, 6>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
     }
   }
 }
@@ -389,16 +408,18 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
 }
 
 template <int FT>
-static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
+static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
+                              hipStream_t s) {
   const int M = (int)p.M;
   const int nt = (M + kAt - 1) / kAt;
   dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
   hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64, p.dev.vid,
-                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32);
+                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr);
   CQM_HIP(hipGetLastError());
 }
 
-void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s) {
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
+                           hipStream_t s) {
   // frequency tile with the fewest padding slots (11 | 33, 13 | 65, 9 | 9)
   const int opts[3] = {13, 11, 9};
   int FT = 13, waste = 1 << 30;
@@ -406,15 +427,15 @@ void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, hipStream_t s
     const int w = ((p.Fsys + f - 1) / f) * f - p.Fsys;
     if (w < waste) waste = w, FT = f;
   }
-  if (FT == 13) dense_assemble_ft<13>(p, d64, d32, s);
-  else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, s);
-  else dense_assemble_ft<9>(p, d64, d32, s);
+  if (FT == 13) dense_assemble_ft<13>(p, d64, d32, ctr, s);
+  else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, ctr, s);
+  else dense_assemble_ft<9>(p, d64, d32, ctr, s);
 }
 
 template void launch_far_apply<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,
-                                      const int*, hipStream_t);
+                                      const int*, unsigned long long*, hipStream_t);
 template void launch_far_apply<double>(const Problem&, int, int, const cf64*, int64_t, cf64*,
-                                       const int*, hipStream_t);
+                                       const int*, unsigned long long*, hipStream_t);
 template void launch_far_reduce_near<float>(const Problem&, int, int, const cf32*, const cf32*,
                                             int64_t, cf32*, int64_t, const cf64*, const int*,
                                             hipStream_t);

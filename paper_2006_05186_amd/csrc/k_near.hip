@@ -127,54 +127,49 @@ void launch_near_static(const Problem& p, hipStream_t s) {
   CQM_HIP(hipGetLastError());
 }
 
-// vals[l][k] = S_k + D_k(s_l) for near pair k of row i, system l.
-__global__ void k_near_values(const double4* __restrict__ pts, const int32_t* __restrict__ rowptr,
+// vals[l][k] = S_k + D_k(s_l) for near pair k (row kr[k]), system l: one
+// thread per pair and frequency.
+__global__ void k_near_values(const double4* __restrict__ pts, const int32_t* __restrict__ krow,
                               const int32_t* __restrict__ col, const double* __restrict__ stat,
-                              const cf64* __restrict__ sfreq, int M, int64_t nnz,
-                              cf64* __restrict__ vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                              const cf64* __restrict__ sfreq, int64_t nnz, cf64* __restrict__ vals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y;
-  if (i >= M) return;
+  if (k >= nnz) return;
   const double sr = sfreq[l].re, si = sfreq[l].im;
-  double4 tp[kQ];
-#pragma unroll
-  for (int a = 0; a < kQ; ++a) tp[a] = pts[i * kQ + a];
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const int j = col[k];
-    double re = 0.0, im = 0.0;
+  const int i = krow[k], j = col[k];
+  double re = 0.0, im = 0.0;
+  for (int a = 0; a < kQ; ++a) {
+    const double4 tp = pts[i * kQ + a];
     for (int b = 0; b < kQ; ++b) {
       const double4 sp = pts[j * kQ + b];
-#pragma unroll
-      for (int a = 0; a < kQ; ++a) {
-        const double dx = tp[a].x - sp.x, dy = tp[a].y - sp.y, dz = tp[a].z - sp.z;
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        const double ww = tp[a].w * sp.w;
-        double fr, fi;
-        if (r > 0.0) {
-          // expm1(z), z = -s r = x + i y, without cancellation
-          const double x = -sr * r, y = -si * r;
-          double sn, cs;
-          sincos(y, &sn, &cs);
-          const double sh = sin(0.5 * y);
-          fr = (expm1(x) * cs - 2.0 * sh * sh) / r;
-          fi = (exp(x) * sn) / r;
-        } else {
-          fr = -sr;
-          fi = -si;
-        }
-        re += ww * fr;
-        im += ww * fi;
+      const double dx = tp.x - sp.x, dy = tp.y - sp.y, dz = tp.z - sp.z;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double ww = tp.w * sp.w;
+      double fr, fi;
+      if (r > 0.0) {
+        // expm1(z), z = -s r = x + i y, without cancellation
+        const double x = -sr * r, y = -si * r;
+        double sn, cs;
+        sincos(y, &sn, &cs);
+        const double sh = sin(0.5 * y);
+        fr = (expm1(x) * cs - 2.0 * sh * sh) / r;
+        fi = (exp(x) * sn) / r;
+      } else {
+        fr = -sr;
+        fi = -si;
       }
+      re += ww * fr;
+      im += ww * fi;
     }
-    vals[(int64_t)l * nnz + k] = cf64{stat[k] + kInv4Pi * re, kInv4Pi * im};
   }
+  vals[(int64_t)l * nnz + k] = cf64{stat[k] + kInv4Pi * re, kInv4Pi * im};
 }
 
 void launch_near_values(const Problem& p, cf64* vals, hipStream_t s) {
   const int64_t nnz = (int64_t)p.col.size();
-  dim3 grid((p.M + 127) / 128, p.Fsys);
-  hipLaunchKernelGGL(k_near_values, grid, dim3(128), 0, s, p.dev.pts64, p.dev.near_rowptr,
-                     p.dev.near_col, p.dev.near_static, p.dev.s, (int)p.M, nnz, vals);
+  dim3 grid((unsigned)((nnz + 127) / 128), p.Fsys);
+  hipLaunchKernelGGL(k_near_values, grid, dim3(128), 0, s, p.dev.pts64, p.dev.near_row,
+                     p.dev.near_col, p.dev.near_static, p.dev.s, nnz, vals);
   CQM_HIP(hipGetLastError());
 }
 

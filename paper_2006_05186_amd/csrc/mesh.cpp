@@ -159,6 +159,10 @@ void upload_problem(Problem& p) {
   p.dev.verts = upload(p.verts);
   p.dev.near_rowptr = upload(p.rowptr);
   p.dev.near_col = upload(p.col);
+  std::vector<int32_t> krow(p.col.size());
+  for (int64_t i = 0; i < M; ++i)
+    for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k) krow[k] = (int32_t)i;
+  p.dev.near_row = upload(krow);
   p.dev.near_kind = upload(p.kind);
   p.dev.near_vtx = upload(p.nvtx);
   CQM_HIP(hipMalloc(&p.dev.near_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
@@ -232,6 +236,7 @@ size_t state_layout(const Problem& p, SolveState& st) {
   st.g = take(sizeof(cf64) * Fs * (m + 1));
   st.sysd = take(sizeof(double) * 8 * Fs);
   st.sysi = take(sizeof(int) * kSysiStride * Fs);
+  st.part = take(sizeof(double) * Fs * ((M + kArnRows - 1) / kArnRows) * (4 * (m + 1) + 2));
   st.scratch = take(4096);
   st.total = off;
   return off;

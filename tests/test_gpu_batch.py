@@ -27,14 +27,19 @@ def ctx():
     C.cqm_ctx_destroy(c)
 
 
-def test_uneven_batch_matches_alone_and_oracle(ctx):
+@pytest.mark.parametrize("layout", [C.CQM_ARNOLDI_AUTO, C.CQM_ARNOLDI_GROUP])
+def test_uneven_batch_matches_alone_and_oracle(ctx, layout):
+    """Systems of different lengths share the launches (split Arnoldi with
+    different slice counts per system under AUTO here, one workgroup per
+    system under GROUP)."""
     mix = W.problem_mix(6, seed=7, levels=(1, 2), steps=(8, 16), T=2.0)
     say("batch of " + ", ".join(f"{w.name}(M={w.M},N={w.N})" for w in mix))
     probs, alone = [], []
     for w in mix:
         V, T = w.mesh()
         for store in (probs, alone):
-            p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
+            p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                        arnoldi_layout=layout)
             p.set_plane_wave(w.wave.direction, w.wave.sigma, w.wave.t0)
             store.append(p)
     res, rc = solve_batch(probs)

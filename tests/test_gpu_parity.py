@@ -111,6 +111,54 @@ def test_solve_C1_matches_oracle(ctx, c1, form, mode):
     p.close()
 
 
+def test_kernel_work_counters(ctx, c1):
+    """The per-class work the kernels count for the roofline matches what the
+    solve did: every far pair of the symmetric assembly once per frequency,
+    one full operator slice per Arnoldi step, one far field per product."""
+    wl, V, T, r, _ = c1
+    M = len(T)
+    nnz = len(r["pairs"])
+    k = {n: i for i, n in enumerate(C.KERNEL_CLASSES)}
+    say("kernel work counters M=320 dense/matrix-free mixed")
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE, profile=1)
+    p.set_plane_wave()
+    _, rc, d = p.solve()
+    assert rc == C.CQM_OK
+    w = list(d.kernel_work)
+    assert w[k["assemble"]] == (M * M - nnz) // 2 * 36 * d.n_systems
+    assert w[k["gemv32"]] == d.total_iters * (M * M + 2 * M) * 8
+    assert w[k["gemv64"]] % ((M * M + 2 * M) * 16) == 0 and w[k["gemv64"]] > 0
+    assert w[k["arnoldi"]] >= sum(7 * M * 8 for _ in range(d.total_iters))
+    assert d.kernel_calls[k["arnoldi"]] > 0 and d.kernel_ms[k["arnoldi"]] > 0
+    p.close()
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE,
+                profile=1)
+    p.set_plane_wave()
+    _, rc, d = p.solve()
+    assert rc == C.CQM_OK
+    w = list(d.kernel_work)
+    per = (M * M - nnz) * 36
+    assert w[k["far32"]] == d.total_iters * per
+    assert w[k["far64"]] % per == 0 and w[k["far64"]] >= d.n_systems * per
+    p.close()
+
+
+@pytest.mark.parametrize("layout", [C.CQM_ARNOLDI_GROUP, C.CQM_ARNOLDI_SPLIT])
+@pytest.mark.parametrize("mode", [C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN])
+def test_arnoldi_layouts_match_oracle(ctx, c1, layout, mode):
+    """Both Arnoldi layouts (one workgroup per system; split over row slices)
+    reach the oracle's density, in both inner precisions."""
+    wl, V, T, r, area = c1
+    say(f"arnoldi layout={layout} mode={mode} M=320")
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=C.CQM_FORM_DENSE, arnoldi_layout=layout)
+    p.set_plane_wave()
+    q, rc, diag = p.solve()
+    err = O.rel_error(q.cpu().numpy(), r["q"], area)
+    say(f"  rc={rc} err={err:.3e} iters={diag.total_iters} cycles={diag.cycles}")
+    assert rc == C.CQM_OK and diag.max_rel_residual <= 1e-13 and err < 1e-8
+    p.close()
+
+
 def test_solve_C2_against_stored_oracle(ctx):
     wl = W.C2
     path = os.path.join(GOLDEN, f"{wl.name}.npz")
