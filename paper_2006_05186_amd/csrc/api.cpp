@@ -141,6 +141,10 @@ int cqm_ctx_create(int device, cqm_ctx_t* out) {
     CQM_HIP(hipSetDevice(device));
     auto* c = new cqm_ctx_s();
     c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+      c->cus = cus;
     *out = c;
     return CQM_OK;
   });
@@ -150,7 +154,9 @@ int cqm_ctx_destroy(cqm_ctx_t ctx) {
   if (!ctx) return CQM_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->eb.desc) (void)hipFree(ctx->eb.desc);
-  if (ctx->eb.map) (void)hipFree(ctx->eb.map);
+  if (ctx->eb.open_cycle) (void)hipFree(ctx->eb.open_cycle);
+  if (ctx->eb.open_step) (void)hipFree(ctx->eb.open_step);
+  if (ctx->eb.staging) (void)hipHostFree(ctx->eb.staging);
   if (ctx->eb.groups) (void)hipFree(ctx->eb.groups);
   if (ctx->eb.status) (void)hipFree(ctx->eb.status);
   delete ctx;

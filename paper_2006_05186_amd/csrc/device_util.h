@@ -18,6 +18,28 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum of NV per-lane values over the 64 lanes of a wave, scattered: on
+// return lane t holds, in a[0], the total of entry t >> (6 - log2 NV).
+// Each halving step exchanges half of the remaining entries with the
+// partner lane (NV - 1 shuffles in all instead of 6 NV).
+template <int NV, int OFF, typename T>
+__device__ __forceinline__ void wave_reduce_scatter(T* a, int lane) {
+  if constexpr (NV > 1) {
+    constexpr int H = NV / 2;
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const T send = up ? a[u] : a[u + H];
+      const T keep = up ? a[u + H] : a[u];
+      a[u] = keep + __shfl_xor(send, OFF, 64);
+    }
+    wave_reduce_scatter<H, OFF / 2, T>(a, lane);
+  } else {
+#pragma unroll
+    for (int o = OFF; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+  }
+}
+
 // Sum over a workgroup of blockDim.x threads (multiple of 64, <= 1024).
 // `red` is caller-provided shared scratch of >= 16 T; result broadcast to all.
 template <typename T> __device__ __forceinline__ T block_sum(T v, T* red) {

@@ -49,8 +49,10 @@ void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R
     } else {
       V = wsp<cf64>(p, p.lay.dense64);
     }
+    require(p.own.sym != 0, CQM_EINVAL, "no partial-sum buffer for the stored operator");
     Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
-    launch_dense_gemv<R>(V + (int64_t)l0 * M * M, M, nsys, x, xs, y, ys, active, s);
+    launch_dense_gemv<R>(V + (int64_t)l0 * sym_slice(M), M, nsys, x, xs, y, ys, active,
+                         p.own.at<cplx<R>>(p.own.sym), s);
   } else {
     cplx<R>* partial = wsp<cplx<R>>(p, p.lay.partial);
     {
@@ -141,7 +143,7 @@ void post_solve(SolveState& st, hipStream_t s) {
   dg.far_units = p.far_units;
   if (mode_is_h2(p.opt.mode)) h2_stats(p, &dg);
   else if (p.opt.form == CQM_FORM_DENSE)
-    dg.operator_bytes = (int64_t)p.Fsys * p.M * p.M * (p.lay.dense32 ? 24 : 16);
+    dg.operator_bytes = (int64_t)p.Fsys * sym_slice((int)p.M) * (p.lay.dense32 ? 24 : 16);
   else
     dg.operator_bytes = (int64_t)p.Fsys * (int64_t)p.col.size() * 16;
 }
@@ -160,7 +162,7 @@ constexpr int kSplitBelow = 256;
 void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   S_ = S;
   hd_.clear();
-  rows_.clear();
+  lite_.clear();
   groups_.clear();
   std::map<const void*, int> slot;
   maxM_ = 0;
@@ -194,8 +196,9 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
       d.ghat = st->at<cf64>(st->ghat) + (size_t)l * M;
       d.part = st->at<double>(st->part) + (size_t)l * ((M + kArnRows - 1) / kArnRows) * (4 * (m_ + 1) + 2);
       if (dense_form(p)) {
-        d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * M * M;
-        d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * M * M) : nullptr;
+        d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * sym_slice(M);
+        d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * sym_slice(M)) : nullptr;
+        d.symp = st->base + st->sym + sizeof(cf64) * (size_t)l * sym_partials(M);
         // join the group of systems on the same operator slice, if any
         auto it = slot.find(d.V64);
         if (it == slot.end() || groups_[it->second].n == kMaxGroup) {
@@ -203,33 +206,46 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
           g.n = 0;
           slot[d.V64] = (int)groups_.size();
           groups_.push_back(g);
-          for (int r0 = 0; r0 < M; r0 += 4) rows_.push_back(RowBlock{(int)groups_.size() - 1, r0});
+          GroupLite gl{};
+          gl.V32 = d.V32;
+          gl.V64 = d.V64;
+          gl.M = M;
+          lite_.push_back(gl);
           it = slot.find(d.V64);
         }
         GemvGroup& g = groups_[it->second];
+        GroupLite& gl = lite_[it->second];
+        gl.basis[g.n] = d.basis;
+        gl.x[g.n] = d.x;
+        gl.symp[g.n] = d.symp;
+        gl.sysi[g.n] = d.sysi;
         g.sys[g.n++] = (int)hd_.size();
+        gl.n = g.n;
       }
       hd_.push_back(d);
     }
   }
-  grouped_ = false;
-  for (const GemvGroup& g : groups_) grouped_ |= g.n > 1;
   const int n = (int)hd_.size();
   // split the Arnoldi step over row slices when one workgroup per system
   // would leave most compute units idle
   const int lay = S_[0]->p->opt.arnoldi_layout;
   split_ = lay == CQM_ARNOLDI_SPLIT || (lay == CQM_ARNOLDI_AUTO && n < kSplitBelow);
   ensure(ctx.eb.desc, ctx.eb.desc_cap, hd_.size());
-  ensure(ctx.eb.map, ctx.eb.map_cap, std::max<size_t>(1, rows_.size()));
-  ensure(ctx.eb.groups, ctx.eb.groups_cap, std::max<size_t>(1, groups_.size()));
+  ensure(ctx.eb.open_cycle, ctx.eb.cycle_cap, std::max<size_t>(1, lite_.size()));
+  ensure(ctx.eb.open_step, ctx.eb.step_cap, std::max<size_t>(1, lite_.size()));
+  if (ctx.eb.staging_cap < 2 * lite_.size()) {
+    if (ctx.eb.staging) {
+      CQM_HIP(hipStreamSynchronize(s));
+      CQM_HIP(hipHostFree(ctx.eb.staging));
+    }
+    ctx.eb.staging = nullptr;
+    ctx.eb.staging_cap = 0;
+    const size_t c = std::max<size_t>(2 * lite_.size(), 256);
+    CQM_HIP(hipHostMalloc((void**)&ctx.eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
+    ctx.eb.staging_cap = c;
+  }
   ensure(ctx.eb.status, ctx.eb.status_cap, (size_t)kSysiStride * n);
   CQM_HIP(hipMemcpyAsync(ctx.eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
-  if (!rows_.empty()) {
-    CQM_HIP(hipMemcpyAsync(ctx.eb.map, rows_.data(), sizeof(RowBlock) * rows_.size(),
-                           hipMemcpyHostToDevice, s));
-    CQM_HIP(hipMemcpyAsync(ctx.eb.groups, groups_.data(), sizeof(GemvGroup) * groups_.size(),
-                           hipMemcpyHostToDevice, s));
-  }
   flags_.assign((size_t)kSysiStride * n, 0);
 }
 
@@ -245,6 +261,43 @@ void Engine::status(hipStream_t s) {
   launch_gather_status(ctx.eb.desc, n, ctx.eb.status, s);
   CQM_HIP(hipMemcpyAsync(flags_.data(), ctx.eb.status, sizeof(int) * flags_.size(), hipMemcpyDeviceToHost, s));
   CQM_HIP(hipStreamSynchronize(s));
+}
+
+// Groups with a member whose flag `which` (0 system open, 1 cycle open) is
+// set in the host copy of the flags, sorted by mesh size, uploaded through
+// the pinned staging area.  The stream was synchronised by the status read,
+// so the previous upload from the same staging area is complete.
+void Engine::upload_open(int which, GroupLite* dst, size_t stage, std::vector<GClass>& cls,
+                         hipStream_t s) {
+  cls.clear();
+  if (lite_.empty()) return;
+  std::vector<int> open;
+  for (size_t gi = 0; gi < groups_.size(); ++gi) {
+    bool any = false;
+    for (int q = 0; q < groups_[gi].n; ++q)
+      any |= flags_[(size_t)kSysiStride * groups_[gi].sys[q] + which] != 0;
+    if (any) open.push_back((int)gi);
+  }
+  std::stable_sort(open.begin(), open.end(),
+                   [&](int a, int b) { return lite_[a].M < lite_[b].M; });
+  GroupLite* st = ctx.eb.staging + stage;
+  for (size_t k = 0; k < open.size(); ++k) {
+    const GroupLite& g = lite_[open[k]];
+    st[k] = g;
+    if (cls.empty() || cls.back().M != g.M) cls.push_back(GClass{g.M, (int)k, 0, false});
+    cls.back().count += 1;
+    cls.back().grouped |= g.n > 1;
+  }
+  if (!open.empty())
+    CQM_HIP(hipMemcpyAsync(dst, st, sizeof(GroupLite) * open.size(), hipMemcpyHostToDevice, s));
+}
+
+template <typename R>
+void Engine::dense_product(const GroupLite* list, const std::vector<GClass>& cls, int which, int j,
+                           unsigned long long* ctr, hipStream_t s) {
+  for (const GClass& c : cls)
+    launch_dense_gemv_groups<R>(list + c.off, c.count, c.M, c.grouped, which, j, ctr, s);
+  if (!cls.empty()) launch_dense_reduce_desc<R>(ctx.eb.desc, (int)hd_.size(), maxM_, which, j, s);
 }
 
 bool Engine::state_done(int k) const {
@@ -278,12 +331,16 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   }
   const int open = count(0);
   if (open == 0) return 0;
+  // systems open now are the ones whose cycle runs (and whose residual is
+  // formed at its end)
+  upload_open(0, ctx.eb.open_cycle, 0, cyc_cls_, s);
+  const GroupLite* step_list = ctx.eb.open_cycle;
+  step_cls_ = cyc_cls_;
   for (int j = 0; j < m_; ++j) {
-    if (!rows_.empty()) {
+    if (!lite_.empty()) {
       const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
       Timed t(p0, c, s);
-      launch_dense_gemv_desc<R>(sd, ctx.eb.groups, ctx.eb.map, (int)rows_.size(), 0, j, grouped_,
-                                p0.timer.ctr(c), s);
+      dense_product<R>(step_list, step_cls_, 0, j, p0.timer.ctr(c), s);
     }
     for (SolveState* st : S_) {
       Problem& p = *st->p;
@@ -298,16 +355,21 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
       Timed t(p0, CQM_K_ARNOLDI, s);
       launch_arnoldi<R>(sd, n, maxM_, j, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
     }
-    if ((j + 1) % 6 == 0 && j + 1 < m_ && count(1) == 0) break;
+    if ((j + 1) % 6 == 0 && j + 1 < m_) {
+      if (count(1) == 0) break;
+      // drop the groups whose cycles closed
+      upload_open(1, ctx.eb.open_step, lite_.size(), step_cls_, s);
+      step_list = ctx.eb.open_step;
+    }
   }
   {
     Timed t(p0, CQM_K_OTHER, s);
     launch_cycle_finish<R>(sd, n, s);
   }
-  if (!rows_.empty()) {
+  if (!lite_.empty()) {
+    // residuals of the systems that ran this cycle: the list from its start
     Timed t(p0, CQM_K_GEMV64, s);
-    launch_dense_gemv_desc<double>(sd, ctx.eb.groups, ctx.eb.map, (int)rows_.size(), 1, 0, grouped_,
-                                   p0.timer.ctr(CQM_K_GEMV64), s);
+    dense_product<double>(ctx.eb.open_cycle, cyc_cls_, 1, 0, p0.timer.ctr(CQM_K_GEMV64), s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -323,6 +385,10 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   ++cycles_run;
   return open;
 }
+template void Engine::dense_product<float>(const GroupLite*, const std::vector<GClass>&, int, int,
+                                           unsigned long long*, hipStream_t);
+template void Engine::dense_product<double>(const GroupLite*, const std::vector<GClass>&, int, int,
+                                            unsigned long long*, hipStream_t);
 template int Engine::cycle_t<float>(hipStream_t);
 template int Engine::cycle_t<double>(hipStream_t);
 

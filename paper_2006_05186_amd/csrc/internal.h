@@ -75,12 +75,28 @@ struct SysDesc {
   const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
   const cf64* V64;        // dense operator slice in FP64 (dense form) or null
   double* part;           // split Arnoldi: per row slice 4 (m+1) + 2 partial sums
+  void* symp;             // stored form: tile partials of the product (nt x nt kSymB)
 };
 // Rows per workgroup (one per thread) of the split Arnoldi step.
 constexpr int kArnRows = 256;
-struct RowBlock {
-  int group, row0;
-};
+
+// Stored operator slices keep the upper triangle of kSymB x kSymB tiles of
+// the complex symmetric V(s): tile (I, J), I <= J, at J (J + 1) / 2 + I,
+// row-major inside; the last block row/column is padded to kSymB.
+constexpr int kSymB = 64;
+__host__ __device__ inline int sym_blocks(int M) { return (M + kSymB - 1) / kSymB; }
+__host__ __device__ inline int sym_tiles(int M) { return sym_blocks(M) * (sym_blocks(M) + 1) / 2; }
+__host__ __device__ inline int64_t sym_slice(int M) { return (int64_t)sym_tiles(M) * kSymB * kSymB; }
+// entry (i, j) lives in the stored triangle iff block(i) <= block(j)
+__host__ __device__ inline bool sym_stored(int i, int j) { return i / kSymB <= j / kSymB; }
+__host__ __device__ inline int64_t sym_index(int i, int j) {
+  const int I = i / kSymB, J = j / kSymB;
+  return ((int64_t)(J * (J + 1) / 2 + I) * kSymB + i % kSymB) * kSymB + j % kSymB;
+}
+// partial-sum buffer of one product: nt x (nt kSymB) elements
+__host__ __device__ inline int64_t sym_partials(int M) {
+  return (int64_t)sym_blocks(M) * sym_blocks(M) * kSymB;
+}
 // Systems that share one stored operator slice (same mesh, N, T and
 // frequency): their products read each row of the slice once.
 constexpr int kMaxGroup = 8;
@@ -88,14 +104,29 @@ struct GemvGroup {
   int n;
   int sys[kMaxGroup];
 };
+// A group of systems sharing one stored operator slice, as read by the
+// product kernel: everything a workgroup needs hangs off this one record.
+struct GroupLite {
+  const void* V32;  // FP32 slice (mixed form) or null
+  const void* V64;  // FP64 slice
+  int M, n, pad0, pad1;
+  void* basis[kMaxGroup];  // members' Krylov bases (inner precision)
+  cf64* x[kMaxGroup];      // members' FP64 iterates
+  void* symp[kMaxGroup];   // members' partial-sum buffers
+  int* sysi[kMaxGroup];    // members' status flags
+};
 
 
 // Device tables of the batched GMRES engine (library-owned, grow-only).
 struct EngineBufs {
   SysDesc* desc = nullptr;
   size_t desc_cap = 0;
-  RowBlock* map = nullptr;
-  size_t map_cap = 0;
+  GroupLite* open_cycle = nullptr;  // groups open at the cycle start
+  size_t cycle_cap = 0;
+  GroupLite* open_step = nullptr;   // groups with an open cycle
+  size_t step_cap = 0;
+  GroupLite* staging = nullptr;     // pinned host copies of the two lists
+  size_t staging_cap = 0;
   GemvGroup* groups = nullptr;
   size_t groups_cap = 0;
   int* status = nullptr;
@@ -104,6 +135,7 @@ struct EngineBufs {
 
 struct Ctx {
   int device = 0;
+  int cus = 256;  // compute units of the device
   EngineBufs eb;
 };
 
@@ -155,7 +187,7 @@ struct SolveState {
   Problem* p = nullptr;
   char* base = nullptr;
   size_t b = 0, ghat = 0, x = 0, r = 0, basis = 0, H = 0, cs = 0, sn = 0, g = 0, sysd = 0,
-         sysi = 0, part = 0, scratch = 0, total = 0;
+         sysi = 0, part = 0, sym = 0, scratch = 0, total = 0;
   Incident inc;
   double* q_out = nullptr;
   cqm_diag diag{};
@@ -239,7 +271,7 @@ int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the 
 // dense products (k_dense.hip)
 template <typename R>
 void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int64_t xs,
-                       cplx<R>* y, int64_t ys, const int* active, hipStream_t s);
+                       cplx<R>* y, int64_t ys, const int* active, cplx<R>* part, hipStream_t s);
 
 void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s);
 void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
@@ -254,9 +286,11 @@ template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStre
 // basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
 // residual product x -> r of open systems.  rowmap: (system, first row).
 template <typename R>
-void launch_dense_gemv_desc(const SysDesc* sd, const GemvGroup* groups, const RowBlock* map,
-                            int nblocks, int which, int j, bool grouped, unsigned long long* ctr,
-                            hipStream_t s);
+void launch_dense_gemv_groups(const GroupLite* gl, int ngroups, int M, bool grouped, int which,
+                              int j, unsigned long long* ctr, hipStream_t s);
+template <typename R>
+void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
+                              hipStream_t s);
 
 // ------------------------------------------------------------ host helpers
 void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w);
@@ -296,9 +330,20 @@ class Engine {
   Ctx& ctx;
   std::vector<SolveState*> S_;
   std::vector<SysDesc> hd_;
-  std::vector<RowBlock> rows_;
+  std::vector<GroupLite> lite_;   // one record per stored-operator group
+  struct GClass {                 // open groups of one mesh size in a device list
+    int M, off, count;
+    bool grouped;
+  };
+  std::vector<GClass> cyc_cls_, step_cls_;
+  // groups with a member whose flag `which` is set (host flags), by mesh
+  // size, uploaded to dst from the pinned staging area at `stage`
+  void upload_open(int which, GroupLite* dst, size_t stage, std::vector<GClass>& cls,
+                   hipStream_t s);
+  template <typename R>
+  void dense_product(const GroupLite* list, const std::vector<GClass>& cls, int which, int j,
+                     unsigned long long* ctr, hipStream_t s);
   std::vector<GemvGroup> groups_;
-  bool grouped_ = false;  // some operator slice is shared by several systems
   bool split_ = false;    // Arnoldi step split over row slices
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;

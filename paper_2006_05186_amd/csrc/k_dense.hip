@@ -1,239 +1,270 @@
-// Stored dense operator: y_l = V_l x_l for every active frequency system,
-// V_l an M x M row-major complex matrix in HBM.  Bandwidth bound: one wave per
-// row, four independent loads in flight per lane, x_l served from cache.
+// Stored dense operator.  The Galerkin single-layer matrix V(s) is complex
+// symmetric (the kernel depends on |x - y| only and trial and test spaces
+// coincide, Section 2), so only its upper triangle of kSymB x kSymB tiles is
+// kept: tile (I, J), I <= J, at index J (J + 1) / 2 + I, row-major inside, so
+// the tiles of block column J are contiguous.
+//
+// y = V x tile by tile: one workgroup reads tile (I, J) once and forms
+//   rows of block I:  V_IJ x_J        -> P[J][rows of I]
+//   rows of block J:  V_IJ^T x_I      -> P[I][rows of J]   (I < J)
+// so every slot of the partial buffer P (nt slots of nt kSymB rows) is
+// written exactly once, and a second kernel sums y_i = sum_Y P[Y][i] in a
+// fixed order: no atomics, deterministic, half the operator bytes of a full
+// row-major product.  Entries outside [0, M)^2 (ragged last block) are masked,
+// so tile padding is never read as data.
+#include <algorithm>
+
 #include "device_util.h"
 
 namespace cqm {
 
+namespace {
+constexpr int kB = kSymB;
+constexpr int kRowsPerWave = kB / 4;  // 4 waves per tile, 16 rows each
+
+// The tile's values held by this thread: 16 rows per wave, one column per
+// lane (each row read by a wave is 64 contiguous entries).
 template <typename R>
-__global__ __launch_bounds__(256) void k_dense_gemv(const cplx<R>* __restrict__ V, int M,
-                                                    const cplx<R>* __restrict__ x, int64_t xs,
-                                                    cplx<R>* __restrict__ y, int64_t ys,
-                                                    const int* __restrict__ active) {
+__device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ Vt, cplx<R>* a) {
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) a[q] = Vt[(w * kRowsPerWave + q) * kB + c];
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> load_x(const cplx<R>* __restrict__ x, int g, int M) {
+  cplx<R> v;
+  v.re = R(0);
+  v.im = R(0);
+  if (g < M) v = x[g];
+  return v;
+}
+
+// Row sums of a masked tile with x_J (value xj of this lane's column): the
+// wave's 16 rows reduced over its 64 lanes and stored to prow[0..15].
+template <typename R>
+__device__ __forceinline__ void tile_row_sums(const cplx<R>* a, cplx<R> xj, R* prow, int c) {
+  if constexpr (sizeof(R) == 4) {
+    R v[2 * kRowsPerWave];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      v[q] = a[q].re * xj.re - a[q].im * xj.im;
+      v[kRowsPerWave + q] = a[q].re * xj.im + a[q].im * xj.re;
+    }
+    wave_reduce_scatter<2 * kRowsPerWave, 32>(v, c);  // lane t: entry t >> 1
+    if ((c & 1) == 0) {
+      const int e = c >> 1;
+      prow[2 * (e % kRowsPerWave) + e / kRowsPerWave] = v[0];
+    }
+  } else {
+    // FP64: real and imaginary parts in two rounds (register budget)
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      R v[kRowsPerWave];
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q)
+        v[q] = part == 0 ? a[q].re * xj.re - a[q].im * xj.im : a[q].re * xj.im + a[q].im * xj.re;
+      wave_reduce_scatter<kRowsPerWave, 32>(v, c);  // lane t: entry t >> 2
+      if ((c & 3) == 0) prow[2 * (c >> 2) + part] = v[0];
+    }
+  }
+}
+
+__device__ __forceinline__ void decode_tile(int t, int& I, int& J) {
+  int jj = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+  while (jj * (jj + 1) / 2 > t) --jj;
+  while ((jj + 1) * (jj + 2) / 2 <= t) ++jj;
+  J = jj;
+  I = t - jj * (jj + 1) / 2;
+}
+
+// Both contributions of one loaded tile (I, J) for one input vector x:
+// row sums into P[J][rows of I], column sums (off-diagonal tiles) into
+// P[I][rows of J].  x_I and x_J are read one entry per lane; the rows' x_I
+// values are broadcast from their lanes.
+template <typename R>
+__device__ __forceinline__ void tile_products(const cplx<R>* a, int M, int I, int J,
+                                              const cplx<R>* __restrict__ x, cplx<R>* P, int ntB,
+                                              cplx<R> (*colred)[kB]) {
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const cplx<R> xj = load_x<R>(x, J * kB + c, M);
+  tile_row_sums<R>(a, xj, reinterpret_cast<R*>(P + (int64_t)J * ntB + I * kB + w * kRowsPerWave),
+                   c);
+  if (I != J) {
+    const cplx<R> xi = load_x<R>(x, I * kB + c, M);
+    R cre = R(0), cim = R(0);
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      const int r = w * kRowsPerWave + q;
+      const R xr = __shfl(xi.re, r, 64), xm = __shfl(xi.im, r, 64);
+      cre += a[q].re * xr - a[q].im * xm;
+      cim += a[q].re * xm + a[q].im * xr;
+    }
+    colred[w][c].re = cre;
+    colred[w][c].im = cim;
+    __syncthreads();
+    if (w == 0) {
+      cplx<R> o;
+      o.re = (colred[0][c].re + colred[1][c].re) + (colred[2][c].re + colred[3][c].re);
+      o.im = (colred[0][c].im + colred[1][c].im) + (colred[2][c].im + colred[3][c].im);
+      P[(int64_t)I * ntB + J * kB + c] = o;
+    }
+    __syncthreads();
+  }
+}
+
+// Load tile t of a slice and mask the entries outside [0, M)^2.
+template <typename R>
+__device__ __forceinline__ void masked_tile(const cplx<R>* __restrict__ Vs, int t, int M, int I,
+                                            int J, cplx<R>* a) {
+  load_tile<R>(Vs + (int64_t)t * kB * kB, a);
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool col_in = J * kB + c < M;
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const bool in = (I * kB + w * kRowsPerWave + q < M) && col_in;
+    a[q].re = in ? a[q].re : R(0);
+    a[q].im = in ? a[q].im : R(0);
+  }
+}
+
+// y_i = sum_{Y < nt} P[Y][i], fixed order.
+template <typename R>
+__device__ __forceinline__ cplx<R> sum_partials(const cplx<R>* __restrict__ P, int M, int i) {
+  const int nt = (M + kB - 1) / kB, ntB = nt * kB;
+  R re = R(0), im = R(0);
+  for (int Y = 0; Y < nt; ++Y) {
+    const cplx<R> v = P[(int64_t)Y * ntB + i];
+    re += v.re;
+    im += v.im;
+  }
+  cplx<R> o;
+  o.re = re;
+  o.im = im;
+  return o;
+}
+}  // namespace
+
+// ------------------------------------------------------------ plain form
+// y_l = V_l x_l for frequencies l < nsys (slices V + l * sym_slice(M)).
+template <typename R>
+__global__ __launch_bounds__(256) void k_symv(const cplx<R>* __restrict__ V, int M,
+                                              const cplx<R>* __restrict__ x, int64_t xs,
+                                              cplx<R>* __restrict__ part,
+                                              const int* __restrict__ active) {
+  __shared__ cplx<R> colred[4][kB];
   const int l = blockIdx.y;
   if (active && !active[l * kSysiStride]) return;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int t = blockIdx.x;
+  int I, J;
+  decode_tile(t, I, J);
+  cplx<R> a[kRowsPerWave];
+  masked_tile<R>(V + (int64_t)l * sym_slice(M), t, M, I, J, a);
+  tile_products<R>(a, M, I, J, x + (int64_t)l * xs, part + (int64_t)l * sym_partials(M),
+                   sym_blocks(M) * kB, colred);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_symv_reduce(const cplx<R>* __restrict__ part, int M,
+                                                     cplx<R>* __restrict__ y, int64_t ys,
+                                                     const int* __restrict__ active) {
+  const int l = blockIdx.y;
+  if (active && !active[l * kSysiStride]) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
-  const cplx<R>* row = V + ((int64_t)l * M + i) * M;
-  const cplx<R>* xv = x + (int64_t)l * xs;
-  R re = R(0), im = R(0);
-  int j = lane;
-  for (; j + 192 < M; j += 256) {
-    cplx<R> a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = row[j + 64 * u];
-      b[u] = xv[j + 64 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      re += a[u].re * b[u].re - a[u].im * b[u].im;
-      im += a[u].re * b[u].im + a[u].im * b[u].re;
-    }
-  }
-  for (; j < M; j += 64) {
-    const cplx<R> a = row[j], b = xv[j];
-    re += a.re * b.re - a.im * b.im;
-    im += a.re * b.im + a.im * b.re;
-  }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (lane == 0) {
-    cplx<R> o;
-    o.re = re;
-    o.im = im;
-    y[(int64_t)l * ys + i] = o;
-  }
+  y[(int64_t)l * ys + i] = sum_partials<R>(part + (int64_t)l * sym_partials(M), M, i);
 }
 
 template <typename R>
 void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y,
-                       int64_t ys, const int* active, hipStream_t s) {
-  dim3 grid((M + 3) / 4, nsys);
-  hipLaunchKernelGGL((k_dense_gemv<R>), grid, dim3(256), 0, s, V, M, x, xs, y, ys, active);
+                       int64_t ys, const int* active, cplx<R>* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_symv<R>), dim3(sym_tiles(M), nsys), dim3(256), 0, s, V, M, x, xs, part,
+                     active);
+  hipLaunchKernelGGL((k_symv_reduce<R>), dim3((M + 255) / 256, nsys), dim3(256), 0, s, part, M, y,
+                     ys, active);
   CQM_HIP(hipGetLastError());
 }
 
-// Products over system descriptors (systems of several problems, different
-// sizes): one workgroup per (group, 4 rows), one wave per row.  A group is a
-// set of systems sharing the operator slice, so the row is read once and
-// multiplied by every member's vector.
-template <typename R>
-__global__ __launch_bounds__(256) void k_dense_gemv_desc(const SysDesc* __restrict__ sd,
-                                                         const GemvGroup* __restrict__ groups,
-                                                         const RowBlock* __restrict__ map, int which,
-                                                         int j, unsigned long long* ctr) {
-  const RowBlock rb = map[blockIdx.x];
-  const GemvGroup G = groups[rb.group];
-  const SysDesc D0 = sd[G.sys[0]];
-  const int M = D0.M;
-  const int lane = threadIdx.x & 63;
-  const int i = rb.row0 + (threadIdx.x >> 6);
-  if (i >= M) return;
-  const cplx<R>* xs[kMaxGroup];
-  cplx<R>* ys[kMaxGroup];
-  int n = 0;
-  for (int q = 0; q < G.n; ++q) {
-    const SysDesc& D = sd[G.sys[q]];
-    if (which == 0 ? !D.sysi[1] : !D.sysi[0]) continue;
-    if (which == 0) {
-      xs[n] = (const cplx<R>*)D.basis + (int64_t)j * M;
-      ys[n] = (cplx<R>*)D.basis + (int64_t)(j + 1) * M;
-    } else {
-      xs[n] = (const cplx<R>*)(const void*)D.x;
-      ys[n] = (cplx<R>*)(void*)D.r;
-    }
-    ++n;
+// ------------------------------------------------------------ descriptors
+// Products over system groups (a group: systems sharing one operator slice,
+// up to kMaxGroup).  The host launches one grid per mesh size, (tiles x open
+// groups), each workgroup reading its group record once: the tile, the
+// members' flags and vectors all hang off that one load.  The group lists
+// are rebuilt by the host at its status checks; members closed since are
+// skipped.  which = 0: basis[j] -> basis[j+1] of systems with an open cycle
+// (inner precision); which = 1: x -> r of open systems (FP64).
+template <typename R, bool kGrouped>
+__global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict__ gl, int which,
+                                                     int j, unsigned long long* ctr) {
+  __shared__ cplx<R> colred[4][kB];
+  const GroupLite& G = gl[blockIdx.y];
+  const int M = G.M;
+  const int t = blockIdx.x;
+  int I, J;
+  decode_tile(t, I, J);
+  const void* Vs = which == 0 ? (sizeof(R) == 4 ? G.V32 : G.V64) : G.V64;
+  cplx<R> a[kRowsPerWave];
+  masked_tile<R>((const cplx<R>*)Vs, t, M, I, J, a);
+  const int ntB = sym_blocks(M) * kB;
+  const int n = kGrouped ? G.n : 1;
+  int done = 0;
+  for (int k = 0; k < n; ++k) {
+    if (!G.sysi[k][which == 0 ? 1 : 0]) continue;
+    const cplx<R>* x = which == 0 ? (const cplx<R>*)G.basis[k] + (int64_t)j * M
+                                  : (const cplx<R>*)(const void*)G.x[k];
+    tile_products<R>(a, M, I, J, x, (cplx<R>*)G.symp[k], ntB, colred);
+    ++done;
   }
-  if (n == 0) return;
-  if (ctr && threadIdx.x == 0 && rb.row0 == 0) {
-    // algorithmic bytes of the whole product, charged once per group by its
-    // first row block: the operator slice once, each member's input and
-    // result vectors once
+  if (ctr && t == 0 && threadIdx.x == 0 && done) {
+    // algorithmic bytes, charged once per group by its first tile: the upper
+    // triangle of the slice once, each member's vectors once
     const unsigned long long MM = (unsigned long long)M;
-    atomicAdd(ctr, (MM * MM + (unsigned long long)n * 2 * MM) * sizeof(cplx<R>));
+    atomicAdd(ctr, (MM * (MM + 1) / 2 + (unsigned long long)done * 2 * MM) * sizeof(cplx<R>));
   }
-  const cplx<R>* V = (which == 0) ? (const cplx<R>*)(sizeof(R) == 4 ? D0.V32 : (const void*)D0.V64)
-                                  : (const cplx<R>*)(const void*)D0.V64;
-  const cplx<R>* row = V + (int64_t)i * M;
-  if (n == 1) {  // (single-member groups normally take k_dense_gemv_desc1)
-    const cplx<R>* xv = xs[0];
-    R sre = R(0), sim = R(0);
-    int jj = lane;
-    for (; jj + 192 < M; jj += 256) {
-      cplx<R> a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = row[jj + 64 * u];
-        b[u] = xv[jj + 64 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        sre += a[u].re * b[u].re - a[u].im * b[u].im;
-        sim += a[u].re * b[u].im + a[u].im * b[u].re;
-      }
-    }
-    for (; jj < M; jj += 64) {
-      const cplx<R> a = row[jj], b = xv[jj];
-      sre += a.re * b.re - a.im * b.im;
-      sim += a.re * b.im + a.im * b.re;
-    }
-    sre = wave_sum(sre);
-    sim = wave_sum(sim);
-    if (lane == 0) {
-      cplx<R> o;
-      o.re = sre;
-      o.im = sim;
-      ys[0][i] = o;
-    }
-    return;
-  }
-  R re[kMaxGroup], im[kMaxGroup];
-#pragma unroll
-  for (int q = 0; q < kMaxGroup; ++q) re[q] = im[q] = R(0);
-  for (int jj = lane; jj < M; jj += 64) {
-    const cplx<R> a = row[jj];
-#pragma unroll
-    for (int q = 0; q < kMaxGroup; ++q)
-      if (q < n) {
-        const cplx<R> b = xs[q][jj];
-        re[q] += a.re * b.re - a.im * b.im;
-        im[q] += a.re * b.im + a.im * b.re;
-      }
-  }
-#pragma unroll
-  for (int q = 0; q < kMaxGroup; ++q)
-    if (q < n) {
-      const R sr = wave_sum(re[q]), si = wave_sum(im[q]);
-      if (lane == 0) {
-        cplx<R> o;
-        o.re = sr;
-        o.im = si;
-        ys[q][i] = o;
-      }
-    }
 }
 
-// Every group has one member: lean kernel (no per-member arrays, full
-// occupancy), four independent loads in flight per lane.
 template <typename R>
-__global__ __launch_bounds__(256) void k_dense_gemv_desc1(const SysDesc* __restrict__ sd,
-                                                          const GemvGroup* __restrict__ groups,
-                                                          const RowBlock* __restrict__ map, int which,
-                                                          int j, unsigned long long* ctr) {
-  const RowBlock rb = map[blockIdx.x];
-  const SysDesc D = sd[groups[rb.group].sys[0]];
+__global__ __launch_bounds__(256) void k_symv_reduce_desc(const SysDesc* __restrict__ sd, int which,
+                                                          int j) {
+  const SysDesc D = sd[blockIdx.y];
+  if (!D.symp) return;  // not a stored-operator system (matrix-free in a mixed batch)
   if (which == 0 ? !D.sysi[1] : !D.sysi[0]) return;
-  const int lane = threadIdx.x & 63;
-  const int i = rb.row0 + (threadIdx.x >> 6);
   const int M = D.M;
-  if (ctr && threadIdx.x == 0 && rb.row0 == 0) {
-    const unsigned long long MM = (unsigned long long)M;
-    atomicAdd(ctr, (MM * MM + 2 * MM) * sizeof(cplx<R>));
-  }
+  const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
-  const cplx<R>* V;
-  const cplx<R>* xv;
-  cplx<R>* y;
-  if (which == 0) {
-    V = (const cplx<R>*)(sizeof(R) == 4 ? D.V32 : (const void*)D.V64);
-    xv = (const cplx<R>*)D.basis + (int64_t)j * M;
-    y = (cplx<R>*)D.basis + (int64_t)(j + 1) * M;
-  } else {
-    V = (const cplx<R>*)(const void*)D.V64;
-    xv = (const cplx<R>*)(const void*)D.x;
-    y = (cplx<R>*)(void*)D.r;
-  }
-  const cplx<R>* row = V + (int64_t)i * M;
-  R re = R(0), im = R(0);
-  int jj = lane;
-  for (; jj + 192 < M; jj += 256) {
-    cplx<R> a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = row[jj + 64 * u];
-      b[u] = xv[jj + 64 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      re += a[u].re * b[u].re - a[u].im * b[u].im;
-      im += a[u].re * b[u].im + a[u].im * b[u].re;
-    }
-  }
-  for (; jj < M; jj += 64) {
-    const cplx<R> a = row[jj], b = xv[jj];
-    re += a.re * b.re - a.im * b.im;
-    im += a.re * b.im + a.im * b.re;
-  }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (lane == 0) {
-    cplx<R> o;
-    o.re = re;
-    o.im = im;
-    y[i] = o;
-  }
+  cplx<R>* y = which == 0 ? (cplx<R>*)D.basis + (int64_t)(j + 1) * M : (cplx<R>*)(void*)D.r;
+  y[i] = sum_partials<R>((const cplx<R>*)D.symp, M, i);
 }
 
 template <typename R>
-void launch_dense_gemv_desc(const SysDesc* sd, const GemvGroup* groups, const RowBlock* map,
-                            int nblocks, int which, int j, bool grouped, unsigned long long* ctr,
-                            hipStream_t s) {
+void launch_dense_gemv_groups(const GroupLite* gl, int ngroups, int M, bool grouped, int which,
+                              int j, unsigned long long* ctr, hipStream_t s) {
+  if (ngroups <= 0) return;
+  const dim3 grid(sym_tiles(M), ngroups);
   if (grouped)
-    hipLaunchKernelGGL((k_dense_gemv_desc<R>), dim3(nblocks), dim3(256), 0, s, sd, groups, map, which, j, ctr);
+    hipLaunchKernelGGL((k_symv_groups<R, true>), grid, dim3(256), 0, s, gl, which, j, ctr);
   else
-    hipLaunchKernelGGL((k_dense_gemv_desc1<R>), dim3(nblocks), dim3(256), 0, s, sd, groups, map, which, j, ctr);
+    hipLaunchKernelGGL((k_symv_groups<R, false>), grid, dim3(256), 0, s, gl, which, j, ctr);
   CQM_HIP(hipGetLastError());
 }
-template void launch_dense_gemv_desc<float>(const SysDesc*, const GemvGroup*, const RowBlock*, int, int,
-                                            int, bool, unsigned long long*, hipStream_t);
-template void launch_dense_gemv_desc<double>(const SysDesc*, const GemvGroup*, const RowBlock*, int, int,
-                                             int, bool, unsigned long long*, hipStream_t);
+
+template <typename R>
+void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((k_symv_reduce_desc<R>), dim3((maxM + 255) / 256, nsys), dim3(256), 0, s, sd,
+                     which, j);
+  CQM_HIP(hipGetLastError());
+}
+template void launch_dense_gemv_groups<float>(const GroupLite*, int, int, bool, int, int,
+                                              unsigned long long*, hipStream_t);
+template void launch_dense_gemv_groups<double>(const GroupLite*, int, int, bool, int, int,
+                                               unsigned long long*, hipStream_t);
+template void launch_dense_reduce_desc<float>(const SysDesc*, int, int, int, int, hipStream_t);
+template void launch_dense_reduce_desc<double>(const SysDesc*, int, int, int, int, hipStream_t);
 
 template void launch_dense_gemv<float>(const cf32*, int, int, const cf32*, int64_t, cf32*, int64_t,
-                                       const int*, hipStream_t);
+                                       const int*, cf32*, hipStream_t);
 template void launch_dense_gemv<double>(const cf64*, int, int, const cf64*, int64_t, cf64*,
-                                        int64_t, const int*, hipStream_t);
+                                        int64_t, const int*, cf64*, hipStream_t);
 
 }  // namespace cqm

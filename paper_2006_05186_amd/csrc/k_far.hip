@@ -205,12 +205,13 @@ __global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, in
   y[(int64_t)l * ys + i] = o;
 }
 
-// Dense assembly of the far pairs of all frequency systems, FP64 entries (and
-// an optional complex64 copy).  V(s) is symmetric, so only tiles I <= J of a
-// 16 x 16 tiling are evaluated: each thread computes one pair (i, j), i <= j,
-// for FT frequencies, stores it along rows (coalesced) and, through an LDS
-// transpose, stores the mirrored entry (j, i) along rows as well.  Near pairs
-// are left for the near-field scatter.
+// Dense assembly of the far pairs of all frequency systems into the packed
+// upper triangle of 64 x 64 tiles, FP64 entries (and an optional complex64
+// copy).  V(s) is symmetric, so only tiles I <= J of a 16 x 16 tiling are
+// evaluated: each thread computes one pair (i, j), i <= j, for FT
+// frequencies and stores it along rows (coalesced); inside diagonal 64-tiles,
+// which are stored in full, the mirrored entry (j, i) is stored as well
+// through an LDS transpose.  Near pairs are left for the near-field scatter.
 constexpr int kAt = 16;
 template <int FT>
 __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __restrict__ pts,
@@ -276,28 +277,29 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
       }
     }
   }
-  const int64_t MM = (int64_t)M * M;
+  const int64_t SL = sym_slice(M);
 #pragma unroll
   for (int l = 0; l < FT; ++l) {
     const double re = vre[l] * kInv4Pi, im = vim[l] * kInv4Pi;
     tile[l][ty][tx] = cf64{re, im};
     if (live && l < nl) {
-      const int64_t o = (int64_t)(l0 + l) * MM + (int64_t)i * M + j;
+      const int64_t o = (int64_t)(l0 + l) * SL + sym_index(i, j);
       d64[o] = cf64{re, im};
       if (d32) d32[o] = cf32{(float)re, (float)im};
     }
   }
   __syncthreads();
-  // mirrored entries: thread (ty, tx) writes (j', i') = (J*16+ty, I*16+tx)
+  // mirrored entries: thread (ty, tx) writes (j', i') = (J*16+ty, I*16+tx);
+  // they are stored only inside diagonal tiles of the packed triangle
   const int jm = (int)J * kAt + ty, im_ = I * kAt + tx;
-  bool live_m = jm < M && im_ < M && (I != J || im_ < jm);
+  bool live_m = jm < M && im_ < M && (I != J || im_ < jm) && sym_stored(jm, im_);
   if (live_m) live_m = !share_vertex(vid[im_], vid[jm]);
   if (live_m) {
 #pragma unroll
     for (int l = 0; l < FT; ++l)
       if (l < nl) {
         const cf64 v = tile[l][tx][ty];
-        const int64_t o = (int64_t)(l0 + l) * MM + (int64_t)jm * M + im_;
+        const int64_t o = (int64_t)(l0 + l) * SL + sym_index(jm, im_);
         d64[o] = v;
         if (d32) d32[o] = cf32{(float)v.re, (float)v.im};
       }

@@ -178,27 +178,6 @@ __device__ __forceinline__ void basis_combine(const cplx<R>* __restrict__ V, int
   }
 }
 
-// Sum of NV per-lane values over the 64 lanes of a wave, scattered: on
-// return lane t holds, in a[0], the total of entry t >> (6 - log2 NV).
-// Each halving step exchanges half of the remaining entries with the
-// partner lane (NV - 1 shuffles in all instead of 6 NV).
-template <int NV, int OFF>
-__device__ __forceinline__ void wave_reduce_scatter(double* a, int lane) {
-  if constexpr (NV > 1) {
-    constexpr int H = NV / 2;
-    const bool up = (lane & OFF) != 0;
-#pragma unroll
-    for (int u = 0; u < H; ++u) {
-      const double send = up ? a[u] : a[u + H];
-      const double keep = up ? a[u + H] : a[u];
-      a[u] = keep + __shfl_xor(send, OFF, 64);
-    }
-    wave_reduce_scatter<H, OFF / 2>(a, lane);
-  } else {
-#pragma unroll
-    for (int o = OFF; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
-  }
-}
 
 // One Arnoldi step of every open system.  Classical Gram-Schmidt with the
 // DGKS criterion: a second pass is made only if the first one removed more

@@ -237,6 +237,9 @@ size_t state_layout(const Problem& p, SolveState& st) {
   st.sysd = take(sizeof(double) * 8 * Fs);
   st.sysi = take(sizeof(int) * kSysiStride * Fs);
   st.part = take(sizeof(double) * Fs * ((M + kArnRows - 1) / kArnRows) * (4 * (m + 1) + 2));
+  // tile partial sums of stored-operator products (sized for FP64)
+  const bool stored = !mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE;
+  st.sym = stored ? take(sizeof(cf64) * Fs * sym_partials((int)M)) : 0;
   st.scratch = take(4096);
   st.total = off;
   return off;
@@ -259,8 +262,8 @@ void compute_layout(Problem& p) {
   } else {
     L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
     if (p.opt.form == CQM_FORM_DENSE) {
-      L.dense64 = take(sizeof(cf64) * Fs * M * M);
-      if (mode_is_mixed(p.opt.mode)) L.dense32 = take(sizeof(cf32) * Fs * M * M);
+      L.dense64 = take(sizeof(cf64) * Fs * sym_slice((int)M));
+      if (mode_is_mixed(p.opt.mode)) L.dense32 = take(sizeof(cf32) * Fs * sym_slice((int)M));
     } else {
       size_t worst = 0;
       for (int nl = 1; nl <= (int)Fs; ++nl) {

@@ -90,8 +90,10 @@ def test_admission_by_budget_and_rejection(ctx):
     op_bytes = p.workspace_bytes
     p.close()
     # room for the operator (with its own state) and about one more request
-    # state: requests must queue.  The dense mixed operator is Fsys M^2 x 24 B.
-    state = op_bytes - (N // 2 + 1) * len(T) ** 2 * 24
+    # state: requests must queue.  The dense mixed operator keeps the upper
+    # triangle of 64 x 64 tiles of each of the Fsys slices, 24 B per entry.
+    nt = (len(T) + 63) // 64
+    state = op_bytes - (N // 2 + 1) * (nt * (nt + 1) // 2) * 64 * 64 * 24
     srv = Server(ctx, int(op_bytes + 1.5 * state), max_active=8, mode=C.CQM_MIXED_PLAIN,
                  form=C.CQM_FORM_DENSE)
     ts = [srv.submit(V, T, N, 2.0) for _ in range(4)]
