@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference "
+                         "kernel for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs "
@@ -257,6 +260,16 @@ def main():
     from paper_2006_05186_amd.solver import Problem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     ctx = C.cqm_ctx_create(0)
     main_mode, main_form = C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE

@@ -159,6 +159,7 @@ int cqm_ctx_destroy(cqm_ctx_t ctx) {
   if (ctx->eb.staging) (void)hipHostFree(ctx->eb.staging);
   if (ctx->eb.groups) (void)hipFree(ctx->eb.groups);
   if (ctx->eb.status) (void)hipFree(ctx->eb.status);
+  if (ctx->eb.status_host) (void)hipHostFree(ctx->eb.status_host);
   delete ctx;
   return CQM_OK;
 }

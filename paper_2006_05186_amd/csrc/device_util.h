@@ -40,6 +40,23 @@ __device__ __forceinline__ void wave_reduce_scatter(T* a, int lane) {
   }
 }
 
+// Row i of a stored-operator product from its tile partial sums:
+// y_i = sum_{Y < nt} P[Y][i] in a fixed order (P: nt slots of nt kSymB rows).
+template <typename R>
+__device__ __forceinline__ cplx<R> sym_row_sum(const cplx<R>* __restrict__ P, int M, int i) {
+  const int nt = sym_blocks(M), ntB = nt * kSymB;
+  R re = R(0), im = R(0);
+  for (int Y = 0; Y < nt; ++Y) {
+    const cplx<R> v = P[(int64_t)Y * ntB + i];
+    re += v.re;
+    im += v.im;
+  }
+  cplx<R> o;
+  o.re = re;
+  o.im = im;
+  return o;
+}
+
 // Sum over a workgroup of blockDim.x threads (multiple of 64, <= 1024).
 // `red` is caller-provided shared scratch of >= 16 T; result broadcast to all.
 template <typename T> __device__ __forceinline__ T block_sum(T v, T* red) {

@@ -245,8 +245,37 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     ctx.eb.staging_cap = c;
   }
   ensure(ctx.eb.status, ctx.eb.status_cap, (size_t)kSysiStride * n);
+  if (ctx.eb.status_host_cap < (size_t)kSysiStride * n) {
+    if (ctx.eb.status_host) {
+      CQM_HIP(hipStreamSynchronize(s));
+      CQM_HIP(hipHostFree(ctx.eb.status_host));
+    }
+    ctx.eb.status_host = nullptr;
+    ctx.eb.status_host_cap = 0;
+    const size_t c = std::max<size_t>((size_t)kSysiStride * n, 1024);
+    CQM_HIP(hipHostMalloc((void**)&ctx.eb.status_host, sizeof(int) * c, hipHostMallocDefault));
+    ctx.eb.status_host_cap = c;
+  }
   CQM_HIP(hipMemcpyAsync(ctx.eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
   flags_.assign((size_t)kSysiStride * n, 0);
+}
+
+Engine::~Engine() {
+  if (snap_ev_) (void)hipEventDestroy(snap_ev_);
+}
+
+void Engine::snapshot(hipStream_t s) {
+  const int n = (int)hd_.size();
+  if (!snap_ev_) CQM_HIP(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
+  launch_gather_status(ctx.eb.desc, n, ctx.eb.status, s);
+  CQM_HIP(hipMemcpyAsync(ctx.eb.status_host, ctx.eb.status, sizeof(int) * flags_.size(),
+                         hipMemcpyDeviceToHost, s));
+  CQM_HIP(hipEventRecord(snap_ev_, s));
+}
+
+void Engine::read_snapshot() {
+  CQM_HIP(hipEventSynchronize(snap_ev_));
+  std::copy(ctx.eb.status_host, ctx.eb.status_host + flags_.size(), flags_.begin());
 }
 
 void Engine::init(int k, hipStream_t s) {
@@ -294,10 +323,11 @@ void Engine::upload_open(int which, GroupLite* dst, size_t stage, std::vector<GC
 
 template <typename R>
 void Engine::dense_product(const GroupLite* list, const std::vector<GClass>& cls, int which, int j,
-                           unsigned long long* ctr, hipStream_t s) {
+                           bool reduce, unsigned long long* ctr, hipStream_t s) {
   for (const GClass& c : cls)
     launch_dense_gemv_groups<R>(list + c.off, c.count, c.M, c.grouped, which, j, ctr, s);
-  if (!cls.empty()) launch_dense_reduce_desc<R>(ctx.eb.desc, (int)hd_.size(), maxM_, which, j, s);
+  if (reduce && !cls.empty())
+    launch_dense_reduce_desc<R>(ctx.eb.desc, (int)hd_.size(), maxM_, which, j, s);
 }
 
 bool Engine::state_done(int k) const {
@@ -336,11 +366,12 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   upload_open(0, ctx.eb.open_cycle, 0, cyc_cls_, s);
   const GroupLite* step_list = ctx.eb.open_cycle;
   step_cls_ = cyc_cls_;
+  int snap_j = -1;  // step behind which a status snapshot is pending
   for (int j = 0; j < m_; ++j) {
     if (!lite_.empty()) {
       const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
       Timed t(p0, c, s);
-      dense_product<R>(step_list, step_cls_, 0, j, p0.timer.ctr(c), s);
+      dense_product<R>(step_list, step_cls_, 0, j, !split_, p0.timer.ctr(c), s);
     }
     for (SolveState* st : S_) {
       Problem& p = *st->p;
@@ -353,13 +384,23 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     }
     {
       Timed t(p0, CQM_K_ARNOLDI, s);
-      launch_arnoldi<R>(sd, n, maxM_, j, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
+      launch_arnoldi<R>(sd, n, maxM_, j, split_, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
     }
-    if ((j + 1) % 6 == 0 && j + 1 < m_) {
-      if (count(1) == 0) break;
-      // drop the groups whose cycles closed
+    // status: a snapshot behind step j is read three steps later, so the
+    // stream keeps three steps of queued work while the host decides
+    if (snap_j >= 0 && j == snap_j + 3) {
+      read_snapshot();
+      snap_j = -1;
+      int c = 0;
+      for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + 1] != 0;
+      if (c == 0) break;
+      // drop the groups whose cycles had closed by then
       upload_open(1, ctx.eb.open_step, lite_.size(), step_cls_, s);
       step_list = ctx.eb.open_step;
+    }
+    if ((j + 1) % 6 == 0 && j + 4 < m_ && snap_j < 0) {
+      snapshot(s);
+      snap_j = j;
     }
   }
   {
@@ -369,7 +410,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start
     Timed t(p0, CQM_K_GEMV64, s);
-    dense_product<double>(ctx.eb.open_cycle, cyc_cls_, 1, 0, p0.timer.ctr(CQM_K_GEMV64), s);
+    dense_product<double>(ctx.eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -386,9 +427,9 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   return open;
 }
 template void Engine::dense_product<float>(const GroupLite*, const std::vector<GClass>&, int, int,
-                                           unsigned long long*, hipStream_t);
+                                           bool, unsigned long long*, hipStream_t);
 template void Engine::dense_product<double>(const GroupLite*, const std::vector<GClass>&, int, int,
-                                            unsigned long long*, hipStream_t);
+                                            bool, unsigned long long*, hipStream_t);
 template int Engine::cycle_t<float>(hipStream_t);
 template int Engine::cycle_t<double>(hipStream_t);
 

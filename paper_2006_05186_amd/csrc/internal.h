@@ -131,6 +131,8 @@ struct EngineBufs {
   size_t groups_cap = 0;
   int* status = nullptr;
   size_t status_cap = 0;
+  int* status_host = nullptr;       // pinned copy for lagged snapshots
+  size_t status_host_cap = 0;
 };
 
 struct Ctx {
@@ -278,9 +280,11 @@ void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
 void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s);
 template <typename R>
 void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s);
+// split: three launches over row slices; fused (split only): the first one
+// also sums the stored-operator partials of w = A v_j (no separate reduction)
 template <typename R>
-void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, unsigned long long* ctr,
-                    hipStream_t s);
+void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
+                    unsigned long long* ctr, hipStream_t s);
 template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s);
 // dense products over descriptors (k_dense.hip): which = 0 inner product
 // basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
@@ -317,6 +321,9 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s);  // full solves, 
 class Engine {
  public:
   explicit Engine(Ctx& c) : ctx(c) {}
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
   void set(const std::vector<SolveState*>& S, hipStream_t s);  // rebuild descriptors
   void init(int k, hipStream_t s);                              // x = 0, r = ghat of state k
   int cycle(hipStream_t s);                                     // returns systems still open
@@ -340,13 +347,20 @@ class Engine {
   // size, uploaded to dst from the pinned staging area at `stage`
   void upload_open(int which, GroupLite* dst, size_t stage, std::vector<GClass>& cls,
                    hipStream_t s);
+  // reduce = false leaves the partial sums for the Arnoldi step to add up
   template <typename R>
   void dense_product(const GroupLite* list, const std::vector<GClass>& cls, int which, int j,
-                     unsigned long long* ctr, hipStream_t s);
+                     bool reduce, unsigned long long* ctr, hipStream_t s);
   std::vector<GemvGroup> groups_;
   bool split_ = false;    // Arnoldi step split over row slices
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
+  // lagged status snapshot inside a cycle: flags copied to pinned memory
+  // behind the queued launches, read a few steps later without draining the
+  // stream
+  hipEvent_t snap_ev_ = nullptr;
+  void snapshot(hipStream_t s);
+  void read_snapshot();
 };
 
 // RAII helper: times the launches issued in its scope as one class.

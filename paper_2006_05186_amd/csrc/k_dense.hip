@@ -128,20 +128,9 @@ __device__ __forceinline__ void masked_tile(const cplx<R>* __restrict__ Vs, int 
   }
 }
 
-// y_i = sum_{Y < nt} P[Y][i], fixed order.
 template <typename R>
 __device__ __forceinline__ cplx<R> sum_partials(const cplx<R>* __restrict__ P, int M, int i) {
-  const int nt = (M + kB - 1) / kB, ntB = nt * kB;
-  R re = R(0), im = R(0);
-  for (int Y = 0; Y < nt; ++Y) {
-    const cplx<R> v = P[(int64_t)Y * ntB + i];
-    re += v.re;
-    im += v.im;
-  }
-  cplx<R> o;
-  o.re = re;
-  o.im = im;
-  return o;
+  return sym_row_sum<R>(P, M, i);
 }
 }  // namespace
 

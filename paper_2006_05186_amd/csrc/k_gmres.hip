@@ -362,7 +362,7 @@ template <typename R> struct ArnChunk { static constexpr int v = 16; };
 
 template <typename R>
 __global__ __launch_bounds__(kArnRows) void k_arn_dots(const SysDesc* __restrict__ sd, int j,
-                                                      unsigned long long* ctr) {
+                                                      int fused, unsigned long long* ctr) {
   constexpr int kC = ArnChunk<R>::v;
   __shared__ double red[(kArnRows / 64) * 2 * kC];
   const SysDesc D = sd[blockIdx.y];
@@ -372,11 +372,19 @@ __global__ __launch_bounds__(kArnRows) void k_arn_dots(const SysDesc* __restrict
   if (s * kArnRows >= M) return;
   const int i = s * kArnRows + threadIdx.x;
   const bool valid = i < M;
-  const cplx<R>* V = (const cplx<R>*)D.basis;
+  cplx<R>* V = (cplx<R>*)D.basis;
   cplx<R> x;
   x.re = R(0);
   x.im = R(0);
-  if (valid) x = V[(int64_t)(j + 1) * M + i];
+  if (valid) {
+    if (fused && D.symp) {
+      // w = A v_j of a stored operator: sum its tile partials here
+      x = sym_row_sum<R>((const cplx<R>*)D.symp, M, i);
+      V[(int64_t)(j + 1) * M + i] = x;
+    } else {
+      x = V[(int64_t)(j + 1) * M + i];
+    }
+  }
   double* P = D.part + (int64_t)s * arn_stride(m);
   slice_dots<R, kC>(V, M, i, valid, x, j, reinterpret_cast<cf64*>(P), red);
   const double nn = block_sum((double)x.re * x.re + (double)x.im * x.im, red);
@@ -593,11 +601,11 @@ void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner
 // reductions dominates for short vectors, memory parallelism for long ones),
 // or the three-launch split over row slices.
 template <typename R>
-void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, unsigned long long* ctr,
-                    hipStream_t s) {
+void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
+                    unsigned long long* ctr, hipStream_t s) {
   if (split) {
     const dim3 grid((maxM + kArnRows - 1) / kArnRows, n);
-    hipLaunchKernelGGL((k_arn_dots<R>), grid, dim3(kArnRows), 0, s, sd, j, ctr);
+    hipLaunchKernelGGL((k_arn_dots<R>), grid, dim3(kArnRows), 0, s, sd, j, fused ? 1 : 0, ctr);
     hipLaunchKernelGGL((k_arn_update<R>), grid, dim3(kArnRows), 0, s, sd, j, ctr);
     hipLaunchKernelGGL((k_arn_finish<R>), grid, dim3(kArnRows), 0, s, sd, j, ctr);
   } else if (maxM < 3072) {
@@ -614,10 +622,10 @@ template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStre
 
 template void launch_cycle_start<float>(const SysDesc*, int, double, double, hipStream_t);
 template void launch_cycle_start<double>(const SysDesc*, int, double, double, hipStream_t);
-template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, unsigned long long*,
-                                    hipStream_t);
-template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, unsigned long long*,
-                                     hipStream_t);
+template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, bool,
+                                    unsigned long long*, hipStream_t);
+template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, bool,
+                                     unsigned long long*, hipStream_t);
 template void launch_cycle_finish<float>(const SysDesc*, int, hipStream_t);
 template void launch_cycle_finish<double>(const SysDesc*, int, hipStream_t);
 
