@@ -32,6 +32,17 @@ PEAK_HBM_GBS = 8000.0
 # evaluations (exp, sin, cos; one flop each), three multiplies (sigma r,
 # omega r, weight) and two fused multiply-adds (4 flops).
 FLOPS_PER_UNIT = 10
+# Kernel-value ceilings from the chip's unit counts: 256 CUs x 64 lanes x
+# 2.4 GHz = 3.93e13 lane-cycles/s.  FP32: 3 transcendentals at quarter rate
+# plus ~6 full-rate ops = ~18 lane-cycles per value.  FP64 (no hardware
+# transcendentals): ~48 FP64 lane-cycles per value for the software
+# exp (degree-13 Horner + reduction) and sincos (degrees 17/18 + reduction)
+# plus the multiplies and accumulation.  Expressed in TFLOP/s with the
+# 10-flop convention above.
+LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
+ALU_PEAK_TFLOPS = {"far32": LANE_CYCLES_PER_S / 18 * FLOPS_PER_UNIT / 1e12,
+                   "far64": LANE_CYCLES_PER_S / 48 * FLOPS_PER_UNIT / 1e12,
+                   "assemble": LANE_CYCLES_PER_S / 48 * FLOPS_PER_UNIT / 1e12}
 
 WORKLOADS = {"C1": W.C1, "C2": W.C2, "C3": W.C3}
 KCLS = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
@@ -100,10 +111,12 @@ def roofline(diags):
            "work_per_launch": work[k] / n}
     if name in ("far32", "far64", "assemble"):
         ach = work[k] / n * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP32_TFLOPS if name == "far32" else PEAK_FP64_TFLOPS
+        peak = ALU_PEAK_TFLOPS[name]
+        vendor = PEAK_FP32_TFLOPS if name == "far32" else PEAK_FP64_TFLOPS
         return out | {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                      "frac": ach / peak, "traffic": None, "work_unit": "kernel values",
-                      "flops_per_unit": FLOPS_PER_UNIT}
+                      "frac": ach / peak, "traffic": traffic_per_launch(name),
+                      "work_unit": "kernel values", "flops_per_unit": FLOPS_PER_UNIT,
+                      "frac_of_vendor_peak": ach / vendor}
     if name in ("gemv32", "gemv64", "arnoldi"):
         ach = work[k] / n / (avg_ms * 1e-3) / 1e9
         return out | {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -347,7 +360,8 @@ def main():
         var["far32_apply_probe"] = {"ms": t_apply * 1e3, "units_per_s": u / t_apply,
                                     "entries_per_s": u / 36 / t_apply,
                                     "tflops": u * FLOPS_PER_UNIT / t_apply / 1e12,
-                                    "frac_fp32_peak": u * FLOPS_PER_UNIT / t_apply / 1e12 / PEAK_FP32_TFLOPS}
+                                    "frac_fp32_peak": u * FLOPS_PER_UNIT / t_apply / 1e12 / PEAK_FP32_TFLOPS,
+                                    "frac_transcendental_ceiling": u / t_apply / (LANE_CYCLES_PER_S / 18)}
         p.close()
         out["variants"] = var
     if not args.no_variants:
