@@ -64,6 +64,45 @@ void setup_structure(Problem& p) {
     tasks.insert(tasks.end(), per_leaf[k].begin(), per_leaf[k].end());
     trow[k + 1] = (int)tasks.size();
   }
+  // block-rank product tables (16-row tiles)
+  {
+    std::vector<RankTile> ct, lt;
+    std::vector<RankTask> ck, lk;
+    const int P = h.p;
+    for (int r = 0; r < ncl; ++r)
+      for (int r0 = 0; r0 < P; r0 += 16) {
+        RankTile t{r * P + r0, std::min(16, P - r0), (int)ck.size(), 0};
+        for (int b : h.core_by_row[r]) {
+          const BlockDesc& B = h.blocks[b];
+          ck.push_back(RankTask{B.c_off + (int64_t)r0 * B.acols, B.d_off, B.arows * B.acols, B.acols,
+                                B.acols, b, B.c * P, 0});
+        }
+        t.t1 = (int)ck.size();
+        ct.push_back(t);
+      }
+    for (int k = 0; k < nleaf; ++k) {
+      const Cluster& Lc = h.cl[h.leaves[k]];
+      for (int r0 = 0; r0 < Lc.size(); r0 += 16) {
+        RankTile t{Lc.begin + r0, std::min(16, Lc.size() - r0), (int)lk.size(), 0};
+        for (int q = trow[k]; q < trow[k + 1]; ++q) {
+          const LeafTask& T = tasks[q];
+          const BlockDesc& B = h.blocks[T.block];
+          lk.push_back(RankTask{B.c_off + (int64_t)(T.rowoff + r0) * B.acols, B.d_off,
+                                B.arows * B.acols, B.acols, B.acols, T.block, h.cl[B.c].begin, 0});
+        }
+        t.t1 = (int)lk.size();
+        lt.push_back(t);
+      }
+    }
+    if (ck.empty()) ck.push_back(RankTask{});
+    if (lk.empty()) lk.push_back(RankTask{});
+    h.core_tiles_d = up(ct);
+    h.core_tasks_d = up(ck);
+    h.leaf_tiles_d = up(lt);
+    h.leaf_tasks_d = up(lk);
+    h.n_core_tiles = (int)ct.size();
+    h.n_leaf_tiles = (int)lt.size();
+  }
   // cluster table: begin, end, parent, leaf_id; then two sons per cluster
   std::vector<int> clt(6 * ncl);
   for (int c = 0; c < ncl; ++c) {
@@ -196,6 +235,10 @@ void h2_release(Problem& p) {
   release(h.task_rowptr_d);
   release(h.tasks_d);
   release(h.level_cl_d);
+  release(h.core_tiles_d);
+  release(h.core_tasks_d);
+  release(h.leaf_tiles_d);
+  release(h.leaf_tasks_d);
   delete p.h2;
   p.h2 = nullptr;
 }

@@ -36,6 +36,21 @@ struct LeafTask {
   int rowoff;  // first row of the leaf inside the block's row cluster
 };
 
+// Block-rank products on the matrix cores: 16 output rows and their tasks.
+struct RankTile {
+  int out_row0, nrows, t0, t1;
+};
+struct RankTask {
+  int64_t c_off;  // slice element of (first row of the tile, column 0), rank term 0
+  int64_t d_off;  // fibre of rank term 0 (stride: systems of the operator)
+  int cstride;    // elements between rank terms
+  int ldc;        // row length of the slice
+  int acols;      // columns
+  int block;      // block index (its rank is read on the device)
+  int x_row0;     // first input row
+  int pad;
+};
+
 struct H2Operator {
   int m = 4, p = 64, nsys = 0, Rcap = 48;
   std::vector<int> perm, iperm;
@@ -78,6 +93,13 @@ struct H2Operator {
   int* task_rowptr_d = nullptr;
   LeafTask* tasks_d = nullptr;
   int* level_cl_d = nullptr;     // clusters grouped by level
+  // block-rank product tables: couplings into cluster coefficient rows, and
+  // expanded-far / near blocks into the leaves' rows (cluster order)
+  RankTile* core_tiles_d = nullptr;
+  RankTask* core_tasks_d = nullptr;
+  RankTile* leaf_tiles_d = nullptr;
+  RankTask* leaf_tasks_d = nullptr;
+  int n_core_tiles = 0, n_leaf_tiles = 0;
   std::vector<int> level_off;
   // workspace regions (byte offsets from the problem's H2 region)
   size_t off_cstore = 0, off_dvec = 0, off_stage = 0, off_xhat = 0, off_yhat = 0, total = 0;

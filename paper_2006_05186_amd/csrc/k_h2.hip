@@ -100,43 +100,6 @@ __global__ __launch_bounds__(kHB) void k_h2_up(const int* __restrict__ list, con
 }
 
 // yhat_r = sum over core blocks (r, c): sum_k d_bk[l0+l] C_bk xhat_c  (every cluster)
-template <typename R, typename S>
-__global__ __launch_bounds__(kHB) void k_h2_couple(const int* __restrict__ rowptr, const int* __restrict__ list,
-                                                   const BlockDesc* __restrict__ blocks,
-                                                   const int* __restrict__ ranks,
-                                                   const cplx<S>* __restrict__ cstore,
-                                                   const cf64* __restrict__ dvec, int dstride, int l0,
-                                                   int P, int nsys, const cplx<R>* __restrict__ xhat,
-                                                   cplx<R>* __restrict__ yhat) {
-  const int r = blockIdx.x;
-  cplx<R>* out = yhat + (int64_t)r * P * nsys;
-  const int lb = blockIdx.y * kLC, ln = min(kLC, nsys - lb);
-  for (int e = threadIdx.x; e < P * ln; e += kHB) {
-    const int mu = e / ln, l = lb + e % ln;
-    R re = R(0), im = R(0);
-    for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
-      const int b = list[q];
-      const BlockDesc B = blocks[b];
-      const cplx<R>* xc = xhat + (int64_t)B.c * P * nsys;
-      const int rk = ranks[b];
-      for (int t = 0; t < rk; ++t) {
-        const cplx<S>* Ct = cstore + B.c_off + (int64_t)t * P * P + (int64_t)mu * P;
-        R sr = R(0), si = R(0);
-        for (int nu = 0; nu < P; ++nu) {
-          const cplx<S> c = Ct[nu];
-          const cplx<R> v = xc[(int64_t)nu * nsys + l];
-          cadd_mul<R>(sr, si, (R)c.re, (R)c.im, v.re, v.im);
-        }
-        const cf64 dv = dvec[B.d_off + (int64_t)t * dstride + l0 + l];
-        cadd_mul<R>(re, im, (R)dv.re, (R)dv.im, sr, si);
-      }
-    }
-    cplx<R> o;
-    o.re = re;
-    o.im = im;
-    out[(int64_t)mu * nsys + l] = o;
-  }
-}
 
 // yhat_c += E_c yhat_parent for the clusters of one level (top-down)
 template <typename R, typename U>
@@ -167,14 +130,13 @@ __global__ __launch_bounds__(kHB) void k_h2_down(const int* __restrict__ list, c
 
 // y at the triangles of one leaf: U_leaf yhat_leaf plus the expanded far and
 // near blocks whose row cluster contains the leaf.
-template <typename R, typename S, typename U>
-__global__ __launch_bounds__(kHB) void k_h2_leaf_out(
-    const int* __restrict__ cl, const int* __restrict__ leaves, const int* __restrict__ perm,
-    const U* __restrict__ Uleaf, const int64_t* __restrict__ uoff, int P, int nsys,
-    const cplx<R>* __restrict__ yhat, const int* __restrict__ trow, const LeafTask* __restrict__ tasks,
-    const BlockDesc* __restrict__ blocks, const int* __restrict__ ranks,
-    const cplx<S>* __restrict__ cstore, const cf64* __restrict__ dvec, int dstride, int l0,
-    const cplx<R>* __restrict__ xp, cplx<R>* __restrict__ yp) {
+template <typename R, typename U>
+__global__ __launch_bounds__(kHB) void k_h2_leaf_out(const int* __restrict__ cl,
+                                                     const int* __restrict__ leaves,
+                                                     const U* __restrict__ Uleaf,
+                                                     const int64_t* __restrict__ uoff, int P,
+                                                     int nsys, const cplx<R>* __restrict__ yhat,
+                                                     cplx<R>* __restrict__ yp) {
   const int lf = blockIdx.x, c = leaves[lf];
   const int beg = cl[4 * c], n = cl[4 * c + 1] - beg;
   const U* Ul = Uleaf + uoff[lf];
@@ -189,24 +151,6 @@ __global__ __launch_bounds__(kHB) void k_h2_leaf_out(
       re += u * v.re;
       im += u * v.im;
     }
-    for (int q = trow[lf]; q < trow[lf + 1]; ++q) {
-      const LeafTask T = tasks[q];
-      const BlockDesc B = blocks[T.block];
-      const int cb = cl[4 * B.c];
-      const int rk = ranks[T.block];
-      const int row = T.rowoff + i;
-      for (int t = 0; t < rk; ++t) {
-        const cplx<S>* Ct = cstore + B.c_off + (int64_t)t * B.arows * B.acols + (int64_t)row * B.acols;
-        R sr = R(0), si = R(0);
-        for (int j = 0; j < B.acols; ++j) {
-          const cplx<S> cc = Ct[j];
-          const cplx<R> v = xp[(int64_t)(cb + j) * nsys + l];
-          cadd_mul<R>(sr, si, (R)cc.re, (R)cc.im, v.re, v.im);
-        }
-        const cf64 dv = dvec[B.d_off + (int64_t)t * dstride + l0 + l];
-        cadd_mul<R>(re, im, (R)dv.re, (R)dv.im, sr, si);
-      }
-    }
     cplx<R> o;
     o.re = re;
     o.im = im;
@@ -219,6 +163,155 @@ size_t h2_apply_scratch_bytes(const H2Operator& h, int nsys) {
 }
 size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
   return sizeof(cf64) * h.perm.size() * (size_t)nsys;
+}
+
+// ------------------------------------------------------------------
+// Block-rank products on the matrix cores: for every output row tile
+// (16 rows) and its task list,
+//   out[row, l] (+)= sum_tasks sum_t d_t[l] sum_j C_t[row, j] x[x_row0 + j, l],
+// the contraction of the MACA slices C_t with the cluster vectors, scaled by
+// the frequency fibres d_t (eq. lrfinal).  One wave owns NF tiles of 16
+// frequencies; each rank term is a complex 16 x acols x 16 product done as
+// four real MFMA chains (re re, im im, re im, im re), then scaled by d_t[l]
+// and accumulated.  Columns are taken 64 at a time so the input block stays
+// in registers across the rank terms.
+namespace {
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = mf4;
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in element v of lane L
+  static __device__ __forceinline__ int row(int L, int v) { return 4 * (L >> 4) + v; }
+};
+template <> struct Mfma<double> {
+  using acc = md4;
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int L, int v) { return (L >> 4) + 4 * v; }
+};
+constexpr int kKC = 64;  // columns per register block
+}  // namespace
+
+template <typename R, typename S, int NF, bool kAccum>
+__global__ __launch_bounds__(256) void k_h2_rank_mfma(const RankTile* __restrict__ tiles,
+                                                      const RankTask* __restrict__ tasks,
+                                                      const int* __restrict__ ranks,
+                                                      const cplx<S>* __restrict__ cstore,
+                                                      const cf64* __restrict__ dvec, int dstride,
+                                                      int l0, int nsys,
+                                                      const cplx<R>* __restrict__ x,
+                                                      cplx<R>* __restrict__ out) {
+  using MF = Mfma<R>;
+  using A4 = typename MF::acc;
+  const RankTile tl = tiles[blockIdx.x];
+  const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int fb = (blockIdx.y * 4 + w) * 16 * NF;  // first frequency of this wave
+  if (fb >= nsys) return;                         // no barrier follows
+  const int arow = L & 15, kq = L >> 4, col = L & 15;
+  A4 accr[NF], acci[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) accr[f] = acci[f] = MF::zero();
+  for (int q = tl.t0; q < tl.t1; ++q) {
+    const RankTask T = tasks[q];
+    const int rk = ranks[T.block];
+    for (int j0 = 0; j0 < T.acols; j0 += kKC) {
+      const int nk = min(kKC, T.acols - j0);
+      const int ks = (nk + 3) >> 2;
+      // input block: x[x_row0 + j0 + 4s + kq, fb + 16 f + col]
+      R xr[kKC / 4][NF], xi[kKC / 4][NF];
+#pragma unroll
+      for (int s = 0; s < kKC / 4; ++s)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          xr[s][f] = R(0);
+          xi[s][f] = R(0);
+          const int j = 4 * s + kq, l = fb + 16 * f + col;
+          if (s < ks && j < nk && l < nsys) {
+            const cplx<R> v = x[(int64_t)(T.x_row0 + j0 + j) * nsys + l];
+            xr[s][f] = v.re;
+            xi[s][f] = v.im;
+          }
+        }
+      for (int t = 0; t < rk; ++t) {
+        const cplx<S>* Ct = cstore + T.c_off + (int64_t)t * T.cstride + (int64_t)arow * T.ldc + j0;
+        A4 p1[NF], p2[NF], p3[NF], p4[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) p1[f] = p2[f] = p3[f] = p4[f] = MF::zero();
+#pragma unroll
+        for (int s = 0; s < kKC / 4; ++s) {
+          if (s < ks) {
+            const int j = 4 * s + kq;
+            R ar = R(0), ai = R(0);
+            if (arow < tl.nrows && j < nk) {
+              const cplx<S> c = Ct[j];
+              ar = (R)c.re;
+              ai = (R)c.im;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+              p1[f] = MF::mac(ar, xr[s][f], p1[f]);
+              p2[f] = MF::mac(ai, xi[s][f], p2[f]);
+              p3[f] = MF::mac(ar, xi[s][f], p3[f]);
+              p4[f] = MF::mac(ai, xr[s][f], p4[f]);
+            }
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int l = fb + 16 * f + col;
+          R dr = R(0), di = R(0);
+          if (l < nsys) {
+            const cf64 d = dvec[T.d_off + (int64_t)t * dstride + l0 + l];
+            dr = (R)d.re;
+            di = (R)d.im;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const R zr = p1[f][v] - p2[f][v], zi = p3[f][v] + p4[f][v];
+            accr[f][v] += dr * zr - di * zi;
+            acci[f][v] += dr * zi + di * zr;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = MF::row(L, v), l = fb + 16 * f + col;
+      if (i < tl.nrows && l < nsys) {
+        cplx<R>* o = out + (int64_t)(tl.out_row0 + i) * nsys + l;
+        cplx<R> r;
+        r.re = accr[f][v];
+        r.im = acci[f][v];
+        if (kAccum) {
+          const cplx<R> e = *o;
+          r.re += e.re;
+          r.im += e.im;
+        }
+        *o = r;
+      }
+    }
+}
+
+template <typename R, typename S, bool kAccum>
+static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* tasks,
+                             const int* ranks, const void* cstore, const cf64* dvec, int dstride,
+                             int l0, int nsys, const cplx<R>* x, cplx<R>* out, hipStream_t s) {
+  if (ntiles <= 0) return;
+  constexpr int NF = sizeof(R) == 4 ? 2 : 1;
+  const dim3 grid(ntiles, (nsys + 64 * NF - 1) / (64 * NF));
+  hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(256), 0, s, tiles, tasks, ranks,
+                     (const cplx<S>*)cstore, dvec, dstride, l0, nsys, x, out);
+  CQM_HIP(hipGetLastError());
 }
 
 template <typename R>
@@ -254,15 +347,13 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
                          h.cl_d + 4 * (int)h.cl.size(), h.E_d, P, nsys, xh);
     CQM_HIP(hipGetLastError());
   }
-  // 2. couplings (all clusters; those without core blocks get zero)
-  const int ncl = (int)h.cl.size();
+  // 2. couplings: every cluster's coefficient rows (zero where no core block)
   if (h.store_fp64)
-    hipLaunchKernelGGL((k_h2_couple<R, double>), dim3(ncl, nch), dim3(kHB), 0, s, h.core_rowptr_d, h.core_list_d,
-                       h.blocks_d, h.ranks_d, (const cf64*)h.cstore_d, h.dvec_d, dstride, l0, P, nsys, xh, yh);
+    launch_rank_mfma<R, double, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
+                                       h.cstore_d, h.dvec_d, dstride, l0, nsys, xh, yh, s);
   else
-    hipLaunchKernelGGL((k_h2_couple<R, float>), dim3(ncl, nch), dim3(kHB), 0, s, h.core_rowptr_d, h.core_list_d,
-                       h.blocks_d, h.ranks_d, (const cf32*)h.cstore_d, h.dvec_d, dstride, l0, P, nsys, xh, yh);
-  CQM_HIP(hipGetLastError());
+    launch_rank_mfma<R, float, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
+                                      h.cstore_d, h.dvec_d, dstride, l0, nsys, xh, yh, s);
   // 3. downward pass
   for (int lv = 1; lv < h.nlevels; ++lv) {
     const int cnt = h.level_off[lv + 1] - h.level_off[lv];
@@ -274,28 +365,21 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
                          h.E_d, P, nsys, yh);
     CQM_HIP(hipGetLastError());
   }
-  // 4. leaves
+  // 4. leaves: y_r = U_r yhat_r, then the expanded-far and near blocks
   const int* lvs = h.level_cl_d + h.level_off[h.nlevels];
-  if (h.store_fp64) {
-    if (f32)
-      hipLaunchKernelGGL((k_h2_leaf_out<R, double, float>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs, h.perm_d, h.U32_d,
-                         h.uleaf_off_d, P, nsys, yh, h.task_rowptr_d, h.tasks_d, h.blocks_d, h.ranks_d,
-                         (const cf64*)h.cstore_d, h.dvec_d, dstride, l0, xp, yp);
-    else
-      hipLaunchKernelGGL((k_h2_leaf_out<R, double, double>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs, h.perm_d, h.U_d,
-                         h.uleaf_off_d, P, nsys, yh, h.task_rowptr_d, h.tasks_d, h.blocks_d, h.ranks_d,
-                         (const cf64*)h.cstore_d, h.dvec_d, dstride, l0, xp, yp);
-  } else {
-    if (f32)
-      hipLaunchKernelGGL((k_h2_leaf_out<R, float, float>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs, h.perm_d, h.U32_d,
-                         h.uleaf_off_d, P, nsys, yh, h.task_rowptr_d, h.tasks_d, h.blocks_d, h.ranks_d,
-                         (const cf32*)h.cstore_d, h.dvec_d, dstride, l0, xp, yp);
-    else
-      hipLaunchKernelGGL((k_h2_leaf_out<R, float, double>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs, h.perm_d, h.U_d,
-                         h.uleaf_off_d, P, nsys, yh, h.task_rowptr_d, h.tasks_d, h.blocks_d, h.ranks_d,
-                         (const cf32*)h.cstore_d, h.dvec_d, dstride, l0, xp, yp);
-  }
+  if (f32)
+    hipLaunchKernelGGL((k_h2_leaf_out<R, float>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs,
+                       h.U32_d, h.uleaf_off_d, P, nsys, yh, yp);
+  else
+    hipLaunchKernelGGL((k_h2_leaf_out<R, double>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, lvs,
+                       h.U_d, h.uleaf_off_d, P, nsys, yh, yp);
   CQM_HIP(hipGetLastError());
+  if (h.store_fp64)
+    launch_rank_mfma<R, double, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
+                                      h.cstore_d, h.dvec_d, dstride, l0, nsys, xp, yp, s);
+  else
+    launch_rank_mfma<R, float, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
+                                     h.cstore_d, h.dvec_d, dstride, l0, nsys, xp, yp, s);
   hipLaunchKernelGGL((k_h2_scatter<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, yp, y, ys);
   CQM_HIP(hipGetLastError());
 }
