@@ -173,7 +173,7 @@ size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
 // the frequency fibres d_t (eq. lrfinal).  One wave owns NF tiles of 16
 // frequencies; each rank term is a complex 16 x acols x 16 product done as
 // four real MFMA chains (re re, im im, re im, im re), then scaled by d_t[l]
-// and accumulated.  Columns are taken 64 at a time so the input block stays
+// and accumulated.  Columns are taken 32 at a time so the input block stays
 // in registers across the rank terms.
 namespace {
 typedef float mf4 __attribute__((ext_vector_type(4)));
@@ -196,7 +196,7 @@ template <> struct Mfma<double> {
   }
   static __device__ __forceinline__ int row(int L, int v) { return (L >> 4) + 4 * v; }
 };
-constexpr int kKC = 64;  // columns per register block
+constexpr int kKC = 32;  // columns per register block
 }  // namespace
 
 template <typename R, typename S, int NF, bool kAccum>
@@ -224,60 +224,71 @@ __global__ __launch_bounds__(256) void k_h2_rank_mfma(const RankTile* __restrict
     for (int j0 = 0; j0 < T.acols; j0 += kKC) {
       const int nk = min(kKC, T.acols - j0);
       const int ks = (nk + 3) >> 2;
-      // input block: x[x_row0 + j0 + 4s + kq, fb + 16 f + col]
+      // input block: x[x_row0 + j0 + 4s + kq, fb + 16 f + col].  Loads use
+      // clamped (in-bounds) indices and are masked afterwards, so that they
+      // are all in flight together instead of one branch at a time.
       R xr[kKC / 4][NF], xi[kKC / 4][NF];
 #pragma unroll
       for (int s = 0; s < kKC / 4; ++s)
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-          xr[s][f] = R(0);
-          xi[s][f] = R(0);
           const int j = 4 * s + kq, l = fb + 16 * f + col;
-          if (s < ks && j < nk && l < nsys) {
-            const cplx<R> v = x[(int64_t)(T.x_row0 + j0 + j) * nsys + l];
-            xr[s][f] = v.re;
-            xi[s][f] = v.im;
-          }
+          const bool in = j < nk && l < nsys;
+          const cplx<R> v =
+              x[(int64_t)(T.x_row0 + j0 + min(j, nk - 1)) * nsys + min(l, nsys - 1)];
+          xr[s][f] = in ? v.re : R(0);
+          xi[s][f] = in ? v.im : R(0);
         }
+      // slice entries of rank term t, loaded one term ahead of their use
+      const bool rowin = arow < tl.nrows;
+      const cplx<S>* C0 = cstore + T.c_off + (int64_t)min(arow, tl.nrows - 1) * T.ldc + j0;
+      R ar[kKC / 4], ai[kKC / 4];
+      auto load_a = [&](int t, R* re, R* im) {
+        const cplx<S>* Cr = C0 + (int64_t)min(t, max(rk - 1, 0)) * T.cstride;
+#pragma unroll
+        for (int s = 0; s < kKC / 4; ++s) {
+          const int j = 4 * s + kq;
+          const bool in = rowin && j < nk;
+          const cplx<S> c = Cr[min(j, nk - 1)];
+          re[s] = in ? (R)c.re : R(0);
+          im[s] = in ? (R)c.im : R(0);
+        }
+      };
+      load_a(0, ar, ai);
       for (int t = 0; t < rk; ++t) {
-        const cplx<S>* Ct = cstore + T.c_off + (int64_t)t * T.cstride + (int64_t)arow * T.ldc + j0;
+        R br[kKC / 4], bi[kKC / 4];
+        load_a(t + 1, br, bi);
         A4 p1[NF], p2[NF], p3[NF], p4[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) p1[f] = p2[f] = p3[f] = p4[f] = MF::zero();
 #pragma unroll
         for (int s = 0; s < kKC / 4; ++s) {
           if (s < ks) {
-            const int j = 4 * s + kq;
-            R ar = R(0), ai = R(0);
-            if (arow < tl.nrows && j < nk) {
-              const cplx<S> c = Ct[j];
-              ar = (R)c.re;
-              ai = (R)c.im;
-            }
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-              p1[f] = MF::mac(ar, xr[s][f], p1[f]);
-              p2[f] = MF::mac(ai, xi[s][f], p2[f]);
-              p3[f] = MF::mac(ar, xi[s][f], p3[f]);
-              p4[f] = MF::mac(ai, xr[s][f], p4[f]);
+              p1[f] = MF::mac(ar[s], xr[s][f], p1[f]);
+              p2[f] = MF::mac(ai[s], xi[s][f], p2[f]);
+              p3[f] = MF::mac(ar[s], xi[s][f], p3[f]);
+              p4[f] = MF::mac(ai[s], xr[s][f], p4[f]);
             }
           }
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const int l = fb + 16 * f + col;
-          R dr = R(0), di = R(0);
-          if (l < nsys) {
-            const cf64 d = dvec[T.d_off + (int64_t)t * dstride + l0 + l];
-            dr = (R)d.re;
-            di = (R)d.im;
-          }
+          const cf64 d = dvec[T.d_off + (int64_t)t * dstride + l0 + min(l, nsys - 1)];
+          const R dr = l < nsys ? (R)d.re : R(0), di = l < nsys ? (R)d.im : R(0);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const R zr = p1[f][v] - p2[f][v], zi = p3[f][v] + p4[f][v];
             accr[f][v] += dr * zr - di * zi;
             acci[f][v] += dr * zi + di * zr;
           }
+        }
+#pragma unroll
+        for (int s = 0; s < kKC / 4; ++s) {
+          ar[s] = br[s];
+          ai[s] = bi[s];
         }
       }
     }
@@ -307,7 +318,7 @@ static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* 
                              const int* ranks, const void* cstore, const cf64* dvec, int dstride,
                              int l0, int nsys, const cplx<R>* x, cplx<R>* out, hipStream_t s) {
   if (ntiles <= 0) return;
-  constexpr int NF = sizeof(R) == 4 ? 2 : 1;
+  constexpr int NF = 1;
   const dim3 grid(ntiles, (nsys + 64 * NF - 1) / (64 * NF));
   hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(256), 0, s, tiles, tasks, ranks,
                      (const cplx<S>*)cstore, dvec, dstride, l0, nsys, x, out);
