@@ -182,6 +182,51 @@ def cpu_baseline(wl, sample_freqs=2):
                       f"x{H}", "seconds_per_solve": t_solve}
 
 
+def run_compressed(C, torch, ctx):
+    """The paper's compressed form (H2 in space x MACA across frequencies,
+    cluster leaves 32, eta 1, Chebyshev m = 4, eps 1e-6, full band) on the
+    5120-triangle sphere, N = 128, T = 6, against the stored dense form (FP64
+    refined to 1e-15, itself within 1e-8 of the oracle at the sizes the oracle
+    reaches) and the matrix-free plain form."""
+    from paper_2006_05186_amd.solver import Problem
+    wl = W.C3
+    V, T = wl.mesh()
+    area = area_of(V, T)
+    res = {}
+    ref = None
+    for name, mode, form in (("dense_mixed", C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE),
+                             ("compressed_mixed", C.CQM_MIXED_H2ACA, C.CQM_FORM_DENSE),
+                             ("matrix_free_mixed", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE)):
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form)
+        p.set_plane_wave()
+        p.solve()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q, rc, d = p.solve()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        qn = q.cpu().numpy()
+        r = {"seconds_per_solve": el, "rc": rc, "iters": d.total_iters, "cycles": d.cycles,
+             "t_setup_ms": d.t_setup_ms, "operator_GB": d.operator_bytes / 1e9}
+        if mode == C.CQM_MIXED_H2ACA:
+            r |= {"max_rank": d.max_rank, "mean_rank": d.mean_rank, "far_blocks": d.n_far_blocks,
+                  "near_blocks": d.n_near_blocks}
+        if ref is None:
+            ref = qn
+        else:
+            r["error_vs_dense"] = rel_err(qn, ref, area)
+            num = np.sqrt(np.sum(area[None, :] * (qn - ref) ** 2, axis=1))
+            den = np.sqrt(np.sum(area[None, :] * ref ** 2, axis=1))
+            r["max_step_error_vs_dense"] = float(np.max(num / np.maximum(den, 1e-300)))
+        res[name] = r
+        p.close()
+    res["compressed_speedup_vs_dense"] = (res["dense_mixed"]["seconds_per_solve"] /
+                                          res["compressed_mixed"]["seconds_per_solve"])
+    res["compressed_speedup_vs_matrix_free"] = (res["matrix_free_mixed"]["seconds_per_solve"] /
+                                                res["compressed_mixed"]["seconds_per_solve"])
+    return {"workload": wl.name} | res
+
+
 def run_batch48(C, torch, ctx):
     """Uneven batch: 48 seeded problems (spheres/ellipsoids of 80..5120
     triangles, N in {16,32,64,128}, random direction and pulse width) solved
@@ -365,6 +410,7 @@ def main():
         p.close()
         out["variants"] = var
     if not args.no_variants:
+        out["compressed"] = run_compressed(C, torch, ctx)
         out["batch48"] = run_batch48(C, torch, ctx)
         out["serving"] = run_serving(C, torch, ctx, rate=args.serve_rate, duration=args.serve_seconds)
     C.cqm_ctx_destroy(ctx)

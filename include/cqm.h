@@ -91,7 +91,11 @@ typedef struct cqm_options {
                             on the solve stream (cqm_diag.kernel_ms)  (0)   */
   int32_t arnoldi_layout;/* CQM_ARNOLDI_*: workgroups per system in the
                             Arnoldi step                             (AUTO) */
-  int32_t reserved[5];
+  int32_t autotune;      /* nonzero: time the launch-shape candidates of
+                            the far product and the dense assembly on
+                            their first use per context and problem
+                            shape, keep the fastest (one host wait)  (1)   */
+  int32_t reserved[4];
 } cqm_options;
 
 /* Arnoldi step layouts (cqm_options.arnoldi_layout).  AUTO splits when a
@@ -134,6 +138,9 @@ typedef struct cqm_diag {
                                far-field product (matrix-free form)        */
   double kernel_ms[8];      /* GPU time per CQM_K_* class (profile only)   */
   int32_t kernel_calls[8];  /* launches per CQM_K_* class (profile only)   */
+  int32_t far_tile;         /* frequencies per workgroup of the matrix-free
+                               far product (inner precision) in use       */
+  int32_t far_waves;        /* waves its source split aims for           */
   double kernel_work[8];    /* algorithmic work per CQM_K_* class, counted
                                by the kernels (profile only): FAR32, FAR64
                                and ASSEMBLE in point-pair-frequency kernel

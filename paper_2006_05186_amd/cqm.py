@@ -57,7 +57,8 @@ class cqm_options(ctypes.Structure):
         ("n_min", ctypes.c_int32), ("eta", ctypes.c_double), ("cheb_m", ctypes.c_int32),
         ("eps_aca", ctypes.c_double), ("aca_band", ctypes.c_int32), ("q_duffy", ctypes.c_int32),
         ("reuse_operator", ctypes.c_int32), ("profile", ctypes.c_int32),
-        ("arnoldi_layout", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -71,7 +72,8 @@ class cqm_diag(ctypes.Structure):
         ("max_rank", ctypes.c_int32), ("mean_rank", ctypes.c_double),
         ("n_far_blocks", ctypes.c_int32), ("n_near_blocks", ctypes.c_int32),
         ("far_units", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
-        ("kernel_calls", ctypes.c_int32 * 8), ("kernel_work", ctypes.c_double * 8),
+        ("kernel_calls", ctypes.c_int32 * 8), ("far_tile", ctypes.c_int32),
+        ("far_waves", ctypes.c_int32), ("kernel_work", ctypes.c_double * 8),
         ("reserved", ctypes.c_int32 * 6),
     ]
 

@@ -129,6 +129,7 @@ int cqm_default_options(cqm_options* o) {
   o->aca_band = CQM_BAND_FULL;
   o->q_duffy = 5;
   o->reuse_operator = 0;
+  o->autotune = 1;
   return CQM_OK;
 }
 

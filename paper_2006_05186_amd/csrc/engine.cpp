@@ -141,6 +141,11 @@ void post_solve(SolveState& st, hipStream_t s) {
   dg.imag_ratio = p.full_band() && hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : 0.0;
   dg.n_systems = p.Fsys;
   dg.far_units = p.far_units;
+  if (!mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_MATRIX_FREE) {
+    const FarShape sh = far_shape_of(p, p.Fsys, mode_is_mixed(p.opt.mode) ? 32 : 64);
+    dg.far_tile = sh.ft;
+    dg.far_waves = sh.waves;
+  }
   if (mode_is_h2(p.opt.mode)) h2_stats(p, &dg);
   else if (p.opt.form == CQM_FORM_DENSE)
     dg.operator_bytes = (int64_t)p.Fsys * sym_slice((int)p.M) * (p.lay.dense32 ? 24 : 16);

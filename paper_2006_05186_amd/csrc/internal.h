@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/cqm.h"
@@ -135,10 +137,23 @@ struct EngineBufs {
   size_t status_host_cap = 0;
 };
 
+// Launch shapes picked by timing the candidates on their first use, per
+// device context and problem shape (cqm_options.autotune).
+struct FarShape {
+  int ft = 0;        // frequencies per workgroup
+  int waves = 4096;  // waves the source split aims for
+};
+struct Tuner {
+  std::mutex mu;
+  std::map<uint64_t, FarShape> far;  // (M, systems, precision)
+  std::map<uint64_t, int> assemble;  // (M, systems) -> frequency tile
+};
+
 struct Ctx {
   int device = 0;
   int cus = 256;  // compute units of the device
   EngineBufs eb;
+  Tuner tune;
 };
 
 // Device tables of one mesh (owned by the problem, uploaded at create).
@@ -268,7 +283,8 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
                             const cf64* near_vals, const int* active, hipStream_t s);
 void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
                            hipStream_t s);
-int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product
+int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
+FarShape far_shape_of(const Problem& p, int nsys, int precision);  // shape in use (tuned or default)
 
 // dense products (k_dense.hip)
 template <typename R>

@@ -14,6 +14,8 @@
 // frequencies; per point-pair-frequency the FP32 path issues three
 // transcendentals (v_exp_f32 on a base-2 exponent, v_sin_f32/v_cos_f32 on a
 // phase in revolutions) and five VALU operations.
+#include <algorithm>
+
 #include "device_util.h"
 #include "fp64_math.h"
 
@@ -331,12 +333,12 @@ template <> int pick_ft<double>(int nsys) {
 }
 }  // namespace
 
-// Source split: enough workgroups to fill the chip (about 4096 waves), each
-// source chunk a whole number of LDS tiles.  Returns the number of slots and
+// Source split: enough workgroups to fill the chip (about `waves` waves),
+// each source chunk a whole number of LDS tiles.  Returns the number of slots and
 // the chunk length; both launchers use it so they agree on the slot count.
-int far_splits(int M, int nsys, int FT, int* chunk_out = nullptr) {
+int far_splits(int M, int nsys, int FT, int waves, int* chunk_out = nullptr) {
   const int tiles = ((M + kTgt - 1) / kTgt) * ((nsys + FT - 1) / FT);
-  int S = (4096 + tiles - 1) / tiles;
+  int S = (waves + tiles - 1) / tiles;
   const int maxS = (M + kTs - 1) / kTs;
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
@@ -348,10 +350,11 @@ int far_splits(int M, int nsys, int FT, int* chunk_out = nullptr) {
 
 template <typename R, int FT>
 static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                         cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s) {
+                         cplx<R>* partial, const int* active, unsigned long long* ctr, int waves,
+                         hipStream_t s) {
   const int M = (int)p.M;
   int chunk = 0;
-  const int S = far_splits(M, nsys, FT, &chunk);
+  const int S = far_splits(M, nsys, FT, waves, &chunk);
   dim3 grid((M + kTgt - 1) / kTgt, (nsys + FT - 1) / FT, S);
   const typename Pt4<R>::T* pts;
   const R *ea, *pb;
@@ -369,30 +372,103 @@ static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, i
   CQM_HIP(hipGetLastError());
 }
 
+namespace {
+// Candidate frequency tiles and source-split targets of the far product.
+constexpr int kFt32[5] = {17, 16, 13, 11, 9};
+constexpr int kFt64[3] = {9, 8, 6};
+constexpr int kWaves[3] = {2048, 4096, 8192};
+
 template <typename R>
-void launch_far_apply(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                      cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s) {
-  const int FT = pick_ft<R>(nsys);
+void far_apply_shape(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                     cplx<R>* partial, const int* active, unsigned long long* ctr, FarShape sh,
+                     hipStream_t s) {
   if constexpr (sizeof(R) == 4) {
-    switch (FT) {
-      case 17: far_apply_ft<R, 17>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      case 16: far_apply_ft<R, 16>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      case 13: far_apply_ft<R, 13>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      case 11: far_apply_ft<R, 11>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      default: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+    switch (sh.ft) {
+      case 17: far_apply_ft<R, 17>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      case 16: far_apply_ft<R, 16>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      case 13: far_apply_ft<R, 13>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      case 11: far_apply_ft<R, 11>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      default: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
     }
   } else {
-    switch (FT) {
-      case 9: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      case 8: far_apply_ft<R, 8>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
-      default: far_apply_ft<R, 6>(p, l0, nsys, x, xs, partial, active, ctr, s); break;
+    switch (sh.ft) {
+      case 9: far_apply_ft<R, 9>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      case 8: far_apply_ft<R, 8>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
+      default: far_apply_ft<R, 6>(p, l0, nsys, x, xs, partial, active, ctr, sh.waves, s); break;
     }
   }
 }
 
+uint64_t far_key(int M, int nsys, int precision) {
+  return ((uint64_t)M << 32) ^ ((uint64_t)nsys << 8) ^ (uint64_t)precision;
+}
+
+// Shape of the far product: the tuned one if cached, else (no tuning asked,
+// or tuning not possible here) the heuristic.  With `tune`, every candidate
+// is timed once on the real inputs (after one warm-up launch) and the fastest
+// kept; the candidates write only the partial-sum buffer, which the product
+// that follows overwrites.
+template <typename R>
+FarShape far_shape(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                   cplx<R>* partial, const int* active, bool tune, hipStream_t s) {
+  const int prec = sizeof(R) == 4 ? 32 : 64;
+  const uint64_t key = far_key((int)p.M, nsys, prec);
+  Tuner& tn = p.ctx->tune;
+  {
+    std::lock_guard<std::mutex> g(tn.mu);
+    auto it = tn.far.find(key);
+    if (it != tn.far.end()) return it->second;
+  }
+  FarShape best{pick_ft<R>(nsys), 4096};
+  if (!tune || !p.opt.autotune) return best;
+  hipEvent_t e0, e1;
+  CQM_HIP(hipEventCreate(&e0));
+  CQM_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  const int* fts = sizeof(R) == 4 ? kFt32 : kFt64;
+  const int nft = sizeof(R) == 4 ? 5 : 3;
+  for (int a = 0; a < nft; ++a)
+    for (int w : kWaves) {
+      const FarShape sh{fts[a], w};
+      far_apply_shape<R>(p, l0, nsys, x, xs, partial, active, nullptr, sh, s);
+      CQM_HIP(hipEventRecord(e0, s));
+      far_apply_shape<R>(p, l0, nsys, x, xs, partial, active, nullptr, sh, s);
+      CQM_HIP(hipEventRecord(e1, s));
+      CQM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CQM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) best_ms = ms, best = sh;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(tn.mu);
+  tn.far[key] = best;
+  return best;
+}
+}  // namespace
+
+FarShape far_shape_of(const Problem& p, int nsys, int precision) {
+  Tuner& tn = p.ctx->tune;
+  std::lock_guard<std::mutex> g(tn.mu);
+  auto it = tn.far.find(far_key((int)p.M, nsys, precision));
+  if (it != tn.far.end()) return it->second;
+  return FarShape{precision == 32 ? pick_ft<float>(nsys) : pick_ft<double>(nsys), 4096};
+}
+
+template <typename R>
+void launch_far_apply(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                      cplx<R>* partial, const int* active, unsigned long long* ctr, hipStream_t s) {
+  const FarShape sh = far_shape<R>(p, l0, nsys, x, xs, partial, active, true, s);
+  far_apply_shape<R>(p, l0, nsys, x, xs, partial, active, ctr, sh, s);
+}
+
 int far_partial_slots(int M, int nsys, int precision) {
-  const int FT = precision == 32 ? pick_ft<float>(nsys) : pick_ft<double>(nsys);
-  return far_splits(M, nsys, FT);
+  int S = 1;
+  const int* fts = precision == 32 ? kFt32 : kFt64;
+  const int nft = precision == 32 ? 5 : 3;
+  for (int a = 0; a < nft; ++a)
+    for (int w : kWaves) S = std::max(S, far_splits(M, nsys, fts[a], w));
+  return S;
 }
 
 template <typename R>
@@ -400,8 +476,8 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
                             const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
                             const cf64* near_vals, const int* active, hipStream_t s) {
   const int M = (int)p.M;
-  const int FT = pick_ft<R>(nsys);
-  const int S = far_splits(M, nsys, FT);
+  const FarShape sh = far_shape_of(p, nsys, sizeof(R) == 4 ? 32 : 64);
+  const int S = far_splits(M, nsys, sh.ft, sh.waves);
   dim3 grid((M + 255) / 256, nsys);
   hipLaunchKernelGGL((k_far_reduce_near<R>), grid, dim3(256), 0, s, partial, S, nsys, M, x, xs, y,
                      ys, p.dev.near_rowptr, p.dev.near_col, near_vals, (int64_t)p.col.size(), l0,
@@ -422,16 +498,48 @@ static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, unsigned l
 
 void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
                            hipStream_t s) {
-  // frequency tile with the fewest padding slots (11 | 33, 13 | 65, 9 | 9)
+  auto run = [&](int FT, unsigned long long* c) {
+    if (FT == 13) dense_assemble_ft<13>(p, d64, d32, c, s);
+    else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, c, s);
+    else dense_assemble_ft<9>(p, d64, d32, c, s);
+  };
+  // frequency tile: timed once per (M, systems) when tuning is on (each
+  // candidate writes the same operator), else the one with the fewest
+  // padding slots (11 | 33, 13 | 65, 9 | 9)
   const int opts[3] = {13, 11, 9};
   int FT = 13, waste = 1 << 30;
   for (int f : opts) {
     const int w = ((p.Fsys + f - 1) / f) * f - p.Fsys;
     if (w < waste) waste = w, FT = f;
   }
-  if (FT == 13) dense_assemble_ft<13>(p, d64, d32, ctr, s);
-  else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, ctr, s);
-  else dense_assemble_ft<9>(p, d64, d32, ctr, s);
+  Tuner& tn = p.ctx->tune;
+  const uint64_t key = ((uint64_t)p.M << 32) ^ (uint64_t)p.Fsys;
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> g(tn.mu);
+    auto it = tn.assemble.find(key);
+    if (it != tn.assemble.end()) FT = it->second, cached = true;
+  }
+  if (!cached && p.opt.autotune) {
+    hipEvent_t e0, e1;
+    CQM_HIP(hipEventCreate(&e0));
+    CQM_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int f : opts) {
+      CQM_HIP(hipEventRecord(e0, s));
+      run(f, nullptr);
+      CQM_HIP(hipEventRecord(e1, s));
+      CQM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CQM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) best = ms, FT = f;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> g(tn.mu);
+    tn.assemble[key] = FT;
+  }
+  run(FT, ctr);
 }
 
 template void launch_far_apply<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,

@@ -162,6 +162,34 @@ def test_arnoldi_layouts_match_oracle(ctx, c1, layout, mode):
     p.close()
 
 
+def test_autotuned_shapes_give_the_same_product(ctx, c1):
+    """The far-product launch shape picked by timing (per context and shape)
+    changes only the summation order: the product matches the fixed-shape one
+    and the oracle; the chosen shape is reported."""
+    wl, V, T, r, _ = c1
+    H = O.num_frequencies_half(wl.N + 1)
+    x = torch.as_tensor(W.random_complex((H, len(T)), seed=11), device="cuda")
+    ys = {}
+    for tune in (0, 1):
+        c = C.cqm_ctx_create(0)
+        p = Problem(c, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE,
+                    autotune=tune)
+        ys[tune] = {prec: p.apply(x, 0, prec).cpu().numpy() for prec in (32, 64)}
+        p.set_plane_wave()
+        _, rc, d = p.solve()
+        assert rc == C.CQM_OK
+        assert d.far_tile in (17, 16, 13, 11, 9) and d.far_waves in (2048, 4096, 8192)
+        say(f"  autotune={tune}: far tile {d.far_tile}, waves {d.far_waves}")
+        p.close()
+        C.cqm_ctx_destroy(c)
+    for l in range(H):
+        A = O.assemble_V(V, T, r["s"][l], pairs=r["pairs"], static=r["static"])
+        ref = A @ x.cpu().numpy()[l]
+        for tune in (0, 1):
+            assert np.linalg.norm(ys[tune][64][l] - ref) < 1e-13 * np.linalg.norm(ref)
+            assert np.linalg.norm(ys[tune][32][l] - ref) < 2e-6 * np.linalg.norm(ref)
+
+
 def test_solve_C2_against_stored_oracle(ctx):
     wl = W.C2
     path = os.path.join(GOLDEN, f"{wl.name}.npz")
