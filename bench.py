@@ -294,6 +294,56 @@ def run_serving(C, torch, ctx, rate, duration):
             "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"]}
 
 
+def run_serving_mix(C, torch, ctx, rate, duration, large_frac=0.2):
+    """Poisson stream mixing sphere5120_N128_T6 requests with a fraction of
+    sphere20480_N256_T6 ones.  The large lane is on: requests whose stored
+    dense operator would exceed a quarter of the budget (the 20480-triangle
+    ones) are solved in the compressed form on a second stream; the others in
+    the dense mixed form.  Operators cached; latency per class."""
+    from paper_2006_05186_amd.solver import Server
+    small, large = W.C3, W.C5_LARGE
+    meshes = {small.name: small.mesh(), large.name: large.mesh()}
+    arrivals = W.poisson_arrivals(rate, duration)
+    rng = np.random.default_rng(W.DEFAULT_SEED + 2)
+    kinds = [large if rng.uniform() < large_frac else small for _ in arrivals]
+    srv = Server(ctx, 200 << 30, max_active=16, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                 large_lane=1)
+    tickets = []
+    t0 = time.perf_counter()
+    for a, wl in zip(arrivals, kinds):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        V, T = meshes[wl.name]
+        sigma = float(rng.uniform(0.2, 0.4))
+        tickets.append((srv.submit(V, T, wl.N, wl.T, W.random_direction(rng), sigma, 1.0 + 2 * sigma),
+                        wl.name))
+    lat, rcs = {}, []
+    while len(lat) < len(tickets):
+        for t, name in tickets:
+            if t not in lat:
+                done, rc, _, d, l = srv.poll(t)
+                if done:
+                    lat[t] = (l, name)
+                    rcs.append(rc)
+        time.sleep(0.005)
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    out = {"rate_per_s": rate, "duration_s": duration, "requests": len(tickets),
+           "large_fraction": large_frac, "makespan_s": el, "solves_per_s": len(tickets) / el,
+           "all_ok": all(r == C.CQM_OK for r in rcs), "lane_completed": st["lane_completed"],
+           "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"]}
+    for name in (small.name, large.name):
+        L = np.asarray([l for l, n in lat.values() if n == name])
+        if len(L):
+            out[name] = {"count": int(len(L)), "p50_ms": float(np.percentile(L, 50)),
+                         "p99_ms": float(np.percentile(L, 99)), "max_ms": float(L.max())}
+    L = np.asarray([l for l, _ in lat.values()])
+    out |= {"p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +354,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-mix", type=float, default=0.0, metavar="RATE",
+                    help="only run the mixed serving stream (5120- and 20% 20480-triangle "
+                         "requests) at RATE requests/s for --serve-seconds and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -330,6 +383,11 @@ def main():
         return
     wl = WORKLOADS[args.workload]
     ctx = C.cqm_ctx_create(0)
+    if args.serve_mix > 0:
+        mix = run_serving_mix(C, torch, ctx, args.serve_mix, args.serve_seconds)
+        C.cqm_ctx_destroy(ctx)
+        print(json.dumps({"serving_mix": mix}), flush=True)
+        return
     main_mode, main_form = C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE
     r = run_variant(C, Problem, ctx, wl, main_mode, main_form, args.steps, args.warmup, torch)
     K = args.steps

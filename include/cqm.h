@@ -232,9 +232,14 @@ int cqm_operator_stats(cqm_problem_t p, cqm_diag* out);
  * request that can never fit is rejected with CQM_ENOMEM.  Requests with the
  * same mesh, N and T share one operator (operator cache). */
 typedef struct cqm_server_opts {
-  int32_t max_active;      /* requests advanced together                 (16) */
+  int32_t max_active;      /* requests advanced together per lane        (16) */
   int32_t cache_operators; /* share operators of identical mesh, N, T     (1) */
-  int32_t reserved[6];
+  int32_t large_lane;      /* nonzero: requests whose stored dense operator
+                              (plain form) would exceed large_bytes are
+                              solved in the compressed form (H2 x MACA) by a
+                              second worker on its own stream             (0) */
+  int32_t reserved[5];
+  int64_t large_bytes;     /* size limit of the above; <= 0: budget / 4   (0) */
   cqm_options solver;      /* options of every request (mode, form, tolerances) */
 } cqm_server_opts;
 
@@ -252,7 +257,8 @@ typedef struct cqm_request {
 typedef struct cqm_server_stats {
   int64_t submitted, completed, rejected, active, queued, peak_active;
   int64_t arena_bytes, peak_arena_bytes, operators_built, operator_cache_hits, cycles;
-  int64_t reserved[5];
+  int64_t lane_completed[2]; /* completed requests per lane (1: large)    */
+  int64_t reserved[3];
 } cqm_server_stats_t;
 
 /* Default server options (host). */

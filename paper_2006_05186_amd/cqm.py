@@ -87,7 +87,8 @@ class cqm_diag(ctypes.Structure):
 
 class cqm_server_opts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("cache_operators", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6), ("solver", cqm_options)]
+                ("large_lane", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("large_bytes", ctypes.c_int64), ("solver", cqm_options)]
 
 
 class cqm_request(ctypes.Structure):
@@ -101,10 +102,12 @@ class cqm_server_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "completed", "rejected", "active", "queued", "peak_active", "arena_bytes",
         "peak_arena_bytes", "operators_built", "operator_cache_hits", "cycles")] + \
-        [("reserved", ctypes.c_int64 * 5)]
+        [("lane_completed", ctypes.c_int64 * 2), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        out["lane_completed"] = list(self.lane_completed)
+        return out
 
 
 _lib = None
@@ -297,7 +300,7 @@ def cqm_server_default_options(**solver):
     o = cqm_server_opts()
     _check(load_library().cqm_server_default_options(ctypes.byref(o)))
     for k, v in solver.items():
-        if k in ("max_active", "cache_operators"):
+        if k in ("max_active", "cache_operators", "large_lane", "large_bytes"):
             setattr(o, k, v)
         else:
             setattr(o.solver, k, v)

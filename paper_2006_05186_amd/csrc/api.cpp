@@ -154,13 +154,7 @@ int cqm_ctx_create(int device, cqm_ctx_t* out) {
 int cqm_ctx_destroy(cqm_ctx_t ctx) {
   if (!ctx) return CQM_OK;
   (void)hipSetDevice(ctx->device);
-  if (ctx->eb.desc) (void)hipFree(ctx->eb.desc);
-  if (ctx->eb.open_cycle) (void)hipFree(ctx->eb.open_cycle);
-  if (ctx->eb.open_step) (void)hipFree(ctx->eb.open_step);
-  if (ctx->eb.staging) (void)hipHostFree(ctx->eb.staging);
-  if (ctx->eb.groups) (void)hipFree(ctx->eb.groups);
-  if (ctx->eb.status) (void)hipFree(ctx->eb.status);
-  if (ctx->eb.status_host) (void)hipHostFree(ctx->eb.status_host);
+  release_engine_bufs(ctx->eb);
   delete ctx;
   return CQM_OK;
 }

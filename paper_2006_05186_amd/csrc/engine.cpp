@@ -235,34 +235,45 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   // would leave most compute units idle
   const int lay = S_[0]->p->opt.arnoldi_layout;
   split_ = lay == CQM_ARNOLDI_SPLIT || (lay == CQM_ARNOLDI_AUTO && n < kSplitBelow);
-  ensure(ctx.eb.desc, ctx.eb.desc_cap, hd_.size());
-  ensure(ctx.eb.open_cycle, ctx.eb.cycle_cap, std::max<size_t>(1, lite_.size()));
-  ensure(ctx.eb.open_step, ctx.eb.step_cap, std::max<size_t>(1, lite_.size()));
-  if (ctx.eb.staging_cap < 2 * lite_.size()) {
-    if (ctx.eb.staging) {
+  ensure(eb.desc, eb.desc_cap, hd_.size());
+  ensure(eb.open_cycle, eb.cycle_cap, std::max<size_t>(1, lite_.size()));
+  ensure(eb.open_step, eb.step_cap, std::max<size_t>(1, lite_.size()));
+  if (eb.staging_cap < 2 * lite_.size()) {
+    if (eb.staging) {
       CQM_HIP(hipStreamSynchronize(s));
-      CQM_HIP(hipHostFree(ctx.eb.staging));
+      CQM_HIP(hipHostFree(eb.staging));
     }
-    ctx.eb.staging = nullptr;
-    ctx.eb.staging_cap = 0;
+    eb.staging = nullptr;
+    eb.staging_cap = 0;
     const size_t c = std::max<size_t>(2 * lite_.size(), 256);
-    CQM_HIP(hipHostMalloc((void**)&ctx.eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
-    ctx.eb.staging_cap = c;
+    CQM_HIP(hipHostMalloc((void**)&eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
+    eb.staging_cap = c;
   }
-  ensure(ctx.eb.status, ctx.eb.status_cap, (size_t)kSysiStride * n);
-  if (ctx.eb.status_host_cap < (size_t)kSysiStride * n) {
-    if (ctx.eb.status_host) {
+  ensure(eb.status, eb.status_cap, (size_t)kSysiStride * n);
+  if (eb.status_host_cap < (size_t)kSysiStride * n) {
+    if (eb.status_host) {
       CQM_HIP(hipStreamSynchronize(s));
-      CQM_HIP(hipHostFree(ctx.eb.status_host));
+      CQM_HIP(hipHostFree(eb.status_host));
     }
-    ctx.eb.status_host = nullptr;
-    ctx.eb.status_host_cap = 0;
+    eb.status_host = nullptr;
+    eb.status_host_cap = 0;
     const size_t c = std::max<size_t>((size_t)kSysiStride * n, 1024);
-    CQM_HIP(hipHostMalloc((void**)&ctx.eb.status_host, sizeof(int) * c, hipHostMallocDefault));
-    ctx.eb.status_host_cap = c;
+    CQM_HIP(hipHostMalloc((void**)&eb.status_host, sizeof(int) * c, hipHostMallocDefault));
+    eb.status_host_cap = c;
   }
-  CQM_HIP(hipMemcpyAsync(ctx.eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
+  CQM_HIP(hipMemcpyAsync(eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
   flags_.assign((size_t)kSysiStride * n, 0);
+}
+
+void release_engine_bufs(EngineBufs& b) {
+  if (b.desc) (void)hipFree(b.desc);
+  if (b.groups) (void)hipFree(b.groups);
+  if (b.status) (void)hipFree(b.status);
+  if (b.status_host) (void)hipHostFree(b.status_host);
+  if (b.open_cycle) (void)hipFree(b.open_cycle);
+  if (b.open_step) (void)hipFree(b.open_step);
+  if (b.staging) (void)hipHostFree(b.staging);
+  b = EngineBufs{};
 }
 
 Engine::~Engine() {
@@ -272,28 +283,28 @@ Engine::~Engine() {
 void Engine::snapshot(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!snap_ev_) CQM_HIP(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
-  launch_gather_status(ctx.eb.desc, n, ctx.eb.status, s);
-  CQM_HIP(hipMemcpyAsync(ctx.eb.status_host, ctx.eb.status, sizeof(int) * flags_.size(),
+  launch_gather_status(eb.desc, n, eb.status, s);
+  CQM_HIP(hipMemcpyAsync(eb.status_host, eb.status, sizeof(int) * flags_.size(),
                          hipMemcpyDeviceToHost, s));
   CQM_HIP(hipEventRecord(snap_ev_, s));
 }
 
 void Engine::read_snapshot() {
   CQM_HIP(hipEventSynchronize(snap_ev_));
-  std::copy(ctx.eb.status_host, ctx.eb.status_host + flags_.size(), flags_.begin());
+  std::copy(eb.status_host, eb.status_host + flags_.size(), flags_.begin());
 }
 
 void Engine::init(int k, hipStream_t s) {
   SolveState* st = S_[k];
   Timed t(*S_[0]->p, CQM_K_OTHER, s);
-  launch_gmres_init(ctx.eb.desc + st->first, st->p->Fsys, s);
+  launch_gmres_init(eb.desc + st->first, st->p->Fsys, s);
 }
 
 void Engine::status(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!n) return;
-  launch_gather_status(ctx.eb.desc, n, ctx.eb.status, s);
-  CQM_HIP(hipMemcpyAsync(flags_.data(), ctx.eb.status, sizeof(int) * flags_.size(), hipMemcpyDeviceToHost, s));
+  launch_gather_status(eb.desc, n, eb.status, s);
+  CQM_HIP(hipMemcpyAsync(flags_.data(), eb.status, sizeof(int) * flags_.size(), hipMemcpyDeviceToHost, s));
   CQM_HIP(hipStreamSynchronize(s));
 }
 
@@ -314,7 +325,7 @@ void Engine::upload_open(int which, GroupLite* dst, size_t stage, std::vector<GC
   }
   std::stable_sort(open.begin(), open.end(),
                    [&](int a, int b) { return lite_[a].M < lite_[b].M; });
-  GroupLite* st = ctx.eb.staging + stage;
+  GroupLite* st = eb.staging + stage;
   for (size_t k = 0; k < open.size(); ++k) {
     const GroupLite& g = lite_[open[k]];
     st[k] = g;
@@ -332,7 +343,7 @@ void Engine::dense_product(const GroupLite* list, const std::vector<GClass>& cls
   for (const GClass& c : cls)
     launch_dense_gemv_groups<R>(list + c.off, c.count, c.M, c.grouped, which, j, ctr, s);
   if (reduce && !cls.empty())
-    launch_dense_reduce_desc<R>(ctx.eb.desc, (int)hd_.size(), maxM_, which, j, s);
+    launch_dense_reduce_desc<R>(eb.desc, (int)hd_.size(), maxM_, which, j, s);
 }
 
 bool Engine::state_done(int k) const {
@@ -351,7 +362,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!n) return 0;
   Problem& p0 = *S_[0]->p;
-  const SysDesc* sd = ctx.eb.desc;
+  const SysDesc* sd = eb.desc;
   const double outer_tol = p0.opt.outer_tol;
   const double inner_tol = sizeof(R) == 4 ? std::max(p0.opt.inner_tol, 2e-7) : p0.opt.inner_tol;
   auto count = [&](int which) {
@@ -368,8 +379,8 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   if (open == 0) return 0;
   // systems open now are the ones whose cycle runs (and whose residual is
   // formed at its end)
-  upload_open(0, ctx.eb.open_cycle, 0, cyc_cls_, s);
-  const GroupLite* step_list = ctx.eb.open_cycle;
+  upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
+  const GroupLite* step_list = eb.open_cycle;
   step_cls_ = cyc_cls_;
   int snap_j = -1;  // step behind which a status snapshot is pending
   for (int j = 0; j < m_; ++j) {
@@ -400,8 +411,8 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
       for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + 1] != 0;
       if (c == 0) break;
       // drop the groups whose cycles had closed by then
-      upload_open(1, ctx.eb.open_step, lite_.size(), step_cls_, s);
-      step_list = ctx.eb.open_step;
+      upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
+      step_list = eb.open_step;
     }
     if ((j + 1) % 6 == 0 && j + 4 < m_ && snap_j < 0) {
       snapshot(s);
@@ -415,7 +426,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start
     Timed t(p0, CQM_K_GEMV64, s);
-    dense_product<double>(ctx.eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
+    dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -443,7 +454,7 @@ template int Engine::cycle_t<double>(hipStream_t);
 void Engine::finish_diag(int k, hipStream_t s) {
   SolveState* st = S_[k];
   Problem& p = *st->p;
-  const SysDesc* sd = ctx.eb.desc + st->first;
+  const SysDesc* sd = eb.desc + st->first;
   const double outer_tol = p.opt.outer_tol;
   if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
   else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);

@@ -336,7 +336,8 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s);  // full solves, 
 // precision): used by the batch solve and by the serving loop.
 class Engine {
  public:
-  explicit Engine(Ctx& c) : ctx(c) {}
+  explicit Engine(Ctx& c) : ctx(c), eb(c.eb) {}
+  Engine(Ctx& c, EngineBufs& b) : ctx(c), eb(b) {}  // own descriptor/status buffers
   ~Engine();
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
@@ -351,6 +352,7 @@ class Engine {
  private:
   template <typename R> int cycle_t(hipStream_t s);
   Ctx& ctx;
+  EngineBufs& eb;
   std::vector<SolveState*> S_;
   std::vector<SysDesc> hd_;
   std::vector<GroupLite> lite_;   // one record per stored-operator group
@@ -378,6 +380,8 @@ class Engine {
   void snapshot(hipStream_t s);
   void read_snapshot();
 };
+
+void release_engine_bufs(EngineBufs& b);
 
 // RAII helper: times the launches issued in its scope as one class.
 struct Timed {

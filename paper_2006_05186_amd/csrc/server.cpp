@@ -1,10 +1,14 @@
 // Serving loop: continuous batching of solve requests on one GPU.
 //
-// A worker thread owns a HIP stream and an arena (one allocation of the HBM
-// budget, first-fit free list).  At every GMRES restart-cycle boundary it
-// retires finished requests (inverse transform, copy to host, free state) and
-// admits queued ones whose state -- and operator, unless cached -- fits the
-// arena; then it runs one cycle of the engine over every admitted request.
+// The server owns an arena (one allocation of the HBM budget, first-fit free
+// list) shared by its lanes.  A lane is a worker thread with its own HIP
+// stream: at every GMRES restart-cycle boundary it retires finished requests
+// (inverse transform, copy to host, free state) and admits queued ones whose
+// state -- and operator, unless cached -- fits the arena; then it runs one
+// cycle of its engine over every admitted request.  With the large lane on,
+// requests whose stored dense operator would exceed a size limit are solved
+// in the compressed form on a second lane, so their work overlaps the other
+// lane's on the device.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -92,6 +96,7 @@ struct Request {
   SolveState st;
   size_t off = 0, bytes = 0;
   int cycles = 0;
+  int lane = 0;  // 1: large request, compressed form on the second lane
 };
 
 uint64_t fnv(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
@@ -102,39 +107,63 @@ uint64_t fnv(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
 }  // namespace
 
 struct cqm_server_s {
+  // One lane: a worker thread with its own stream, engine buffers, queue and
+  // active set.  Lane 0 serves ordinary requests; lane 1 (optional) the large
+  // ones, in the compressed form, so that their long cycles run beside
+  // lane 0's work instead of holding it back.
+  struct Lane {
+    int id = 0;
+    hipStream_t stream = nullptr;
+    EngineBufs eb;
+    std::deque<Request*> queue;    // guarded by mu
+    std::vector<Request*> active;  // owned by the lane's worker
+    std::thread worker;
+  };
+
   cqm_ctx_t ctx = nullptr;
   cqm_server_opts opts{};
-  hipStream_t stream = nullptr;
   char* arena_mem = nullptr;
-  Arena arena;
-  std::mutex mu;
+  Arena arena;               // guarded by amu (with the operator cache)
+  std::mutex mu, amu;
   std::condition_variable cv, cv_done;
-  std::thread worker;
   bool stop = false;
   uint64_t next_ticket = 1;
-  std::deque<Request*> queue;
-  std::vector<Request*> active;
+  Lane lanes[2];
+  int nlanes = 1;
   std::map<uint64_t, std::unique_ptr<Request>> all;
   std::vector<std::unique_ptr<OpEntry>> cache;
   cqm_server_stats_t st{};
   std::string worker_error;
 
+  // Stored dense operator bytes of a request in the plain form (the decision
+  // between the lanes and forms is taken on this figure).
+  int64_t dense_bytes(const Request& r) const {
+    const int M = (int)(r.tris.size() / 3);
+    const int64_t F = r.N + 1, Fh = F / 2 + 1;
+    return Fh * sym_slice(M) * 24;
+  }
+
   // ---------------------------------------------------------------- worker
+  // Operator of the request (cached by mesh, N, T and lane).  Called with amu.
   OpEntry* find_or_build(Request& r, bool* cannot_fit) {
     *cannot_fit = false;
     uint64_t key = fnv(r.verts.data(), r.verts.size() * sizeof(double));
     key = fnv(r.tris.data(), r.tris.size() * sizeof(int32_t), key);
     key = fnv(&r.N, sizeof(r.N), key);
     key = fnv(&r.T, sizeof(r.T), key);
+    key = fnv(&r.lane, sizeof(r.lane), key);
     if (opts.cache_operators)
       for (auto& e : cache)
         if (e->key == key && e->ready) {
+          std::lock_guard<std::mutex> lk(mu);
           ++st.operator_cache_hits;
           return e.get();
         }
+    cqm_options so = opts.solver;
+    if (r.lane == 1) so.mode = mode_is_mixed(so.mode) ? CQM_MIXED_H2ACA : CQM_FP64_H2ACA;
     cqm_problem_t h = nullptr;
-    int rc = cqm_problem_create(ctx_handle(), r.verts.data(), (int64_t)r.verts.size() / 3, r.tris.data(),
-                                (int64_t)r.tris.size() / 3, r.N, r.T, &opts.solver, &h);
+    int rc = cqm_problem_create(ctx, r.verts.data(), (int64_t)r.verts.size() / 3, r.tris.data(),
+                                (int64_t)r.tris.size() / 3, r.N, r.T, &so, &h);
     if (rc != CQM_OK) throw Error(rc, cqm_last_error());
     Problem* p = h;
     const size_t need = p->lay.total;
@@ -155,41 +184,46 @@ struct cqm_server_s {
     e->off = off;
     e->bytes = need;
     cache.push_back(std::move(e));
+    std::lock_guard<std::mutex> lk(mu);
     ++st.operators_built;
     return cache.back().get();
   }
-  bool evict_one() {  // least recently used operator without users
+  bool evict_one() {  // least recently used operator without users (amu held)
     int best = -1;
     for (int k = 0; k < (int)cache.size(); ++k)
-      if (cache[k]->users == 0 && (best < 0 || cache[k]->last < cache[best]->last)) best = k;
+      if (cache[k]->users == 0 && cache[k]->ready &&
+          (best < 0 || cache[k]->last < cache[best]->last))
+        best = k;
     if (best < 0) return false;
     arena.release(cache[best]->off, cache[best]->bytes);
     cqm_problem_destroy(static_cast<cqm_problem_t>(cache[best]->prob));
     cache.erase(cache.begin() + best);
     return true;
   }
-  cqm_ctx_t ctx_handle() { return ctx; }
 
-  // admit from the queue; returns true if the active set changed
-  bool admit() {
+  // admit from the lane's queue; returns true if the active set changed
+  bool admit(Lane& L) {
     bool changed = false;
-    while ((int)active.size() < opts.max_active) {
+    while ((int)L.active.size() < opts.max_active) {
       Request* r;
       {
         std::lock_guard<std::mutex> lk(mu);
-        if (queue.empty()) break;
-        r = queue.front();
+        if (L.queue.empty()) break;
+        r = L.queue.front();
       }
+      std::unique_lock<std::mutex> ak(amu);
       bool never = false;
       OpEntry* op = nullptr;
       try {
         op = find_or_build(*r, &never);
       } catch (const Error& e) {
-        reject(r, e.code);
+        ak.unlock();
+        reject(L, r, e.code);
         continue;
       }
       if (!op) {
-        if (never || active.empty()) reject(r, CQM_ENOMEM);
+        ak.unlock();
+        if (never || (L.active.empty() && other_lanes_idle(L))) reject(L, r, CQM_ENOMEM);
         break;  // wait for memory
       }
       Problem& p = *op->prob;
@@ -199,17 +233,26 @@ struct cqm_server_s {
       const size_t sbytes = state_layout(p, s);
       const size_t need = sbytes + sizeof(double) * (size_t)(r->N + 1) * p.M;
       size_t off = arena.alloc(need);
+      if (off == size_t(-1) && L.active.empty()) {
+        // drop idle operators other than this one
+        op->users++;
+        while (off == size_t(-1) && evict_one()) off = arena.alloc(need);
+        op->users--;
+      }
       if (off == size_t(-1)) {
-        if (active.empty()) {
-          // nothing will free up: drop idle operators other than this one
-          op->users++;
-          while (off == size_t(-1) && evict_one()) off = arena.alloc(need);
-          op->users--;
+        if (!op->ready && op->users == 0) {
+          // an operator built for this request alone: give its memory back
+          for (int q = 0; q < (int)cache.size(); ++q)
+            if (cache[q].get() == op) {
+              arena.release(cache[q]->off, cache[q]->bytes);
+              cqm_problem_destroy(static_cast<cqm_problem_t>(cache[q]->prob));
+              cache.erase(cache.begin() + q);
+              break;
+            }
         }
-        if (off == size_t(-1)) {
-          if (active.empty()) reject(r, CQM_ENOMEM);
-          break;
-        }
+        ak.unlock();
+        if (L.active.empty() && other_lanes_idle(L)) reject(L, r, CQM_ENOMEM);
+        break;
       }
       r->off = off;
       r->bytes = need;
@@ -219,118 +262,145 @@ struct cqm_server_s {
       op->users++;
       op->last = clk::now();
       r->op = op;
-      pre_solve(s, stream, !op->ready);
-      op->ready = true;
+      const bool prepare = !op->ready;
+      ak.unlock();
+      pre_solve(s, L.stream, prepare);
       {
-        std::lock_guard<std::mutex> lk(mu);
-        queue.pop_front();
-        r->state = 1;
+        std::lock_guard<std::mutex> a2(amu);
+        op->ready = true;
       }
-      active.push_back(r);
       changed = true;
-      st.peak_active = std::max<int64_t>(st.peak_active, (int64_t)active.size());
+      std::lock_guard<std::mutex> lk(mu);
+      L.queue.pop_front();
+      r->state = 1;
+      L.active.push_back(r);
+      int64_t act = 0;
+      for (int k = 0; k < nlanes; ++k) act += (int64_t)lanes[k].active.size();
+      st.peak_active = std::max<int64_t>(st.peak_active, act);
     }
     return changed;
   }
-  void reject(Request* r, int code) {
+  bool other_lanes_idle(const Lane& L) {
     std::lock_guard<std::mutex> lk(mu);
-    if (!queue.empty() && queue.front() == r) queue.pop_front();
+    for (int k = 0; k < nlanes; ++k)
+      if (&lanes[k] != &L && !lanes[k].active.empty()) return false;
+    return true;
+  }
+  void reject(Lane& L, Request* r, int code) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!L.queue.empty() && L.queue.front() == r) L.queue.pop_front();
     r->state = 3;
     r->rc = code;
     r->t_done = clk::now();
     ++st.rejected;
     cv_done.notify_all();
   }
-  void retire(Engine& E, int k) {
-    Request* r = active[k];
-    E.finish_diag(k, stream);
-    post_solve(r->st, stream);
+  void retire(Lane& L, Engine& E, int k) {
+    Request* r = L.active[k];
+    E.finish_diag(k, L.stream);
+    post_solve(r->st, L.stream);
     r->q.resize((size_t)(r->N + 1) * r->st.p->M);
-    CQM_HIP(hipMemcpyAsync(r->q.data(), r->st.q_out, sizeof(double) * r->q.size(), hipMemcpyDeviceToHost, stream));
-    CQM_HIP(hipStreamSynchronize(stream));
+    CQM_HIP(hipMemcpyAsync(r->q.data(), r->st.q_out, sizeof(double) * r->q.size(),
+                           hipMemcpyDeviceToHost, L.stream));
+    CQM_HIP(hipStreamSynchronize(L.stream));
     r->diag = r->st.diag;
     r->diag.cycles = r->cycles;
-    arena.release(r->off, r->bytes);
-    r->op->users--;
-    r->op->last = clk::now();
-    if (!opts.cache_operators && r->op->users == 0) {
-      for (int q = 0; q < (int)cache.size(); ++q)
-        if (cache[q].get() == r->op) {
-          arena.release(cache[q]->off, cache[q]->bytes);
-          cqm_problem_destroy(static_cast<cqm_problem_t>(cache[q]->prob));
-          cache.erase(cache.begin() + q);
-          break;
-        }
+    {
+      std::lock_guard<std::mutex> ak(amu);
+      arena.release(r->off, r->bytes);
+      r->op->users--;
+      r->op->last = clk::now();
+      if (!opts.cache_operators && r->op->users == 0) {
+        for (int q = 0; q < (int)cache.size(); ++q)
+          if (cache[q].get() == r->op) {
+            arena.release(cache[q]->off, cache[q]->bytes);
+            cqm_problem_destroy(static_cast<cqm_problem_t>(cache[q]->prob));
+            cache.erase(cache.begin() + q);
+            break;
+          }
+      }
     }
     std::lock_guard<std::mutex> lk(mu);
     r->rc = diag_status(r->diag);
     r->state = 2;
     r->t_done = clk::now();
     ++st.completed;
+    ++st.lane_completed[L.id];
     cv_done.notify_all();
   }
 
-  void run() {
+  void run(Lane& L) {
     try {
       CQM_HIP(hipSetDevice(ctx->device));
-      Engine E(*ctx);
+      Engine E(*ctx, L.eb);
       bool dirty = true;
       for (;;) {
         {
           std::unique_lock<std::mutex> lk(mu);
-          cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
-          if (stop && queue.empty() && active.empty()) break;
+          cv.wait(lk, [&] { return stop || !L.queue.empty() || !L.active.empty(); });
+          if (stop && L.queue.empty() && L.active.empty()) break;
         }
-        const size_t before = active.size();
-        if (admit()) dirty = true;
-        if (active.empty()) {
+        const size_t before = L.active.size();
+        if (admit(L)) dirty = true;
+        if (L.active.empty()) {
           std::unique_lock<std::mutex> lk(mu);
           cv.wait_for(lk, std::chrono::milliseconds(1));
           continue;
         }
         if (dirty) {
           std::vector<SolveState*> S;
-          for (Request* r : active) S.push_back(&r->st);
-          E.set(S, stream);
-          for (size_t k = before; k < active.size(); ++k) E.init((int)k, stream);
+          for (Request* r : L.active) S.push_back(&r->st);
+          E.set(S, L.stream);
+          for (size_t k = before; k < L.active.size(); ++k) E.init((int)k, L.stream);
           dirty = false;
         }
-        E.cycle(stream);
-        ++st.cycles;
-        E.status(stream);
-        for (Request* r : active) r->cycles++;
+        E.cycle(L.stream);
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          ++st.cycles;
+        }
+        E.status(L.stream);
+        for (Request* r : L.active) r->cycles++;
         // retire finished (or out-of-cycles) requests, highest index first
-        for (int k = (int)active.size() - 1; k >= 0; --k) {
-          Request* r = active[k];
+        for (int k = (int)L.active.size() - 1; k >= 0; --k) {
+          Request* r = L.active[k];
           if (E.state_done(k) || r->cycles >= r->st.p->opt.max_cycles) {
-            retire(E, k);
-            active.erase(active.begin() + k);
+            retire(L, E, k);
+            std::lock_guard<std::mutex> lk(mu);
+            L.active.erase(L.active.begin() + k);
             dirty = true;
           }
         }
-        if (dirty && !active.empty()) {
+        if (dirty && !L.active.empty()) {
           // keep the survivors' descriptors valid for the next cycle
           std::vector<SolveState*> S;
-          for (Request* r : active) S.push_back(&r->st);
-          E.set(S, stream);
+          for (Request* r : L.active) S.push_back(&r->st);
+          E.set(S, L.stream);
           dirty = false;
         }
       }
     } catch (const std::exception& e) {
       std::lock_guard<std::mutex> lk(mu);
       worker_error = e.what();
-      for (Request* r : queue) {
+      for (Request* r : L.queue) {
         r->state = 3;
         r->rc = CQM_EDEVICE;
+        ++st.rejected;
       }
-      queue.clear();
-      for (Request* r : active) {
+      L.queue.clear();
+      for (Request* r : L.active) {
         r->state = 3;
         r->rc = CQM_EDEVICE;
+        ++st.rejected;
       }
-      active.clear();
+      L.active.clear();
       cv_done.notify_all();
     }
+  }
+  bool idle() const {  // mu held
+    for (int k = 0; k < nlanes; ++k)
+      if (!lanes[k].queue.empty() || !lanes[k].active.empty()) return false;
+    return (int64_t)(st.completed + st.rejected) == st.submitted;
   }
 };
 
@@ -359,14 +429,25 @@ int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* o
   s->opts.solver.reuse_operator = 1;
   s->opts.solver.profile = 0;
   if (s->opts.max_active < 1) s->opts.max_active = 1;
-  if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipMalloc(&s->arena_mem, hbm_budget) != hipSuccess) {
-    if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->opts.large_lane && s->opts.large_bytes <= 0) s->opts.large_bytes = (int64_t)(hbm_budget / 4);
+  s->nlanes = s->opts.large_lane ? 2 : 1;
+  bool ok = hipSetDevice(ctx->device) == hipSuccess;
+  for (int k = 0; ok && k < s->nlanes; ++k) {
+    s->lanes[k].id = k;
+    ok = hipStreamCreateWithFlags(&s->lanes[k].stream, hipStreamNonBlocking) == hipSuccess;
+  }
+  if (ok) ok = hipMalloc(&s->arena_mem, hbm_budget) == hipSuccess;
+  if (!ok) {
+    for (int k = 0; k < s->nlanes; ++k)
+      if (s->lanes[k].stream) (void)hipStreamDestroy(s->lanes[k].stream);
     delete s;
     return CQM_ENOMEM;
   }
   s->arena.init(s->arena_mem, hbm_budget);
-  s->worker = std::thread([s] { s->run(); });
+  for (int k = 0; k < s->nlanes; ++k) {
+    cqm_server_s::Lane* L = &s->lanes[k];
+    L->worker = std::thread([s, L] { s->run(*L); });
+  }
   *out = s;
   return CQM_OK;
 }
@@ -388,10 +469,11 @@ int cqm_server_submit(cqm_server_t s, const cqm_request* q, uint64_t* ticket) {
   r->inc.t0 = q->t0;
   r->inc.amp = q->amplitude;
   r->t_submit = clk::now();
+  r->lane = (s->nlanes > 1 && s->dense_bytes(*r) > s->opts.large_bytes) ? 1 : 0;
   std::lock_guard<std::mutex> lk(s->mu);
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
-  s->queue.push_back(r.get());
+  s->lanes[r->lane].queue.push_back(r.get());
   s->all[r->ticket] = std::move(r);
   ++s->st.submitted;
   s->cv.notify_all();
@@ -421,16 +503,22 @@ int cqm_server_poll(cqm_server_t s, uint64_t ticket, int32_t* done, double* q_ou
 int cqm_server_drain(cqm_server_t s) {
   if (!s) return CQM_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->active.empty() && (int64_t)(s->st.completed + s->st.rejected) == s->st.submitted; });
+  s->cv_done.wait(lk, [&] { return s->idle(); });
   return s->worker_error.empty() ? CQM_OK : CQM_EDEVICE;
 }
 
 int cqm_server_stats(cqm_server_t s, cqm_server_stats_t* out) {
   if (!s || !out) return CQM_EINVAL;
-  std::lock_guard<std::mutex> lk(s->mu);
-  *out = s->st;
-  out->active = (int64_t)s->active.size();
-  out->queued = (int64_t)s->queue.size();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->active = out->queued = 0;
+    for (int k = 0; k < s->nlanes; ++k) {
+      out->active += (int64_t)s->lanes[k].active.size();
+      out->queued += (int64_t)s->lanes[k].queue.size();
+    }
+  }
+  std::lock_guard<std::mutex> ak(s->amu);
   out->arena_bytes = (int64_t)s->arena.size;
   out->peak_arena_bytes = (int64_t)s->arena.peak;
   return CQM_OK;
@@ -444,12 +532,16 @@ int cqm_server_destroy(cqm_server_t s) {
     s->stop = true;
     s->cv.notify_all();
   }
-  if (s->worker.joinable()) s->worker.join();
+  for (int k = 0; k < s->nlanes; ++k)
+    if (s->lanes[k].worker.joinable()) s->lanes[k].worker.join();
   (void)hipSetDevice(s->ctx->device);
   for (auto& e : s->cache) cqm_problem_destroy(static_cast<cqm_problem_t>(e->prob));
   s->cache.clear();
   if (s->arena_mem) (void)hipFree(s->arena_mem);
-  if (s->stream) (void)hipStreamDestroy(s->stream);
+  for (int k = 0; k < s->nlanes; ++k) {
+    release_engine_bufs(s->lanes[k].eb);
+    if (s->lanes[k].stream) (void)hipStreamDestroy(s->lanes[k].stream);
+  }
   delete s;
   return CQM_OK;
 }

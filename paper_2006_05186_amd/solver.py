@@ -77,9 +77,12 @@ class Server:
     """Serving loop on one GPU (cqm_server_*): submit requests as they arrive,
     poll for results.  Marshalling only."""
 
-    def __init__(self, ctx, hbm_budget, max_active=16, cache_operators=1, **solver):
+    def __init__(self, ctx, hbm_budget, max_active=16, cache_operators=1, large_lane=0,
+                 large_bytes=0, **solver):
         self.opts = C.cqm_server_default_options(max_active=max_active,
-                                                 cache_operators=cache_operators, **solver)
+                                                 cache_operators=cache_operators,
+                                                 large_lane=large_lane, large_bytes=large_bytes,
+                                                 **solver)
         self.handle = C.cqm_server_create(ctx, hbm_budget, self.opts)
         self.shapes = {}
 

@@ -112,6 +112,43 @@ def test_admission_by_budget_and_rejection(ctx):
     srv.close()
 
 
+def test_large_lane_compressed_beside_plain(ctx):
+    """With the large lane on, a request whose stored dense operator exceeds
+    the limit is solved in the compressed form on its own stream while the
+    others keep streaming on the first lane; every result equals the same
+    request solved alone in its form."""
+    small = requests(4, seed=13)
+    (VL, TL), NL, TLend = W.icosphere(3), 8, 2.0  # 1280 triangles: over the limit below
+    nt = (len(TL) + 63) // 64
+    limit = (NL // 2 + 1) * (nt * (nt + 1) // 2) * 64 * 64 * 24 - 1
+    srv = Server(ctx, 24 << 30, max_active=8, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                 large_lane=1, large_bytes=limit)
+    say(f"large lane: limit {limit / 1e6:.1f} MB")
+    tl = srv.submit(VL, TL, NL, TLend, (0.0, 0.6, 0.8), 0.3, 1.6)
+    ts = [srv.submit(V, T, N, Tend, d, s, t0) for (V, T, N, Tend, d, s, t0) in small]
+    res = wait_all(srv, [tl] + ts, timeout=300.0)
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["lane_completed"] == [4, 1]
+    srv.close()
+    assert res[tl][0] == 1 and res[tl][1] == C.CQM_OK
+    p = Problem(ctx, VL, TL, NL, TLend, mode=C.CQM_MIXED_H2ACA)
+    p.set_plane_wave((0.0, 0.6, 0.8), 0.3, 1.6)
+    qa = p.solve()[0].cpu().numpy()
+    p.close()
+    _, _, area = O.triangle_quadrature(VL, TL)
+    e = O.rel_error(res[tl][2], qa, area)
+    say(f"  large request vs compressed alone {e:.1e}")
+    assert e < 1e-12
+    for t, (V, T, N, Tend, d, s, t0) in zip(ts, small):
+        p = Problem(ctx, V, T, N, Tend, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
+        p.set_plane_wave(d, s, t0)
+        qa = p.solve()[0].cpu().numpy()
+        p.close()
+        _, _, area = O.triangle_quadrature(V, T)
+        assert res[t][0] == 1 and O.rel_error(res[t][2], qa, area) < 1e-12
+
+
 def test_serving_is_deterministic(ctx):
     reqs = requests(4, seed=9)
     outs = []
