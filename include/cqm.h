@@ -95,7 +95,12 @@ typedef struct cqm_options {
                             the far product and the dense assembly on
                             their first use per context and problem
                             shape, keep the fastest (one host wait)  (1)   */
-  int32_t reserved[4];
+  int32_t graphs;        /* nonzero: Arnoldi steps of stored-form solves
+                            without profiling replay captured HIP graphs
+                            (kept across solves of the same problem; the
+                            full group list is used, so closed groups are
+                            launched and leave at once)               (0)   */
+  int32_t reserved[3];
 } cqm_options;
 
 /* Arnoldi step layouts (cqm_options.arnoldi_layout).  AUTO splits when a

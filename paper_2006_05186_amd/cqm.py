@@ -58,7 +58,7 @@ class cqm_options(ctypes.Structure):
         ("eps_aca", ctypes.c_double), ("aca_band", ctypes.c_int32), ("q_duffy", ctypes.c_int32),
         ("reuse_operator", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -130,6 +130,7 @@ int cqm_default_options(cqm_options* o) {
   o->q_duffy = 5;
   o->reuse_operator = 0;
   o->autotune = 1;
+  o->graphs = 0;
   return CQM_OK;
 }
 
@@ -232,6 +233,9 @@ int cqm_problem_destroy(cqm_problem_t p) {
   (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
   h2_release(*p);
   p->timer.release();
+  delete p->engine;
+  p->engine = nullptr;
+  release_engine_bufs(p->engine_bufs);
   void* bufs[] = {p->dev.pts64, p->dev.pts32, p->dev.vid, p->dev.area, p->dev.verts,
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,

@@ -3,6 +3,8 @@
 // solve states (one problem, an uneven batch, or the serving loop's active
 // requests).
 #include <algorithm>
+#include <cstring>
+#include <memory>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -235,7 +237,9 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   // would leave most compute units idle
   const int lay = S_[0]->p->opt.arnoldi_layout;
   split_ = lay == CQM_ARNOLDI_SPLIT || (lay == CQM_ARNOLDI_AUTO && n < kSplitBelow);
+  const SysDesc* old_desc = eb.desc;
   ensure(eb.desc, eb.desc_cap, hd_.size());
+  if (eb.desc != old_desc) drop_graphs();  // captured steps point at the old buffer
   ensure(eb.open_cycle, eb.cycle_cap, std::max<size_t>(1, lite_.size()));
   ensure(eb.open_step, eb.step_cap, std::max<size_t>(1, lite_.size()));
   if (eb.staging_cap < 2 * lite_.size()) {
@@ -262,6 +266,40 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     eb.status_host_cap = c;
   }
   CQM_HIP(hipMemcpyAsync(eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
+  // graph-captured steps: every state in the stored form, no profiling
+  bool eligible = !lite_.empty();
+  for (SolveState* st : S_)
+    eligible = eligible && dense_form(*st->p) && st->p->opt.graphs && !st->p->opt.profile;
+  const bool same = prev_hd_.size() == hd_.size() &&
+                    std::memcmp(prev_hd_.data(), hd_.data(), sizeof(SysDesc) * hd_.size()) == 0;
+  if (!eligible || !same) drop_graphs();
+  graphs_ = eligible;
+  prev_hd_ = hd_;
+  if (graphs_) {
+    // the full group list, sorted by mesh size, in its own device buffer
+    std::vector<int> ord(lite_.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return lite_[a].M < lite_[b].M; });
+    std::vector<GroupLite> all;
+    all_cls_.clear();
+    for (int gi : ord) {
+      const GroupLite& g = lite_[gi];
+      if (all_cls_.empty() || all_cls_.back().M != g.M)
+        all_cls_.push_back(GClass{g.M, (int)all.size(), 0, false});
+      all_cls_.back().count += 1;
+      all_cls_.back().grouped |= g.n > 1;
+      all.push_back(g);
+    }
+    const GroupLite* old_ptr = eb.all_groups;
+    ensure(eb.all_groups, eb.all_cap, all.size());
+    if (eb.all_groups != old_ptr) drop_graphs();
+    CQM_HIP(hipMemcpyAsync(eb.all_groups, all.data(), sizeof(GroupLite) * all.size(),
+                           hipMemcpyHostToDevice, s));
+    if ((int)gexec_.size() != m_) {
+      drop_graphs();
+      gexec_.assign(m_, nullptr);
+    }
+  }
   flags_.assign((size_t)kSysiStride * n, 0);
 }
 
@@ -273,11 +311,20 @@ void release_engine_bufs(EngineBufs& b) {
   if (b.open_cycle) (void)hipFree(b.open_cycle);
   if (b.open_step) (void)hipFree(b.open_step);
   if (b.staging) (void)hipHostFree(b.staging);
+  if (b.all_groups) (void)hipFree(b.all_groups);
   b = EngineBufs{};
 }
 
 Engine::~Engine() {
+  drop_graphs();
   if (snap_ev_) (void)hipEventDestroy(snap_ev_);
+  if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+}
+
+void Engine::drop_graphs() {
+  for (hipGraphExec_t g : gexec_)
+    if (g) (void)hipGraphExecDestroy(g);
+  gexec_.clear();
 }
 
 void Engine::snapshot(hipStream_t s) {
@@ -358,6 +405,50 @@ int Engine::cycle(hipStream_t s) { return mixed ? cycle_t<float>(s) : cycle_t<do
 // One restart cycle of every open system: start from the FP64 residual, up
 // to m Arnoldi steps, update x, new FP64 residual.  Returns the number of
 // systems that were open at the start (0: nothing was done).
+// One Arnoldi step of every open system, launched directly: products of
+// the stored-operator groups in `list` and of the other problems, then the
+// Arnoldi kernels.
+template <typename R>
+void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>& cls, hipStream_t s) {
+  Problem& p0 = *S_[0]->p;
+  const int n = (int)hd_.size();
+  if (!lite_.empty()) {
+    const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
+    Timed t(p0, c, s);
+    dense_product<R>(list, cls, 0, j, !split_, p0.timer.ctr(c), s);
+  }
+  for (SolveState* st : S_) {
+    Problem& p = *st->p;
+    if (dense_form(p)) continue;
+    const int M = (int)p.M;
+    const int64_t bs = (int64_t)(m_ + 1) * M;
+    cplx<R>* basis = reinterpret_cast<cplx<R>*>(st->base + st->basis);
+    apply_op<R>(p, 0, p.Fsys, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
+                st->at<int>(st->sysi) + 1, s);
+  }
+  Timed t(p0, CQM_K_ARNOLDI, s);
+  launch_arnoldi<R>(eb.desc, n, maxM_, j, split_, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
+}
+
+// The same step from its captured graph (captured on first use).
+template <typename R> void Engine::step_graph(int j, hipStream_t s) {
+  if (!gexec_[j]) {
+    // captured on a private stream (the caller's may be the null stream,
+    // which cannot be captured); nothing executes during capture
+    if (!cap_stream_) CQM_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    CQM_HIP(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+    dense_product<R>(eb.all_groups, all_cls_, 0, j, !split_, nullptr, cap_stream_);
+    launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, nullptr, cap_stream_);
+    const hipError_t ec = hipStreamEndCapture(cap_stream_, &g);
+    CQM_HIP(ec);
+    const hipError_t e = hipGraphInstantiate(&gexec_[j], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    CQM_HIP(e);
+  }
+  CQM_HIP(hipGraphLaunch(gexec_[j], s));
+}
+
 template <typename R> int Engine::cycle_t(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!n) return 0;
@@ -384,24 +475,8 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   step_cls_ = cyc_cls_;
   int snap_j = -1;  // step behind which a status snapshot is pending
   for (int j = 0; j < m_; ++j) {
-    if (!lite_.empty()) {
-      const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
-      Timed t(p0, c, s);
-      dense_product<R>(step_list, step_cls_, 0, j, !split_, p0.timer.ctr(c), s);
-    }
-    for (SolveState* st : S_) {
-      Problem& p = *st->p;
-      if (dense_form(p)) continue;
-      const int M = (int)p.M;
-      const int64_t bs = (int64_t)(m_ + 1) * M;
-      cplx<R>* basis = reinterpret_cast<cplx<R>*>(st->base + st->basis);
-      apply_op<R>(p, 0, p.Fsys, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
-                  st->at<int>(st->sysi) + 1, s);
-    }
-    {
-      Timed t(p0, CQM_K_ARNOLDI, s);
-      launch_arnoldi<R>(sd, n, maxM_, j, split_, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
-    }
+    if (graphs_) step_graph<R>(j, s);
+    else step_eager<R>(j, step_list, step_cls_, s);
     // status: a snapshot behind step j is read three steps later, so the
     // stream keeps three steps of queued work while the host decides
     if (snap_j >= 0 && j == snap_j + 3) {
@@ -410,9 +485,11 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
       int c = 0;
       for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + 1] != 0;
       if (c == 0) break;
-      // drop the groups whose cycles had closed by then
-      upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
-      step_list = eb.open_step;
+      if (!graphs_) {
+        // drop the groups whose cycles had closed by then
+        upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
+        step_list = eb.open_step;
+      }
     }
     if ((j + 1) % 6 == 0 && j + 4 < m_ && snap_j < 0) {
       snapshot(s);
@@ -446,6 +523,10 @@ template void Engine::dense_product<float>(const GroupLite*, const std::vector<G
                                            bool, unsigned long long*, hipStream_t);
 template void Engine::dense_product<double>(const GroupLite*, const std::vector<GClass>&, int, int,
                                             bool, unsigned long long*, hipStream_t);
+template void Engine::step_eager<float>(int, const GroupLite*, const std::vector<GClass>&, hipStream_t);
+template void Engine::step_eager<double>(int, const GroupLite*, const std::vector<GClass>&, hipStream_t);
+template void Engine::step_graph<float>(int, hipStream_t);
+template void Engine::step_graph<double>(int, hipStream_t);
 template int Engine::cycle_t<float>(hipStream_t);
 template int Engine::cycle_t<double>(hipStream_t);
 
@@ -495,7 +576,18 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
       if (G[k]->p != &p0) G[k]->p->timer.on = false;
     for (SolveState* st : G) pre_solve(*st, s, true);
     auto t1 = std::chrono::steady_clock::now();
-    Engine E(*p0.ctx);
+    // a problem's own solve keeps its engine (buffers, captured graphs)
+    std::unique_ptr<Engine> local;
+    Engine* Ep;
+    if (G.size() == 1 && G[0] == &p0.own) {
+      if (!p0.engine) p0.engine = new Engine(*p0.ctx, p0.engine_bufs);
+      Ep = p0.engine;
+    } else {
+      local = std::make_unique<Engine>(*p0.ctx);
+      Ep = local.get();
+    }
+    Engine& E = *Ep;
+    E.cycles_run = 0;
     E.set(G, s);
     for (size_t k = 0; k < G.size(); ++k) E.init((int)k, s);
     for (int c = 0; c < p0.opt.max_cycles; ++c)

@@ -129,6 +129,8 @@ struct EngineBufs {
   size_t step_cap = 0;
   GroupLite* staging = nullptr;     // pinned host copies of the two lists
   size_t staging_cap = 0;
+  GroupLite* all_groups = nullptr;  // every group (graph-captured steps)
+  size_t all_cap = 0;
   GemvGroup* groups = nullptr;
   size_t groups_cap = 0;
   int* status = nullptr;
@@ -256,6 +258,10 @@ struct Problem {
   cqm_diag last{};
   int64_t far_units = 0;
   KernelTimer timer;
+  // engine of the problem's own solves, kept across them (with its buffers
+  // and captured step graphs)
+  class Engine* engine = nullptr;
+  EngineBufs engine_bufs;
   bool full_band() const { return Fsys == F; }
 };
 
@@ -379,6 +385,19 @@ class Engine {
   hipEvent_t snap_ev_ = nullptr;
   void snapshot(hipStream_t s);
   void read_snapshot();
+  // HIP graphs of the Arnoldi steps (dense-form batches without profiling):
+  // step j = products of every group + the Arnoldi step, over the full group
+  // list (closed systems are skipped inside the kernels).  Captured on first
+  // use and kept while set() rebuilds the same descriptors.
+  bool graphs_ = false;
+  hipStream_t cap_stream_ = nullptr;
+  std::vector<GClass> all_cls_;
+  std::vector<hipGraphExec_t> gexec_;
+  std::vector<SysDesc> prev_hd_;
+  void drop_graphs();
+  template <typename R> void step_eager(int j, const GroupLite* list, const std::vector<GClass>& cls,
+                                        hipStream_t s);
+  template <typename R> void step_graph(int j, hipStream_t s);
 };
 
 void release_engine_bufs(EngineBufs& b);

@@ -189,6 +189,13 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
   const GroupLite& G = gl[blockIdx.y];
   const int M = G.M;
   const int t = blockIdx.x;
+  {
+    // groups with no open member leave at once (the full list is used by
+    // graph-captured steps)
+    bool any = false;
+    for (int k = 0; k < (kGrouped ? G.n : 1); ++k) any |= G.sysi[k][which == 0 ? 1 : 0] != 0;
+    if (!any) return;
+  }
   int I, J;
   decode_tile(t, I, J);
   const void* Vs = which == 0 ? (sizeof(R) == 4 ? G.V32 : G.V64) : G.V64;

@@ -190,6 +190,29 @@ def test_autotuned_shapes_give_the_same_product(ctx, c1):
             assert np.linalg.norm(ys[tune][32][l] - ref) < 2e-6 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("mode", [C.CQM_MIXED_PLAIN, C.CQM_FP64_PLAIN])
+def test_graph_replayed_steps_equal_launched_ones(ctx, c1, mode):
+    """Arnoldi steps replayed from captured HIP graphs (kept across solves of
+    the same problem) give bit-identical densities to directly launched ones,
+    on the first solve (capture) and on later ones (replay), with eager work
+    and host synchronisations between replays."""
+    wl, V, T, r, area = c1
+    qs = {}
+    for graphs in (0, 1):
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=C.CQM_FORM_DENSE, graphs=graphs)
+        p.set_plane_wave()
+        qs[graphs] = []
+        for rep in range(3):
+            q, rc, d = p.solve()
+            assert rc == C.CQM_OK
+            qs[graphs].append(q.cpu().numpy())
+        p.close()
+    say(f"graphs mode={mode}: err vs oracle {O.rel_error(qs[1][2], r['q'], area):.2e}")
+    for q in qs[0] + qs[1]:
+        assert np.array_equal(q, qs[0][0])
+    assert O.rel_error(qs[1][2], r["q"], area) < 1e-8
+
+
 def test_solve_C2_against_stored_oracle(ctx):
     wl = W.C2
     path = os.path.join(GOLDEN, f"{wl.name}.npz")
