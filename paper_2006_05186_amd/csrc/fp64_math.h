@@ -71,4 +71,54 @@ __device__ __forceinline__ void sincos_bounded(double t, double* s, double* c) {
   *c = ((q + 1) & 2) ? -b : b;
 }
 
+// Table-driven variants (Tang's method, "Table-driven implementation of the
+// exponential function in IEEE floating-point arithmetic", ACM TOMS 1989,
+// and the same idea for sine/cosine): reduce by a multiple of a table step,
+// look the step's value up, and evaluate a short Taylor polynomial on the
+// small remainder.  `tab` (in LDS) holds 2^(j/64), then sin(j pi/32) and
+// cos(j pi/32) for j = 0..63 (kFp64TabLen doubles, filled on the host).
+constexpr int kFp64TabLen = 192;
+
+__device__ __forceinline__ double exp_tab(double x, const double* tab) {
+  // x <= 0 expected; x = (64 m + j) ln2/64 + r, |r| <= ln2/128
+  if (x < -708.0) return 0.0;
+  const double k = rint(x * 92.332482616893657);
+  double r = fma(-k, 0.01083042469326756, x);
+  r = fma(-k, 2.9815858269852933e-12, r);
+  // exp r through r^5 (truncation < 3e-17 relative)
+  double p = 0.008333333333333333;       // 1/5!
+  p = fma(p, r, 0.041666666666666664);    // 1/4!
+  p = fma(p, r, 0.16666666666666666);     // 1/3!
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const int ik = (int)k;
+  return ldexp(tab[ik & 63] * p, ik >> 6);
+}
+
+__device__ __forceinline__ void sincos_tab(double t, const double* tab, double* s, double* c) {
+  // t = k pi/32 + r, |r| <= pi/64; (sin, cos)(k pi/32) from the table (k mod 64)
+  const double k = rint(t * 10.185916357881302);
+  double r = fma(-k, 0.098174770420882851, t);
+  r = fma(-k, 3.7981878164399787e-12, r);
+  r = fma(-k, 1.2639164054974691e-22, r);
+  const double r2 = r * r;
+  // sin r through r^9, cos r through r^10 (truncation < 1e-19)
+  double ps = 2.7557319223985893e-06;         // 1/9!
+  ps = fma(ps, r2, -0.0001984126984126984);    // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);      // 1/5!
+  ps = fma(ps, r2, -0.16666666666666666);      // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  double pc = -2.755731922398589e-07;          // -1/10!
+  pc = fma(pc, r2, 2.48015873015873e-05);      // 1/8!
+  pc = fma(pc, r2, -0.001388888888888889);     // -1/6!
+  pc = fma(pc, r2, 0.041666666666666664);      // 1/4!
+  pc = fma(pc, r2, -0.5);                      // -1/2!
+  const double cr = fma(pc, r2, 1.0);
+  const int j = ((int)k) & 63;
+  const double sa = tab[64 + j], ca = tab[128 + j];
+  *s = fma(sa, cr, ca * sr);
+  *c = fma(ca, cr, -(sa * sr));
+}
+
 }  // namespace cqm

@@ -29,9 +29,9 @@ constexpr double kInv4Pi = 0.07957747154594767;
 template <typename R> struct KMath;
 template <> struct KMath<float> {
   static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-  // e = 2^(ea r), (c, sn) = (cos, sin)(2 pi pb r)
+  // e = 2^(ea r), (c, sn) = (cos, sin)(2 pi pb r); no table
   static __device__ __forceinline__ void eval(float ea, float pb, float r, float& e, float& c,
-                                              float& sn) {
+                                              float& sn, const double*) {
     e = __builtin_amdgcn_exp2f(ea * r);
     const float ph = pb * r;
     c = __builtin_amdgcn_cosf(ph);
@@ -40,11 +40,11 @@ template <> struct KMath<float> {
 };
 template <> struct KMath<double> {
   static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-  // e = exp(ea r) (ea <= 0), (c, sn) = (cos, sin)(pb r)
+  // e = exp(ea r) (ea <= 0), (c, sn) = (cos, sin)(pb r), table in LDS
   static __device__ __forceinline__ void eval(double ea, double pb, double r, double& e,
-                                              double& c, double& sn) {
-    e = exp_nonpos(ea * r);
-    sincos_bounded(pb * r, &sn, &c);
+                                              double& c, double& sn, const double* tab) {
+    e = exp_tab(ea * r, tab);
+    sincos_tab(pb * r, tab, &sn, &c);
   }
 };
 
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     const typename Pt4<R>::T* __restrict__ pts, const int4* __restrict__ vid, int M,
     const R* __restrict__ ea, const R* __restrict__ pb, int nsys, const cplx<R>* __restrict__ x,
     int64_t xs, cplx<R>* __restrict__ partial, int chunk, const int* __restrict__ active,
-    unsigned long long* ctr) {
+    unsigned long long* ctr, const double* __restrict__ ftab) {
   using P4 = typename Pt4<R>::T;
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
@@ -68,6 +68,11 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     nact = 0;
     for (int l = 0; l < nl; ++l) nact += active[(l0 + l) * kSysiStride] != 0;
     if (!nact) return;
+  }
+  __shared__ double stab[sizeof(R) == 8 ? kFp64TabLen : 1];
+  if constexpr (sizeof(R) == 8) {
+    for (int k = threadIdx.x; k < kFp64TabLen; k += kTgt) stab[k] = ftab[k];
+    __syncthreads();
   }
   const int i = blockIdx.x * kTgt + threadIdx.x;
   const int ic = i < M ? i : M - 1;
@@ -129,7 +134,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
           R e, c, sn;
-          KMath<R>::eval(fe[l], fp[l], r, e, c, sn);
+          KMath<R>::eval(fe[l], fp[l], r, e, c, sn, stab);
           e *= w;
           vre[l] += e * c;
           vim[l] -= e * sn;
@@ -222,7 +227,8 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
                                                               const double* __restrict__ pb,
                                                               int nsys, cf64* __restrict__ d64,
                                                               cf32* __restrict__ d32,
-                                                              unsigned long long* ctr) {
+                                                              unsigned long long* ctr,
+                                                              const double* __restrict__ ftab) {
   // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I
   const long long kk = blockIdx.x;
   long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
@@ -234,6 +240,9 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
   __shared__ cf64 tile[FT][kAt][kAt + 1];
+  __shared__ double stab[kFp64TabLen];
+  for (int k = threadIdx.x; k < kFp64TabLen; k += kAt * kAt) stab[k] = ftab[k];
+  __syncthreads();
   bool live = i < M && j < M && (I != J || i <= j);
   if (live) live = !share_vertex(vid[i], vid[j]);
   if (ctr) {
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
           double e, c, sn;
-          KMath<double>::eval(fe[l], fp[l], r, e, c, sn);
+          KMath<double>::eval(fe[l], fp[l], r, e, c, sn, stab);
           e *= w;
           vre[l] += e * c;
           vim[l] -= e * sn;
@@ -368,7 +377,7 @@ static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, i
     pb = p.dev.pb64 + l0;
   }
   hipLaunchKernelGGL((k_far_apply<R, FT>), grid, dim3(kTgt), 0, s, pts, p.dev.vid, M, ea, pb,
-                     nsys, x, xs, partial, chunk, active, ctr);
+                     nsys, x, xs, partial, chunk, active, ctr, p.dev.ftab);
   CQM_HIP(hipGetLastError());
 }
 
@@ -492,7 +501,7 @@ static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, unsigned l
   const int nt = (M + kAt - 1) / kAt;
   dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
   hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64, p.dev.vid,
-                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr);
+                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr, p.dev.ftab);
   CQM_HIP(hipGetLastError());
 }
 

@@ -6,6 +6,7 @@
 #include <set>
 
 #include "internal.h"
+#include "fp64_math.h"
 
 namespace cqm {
 
@@ -205,6 +206,15 @@ void upload_problem(Problem& p) {
   }
   p.dev.ea64 = upload(ea64);
   p.dev.pb64 = upload(pb64);
+  // tables of the FP64 exp/sincos (extended precision, rounded once)
+  std::vector<double> ftab(kFp64TabLen);
+  const long double pi_l = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < 64; ++j) {
+    ftab[j] = (double)std::exp2((long double)j / 64.0L);
+    ftab[64 + j] = (double)std::sin(pi_l * j / 32.0L);
+    ftab[128 + j] = (double)std::cos(pi_l * j / 32.0L);
+  }
+  p.dev.ftab = upload(ftab);
   p.dev.ea32 = upload(ea32);
   p.dev.pb32 = upload(pb32);
 }
