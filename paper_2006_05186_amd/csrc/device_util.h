@@ -46,15 +46,36 @@ template <typename R>
 __device__ __forceinline__ cplx<R> sym_row_sum(const cplx<R>* __restrict__ P, int M, int i) {
   const int nt = sym_blocks(M), ntB = nt * kSymB;
   R re = R(0), im = R(0);
-  for (int Y = 0; Y < nt; ++Y) {
-    const cplx<R> v = P[(int64_t)Y * ntB + i];
-    re += v.re;
-    im += v.im;
+  for (int Y0 = 0; Y0 < nt; Y0 += 8) {
+    // eight loads in flight (clamped indices), added in slot order
+    cplx<R> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)min(Y0 + u, nt - 1) * ntB + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (Y0 + u < nt) {
+        re += v[u].re;
+        im += v[u].im;
+      }
   }
   cplx<R> o;
   o.re = re;
   o.im = im;
   return o;
+}
+
+// sum_{q < S} P[q * stride] (doubles) in slot order, eight loads in flight.
+__device__ __forceinline__ double slot_sum(const double* __restrict__ P, int S, int64_t stride) {
+  double acc = 0.0;
+  for (int q0 = 0; q0 < S; q0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)min(q0 + u, S - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q0 + u < S) acc += v[u];
+  }
+  return acc;
 }
 
 // Sum over a workgroup of blockDim.x threads (multiple of 64, <= 1024).

@@ -164,17 +164,19 @@ __device__ __forceinline__ void basis_combine(const cplx<R>* __restrict__ V, int
                                               const cf64* c, int n, double sign, double& re,
                                               double& im) {
   for (int kc = 0; kc < n; kc += kU) {
+    // clamped (in-bounds) loads, all in flight together; terms beyond n are
+    // dropped by a zero coefficient
     cplx<R> v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (kc + u < n) v[u] = V[(int64_t)(kc + u) * M + i];
+    for (int u = 0; u < kU; ++u) v[u] = V[(int64_t)min(kc + u, n - 1) * M + i];
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (kc + u < n) {
-        const cf64 a{sign * c[kc + u].re, sign * c[kc + u].im};
-        re += a.re * v[u].re - a.im * v[u].im;
-        im += a.re * v[u].im + a.im * v[u].re;
-      }
+    for (int u = 0; u < kU; ++u) {
+      const bool in = kc + u < n;
+      const cf64 cu = c[min(kc + u, n - 1)];
+      const cf64 a{in ? sign * cu.re : 0.0, in ? sign * cu.im : 0.0};
+      re += a.re * v[u].re - a.im * v[u].im;
+      im += a.re * v[u].im + a.im * v[u].re;
+    }
   }
 }
 
@@ -321,23 +323,24 @@ __device__ __forceinline__ int arn_stride(int m) { return 4 * (m + 1) + 2; }
 // out[k] (k <= j) = sum over this slice of conj(v_k[i]) x_i (x_i = 0 and no
 // loads where !valid); kC inner products per reduction round.
 template <typename R, int kC>
-__device__ void slice_dots(const cplx<R>* __restrict__ V, int64_t M, int i, bool valid,
+__device__ __forceinline__ void slice_dots(const cplx<R>* __restrict__ V, int64_t M, int i, bool valid,
                            cplx<R> x, int j, cf64* out, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = kArnRows / 64;
+  // loads use clamped (in-bounds) indices and are masked afterwards, so all
+  // kC of them are in flight together
+  const int ic = valid ? i : (int)M - 1;
   for (int kc = 0; kc <= j; kc += kC) {
     cplx<R> v[kC];
 #pragma unroll
-    for (int u = 0; u < kC; ++u) {
-      v[u].re = R(0);
-      v[u].im = R(0);
-      if (valid && kc + u <= j) v[u] = V[(int64_t)(kc + u) * M + i];
-    }
+    for (int u = 0; u < kC; ++u) v[u] = V[(int64_t)min(kc + u, j) * M + ic];
     double a[2 * kC];
 #pragma unroll
     for (int u = 0; u < kC; ++u) {
-      a[u] = (double)v[u].re * x.re + (double)v[u].im * x.im;
-      a[kC + u] = (double)v[u].re * x.im - (double)v[u].im * x.re;
+      const bool in = valid && kc + u <= j;
+      const double vr = in ? (double)v[u].re : 0.0, vi = in ? (double)v[u].im : 0.0;
+      a[u] = vr * x.re + vi * x.im;
+      a[kC + u] = vr * x.im - vi * x.re;
     }
     wave_reduce_scatter<2 * kC, 32>(a, lane);
     constexpr int kSh = kC == 32 ? 0 : kC == 16 ? 1 : 2;
@@ -410,15 +413,8 @@ __global__ __launch_bounds__(kArnRows) void k_arn_update(const SysDesc* __restri
   if (s * kArnRows >= M) return;
   const int S = (M + kArnRows - 1) / kArnRows;
   const int str = arn_stride(m);
-  for (int k = threadIdx.x; k <= j; k += kArnRows) {
-    double re = 0.0, im = 0.0;
-    for (int q = 0; q < S; ++q) {
-      const double* P = D.part + (int64_t)q * str;
-      re += P[2 * k];
-      im += P[2 * k + 1];
-    }
-    coef[k] = cf64{re, im};
-  }
+  for (int k = threadIdx.x; k <= j; k += kArnRows)
+    coef[k] = cf64{slot_sum(D.part + 2 * k, S, str), slot_sum(D.part + 2 * k + 1, S, str)};
   __syncthreads();
   const int i = s * kArnRows + threadIdx.x;
   const bool valid = i < M;
@@ -465,11 +461,8 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
   const int str = arn_stride(m);
   const int tid = threadIdx.x;
   if (tid == 0) {
-    double n0 = 0.0, n1 = 0.0;
-    for (int q = 0; q < S; ++q) {
-      n0 += D.part[(int64_t)q * str + 4 * (m + 1)];
-      n1 += D.part[(int64_t)q * str + 4 * (m + 1) + 1];
-    }
+    const double n0 = slot_sum(D.part + 4 * (m + 1), S, str);
+    const double n1 = slot_sum(D.part + 4 * (m + 1) + 1, S, str);
     nsh[0] = n0;
     nsh[1] = n1;
     second_s = n1 < 0.49 * n0;
@@ -477,14 +470,8 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
   __syncthreads();
   const bool second = second_s != 0;
   for (int k = tid; k <= j; k += kArnRows) {
-    double re = 0.0, im = 0.0;
-    if (second)
-      for (int q = 0; q < S; ++q) {
-        const double* P = D.part + (int64_t)q * str + 2 * (m + 1);
-        re += P[2 * k];
-        im += P[2 * k + 1];
-      }
-    c2[k] = cf64{re, im};
+    const double* P = D.part + 2 * (m + 1) + 2 * k;
+    c2[k] = second ? cf64{slot_sum(P, S, str), slot_sum(P + 1, S, str)} : cf64{0.0, 0.0};
   }
   __syncthreads();
   if (tid == 0) {
@@ -515,15 +502,9 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
     atomicAdd(ctr, rows * (second ? j + 3 : 2) * sizeof(cplx<R>));
   }
   if (s != 0) return;
-  for (int k = tid; k <= j; k += kArnRows) {
-    double re = 0.0, im = 0.0;
-    for (int q = 0; q < S; ++q) {
-      const double* P = D.part + (int64_t)q * str;
-      re += P[2 * k];
-      im += P[2 * k + 1];
-    }
-    h[k] = cf64{re + c2[k].re, im + c2[k].im};
-  }
+  for (int k = tid; k <= j; k += kArnRows)
+    h[k] = cf64{slot_sum(D.part + 2 * k, S, str) + c2[k].re,
+                slot_sum(D.part + 2 * k + 1, S, str) + c2[k].im};
   for (int k = tid; k < j; k += kArnRows) {
     rc_s[k] = D.cs[k];
     rs_s[k] = D.sn[k];
