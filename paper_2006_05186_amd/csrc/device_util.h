@@ -5,6 +5,22 @@
 
 namespace cqm {
 
+// Global-memory view of a generic pointer: loads through it compile to
+// global (not flat) loads, which count only against vmcnt and so do not make
+// waits for scalar or LDS traffic wait for them as well.  (The host pass of
+// the same source sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CQM_GLOBAL __attribute__((address_space(1)))
+#else
+#define CQM_GLOBAL
+#endif
+template <typename T> __device__ __forceinline__ const CQM_GLOBAL T* as_global(const T* p) {
+  return (const CQM_GLOBAL T*)p;
+}
+template <typename T> __device__ __forceinline__ CQM_GLOBAL T* as_global(T* p) {
+  return (CQM_GLOBAL T*)p;
+}
+
 template <typename R> __device__ __forceinline__ cplx<R> cmake(R re, R im) {
   cplx<R> z;
   z.re = re;

@@ -270,11 +270,12 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   bool eligible = !lite_.empty();
   for (SolveState* st : S_)
     eligible = eligible && dense_form(*st->p) && st->p->opt.graphs && !st->p->opt.profile;
-  const bool same = prev_hd_.size() == hd_.size() &&
+  const bool same = prev_hd_.size() == hd_.size() && prev_split_ == split_ &&
                     std::memcmp(prev_hd_.data(), hd_.data(), sizeof(SysDesc) * hd_.size()) == 0;
   if (!eligible || !same) drop_graphs();
   graphs_ = eligible;
   prev_hd_ = hd_;
+  prev_split_ = split_;
   if (graphs_) {
     // the full group list, sorted by mesh size, in its own device buffer
     std::vector<int> ord(lite_.size());

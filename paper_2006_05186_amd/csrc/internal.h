@@ -61,24 +61,27 @@ template <typename R> struct FreqTab {
 
 // ------------------------------------------------------------ problem state
 // GMRES (k_gmres.hip).  One descriptor per frequency system.
+// 128 bytes; the fields every Arnoldi kernel reads first share the leading
+// 64-byte line (one scalar cache line per descriptor fetch).
 struct SysDesc {
   int M, m;               // length, restart length
   int prob, l;            // problem index (in a batch) and frequency index
   void* basis;            // (m+1) x M, inner precision
-  cf64* H;                // (m+1) x m, column-major
+  double* part;           // split Arnoldi: per row slice 4 (m+1) + 2 partial sums
+  int* sysi;              // kSysiStride ints of status
+  void* symp;             // stored form: tile partials of the product (nt x nt kSymB)
   double* cs;             // m
   cf64* sn;               // m
   cf64* g;                // m+1
+  cf64* H;                // (m+1) x m, column-major
   double* sysd;           // 8 doubles of status
-  int* sysi;              // kSysiStride ints of status
   cf64* x;                // M, FP64 solution
   cf64* r;                // M, FP64 residual
   const cf64* ghat;       // M, right-hand side
   const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
   const cf64* V64;        // dense operator slice in FP64 (dense form) or null
-  double* part;           // split Arnoldi: per row slice 4 (m+1) + 2 partial sums
-  void* symp;             // stored form: tile partials of the product (nt x nt kSymB)
 };
+static_assert(sizeof(SysDesc) == 128, "SysDesc layout");
 // Rows per workgroup (one per thread) of the split Arnoldi step.
 constexpr int kArnRows = 256;
 
@@ -378,6 +381,7 @@ class Engine {
                      bool reduce, unsigned long long* ctr, hipStream_t s);
   std::vector<GemvGroup> groups_;
   bool split_ = false;    // Arnoldi step split over row slices
+  bool prev_split_ = false;  // layout the captured steps were recorded with
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
   // lagged status snapshot inside a cycle: flags copied to pinned memory

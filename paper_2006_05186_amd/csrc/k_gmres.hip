@@ -119,11 +119,18 @@ __device__ void hessenberg_column(const SysDesc& D, int j, cf64* h, const double
   const int m = D.m;
   cf64* Hc = D.H + (int64_t)(m + 1) * j;
   // previous rotations: (h_k, h_k+1) <- (c h_k + s h_k+1, -conj(s) h_k + c h_k+1)
-  for (int k = 0; k < j; ++k) {
-    const double c = rc[k];
-    const cf64 s = rs[k], a = h[k], b = h[k + 1];
-    h[k] = cf64{c * a.re + s.re * b.re - s.im * b.im, c * a.im + s.re * b.im + s.im * b.re};
-    h[k + 1] = cf64{-(s.re * a.re + s.im * a.im) + c * b.re, -(s.re * a.im - s.im * a.re) + c * b.im};
+  // the running entry h[k] is carried in registers: only it depends on the
+  // previous rotation, the loads of rc, rs and h[k+1] do not
+  if (j > 0) {
+    cf64 a = h[0];
+#pragma unroll 4
+    for (int k = 0; k < j; ++k) {
+      const double c = rc[k];
+      const cf64 s = rs[k], b = h[k + 1];
+      h[k] = cf64{c * a.re + s.re * b.re - s.im * b.im, c * a.im + s.re * b.im + s.im * b.re};
+      a = cf64{-(s.re * a.re + s.im * a.im) + c * b.re, -(s.re * a.im - s.im * a.re) + c * b.im};
+    }
+    h[j] = a;
   }
   // new rotation zeroing h_{j+1}
   const cf64 a = h[j];
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, 
   const SysDesc D = sd[blockIdx.x];
   int* st = D.sysi;
   if (!st[1]) return;
-  const int M = D.M, m = D.m;
+  const int M = D.M;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   cplx<R>* V = (cplx<R>*)D.basis;
   cplx<R>* w = V + (int64_t)(j + 1) * M;
@@ -220,14 +227,17 @@ __global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, 
       for (int u = 0; u < kChunk; ++u) ar[u] = ai[u] = 0.0;
       double ww = 0.0;
       for (int i = tid; i < M; i += BS) {
+        // clamped (in-bounds) loads, all in flight together
         const cplx<R> x = w[i];
+        cplx<R> v[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) v[u] = V[(int64_t)min(kc + u, j) * M + i];
         if (kc == 0) ww += (double)x.re * x.re + (double)x.im * x.im;
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
           if (kc + u <= j) {
-            const cplx<R> v = V[(int64_t)(kc + u) * M + i];
-            ar[u] += (double)v.re * x.re + (double)v.im * x.im;
-            ai[u] += (double)v.re * x.im - (double)v.im * x.re;
+            ar[u] += (double)v[u].re * x.re + (double)v[u].im * x.im;
+            ai[u] += (double)v[u].re * x.im - (double)v[u].im * x.re;
           }
       }
       // entries 0..kChunk-1: real parts, kChunk..2kChunk-1: imaginary parts
@@ -320,199 +330,328 @@ __global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, 
 // same order, so all workgroups of a system take identical decisions.
 __device__ __forceinline__ int arn_stride(int m) { return 4 * (m + 1) + 2; }
 
-// out[k] (k <= j) = sum over this slice of conj(v_k[i]) x_i (x_i = 0 and no
-// loads where !valid); kC inner products per reduction round.
-template <typename R, int kC>
-__device__ __forceinline__ void slice_dots(const cplx<R>* __restrict__ V, int64_t M, int i, bool valid,
-                           cplx<R> x, int j, cf64* out, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// The kernels are latency-bound (a few KB per workgroup), so each one issues
+// all of its loads in one round: the open flag, the product partials or w,
+// a chunk of kVC basis entries per row (held in registers and used by both
+// the update and the second inner products) and the slot sums it needs.
+// Closed systems and slices past the end run the same code and write
+// nothing (a branch before the loads would add a dependent round trip).
+// kVC, the basis vectors per register chunk, is 16 while j < 16 and 32 after
+// (one chunk covers the default restart length).
+constexpr int kPB = 32;  // product partials summed per round of loads
+
+template <typename R> using gcplx = const CQM_GLOBAL cplx<R>;
+
+template <typename R, int kVC>
+__device__ __forceinline__ void load_chunk(gcplx<R>* __restrict__ V, int64_t M, int ic, int kc, int j,
+                                           cplx<R> (&v)[kVC]) {
+#pragma unroll
+  for (int u = 0; u < kVC; ++u) v[u] = V[(int64_t)min(kc + u, j) * M + ic];
+}
+
+// Slice inner products of chunk kc with x: out[2k], out[2k+1] = re, im of
+// sum_i conj(v_k[i]) x_i for kc <= k <= min(kc + kVC - 1, j); with nrm, also
+// *nrm = sum_i |x_i|^2.  Written only when wr.  red: LDS, 4 (2 kVC + 1)
+// doubles.
+template <typename R, int kVC>
+__device__ __forceinline__ void chunk_dots(const cplx<R> (&v)[kVC], cplx<R> x, bool valid, int kc,
+                                           int j, bool wr, double* out, double* nrm, double* red) {
   constexpr int NW = kArnRows / 64;
-  // loads use clamped (in-bounds) indices and are masked afterwards, so all
-  // kC of them are in flight together
-  const int ic = valid ? i : (int)M - 1;
-  for (int kc = 0; kc <= j; kc += kC) {
-    cplx<R> v[kC];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double a[2 * kVC];
 #pragma unroll
-    for (int u = 0; u < kC; ++u) v[u] = V[(int64_t)min(kc + u, j) * M + ic];
-    double a[2 * kC];
+  for (int u = 0; u < kVC; ++u) {
+    const bool in = valid && kc + u <= j;
+    const double vr = in ? (double)v[u].re : 0.0, vi = in ? (double)v[u].im : 0.0;
+    a[u] = vr * x.re + vi * x.im;
+    a[kVC + u] = vr * x.im - vi * x.re;
+  }
+  wave_reduce_scatter<2 * kVC, 32>(a, lane);  // lane t: entry t >> kSh
+  constexpr int kSh = kVC == 32 ? 0 : kVC == 16 ? 1 : 2;
+  double nn = 0.0;
+  if (nrm) nn = wave_sum(valid ? (double)x.re * x.re + (double)x.im * x.im : 0.0);
+  __syncthreads();
+  if ((lane & ((1 << kSh) - 1)) == 0) red[wv * 2 * kVC + (lane >> kSh)] = a[0];
+  if (nrm && lane == 0) red[NW * 2 * kVC + wv] = nn;
+  __syncthreads();
+  if (wr && tid < 2 * kVC) {
+    // entry t < kVC: real part of product kc + t; else imaginary part
+    const int k = kc + (tid % kVC), comp = tid / kVC;
+    if (k <= j) {
+      double t = 0.0;
 #pragma unroll
-    for (int u = 0; u < kC; ++u) {
-      const bool in = valid && kc + u <= j;
-      const double vr = in ? (double)v[u].re : 0.0, vi = in ? (double)v[u].im : 0.0;
-      a[u] = vr * x.re + vi * x.im;
-      a[kC + u] = vr * x.im - vi * x.re;
+      for (int q = 0; q < NW; ++q) t += red[q * 2 * kVC + tid];
+      as_global(out)[2 * k + comp] = t;
     }
-    wave_reduce_scatter<2 * kC, 32>(a, lane);
-    constexpr int kSh = kC == 32 ? 0 : kC == 16 ? 1 : 2;
-    __syncthreads();
-    if ((lane & ((1 << kSh) - 1)) == 0) red[wv * 2 * kC + (lane >> kSh)] = a[0];
-    __syncthreads();
-    if (tid < kC && kc + tid <= j) {
-      double sr = 0.0, si = 0.0;
+  }
+  if (wr && nrm && tid == 2 * kVC) {
+    double t = 0.0;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        sr += red[q * 2 * kC + tid];
-        si += red[q * 2 * kC + kC + tid];
-      }
-      out[kc + tid] = cf64{sr, si};
-    }
+    for (int q = 0; q < NW; ++q) t += red[NW * 2 * kVC + q];
+    *as_global(nrm) = t;
   }
 }
 
-// inner products per reduction round (register budget: 2 kC doubles and kC
-// loaded basis entries per thread)
-template <typename R> struct ArnChunk { static constexpr int v = 16; };
+// re, im -= sum_{k in chunk} c_k v_k (c: LDS, re/im interleaved doubles).
+template <typename R, int kVC>
+__device__ __forceinline__ void chunk_update(const cplx<R> (&v)[kVC], int kc, int j, const double* c,
+                                             double& re, double& im) {
+#pragma unroll
+  for (int u = 0; u < kVC; ++u) {
+    const bool in = kc + u <= j;
+    const int k = min(kc + u, j);
+    const double cr = in ? c[2 * k] : 0.0, ci = in ? c[2 * k + 1] : 0.0;
+    re -= cr * v[u].re - ci * v[u].im;
+    im -= cr * v[u].im + ci * v[u].re;
+  }
+}
 
-template <typename R>
+// sum_{q < S} P[q * stride] in slot order.  The first eight loads are
+// straight-line code (clamped indices), so they join the caller's round of
+// loads; slices beyond eight take further rounds.
+__device__ __forceinline__ double slot_sum_g(const CQM_GLOBAL double* __restrict__ P, int S,
+                                             int64_t stride) {
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)min(u, S - 1) * stride];
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (u < S) acc += v[u];
+  for (int q0 = 8; q0 < S; q0 += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(int64_t)min(q0 + u, S - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q0 + u < S) acc += v[u];
+  }
+  return acc;
+}
+
+template <typename R, int kVC>
 __global__ __launch_bounds__(kArnRows) void k_arn_dots(const SysDesc* __restrict__ sd, int j,
                                                       int fused, unsigned long long* ctr) {
-  constexpr int kC = ArnChunk<R>::v;
-  __shared__ double red[(kArnRows / 64) * 2 * kC];
+  __shared__ double red[(kArnRows / 64) * (2 * kVC + 1)];
   const SysDesc D = sd[blockIdx.y];
-  if (!D.sysi[1]) return;
   const int M = D.M, m = D.m;
   const int s = blockIdx.x;
-  if (s * kArnRows >= M) return;
   const int i = s * kArnRows + threadIdx.x;
   const bool valid = i < M;
-  cplx<R>* V = (cplx<R>*)D.basis;
-  cplx<R> x;
-  x.re = R(0);
-  x.im = R(0);
-  if (valid) {
-    if (fused && D.symp) {
-      // w = A v_j of a stored operator: sum its tile partials here
-      x = sym_row_sum<R>((const cplx<R>*)D.symp, M, i);
-      V[(int64_t)(j + 1) * M + i] = x;
-    } else {
-      x = V[(int64_t)(j + 1) * M + i];
-    }
+  const int ic = valid ? i : M - 1;
+  gcplx<R>* V = as_global((const cplx<R>*)D.basis);
+  // w = A v_j: summed here from the tile partials of a stored operator
+  const bool sum = fused && D.symp;
+  const int nt = sym_blocks(M), ntB = nt * kSymB;
+  gcplx<R>* Pp = as_global((const cplx<R>*)(sum ? D.symp : D.basis));
+  cplx<R> pv[kPB];
+  if (sum) {
+#pragma unroll
+    for (int u = 0; u < kPB; ++u) pv[u] = Pp[(int64_t)min(u, nt - 1) * ntB + ic];
+  } else {
+    pv[0] = V[(int64_t)(j + 1) * M + ic];
   }
-  double* P = D.part + (int64_t)s * arn_stride(m);
-  slice_dots<R, kC>(V, M, i, valid, x, j, reinterpret_cast<cf64*>(P), red);
-  const double nn = block_sum((double)x.re * x.re + (double)x.im * x.im, red);
-  if (threadIdx.x == 0) {
-    P[4 * (m + 1)] = nn;
-    if (ctr) {
-      const unsigned long long rows = min(kArnRows, M - s * kArnRows);
-      atomicAdd(ctr, rows * (j + 2) * sizeof(cplx<R>));
+  cplx<R> v[kVC];
+  load_chunk<R, kVC>(V, M, ic, 0, j, v);
+  const bool wr = *as_global(D.sysi + 1) != 0 && s * kArnRows < M;
+  cplx<R> x = pv[0];
+  if (sum) {
+    R re = R(0), im = R(0);
+#pragma unroll
+    for (int u = 0; u < kPB; ++u)
+      if (u < nt) {
+        re += pv[u].re;
+        im += pv[u].im;
+      }
+    for (int Y0 = kPB; Y0 < nt; Y0 += kPB) {  // meshes of more than kPB blocks
+#pragma unroll
+      for (int u = 0; u < kPB; ++u) pv[u] = Pp[(int64_t)min(Y0 + u, nt - 1) * ntB + ic];
+#pragma unroll
+      for (int u = 0; u < kPB; ++u)
+        if (Y0 + u < nt) {
+          re += pv[u].re;
+          im += pv[u].im;
+        }
     }
+    x = cmake<R>(re, im);
+  }
+  if (!valid) x = cmake<R>(R(0), R(0));
+  double* P = D.part + (int64_t)s * arn_stride(m);
+  chunk_dots<R, kVC>(v, x, valid, 0, j, wr, P, P + 4 * (m + 1), red);
+  for (int kc = kVC; kc <= j; kc += kVC) {
+    load_chunk<R, kVC>(V, M, ic, kc, j, v);
+    chunk_dots<R, kVC>(v, x, valid, kc, j, wr, P, nullptr, red);
+  }
+  if (!wr) return;
+  if (sum && valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = x;
+  if (ctr && threadIdx.x == 0) {
+    const unsigned long long rows = min(kArnRows, M - s * kArnRows);
+    atomicAdd(ctr, rows * (j + 2) * sizeof(cplx<R>));
   }
 }
 
-template <typename R>
+template <typename R, int kVC>
 __global__ __launch_bounds__(kArnRows) void k_arn_update(const SysDesc* __restrict__ sd, int j,
                                                         unsigned long long* ctr) {
-  constexpr int kC = ArnChunk<R>::v;
-  __shared__ double red[(kArnRows / 64) * 2 * kC];
-  __shared__ cf64 coef[kMaxM + 1];
+  __shared__ double red[(kArnRows / 64) * (2 * kVC + 1)];
+  __shared__ double cf[2 * (kMaxM + 1)];
   const SysDesc D = sd[blockIdx.y];
-  if (!D.sysi[1]) return;
   const int M = D.M, m = D.m;
   const int s = blockIdx.x;
-  if (s * kArnRows >= M) return;
   const int S = (M + kArnRows - 1) / kArnRows;
   const int str = arn_stride(m);
-  for (int k = threadIdx.x; k <= j; k += kArnRows)
-    coef[k] = cf64{slot_sum(D.part + 2 * k, S, str), slot_sum(D.part + 2 * k + 1, S, str)};
-  __syncthreads();
   const int i = s * kArnRows + threadIdx.x;
   const bool valid = i < M;
-  cplx<R>* V = (cplx<R>*)D.basis;
-  cplx<R> x;
-  x.re = R(0);
-  x.im = R(0);
-  if (valid) {
-    cplx<R>* w = V + (int64_t)(j + 1) * M;
-    const cplx<R> x0 = w[i];
-    double re = x0.re, im = x0.im;
-    basis_combine<R, 16>(V, M, i, coef, j + 1, -1.0, re, im);
-    x.re = (R)re;
-    x.im = (R)im;
-    w[i] = x;
+  const int ic = valid ? i : M - 1;
+  gcplx<R>* V = as_global((const cplx<R>*)D.basis);
+  const cplx<R> x0 = V[(int64_t)(j + 1) * M + ic];
+  cplx<R> v[kVC];
+  load_chunk<R, kVC>(V, M, ic, 0, j, v);
+  const CQM_GLOBAL double* part = as_global((const double*)D.part);
+  {
+    // coefficient entry t = threadIdx.x (clamped loads; stored if t is one)
+    const int n2j = 2 * (j + 1), t = threadIdx.x;
+    const double val = slot_sum_g(part + min(t, n2j - 1), S, str);
+    if (t < n2j) cf[t] = val;
+    for (int t2 = t + kArnRows; t2 < n2j; t2 += kArnRows) cf[t2] = slot_sum_g(part + t2, S, str);
   }
+  const bool wr = *as_global(D.sysi + 1) != 0 && s * kArnRows < M;
+  __syncthreads();
+  // w' = w - V c
+  double re = x0.re, im = x0.im;
+  chunk_update<R, kVC>(v, 0, j, cf, re, im);
+  for (int kc = kVC; kc <= j; kc += kVC) {
+    cplx<R> u[kVC];
+    load_chunk<R, kVC>(V, M, ic, kc, j, u);
+    chunk_update<R, kVC>(u, kc, j, cf, re, im);
+  }
+  const cplx<R> x = valid ? cmake<R>((R)re, (R)im) : cmake<R>(R(0), R(0));
+  // c' = V^H w' and ||w'||^2 (the first chunk from registers)
   double* P = D.part + (int64_t)s * str;
-  slice_dots<R, kC>(V, M, i, valid, x, j, reinterpret_cast<cf64*>(P + 2 * (m + 1)), red);
-  const double nn = block_sum((double)x.re * x.re + (double)x.im * x.im, red);
-  if (threadIdx.x == 0) {
-    P[4 * (m + 1) + 1] = nn;
-    if (ctr) {
-      const unsigned long long rows = min(kArnRows, M - s * kArnRows);
-      atomicAdd(ctr, rows * (j + 3) * sizeof(cplx<R>));
-    }
+  chunk_dots<R, kVC>(v, x, valid, 0, j, wr, P + 2 * (m + 1), P + 4 * (m + 1) + 1, red);
+  for (int kc = kVC; kc <= j; kc += kVC) {
+    load_chunk<R, kVC>(V, M, ic, kc, j, v);
+    chunk_dots<R, kVC>(v, x, valid, kc, j, wr, P + 2 * (m + 1), nullptr, red);
+  }
+  if (!wr) return;
+  if (valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = x;
+  if (ctr && threadIdx.x == 0) {
+    const unsigned long long rows = min(kArnRows, M - s * kArnRows);
+    atomicAdd(ctr, rows * (j + 3) * sizeof(cplx<R>));
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restrict__ sd, int j,
-                                                        unsigned long long* ctr) {
-  __shared__ cf64 c2[kMaxM + 1];
+// The Hessenberg column of step j (one extra workgroup per system, running
+// beside the row slices): h = c + c', h_{j+1} = ||w''||, previous rotations,
+// new rotation, residual estimate.
+__device__ __forceinline__ void arn_hessenberg(const SysDesc& D, int j, int S, int str) {
+  __shared__ double c1[2 * (kMaxM + 1)], c2[2 * (kMaxM + 1)];
   __shared__ cf64 h[kMaxM + 2];
   __shared__ double rc_s[kMaxM];
   __shared__ cf64 rs_s[kMaxM];
-  __shared__ double nsh[2];
-  __shared__ int second_s;
+  __shared__ double nsh[3];
+  const int m = D.m, tid = threadIdx.x, lane = tid & 63;
+  const CQM_GLOBAL double* part = as_global((const double*)D.part);
+  const int n2j = 2 * (j + 1), T = 2 * n2j + 2;
+  // task t: c (t < n2j), c' (t < 2 n2j), ||w||^2 and ||w'||^2
+  auto task_off = [&](int t) -> int64_t {
+    return t < n2j ? t : t < 2 * n2j ? 2 * (m + 1) + (t - n2j) : 4 * (m + 1) + (t - 2 * n2j);
+  };
+  auto task_put = [&](int t, double val) {
+    if (t < n2j) c1[t] = val;
+    else if (t < 2 * n2j) c2[t - n2j] = val;
+    else nsh[t - 2 * n2j] = val;
+  };
+  const double val = slot_sum_g(part + task_off(min(tid, T - 1)), S, str);
+  const int kq = min(tid, m - 1);
+  const double rcv = as_global((const double*)D.cs)[kq];
+  const cf64 rsv = as_global((const cf64*)D.sn)[kq];
+  const cf64 gj = as_global((const cf64*)D.g)[j];
+  const bool open = *as_global(D.sysi + 1) != 0;
+  if (tid < T) task_put(tid, val);
+  for (int t = tid + kArnRows; t < T; t += kArnRows) task_put(t, slot_sum_g(part + task_off(t), S, str));
+  if (tid < j) {
+    rc_s[tid] = rcv;
+    rs_s[tid] = rsv;
+  }
+  __syncthreads();
+  const bool second = nsh[1] < 0.49 * nsh[0];
+  if (tid <= j)
+    h[tid] = second ? cf64{c1[2 * tid] + c2[2 * tid], c1[2 * tid + 1] + c2[2 * tid + 1]}
+                    : cf64{c1[2 * tid], c1[2 * tid + 1]};
+  if (tid < 64) {
+    double q = 0.0;
+    if (second && lane <= j) q = c2[2 * lane] * c2[2 * lane] + c2[2 * lane + 1] * c2[2 * lane + 1];
+    q = wave_sum(q);
+    if (lane == 0) nsh[2] = second ? fmax(nsh[1] - q, 0.0) : nsh[1];
+  }
+  __syncthreads();
+  if (!open || tid != 0) return;
+  const double nr = sqrt(nsh[2]);
+  h[j + 1] = cf64{nr, 0.0};
+  hessenberg_column(D, j, h, rc_s, rs_s, gj, nr);
+}
+
+// Grid (S_max + 1, systems): x-blocks below S are row slices, the last one
+// forms the Hessenberg column.
+template <typename R, int kVC>
+__global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restrict__ sd, int j,
+                                                        unsigned long long* ctr) {
+  __shared__ double c2[2 * (kMaxM + 1)];
+  __shared__ double nsh[3];
   const SysDesc D = sd[blockIdx.y];
-  if (!D.sysi[1]) return;
   const int M = D.M, m = D.m;
   const int s = blockIdx.x;
-  if (s * kArnRows >= M) return;
   const int S = (M + kArnRows - 1) / kArnRows;
   const int str = arn_stride(m);
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    const double n0 = slot_sum(D.part + 4 * (m + 1), S, str);
-    const double n1 = slot_sum(D.part + 4 * (m + 1) + 1, S, str);
-    nsh[0] = n0;
-    nsh[1] = n1;
-    second_s = n1 < 0.49 * n0;
+  if (s == (int)gridDim.x - 1) {
+    arn_hessenberg(D, j, S, str);
+    return;
   }
-  __syncthreads();
-  const bool second = second_s != 0;
-  for (int k = tid; k <= j; k += kArnRows) {
-    const double* P = D.part + 2 * (m + 1) + 2 * k;
-    c2[k] = second ? cf64{slot_sum(P, S, str), slot_sum(P + 1, S, str)} : cf64{0.0, 0.0};
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double n2 = nsh[1];
-    if (second) {
-      for (int k = 0; k <= j; ++k) n2 -= c2[k].re * c2[k].re + c2[k].im * c2[k].im;
-      n2 = fmax(n2, 0.0);
-    }
-    nsh[0] = sqrt(n2);
-  }
-  __syncthreads();
-  const double nr = nsh[0];
-  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int i = s * kArnRows + tid;
-  cplx<R>* V = (cplx<R>*)D.basis;
-  if (i < M) {
-    cplx<R>* w = V + (int64_t)(j + 1) * M;
-    const cplx<R> x0 = w[i];
-    double re = x0.re, im = x0.im;
-    if (second) basis_combine<R, 16>(V, M, i, c2, j + 1, -1.0, re, im);
-    cplx<R> o;
-    o.re = (R)(re * inv);
-    o.im = (R)(im * inv);
-    w[i] = o;
+  const bool valid = i < M;
+  const int ic = valid ? i : M - 1;
+  gcplx<R>* V = as_global((const cplx<R>*)D.basis);
+  const cplx<R> x0 = V[(int64_t)(j + 1) * M + ic];
+  // the first chunk is loaded before the second pass is known to be needed
+  cplx<R> v[kVC];
+  load_chunk<R, kVC>(V, M, ic, 0, j, v);
+  // slot sums, task t: c' (t < 2 (j+1)), then ||w||^2 and ||w'||^2
+  const CQM_GLOBAL double* part = as_global((const double*)D.part);
+  const int n2j = 2 * (j + 1), T = n2j + 2;
+  const double val = slot_sum_g(part + (min(tid, T - 1) < n2j ? 2 * (m + 1) + min(tid, T - 1)
+                                                                 : 4 * (m + 1) + (min(tid, T - 1) - n2j)),
+                                S, str);
+  const bool wr = *as_global(D.sysi + 1) != 0 && s * kArnRows < M;
+  if (tid < n2j) c2[tid] = val;
+  else if (tid < T) nsh[tid - n2j] = val;
+  for (int t = tid + kArnRows; t < n2j; t += kArnRows) c2[t] = slot_sum_g(part + 2 * (m + 1) + t, S, str);
+  __syncthreads();
+  const bool second = nsh[1] < 0.49 * nsh[0];
+  if (tid < 64) {
+    // ||w''||^2 = ||w'||^2 - ||c'||^2 (basis orthonormal); j + 1 <= 64 lanes
+    double q = 0.0;
+    if (second && lane <= j) q = c2[2 * lane] * c2[2 * lane] + c2[2 * lane + 1] * c2[2 * lane + 1];
+    q = wave_sum(q);
+    if (lane == 0) nsh[2] = second ? fmax(nsh[1] - q, 0.0) : nsh[1];
   }
+  __syncthreads();
+  const double nr = sqrt(nsh[2]);
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  double re = x0.re, im = x0.im;
+  if (second) {
+    chunk_update<R, kVC>(v, 0, j, c2, re, im);
+    for (int kc = kVC; kc <= j; kc += kVC) {
+      load_chunk<R, kVC>(V, M, ic, kc, j, v);
+      chunk_update<R, kVC>(v, kc, j, c2, re, im);
+    }
+  }
+  if (!wr) return;
+  if (valid)
+    as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = cmake<R>((R)(re * inv), (R)(im * inv));
   if (ctr && tid == 0) {
     const unsigned long long rows = min(kArnRows, M - s * kArnRows);
     atomicAdd(ctr, rows * (second ? j + 3 : 2) * sizeof(cplx<R>));
-  }
-  if (s != 0) return;
-  for (int k = tid; k <= j; k += kArnRows)
-    h[k] = cf64{slot_sum(D.part + 2 * k, S, str) + c2[k].re,
-                slot_sum(D.part + 2 * k + 1, S, str) + c2[k].im};
-  for (int k = tid; k < j; k += kArnRows) {
-    rc_s[k] = D.cs[k];
-    rs_s[k] = D.sn[k];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    h[j + 1] = cf64{nr, 0.0};
-    hessenberg_column(D, j, h, rc_s, rs_s, D.g[j], nr);
   }
 }
 
@@ -578,17 +717,24 @@ void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner
   hipLaunchKernelGGL((k_cycle_start<R>), dim3(n), dim3(256), 0, s, sd, outer_tol, inner_tol);
   CQM_HIP(hipGetLastError());
 }
-// One workgroup per system (threads per system: latency of the block
-// reductions dominates for short vectors, memory parallelism for long ones),
-// or the three-launch split over row slices.
+// One workgroup per system, or the three launches over row slices (the
+// finish launch has one more x-block per system for the Hessenberg column).
 template <typename R>
 void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
                     unsigned long long* ctr, hipStream_t s) {
+  const int f = fused ? 1 : 0;
   if (split) {
-    const dim3 grid((maxM + kArnRows - 1) / kArnRows, n);
-    hipLaunchKernelGGL((k_arn_dots<R>), grid, dim3(kArnRows), 0, s, sd, j, fused ? 1 : 0, ctr);
-    hipLaunchKernelGGL((k_arn_update<R>), grid, dim3(kArnRows), 0, s, sd, j, ctr);
-    hipLaunchKernelGGL((k_arn_finish<R>), grid, dim3(kArnRows), 0, s, sd, j, ctr);
+    const int S = (maxM + kArnRows - 1) / kArnRows;
+    const dim3 grid(S, n), gfin(S + 1, n), blk(kArnRows);
+    if (j < 16) {
+      hipLaunchKernelGGL((k_arn_dots<R, 16>), grid, blk, 0, s, sd, j, f, ctr);
+      hipLaunchKernelGGL((k_arn_update<R, 16>), grid, blk, 0, s, sd, j, ctr);
+      hipLaunchKernelGGL((k_arn_finish<R, 16>), gfin, blk, 0, s, sd, j, ctr);
+    } else {
+      hipLaunchKernelGGL((k_arn_dots<R, 32>), grid, blk, 0, s, sd, j, f, ctr);
+      hipLaunchKernelGGL((k_arn_update<R, 32>), grid, blk, 0, s, sd, j, ctr);
+      hipLaunchKernelGGL((k_arn_finish<R, 32>), gfin, blk, 0, s, sd, j, ctr);
+    }
   } else if (maxM < 3072) {
     hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(n), dim3(256), 0, s, sd, j, ctr);
   } else {
@@ -611,3 +757,4 @@ template void launch_cycle_finish<float>(const SysDesc*, int, hipStream_t);
 template void launch_cycle_finish<double>(const SysDesc*, int, hipStream_t);
 
 }  // namespace cqm
+
