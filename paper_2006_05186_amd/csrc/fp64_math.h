@@ -75,50 +75,55 @@ __device__ __forceinline__ void sincos_bounded(double t, double* s, double* c) {
 // exponential function in IEEE floating-point arithmetic", ACM TOMS 1989,
 // and the same idea for sine/cosine): reduce by a multiple of a table step,
 // look the step's value up, and evaluate a short Taylor polynomial on the
-// small remainder.  `tab` (in LDS) holds 2^(j/64), then sin(j pi/32) and
-// cos(j pi/32) for j = 0..63 (kFp64TabLen doubles, filled on the host).
-constexpr int kFp64TabLen = 192;
+// small remainder.  `tab` (in LDS, 16-byte aligned) holds 2^(j/256) for
+// j = 0..255, then the pairs (sin, cos)(2 pi j/256) (kFp64TabLen doubles,
+// filled on the host in extended precision).  The nearest integer k comes
+// from adding 1.5 * 2^52 (its low 32 bits are then k in two's complement),
+// which also gives k for the table index without a conversion; the step is
+// split into a leading part of 35 bits (k * hi exact for |k| < 2^18) and a
+// remainder.  Both functions are branch-free.
+constexpr int kFp64TabLen = 768;
+constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
 
 __device__ __forceinline__ double exp_tab(double x, const double* tab) {
-  // x <= 0 expected; x = (64 m + j) ln2/64 + r, |r| <= ln2/128
-  if (x < -708.0) return 0.0;
-  const double k = rint(x * 92.332482616893657);
-  double r = fma(-k, 0.01083042469326756, x);
-  r = fma(-k, 2.9815858269852933e-12, r);
-  // exp r through r^5 (truncation < 3e-17 relative)
-  double p = 0.008333333333333333;       // 1/5!
-  p = fma(p, r, 0.041666666666666664);    // 1/4!
+  // x = (256 m + j) ln2/256 + r, |r| <= ln2/512; x < -708 gives 0
+  const double xc = fmax(x, -708.0);
+  const double kd = fma(xc, 369.3299304675746, kRoundMagic);  // 256/ln2
+  const int ik = (int)__double_as_longlong(kd);
+  const double k = kd - kRoundMagic;
+  double r = fma(-k, 0.0027076061741126978, xc);
+  r = fma(-k, -5.0411407304988844e-14, r);
+  // exp r through r^4 (truncation < 4e-17 relative)
+  double p = 0.041666666666666664;        // 1/4!
   p = fma(p, r, 0.16666666666666666);     // 1/3!
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  const int ik = (int)k;
-  return ldexp(tab[ik & 63] * p, ik >> 6);
+  const double e = ldexp(tab[ik & 255] * p, ik >> 8);
+  return x < -708.0 ? 0.0 : e;
 }
 
 __device__ __forceinline__ void sincos_tab(double t, const double* tab, double* s, double* c) {
-  // t = k pi/32 + r, |r| <= pi/64; (sin, cos)(k pi/32) from the table (k mod 64)
-  const double k = rint(t * 10.185916357881302);
-  double r = fma(-k, 0.098174770420882851, t);
-  r = fma(-k, 3.7981878164399787e-12, r);
-  r = fma(-k, 1.2639164054974691e-22, r);
+  // t = k 2pi/256 + r, |r| <= pi/256; (sin, cos)(2 pi k/256) from the table
+  const double kd = fma(t, 40.74366543152521, kRoundMagic);  // 256/(2 pi)
+  const int ik = (int)__double_as_longlong(kd);
+  const double k = kd - kRoundMagic;
+  double r = fma(-k, 0.024543692606130207, t);
+  r = fma(-k, 4.005225236866436e-14, r);
   const double r2 = r * r;
-  // sin r through r^9, cos r through r^10 (truncation < 1e-19)
-  double ps = 2.7557319223985893e-06;         // 1/9!
-  ps = fma(ps, r2, -0.0001984126984126984);    // -1/7!
-  ps = fma(ps, r2, 0.008333333333333333);      // 1/5!
-  ps = fma(ps, r2, -0.16666666666666666);      // -1/3!
+  // sin r through r^7, cos r - 1 through r^6 (truncation < 2e-20)
+  double ps = -0.0001984126984126984;         // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);     // 1/5!
+  ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
   const double sr = fma(ps * r2, r, r);
-  double pc = -2.755731922398589e-07;          // -1/10!
-  pc = fma(pc, r2, 2.48015873015873e-05);      // 1/8!
-  pc = fma(pc, r2, -0.001388888888888889);     // -1/6!
-  pc = fma(pc, r2, 0.041666666666666664);      // 1/4!
-  pc = fma(pc, r2, -0.5);                      // -1/2!
-  const double cr = fma(pc, r2, 1.0);
-  const int j = ((int)k) & 63;
-  const double sa = tab[64 + j], ca = tab[128 + j];
-  *s = fma(sa, cr, ca * sr);
-  *c = fma(ca, cr, -(sa * sr));
+  double pc = -0.001388888888888889;          // -1/6!
+  pc = fma(pc, r2, 0.041666666666666664);     // 1/4!
+  pc = fma(pc, r2, -0.5);                     // -1/2!
+  const double cm1 = pc * r2;
+  const double2 sc = *reinterpret_cast<const double2*>(tab + 256 + 2 * (ik & 255));
+  // sin(A + r) = sA + (sA (cos r - 1) + cA sin r), likewise cos(A + r)
+  *s = fma(sc.y, sr, fma(sc.x, cm1, sc.x));
+  *c = fma(-sc.x, sr, fma(sc.y, cm1, sc.y));
 }
 
 }  // namespace cqm

@@ -180,7 +180,7 @@ struct MeshDev {
   cf64* tw_inv = nullptr;         // F: zeta^+k
   double* rho_pow = nullptr;      // F: rho^n
   double* rho_ipow = nullptr;     // F: rho^-n / F
-  double* ftab = nullptr;         // FP64 exp/sincos tables (2^(j/64), sin, cos(j pi/32))
+  double* ftab = nullptr;         // FP64 exp/sincos tables (2^(j/256), (sin, cos)(2 pi j/256))
   double* ea64 = nullptr;         // Fpad
   double* pb64 = nullptr;
   float* ea32 = nullptr;

@@ -209,10 +209,10 @@ void upload_problem(Problem& p) {
   // tables of the FP64 exp/sincos (extended precision, rounded once)
   std::vector<double> ftab(kFp64TabLen);
   const long double pi_l = 3.141592653589793238462643383279502884L;
-  for (int j = 0; j < 64; ++j) {
-    ftab[j] = (double)std::exp2((long double)j / 64.0L);
-    ftab[64 + j] = (double)std::sin(pi_l * j / 32.0L);
-    ftab[128 + j] = (double)std::cos(pi_l * j / 32.0L);
+  for (int j = 0; j < 256; ++j) {
+    ftab[j] = (double)std::exp2((long double)j / 256.0L);
+    ftab[256 + 2 * j] = (double)std::sin(pi_l * j / 128.0L);
+    ftab[256 + 2 * j + 1] = (double)std::cos(pi_l * j / 128.0L);
   }
   p.dev.ftab = upload(ftab);
   p.dev.ea32 = upload(ea32);
