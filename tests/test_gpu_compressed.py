@@ -1,6 +1,7 @@
 """GPU parity of the compressed operator (H2 x MACA) against the oracle's
-compressed operator, and of the compressed solve against the oracle's solve
-with the same compressed operator."""
+compressed operator, of the compressed solve against the oracle's solve
+with the same compressed operator, and of a compressed solve with strict
+admissibility against the plain oracle solve."""
 import sys
 
 import numpy as np
@@ -79,3 +80,28 @@ def test_compressed_solve_matches_oracle_compressed_solve(ctx, case):
             f"(oracle {im_ref:.1e})")
         assert rc == C.CQM_OK and err < 1e-6
         p.close()
+
+
+def test_compressed_solve_meets_1e5_against_plain_oracle(ctx):
+    """The mixed compressed solve of the 320-triangle sphere (N = 32) against
+    the plain oracle solution: with eps = 1e-10 it must meet the 1e-5
+    time-domain bound of the mixed H2/ACA path.  eps = 1e-6 is reported
+    beside it: its error (~7e-4) grows with n, the MACA error of the weakest
+    frequencies being amplified by rho^-n in the inverse transform."""
+    wl = W.C1
+    V, T = wl.mesh()
+    w = wl.wave
+    say("compressed (eps 1e-10 and 1e-6) vs plain oracle, M=320")
+    qref = O.solve(V, T, wl.N, wl.T, direction=w.direction, sigma=w.sigma, t0=w.t0,
+                   amplitude=w.amplitude)
+    _, _, area = O.triangle_quadrature(V, T)
+    errs = {}
+    for eps in (1e-10, 1e-6):
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_H2ACA, eps_aca=eps)
+        p.set_plane_wave(w.direction, w.sigma, w.t0, w.amplitude)
+        q, rc, d = p.solve()
+        errs[eps] = O.rel_error(q.cpu().numpy(), qref, area)
+        say(f"  eps={eps} rc={rc} max rank {d.max_rank} err vs plain oracle {errs[eps]:.2e}")
+        assert rc == C.CQM_OK
+        p.close()
+    assert errs[1e-10] < 1e-5
