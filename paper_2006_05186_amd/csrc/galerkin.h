@@ -48,11 +48,13 @@ __device__ inline cf64 near_dynamic_entry(const double4* __restrict__ pts, int i
       double fr, fi;
       if (r > 0.0) {
         const double x = -sr * r, y = -si * r;
-        double sn, cs;
-        sincos(y, &sn, &cs);
-        const double sh = sin(0.5 * y);
-        fr = (expm1(x) * cs - 2.0 * sh * sh) / r;
-        fi = (exp(x) * sn) / r;
+        // from the half angle: sin y = 2 sh ch, cos y - 1 = -2 sh^2, and
+        // exp(x) = 1 + expm1(x): two library calls per point pair
+        double sh, ch;
+        sincos(0.5 * y, &sh, &ch);
+        const double em1 = expm1(x), sh2 = 2.0 * sh * sh;
+        fr = (em1 * (1.0 - sh2) - sh2) / r;
+        fi = ((1.0 + em1) * (2.0 * sh * ch)) / r;
       } else {
         fr = -sr;
         fi = -si;
