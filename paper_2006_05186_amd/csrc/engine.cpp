@@ -253,7 +253,6 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     CQM_HIP(hipHostMalloc((void**)&eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
     eb.staging_cap = c;
   }
-  ensure(eb.status, eb.status_cap, (size_t)kSysiStride * n);
   if (eb.status_host_cap < (size_t)kSysiStride * n) {
     if (eb.status_host) {
       CQM_HIP(hipStreamSynchronize(s));
@@ -263,6 +262,7 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     eb.status_host_cap = 0;
     const size_t c = std::max<size_t>((size_t)kSysiStride * n, 1024);
     CQM_HIP(hipHostMalloc((void**)&eb.status_host, sizeof(int) * c, hipHostMallocDefault));
+    CQM_HIP(hipHostGetDevicePointer((void**)&eb.status_host_dev, eb.status_host, 0));
     eb.status_host_cap = c;
   }
   CQM_HIP(hipMemcpyAsync(eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
@@ -307,7 +307,6 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
 void release_engine_bufs(EngineBufs& b) {
   if (b.desc) (void)hipFree(b.desc);
   if (b.groups) (void)hipFree(b.groups);
-  if (b.status) (void)hipFree(b.status);
   if (b.status_host) (void)hipHostFree(b.status_host);
   if (b.open_cycle) (void)hipFree(b.open_cycle);
   if (b.open_step) (void)hipFree(b.open_step);
@@ -331,9 +330,9 @@ void Engine::drop_graphs() {
 void Engine::snapshot(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!snap_ev_) CQM_HIP(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
-  launch_gather_status(eb.desc, n, eb.status, s);
-  CQM_HIP(hipMemcpyAsync(eb.status_host, eb.status, sizeof(int) * flags_.size(),
-                         hipMemcpyDeviceToHost, s));
+  // the gather kernel writes the flags straight into pinned host memory (no
+  // copy launch); the event orders the host's read after it
+  launch_gather_status(eb.desc, n, eb.status_host_dev, s);
   CQM_HIP(hipEventRecord(snap_ev_, s));
 }
 
@@ -351,9 +350,9 @@ void Engine::init(int k, hipStream_t s) {
 void Engine::status(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!n) return;
-  launch_gather_status(eb.desc, n, eb.status, s);
-  CQM_HIP(hipMemcpyAsync(flags_.data(), eb.status, sizeof(int) * flags_.size(), hipMemcpyDeviceToHost, s));
+  launch_gather_status(eb.desc, n, eb.status_host_dev, s);
   CQM_HIP(hipStreamSynchronize(s));
+  std::copy(eb.status_host, eb.status_host + flags_.size(), flags_.begin());
 }
 
 // Groups with a member whose flag `which` (0 system open, 1 cycle open) is

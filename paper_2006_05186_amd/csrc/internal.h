@@ -136,9 +136,8 @@ struct EngineBufs {
   size_t all_cap = 0;
   GemvGroup* groups = nullptr;
   size_t groups_cap = 0;
-  int* status = nullptr;
-  size_t status_cap = 0;
-  int* status_host = nullptr;       // pinned copy for lagged snapshots
+  int* status_host = nullptr;       // pinned status flags, written by the device
+  int* status_host_dev = nullptr;   // the same buffer's device address
   size_t status_host_cap = 0;
 };
 

@@ -101,12 +101,14 @@ __global__ __launch_bounds__(256) void k_residual_combine(const SysDesc* __restr
     D.r[i] = cf64{D.ghat[i].re - D.r[i].re, D.ghat[i].im - D.r[i].im};
 }
 
-// status of every system into one array (one host copy per check)
+// status of every system into one array, written straight into pinned host
+// memory (made visible to the host before the kernel ends)
 __global__ void k_gather_status(const SysDesc* __restrict__ sd, int n, int* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int* st = sd[k].sysi;
   for (int q = 0; q < kSysiStride; ++q) out[k * kSysiStride + q] = st[q];
+  __threadfence_system();
 }
 
 // New Hessenberg column h[0..j+1] of system D (h[j+1] = ||w|| real): the
