@@ -86,7 +86,8 @@ constexpr int kFp64TabLen = 768;
 constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
 
 __device__ __forceinline__ double exp_tab(double x, const double* tab) {
-  // x = (256 m + j) ln2/256 + r, |r| <= ln2/512; x < -708 gives 0
+  // x = (256 m + j) ln2/256 + r, |r| <= ln2/512; x below -708 is taken as
+  // -708 (the result, 3.3e-308, stands for 0)
   const double xc = fmax(x, -708.0);
   const double kd = fma(xc, 369.3299304675746, kRoundMagic);  // 256/ln2
   const int ik = (int)__double_as_longlong(kd);
@@ -99,8 +100,7 @@ __device__ __forceinline__ double exp_tab(double x, const double* tab) {
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  const double e = ldexp(tab[ik & 255] * p, ik >> 8);
-  return x < -708.0 ? 0.0 : e;
+  return ldexp(tab[ik & 255] * p, ik >> 8);
 }
 
 __device__ __forceinline__ void sincos_tab(double t, const double* tab, double* s, double* c) {
@@ -111,9 +111,9 @@ __device__ __forceinline__ void sincos_tab(double t, const double* tab, double* 
   double r = fma(-k, 0.024543692606130207, t);
   r = fma(-k, 4.005225236866436e-14, r);
   const double r2 = r * r;
-  // sin r through r^7, cos r - 1 through r^6 (truncation < 2e-20)
-  double ps = -0.0001984126984126984;         // -1/7!
-  ps = fma(ps, r2, 0.008333333333333333);     // 1/5!
+  // sin r through r^5 (truncation < 1e-17 absolute), cos r - 1 through r^6
+  // (truncation < 2e-20)
+  double ps = 0.008333333333333333;           // 1/5!
   ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
   const double sr = fma(ps * r2, r, r);
   double pc = -0.001388888888888889;          // -1/6!
