@@ -498,7 +498,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   }
   {
     Timed t(p0, CQM_K_OTHER, s);
-    launch_cycle_finish<R>(sd, n, s);
+    launch_cycle_finish<R>(sd, n, maxM_, s);
   }
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start

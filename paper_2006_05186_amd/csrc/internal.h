@@ -310,7 +310,7 @@ void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner
 template <typename R>
 void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
                     unsigned long long* ctr, hipStream_t s);
-template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s);
+template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, int maxM, hipStream_t s);
 // dense products over descriptors (k_dense.hip): which = 0 inner product
 // basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
 // residual product x -> r of open systems.  rowmap: (system, first row).

@@ -657,18 +657,25 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
   }
 }
 
+// Solution update of a finished cycle: y = R^-1 g (R the rotated Hessenberg
+// factor, k x k upper triangular), then x += V_k y.  Grid (row slices of 256,
+// systems); each slice's first wave solves the small triangular system
+// (column-oriented: lane t holds the right-hand side entry t, y_i is
+// broadcast and the lanes above subtract its column), then every thread
+// updates one row of x.
 template <typename R>
 __global__ __launch_bounds__(256) void k_cycle_finish(const SysDesc* __restrict__ sd) {
   __shared__ cf64 y[kMaxM];
   __shared__ cf64 Hs[kMaxM * (kMaxM + 1) / 2];  // upper triangle, column by column
-  const SysDesc D = sd[blockIdx.x];
+  const SysDesc D = sd[blockIdx.y];
   const int* st = D.sysi;
   if (!st[0]) return;
   const int k = st[2];
   if (k == 0) return;
   const int M = D.M, m = D.m;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= M) return;
   const cf64* Hl = D.H;
-  const cf64* gl = D.g;
   // column t of the triangular factor holds rows 0..t: offset t (t+1) / 2
   for (int e = threadIdx.x; e < k * (k + 1) / 2; e += 256) {
     int t = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
@@ -677,29 +684,36 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const SysDesc* __restrict_
     const int r = e - t * (t + 1) / 2;
     Hs[e] = Hl[(int64_t)(m + 1) * t + r];
   }
-  if (threadIdx.x < k) y[threadIdx.x] = gl[threadIdx.x];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = k - 1; i >= 0; --i) {
-      double re = y[i].re, im = y[i].im;
-      for (int t = i + 1; t < k; ++t) {
-        const cf64 a = Hs[t * (t + 1) / 2 + i];
-        re -= a.re * y[t].re - a.im * y[t].im;
-        im -= a.re * y[t].im + a.im * y[t].re;
-      }
-      const cf64 d = Hs[i * (i + 1) / 2 + i];
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    cf64 rhs = t < k ? D.g[t] : cf64{0.0, 0.0};
+    // 1 / R_tt, one per lane
+    cf64 inv{0.0, 0.0};
+    if (t < k) {
+      const cf64 d = Hs[t * (t + 1) / 2 + t];
       const double dn = d.re * d.re + d.im * d.im;
-      y[i] = cf64{(re * d.re + im * d.im) / dn, (im * d.re - re * d.im) / dn};
+      inv = cf64{d.re / dn, -d.im / dn};
+    }
+    for (int c = k - 1; c >= 0; --c) {
+      const cf64 a = t < c ? Hs[c * (c + 1) / 2 + t] : cf64{0.0, 0.0};
+      const double yr0 = rhs.re * inv.re - rhs.im * inv.im;
+      const double yi0 = rhs.re * inv.im + rhs.im * inv.re;
+      const double yr = __shfl(yr0, c, 64), yi = __shfl(yi0, c, 64);
+      if (t == c) y[c] = cf64{yr, yi};
+      if (t < c) {
+        rhs.re -= a.re * yr - a.im * yi;
+        rhs.im -= a.re * yi + a.im * yr;
+      }
     }
   }
   __syncthreads();
+  if (i >= M) return;
   const cplx<R>* V = (const cplx<R>*)D.basis;
   cf64* xl = D.x;
-  for (int i = threadIdx.x; i < M; i += 256) {
-    double re = xl[i].re, im = xl[i].im;
-    basis_combine<R, 16>(V, M, i, y, k, 1.0, re, im);
-    xl[i] = cf64{re, im};
-  }
+  double re = xl[i].re, im = xl[i].im;
+  basis_combine<R, 16>(V, M, i, y, k, 1.0, re, im);
+  xl[i] = cf64{re, im};
 }
 
 void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s) {
@@ -744,8 +758,8 @@ void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool 
   }
   CQM_HIP(hipGetLastError());
 }
-template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, hipStream_t s) {
-  hipLaunchKernelGGL((k_cycle_finish<R>), dim3(n), dim3(256), 0, s, sd);
+template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, int maxM, hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_finish<R>), dim3((maxM + 255) / 256, n), dim3(256), 0, s, sd);
   CQM_HIP(hipGetLastError());
 }
 
@@ -755,8 +769,8 @@ template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, bool,
                                     unsigned long long*, hipStream_t);
 template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, bool,
                                      unsigned long long*, hipStream_t);
-template void launch_cycle_finish<float>(const SysDesc*, int, hipStream_t);
-template void launch_cycle_finish<double>(const SysDesc*, int, hipStream_t);
+template void launch_cycle_finish<float>(const SysDesc*, int, int, hipStream_t);
+template void launch_cycle_finish<double>(const SysDesc*, int, int, hipStream_t);
 
 }  // namespace cqm
 
