@@ -56,6 +56,72 @@ __device__ __forceinline__ void wave_reduce_scatter(T* a, int lane) {
   }
 }
 
+// Partner value for the exchange between lanes l and l ^ OFF: DPP moves
+// within a row of 16 lanes for OFF = 1, 2, 8 (VALU, no LDS traffic), an LDS
+// swizzle for 4 and 16, a permute for 32.
+template <int OFF> __device__ __forceinline__ int xor_lane_i(int v) {
+  if constexpr (OFF == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
+  else if constexpr (OFF == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad [2,3,0,1]
+  else if constexpr (OFF == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row rotate 8
+  else if constexpr (OFF == 4 || OFF == 16) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (OFF << 10));
+  else return __shfl_xor(v, OFF, 64);
+}
+template <int OFF> __device__ __forceinline__ double xor_lane(double v) {
+  const int lo = xor_lane_i<OFF>(__double2loint(v));
+  const int hi = xor_lane_i<OFF>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int OFF> __device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_lane_i<OFF>(__float_as_int(v)));
+}
+
+// Sum of NV (<= 64) per-lane values over the 64 lanes of a wave, scattered:
+// on return lane l holds, in a[0], the total of entry scatter_entry<NV>(l)
+// (lanes that differ only in bits >= log2 NV hold the same entry).  The
+// exchanges go from the nearest lanes outwards, so the levels that move the
+// most values are DPP moves.
+template <int NV, int OFF = 1, typename T>
+__device__ __forceinline__ void wave_reduce_scatter_near(T* a, int lane) {
+  if constexpr (NV > 1) {
+    constexpr int H = NV / 2;
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const T send = up ? a[u] : a[u + H];
+      const T keep = up ? a[u + H] : a[u];
+      a[u] = keep + xor_lane<OFF>(send);
+    }
+    wave_reduce_scatter_near<H, OFF * 2, T>(a, lane);
+  } else if constexpr (OFF < 64) {
+    a[0] += xor_lane<OFF>(a[0]);
+    wave_reduce_scatter_near<1, OFF * 2, T>(a, lane);
+  }
+}
+template <typename T> __device__ __forceinline__ T wave_sum_near(T v) {
+  T a[1] = {v};
+  wave_reduce_scatter_near<1, 1, T>(a, 0);
+  return a[0];
+}
+// value of lane `src` (wave-uniform) in every lane
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+// entry whose total lane l holds after wave_reduce_scatter_near<NV>: bit b of
+// the lane (from b = 0) selected the upper half at the level with NV >> b
+// values
+template <int NV> __device__ __forceinline__ int scatter_entry(int lane) {
+  int e = 0;
+#pragma unroll
+  for (int b = 0, h = NV / 2; h >= 1; ++b, h >>= 1)
+    if (lane & (1 << b)) e += h;
+  return e;
+}
+
 // Row i of a stored-operator product from its tile partial sums:
 // y_i = sum_{Y < nt} P[Y][i] in a fixed order (P: nt slots of nt kSymB rows).
 template <typename R>

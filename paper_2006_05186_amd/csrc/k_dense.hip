@@ -51,9 +51,9 @@ __device__ __forceinline__ void tile_row_sums(const cplx<R>* a, cplx<R> xj, R* p
       v[q] = a[q].re * xj.re - a[q].im * xj.im;
       v[kRowsPerWave + q] = a[q].re * xj.im + a[q].im * xj.re;
     }
-    wave_reduce_scatter<2 * kRowsPerWave, 32>(v, c);  // lane t: entry t >> 1
-    if ((c & 1) == 0) {
-      const int e = c >> 1;
+    wave_reduce_scatter_near<2 * kRowsPerWave>(v, c);
+    if (c < 2 * kRowsPerWave) {
+      const int e = scatter_entry<2 * kRowsPerWave>(c);
       prow[2 * (e % kRowsPerWave) + e / kRowsPerWave] = v[0];
     }
   } else {
@@ -64,8 +64,8 @@ __device__ __forceinline__ void tile_row_sums(const cplx<R>* a, cplx<R> xj, R* p
 #pragma unroll
       for (int q = 0; q < kRowsPerWave; ++q)
         v[q] = part == 0 ? a[q].re * xj.re - a[q].im * xj.im : a[q].re * xj.im + a[q].im * xj.re;
-      wave_reduce_scatter<kRowsPerWave, 32>(v, c);  // lane t: entry t >> 2
-      if ((c & 3) == 0) prow[2 * (c >> 2) + part] = v[0];
+      wave_reduce_scatter_near<kRowsPerWave>(v, c);
+      if (c < kRowsPerWave) prow[2 * scatter_entry<kRowsPerWave>(c) + part] = v[0];
     }
   }
 }
@@ -96,7 +96,7 @@ __device__ __forceinline__ void tile_products(const cplx<R>* a, int M, int I, in
 #pragma unroll
     for (int q = 0; q < kRowsPerWave; ++q) {
       const int r = w * kRowsPerWave + q;
-      const R xr = __shfl(xi.re, r, 64), xm = __shfl(xi.im, r, 64);
+      const R xr = lane_bcast(xi.re, r), xm = lane_bcast(xi.im, r);  // r is wave-uniform
       cre += a[q].re * xr - a[q].im * xm;
       cim += a[q].re * xm + a[q].im * xr;
     }

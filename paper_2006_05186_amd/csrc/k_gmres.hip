@@ -368,12 +368,11 @@ __device__ __forceinline__ void chunk_dots(const cplx<R> (&v)[kVC], cplx<R> x, b
     a[u] = vr * x.re + vi * x.im;
     a[kVC + u] = vr * x.im - vi * x.re;
   }
-  wave_reduce_scatter<2 * kVC, 32>(a, lane);  // lane t: entry t >> kSh
-  constexpr int kSh = kVC == 32 ? 0 : kVC == 16 ? 1 : 2;
+  wave_reduce_scatter_near<2 * kVC>(a, lane);
   double nn = 0.0;
-  if (nrm) nn = wave_sum(valid ? (double)x.re * x.re + (double)x.im * x.im : 0.0);
+  if (nrm) nn = wave_sum_near(valid ? (double)x.re * x.re + (double)x.im * x.im : 0.0);
   __syncthreads();
-  if ((lane & ((1 << kSh) - 1)) == 0) red[wv * 2 * kVC + (lane >> kSh)] = a[0];
+  if (lane < 2 * kVC) red[wv * 2 * kVC + scatter_entry<2 * kVC>(lane)] = a[0];
   if (nrm && lane == 0) red[NW * 2 * kVC + wv] = nn;
   __syncthreads();
   if (wr && tid < 2 * kVC) {
