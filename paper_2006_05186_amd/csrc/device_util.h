@@ -1,6 +1,7 @@
 // Small device helpers: complex arithmetic on (re, im) pairs, wave64 and
 // workgroup reductions.
 #pragma once
+#include <type_traits>
 #include "internal.h"
 
 namespace cqm {
@@ -26,34 +27,6 @@ template <typename R> __device__ __forceinline__ cplx<R> cmake(R re, R im) {
   z.re = re;
   z.im = im;
   return z;
-}
-
-template <typename T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum of NV per-lane values over the 64 lanes of a wave, scattered: on
-// return lane t holds, in a[0], the total of entry t >> (6 - log2 NV).
-// Each halving step exchanges half of the remaining entries with the
-// partner lane (NV - 1 shuffles in all instead of 6 NV).
-template <int NV, int OFF, typename T>
-__device__ __forceinline__ void wave_reduce_scatter(T* a, int lane) {
-  if constexpr (NV > 1) {
-    constexpr int H = NV / 2;
-    const bool up = (lane & OFF) != 0;
-#pragma unroll
-    for (int u = 0; u < H; ++u) {
-      const T send = up ? a[u] : a[u + H];
-      const T keep = up ? a[u + H] : a[u];
-      a[u] = keep + __shfl_xor(send, OFF, 64);
-    }
-    wave_reduce_scatter<H, OFF / 2, T>(a, lane);
-  } else {
-#pragma unroll
-    for (int o = OFF; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
-  }
 }
 
 // Partner value for the exchange between lanes l and l ^ OFF: DPP moves
@@ -121,6 +94,17 @@ template <int NV> __device__ __forceinline__ int scatter_entry(int lane) {
     if (lane & (1 << b)) e += h;
   return e;
 }
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+  if constexpr (std::is_same_v<T, float> || std::is_same_v<T, double>) {
+    return wave_sum_near(v);
+  } else {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+  }
+}
+
 
 // Row i of a stored-operator product from its tile partial sums:
 // y_i = sum_{Y < nt} P[Y][i] in a fixed order (P: nt slots of nt kSymB rows).

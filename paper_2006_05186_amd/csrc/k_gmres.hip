@@ -249,11 +249,10 @@ __global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, 
         a2[u] = ar[u];
         a2[kChunk + u] = ai[u];
       }
-      wave_reduce_scatter<2 * kChunk, 32>(a2, lane);
+      wave_reduce_scatter_near<2 * kChunk>(a2, lane);
       ww = wave_sum(ww);
-      constexpr int kSh = 6 - (kChunk == 32 ? 6 : kChunk == 16 ? 5 : kChunk == 8 ? 4 : 3);
       __syncthreads();
-      if ((lane & ((1 << kSh) - 1)) == 0) red[wv * 2 * kChunk + (lane >> kSh)] = a2[0];
+      if (lane < 2 * kChunk) red[wv * 2 * kChunk + scatter_entry<2 * kChunk>(lane)] = a2[0];
       if (lane == 0) red[NW * 2 * kChunk + wv] = ww;
       __syncthreads();
       if (tid < kChunk && kc + tid <= j) {
