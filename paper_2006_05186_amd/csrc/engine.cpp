@@ -124,15 +124,14 @@ void pre_solve(SolveState& st, hipStream_t s, bool prepare) {
   }
   Timed t(p, CQM_K_OTHER, s);
   launch_rhs(p, st.inc, st.at<double>(st.b), s);
-  launch_dft_forward(p, st.at<double>(st.b), st.at<cf64>(st.ghat), s);
+  launch_dft_forward(p, st.at<double>(st.b), st.at<cf64>(st.ghat), st.at<double>(st.scratch), s);
 }
 
 // Inverse transform and operator diagnostics of one state.
 void post_solve(SolveState& st, hipStream_t s) {
   Problem& p = *st.p;
   cqm_diag& dg = st.diag;
-  double* sums = st.at<double>(st.scratch);
-  CQM_HIP(hipMemsetAsync(sums, 0, 2 * sizeof(double), s));
+  double* sums = st.at<double>(st.scratch);  // cleared by the forward transform
   {
     Timed t(p, CQM_K_OTHER, s);
     launch_dft_inverse(p, st.at<cf64>(st.x), st.q_out, sums, sums + 1, s);
@@ -308,6 +307,8 @@ void release_engine_bufs(EngineBufs& b) {
   if (b.desc) (void)hipFree(b.desc);
   if (b.groups) (void)hipFree(b.groups);
   if (b.status_host) (void)hipHostFree(b.status_host);
+  if (b.diag_flags) (void)hipHostFree(b.diag_flags);
+  if (b.diag_norms) (void)hipHostFree(b.diag_norms);
   if (b.open_cycle) (void)hipFree(b.open_cycle);
   if (b.open_step) (void)hipFree(b.open_step);
   if (b.staging) (void)hipHostFree(b.staging);
@@ -532,18 +533,38 @@ template int Engine::cycle_t<double>(hipStream_t);
 
 // Closing status pass for state k: residual norms refreshed by one more
 // cycle start (systems still open keep their flags) and the diagnostics.
-void Engine::finish_diag(int k, hipStream_t s) {
+void Engine::finish_diag(int k, hipStream_t s, bool refresh) {
   SolveState* st = S_[k];
   Problem& p = *st->p;
   const SysDesc* sd = eb.desc + st->first;
   const double outer_tol = p.opt.outer_tol;
-  if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
-  else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);
-  std::vector<double> sdv(8 * (size_t)p.Fsys);
-  std::vector<int> fl((size_t)kSysiStride * p.Fsys);
-  CQM_HIP(hipMemcpyAsync(sdv.data(), st->at<double>(st->sysd), sizeof(double) * sdv.size(), hipMemcpyDeviceToHost, s));
-  CQM_HIP(hipMemcpyAsync(fl.data(), st->at<int>(st->sysi), sizeof(int) * fl.size(), hipMemcpyDeviceToHost, s));
+  if (refresh) {
+    if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
+    else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);
+  }
+  // flags and norms gathered straight into pinned host memory
+  if (eb.diag_cap < (size_t)p.Fsys) {
+    if (eb.diag_flags) {
+      CQM_HIP(hipStreamSynchronize(s));
+      CQM_HIP(hipHostFree(eb.diag_flags));
+      CQM_HIP(hipHostFree(eb.diag_norms));
+    }
+    eb.diag_flags = nullptr;
+    eb.diag_norms = nullptr;
+    eb.diag_cap = 0;
+    const size_t c = std::max<size_t>(p.Fsys, 256);
+    CQM_HIP(hipHostMalloc((void**)&eb.diag_flags, sizeof(int) * kSysiStride * c, hipHostMallocDefault));
+    CQM_HIP(hipHostMalloc((void**)&eb.diag_norms, sizeof(double) * 3 * c, hipHostMallocDefault));
+    eb.diag_cap = c;
+  }
+  int* fl_dev = nullptr;
+  double* nm_dev = nullptr;
+  CQM_HIP(hipHostGetDevicePointer((void**)&fl_dev, eb.diag_flags, 0));
+  CQM_HIP(hipHostGetDevicePointer((void**)&nm_dev, eb.diag_norms, 0));
+  launch_gather_diag(sd, p.Fsys, fl_dev, nm_dev, s);
   CQM_HIP(hipStreamSynchronize(s));
+  const int* fl = eb.diag_flags;
+  const double* nm = eb.diag_norms;
   cqm_diag& d = st->diag;
   d.cycles = cycles_run;
   d.total_iters = d.max_iters = 0;
@@ -553,10 +574,10 @@ void Engine::finish_diag(int k, hipStream_t s) {
     const int* f = &fl[(size_t)kSysiStride * l];
     d.total_iters += f[3];
     d.max_iters = std::max(d.max_iters, f[3]);
-    const double bn = sdv[8 * l + 2], rn = sdv[8 * l + 3];
+    const double bn = nm[3 * l], rn = nm[3 * l + 1];
     if (bn > 0) d.max_rel_residual = std::max(d.max_rel_residual, rn / bn);
     open += f[0] != 0;
-    nan += sdv[8 * l + 4] != 0.0;
+    nan += nm[3 * l + 2] != 0.0;
   }
   d.converged = nan ? -1 : (open == 0 ? 1 : 0);
 }
@@ -590,9 +611,10 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
     E.cycles_run = 0;
     E.set(G, s);
     for (size_t k = 0; k < G.size(); ++k) E.init((int)k, s);
-    for (int c = 0; c < p0.opt.max_cycles; ++c)
-      if (E.cycle(s) == 0) break;
-    for (size_t k = 0; k < G.size(); ++k) E.finish_diag((int)k, s);
+    // a loop ended by convergence has just refreshed every residual norm
+    bool converged = false;
+    for (int c = 0; c < p0.opt.max_cycles && !converged; ++c) converged = E.cycle(s) == 0;
+    for (size_t k = 0; k < G.size(); ++k) E.finish_diag((int)k, s, !converged);
     for (SolveState* st : G) post_solve(*st, s);
     const double el = ms_since(t1);
     if (p0.timer.on) p0.timer.collect(G[0]->diag.kernel_ms, G[0]->diag.kernel_calls, G[0]->diag.kernel_work);

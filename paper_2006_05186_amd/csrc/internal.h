@@ -139,6 +139,9 @@ struct EngineBufs {
   int* status_host = nullptr;       // pinned status flags, written by the device
   int* status_host_dev = nullptr;   // the same buffer's device address
   size_t status_host_cap = 0;
+  int* diag_flags = nullptr;        // pinned, closing diagnostics (flags, norms)
+  double* diag_norms = nullptr;
+  size_t diag_cap = 0;
 };
 
 // Launch shapes picked by timing the candidates on their first use, per
@@ -271,7 +274,9 @@ struct Problem {
 // ------------------------------------------------------------ launchers
 // tables / transforms (k_transform.hip)
 void launch_rhs(const Problem& p, const Incident& inc, double* b, hipStream_t s);
-void launch_dft_forward(const Problem& p, const double* b, cf64* ghat, hipStream_t s);
+// (also clears zero2[0..1], the inverse transform's accumulators, if given)
+void launch_dft_forward(const Problem& p, const double* b, cf64* ghat, double* zero2,
+                        hipStream_t s);
 void launch_dft_inverse(const Problem& p, const cf64* xhat, double* q, double* imag_sq,
                         double* real_sq, hipStream_t s);
 void launch_vec_norms(const cf64* v, int64_t stride, int M, int nsys, double* out, hipStream_t s);
@@ -303,6 +308,9 @@ void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int6
 void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s);
 void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
 void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s);
+// flags (kSysiStride ints) and ||ghat||, last residual norm, non-finite flag
+// (3 doubles) of n systems, into host-visible memory
+void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hipStream_t s);
 template <typename R>
 void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s);
 // split: three launches over row slices; fused (split only): the first one
@@ -355,7 +363,8 @@ class Engine {
   int cycle(hipStream_t s);                                     // returns systems still open
   void status(hipStream_t s);                                   // refresh host flags
   bool state_done(int k) const;                                 // every system of state k closed
-  void finish_diag(int k, hipStream_t s);                       // fill diag of state k
+  // fill diag of state k (refresh: recompute the residual norms first)
+  void finish_diag(int k, hipStream_t s, bool refresh = true);
   int cycles_run = 0;
   bool mixed = true;
  private:

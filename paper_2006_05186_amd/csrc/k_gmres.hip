@@ -111,6 +111,16 @@ __global__ void k_gather_status(const SysDesc* __restrict__ sd, int n, int* __re
   __threadfence_system();
 }
 
+__global__ void k_gather_diag(const SysDesc* __restrict__ sd, int n, int* __restrict__ flags,
+                              double* __restrict__ norms) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const SysDesc& D = sd[k];
+  for (int q = 0; q < kSysiStride; ++q) flags[k * kSysiStride + q] = D.sysi[q];
+  for (int q = 0; q < 3; ++q) norms[3 * k + q] = D.sysd[2 + q];
+  __threadfence_system();
+}
+
 // New Hessenberg column h[0..j+1] of system D (h[j+1] = ||w|| real): the
 // previous rotations are applied, a new one zeroes h[j+1], the column and
 // the residual estimate |g[j+1]| are stored, and the cycle closes when that
@@ -720,6 +730,10 @@ void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s) {
 }
 void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_residual_combine, dim3(n), dim3(256), 0, s, sd);
+  CQM_HIP(hipGetLastError());
+}
+void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_diag, dim3((n + 255) / 256), dim3(256), 0, s, sd, n, flags, norms);
   CQM_HIP(hipGetLastError());
 }
 void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s) {

@@ -37,11 +37,14 @@ void launch_rhs(const Problem& p, const Incident& inc, double* b, hipStream_t s)
   CQM_HIP(hipGetLastError());
 }
 
-// ghat[l][i] = sum_n rho^n b[n][i] zeta^-(n l mod F), l < nsys.
+// ghat[l][i] = sum_n rho^n b[n][i] zeta^-(n l mod F), l < nsys.  zero2: two
+// accumulators of the inverse transform of the same solve, cleared here.
 __global__ void k_dft_fwd(const double* __restrict__ b, const double* __restrict__ rho_pow,
-                          const cf64* __restrict__ tw, int M, int F, cf64* __restrict__ ghat) {
+                          const cf64* __restrict__ tw, int M, int F, cf64* __restrict__ ghat,
+                          double* __restrict__ zero2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y;
+  if (zero2 && blockIdx.x == 0 && l == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0.0;
   if (i >= M) return;
   double re = 0.0, im = 0.0;
   int k = 0;  // (n * l) mod F, advanced incrementally
@@ -56,10 +59,11 @@ __global__ void k_dft_fwd(const double* __restrict__ b, const double* __restrict
   ghat[(int64_t)l * M + i] = cf64{re, im};
 }
 
-void launch_dft_forward(const Problem& p, const double* b, cf64* ghat, hipStream_t s) {
+void launch_dft_forward(const Problem& p, const double* b, cf64* ghat, double* zero2,
+                        hipStream_t s) {
   dim3 grid((p.M + 255) / 256, p.Fsys);
   hipLaunchKernelGGL(k_dft_fwd, grid, dim3(256), 0, s, b, p.dev.rho_pow, p.dev.tw_fwd, (int)p.M,
-                     p.F, ghat);
+                     p.F, ghat, zero2);
   CQM_HIP(hipGetLastError());
 }
 
