@@ -233,6 +233,8 @@ int cqm_problem_destroy(cqm_problem_t p) {
   (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
   h2_release(*p);
   p->timer.release();
+  for (hipEvent_t e : p->setup_ev)
+    if (e) (void)hipEventDestroy(e);
   delete p->engine;
   p->engine = nullptr;
   release_engine_bufs(p->engine_bufs);

@@ -99,16 +99,14 @@ void prepare_operator(Problem& p, hipStream_t s) {
     cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
     {
       Timed t(p, CQM_K_ASSEMBLE, s);
-      launch_dense_assemble(p, d64, d32, p.timer.ctr(CQM_K_ASSEMBLE), s);
+      launch_dense_assemble(p, d64, d32, nv, p.timer.ctr(CQM_K_ASSEMBLE), s);
     }
-    Timed t(p, CQM_K_NEAR, s);
-    launch_dense_scatter_near(p, nv, d64, d32, s);
     p.dense_ready = true;
   }
 }
 
 // Operator (optionally), right-hand side and forward transform of one state.
-void pre_solve(SolveState& st, hipStream_t s, bool prepare) {
+void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed) {
   Problem& p = *st.p;
   CQM_HIP(hipSetDevice(p.ctx->device));
   require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
@@ -116,7 +114,15 @@ void pre_solve(SolveState& st, hipStream_t s, bool prepare) {
   require(st.inc.kind != 0, CQM_EINVAL, "no incident data set");
   require(st.q_out != nullptr, CQM_EINVAL, "q_out is NULL");
   st.diag = cqm_diag{};
-  if (prepare) {
+  if (prepare && timed) {
+    // GPU time of the setup, read after the solve's closing synchronisation
+    for (hipEvent_t& e : p.setup_ev)
+      if (!e) CQM_HIP(hipEventCreate(&e));
+    CQM_HIP(hipEventRecord(p.setup_ev[0], s));
+    prepare_operator(p, s);
+    CQM_HIP(hipEventRecord(p.setup_ev[1], s));
+    st.diag.t_setup_ms = -1.0;  // pending
+  } else if (prepare) {
     auto t0 = std::chrono::steady_clock::now();
     prepare_operator(p, s);
     CQM_HIP(hipStreamSynchronize(s));
@@ -139,6 +145,11 @@ void post_solve(SolveState& st, hipStream_t s) {
   double hs[2];
   CQM_HIP(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, s));
   CQM_HIP(hipStreamSynchronize(s));
+  if (dg.t_setup_ms < 0.0) {
+    float ms = 0.f;
+    CQM_HIP(hipEventElapsedTime(&ms, p.setup_ev[0], p.setup_ev[1]));
+    dg.t_setup_ms = ms;
+  }
   dg.imag_ratio = p.full_band() && hs[1] > 0 ? std::sqrt(hs[0] / hs[1]) : 0.0;
   dg.n_systems = p.Fsys;
   dg.far_units = p.far_units;
@@ -595,7 +606,7 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
     p0.timer.reset(s);
     for (size_t k = 1; k < G.size(); ++k)
       if (G[k]->p != &p0) G[k]->p->timer.on = false;
-    for (SolveState* st : G) pre_solve(*st, s, true);
+    for (SolveState* st : G) pre_solve(*st, s, true, true);
     auto t1 = std::chrono::steady_clock::now();
     // a problem's own solve keeps its engine (buffers, captured graphs)
     std::unique_ptr<Engine> local;

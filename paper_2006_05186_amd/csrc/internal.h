@@ -267,6 +267,7 @@ struct Problem {
   // engine of the problem's own solves, kept across them (with its buffers
   // and captured step graphs)
   class Engine* engine = nullptr;
+  hipEvent_t setup_ev[2] = {nullptr, nullptr};  // brackets the operator setup of a solve
   EngineBufs engine_bufs;
   bool full_band() const { return Fsys == F; }
 };
@@ -284,8 +285,6 @@ void launch_vec_norms(const cf64* v, int64_t stride, int M, int nsys, double* ou
 // near field (k_near.hip)
 void launch_near_static(const Problem& p, hipStream_t s);
 void launch_near_values(const Problem& p, cf64* vals, hipStream_t s);
-void launch_dense_scatter_near(const Problem& p, const cf64* vals, cf64* d64, cf32* d32,
-                               hipStream_t s);
 
 // far field (k_far.hip)
 template <typename R>
@@ -295,8 +294,10 @@ template <typename R>
 void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* partial,
                             const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
                             const cf64* near_vals, const int* active, hipStream_t s);
-void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
-                           hipStream_t s);
+// all frequency slices of the packed operator: far entries evaluated, near
+// ones (pairs sharing a vertex) copied from the near-field values nv
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
+                           unsigned long long* ctr, hipStream_t s);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
 FarShape far_shape_of(const Problem& p, int nsys, int precision);  // shape in use (tuned or default)
 
@@ -344,7 +345,9 @@ template <typename R>
 void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
               const int* active, hipStream_t s);
 void prepare_operator(Problem& p, hipStream_t s);
-void pre_solve(SolveState& st, hipStream_t s, bool prepare);
+// timed: measure the setup with the problem's events instead of a stream
+// synchronisation (one caller per problem at a time)
+void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed = false);
 void post_solve(SolveState& st, hipStream_t s);
 int diag_status(const cqm_diag& dg);  // CQM_OK / CQM_ENOCONV / CQM_ENAN
 void solve_states(std::vector<SolveState*>& S, hipStream_t s);  // full solves, grouped by precision

@@ -228,7 +228,11 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
                                                               int nsys, cf64* __restrict__ d64,
                                                               cf32* __restrict__ d32,
                                                               unsigned long long* ctr,
-                                                              const double* __restrict__ ftab) {
+                                                              const double* __restrict__ ftab,
+                                                              const int32_t* __restrict__ nrp,
+                                                              const int32_t* __restrict__ ncol,
+                                                              const cf64* __restrict__ nval,
+                                                              int64_t nnz) {
   // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I
   const long long kk = blockIdx.x;
   long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
@@ -242,8 +246,9 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
   __shared__ __align__(16) double stab[kFp64TabLen];
   for (int k = threadIdx.x; k < kFp64TabLen; k += kAt * kAt) stab[k] = ftab[k];
   __syncthreads();
-  bool live = i < M && j < M && (I != J || i <= j);
-  if (live) live = !share_vertex(vid[i], vid[j]);
+  const bool inb = i < M && j < M && (I != J || i <= j);
+  const bool nearp = inb && share_vertex(vid[i], vid[j]);
+  const bool live = inb && !nearp;
   if (ctr) {
     // point-pair-frequency kernel values evaluated by this tile
     unsigned long long u = live ? (unsigned long long)kQ * kQ * nl : 0ull;
@@ -290,8 +295,32 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
   const int64_t SL = sym_slice(M);
   // the mirrored entry (j, i) is stored too when both lie in one diagonal
   // block of the packed triangle (written directly: about 6 % of tiles)
-  const bool mir = live && i != j && sym_stored(j, i);
-  const int64_t oi = sym_index(i, j), om = mir ? sym_index(j, i) : 0;
+  const bool mirpos = i != j && sym_stored(j, i);
+  const bool mir = live && mirpos;
+  const int64_t oi = sym_index(i, j), om = mirpos ? sym_index(j, i) : 0;
+  if (nearp && nval) {
+    // a pair sharing a vertex takes its near-field value (static plus
+    // dynamic part), found in the CSR rows of i and, mirrored, of j
+    auto find = [&](int r, int c) {
+      for (int k = nrp[r]; k < nrp[r + 1]; ++k)
+        if (ncol[k] == c) return k;
+      return -1;
+    };
+    const int kij = find(i, j), kji = mirpos ? find(j, i) : -1;
+    for (int l = 0; l < nl; ++l) {
+      const int64_t base = (int64_t)(l0 + l) * SL;
+      if (kij >= 0) {
+        const cf64 v = nval[(int64_t)(l0 + l) * nnz + kij];
+        d64[base + oi] = v;
+        if (d32) d32[base + oi] = cf32{(float)v.re, (float)v.im};
+      }
+      if (kji >= 0) {
+        const cf64 v = nval[(int64_t)(l0 + l) * nnz + kji];
+        d64[base + om] = v;
+        if (d32) d32[base + om] = cf32{(float)v.re, (float)v.im};
+      }
+    }
+  }
 #pragma unroll
   for (int l = 0; l < FT; ++l) {
     if (!live || l >= nl) continue;
@@ -484,22 +513,23 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
 }
 
 template <int FT>
-static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
-                              hipStream_t s) {
+static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
+                              unsigned long long* ctr, hipStream_t s) {
   const int M = (int)p.M;
   const int nt = (M + kAt - 1) / kAt;
   dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
   hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64, p.dev.vid,
-                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr, p.dev.ftab);
+                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr, p.dev.ftab,
+                     p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
   CQM_HIP(hipGetLastError());
 }
 
-void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, unsigned long long* ctr,
-                           hipStream_t s) {
+void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
+                           unsigned long long* ctr, hipStream_t s) {
   auto run = [&](int FT, unsigned long long* c) {
-    if (FT == 13) dense_assemble_ft<13>(p, d64, d32, c, s);
-    else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, c, s);
-    else dense_assemble_ft<9>(p, d64, d32, c, s);
+    if (FT == 13) dense_assemble_ft<13>(p, d64, d32, nv, c, s);
+    else if (FT == 11) dense_assemble_ft<11>(p, d64, d32, nv, c, s);
+    else dense_assemble_ft<9>(p, d64, d32, nv, c, s);
   };
   // frequency tile: timed once per (M, systems) when tuning is on (each
   // candidate writes the same operator), else the one with the fewest

@@ -175,32 +175,4 @@ void launch_near_values(const Problem& p, cf64* vals, hipStream_t s) {
   CQM_HIP(hipGetLastError());
 }
 
-// Write near values into the packed per-frequency operators (the entries of
-// the stored triangle; the near list holds both (i, j) and (j, i)).
-__global__ void k_dense_scatter(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                const cf64* __restrict__ vals, int M, int64_t nnz,
-                                cf64* __restrict__ d64, cf32* __restrict__ d32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = blockIdx.y;
-  if (i >= M) return;
-  const int64_t base = (int64_t)l * sym_slice(M);
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const int j = col[k];
-    if (!sym_stored(i, j)) continue;
-    const cf64 v = vals[(int64_t)l * nnz + k];
-    const int64_t o = base + sym_index(i, j);
-    if (d64) d64[o] = v;
-    if (d32) d32[o] = cf32{(float)v.re, (float)v.im};
-  }
-}
-
-void launch_dense_scatter_near(const Problem& p, const cf64* vals, cf64* d64, cf32* d32,
-                               hipStream_t s) {
-  const int64_t nnz = (int64_t)p.col.size();
-  dim3 grid((p.M + 127) / 128, p.Fsys);
-  hipLaunchKernelGGL(k_dense_scatter, grid, dim3(128), 0, s, p.dev.near_rowptr, p.dev.near_col,
-                     vals, (int)p.M, nnz, d64, d32);
-  CQM_HIP(hipGetLastError());
-}
-
 }  // namespace cqm
