@@ -100,8 +100,19 @@ typedef struct cqm_options {
                             (kept across solves of the same problem; the
                             full group list is used, so closed groups are
                             launched and leave at once)               (0)   */
-  int32_t reserved[3];
+  int32_t precond;       /* CQM_PRECOND_*: right preconditioner of the
+                            inner GMRES for the stored dense form: the
+                            inverses of the 64 x 64 diagonal blocks of
+                            every V(s_l), formed once per operator.  It
+                            does not change the solution (the refinement
+                            residual is the unpreconditioned one), only
+                            the number of inner steps.        (BLOCK_JACOBI) */
+  int32_t reserved[2];
 } cqm_options;
+
+/* Inner preconditioners (cqm_options.precond). */
+#define CQM_PRECOND_NONE 0
+#define CQM_PRECOND_BLOCK_JACOBI 1
 
 /* Arnoldi step layouts (cqm_options.arnoldi_layout).  AUTO splits when a
    batch has fewer systems than the GPU has compute units (256). */
@@ -202,7 +213,9 @@ int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream
 
 /* Solve `count` independent problems (different meshes, N and T allowed)
  * together: their frequency systems are batched in shared launches.
- * q_outs[k] and diags[k] as for cqm_solve (diags may be NULL). */
+ * q_outs[k] and diags[k] as for cqm_solve (diags may be NULL).  The
+ * problems must share gmres_restart, and those in the stored dense form
+ * must share precond; otherwise CQM_EINVAL before any work is queued. */
 int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
                     cqm_diag* diags, hipStream_t stream);
 

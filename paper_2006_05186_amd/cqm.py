@@ -16,6 +16,7 @@ __all__ = [
     "CQM_FP64_PLAIN", "CQM_MIXED_PLAIN", "CQM_MIXED_H2ACA", "CQM_FP64_H2ACA",
     "CQM_FORM_MATRIX_FREE", "CQM_FORM_DENSE", "CQM_BAND_FULL", "CQM_BAND_HALF", "KERNEL_CLASSES",
     "CQM_ARNOLDI_AUTO", "CQM_ARNOLDI_GROUP", "CQM_ARNOLDI_SPLIT",
+    "CQM_PRECOND_NONE", "CQM_PRECOND_BLOCK_JACOBI",
     "CqmError", "cqm_options", "cqm_diag", "library_path", "load_library",
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
@@ -31,6 +32,7 @@ CQM_FP64_PLAIN, CQM_MIXED_PLAIN, CQM_MIXED_H2ACA, CQM_FP64_H2ACA = 0, 1, 2, 3
 CQM_FORM_MATRIX_FREE, CQM_FORM_DENSE = 0, 1
 CQM_BAND_FULL, CQM_BAND_HALF = 0, 1
 CQM_ARNOLDI_AUTO, CQM_ARNOLDI_GROUP, CQM_ARNOLDI_SPLIT = 0, 1, 2
+CQM_PRECOND_NONE, CQM_PRECOND_BLOCK_JACOBI = 0, 1
 KERNEL_CLASSES = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
 
 EXPORTED_SYMBOLS = [
@@ -58,7 +60,7 @@ class cqm_options(ctypes.Structure):
         ("eps_aca", ctypes.c_double), ("aca_band", ctypes.c_int32), ("q_duffy", ctypes.c_int32),
         ("reuse_operator", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -131,6 +131,7 @@ int cqm_default_options(cqm_options* o) {
   o->reuse_operator = 0;
   o->autotune = 1;
   o->graphs = 0;
+  o->precond = CQM_PRECOND_BLOCK_JACOBI;
   return CQM_OK;
 }
 
@@ -183,6 +184,8 @@ int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv, const 
     require(o.aca_band == CQM_BAND_FULL || o.aca_band == CQM_BAND_HALF, CQM_EINVAL, "aca_band");
     require(o.arnoldi_layout >= CQM_ARNOLDI_AUTO && o.arnoldi_layout <= CQM_ARNOLDI_SPLIT, CQM_EINVAL,
             "arnoldi_layout");
+    require(o.precond == CQM_PRECOND_NONE || o.precond == CQM_PRECOND_BLOCK_JACOBI, CQM_EINVAL,
+            "precond");
     for (int64_t k = 0; k < 3 * nv; ++k)
       require(std::isfinite(vertices[k]), CQM_EINVAL, "non-finite vertex coordinate");
     for (int64_t k = 0; k < 3 * M; ++k)

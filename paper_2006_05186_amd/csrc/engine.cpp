@@ -101,6 +101,11 @@ void prepare_operator(Problem& p, hipStream_t s) {
       Timed t(p, CQM_K_ASSEMBLE, s);
       launch_dense_assemble(p, d64, d32, nv, p.timer.ctr(CQM_K_ASSEMBLE), s);
     }
+    if (p.lay.pinv) {
+      Timed t(p, CQM_K_OTHER, s);
+      if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(d64, (int)p.M, p.Fsys, wsp<cf32>(p, p.lay.pinv), s);
+      else launch_block_inverse<double>(d64, (int)p.M, p.Fsys, wsp<cf64>(p, p.lay.pinv), s);
+    }
     p.dense_ready = true;
   }
 }
@@ -186,6 +191,8 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   if (S_.empty()) return;
   m_ = S_[0]->p->opt.gmres_restart;
   mixed = mode_is_mixed(S_[0]->p->opt.mode);
+  pre_ = false;
+  bool pre_set = false;
   for (size_t k = 0; k < S_.size(); ++k) {
     SolveState* st = S_[k];
     Problem& p = *st->p;
@@ -194,6 +201,14 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     const int M = (int)p.M;
     maxM_ = std::max(maxM_, M);
     st->first = (int)hd_.size();
+    if (dense_form(p)) {
+      // one Krylov layout for every stored-operator system of the batch
+      const bool pk = p.lay.pinv != 0;
+      require(!pre_set || pk == pre_, CQM_EINVAL,
+              "batched stored-operator problems must share the preconditioner");
+      pre_ = pk;
+      pre_set = true;
+    }
     const size_t isz = mixed ? sizeof(cf32) : sizeof(cf64);
     for (int l = 0; l < p.Fsys; ++l) {
       SysDesc d{};
@@ -216,6 +231,9 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
         d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * sym_slice(M);
         d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * sym_slice(M)) : nullptr;
         d.symp = st->base + st->sym + sizeof(cf64) * (size_t)l * sym_partials(M);
+        if (p.lay.pinv)
+          d.Pinv = mixed ? (const void*)(wsp<cf32>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M))
+                         : (const void*)(wsp<cf64>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M));
         // join the group of systems on the same operator slice, if any
         auto it = slot.find(d.V64);
         if (it == slot.end() || groups_[it->second].n == kMaxGroup) {
@@ -280,12 +298,13 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   bool eligible = !lite_.empty();
   for (SolveState* st : S_)
     eligible = eligible && dense_form(*st->p) && st->p->opt.graphs && !st->p->opt.profile;
-  const bool same = prev_hd_.size() == hd_.size() && prev_split_ == split_ &&
+  const bool same = prev_hd_.size() == hd_.size() && prev_split_ == split_ && prev_pre_ == pre_ &&
                     std::memcmp(prev_hd_.data(), hd_.data(), sizeof(SysDesc) * hd_.size()) == 0;
   if (!eligible || !same) drop_graphs();
   graphs_ = eligible;
   prev_hd_ = hd_;
   prev_split_ = split_;
+  prev_pre_ = pre_;
   if (graphs_) {
     // the full group list, sorted by mesh size, in its own device buffer
     std::vector<int> ord(lite_.size());
@@ -399,8 +418,10 @@ void Engine::upload_open(int which, GroupLite* dst, size_t stage, std::vector<GC
 template <typename R>
 void Engine::dense_product(const GroupLite* list, const std::vector<GClass>& cls, int which, int j,
                            bool reduce, unsigned long long* ctr, hipStream_t s) {
+  // preconditioned Arnoldi steps: P v_j waits in slot j + 1 for the product
+  const int xj = which == 0 && pre_ ? j + 1 : j;
   for (const GClass& c : cls)
-    launch_dense_gemv_groups<R>(list + c.off, c.count, c.M, c.grouped, which, j, ctr, s);
+    launch_dense_gemv_groups<R>(list + c.off, c.count, c.M, c.grouped, which, xj, ctr, s);
   if (reduce && !cls.empty())
     launch_dense_reduce_desc<R>(eb.desc, (int)hd_.size(), maxM_, which, j, s);
 }
@@ -427,6 +448,7 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
   if (!lite_.empty()) {
     const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
     Timed t(p0, c, s);
+    if (pre_) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
     dense_product<R>(list, cls, 0, j, !split_, p0.timer.ctr(c), s);
   }
   for (SolveState* st : S_) {
@@ -450,6 +472,7 @@ template <typename R> void Engine::step_graph(int j, hipStream_t s) {
     if (!cap_stream_) CQM_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     CQM_HIP(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+    if (pre_) launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, 0, j, cap_stream_);
     dense_product<R>(eb.all_groups, all_cls_, 0, j, !split_, nullptr, cap_stream_);
     launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, nullptr, cap_stream_);
     const hipError_t ec = hipStreamEndCapture(cap_stream_, &g);
@@ -511,6 +534,8 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   {
     Timed t(p0, CQM_K_OTHER, s);
     launch_cycle_finish<R>(sd, n, maxM_, s);
+    // right preconditioning: the cycle left V y in r, x += P (V y)
+    if (pre_) launch_block_apply<R>(sd, n, maxM_, 1, 0, s);
   }
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start
@@ -606,6 +631,18 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
     p0.timer.reset(s);
     for (size_t k = 1; k < G.size(); ++k)
       if (G[k]->p != &p0) G[k]->p->timer.on = false;
+    // what the shared launches need in common, checked before any work
+    int pre = -1;
+    for (SolveState* st : G) {
+      const Problem& p = *st->p;
+      require(p.opt.gmres_restart == p0.opt.gmres_restart, CQM_EINVAL,
+              "batched problems must share gmres_restart");
+      if (!dense_form(p)) continue;
+      const int pk = p.lay.pinv != 0;
+      require(pre < 0 || pk == pre, CQM_EINVAL,
+              "batched stored-operator problems must share the preconditioner");
+      pre = pk;
+    }
     for (SolveState* st : G) pre_solve(*st, s, true, true);
     auto t1 = std::chrono::steady_clock::now();
     // a problem's own solve keeps its engine (buffers, captured graphs)

@@ -61,8 +61,8 @@ template <typename R> struct FreqTab {
 
 // ------------------------------------------------------------ problem state
 // GMRES (k_gmres.hip).  One descriptor per frequency system.
-// 128 bytes; the fields every Arnoldi kernel reads first share the leading
-// 64-byte line (one scalar cache line per descriptor fetch).
+// The fields every Arnoldi kernel reads first share the leading 64-byte line
+// (one scalar cache line per descriptor fetch).
 struct SysDesc {
   int M, m;               // length, restart length
   int prob, l;            // problem index (in a batch) and frequency index
@@ -80,8 +80,9 @@ struct SysDesc {
   const cf64* ghat;       // M, right-hand side
   const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
   const cf64* V64;        // dense operator slice in FP64 (dense form) or null
+  const void* Pinv;       // block-Jacobi inverses (inner precision) or null
 };
-static_assert(sizeof(SysDesc) == 128, "SysDesc layout");
+static_assert(sizeof(SysDesc) == 136, "SysDesc layout");
 // Rows per workgroup (one per thread) of the split Arnoldi step.
 constexpr int kArnRows = 256;
 
@@ -191,7 +192,7 @@ struct MeshDev {
 
 // Offsets (bytes) of the solve workspace.
 struct Layout {
-  size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, total = 0;
+  size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, pinv = 0, total = 0;
 };
 
 struct H2Operator;  // compressed representation (h2.cpp)
@@ -329,6 +330,15 @@ void launch_dense_gemv_groups(const GroupLite* gl, int ngroups, int M, bool grou
 template <typename R>
 void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
                               hipStream_t s);
+// Block-Jacobi preconditioner of the stored form (k_dense.hip): inverses of
+// the kSymB x kSymB diagonal tiles of every slice (FP64 elimination, stored
+// in R); application z = P v_j into basis slot j+1 (mode 0, systems with an
+// open cycle) or x += P r (mode 1, systems whose cycle ran).
+template <typename R>
+void launch_block_inverse(const cf64* d64, int M, int nsys, cplx<R>* pinv, hipStream_t s);
+template <typename R>
+void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s);
+inline int64_t block_inverse_elems(int M) { return (int64_t)sym_blocks(M) * kSymB * kSymB; }
 
 // ------------------------------------------------------------ host helpers
 void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w);
@@ -393,6 +403,9 @@ class Engine {
   std::vector<GemvGroup> groups_;
   bool split_ = false;    // Arnoldi step split over row slices
   bool prev_split_ = false;  // layout the captured steps were recorded with
+  // block-Jacobi right preconditioning of the stored-operator systems: each
+  // step forms P v_j before the product, each cycle closes with x += P V y
+  bool pre_ = false, prev_pre_ = false;
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
   // lagged status snapshot inside a cycle: flags copied to pinned memory

@@ -251,6 +251,144 @@ void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, 
                      which, j);
   CQM_HIP(hipGetLastError());
 }
+// ------------------------------------------------------------------
+// Block-Jacobi preconditioner.  The diagonal tile (I, I) of the packed slice
+// holds the full kSymB x kSymB block of V(s); its inverse comes from
+// Gauss-Jordan elimination in LDS without pivoting (s-bar V(s) has a positive
+// definite Hermitian part for Re s > 0, so the pivots stay away from zero;
+// a vanishing or non-finite pivot leaves the identity for that block).
+// Rows and columns past M (the ragged last block) are the identity.
+template <typename R>
+__global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ d64, int M,
+                                                       cplx<R>* __restrict__ pinv) {
+  __shared__ cf64 A[kB][kB + 1];
+  __shared__ cf64 rowk[kB], colk[kB];
+  __shared__ int bad;
+  const int I = blockIdx.x, l = blockIdx.y, nb = sym_blocks(M);
+  const cf64* T = d64 + (int64_t)l * sym_slice(M) + (int64_t)(I * (I + 1) / 2 + I) * kB * kB;
+  const int rows = min(kB, M - I * kB);
+  for (int e = threadIdx.x; e < kB * kB; e += 256) {
+    const int r = e / kB, c = e % kB;
+    A[r][c] = (r < rows && c < rows) ? T[e] : cf64{r == c ? 1.0 : 0.0, 0.0};
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < kB; ++k) {
+    const cf64 d = A[k][k];
+    const double dn = d.re * d.re + d.im * d.im;
+    if (!(dn > 0.0) || !isfinite(dn)) {  // block-uniform
+      if (threadIdx.x == 0) bad = 1;
+      break;
+    }
+    const cf64 pk{d.re / dn, -d.im / dn};  // 1 / a_kk
+    if (threadIdx.x < kB) {
+      rowk[threadIdx.x] = A[k][threadIdx.x];
+      colk[threadIdx.x] = A[threadIdx.x][k];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kB * kB; e += 256) {
+      const int r = e / kB, c = e % kB;
+      cf64 v;
+      if (r == k && c == k) {
+        v = pk;
+      } else if (r == k) {  // a_kj / a_kk
+        const cf64 a = rowk[c];
+        v = cf64{a.re * pk.re - a.im * pk.im, a.re * pk.im + a.im * pk.re};
+      } else if (c == k) {  // -a_ik / a_kk
+        const cf64 a = colk[r];
+        v = cf64{-(a.re * pk.re - a.im * pk.im), -(a.re * pk.im + a.im * pk.re)};
+      } else {  // a_ij - a_ik a_kj / a_kk
+        const cf64 a = colk[r], b = rowk[c];
+        const cf64 t{a.re * pk.re - a.im * pk.im, a.re * pk.im + a.im * pk.re};
+        const cf64 x = A[r][c];
+        v = cf64{x.re - (t.re * b.re - t.im * b.im), x.im - (t.re * b.im + t.im * b.re)};
+      }
+      A[r][c] = v;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  cplx<R>* out = pinv + ((int64_t)l * nb + I) * kB * kB;
+  for (int e = threadIdx.x; e < kB * kB; e += 256) {
+    const int r = e / kB, c = e % kB;
+    const cf64 v = bad ? cf64{r == c ? 1.0 : 0.0, 0.0} : A[r][c];
+    cplx<R> o;
+    o.re = (R)v.re;
+    o.im = (R)v.im;
+    out[e] = o;
+  }
+}
+
+// mode 0: basis[j+1] = P basis[j] (systems with an open cycle);
+// mode 1: x += P r (systems whose cycle ran; r holds V y).  One workgroup per
+// (diagonal block, system); each wave forms 16 rows.
+template <typename R>
+__global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__ sd, int mode,
+                                                     int j) {
+  const SysDesc D = sd[blockIdx.y];
+  if (!D.Pinv) return;
+  const int* st = D.sysi;
+  if (mode == 0 ? !st[1] : (!st[0] || st[2] == 0)) return;
+  const int M = D.M, b = blockIdx.x;
+  if (b * kB >= M) return;
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const cplx<R>* P = (const cplx<R>*)D.Pinv + (int64_t)b * kB * kB;
+  cplx<R> a[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) a[q] = P[(w * kRowsPerWave + q) * kB + c];
+  const int col = b * kB + c;
+  if (mode == 0) {
+    const cplx<R>* v = (const cplx<R>*)D.basis + (int64_t)j * M;
+    const cplx<R> x = load_x<R>(v, col, M);
+    R* out = (R*)((cplx<R>*)D.basis + (int64_t)(j + 1) * M);
+    // row sums into a kB-entry staging row per wave, then rows < M stored
+    __shared__ R rowbuf[4][2 * kRowsPerWave];
+    tile_row_sums<R>(a, x, rowbuf[w], c);
+    __syncthreads();
+    if (c < kRowsPerWave) {
+      const int r = b * kB + w * kRowsPerWave + c;
+      if (r < M) {
+        out[2 * r] = rowbuf[w][2 * c];
+        out[2 * r + 1] = rowbuf[w][2 * c + 1];
+      }
+    }
+  } else {
+    // FP64 accumulation of P (R) times r (FP64)
+    const cf64 x = col < M ? D.r[col] : cf64{0.0, 0.0};
+    double v[2 * kRowsPerWave];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      v[q] = (double)a[q].re * x.re - (double)a[q].im * x.im;
+      v[kRowsPerWave + q] = (double)a[q].re * x.im + (double)a[q].im * x.re;
+    }
+    wave_reduce_scatter_near<2 * kRowsPerWave>(v, c);
+    if (c < 2 * kRowsPerWave) {
+      const int e = scatter_entry<2 * kRowsPerWave>(c);
+      const int r = b * kB + w * kRowsPerWave + e % kRowsPerWave;
+      if (r < M) {
+        double* xr = (double*)D.x;
+        xr[2 * r + e / kRowsPerWave] += v[0];
+      }
+    }
+  }
+}
+
+template <typename R>
+void launch_block_inverse(const cf64* d64, int M, int nsys, cplx<R>* pinv, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_inverse<R>), dim3(sym_blocks(M), nsys), dim3(256), 0, s, d64, M,
+                     pinv);
+  CQM_HIP(hipGetLastError());
+}
+template <typename R>
+void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s) {
+  hipLaunchKernelGGL((k_block_apply<R>), dim3(sym_blocks(maxM), n), dim3(256), 0, s, sd, mode, j);
+  CQM_HIP(hipGetLastError());
+}
+template void launch_block_inverse<float>(const cf64*, int, int, cf32*, hipStream_t);
+template void launch_block_inverse<double>(const cf64*, int, int, cf64*, hipStream_t);
+template void launch_block_apply<float>(const SysDesc*, int, int, int, int, hipStream_t);
+template void launch_block_apply<double>(const SysDesc*, int, int, int, int, hipStream_t);
+
 template void launch_dense_gemv_groups<float>(const GroupLite*, int, int, bool, int, int,
                                               unsigned long long*, hipStream_t);
 template void launch_dense_gemv_groups<double>(const GroupLite*, int, int, bool, int, int,

@@ -718,8 +718,9 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const SysDesc* __restrict_
   __syncthreads();
   if (i >= M) return;
   const cplx<R>* V = (const cplx<R>*)D.basis;
-  cf64* xl = D.x;
-  double re = xl[i].re, im = xl[i].im;
+  // preconditioned systems: V y to r, from which the next launch adds P V y
+  cf64* xl = D.Pinv ? D.r : D.x;
+  double re = D.Pinv ? 0.0 : xl[i].re, im = D.Pinv ? 0.0 : xl[i].im;
   basis_combine<R, 16>(V, M, i, y, k, 1.0, re, im);
   xl[i] = cf64{re, im};
 }

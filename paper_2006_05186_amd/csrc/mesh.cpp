@@ -274,6 +274,9 @@ void compute_layout(Problem& p) {
     if (p.opt.form == CQM_FORM_DENSE) {
       L.dense64 = take(sizeof(cf64) * Fs * sym_slice((int)M));
       if (mode_is_mixed(p.opt.mode)) L.dense32 = take(sizeof(cf32) * Fs * sym_slice((int)M));
+      if (p.opt.precond == CQM_PRECOND_BLOCK_JACOBI)
+        L.pinv = take((mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64)) * Fs *
+                      block_inverse_elems((int)M));
     } else {
       size_t worst = 0;
       for (int nl = 1; nl <= (int)Fs; ++nl) {

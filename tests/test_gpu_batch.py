@@ -77,3 +77,25 @@ def test_batch_mixing_forms_and_precisions(ctx):
         assert O.rel_error(q.cpu().numpy(), ref, area) < 1e-8
     for p in probs:
         p.close()
+
+
+def test_batch_rejects_mixed_preconditioning(ctx):
+    """Stored-operator problems batched together share one Krylov layout: a
+    batch mixing preconditioned and plain ones is refused, not half-solved."""
+    V1, T1 = W.icosphere(1)
+    say("batch precond mismatch M=80")
+    a = Problem(ctx, V1, T1, 6, 2.0, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                precond=C.CQM_PRECOND_BLOCK_JACOBI)
+    b = Problem(ctx, V1, T1, 6, 2.0, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                precond=C.CQM_PRECOND_NONE)
+    for p in (a, b):
+        p.set_plane_wave()
+    with pytest.raises(C.CqmError) as e:
+        solve_batch([a, b])
+    assert e.value.code == C.CQM_EINVAL
+    # each alone still solves
+    for p in (a, b):
+        _, rc, d = p.solve()
+        assert rc == C.CQM_OK and d.converged == 1
+    a.close()
+    b.close()

@@ -111,6 +111,32 @@ def test_solve_C1_matches_oracle(ctx, c1, form, mode):
     p.close()
 
 
+@pytest.mark.parametrize("mode", [C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN])
+def test_block_jacobi_keeps_the_answer_and_cuts_steps(ctx, c1, mode):
+    """Right preconditioning by the inverses of the 64 x 64 diagonal blocks
+    changes the Krylov space, not the system: both runs meet the oracle's
+    answer, the preconditioned one in fewer Arnoldi steps."""
+    wl, V, T, r, area = c1
+    runs = {}
+    for pc in (C.CQM_PRECOND_NONE, C.CQM_PRECOND_BLOCK_JACOBI):
+        say(f"block-Jacobi C1 mode={mode} precond={pc}")
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=C.CQM_FORM_DENSE, precond=pc)
+        p.set_plane_wave()
+        q, rc, d = p.solve()
+        q = q.cpu().numpy()
+        err = O.rel_error(q, r["q"], area)
+        say(f"  rc={rc} err={err:.3e} iters={d.total_iters} max={d.max_iters} cycles={d.cycles}")
+        assert rc == C.CQM_OK and d.converged == 1
+        assert d.max_rel_residual <= 1e-13
+        assert err < 1e-8
+        runs[pc] = (q, d.total_iters)
+        p.close()
+    q0, it0 = runs[C.CQM_PRECOND_NONE]
+    q1, it1 = runs[C.CQM_PRECOND_BLOCK_JACOBI]
+    assert it1 < it0
+    assert O.rel_error(q1, q0, area) < 1e-8
+
+
 def test_kernel_work_counters(ctx, c1):
     """The per-class work the kernels count for the roofline matches what the
     solve did: every far pair of the symmetric assembly once per frequency,

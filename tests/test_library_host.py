@@ -42,3 +42,4 @@ def test_host_argument_errors():
     assert (o.gmres_restart, o.n_min, o.cheb_m, o.q_duffy) == (30, 32, 4, 5)
     assert o.eps_aca == 1e-6 and o.eta == 1.0 and o.outer_tol == 1e-15
     assert o.autotune == 1 and o.arnoldi_layout == C.CQM_ARNOLDI_AUTO and o.graphs == 0
+    assert o.precond == C.CQM_PRECOND_BLOCK_JACOBI
