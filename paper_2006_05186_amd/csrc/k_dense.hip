@@ -28,7 +28,7 @@ template <typename R>
 __device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ Vt, cplx<R>* a) {
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) a[q] = Vt[(w * kRowsPerWave + q) * kB + c];
+  for (int q = 0; q < kRowsPerWave; ++q) a[q] = as_global(Vt)[(w * kRowsPerWave + q) * kB + c];
 }
 
 template <typename R>
@@ -36,7 +36,7 @@ __device__ __forceinline__ cplx<R> load_x(const cplx<R>* __restrict__ x, int g, 
   cplx<R> v;
   v.re = R(0);
   v.im = R(0);
-  if (g < M) v = x[g];
+  if (g < M) v = as_global(x)[g];
   return v;
 }
 
@@ -254,68 +254,70 @@ void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, 
 // ------------------------------------------------------------------
 // Block-Jacobi preconditioner.  The diagonal tile (I, I) of the packed slice
 // holds the full kSymB x kSymB block of V(s); its inverse comes from
-// Gauss-Jordan elimination in LDS without pivoting (s-bar V(s) has a positive
+// Gauss-Jordan elimination without pivoting (s-bar V(s) has a positive
 // definite Hermitian part for Re s > 0, so the pivots stay away from zero;
 // a vanishing or non-finite pivot leaves the identity for that block).
 // Rows and columns past M (the ragged last block) are the identity.
+// The block stays in registers: lane c of wave w holds column c of rows
+// 16 w .. 16 w + 15.  Step k publishes pivot row k (from its owner wave)
+// and each wave's entries of column k (from lane k) through LDS, double
+// buffered by the parity of k, so each step has one barrier.
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ d64, int M,
                                                        cplx<R>* __restrict__ pinv) {
-  __shared__ cf64 A[kB][kB + 1];
-  __shared__ cf64 rowk[kB], colk[kB];
-  __shared__ int bad;
+  __shared__ cf64 rowb[2][kB];
+  __shared__ cf64 colb[2][4][kRowsPerWave];
   const int I = blockIdx.x, l = blockIdx.y, nb = sym_blocks(M);
   const cf64* T = d64 + (int64_t)l * sym_slice(M) + (int64_t)(I * (I + 1) / 2 + I) * kB * kB;
   const int rows = min(kB, M - I * kB);
-  for (int e = threadIdx.x; e < kB * kB; e += 256) {
-    const int r = e / kB, c = e % kB;
-    A[r][c] = (r < rows && c < rows) ? T[e] : cf64{r == c ? 1.0 : 0.0, 0.0};
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  cf64 a[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const int r = w * kRowsPerWave + q;
+    a[q] = (r < rows && c < rows) ? T[r * kB + c] : cf64{r == c ? 1.0 : 0.0, 0.0};
   }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < kB; ++k) {
-    const cf64 d = A[k][k];
-    const double dn = d.re * d.re + d.im * d.im;
-    if (!(dn > 0.0) || !isfinite(dn)) {  // block-uniform
-      if (threadIdx.x == 0) bad = 1;
-      break;
-    }
-    const cf64 pk{d.re / dn, -d.im / dn};  // 1 / a_kk
-    if (threadIdx.x < kB) {
-      rowk[threadIdx.x] = A[k][threadIdx.x];
-      colk[threadIdx.x] = A[threadIdx.x][k];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kB * kB; e += 256) {
-      const int r = e / kB, c = e % kB;
-      cf64 v;
-      if (r == k && c == k) {
-        v = pk;
-      } else if (r == k) {  // a_kj / a_kk
-        const cf64 a = rowk[c];
-        v = cf64{a.re * pk.re - a.im * pk.im, a.re * pk.im + a.im * pk.re};
-      } else if (c == k) {  // -a_ik / a_kk
-        const cf64 a = colk[r];
-        v = cf64{-(a.re * pk.re - a.im * pk.im), -(a.re * pk.im + a.im * pk.re)};
-      } else {  // a_ij - a_ik a_kj / a_kk
-        const cf64 a = colk[r], b = rowk[c];
-        const cf64 t{a.re * pk.re - a.im * pk.im, a.re * pk.im + a.im * pk.re};
-        const cf64 x = A[r][c];
-        v = cf64{x.re - (t.re * b.re - t.im * b.im), x.im - (t.re * b.im + t.im * b.re)};
+  bool bad = false;
+  for (int kb = 0; kb < 4; ++kb) {
+#pragma unroll
+    for (int kq = 0; kq < kRowsPerWave; ++kq) {
+      const int k = kb * kRowsPerWave + kq, buf = kq & 1;
+      if (w == kb) rowb[buf][c] = a[kq];
+      if (c == k) {
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) colb[buf][w][q] = a[q];
       }
-      A[r][c] = v;
+      __syncthreads();
+      const cf64 d = rowb[buf][k];
+      const double dn = d.re * d.re + d.im * d.im;
+      bad |= !(dn > 0.0) || !isfinite(dn);
+      const double id = 1.0 / dn;
+      const cf64 pk{d.re * id, -d.im * id};  // 1 / a_kk
+      // new pivot row: a_kc / a_kk, and 1 / a_kk at c = k
+      const cf64 rk = rowb[buf][c];
+      const cf64 nr = c == k ? pk : cf64{rk.re * pk.re - rk.im * pk.im, rk.re * pk.im + rk.im * pk.re};
+      // rows r != k: a_rc - a_rk a'_kc, and at c = k the new entry
+      // -a_rk / a_kk, which is a_rk - a_rk (1 / a_kk + 1): one update form
+      // for every lane
+      const cf64 nu{c == k ? nr.re + 1.0 : nr.re, nr.im};
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q) {
+        const cf64 ck = colb[buf][w][q];  // a_rk, r = 16 w + q
+        a[q].re = fma(-ck.re, nu.re, fma(ck.im, nu.im, a[q].re));
+        a[q].im = fma(-ck.re, nu.im, fma(-ck.im, nu.re, a[q].im));
+      }
+      if (w == kb) a[kq] = nr;
     }
-    __syncthreads();
   }
-  __syncthreads();
   cplx<R>* out = pinv + ((int64_t)l * nb + I) * kB * kB;
-  for (int e = threadIdx.x; e < kB * kB; e += 256) {
-    const int r = e / kB, c = e % kB;
-    const cf64 v = bad ? cf64{r == c ? 1.0 : 0.0, 0.0} : A[r][c];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const int r = w * kRowsPerWave + q;
+    const cf64 v = bad ? cf64{r == c ? 1.0 : 0.0, 0.0} : a[q];
     cplx<R> o;
     o.re = (R)v.re;
     o.im = (R)v.im;
-    out[e] = o;
+    out[r * kB + c] = o;
   }
 }
 
