@@ -157,4 +157,44 @@ template <typename T> __device__ __forceinline__ T block_sum(T v, T* red) {
   return t;
 }
 
+// Block-Jacobi application to one kSymB-row block by one wave: lane r adds
+// sum_c P[c][r] v_c.  The stored inverse of a complex symmetric block is
+// symmetric up to rounding; every application (inner steps and the update
+// of x) uses this one orientation, so the preconditioner is one fixed
+// matrix.  p holds the block's entries P[c][lane] (column-major for lane r),
+// vb the block of v in LDS; A is the accumulation type.
+template <typename R, typename A>
+__device__ __forceinline__ void pblock_acc(const cplx<R> (&p)[kSymB], const cplx<A>* vb, A& re,
+                                           A& im) {
+#pragma unroll
+  for (int c = 0; c < kSymB; ++c) {
+    const cplx<A> v = vb[c];
+    re += (A)p[c].re * v.re - (A)p[c].im * v.im;
+    im += (A)p[c].re * v.im + (A)p[c].im * v.re;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void pblock_load(const cplx<R>* __restrict__ Pb, int lane,
+                                            cplx<R> (&p)[kSymB]) {
+#pragma unroll
+  for (int c = 0; c < kSymB; ++c) p[c] = as_global(Pb)[c * kSymB + lane];
+}
+// The same sum with the entries loaded NC columns at a time (FP64 blocks:
+// register budget).
+template <typename R, typename A, int NC>
+__device__ __forceinline__ void pblock_mul(const cplx<R>* __restrict__ Pb, const cplx<A>* vb,
+                                           int lane, A& re, A& im) {
+  for (int c0 = 0; c0 < kSymB; c0 += NC) {
+    cplx<R> p[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) p[u] = as_global(Pb)[(c0 + u) * kSymB + lane];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const cplx<A> v = vb[c0 + u];
+      re += (A)p[u].re * v.re - (A)p[u].im * v.im;
+      im += (A)p[u].re * v.im + (A)p[u].im * v.re;
+    }
+  }
+}
+
 }  // namespace cqm

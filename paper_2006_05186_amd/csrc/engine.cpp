@@ -293,6 +293,19 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     CQM_HIP(hipHostGetDevicePointer((void**)&eb.status_host_dev, eb.status_host, 0));
     eb.status_host_cap = c;
   }
+  if (eb.cyc_cap < (size_t)n + 1) {
+    if (eb.cyc_host) {
+      CQM_HIP(hipStreamSynchronize(s));
+      CQM_HIP(hipHostFree(eb.cyc_host));
+    }
+    eb.cyc_host = nullptr;
+    eb.cyc_cap = 0;
+    const size_t c = std::max<size_t>((size_t)n + 1, 256);
+    CQM_HIP(hipHostMalloc((void**)&eb.cyc_host, sizeof(int) * c, hipHostMallocDefault));
+    CQM_HIP(hipHostGetDevicePointer((void**)&eb.cyc_host_dev, eb.cyc_host, 0));
+    eb.cyc_cap = c;
+  }
+  for (int k = 0; k < n; ++k) hd_[k].hflag = eb.cyc_host_dev + 1 + k;
   CQM_HIP(hipMemcpyAsync(eb.desc, hd_.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, s));
   // graph-captured steps: every state in the stored form, no profiling
   bool eligible = !lite_.empty();
@@ -337,6 +350,7 @@ void release_engine_bufs(EngineBufs& b) {
   if (b.desc) (void)hipFree(b.desc);
   if (b.groups) (void)hipFree(b.groups);
   if (b.status_host) (void)hipHostFree(b.status_host);
+  if (b.cyc_host) (void)hipHostFree(b.cyc_host);
   if (b.diag_flags) (void)hipHostFree(b.diag_flags);
   if (b.diag_norms) (void)hipHostFree(b.diag_norms);
   if (b.open_cycle) (void)hipFree(b.open_cycle);
@@ -348,7 +362,6 @@ void release_engine_bufs(EngineBufs& b) {
 
 Engine::~Engine() {
   drop_graphs();
-  if (snap_ev_) (void)hipEventDestroy(snap_ev_);
   if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
 }
 
@@ -358,18 +371,19 @@ void Engine::drop_graphs() {
   gexec_.clear();
 }
 
-void Engine::snapshot(hipStream_t s) {
-  const int n = (int)hd_.size();
-  if (!snap_ev_) CQM_HIP(hipEventCreateWithFlags(&snap_ev_, hipEventDisableTiming));
-  // the gather kernel writes the flags straight into pinned host memory (no
-  // copy launch); the event orders the host's read after it
-  launch_gather_status(eb.desc, n, eb.status_host_dev, s);
-  CQM_HIP(hipEventRecord(snap_ev_, s));
-}
-
-void Engine::read_snapshot() {
-  CQM_HIP(hipEventSynchronize(snap_ev_));
-  std::copy(eb.status_host, eb.status_host + flags_.size(), flags_.begin());
+// Spin on the progress word until the last kernel of step target - 1 has
+// started; a wait beyond a few hundred milliseconds falls back to draining
+// the stream (which also reports a device error).
+void Engine::wait_progress(int target, hipStream_t s) {
+  const volatile int* prog = eb.cyc_host;
+  if (*prog >= target) return;
+  const auto t0 = std::chrono::steady_clock::now();
+  while (*prog < target) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(300)) {
+      CQM_HIP(hipStreamSynchronize(s));
+      return;
+    }
+  }
 }
 
 void Engine::init(int k, hipStream_t s) {
@@ -448,7 +462,7 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
   if (!lite_.empty()) {
     const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
     Timed t(p0, c, s);
-    if (pre_) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
+    if (pre_ && (j == 0 || !fuse_pre<R>())) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
     dense_product<R>(list, cls, 0, j, !split_, p0.timer.ctr(c), s);
   }
   for (SolveState* st : S_) {
@@ -461,7 +475,8 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
                 st->at<int>(st->sysi) + 1, s);
   }
   Timed t(p0, CQM_K_ARNOLDI, s);
-  launch_arnoldi<R>(eb.desc, n, maxM_, j, split_, split_, p0.timer.ctr(CQM_K_ARNOLDI), s);
+  launch_arnoldi<R>(eb.desc, n, maxM_, j, split_, split_, fuse_pre<R>(),
+                    p0.timer.ctr(CQM_K_ARNOLDI), eb.cyc_host_dev, s);
 }
 
 // The same step from its captured graph (captured on first use).
@@ -472,9 +487,11 @@ template <typename R> void Engine::step_graph(int j, hipStream_t s) {
     if (!cap_stream_) CQM_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     CQM_HIP(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-    if (pre_) launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, 0, j, cap_stream_);
+    if (pre_ && (j == 0 || !fuse_pre<R>()))
+      launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, 0, j, cap_stream_);
     dense_product<R>(eb.all_groups, all_cls_, 0, j, !split_, nullptr, cap_stream_);
-    launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, nullptr, cap_stream_);
+    launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, fuse_pre<R>(), nullptr,
+                      eb.cyc_host_dev, cap_stream_);
     const hipError_t ec = hipStreamEndCapture(cap_stream_, &g);
     CQM_HIP(ec);
     const hipError_t e = hipGraphInstantiate(&gexec_[j], g, nullptr, nullptr, 0);
@@ -508,27 +525,35 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
   const GroupLite* step_list = eb.open_cycle;
   step_cls_ = cyc_cls_;
-  int snap_j = -1;  // step behind which a status snapshot is pending
+  // host copies of the cycle-open flags: set here for the systems whose
+  // cycle starts (the stream is idle after the status read), then written by
+  // the device at every step
+  eb.cyc_host[0] = 0;
+  for (int k = 0; k < n; ++k) eb.cyc_host[1 + k] = flags_[(size_t)kSysiStride * k + 1] != 0;
+  int listed = open, upload_j = 0;  // groups in step_list, and the step it was built at
   for (int j = 0; j < m_; ++j) {
     if (graphs_) step_graph<R>(j, s);
     else step_eager<R>(j, step_list, step_cls_, s);
-    // status: a snapshot behind step j is read three steps later, so the
-    // stream keeps three steps of queued work while the host decides
-    if (snap_j >= 0 && j == snap_j + 3) {
-      read_snapshot();
-      snap_j = -1;
-      int c = 0;
-      for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + 1] != 0;
-      if (c == 0) break;
-      if (!graphs_) {
-        // drop the groups whose cycles had closed by then
-        upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
-        step_list = eb.open_step;
-      }
+    // the host queues at most kAhead steps beyond the last started one
+    if (j >= kAhead) wait_progress(j - kAhead + 1, s);
+    // a cycle flag only ever drops to 0, so the device's latest writes can
+    // be read at any time: all 0 means the steps still queued do nothing
+    const volatile int* cf = eb.cyc_host + 1;
+    int c = 0;
+    for (int k = 0; k < n; ++k) {
+      const int f = cf[k];
+      flags_[(size_t)kSysiStride * k + 1] = f;
+      c += f != 0;
     }
-    if ((j + 1) % 6 == 0 && j + 4 < m_ && snap_j < 0) {
-      snapshot(s);
-      snap_j = j;
+    if (c == 0) break;
+    // eager lists drop the groups closed since the list was built once a
+    // quarter of them has closed; the staging copy of the previous list was
+    // queued before step j - kAhead + 1, whose last kernel has started
+    if (!graphs_ && j - kAhead > upload_j && 4 * c <= 3 * listed) {
+      upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
+      step_list = eb.open_step;
+      listed = c;
+      upload_j = j;
     }
   }
   {

@@ -81,8 +81,10 @@ struct SysDesc {
   const void* V32;        // dense operator slice in FP32 (dense mixed form) or null
   const cf64* V64;        // dense operator slice in FP64 (dense form) or null
   const void* Pinv;       // block-Jacobi inverses (inner precision) or null
+  int* hflag;             // pinned host word: the cycle-open flag, written at
+                          // every Arnoldi step (or null)
 };
-static_assert(sizeof(SysDesc) == 136, "SysDesc layout");
+static_assert(sizeof(SysDesc) == 144, "SysDesc layout");
 // Rows per workgroup (one per thread) of the split Arnoldi step.
 constexpr int kArnRows = 256;
 
@@ -140,6 +142,10 @@ struct EngineBufs {
   int* status_host = nullptr;       // pinned status flags, written by the device
   int* status_host_dev = nullptr;   // the same buffer's device address
   size_t status_host_cap = 0;
+  int* cyc_host = nullptr;          // pinned: [0] step progress, then the
+                                    // cycle-open flag of every system
+  int* cyc_host_dev = nullptr;
+  size_t cyc_cap = 0;
   int* diag_flags = nullptr;        // pinned, closing diagnostics (flags, norms)
   double* diag_norms = nullptr;
   size_t diag_cap = 0;
@@ -319,7 +325,7 @@ void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner
 // also sums the stored-operator partials of w = A v_j (no separate reduction)
 template <typename R>
 void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
-                    unsigned long long* ctr, hipStream_t s);
+                    bool pre, unsigned long long* ctr, int* prog, hipStream_t s);
 template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, int maxM, hipStream_t s);
 // dense products over descriptors (k_dense.hip): which = 0 inner product
 // basis[j] -> basis[j+1] of systems with an open cycle; which = 1 FP64
@@ -406,14 +412,15 @@ class Engine {
   // block-Jacobi right preconditioning of the stored-operator systems: each
   // step forms P v_j before the product, each cycle closes with x += P V y
   bool pre_ = false, prev_pre_ = false;
+  // FP32 split steps form P v_{j+1} inside the Arnoldi finish kernel; only
+  // the first step of a cycle launches the block product itself
+  template <typename R> bool fuse_pre() const { return pre_ && split_ && sizeof(R) == 4; }
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
-  // lagged status snapshot inside a cycle: flags copied to pinned memory
-  // behind the queued launches, read a few steps later without draining the
-  // stream
-  hipEvent_t snap_ev_ = nullptr;
-  void snapshot(hipStream_t s);
-  void read_snapshot();
+  // inside a cycle the host runs at most kAhead steps ahead of the device
+  // (progress word) and reads the cycle-open flags after queueing each step
+  static constexpr int kAhead = 3;
+  void wait_progress(int target, hipStream_t s);
   // HIP graphs of the Arnoldi steps (dense-form batches without profiling):
   // step j = products of every group + the Arnoldi step, over the full group
   // list (closed systems are skipped inside the kernels).  Captured on first

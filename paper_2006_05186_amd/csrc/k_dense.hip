@@ -322,55 +322,54 @@ __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ 
 }
 
 // mode 0: basis[j+1] = P basis[j] (systems with an open cycle);
-// mode 1: x += P r (systems whose cycle ran; r holds V y).  One workgroup per
-// (diagonal block, system); each wave forms 16 rows.
+// mode 1: x += P r (systems whose cycle ran; r holds V y).  Four blocks per
+// workgroup, one wave each.
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__ sd, int mode,
                                                      int j) {
+  __shared__ cf64 vb64[4][kB];
+  __shared__ cplx<R> vbR[4][kB];
   const SysDesc D = sd[blockIdx.y];
   if (!D.Pinv) return;
   const int* st = D.sysi;
   if (mode == 0 ? !st[1] : (!st[0] || st[2] == 0)) return;
-  const int M = D.M, b = blockIdx.x;
-  if (b * kB >= M) return;
-  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const cplx<R>* P = (const cplx<R>*)D.Pinv + (int64_t)b * kB * kB;
-  cplx<R> a[kRowsPerWave];
-#pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) a[q] = P[(w * kRowsPerWave + q) * kB + c];
-  const int col = b * kB + c;
+  const int M = D.M, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + w;
+  if (blockIdx.x * 4 * kB >= M) return;
+  const bool blk = b * kB < M;  // wave-uniform: this wave's block exists
+  const int i = b * kB + lane;
+  const cplx<R>* Pb = (const cplx<R>*)D.Pinv + (int64_t)b * kB * kB;
+  // FP32 blocks are loaded whole before the vector; FP64 ones in chunks
+  constexpr bool kWhole = sizeof(R) == 4;
+  cplx<R> p[kWhole ? kB : 1];
+  if constexpr (kWhole) {
+    if (blk) pblock_load<R>(Pb, lane, p);
+  }
   if (mode == 0) {
     const cplx<R>* v = (const cplx<R>*)D.basis + (int64_t)j * M;
-    const cplx<R> x = load_x<R>(v, col, M);
-    R* out = (R*)((cplx<R>*)D.basis + (int64_t)(j + 1) * M);
-    // row sums into a kB-entry staging row per wave, then rows < M stored
-    __shared__ R rowbuf[4][2 * kRowsPerWave];
-    tile_row_sums<R>(a, x, rowbuf[w], c);
+    cplx<R> vi = cmake<R>(R(0), R(0));
+    if (i < M) vi = as_global(v)[i];
+    vbR[w][lane] = vi;
     __syncthreads();
-    if (c < kRowsPerWave) {
-      const int r = b * kB + w * kRowsPerWave + c;
-      if (r < M) {
-        out[2 * r] = rowbuf[w][2 * c];
-        out[2 * r + 1] = rowbuf[w][2 * c + 1];
-      }
-    }
+    if (!blk) return;
+    R re = R(0), im = R(0);
+    if constexpr (kWhole) pblock_acc<R, R>(p, vbR[w], re, im);
+    else pblock_mul<R, R, 16>(Pb, vbR[w], lane, re, im);
+    if (i < M) ((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = cmake<R>(re, im);
   } else {
-    // FP64 accumulation of P (R) times r (FP64)
-    const cf64 x = col < M ? D.r[col] : cf64{0.0, 0.0};
-    double v[2 * kRowsPerWave];
-#pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-      v[q] = (double)a[q].re * x.re - (double)a[q].im * x.im;
-      v[kRowsPerWave + q] = (double)a[q].re * x.im + (double)a[q].im * x.re;
-    }
-    wave_reduce_scatter_near<2 * kRowsPerWave>(v, c);
-    if (c < 2 * kRowsPerWave) {
-      const int e = scatter_entry<2 * kRowsPerWave>(c);
-      const int r = b * kB + w * kRowsPerWave + e % kRowsPerWave;
-      if (r < M) {
-        double* xr = (double*)D.x;
-        xr[2 * r + e / kRowsPerWave] += v[0];
-      }
+    cf64 ri{0.0, 0.0};
+    if (i < M) ri = as_global((const cf64*)D.r)[i];
+    vb64[w][lane] = ri;
+    __syncthreads();
+    if (!blk) return;
+    double re = 0.0, im = 0.0;
+    if constexpr (kWhole) pblock_acc<R, double>(p, vb64[w], re, im);
+    else pblock_mul<R, double, 16>(Pb, vb64[w], lane, re, im);
+    if (i < M) {
+      cf64 x = D.x[i];
+      x.re += re;
+      x.im += im;
+      D.x[i] = x;
     }
   }
 }
@@ -383,7 +382,8 @@ void launch_block_inverse(const cf64* d64, int M, int nsys, cplx<R>* pinv, hipSt
 }
 template <typename R>
 void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s) {
-  hipLaunchKernelGGL((k_block_apply<R>), dim3(sym_blocks(maxM), n), dim3(256), 0, s, sd, mode, j);
+  hipLaunchKernelGGL((k_block_apply<R>), dim3((sym_blocks(maxM) + 3) / 4, n), dim3(256), 0, s, sd,
+                     mode, j);
   CQM_HIP(hipGetLastError());
 }
 template void launch_block_inverse<float>(const cf64*, int, int, cf32*, hipStream_t);

@@ -173,6 +173,11 @@ __device__ void hessenberg_column(const SysDesc& D, int j, cf64* h, const double
   st[2] = j + 1;
   st[3] += 1;
   if (!(res > D.sysd[1]) || j + 1 >= m || nr == 0.0) st[1] = 0;
+  if (D.hflag) {
+    // host-visible copy, read after the step's completion event
+    *D.hflag = st[1];
+    __threadfence_system();
+  }
 }
 
 // acc += sign * sum_{k < n} c_k v_k[i] for basis vectors v_k = V + k M
@@ -200,13 +205,24 @@ __device__ __forceinline__ void basis_combine(const cplx<R>* __restrict__ V, int
 }
 
 
+// Progress word in pinned host memory: the last kernel of Arnoldi step j
+// stores j + 1 when it starts, so everything queued before it (earlier
+// steps, copies) has completed.  Written whether or not a system is open.
+__device__ __forceinline__ void step_progress(int* prog, int j) {
+  if (prog && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    *prog = j + 1;
+    __threadfence_system();
+  }
+}
+
 // One Arnoldi step of every open system.  Classical Gram-Schmidt with the
 // DGKS criterion: a second pass is made only if the first one removed more
 // than about 30% of the norm of w (||w'||^2 < 0.49 ||w||^2, with ||w'||^2
 // accumulated while w is updated).  BS threads per system.
 template <typename R, int BS>
 __global__ __launch_bounds__(BS) void k_arnoldi(const SysDesc* __restrict__ sd, int j,
-                                                unsigned long long* ctr) {
+                                                unsigned long long* ctr, int* prog) {
+  step_progress(prog, j);
   // inner products per pass over w: all of them for j < 32 with 4 waves,
   // half as many with 16 waves (register budget)
   constexpr int kChunk = BS <= 256 ? 32 : 8;
@@ -602,12 +618,19 @@ __device__ __forceinline__ void arn_hessenberg(const SysDesc& D, int j, int S, i
 }
 
 // Grid (S_max + 1, systems): x-blocks below S are row slices, the last one
-// forms the Hessenberg column.
+// forms the Hessenberg column.  pre != 0 (FP32 inner steps): block-Jacobi
+// preconditioned systems also form P v_{j+1} for the next step's product,
+// into slot j + 2, each wave for its own kSymB-row block (the block's
+// inverse is loaded first, beside the slot sums).
+static_assert(kArnRows == 4 * kSymB, "one diagonal block per wave of a row slice");
 template <typename R, int kVC>
 __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restrict__ sd, int j,
-                                                        unsigned long long* ctr) {
+                                                        int pre, unsigned long long* ctr,
+                                                        int* prog) {
   __shared__ double c2[2 * (kMaxM + 1)];
   __shared__ double nsh[3];
+  __shared__ cplx<R> vz[kArnRows];
+  step_progress(prog, j);
   const SysDesc D = sd[blockIdx.y];
   const int M = D.M, m = D.m;
   const int s = blockIdx.x;
@@ -621,6 +644,14 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
   const int i = s * kArnRows + tid;
   const bool valid = i < M;
   const int ic = valid ? i : M - 1;
+  constexpr bool kCanFuse = sizeof(R) == 4;  // register budget
+  const bool fuse = kCanFuse && pre && D.Pinv && j + 2 <= m;
+  const int bw = s * (kArnRows / kSymB) + (tid >> 6);  // this wave's diagonal block
+  const bool bin = bw * kSymB < M;
+  cplx<R> pp[kCanFuse ? kSymB : 1];
+  if constexpr (kCanFuse) {
+    if (fuse && bin) pblock_load<R>((const cplx<R>*)D.Pinv + (int64_t)bw * kSymB * kSymB, lane, pp);
+  }
   gcplx<R>* V = as_global((const cplx<R>*)D.basis);
   const cplx<R> x0 = V[(int64_t)(j + 1) * M + ic];
   // the first chunk is loaded before the second pass is known to be needed
@@ -657,8 +688,17 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
     }
   }
   if (!wr) return;
-  if (valid)
-    as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = cmake<R>((R)(re * inv), (R)(im * inv));
+  const cplx<R> nv = cmake<R>((R)(re * inv), (R)(im * inv));
+  if (valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = nv;
+  if constexpr (kCanFuse) {
+    if (fuse) {
+      vz[tid] = valid ? nv : cmake<R>(R(0), R(0));
+      __syncthreads();
+      R zr = R(0), zi = R(0);
+      if (bin) pblock_acc<R, R>(pp, vz + (tid & ~63), zr, zi);
+      if (valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 2) * M + i] = cmake<R>(zr, zi);
+    }
+  }
   if (ctr && tid == 0) {
     const unsigned long long rows = min(kArnRows, M - s * kArnRows);
     atomicAdd(ctr, rows * (second ? j + 3 : 2) * sizeof(cplx<R>));
@@ -750,7 +790,8 @@ void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner
 // finish launch has one more x-block per system for the Hessenberg column).
 template <typename R>
 void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool fused,
-                    unsigned long long* ctr, hipStream_t s) {
+                    bool pre, unsigned long long* ctr, int* prog, hipStream_t s) {
+  const int pf = pre ? 1 : 0;
   const int f = fused ? 1 : 0;
   if (split) {
     const int S = (maxM + kArnRows - 1) / kArnRows;
@@ -758,16 +799,16 @@ void launch_arnoldi(const SysDesc* sd, int n, int maxM, int j, bool split, bool 
     if (j < 16) {
       hipLaunchKernelGGL((k_arn_dots<R, 16>), grid, blk, 0, s, sd, j, f, ctr);
       hipLaunchKernelGGL((k_arn_update<R, 16>), grid, blk, 0, s, sd, j, ctr);
-      hipLaunchKernelGGL((k_arn_finish<R, 16>), gfin, blk, 0, s, sd, j, ctr);
+      hipLaunchKernelGGL((k_arn_finish<R, 16>), gfin, blk, 0, s, sd, j, pf, ctr, prog);
     } else {
       hipLaunchKernelGGL((k_arn_dots<R, 32>), grid, blk, 0, s, sd, j, f, ctr);
       hipLaunchKernelGGL((k_arn_update<R, 32>), grid, blk, 0, s, sd, j, ctr);
-      hipLaunchKernelGGL((k_arn_finish<R, 32>), gfin, blk, 0, s, sd, j, ctr);
+      hipLaunchKernelGGL((k_arn_finish<R, 32>), gfin, blk, 0, s, sd, j, pf, ctr, prog);
     }
   } else if (maxM < 3072) {
-    hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(n), dim3(256), 0, s, sd, j, ctr);
+    hipLaunchKernelGGL((k_arnoldi<R, 256>), dim3(n), dim3(256), 0, s, sd, j, ctr, prog);
   } else {
-    hipLaunchKernelGGL((k_arnoldi<R, 1024>), dim3(n), dim3(1024), 0, s, sd, j, ctr);
+    hipLaunchKernelGGL((k_arnoldi<R, 1024>), dim3(n), dim3(1024), 0, s, sd, j, ctr, prog);
   }
   CQM_HIP(hipGetLastError());
 }
@@ -778,10 +819,10 @@ template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, int max
 
 template void launch_cycle_start<float>(const SysDesc*, int, double, double, hipStream_t);
 template void launch_cycle_start<double>(const SysDesc*, int, double, double, hipStream_t);
-template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, bool,
-                                    unsigned long long*, hipStream_t);
-template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, bool,
-                                     unsigned long long*, hipStream_t);
+template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, bool, bool,
+                                    unsigned long long*, int*, hipStream_t);
+template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, bool, bool,
+                                     unsigned long long*, int*, hipStream_t);
 template void launch_cycle_finish<float>(const SysDesc*, int, int, hipStream_t);
 template void launch_cycle_finish<double>(const SysDesc*, int, int, hipStream_t);
 
