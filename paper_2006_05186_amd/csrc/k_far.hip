@@ -221,7 +221,7 @@ __global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, in
 // through an LDS transpose.  Near pairs are left for the near-field scatter.
 constexpr int kAt = 16;
 template <int FT>
-__global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __restrict__ pts,
+__global__ __launch_bounds__(kAt * kAt, 5) void k_dense_assemble(const double4* __restrict__ pts,
                                                               const int4* __restrict__ vid, int M,
                                                               const double* __restrict__ ea,
                                                               const double* __restrict__ pb,
@@ -244,7 +244,15 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
   __shared__ __align__(16) double stab[kFp64TabLen];
+  // quadrature points of the tile's kAt source triangles (shared by the
+  // threads of one column), staged once instead of held in registers
+  __shared__ double4 spt[kAt][kQ];
   for (int k = threadIdx.x; k < kFp64TabLen; k += kAt * kAt) stab[k] = ftab[k];
+  if (threadIdx.x < kAt * kQ) {
+    const int jt = (int)J * kAt + threadIdx.x / kQ;
+    spt[threadIdx.x / kQ][threadIdx.x % kQ] =
+        jt < M ? pts[jt * kQ + threadIdx.x % kQ] : double4{0.0, 0.0, 0.0, 0.0};
+  }
   __syncthreads();
   const bool inb = i < M && j < M && (I != J || i <= j);
   const bool nearp = inb && share_vertex(vid[i], vid[j]);
@@ -259,15 +267,6 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
 #pragma unroll
   for (int l = 0; l < FT; ++l) vre[l] = vim[l] = 0.0;
   if (live) {
-    double sx[kQ], sy[kQ], sz[kQ], sw[kQ];
-#pragma unroll
-    for (int b = 0; b < kQ; ++b) {
-      const double4 q = pts[j * kQ + b];
-      sx[b] = q.x;
-      sy[b] = q.y;
-      sz[b] = q.z;
-      sw[b] = q.w;
-    }
     double fe[FT], fp[FT];
 #pragma unroll
     for (int l = 0; l < FT; ++l) {
@@ -278,9 +277,10 @@ __global__ __launch_bounds__(kAt * kAt) void k_dense_assemble(const double4* __r
       const double4 t = pts[i * kQ + a];
 #pragma unroll 1
       for (int b = 0; b < kQ; ++b) {
-        const double dx = t.x - sx[b], dy = t.y - sy[b], dz = t.z - sz[b];
+        const double4 q = spt[tx][b];
+        const double dx = t.x - q.x, dy = t.y - q.y, dz = t.z - q.z;
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        const double w = t.w * sw[b] / r;
+        const double w = t.w * q.w / r;
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
           double e, c, sn;
