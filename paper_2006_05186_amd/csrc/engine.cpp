@@ -281,16 +281,20 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     CQM_HIP(hipHostMalloc((void**)&eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
     eb.staging_cap = c;
   }
-  if (eb.status_host_cap < (size_t)kSysiStride * n) {
+  if (eb.status_host_cap < (size_t)n) {
     if (eb.status_host) {
       CQM_HIP(hipStreamSynchronize(s));
       CQM_HIP(hipHostFree(eb.status_host));
+      CQM_HIP(hipHostFree(eb.status_norms));
     }
     eb.status_host = nullptr;
+    eb.status_norms = nullptr;
     eb.status_host_cap = 0;
-    const size_t c = std::max<size_t>((size_t)kSysiStride * n, 1024);
-    CQM_HIP(hipHostMalloc((void**)&eb.status_host, sizeof(int) * c, hipHostMallocDefault));
+    const size_t c = std::max<size_t>((size_t)n, 256);  // systems
+    CQM_HIP(hipHostMalloc((void**)&eb.status_host, sizeof(int) * kSysiStride * c, hipHostMallocDefault));
     CQM_HIP(hipHostGetDevicePointer((void**)&eb.status_host_dev, eb.status_host, 0));
+    CQM_HIP(hipHostMalloc((void**)&eb.status_norms, sizeof(double) * 3 * c, hipHostMallocDefault));
+    CQM_HIP(hipHostGetDevicePointer((void**)&eb.status_norms_dev, eb.status_norms, 0));
     eb.status_host_cap = c;
   }
   if (eb.cyc_cap < (size_t)n + 1) {
@@ -351,8 +355,7 @@ void release_engine_bufs(EngineBufs& b) {
   if (b.groups) (void)hipFree(b.groups);
   if (b.status_host) (void)hipHostFree(b.status_host);
   if (b.cyc_host) (void)hipHostFree(b.cyc_host);
-  if (b.diag_flags) (void)hipHostFree(b.diag_flags);
-  if (b.diag_norms) (void)hipHostFree(b.diag_norms);
+  if (b.status_norms) (void)hipHostFree(b.status_norms);
   if (b.open_cycle) (void)hipFree(b.open_cycle);
   if (b.open_step) (void)hipFree(b.open_step);
   if (b.staging) (void)hipHostFree(b.staging);
@@ -395,7 +398,8 @@ void Engine::init(int k, hipStream_t s) {
 void Engine::status(hipStream_t s) {
   const int n = (int)hd_.size();
   if (!n) return;
-  launch_gather_status(eb.desc, n, eb.status_host_dev, s);
+  // flags and norms of every system straight into pinned host memory
+  launch_gather_diag(eb.desc, n, eb.status_host_dev, eb.status_norms_dev, s);
   CQM_HIP(hipStreamSynchronize(s));
   std::copy(eb.status_host, eb.status_host + flags_.size(), flags_.begin());
 }
@@ -597,35 +601,17 @@ template int Engine::cycle_t<double>(hipStream_t);
 void Engine::finish_diag(int k, hipStream_t s, bool refresh) {
   SolveState* st = S_[k];
   Problem& p = *st->p;
-  const SysDesc* sd = eb.desc + st->first;
   const double outer_tol = p.opt.outer_tol;
   if (refresh) {
+    // residual norms of the last cycle, then the status of every system
+    const SysDesc* sd = eb.desc + st->first;
     if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
     else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);
+    status(s);
   }
-  // flags and norms gathered straight into pinned host memory
-  if (eb.diag_cap < (size_t)p.Fsys) {
-    if (eb.diag_flags) {
-      CQM_HIP(hipStreamSynchronize(s));
-      CQM_HIP(hipHostFree(eb.diag_flags));
-      CQM_HIP(hipHostFree(eb.diag_norms));
-    }
-    eb.diag_flags = nullptr;
-    eb.diag_norms = nullptr;
-    eb.diag_cap = 0;
-    const size_t c = std::max<size_t>(p.Fsys, 256);
-    CQM_HIP(hipHostMalloc((void**)&eb.diag_flags, sizeof(int) * kSysiStride * c, hipHostMallocDefault));
-    CQM_HIP(hipHostMalloc((void**)&eb.diag_norms, sizeof(double) * 3 * c, hipHostMallocDefault));
-    eb.diag_cap = c;
-  }
-  int* fl_dev = nullptr;
-  double* nm_dev = nullptr;
-  CQM_HIP(hipHostGetDevicePointer((void**)&fl_dev, eb.diag_flags, 0));
-  CQM_HIP(hipHostGetDevicePointer((void**)&nm_dev, eb.diag_norms, 0));
-  launch_gather_diag(sd, p.Fsys, fl_dev, nm_dev, s);
-  CQM_HIP(hipStreamSynchronize(s));
-  const int* fl = eb.diag_flags;
-  const double* nm = eb.diag_norms;
+  // else the status read that found every system closed is still current
+  const int* fl = eb.status_host + (size_t)kSysiStride * st->first;
+  const double* nm = eb.status_norms + (size_t)3 * st->first;
   cqm_diag& d = st->diag;
   d.cycles = cycles_run;
   d.total_iters = d.max_iters = 0;

@@ -146,9 +146,8 @@ struct EngineBufs {
                                     // cycle-open flag of every system
   int* cyc_host_dev = nullptr;
   size_t cyc_cap = 0;
-  int* diag_flags = nullptr;        // pinned, closing diagnostics (flags, norms)
-  double* diag_norms = nullptr;
-  size_t diag_cap = 0;
+  double* status_norms = nullptr;   // pinned, 3 per system: ||ghat||, last true
+  double* status_norms_dev = nullptr;  // residual norm, non-finite flag
 };
 
 // Launch shapes picked by timing the candidates on their first use, per
@@ -315,7 +314,7 @@ void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int6
 
 void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s);
 void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
-void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s);
+
 // flags (kSysiStride ints) and ||ghat||, last residual norm, non-finite flag
 // (3 doubles) of n systems, into host-visible memory
 void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hipStream_t s);

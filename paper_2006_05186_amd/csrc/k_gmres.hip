@@ -103,14 +103,6 @@ __global__ __launch_bounds__(256) void k_residual_combine(const SysDesc* __restr
 
 // status of every system into one array, written straight into pinned host
 // memory (made visible to the host before the kernel ends)
-__global__ void k_gather_status(const SysDesc* __restrict__ sd, int n, int* __restrict__ out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int* st = sd[k].sysi;
-  for (int q = 0; q < kSysiStride; ++q) out[k * kSysiStride + q] = st[q];
-  __threadfence_system();
-}
-
 __global__ void k_gather_diag(const SysDesc* __restrict__ sd, int n, int* __restrict__ flags,
                               double* __restrict__ norms) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -775,10 +767,6 @@ void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s) {
 }
 void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_diag, dim3((n + 255) / 256), dim3(256), 0, s, sd, n, flags, norms);
-  CQM_HIP(hipGetLastError());
-}
-void launch_gather_status(const SysDesc* sd, int n, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_status, dim3((n + 255) / 256), dim3(256), 0, s, sd, n, out);
   CQM_HIP(hipGetLastError());
 }
 template <typename R>
