@@ -336,7 +336,7 @@ template <typename R>
 void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
                               hipStream_t s);
 // Block-Jacobi preconditioner of the stored form (k_dense.hip): inverses of
-// the kSymB x kSymB diagonal tiles of every slice (FP64 elimination, stored
+// the kSymB x kSymB diagonal tiles of every slice (elimination and storage
 // in R); application z = P v_j into basis slot j+1 (mode 0, systems with an
 // open cycle) or x += P r (mode 1, systems whose cycle ran).
 template <typename R>

@@ -265,17 +265,22 @@ void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, 
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ d64, int M,
                                                        cplx<R>* __restrict__ pinv) {
-  __shared__ cf64 rowb[2][kB];
-  __shared__ cf64 colb[2][4][kRowsPerWave];
+  // elimination in the precision of the stored inverse (FP32 for the mixed
+  // form: half the registers, so every block of a C2 operator is resident
+  // at once; the preconditioner only has to be one fixed matrix)
+  using Z = cplx<R>;
+  __shared__ Z rowb[2][kB];
+  __shared__ Z colb[2][4][kRowsPerWave];
   const int I = blockIdx.x, l = blockIdx.y, nb = sym_blocks(M);
   const cf64* T = d64 + (int64_t)l * sym_slice(M) + (int64_t)(I * (I + 1) / 2 + I) * kB * kB;
   const int rows = min(kB, M - I * kB);
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  cf64 a[kRowsPerWave];
+  Z a[kRowsPerWave];
 #pragma unroll
   for (int q = 0; q < kRowsPerWave; ++q) {
     const int r = w * kRowsPerWave + q;
-    a[q] = (r < rows && c < rows) ? T[r * kB + c] : cf64{r == c ? 1.0 : 0.0, 0.0};
+    const cf64 v = (r < rows && c < rows) ? T[r * kB + c] : cf64{r == c ? 1.0 : 0.0, 0.0};
+    a[q] = cmake<R>((R)v.re, (R)v.im);
   }
   bool bad = false;
   for (int kb = 0; kb < 4; ++kb) {
@@ -288,36 +293,32 @@ __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ 
         for (int q = 0; q < kRowsPerWave; ++q) colb[buf][w][q] = a[q];
       }
       __syncthreads();
-      const cf64 d = rowb[buf][k];
-      const double dn = d.re * d.re + d.im * d.im;
-      bad |= !(dn > 0.0) || !isfinite(dn);
-      const double id = 1.0 / dn;
-      const cf64 pk{d.re * id, -d.im * id};  // 1 / a_kk
+      const Z d = rowb[buf][k];
+      const R dn = d.re * d.re + d.im * d.im;
+      bad |= !(dn > R(0)) || !isfinite(dn);
+      const R id = R(1) / dn;
+      const Z pk = cmake<R>(d.re * id, -d.im * id);  // 1 / a_kk
       // new pivot row: a_kc / a_kk, and 1 / a_kk at c = k
-      const cf64 rk = rowb[buf][c];
-      const cf64 nr = c == k ? pk : cf64{rk.re * pk.re - rk.im * pk.im, rk.re * pk.im + rk.im * pk.re};
+      const Z rk = rowb[buf][c];
+      const Z nr = c == k ? pk : cmake<R>(rk.re * pk.re - rk.im * pk.im, rk.re * pk.im + rk.im * pk.re);
       // rows r != k: a_rc - a_rk a'_kc, and at c = k the new entry
       // -a_rk / a_kk, which is a_rk - a_rk (1 / a_kk + 1): one update form
       // for every lane
-      const cf64 nu{c == k ? nr.re + 1.0 : nr.re, nr.im};
+      const Z nu = cmake<R>(c == k ? nr.re + R(1) : nr.re, nr.im);
 #pragma unroll
       for (int q = 0; q < kRowsPerWave; ++q) {
-        const cf64 ck = colb[buf][w][q];  // a_rk, r = 16 w + q
+        const Z ck = colb[buf][w][q];  // a_rk, r = 16 w + q
         a[q].re = fma(-ck.re, nu.re, fma(ck.im, nu.im, a[q].re));
         a[q].im = fma(-ck.re, nu.im, fma(-ck.im, nu.re, a[q].im));
       }
       if (w == kb) a[kq] = nr;
     }
   }
-  cplx<R>* out = pinv + ((int64_t)l * nb + I) * kB * kB;
+  Z* out = pinv + ((int64_t)l * nb + I) * kB * kB;
 #pragma unroll
   for (int q = 0; q < kRowsPerWave; ++q) {
     const int r = w * kRowsPerWave + q;
-    const cf64 v = bad ? cf64{r == c ? 1.0 : 0.0, 0.0} : a[q];
-    cplx<R> o;
-    o.re = (R)v.re;
-    o.im = (R)v.im;
-    out[r * kB + c] = o;
+    out[r * kB + c] = bad ? cmake<R>(r == c ? R(1) : R(0), R(0)) : a[q];
   }
 }
 
