@@ -244,7 +244,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
   void* bufs[] = {p->dev.pts64, p->dev.pts32, p->dev.vid, p->dev.area, p->dev.verts,
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
-                  p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ftab, p->dev.ea32,
+                  p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea64u, p->dev.pb64u, p->dev.ftab, p->dev.ea32,
                   p->dev.pb32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);

@@ -222,7 +222,7 @@ __global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, in
 // waves per SIMD (six for the smallest frequency tile), with the source
 // quadrature points in LDS rather than registers.
 constexpr int kAt = 16;
-template <int FT>
+template <int FT, bool kClamp>
 __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(const double4* __restrict__ pts,
                                                               const int4* __restrict__ vid, int M,
                                                               const double* __restrict__ ea,
@@ -286,7 +286,11 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
           double e, c, sn;
-          KMath<double>::eval(fe[l], fp[l], r, e, c, sn, stab);
+          // arguments in table steps; the host has bounded -Re(s) r below
+          // by -708 unless kClamp
+          const double ue = fe[l] * r;
+          e = exp_tabu(kClamp ? fmax(ue, -261474.0) : ue, stab);
+          sincos_tabu(fp[l] * r, stab, &sn, &c);
           e *= w;
           vre[l] += e * c;
           vim[l] -= e * sn;
@@ -520,9 +524,27 @@ static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64
   const int M = (int)p.M;
   const int nt = (M + kAt - 1) / kAt;
   dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
-  hipLaunchKernelGGL((k_dense_assemble<FT>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64, p.dev.vid,
-                     M, p.dev.ea64, p.dev.pb64, p.Fsys, d64, d32, ctr, p.dev.ftab,
-                     p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
+  // -Re(s_l) r >= -(max Re s_l) (bounding-box diagonal): the exponential
+  // needs no clamp when that stays above -700
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (size_t v = 0; v < p.verts.size() / 3; ++v)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], p.verts[3 * v + d]);
+      hi[d] = std::max(hi[d], p.verts[3 * v + d]);
+    }
+  const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  double sr = 0.0;
+  for (int l = 0; l < p.Fsys; ++l) sr = std::max(sr, p.s_re[l]);
+  const bool clamp = !(sr * diag <= 700.0);
+  if (clamp)
+    hipLaunchKernelGGL((k_dense_assemble<FT, true>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
+                       p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
+                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
+  else
+    hipLaunchKernelGGL((k_dense_assemble<FT, false>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
+                       p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
+                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
   CQM_HIP(hipGetLastError());
 }
 

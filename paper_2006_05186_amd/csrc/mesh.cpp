@@ -206,6 +206,18 @@ void upload_problem(Problem& p) {
   }
   p.dev.ea64 = upload(ea64);
   p.dev.pb64 = upload(pb64);
+  // the same coefficients in table steps (256/ln2 and 256/(2 pi) per unit)
+  {
+    std::vector<double> eu(F), pu(F);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    const long double ln2 = 0.693147180559945309417232121458176568L;
+    for (int l = 0; l < F; ++l) {
+      eu[l] = (double)((long double)ea64[l] * 256.0L / ln2);
+      pu[l] = (double)((long double)pb64[l] * 256.0L / two_pi);
+    }
+    p.dev.ea64u = upload(eu);
+    p.dev.pb64u = upload(pu);
+  }
   // tables of the FP64 exp/sincos (extended precision, rounded once)
   std::vector<double> ftab(kFp64TabLen);
   const long double pi_l = 3.141592653589793238462643383279502884L;
