@@ -83,6 +83,12 @@ __device__ __forceinline__ void sincos_bounded(double t, double* s, double* c) {
 // split into a leading part of 35 bits (k * hi exact for |k| < 2^18) and a
 // remainder.  Both functions are branch-free.
 constexpr int kFp64TabLen = 768;
+// A finer sine/cosine table, (sin, cos)(2 pi j/512) for j = 0..511, stored
+// after the first one (the dense assembly stages the exponential part and
+// this one): its remainder is half as large, so cos - 1 needs one Taylor
+// term less.
+constexpr int kFp64Tab512Off = 768, kFp64Tab512Len = 1024;
+constexpr int kFp64TabTotal = kFp64Tab512Off + kFp64Tab512Len;
 constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
 
 // kClamp = false requires x >= -708 (the caller has bounded it).
@@ -147,6 +153,27 @@ __device__ __forceinline__ double exp_tabu(double u, const double* tab) {
   p = fma(p, f, L);
   p = fma(p, f, 1.0);
   return ldexp(tab[ik & 255] * p, ik >> 8);
+}
+
+// u in steps of 2 pi/512; tab512 is the 512-entry (sin, cos) table.
+__device__ __forceinline__ void sincos_tabu512(double u, const double* tab512, double* s,
+                                               double* c) {
+  constexpr double A = 0.01227184630308513;  // 2 pi/512
+  const double kd = u + kRoundMagic;
+  const int ik = (int)__double_as_longlong(kd);
+  const double f = u - (kd - kRoundMagic);  // |A f| <= pi/512
+  const double f2 = f * f;
+  // sin(A f) through (A f)^5; cos(A f) - 1 through (A f)^4 (the next term
+  // is below 8e-17)
+  double ps = A * A * A * A * A / 120.0;
+  ps = fma(ps, f2, -A * A * A / 6.0);
+  ps = fma(ps, f2, A);
+  const double sr = ps * f;
+  const double pc = fma(A * A * A * A / 24.0, f2, -A * A / 2.0);
+  const double cm1 = pc * f2;
+  const double2 sc = *reinterpret_cast<const double2*>(tab512 + 2 * (ik & 511));
+  *s = fma(sc.y, sr, fma(sc.x, cm1, sc.x));
+  *c = fma(-sc.x, sr, fma(sc.y, cm1, sc.y));
 }
 
 __device__ __forceinline__ void sincos_tabu(double u, const double* tab, double* s, double* c) {

@@ -191,7 +191,7 @@ struct MeshDev {
   double* ftab = nullptr;         // FP64 exp/sincos tables (2^(j/256), (sin, cos)(2 pi j/256))
   double* ea64 = nullptr;         // Fpad
   double* pb64 = nullptr;
-  double* ea64u = nullptr;        // ea64 in steps of ln2/256, pb64 in steps of 2 pi/256
+  double* ea64u = nullptr;        // ea64 in steps of ln2/256, pb64 in steps of 2 pi/512
   double* pb64u = nullptr;
   float* ea32 = nullptr;
   float* pb32 = nullptr;

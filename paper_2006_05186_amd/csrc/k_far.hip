@@ -245,11 +245,13 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
   const int i = I * kAt + ty, j = (int)J * kAt + tx;
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
-  __shared__ __align__(16) double stab[kFp64TabLen];
+  // exponential table, then the 512-entry sine/cosine table
+  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
   // quadrature points of the tile's kAt source triangles (shared by the
   // threads of one column), staged once instead of held in registers
   __shared__ double4 spt[kAt][kQ];
-  for (int k = threadIdx.x; k < kFp64TabLen; k += kAt * kAt) stab[k] = ftab[k];
+  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kAt * kAt)
+    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
   if (threadIdx.x < kAt * kQ) {
     const int jt = (int)J * kAt + threadIdx.x / kQ;
     spt[threadIdx.x / kQ][threadIdx.x % kQ] =
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
           // by -708 unless kClamp
           const double ue = fe[l] * r;
           e = exp_tabu(kClamp ? fmax(ue, -261474.0) : ue, stab);
-          sincos_tabu(fp[l] * r, stab, &sn, &c);
+          sincos_tabu512(fp[l] * r, stab + 256, &sn, &c);
           e *= w;
           vre[l] += e * c;
           vim[l] -= e * sn;

@@ -206,25 +206,30 @@ void upload_problem(Problem& p) {
   }
   p.dev.ea64 = upload(ea64);
   p.dev.pb64 = upload(pb64);
-  // the same coefficients in table steps (256/ln2 and 256/(2 pi) per unit)
+  // the same coefficients in table steps (256/ln2 and 512/(2 pi) per unit:
+  // the dense assembly's exponential and fine sine/cosine tables)
   {
     std::vector<double> eu(F), pu(F);
     const long double two_pi = 6.283185307179586476925286766559005768L;
     const long double ln2 = 0.693147180559945309417232121458176568L;
     for (int l = 0; l < F; ++l) {
       eu[l] = (double)((long double)ea64[l] * 256.0L / ln2);
-      pu[l] = (double)((long double)pb64[l] * 256.0L / two_pi);
+      pu[l] = (double)((long double)pb64[l] * 512.0L / two_pi);
     }
     p.dev.ea64u = upload(eu);
     p.dev.pb64u = upload(pu);
   }
   // tables of the FP64 exp/sincos (extended precision, rounded once)
-  std::vector<double> ftab(kFp64TabLen);
+  std::vector<double> ftab(kFp64TabTotal);
   const long double pi_l = 3.141592653589793238462643383279502884L;
   for (int j = 0; j < 256; ++j) {
     ftab[j] = (double)std::exp2((long double)j / 256.0L);
     ftab[256 + 2 * j] = (double)std::sin(pi_l * j / 128.0L);
     ftab[256 + 2 * j + 1] = (double)std::cos(pi_l * j / 128.0L);
+  }
+  for (int j = 0; j < 512; ++j) {
+    ftab[kFp64Tab512Off + 2 * j] = (double)std::sin(pi_l * j / 256.0L);
+    ftab[kFp64Tab512Off + 2 * j + 1] = (double)std::cos(pi_l * j / 256.0L);
   }
   p.dev.ftab = upload(ftab);
   p.dev.ea32 = upload(ea32);
