@@ -40,11 +40,13 @@ template <> struct KMath<float> {
 };
 template <> struct KMath<double> {
   static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-  // e = exp(ea r) (ea <= 0), (c, sn) = (cos, sin)(pb r), table in LDS
+  // e = exp(-Re(s) r), (c, sn) = (cos, sin)(Im(s) r) with the coefficients
+  // in table steps (ea = -Re(s) 256/ln2 <= 0, pb = Im(s) 512/(2 pi)); tab:
+  // the exponential table, then the 512-entry sine/cosine table, in LDS
   static __device__ __forceinline__ void eval(double ea, double pb, double r, double& e,
                                               double& c, double& sn, const double* tab) {
-    e = exp_tab(ea * r, tab);
-    sincos_tab(pb * r, tab, &sn, &c);
+    e = exp_tabu(fmax(ea * r, -261474.0), tab);
+    sincos_tabu512(pb * r, tab + 256, &sn, &c);
   }
 };
 
@@ -69,9 +71,10 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     for (int l = 0; l < nl; ++l) nact += active[(l0 + l) * kSysiStride] != 0;
     if (!nact) return;
   }
-  __shared__ __align__(16) double stab[sizeof(R) == 8 ? kFp64TabLen : 2];
+  __shared__ __align__(16) double stab[sizeof(R) == 8 ? 256 + kFp64Tab512Len : 2];
   if constexpr (sizeof(R) == 8) {
-    for (int k = threadIdx.x; k < kFp64TabLen; k += kTgt) stab[k] = ftab[k];
+    for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kTgt)
+      stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
     __syncthreads();
   }
   const int i = blockIdx.x * kTgt + threadIdx.x;
@@ -399,8 +402,8 @@ static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, i
     pb = p.dev.pb32 + l0;
   } else {
     pts = p.dev.pts64;
-    ea = p.dev.ea64 + l0;
-    pb = p.dev.pb64 + l0;
+    ea = p.dev.ea64u + l0;  // in table steps
+    pb = p.dev.pb64u + l0;
   }
   hipLaunchKernelGGL((k_far_apply<R, FT>), grid, dim3(kTgt), 0, s, pts, p.dev.vid, M, ea, pb,
                      nsys, x, xs, partial, chunk, active, ctr, p.dev.ftab);
