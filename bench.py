@@ -39,12 +39,12 @@ FLOPS_PER_UNIT = 10
 # full rate): VALU instructions per value counted in the ISA of the inner
 # loop, 32 for the dense assembly (table-driven exp and sincos on arguments
 # pre-scaled to table steps, index arithmetic, accumulation; 356 per 11
-# frequencies) and 89 for the FP64 matrix-free apply (which also
-# multiplies by x and accumulates per target).  Expressed in TFLOP/s with the
-# 10-flop convention above.
+# frequencies) and 36 for the FP64 matrix-free apply (the same math, which
+# also multiplies by x and accumulates per target; 328 per 9 frequencies).
+# Expressed in TFLOP/s with the 10-flop convention above.
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 ALU_PEAK_TFLOPS = {"far32": LANE_CYCLES_PER_S / 18 * FLOPS_PER_UNIT / 1e12,
-                   "far64": LANE_CYCLES_PER_S / 89 * FLOPS_PER_UNIT / 1e12,
+                   "far64": LANE_CYCLES_PER_S / 36 * FLOPS_PER_UNIT / 1e12,
                    "assemble": LANE_CYCLES_PER_S / 32 * FLOPS_PER_UNIT / 1e12}
 
 WORKLOADS = {"C1": W.C1, "C2": W.C2, "C3": W.C3}
