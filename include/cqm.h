@@ -101,12 +101,16 @@ typedef struct cqm_options {
                             full group list is used, so closed groups are
                             launched and leave at once)               (0)   */
   int32_t precond;       /* CQM_PRECOND_*: right preconditioner of the
-                            inner GMRES for the stored dense form: the
-                            inverses of the 64 x 64 diagonal blocks of
-                            every V(s_l), formed once per operator.  It
-                            does not change the solution (the refinement
-                            residual is the unpreconditioned one), only
-                            the number of inner steps.        (BLOCK_JACOBI) */
+                            inner GMRES for the plain forms: the inverses
+                            of the 64 x 64 diagonal blocks of every
+                            V(s_l), formed once per operator (stored form:
+                            from its diagonal tiles; matrix-free form:
+                            those blocks assembled on their own, 16 B per
+                            entry plus the inverses).  It does not change
+                            the solution (the refinement residual is the
+                            unpreconditioned one), only the number of
+                            inner steps; the compressed modes ignore it.
+                                                                (BLOCK_JACOBI) */
   int32_t reserved[2];
 } cqm_options;
 

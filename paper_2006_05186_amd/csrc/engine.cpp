@@ -94,6 +94,17 @@ void prepare_operator(Problem& p, hipStream_t s) {
     launch_near_values(p, nv, s);
   }
   p.near_ready = true;
+  if (p.opt.form == CQM_FORM_MATRIX_FREE && p.lay.pinv) {
+    // block-Jacobi: the diagonal blocks assembled on their own, inverted
+    cf64* dg = wsp<cf64>(p, p.lay.diag64);
+    {
+      Timed t(p, CQM_K_ASSEMBLE, s);
+      launch_diag_blocks(p, dg, nv, s);
+    }
+    Timed t(p, CQM_K_OTHER, s);
+    if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(dg, (int)p.M, p.Fsys, true, wsp<cf32>(p, p.lay.pinv), s);
+    else launch_block_inverse<double>(dg, (int)p.M, p.Fsys, true, wsp<cf64>(p, p.lay.pinv), s);
+  }
   if (p.opt.form == CQM_FORM_DENSE) {
     cf64* d64 = wsp<cf64>(p, p.lay.dense64);
     cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
@@ -103,8 +114,8 @@ void prepare_operator(Problem& p, hipStream_t s) {
     }
     if (p.lay.pinv) {
       Timed t(p, CQM_K_OTHER, s);
-      if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(d64, (int)p.M, p.Fsys, wsp<cf32>(p, p.lay.pinv), s);
-      else launch_block_inverse<double>(d64, (int)p.M, p.Fsys, wsp<cf64>(p, p.lay.pinv), s);
+      if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(d64, (int)p.M, p.Fsys, false, wsp<cf32>(p, p.lay.pinv), s);
+      else launch_block_inverse<double>(d64, (int)p.M, p.Fsys, false, wsp<cf64>(p, p.lay.pinv), s);
     }
     p.dense_ready = true;
   }
@@ -192,6 +203,7 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   m_ = S_[0]->p->opt.gmres_restart;
   mixed = mode_is_mixed(S_[0]->p->opt.mode);
   pre_ = false;
+  anypre_ = false;
   bool pre_set = false;
   for (size_t k = 0; k < S_.size(); ++k) {
     SolveState* st = S_[k];
@@ -227,13 +239,23 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
       d.r = st->at<cf64>(st->r) + (size_t)l * M;
       d.ghat = st->at<cf64>(st->ghat) + (size_t)l * M;
       d.part = st->at<double>(st->part) + (size_t)l * ((M + kArnRows - 1) / kArnRows) * (4 * (m_ + 1) + 2);
+      if (!dense_form(p) && !mode_is_h2(p.opt.mode) && p.lay.pinv) {
+        // matrix-free form: P v_j is formed in r's memory (the product reads
+        // it and writes basis slot j + 1)
+        d.Pinv = mixed ? (const void*)(wsp<cf32>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M))
+                       : (const void*)(wsp<cf64>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M));
+        d.zb = d.r;
+        anypre_ = true;
+      }
       if (dense_form(p)) {
         d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * sym_slice(M);
         d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * sym_slice(M)) : nullptr;
         d.symp = st->base + st->sym + sizeof(cf64) * (size_t)l * sym_partials(M);
-        if (p.lay.pinv)
+        if (p.lay.pinv) {
           d.Pinv = mixed ? (const void*)(wsp<cf32>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M))
                          : (const void*)(wsp<cf64>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M));
+          anypre_ = true;
+        }
         // join the group of systems on the same operator slice, if any
         auto it = slot.find(d.V64);
         if (it == slot.end() || groups_[it->second].n == kMaxGroup) {
@@ -315,13 +337,13 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
   bool eligible = !lite_.empty();
   for (SolveState* st : S_)
     eligible = eligible && dense_form(*st->p) && st->p->opt.graphs && !st->p->opt.profile;
-  const bool same = prev_hd_.size() == hd_.size() && prev_split_ == split_ && prev_pre_ == pre_ &&
+  const bool same = prev_hd_.size() == hd_.size() && prev_split_ == split_ && prev_pre_ == anypre_ &&
                     std::memcmp(prev_hd_.data(), hd_.data(), sizeof(SysDesc) * hd_.size()) == 0;
   if (!eligible || !same) drop_graphs();
   graphs_ = eligible;
   prev_hd_ = hd_;
   prev_split_ = split_;
-  prev_pre_ = pre_;
+  prev_pre_ = anypre_;
   if (graphs_) {
     // the full group list, sorted by mesh size, in its own device buffer
     std::vector<int> ord(lite_.size());
@@ -466,8 +488,10 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
   if (!lite_.empty()) {
     const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
     Timed t(p0, c, s);
-    if (pre_ && (j == 0 || !fuse_pre<R>())) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
+    if (anypre_ && (j == 0 || !fuse_pre<R>())) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
     dense_product<R>(list, cls, 0, j, !split_, p0.timer.ctr(c), s);
+  } else if (anypre_ && (j == 0 || !fuse_pre<R>())) {
+    launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -475,8 +499,15 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
     const int M = (int)p.M;
     const int64_t bs = (int64_t)(m_ + 1) * M;
     cplx<R>* basis = reinterpret_cast<cplx<R>*>(st->base + st->basis);
-    apply_op<R>(p, 0, p.Fsys, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
-                st->at<int>(st->sysi) + 1, s);
+    if (p.lay.pinv) {
+      // preconditioned: the product of P v_j, formed in r's memory
+      const cplx<R>* z = reinterpret_cast<const cplx<R>*>(st->base + st->r);
+      apply_op<R>(p, 0, p.Fsys, z, (int64_t)M * (int64_t)(sizeof(cf64) / sizeof(cplx<R>)),
+                  basis + (int64_t)(j + 1) * M, bs, st->at<int>(st->sysi) + 1, s);
+    } else {
+      apply_op<R>(p, 0, p.Fsys, basis + (int64_t)j * M, bs, basis + (int64_t)(j + 1) * M, bs,
+                  st->at<int>(st->sysi) + 1, s);
+    }
   }
   Timed t(p0, CQM_K_ARNOLDI, s);
   launch_arnoldi<R>(eb.desc, n, maxM_, j, split_, split_, fuse_pre<R>(),
@@ -491,7 +522,7 @@ template <typename R> void Engine::step_graph(int j, hipStream_t s) {
     if (!cap_stream_) CQM_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     CQM_HIP(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-    if (pre_ && (j == 0 || !fuse_pre<R>()))
+    if (anypre_ && (j == 0 || !fuse_pre<R>()))
       launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, 0, j, cap_stream_);
     dense_product<R>(eb.all_groups, all_cls_, 0, j, !split_, nullptr, cap_stream_);
     launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, fuse_pre<R>(), nullptr,
@@ -564,7 +595,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     Timed t(p0, CQM_K_OTHER, s);
     launch_cycle_finish<R>(sd, n, maxM_, s);
     // right preconditioning: the cycle left V y in r, x += P (V y)
-    if (pre_) launch_block_apply<R>(sd, n, maxM_, 1, 0, s);
+    if (anypre_) launch_block_apply<R>(sd, n, maxM_, 1, 0, s);
   }
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start

@@ -83,8 +83,12 @@ struct SysDesc {
   const void* Pinv;       // block-Jacobi inverses (inner precision) or null
   int* hflag;             // pinned host word: the cycle-open flag, written at
                           // every Arnoldi step (or null)
+  void* zb;               // where P v_j is formed for the next product: null
+                          // for basis slot j + 1 (stored form), else a vector
+                          // of its own (matrix-free form: the memory of r,
+                          // which the product may not overwrite in place)
 };
-static_assert(sizeof(SysDesc) == 144, "SysDesc layout");
+static_assert(sizeof(SysDesc) == 152, "SysDesc layout");
 // Rows per workgroup (one per thread) of the split Arnoldi step.
 constexpr int kArnRows = 256;
 
@@ -199,7 +203,7 @@ struct MeshDev {
 
 // Offsets (bytes) of the solve workspace.
 struct Layout {
-  size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, pinv = 0, total = 0;
+  size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, pinv = 0, diag64 = 0, total = 0;
 };
 
 struct H2Operator;  // compressed representation (h2.cpp)
@@ -342,7 +346,11 @@ void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, 
 // in R); application z = P v_j into basis slot j+1 (mode 0, systems with an
 // open cycle) or x += P r (mode 1, systems whose cycle ran).
 template <typename R>
-void launch_block_inverse(const cf64* d64, int M, int nsys, cplx<R>* pinv, hipStream_t s);
+void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R>* pinv,
+                          hipStream_t s);
+// the diagonal kSymB-blocks of every V(s_l), FP64, compact [l][block][row][col]
+// (block-Jacobi preconditioner of the matrix-free form; k_far.hip)
+void launch_diag_blocks(const Problem& p, cf64* d, const cf64* nv, hipStream_t s);
 template <typename R>
 void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s);
 inline int64_t block_inverse_elems(int M) { return (int64_t)sym_blocks(M) * kSymB * kSymB; }
@@ -412,10 +420,12 @@ class Engine {
   bool prev_split_ = false;  // layout the captured steps were recorded with
   // block-Jacobi right preconditioning of the stored-operator systems: each
   // step forms P v_j before the product, each cycle closes with x += P V y
-  bool pre_ = false, prev_pre_ = false;
+  // pre_: the stored-form products read slot j + 1; anypre_: some system
+  // (either form) is preconditioned
+  bool pre_ = false, anypre_ = false, prev_pre_ = false;
   // FP32 split steps form P v_{j+1} inside the Arnoldi finish kernel; only
   // the first step of a cycle launches the block product itself
-  template <typename R> bool fuse_pre() const { return pre_ && split_ && sizeof(R) == 4; }
+  template <typename R> bool fuse_pre() const { return anypre_ && split_ && sizeof(R) == 4; }
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
   // inside a cycle the host runs at most kAhead steps ahead of the device

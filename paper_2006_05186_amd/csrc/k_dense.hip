@@ -264,7 +264,7 @@ void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, 
 // buffered by the parity of k, so each step has one barrier.
 template <typename R>
 __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ d64, int M,
-                                                       cplx<R>* __restrict__ pinv) {
+                                                       int compact, cplx<R>* __restrict__ pinv) {
   // elimination in the precision of the stored inverse (FP32 for the mixed
   // form: half the registers, so every block of a C2 operator is resident
   // at once; the preconditioner only has to be one fixed matrix)
@@ -272,7 +272,10 @@ __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ 
   __shared__ Z rowb[2][kB];
   __shared__ Z colb[2][4][kRowsPerWave];
   const int I = blockIdx.x, l = blockIdx.y, nb = sym_blocks(M);
-  const cf64* T = d64 + (int64_t)l * sym_slice(M) + (int64_t)(I * (I + 1) / 2 + I) * kB * kB;
+  // the diagonal tile of the packed slice, or block I of the compact
+  // array of diagonal blocks [frequency][block]
+  const cf64* T = compact ? d64 + ((int64_t)l * nb + I) * kB * kB
+                          : d64 + (int64_t)l * sym_slice(M) + (int64_t)(I * (I + 1) / 2 + I) * kB * kB;
   const int rows = min(kB, M - I * kB);
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
   Z a[kRowsPerWave];
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ 
   }
 }
 
-// mode 0: basis[j+1] = P basis[j] (systems with an open cycle);
+// mode 0: basis[j+1] (or zb) = P basis[j] (systems with an open cycle);
 // mode 1: x += P r (systems whose cycle ran; r holds V y).  Four blocks per
 // workgroup, one wave each.
 template <typename R>
@@ -356,7 +359,8 @@ __global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__
     R re = R(0), im = R(0);
     if constexpr (kWhole) pblock_acc<R, R>(p, vbR[w], re, im);
     else pblock_mul<R, R, 16>(Pb, vbR[w], lane, re, im);
-    if (i < M) ((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = cmake<R>(re, im);
+    cplx<R>* z = D.zb ? (cplx<R>*)D.zb : (cplx<R>*)D.basis + (int64_t)(j + 1) * M;
+    if (i < M) z[i] = cmake<R>(re, im);
   } else {
     cf64 ri{0.0, 0.0};
     if (i < M) ri = as_global((const cf64*)D.r)[i];
@@ -376,9 +380,10 @@ __global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__
 }
 
 template <typename R>
-void launch_block_inverse(const cf64* d64, int M, int nsys, cplx<R>* pinv, hipStream_t s) {
+void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R>* pinv,
+                          hipStream_t s) {
   hipLaunchKernelGGL((k_block_inverse<R>), dim3(sym_blocks(M), nsys), dim3(256), 0, s, d64, M,
-                     pinv);
+                     compact ? 1 : 0, pinv);
   CQM_HIP(hipGetLastError());
 }
 template <typename R>
@@ -387,8 +392,8 @@ void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hip
                      mode, j);
   CQM_HIP(hipGetLastError());
 }
-template void launch_block_inverse<float>(const cf64*, int, int, cf32*, hipStream_t);
-template void launch_block_inverse<double>(const cf64*, int, int, cf64*, hipStream_t);
+template void launch_block_inverse<float>(const cf64*, int, int, bool, cf32*, hipStream_t);
+template void launch_block_inverse<double>(const cf64*, int, int, bool, cf64*, hipStream_t);
 template void launch_block_apply<float>(const SysDesc*, int, int, int, int, hipStream_t);
 template void launch_block_apply<double>(const SysDesc*, int, int, int, int, hipStream_t);
 

@@ -225,7 +225,11 @@ __global__ void k_far_reduce_near(const cplx<R>* __restrict__ partial, int S, in
 // waves per SIMD (six for the smallest frequency tile), with the source
 // quadrature points in LDS rather than registers.
 constexpr int kAt = 16;
-template <int FT, bool kClamp>
+// kDiag: only the pairs inside diagonal kSymB-blocks (10 tile pairs per
+// block), both triangles, FP64, into a compact array of full blocks
+// [frequency][block][kSymB x kSymB] (the block-Jacobi preconditioner of the
+// matrix-free form).
+template <int FT, bool kClamp, bool kDiag>
 __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(const double4* __restrict__ pts,
                                                               const int4* __restrict__ vid, int M,
                                                               const double* __restrict__ ea,
@@ -238,12 +242,19 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
                                                               const int32_t* __restrict__ ncol,
                                                               const cf64* __restrict__ nval,
                                                               int64_t nnz) {
-  // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I
-  const long long kk = blockIdx.x;
+  // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I (in
+  // the diagonal mode, within block blockIdx.x / 10)
+  constexpr int kSub = kSymB / kAt;
+  const long long kk = kDiag ? blockIdx.x % (kSub * (kSub + 1) / 2) : blockIdx.x;
   long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
   while (J * (J + 1) / 2 > kk) --J;
   while ((J + 1) * (J + 2) / 2 <= kk) ++J;
-  const int I = (int)(kk - J * (J + 1) / 2);
+  int I = (int)(kk - J * (J + 1) / 2);
+  if (kDiag) {
+    const int Bk = blockIdx.x / (kSub * (kSub + 1) / 2);
+    I += Bk * kSub;
+    J += Bk * kSub;
+  }
   const int tx = threadIdx.x % kAt, ty = threadIdx.x / kAt;
   const int i = I * kAt + ty, j = (int)J * kAt + tx;
   const int l0 = blockIdx.y * FT;
@@ -303,12 +314,19 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
       }
     }
   }
-  const int64_t SL = sym_slice(M);
+  // compact diagonal mode: block b = i / kSymB holds rows and columns
+  // b kSymB .. b kSymB + kSymB - 1, row-major
+  auto cidx = [&](int r, int c) -> int64_t {
+    const int b = r / kSymB;
+    return ((int64_t)b * kSymB + (r - b * kSymB)) * kSymB + (c - b * kSymB);
+  };
+  const int64_t SL = kDiag ? (int64_t)sym_blocks(M) * kSymB * kSymB : sym_slice(M);
   // the mirrored entry (j, i) is stored too when both lie in one diagonal
   // block of the packed triangle (written directly: about 6 % of tiles)
-  const bool mirpos = i != j && sym_stored(j, i);
+  const bool mirpos = i != j && (kDiag || sym_stored(j, i));
   const bool mir = live && mirpos;
-  const int64_t oi = sym_index(i, j), om = mirpos ? sym_index(j, i) : 0;
+  const int64_t oi = kDiag ? cidx(i, j) : sym_index(i, j);
+  const int64_t om = mirpos ? (kDiag ? cidx(j, i) : sym_index(j, i)) : 0;
   if (nearp && nval) {
     // a pair sharing a vertex takes its near-field value (static plus
     // dynamic part), found in the CSR rows of i and, mirrored, of j
@@ -523,12 +541,15 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
   CQM_HIP(hipGetLastError());
 }
 
-template <int FT>
+template <int FT, bool kDiag = false>
 static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
                               unsigned long long* ctr, hipStream_t s) {
   const int M = (int)p.M;
   const int nt = (M + kAt - 1) / kAt;
-  dim3 grid((unsigned)((int64_t)nt * (nt + 1) / 2), (p.Fsys + FT - 1) / FT);
+  constexpr int kSub = kSymB / kAt;
+  const int64_t gx = kDiag ? (int64_t)sym_blocks(M) * (kSub * (kSub + 1) / 2)
+                           : (int64_t)nt * (nt + 1) / 2;
+  dim3 grid((unsigned)gx, (p.Fsys + FT - 1) / FT);
   // -Re(s_l) r >= -(max Re s_l) (bounding-box diagonal): the exponential
   // needs no clamp when that stays above -700
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -543,11 +564,11 @@ static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64
   for (int l = 0; l < p.Fsys; ++l) sr = std::max(sr, p.s_re[l]);
   const bool clamp = !(sr * diag <= 700.0);
   if (clamp)
-    hipLaunchKernelGGL((k_dense_assemble<FT, true>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
+    hipLaunchKernelGGL((k_dense_assemble<FT, true, kDiag>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
                        p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
                        p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
   else
-    hipLaunchKernelGGL((k_dense_assemble<FT, false>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
+    hipLaunchKernelGGL((k_dense_assemble<FT, false, kDiag>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
                        p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
                        p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
   CQM_HIP(hipGetLastError());
@@ -598,6 +619,10 @@ void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* n
     tn.assemble[key] = FT;
   }
   run(FT, ctr);
+}
+
+void launch_diag_blocks(const Problem& p, cf64* d, const cf64* nv, hipStream_t s) {
+  dense_assemble_ft<11, true>(p, d, nullptr, nv, nullptr, s);
 }
 
 template void launch_far_apply<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,

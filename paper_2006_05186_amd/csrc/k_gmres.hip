@@ -612,7 +612,7 @@ __device__ __forceinline__ void arn_hessenberg(const SysDesc& D, int j, int S, i
 // Grid (S_max + 1, systems): x-blocks below S are row slices, the last one
 // forms the Hessenberg column.  pre != 0 (FP32 inner steps): block-Jacobi
 // preconditioned systems also form P v_{j+1} for the next step's product,
-// into slot j + 2, each wave for its own kSymB-row block (the block's
+// into slot j + 2 (or zb), each wave for its own kSymB-row block (the block's
 // inverse is loaded first, beside the slot sums).
 static_assert(kArnRows == 4 * kSymB, "one diagonal block per wave of a row slice");
 template <typename R, int kVC>
@@ -688,7 +688,8 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
       __syncthreads();
       R zr = R(0), zi = R(0);
       if (bin) pblock_acc<R, R>(pp, vz + (tid & ~63), zr, zi);
-      if (valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 2) * M + i] = cmake<R>(zr, zi);
+      cplx<R>* z = D.zb ? (cplx<R>*)D.zb : (cplx<R>*)D.basis + (int64_t)(j + 2) * M;
+      if (valid) as_global(z)[i] = cmake<R>(zr, zi);
     }
   }
   if (ctr && tid == 0) {

@@ -302,6 +302,12 @@ void compute_layout(Problem& p) {
         worst = std::max(worst, std::max(a, b));
       }
       L.partial = take(worst * M);
+      if (p.opt.precond == CQM_PRECOND_BLOCK_JACOBI) {
+        // the diagonal blocks (FP64, compact) and their inverses
+        L.diag64 = take(sizeof(cf64) * Fs * block_inverse_elems((int)M));
+        L.pinv = take((mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64)) * Fs *
+                      block_inverse_elems((int)M));
+      }
     }
   }
   L.total = off;
