@@ -109,7 +109,9 @@ typedef struct cqm_options {
                             entry plus the inverses).  It does not change
                             the solution (the refinement residual is the
                             unpreconditioned one), only the number of
-                            inner steps; the compressed modes ignore it.
+                            inner steps; the compressed modes use the
+                            plain operator's diagonal blocks the same way
+                            (the near-field values they need as well).
                                                                 (BLOCK_JACOBI) */
   int32_t reserved[2];
 } cqm_options;

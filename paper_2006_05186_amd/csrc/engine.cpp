@@ -70,6 +70,20 @@ void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R
 template void apply_op<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
 template void apply_op<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);
 
+// Block-Jacobi inverses of the matrix-free and compressed forms: the plain
+// operator's diagonal blocks assembled on their own (near pairs from nv),
+// then inverted.
+static void diag_block_inverses(Problem& p, const cf64* nv, hipStream_t s) {
+  cf64* dg = wsp<cf64>(p, p.lay.diag64);
+  {
+    Timed t(p, CQM_K_ASSEMBLE, s);
+    launch_diag_blocks(p, dg, nv, s);
+  }
+  Timed t(p, CQM_K_OTHER, s);
+  if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(dg, (int)p.M, p.Fsys, true, wsp<cf32>(p, p.lay.pinv), s);
+  else launch_block_inverse<double>(dg, (int)p.M, p.Fsys, true, wsp<cf64>(p, p.lay.pinv), s);
+}
+
 // Near field and (dense form) the assembled operator, or the compressed one.
 void prepare_operator(Problem& p, hipStream_t s) {
   require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
@@ -80,8 +94,18 @@ void prepare_operator(Problem& p, hipStream_t s) {
   }
   if (mode_is_h2(p.opt.mode)) {
     if (!(p.opt.reuse_operator && p.near_ready)) {
-      Timed t(p, CQM_K_ASSEMBLE, s);
-      h2_prepare(p, s);
+      {
+        Timed t(p, CQM_K_ASSEMBLE, s);
+        h2_prepare(p, s);
+      }
+      if (p.lay.pinv) {
+        cf64* nv = wsp<cf64>(p, p.lay.near_val);
+        {
+          Timed t(p, CQM_K_NEAR, s);
+          launch_near_values(p, nv, s);
+        }
+        diag_block_inverses(p, nv, s);
+      }
     }
     p.near_ready = true;
     return;
@@ -94,17 +118,7 @@ void prepare_operator(Problem& p, hipStream_t s) {
     launch_near_values(p, nv, s);
   }
   p.near_ready = true;
-  if (p.opt.form == CQM_FORM_MATRIX_FREE && p.lay.pinv) {
-    // block-Jacobi: the diagonal blocks assembled on their own, inverted
-    cf64* dg = wsp<cf64>(p, p.lay.diag64);
-    {
-      Timed t(p, CQM_K_ASSEMBLE, s);
-      launch_diag_blocks(p, dg, nv, s);
-    }
-    Timed t(p, CQM_K_OTHER, s);
-    if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(dg, (int)p.M, p.Fsys, true, wsp<cf32>(p, p.lay.pinv), s);
-    else launch_block_inverse<double>(dg, (int)p.M, p.Fsys, true, wsp<cf64>(p, p.lay.pinv), s);
-  }
+  if (p.opt.form == CQM_FORM_MATRIX_FREE && p.lay.pinv) diag_block_inverses(p, nv, s);
   if (p.opt.form == CQM_FORM_DENSE) {
     cf64* d64 = wsp<cf64>(p, p.lay.dense64);
     cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
@@ -239,9 +253,9 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
       d.r = st->at<cf64>(st->r) + (size_t)l * M;
       d.ghat = st->at<cf64>(st->ghat) + (size_t)l * M;
       d.part = st->at<double>(st->part) + (size_t)l * ((M + kArnRows - 1) / kArnRows) * (4 * (m_ + 1) + 2);
-      if (!dense_form(p) && !mode_is_h2(p.opt.mode) && p.lay.pinv) {
-        // matrix-free form: P v_j is formed in r's memory (the product reads
-        // it and writes basis slot j + 1)
+      if (!dense_form(p) && p.lay.pinv) {
+        // matrix-free and compressed forms: P v_j is formed in r's memory
+        // (the product reads it and writes basis slot j + 1)
         d.Pinv = mixed ? (const void*)(wsp<cf32>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M))
                        : (const void*)(wsp<cf64>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M));
         d.zb = d.r;

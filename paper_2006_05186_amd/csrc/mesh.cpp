@@ -286,6 +286,14 @@ void compute_layout(Problem& p) {
   off = state_layout(p, p.own);
   if (mode_is_h2(p.opt.mode)) {
     L.partial = take(h2_workspace_bytes(p));
+    if (p.opt.precond == CQM_PRECOND_BLOCK_JACOBI) {
+      // block-Jacobi from the plain operator's diagonal blocks: near values,
+      // the blocks (FP64, compact) and their inverses
+      L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
+      L.diag64 = take(sizeof(cf64) * Fs * block_inverse_elems((int)M));
+      L.pinv = take((mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64)) * Fs *
+                    block_inverse_elems((int)M));
+    }
   } else {
     L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
     if (p.opt.form == CQM_FORM_DENSE) {
