@@ -428,9 +428,13 @@ class Engine {
   template <typename R> bool fuse_pre() const { return anypre_ && split_ && sizeof(R) == 4; }
   std::vector<int> flags_;
   int maxM_ = 0, m_ = 30;
-  // inside a cycle the host runs at most kAhead steps ahead of the device
-  // (progress word) and reads the cycle-open flags after queueing each step
-  static constexpr int kAhead = 3;
+  // inside a cycle the host queues step j + 1 once the last kernel of step
+  // j - kAhead has started (progress word) and reads the cycle-open flags
+  // after queueing each step.  0 measured best at C2 (3.21 ms per solve,
+  // against 3.24 / 3.29 / 3.35 / 3.55 ms for 1 / 2 / 3 / 5): every step
+  // queued beyond a cycle's last useful one costs a full launch sequence,
+  // while issuing a step takes the host less time than the kernel it waits on
+  static constexpr int kAhead = 0;
   void wait_progress(int target, hipStream_t s);
   // HIP graphs of the Arnoldi steps (dense-form batches without profiling):
   // step j = products of every group + the Arnoldi step, over the full group
