@@ -91,12 +91,10 @@ constexpr int kFp64Tab512Off = 768, kFp64Tab512Len = 1024;
 constexpr int kFp64TabTotal = kFp64Tab512Off + kFp64Tab512Len;
 constexpr double kRoundMagic = 6755399441055744.0;  // 1.5 * 2^52
 
-// kClamp = false requires x >= -708 (the caller has bounded it).
-template <bool kClamp = true>
 __device__ __forceinline__ double exp_tab(double x, const double* tab) {
   // x = (256 m + j) ln2/256 + r, |r| <= ln2/512; x below -708 is taken as
   // -708 (the result, 3.3e-308, stands for 0)
-  const double xc = kClamp ? fmax(x, -708.0) : x;
+  const double xc = fmax(x, -708.0);
   const double kd = fma(xc, 369.3299304675746, kRoundMagic);  // 256/ln2
   const int ik = (int)__double_as_longlong(kd);
   const double k = kd - kRoundMagic;
@@ -134,12 +132,12 @@ __device__ __forceinline__ void sincos_tab(double t, const double* tab, double* 
   *c = fma(-sc.x, sr, fma(sc.y, cm1, sc.y));
 }
 
-// The same two functions for arguments given in table steps: u = x 256/ln2
-// for the exponential, u = t 256/(2 pi) for sine/cosine (the caller scales
-// the frequency once instead of every argument).  k = round(u) and the
-// remainder f = u - k are exact, so no Cody-Waite split is needed; the
-// Taylor coefficients carry the powers of the step (ln2/256, 2 pi/256).  The
-// rounding of u costs about |x| 2^-53 absolute in the argument, the same
+// The same functions for arguments given in table steps: u = x 256/ln2 for
+// the exponential, u = t 512/(2 pi) for sine/cosine on the finer table (the
+// caller scales the frequency once instead of every argument).  k = round(u)
+// and the remainder f = u - k are exact, so no Cody-Waite split is needed;
+// the Taylor coefficients carry the powers of the step (ln2/256, 2 pi/512).
+// The rounding of u costs about |x| 2^-53 absolute in the argument, the same
 // order as forming x = -Re(s) r itself.  exp_tabu requires u >= -708 256/ln2.
 __device__ __forceinline__ double exp_tabu(double u, const double* tab) {
   constexpr double L = 0.0027076061740622863;  // ln2/256
@@ -176,24 +174,5 @@ __device__ __forceinline__ void sincos_tabu512(double u, const double* tab512, d
   *c = fma(-sc.x, sr, fma(sc.y, cm1, sc.y));
 }
 
-__device__ __forceinline__ void sincos_tabu(double u, const double* tab, double* s, double* c) {
-  constexpr double A = 0.024543692606170259;  // 2 pi/256
-  const double kd = u + kRoundMagic;
-  const int ik = (int)__double_as_longlong(kd);
-  const double f = u - (kd - kRoundMagic);
-  const double f2 = f * f;
-  // sin(A f) through (A f)^5, cos(A f) - 1 through (A f)^6
-  double ps = A * A * A * A * A / 120.0;
-  ps = fma(ps, f2, -A * A * A / 6.0);
-  ps = fma(ps, f2, A);
-  const double sr = ps * f;
-  double pc = -A * A * A * A * A * A / 720.0;
-  pc = fma(pc, f2, A * A * A * A / 24.0);
-  pc = fma(pc, f2, -A * A / 2.0);
-  const double cm1 = pc * f2;
-  const double2 sc = *reinterpret_cast<const double2*>(tab + 256 + 2 * (ik & 255));
-  *s = fma(sc.y, sr, fma(sc.x, cm1, sc.x));
-  *c = fma(-sc.x, sr, fma(sc.y, cm1, sc.y));
-}
 
 }  // namespace cqm
