@@ -140,6 +140,25 @@ def test_block_jacobi_keeps_the_answer_and_cuts_steps(ctx, c1, mode, form):
     assert O.rel_error(q1, q0, area) < 1e-8
 
 
+@pytest.mark.parametrize("restart", [2, 3, 5])
+@pytest.mark.parametrize("form", [C.CQM_FORM_DENSE, C.CQM_FORM_MATRIX_FREE])
+def test_short_restarts_match_oracle(ctx, c1, form, restart):
+    """Restart lengths of a few steps: cycles end on the basis being full
+    (the block product of the next step is then formed by the first step of
+    the next cycle), many refinement cycles; both precisions."""
+    wl, V, T, r, area = c1
+    for mode in (C.CQM_FP64_PLAIN, C.CQM_MIXED_PLAIN):
+        say(f"short restart m={restart} form={form} mode={mode}")
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form, gmres_restart=restart,
+                    max_cycles=400)
+        p.set_plane_wave()
+        q, rc, d = p.solve()
+        err = O.rel_error(q.cpu().numpy(), r["q"], area)
+        say(f"  rc={rc} err={err:.3e} iters={d.total_iters} cycles={d.cycles}")
+        assert rc == C.CQM_OK and d.converged == 1 and err < 1e-8
+        p.close()
+
+
 def test_kernel_work_counters(ctx, c1):
     """The per-class work the kernels count for the roofline matches what the
     solve did: every far pair of the symmetric assembly once per frequency,
