@@ -616,14 +616,16 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     Timed t(p0, CQM_K_GEMV64, s);
     dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
   }
+  bool other_forms = false;  // stored-form residuals are complete already
   for (SolveState* st : S_) {
     Problem& p = *st->p;
     if (dense_form(p)) continue;
+    other_forms = true;
     const int M = (int)p.M;
     apply_op<double>(p, 0, p.Fsys, st->at<cf64>(st->x), M, st->at<cf64>(st->r), M,
                      st->at<int>(st->sysi), s);
   }
-  {
+  if (other_forms) {
     Timed t(p0, CQM_K_OTHER, s);
     launch_residual_combine(sd, n, s);
   }

@@ -181,7 +181,7 @@ void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int6
 // members' flags and vectors all hang off that one load.  The group lists
 // are rebuilt by the host at its status checks; members closed since are
 // skipped.  which = 0: basis[j] -> basis[j+1] of systems with an open cycle
-// (inner precision); which = 1: x -> r of open systems (FP64).
+// (inner precision); which = 1: x -> r = ghat - V x of open systems (FP64).
 template <typename R, bool kGrouped>
 __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict__ gl, int which,
                                                      int j, unsigned long long* ctr) {
@@ -228,8 +228,16 @@ __global__ __launch_bounds__(256) void k_symv_reduce_desc(const SysDesc* __restr
   const int M = D.M;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
-  cplx<R>* y = which == 0 ? (cplx<R>*)D.basis + (int64_t)(j + 1) * M : (cplx<R>*)(void*)D.r;
-  y[i] = sum_partials<R>((const cplx<R>*)D.symp, M, i);
+  const cplx<R> v = sum_partials<R>((const cplx<R>*)D.symp, M, i);
+  if (which == 0) {
+    ((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = v;
+  } else {
+    // the FP64 residual ghat - V x, formed here
+    cplx<R> o;
+    o.re = (R)D.ghat[i].re - v.re;
+    o.im = (R)D.ghat[i].im - v.im;
+    ((cplx<R>*)(void*)D.r)[i] = o;
+  }
 }
 
 template <typename R>

@@ -94,9 +94,11 @@ __global__ __launch_bounds__(256) void k_cycle_start(const SysDesc* __restrict__
 }
 
 // r <- ghat - r for open systems (r holds V x on entry).
+// Stored-operator systems (symp set) have theirs formed by the product's
+// reduction already.
 __global__ __launch_bounds__(256) void k_residual_combine(const SysDesc* __restrict__ sd) {
   const SysDesc D = sd[blockIdx.x];
-  if (!D.sysi[0]) return;
+  if (!D.sysi[0] || D.symp) return;
   for (int i = threadIdx.x; i < D.M; i += 256)
     D.r[i] = cf64{D.ghat[i].re - D.r[i].re, D.ghat[i].im - D.r[i].im};
 }
