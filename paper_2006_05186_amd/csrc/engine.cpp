@@ -502,10 +502,10 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
   if (!lite_.empty()) {
     const int c = sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64;
     Timed t(p0, c, s);
-    if (anypre_ && (j == 0 || !fuse_pre<R>())) launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
+    if (anypre_ && (j == 0 || !fuse_pre<R>())) launch_block_apply<R>(eb.desc, n, maxM_, j, s);
     dense_product<R>(list, cls, 0, j, !split_, p0.timer.ctr(c), s);
   } else if (anypre_ && (j == 0 || !fuse_pre<R>())) {
-    launch_block_apply<R>(eb.desc, n, maxM_, 0, j, s);
+    launch_block_apply<R>(eb.desc, n, maxM_, j, s);
   }
   for (SolveState* st : S_) {
     Problem& p = *st->p;
@@ -537,7 +537,7 @@ template <typename R> void Engine::step_graph(int j, hipStream_t s) {
     hipGraph_t g = nullptr;
     CQM_HIP(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
     if (anypre_ && (j == 0 || !fuse_pre<R>()))
-      launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, 0, j, cap_stream_);
+      launch_block_apply<R>(eb.desc, (int)hd_.size(), maxM_, j, cap_stream_);
     dense_product<R>(eb.all_groups, all_cls_, 0, j, !split_, nullptr, cap_stream_);
     launch_arnoldi<R>(eb.desc, (int)hd_.size(), maxM_, j, split_, split_, fuse_pre<R>(), nullptr,
                       eb.cyc_host_dev, cap_stream_);
@@ -607,9 +607,8 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   }
   {
     Timed t(p0, CQM_K_OTHER, s);
+    // x += V y, or x += P (V y) for preconditioned systems
     launch_cycle_finish<R>(sd, n, maxM_, s);
-    // right preconditioning: the cycle left V y in r, x += P (V y)
-    if (anypre_) launch_block_apply<R>(sd, n, maxM_, 1, 0, s);
   }
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle: the list from its start

@@ -341,10 +341,12 @@ void launch_dense_gemv_groups(const GroupLite* gl, int ngroups, int M, bool grou
 template <typename R>
 void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
                               hipStream_t s);
-// Block-Jacobi preconditioner of the stored form (k_dense.hip): inverses of
-// the kSymB x kSymB diagonal tiles of every slice (elimination and storage
-// in R); application z = P v_j into basis slot j+1 (mode 0, systems with an
-// open cycle) or x += P r (mode 1, systems whose cycle ran).
+// Block-Jacobi preconditioner (k_dense.hip): inverses of the kSymB x kSymB
+// diagonal blocks of every slice (elimination and storage in R), from the
+// packed slice's diagonal tiles or from a compact array of the blocks;
+// application z = P v_j into basis slot j+1 (or zb) for systems with an open
+// cycle.  (The FP32 finish kernel forms the next step's z itself, the cycle
+// finish x += P V y.)
 template <typename R>
 void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R>* pinv,
                           hipStream_t s);
@@ -352,7 +354,7 @@ void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R
 // (block-Jacobi preconditioner of the matrix-free form; k_far.hip)
 void launch_diag_blocks(const Problem& p, cf64* d, const cf64* nv, hipStream_t s);
 template <typename R>
-void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s);
+void launch_block_apply(const SysDesc* sd, int n, int maxM, int j, hipStream_t s);
 inline int64_t block_inverse_elems(int M) { return (int64_t)sym_blocks(M) * kSymB * kSymB; }
 
 // ------------------------------------------------------------ host helpers

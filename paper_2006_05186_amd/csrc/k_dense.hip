@@ -333,18 +333,13 @@ __global__ __launch_bounds__(256) void k_block_inverse(const cf64* __restrict__ 
   }
 }
 
-// mode 0: basis[j+1] (or zb) = P basis[j] (systems with an open cycle);
-// mode 1: x += P r (systems whose cycle ran; r holds V y).  Four blocks per
-// workgroup, one wave each.
+// basis[j+1] (or zb) = P basis[j] for systems with an open cycle.  Four
+// blocks per workgroup, one wave each.
 template <typename R>
-__global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__ sd, int mode,
-                                                     int j) {
-  __shared__ cf64 vb64[4][kB];
-  __shared__ cplx<R> vbR[4][kB];
+__global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__ sd, int j) {
+  __shared__ cplx<R> vb[4][kB];
   const SysDesc D = sd[blockIdx.y];
-  if (!D.Pinv) return;
-  const int* st = D.sysi;
-  if (mode == 0 ? !st[1] : (!st[0] || st[2] == 0)) return;
+  if (!D.Pinv || !D.sysi[1]) return;
   const int M = D.M, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.x * 4 + w;
   if (blockIdx.x * 4 * kB >= M) return;
@@ -357,34 +352,17 @@ __global__ __launch_bounds__(256) void k_block_apply(const SysDesc* __restrict__
   if constexpr (kWhole) {
     if (blk) pblock_load<R>(Pb, lane, p);
   }
-  if (mode == 0) {
-    const cplx<R>* v = (const cplx<R>*)D.basis + (int64_t)j * M;
-    cplx<R> vi = cmake<R>(R(0), R(0));
-    if (i < M) vi = as_global(v)[i];
-    vbR[w][lane] = vi;
-    __syncthreads();
-    if (!blk) return;
-    R re = R(0), im = R(0);
-    if constexpr (kWhole) pblock_acc<R, R>(p, vbR[w], re, im);
-    else pblock_mul<R, R, 16>(Pb, vbR[w], lane, re, im);
-    cplx<R>* z = D.zb ? (cplx<R>*)D.zb : (cplx<R>*)D.basis + (int64_t)(j + 1) * M;
-    if (i < M) z[i] = cmake<R>(re, im);
-  } else {
-    cf64 ri{0.0, 0.0};
-    if (i < M) ri = as_global((const cf64*)D.r)[i];
-    vb64[w][lane] = ri;
-    __syncthreads();
-    if (!blk) return;
-    double re = 0.0, im = 0.0;
-    if constexpr (kWhole) pblock_acc<R, double>(p, vb64[w], re, im);
-    else pblock_mul<R, double, 16>(Pb, vb64[w], lane, re, im);
-    if (i < M) {
-      cf64 x = D.x[i];
-      x.re += re;
-      x.im += im;
-      D.x[i] = x;
-    }
-  }
+  const cplx<R>* v = (const cplx<R>*)D.basis + (int64_t)j * M;
+  cplx<R> vi = cmake<R>(R(0), R(0));
+  if (i < M) vi = as_global(v)[i];
+  vb[w][lane] = vi;
+  __syncthreads();
+  if (!blk) return;
+  R re = R(0), im = R(0);
+  if constexpr (kWhole) pblock_acc<R, R>(p, vb[w], re, im);
+  else pblock_mul<R, R, 16>(Pb, vb[w], lane, re, im);
+  cplx<R>* z = D.zb ? (cplx<R>*)D.zb : (cplx<R>*)D.basis + (int64_t)(j + 1) * M;
+  if (i < M) z[i] = cmake<R>(re, im);
 }
 
 template <typename R>
@@ -395,15 +373,15 @@ void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R
   CQM_HIP(hipGetLastError());
 }
 template <typename R>
-void launch_block_apply(const SysDesc* sd, int n, int maxM, int mode, int j, hipStream_t s) {
+void launch_block_apply(const SysDesc* sd, int n, int maxM, int j, hipStream_t s) {
   hipLaunchKernelGGL((k_block_apply<R>), dim3((sym_blocks(maxM) + 3) / 4, n), dim3(256), 0, s, sd,
-                     mode, j);
+                     j);
   CQM_HIP(hipGetLastError());
 }
 template void launch_block_inverse<float>(const cf64*, int, int, bool, cf32*, hipStream_t);
 template void launch_block_inverse<double>(const cf64*, int, int, bool, cf64*, hipStream_t);
-template void launch_block_apply<float>(const SysDesc*, int, int, int, int, hipStream_t);
-template void launch_block_apply<double>(const SysDesc*, int, int, int, int, hipStream_t);
+template void launch_block_apply<float>(const SysDesc*, int, int, int, hipStream_t);
+template void launch_block_apply<double>(const SysDesc*, int, int, int, hipStream_t);
 
 template void launch_dense_gemv_groups<float>(const GroupLite*, int, int, bool, int, int,
                                               unsigned long long*, hipStream_t);

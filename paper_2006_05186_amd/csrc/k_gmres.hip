@@ -751,13 +751,32 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const SysDesc* __restrict_
     }
   }
   __syncthreads();
-  if (i >= M) return;
   const cplx<R>* V = (const cplx<R>*)D.basis;
-  // preconditioned systems: V y to r, from which the next launch adds P V y
-  cf64* xl = D.Pinv ? D.r : D.x;
-  double re = D.Pinv ? 0.0 : xl[i].re, im = D.Pinv ? 0.0 : xl[i].im;
-  basis_combine<R, 16>(V, M, i, y, k, 1.0, re, im);
-  xl[i] = cf64{re, im};
+  const bool valid = i < M;
+  double re = 0.0, im = 0.0;
+  basis_combine<R, 16>(V, M, valid ? i : M - 1, y, k, 1.0, re, im);  // (V y)_i
+  if (!D.Pinv) {
+    if (valid) {
+      const cf64 xv = D.x[i];
+      D.x[i] = cf64{xv.re + re, xv.im + im};
+    }
+    return;
+  }
+  // right preconditioning: x += P (V y); a workgroup's 256 rows are four
+  // whole diagonal blocks, one per wave
+  __shared__ cf64 vy[256];
+  vy[threadIdx.x] = valid ? cf64{re, im} : cf64{0.0, 0.0};
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + w;
+  if (b * kSymB >= M) return;
+  double zr = 0.0, zi = 0.0;
+  pblock_mul<R, double, 16>((const cplx<R>*)D.Pinv + (int64_t)b * kSymB * kSymB, vy + w * kSymB,
+                            lane, zr, zi);
+  if (valid) {
+    const cf64 xv = D.x[i];
+    D.x[i] = cf64{xv.re + zr, xv.im + zi};
+  }
 }
 
 void launch_gmres_init(const SysDesc* sd, int n, hipStream_t s) {
