@@ -422,6 +422,7 @@ void Engine::wait_progress(int target, hipStream_t s) {
       CQM_HIP(hipStreamSynchronize(s));
       return;
     }
+    __builtin_ia32_pause();  // spin-wait hint to the core
   }
 }
 
