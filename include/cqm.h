@@ -227,7 +227,8 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
 
 /* ------------------------------------------------------------ test hooks */
 /* BDF2 CQM frequencies for N steps on (0,T]; rho = 0 selects rho^N = 1e-8.
- * s_re, s_im: host arrays of N+1 doubles. */
+ * s_re, s_im: host arrays of N+1 doubles.  CQM_EINVAL unless N >= 1, T > 0
+ * and 0 <= rho < 1. */
 int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im);
 
 /* y_l = V(s_l) x_l for l = l0 .. l0+nl-1 with the problem's operator in the

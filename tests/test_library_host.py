@@ -34,6 +34,21 @@ def test_host_frequencies_match_oracle(N, T):
     assert np.max(np.abs(s - ref) / np.abs(ref)) < 1e-14
 
 
+@pytest.mark.parametrize("N,T,rho", [(16, 2.0, 0.5), (33, 4.0, 0.97), (64, 4.0, 10 ** (-8 / 64))])
+def test_host_frequencies_with_explicit_radius(N, T, rho):
+    s = C.cqm_frequencies(N, T, rho)
+    ref, r, _ = O.frequencies(N, T, rho)
+    assert r == rho
+    assert np.max(np.abs(s - ref) / np.abs(ref)) < 1e-14
+
+
+@pytest.mark.parametrize("N,T,rho", [(8, 1.0, 1.0), (8, 1.0, -0.1), (8, 0.0, 0.5), (8, -1.0, 0.0)])
+def test_host_frequencies_reject_bad_arguments(N, T, rho):
+    with pytest.raises(C.CqmError) as e:
+        C.cqm_frequencies(N, T, rho)
+    assert e.value.code == C.CQM_EINVAL
+
+
 def test_host_argument_errors():
     with pytest.raises(C.CqmError) as e:
         C.cqm_frequencies(0, 1.0)
