@@ -371,7 +371,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs "
-              f"is described in DESIGN.md and not built", file=sys.stderr)
+              f"is not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
