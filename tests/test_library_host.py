@@ -27,6 +27,17 @@ def test_library_exports_every_declared_symbol():
     assert set(C.EXPORTED_SYMBOLS) <= set(names)
 
 
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback: every entry point goes through load_library, which raises
+    monkeypatch.setattr(C, "_lib", None)
+    monkeypatch.setattr(C, "library_path", lambda: str(tmp_path / "libcqm.so"))
+    for call in (lambda: C.cqm_frequencies(8, 1.0), C.cqm_default_options,
+                 lambda: C.cqm_ctx_create(0)):
+        with pytest.raises(C.CqmError) as e:
+            call()
+        assert "not built" in str(e.value)
+
+
 @pytest.mark.parametrize("N,T", [(8, 2.0), (32, 4.0), (64, 4.0), (128, 6.0), (256, 6.0)])
 def test_host_frequencies_match_oracle(N, T):
     s = C.cqm_frequencies(N, T)
