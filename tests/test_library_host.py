@@ -1,5 +1,6 @@
 """Host-side checks of the C-ABI library: it loads, exports every declared
 symbol, and its host-only entry points agree with the oracle (no GPU calls)."""
+import ctypes
 import os
 import re
 
@@ -25,6 +26,20 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert set(C.EXPORTED_SYMBOLS) <= set(names)
+
+
+def test_binding_signatures_match_the_header():
+    src = open(os.path.join(ROOT, "include", "cqm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    decls = re.findall(r"\b(int|const char\*)\s+(cqm_\w+)\s*\(([^)]*)\)\s*;", src)
+    assert len(decls) == len(declared_functions())
+    L = C.load_library()
+    for ret, name, args in decls:
+        args = args.strip()
+        nargs = 0 if args in ("", "void") else len(args.split(","))
+        f = getattr(L, name)
+        assert f.argtypes is not None and len(f.argtypes) == nargs, name
+        assert f.restype is (ctypes.c_char_p if ret == "const char*" else ctypes.c_int), name
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
