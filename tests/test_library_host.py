@@ -84,3 +84,17 @@ def test_host_argument_errors():
     assert o.eps_aca == 1e-6 and o.eta == 1.0 and o.outer_tol == 1e-15
     assert o.autotune == 1 and o.arnoldi_layout == C.CQM_ARNOLDI_AUTO and o.graphs == 0
     assert o.precond == C.CQM_PRECOND_BLOCK_JACOBI
+
+
+def test_server_default_options_as_documented():
+    o = C.cqm_server_default_options()
+    assert (o.max_active, o.cache_operators, o.large_lane, o.large_bytes) == (16, 1, 0, 0)
+    d = C.cqm_default_options()
+    # the solver defaults are the library's, with operator reuse switched on
+    for name, _ in C.cqm_options._fields_:
+        if name in ("reserved", "reuse_operator"):
+            continue
+        assert getattr(o.solver, name) == getattr(d, name), name
+    assert o.solver.reuse_operator == 1
+    with pytest.raises(C.CqmError):
+        C._check(C.load_library().cqm_server_default_options(None))
