@@ -22,8 +22,11 @@
  *     per-mesh tables it uploads at cqm_problem_create.
  *   - Pointers are DEVICE pointers unless the parameter says "host".
  *   - Calls taking a hipStream_t enqueue on that stream.  cqm_solve and
- *     cqm_solve_batch synchronise that stream internally (convergence checks)
- *     and return when the output is written.
+ *     cqm_solve_batch synchronise that stream internally (convergence is
+ *     steered by flags the device writes to host memory) and return when the
+ *     output is written; cqm_apply_V returns once its launches are queued.
+ *   - Each declaration names the passage of the paper that defines what it
+ *     computes, or says "Paper: no passage" for plumbing.
  *   - Complex device arrays are interleaved (re, im) pairs of double
  *     (precision 64) or float (precision 32).
  *   - Time-step arrays are row-major (N+1) x M: row n is t_n = n*dt, column i
@@ -53,8 +56,13 @@ extern "C" {
 /* ------------------------------------------------------------ options */
 /* Precision / representation of the operator. */
 #define CQM_FP64_PLAIN 0   /* FP64 kernel evaluation, FP64 GMRES            */
-#define CQM_MIXED_PLAIN 1  /* FP32 inner GMRES on an FP32 far field, FP64
-                              near field and FP64 outer residuals            */
+#define CQM_MIXED_PLAIN 1  /* FP32 inner GMRES, FP64 outer residuals.  The
+                              near-field entries are computed in FP64; the
+                              matrix-free form also applies them in FP64,
+                              while the stored form keeps one FP32 copy of
+                              the whole operator (near entries included) for
+                              the inner products and the FP64 one for the
+                              residuals                                      */
 #define CQM_MIXED_H2ACA 2  /* H2 x MACA operator, FP32-stored factors in the
                               inner solve, FP64 residuals                    */
 #define CQM_FP64_H2ACA 3   /* H2 x MACA operator, all FP64                    */
@@ -176,49 +184,82 @@ typedef struct cqm_ctx_s* cqm_ctx_t;
 typedef struct cqm_problem_s* cqm_problem_t;
 typedef struct cqm_server_s* cqm_server_t;
 
-/* Thread-local message describing the last error (never NULL). */
+/* Thread-local message describing the last error (never NULL).
+ * Paper: no passage (error reporting of the library). */
 const char* cqm_last_error(void);
 
-/* Fill *opt (host) with the defaults listed above. */
+/* Fill *opt (host) with the defaults listed above.  The method parameters
+ * follow Section 3.1 (rho, eq. cqm_freq), Section 4.1 (n_min, eta,
+ * eq. qadm), Section 4.2 (cheb_m, Algorithm 1) and Section 5.1 (eps_aca,
+ * Algorithm 2); the solver parameters are this library's (the paper solves
+ * by LU, Section 3.2, and suggests iterative solvers, Section 6.2).
+ * CQM_EINVAL if opt is NULL. */
 int cqm_default_options(cqm_options* opt);
 
 /* ------------------------------------------------------------ context */
-/* Bind a context to HIP device `device`. */
+/* Bind a context to HIP device `device` (library-owned handle, freed by
+ * cqm_ctx_destroy after every problem and server on it).  CQM_EINVAL for a
+ * bad device index or NULL out.  Paper: no passage (device binding). */
 int cqm_ctx_create(int device, cqm_ctx_t* out);
 int cqm_ctx_destroy(cqm_ctx_t ctx);
 
 /* ------------------------------------------------------------ problems */
-/* Create a problem on a closed surface mesh.
+/* Create a problem on a closed surface mesh: the flat triangles and the
+ * piecewise-constant space S_h^0 of Section 3.2, N steps of size dt = T/N
+ * (Section 3.1), and for the compressed modes the cluster and block trees of
+ * Section 4.1 (eq. qadm) with the Chebyshev bases of Section 4.2.
  *   vertices: host, nv x 3 doubles;  tris: host, M x 3 int32 vertex indices
- *   (0-based).  N >= 2 time steps on (0, T].  Triangles sharing a vertex index
- *   are the near field (singular quadrature).  Uploads per-mesh tables.
- *   CQM_EINVAL on degenerate triangles, out-of-range indices or bad options. */
+ *   (0-based), both copied.  N >= 2 time steps on (0, T].  Triangles sharing
+ *   a vertex index are the near field (singular quadrature of the Galerkin
+ *   entries, Section 3.2).  Uploads per-mesh tables (library-owned, freed by
+ *   cqm_problem_destroy).  opt may be NULL (defaults).
+ *   CQM_EINVAL on degenerate triangles, out-of-range indices or bad options;
+ *   CQM_EDEVICE if the upload fails. */
 int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv,
                        const int32_t* tris, int64_t M, int32_t N, double T,
                        const cqm_options* opt, cqm_problem_t* out);
 int cqm_problem_destroy(cqm_problem_t p);
 
-/* Bytes of device workspace a solve of this problem needs (host out). */
+/* Bytes of device workspace a solve of this problem needs (host out).
+ * Paper: no passage (memory plan; the storage it holds is that of
+ * Section 6.2, Corollary cor:complex, for the compressed modes). */
 int cqm_workspace_size(cqm_problem_t p, size_t* bytes);
 /* Attach caller-owned device memory (>= cqm_workspace_size, 256-byte
- * aligned).  The library never allocates on the solve path. */
+ * aligned; the caller keeps ownership and must keep it alive while the
+ * problem is used).  The library never allocates on the solve path.
+ * CQM_ENOMEM if too small, CQM_EINVAL if NULL or misaligned.
+ * Paper: no passage (memory plumbing). */
 int cqm_set_workspace(cqm_problem_t p, void* dev_ptr, size_t bytes);
 
-/* Incident data.  Plane wave (host arguments): g_D = -A exp(-((t - x.d -
- * t0)/sigma)^2), d normalised by the library.  Or caller samples of g_D at the
- * 6 quadrature points of every triangle: device, (N+1) x M x 6 doubles, read
- * during cqm_solve (the pointer must stay valid). */
+/* Incident data: the Dirichlet condition of Section 2.1 (eq. bc), projected
+ * onto S_h^0 at every step t_n (the L2 projection of Section 3.2, with the
+ * 6-point rule on each triangle).  Plane wave (host arguments):
+ * g_D = -A exp(-((t - x.d - t0)/sigma)^2), d normalised by the library
+ * (CQM_EINVAL for a zero direction or sigma <= 0).  Or caller samples of g_D
+ * at the 6 quadrature points of every triangle: device, (N+1) x M x 6
+ * doubles, caller-owned, read during cqm_solve (the pointer must stay
+ * valid). */
 int cqm_set_plane_wave(cqm_problem_t p, const double direction[3], double sigma,
                        double t0, double amplitude);
 int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g);
 
-/* Solve.  q_out: device, (N+1) x M doubles (density coefficient of triangle
- * i at step n).  diag: host, may be NULL.  Returns CQM_ENOCONV (with output
- * written) if some frequency missed outer_tol. */
+/* Solve the all-at-once form of the convolution quadrature (Section 3.1,
+ * eq. cqm, omega_n, cqm_freq; the remark closing Section 6.2): right-hand
+ * sides b_n (Section 3.2), the scaled transform ghat_l = sum_n rho^n b_n
+ * zeta^-nl, one Galerkin system V(s_l) xhat_l = ghat_l per frequency, and
+ * the inverse transform q_n = rho^-n/(N+1) sum_l xhat_l zeta^nl (eq. vhat,
+ * eq. dft).  q_out: device, (N+1) x M doubles, caller-owned (density
+ * coefficient of triangle i at step n).  diag: host, may be NULL.  Returns
+ * CQM_ENOCONV (with output written) if some frequency missed outer_tol,
+ * CQM_ENAN on non-finite data, CQM_ENOMEM without a workspace.  The call
+ * waits for the stream: convergence is steered by flags the device writes
+ * to host memory, so it returns after q_out is written. */
 int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream);
 
 /* Solve `count` independent problems (different meshes, N and T allowed)
- * together: their frequency systems are batched in shared launches.
+ * together, each as cqm_solve (Section 3.1, remark closing Section 6.2):
+ * their frequency systems are batched in shared launches (batching itself
+ * has no passage in the paper).
  * q_outs[k] and diags[k] as for cqm_solve (diags may be NULL).  The
  * problems must share gmres_restart, and those in the stored dense form
  * must share precond; otherwise CQM_EINVAL before any work is queued. */
@@ -226,25 +267,37 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
                     cqm_diag* diags, hipStream_t stream);
 
 /* ------------------------------------------------------------ test hooks */
-/* BDF2 CQM frequencies for N steps on (0,T]; rho = 0 selects rho^N = 1e-8.
+/* BDF2 CQM frequencies s_l = delta(rho zeta^-l)/dt for N steps on (0,T]
+ * (Section 3.1, eq. cqm_freq; delta(xi) = (1-xi)(3-xi)/2); rho = 0 selects
+ * rho^N = 1e-8.
  * s_re, s_im: host arrays of N+1 doubles.  CQM_EINVAL unless N >= 1, T > 0
  * and 0 <= rho < 1. */
 int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im);
 
-/* y_l = V(s_l) x_l for l = l0 .. l0+nl-1 with the problem's operator in the
- * given precision (32 or 64; 32 is the inner-iteration operator).  x, y:
- * device complex arrays nl x M (triangle order of the caller).  Assembles
- * what the operator needs on first use. */
+/* y_l = V(s_l) x_l for l = l0 .. l0+nl-1: the Galerkin matrices
+ * V_l[m,i] = <phi_m, V(s_l) phi_i> of Section 3.2 with the kernel of
+ * eq. fundsol (plain modes), or their compressed form of Section 6,
+ * eq. lrfinal (H2 x MACA modes), in the given precision (32 or 64; 32 is the
+ * inner-iteration operator).  x, y: device complex arrays nl x M
+ * (caller-owned, triangle order of the caller).  Assembles what the operator
+ * needs on first use, into the workspace.  CQM_EINVAL for a frequency range
+ * outside the solved band or a bad precision; CQM_ENOMEM without a
+ * workspace. */
 int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
                 const void* x, void* y, hipStream_t stream);
 
-/* Near-field (vertex-sharing) pairs and their static Duffy integrals.
- * Host arrays; pass NULL to query *nnz first.  row_ptr: M+1, col: nnz,
- * static_vals: nnz doubles (integral of 1/(4 pi |x-y|) over the pair). */
+/* Near-field (vertex-sharing) pairs and their static Duffy integrals: the
+ * singular part of the Galerkin entries of Section 3.2 (kernel of
+ * eq. fundsol at s = 0).  Host arrays, caller-owned; pass NULL to query
+ * *nnz first.  row_ptr: M+1, col: nnz, static_vals: nnz doubles (integral
+ * of 1/(4 pi |x-y|) over the pair).  CQM_EINVAL on NULL p or nnz. */
 int cqm_near_entries(cqm_problem_t p, int64_t* nnz, int32_t* row_ptr,
                      int32_t* col, double* static_vals);
 
-/* Operator statistics after a solve or apply (host struct; solve fields 0). */
+/* Operator statistics after a solve or apply (host struct; solve fields 0):
+ * block counts of the partition (Section 4.1), MACA ranks (Section 5.1,
+ * Algorithm 2) and the operator's storage (Section 6.2, Corollary
+ * cor:complex).  CQM_EINVAL on NULL arguments. */
 int cqm_operator_stats(cqm_problem_t p, cqm_diag* out);
 
 /* ------------------------------------------------------------ serving */
@@ -263,7 +316,10 @@ typedef struct cqm_server_opts {
                               (plain form) would exceed large_bytes are
                               solved in the compressed form (H2 x MACA) by a
                               second worker on its own stream             (0) */
-  int32_t reserved[5];
+  int32_t fail_after_cycles; /* failure-path test hook: > 0 makes lane 0's
+                              worker stop with CQM_EDEVICE after that many
+                              restart cycles, as after a device error     (0) */
+  int32_t reserved[4];
   int64_t large_bytes;     /* size limit of the above; <= 0: budget / 4   (0) */
   cqm_options solver;      /* options of every request (mode, form, tolerances) */
 } cqm_server_opts;
@@ -283,27 +339,37 @@ typedef struct cqm_server_stats {
   int64_t submitted, completed, rejected, active, queued, peak_active;
   int64_t arena_bytes, peak_arena_bytes, operators_built, operator_cache_hits, cycles;
   int64_t lane_completed[2]; /* completed requests per lane (1: large)    */
-  int64_t reserved[3];
+  int64_t arena_used;        /* arena bytes held now (states + operators) */
+  int64_t reserved[2];
 } cqm_server_stats_t;
 
-/* Default server options (host). */
+/* Default server options (host).  Paper: no passage (serving loop). */
 int cqm_server_default_options(cqm_server_opts* opts);
-/* Start a server on ctx's device with an arena of hbm_budget bytes. */
+/* Start a server on ctx's device with an arena of hbm_budget bytes
+ * (library-owned until cqm_server_destroy).  CQM_ENOMEM if the arena cannot
+ * be allocated.  Paper: no passage (serving loop). */
 int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* opts,
                       cqm_server_t* out);
-/* Queue a request (mesh copied); *ticket identifies it.  Returns at once. */
+/* Queue a request (mesh copied); *ticket identifies it.  Returns at once.
+ * Each request is solved as cqm_solve (Section 3.1, remark closing
+ * Section 6.2).  CQM_EINVAL on bad arguments; CQM_EDEVICE (nothing queued)
+ * when the lane the request belongs to has stopped after a device error. */
 int cqm_server_submit(cqm_server_t s, const cqm_request* req, uint64_t* ticket);
-/* *done: 0 queued or running, 1 finished (return value: the request's
+/* Paper: no passage (serving loop).
+ * *done: 0 queued or running, 1 finished (return value: the request's
  * CQM_OK / CQM_ENOCONV / CQM_ENAN), -1 rejected (return value CQM_ENOMEM or
  * CQM_EINVAL).  When finished, q_out (host, (N+1) x M doubles, may be NULL),
  * diag (may be NULL) and latency_ms (submit to completion, may be NULL) are
  * written.  A finished ticket stays readable until the server is destroyed. */
 int cqm_server_poll(cqm_server_t s, uint64_t ticket, int32_t* done, double* q_out,
                     cqm_diag* diag, double* latency_ms);
-/* Block until every submitted request has finished or been rejected. */
+/* Block until every submitted request has finished or been rejected.
+ * CQM_EDEVICE if a lane stopped after a device error (its requests are
+ * rejected with CQM_EDEVICE).  Paper: no passage (serving loop). */
 int cqm_server_drain(cqm_server_t s);
+/* Counters of the server (host struct).  Paper: no passage. */
 int cqm_server_stats(cqm_server_t s, cqm_server_stats_t* out);
-/* Drain, stop the worker and release the arena. */
+/* Drain, stop the worker and release the arena.  Paper: no passage. */
 int cqm_server_destroy(cqm_server_t s);
 
 #ifdef __cplusplus

@@ -89,7 +89,8 @@ class cqm_diag(ctypes.Structure):
 
 class cqm_server_opts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("cache_operators", ctypes.c_int32),
-                ("large_lane", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("large_lane", ctypes.c_int32), ("fail_after_cycles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4),
                 ("large_bytes", ctypes.c_int64), ("solver", cqm_options)]
 
 
@@ -104,7 +105,8 @@ class cqm_server_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "completed", "rejected", "active", "queued", "peak_active", "arena_bytes",
         "peak_arena_bytes", "operators_built", "operator_cache_hits", "cycles")] + \
-        [("lane_completed", ctypes.c_int64 * 2), ("reserved", ctypes.c_int64 * 3)]
+        [("lane_completed", ctypes.c_int64 * 2), ("arena_used", ctypes.c_int64),
+         ("reserved", ctypes.c_int64 * 2)]
 
     def as_dict(self):
         out = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -302,7 +304,7 @@ def cqm_server_default_options(**solver):
     o = cqm_server_opts()
     _check(load_library().cqm_server_default_options(ctypes.byref(o)))
     for k, v in solver.items():
-        if k in ("max_active", "cache_operators", "large_lane", "large_bytes"):
+        if k in ("max_active", "cache_operators", "large_lane", "large_bytes", "fail_after_cycles"):
             setattr(o, k, v)
         else:
             setattr(o.solver, k, v)

@@ -528,18 +528,26 @@ int far_partial_slots(int M, int nsys, int precision) {
 }
 
 template <typename R>
-void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* partial,
-                            const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
-                            const cf64* near_vals, const int* active, hipStream_t s) {
+static void far_reduce_near_slots(const Problem& p, int l0, int nsys, const cplx<R>* partial,
+                                  int S, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+                                  const cf64* near_vals, const int* active, hipStream_t s) {
   const int M = (int)p.M;
-  const FarShape sh = far_shape_of(p, nsys, sizeof(R) == 4 ? 32 : 64);
-  const int S = far_splits(M, nsys, sh.ft, sh.waves);
   dim3 grid((M + 255) / 256, nsys);
   hipLaunchKernelGGL((k_far_reduce_near<R>), grid, dim3(256), 0, s, partial, S, nsys, M, x, xs, y,
                      ys, p.dev.near_rowptr, p.dev.near_col, near_vals, (int64_t)p.col.size(), l0,
                      active);
   CQM_HIP(hipGetLastError());
 }
+
+template <typename R>
+void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* partial,
+                            const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
+                            const cf64* near_vals, const int* active, hipStream_t s) {
+  const FarShape sh = far_shape_of(p, nsys, sizeof(R) == 4 ? 32 : 64);
+  const int S = far_splits((int)p.M, nsys, sh.ft, sh.waves);
+  far_reduce_near_slots<R>(p, l0, nsys, partial, S, x, xs, y, ys, near_vals, active, s);
+}
+
 
 template <int FT, bool kDiag = false>
 static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,

@@ -118,6 +118,7 @@ struct cqm_server_s {
     std::deque<Request*> queue;    // guarded by mu
     std::vector<Request*> active;  // owned by the lane's worker
     std::thread worker;
+    bool dead = false;             // guarded by mu: the worker stopped on an error
   };
 
   cqm_ctx_t ctx = nullptr;
@@ -264,7 +265,15 @@ struct cqm_server_s {
       r->op = op;
       const bool prepare = !op->ready;
       ak.unlock();
-      pre_solve(s, L.stream, prepare);
+      try {
+        pre_solve(s, L.stream, prepare);
+      } catch (...) {
+        std::lock_guard<std::mutex> a2(amu);
+        arena.release(r->off, r->bytes);
+        op->users--;
+        r->op = nullptr;
+        throw;
+      }
       {
         std::lock_guard<std::mutex> a2(amu);
         op->ready = true;
@@ -334,6 +343,7 @@ struct cqm_server_s {
       CQM_HIP(hipSetDevice(ctx->device));
       Engine E(*ctx, L.eb);
       bool dirty = true;
+      int64_t lane_cycles = 0;
       for (;;) {
         {
           std::unique_lock<std::mutex> lk(mu);
@@ -359,6 +369,11 @@ struct cqm_server_s {
           std::lock_guard<std::mutex> lk(mu);
           ++st.cycles;
         }
+        ++lane_cycles;
+        if (L.id == 0 && opts.fail_after_cycles > 0 && lane_cycles >= opts.fail_after_cycles) {
+          CQM_HIP(hipStreamSynchronize(L.stream));
+          throw Error(CQM_EDEVICE, "lane 0 stopped by the fail_after_cycles test hook");
+        }
         E.status(L.stream);
         for (Request* r : L.active) r->cycles++;
         // retire finished (or out-of-cycles) requests, highest index first
@@ -380,24 +395,49 @@ struct cqm_server_s {
         }
       }
     } catch (const std::exception& e) {
+      // The lane stops: give back the arena regions and operator uses of
+      // its active requests (operators left half-built are dropped), reject
+      // everything it holds, and mark it dead so that submit refuses new
+      // requests for it and drain/destroy do not wait on it.  (Operators
+      // without users are kept only when caching is on.)
+      (void)hipStreamSynchronize(L.stream);
+      {
+        std::lock_guard<std::mutex> ak(amu);
+        for (Request* r : L.active)
+          if (r->op) {
+            arena.release(r->off, r->bytes);
+            r->op->users--;
+            r->op = nullptr;
+          }
+        for (int q = (int)cache.size() - 1; q >= 0; --q)
+          if ((!cache[q]->ready || !opts.cache_operators) && cache[q]->users == 0) {
+            arena.release(cache[q]->off, cache[q]->bytes);
+            cqm_problem_destroy(static_cast<cqm_problem_t>(cache[q]->prob));
+            cache.erase(cache.begin() + q);
+          }
+      }
       std::lock_guard<std::mutex> lk(mu);
+      L.dead = true;
       worker_error = e.what();
+      const auto now = clk::now();
       for (Request* r : L.queue) {
         r->state = 3;
         r->rc = CQM_EDEVICE;
+        r->t_done = now;
         ++st.rejected;
       }
       L.queue.clear();
       for (Request* r : L.active) {
         r->state = 3;
         r->rc = CQM_EDEVICE;
+        r->t_done = now;
         ++st.rejected;
       }
       L.active.clear();
       cv_done.notify_all();
     }
   }
-  bool idle() const {  // mu held
+  bool idle() const {  // mu held; a dead lane holds nothing
     for (int k = 0; k < nlanes; ++k)
       if (!lanes[k].queue.empty() || !lanes[k].active.empty()) return false;
     return (int64_t)(st.completed + st.rejected) == st.submitted;
@@ -471,6 +511,7 @@ int cqm_server_submit(cqm_server_t s, const cqm_request* q, uint64_t* ticket) {
   r->t_submit = clk::now();
   r->lane = (s->nlanes > 1 && s->dense_bytes(*r) > s->opts.large_bytes) ? 1 : 0;
   std::lock_guard<std::mutex> lk(s->mu);
+  if (s->lanes[r->lane].dead) return CQM_EDEVICE;
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
   s->lanes[r->lane].queue.push_back(r.get());
@@ -519,6 +560,7 @@ int cqm_server_stats(cqm_server_t s, cqm_server_stats_t* out) {
     }
   }
   std::lock_guard<std::mutex> ak(s->amu);
+  out->arena_used = (int64_t)s->arena.used;
   out->arena_bytes = (int64_t)s->arena.size;
   out->peak_arena_bytes = (int64_t)s->arena.peak;
   return CQM_OK;

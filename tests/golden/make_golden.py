@@ -1,24 +1,32 @@
 """Write stored oracle outputs used by the GPU parity tests.
 
 Calls only oracle/ and cqm_workloads/ (no GPU code).  Run from the repository
-root:  python tests/golden/make_golden.py
-Outputs: tests/golden/sphere1280_N64_T4.npz with the density q (N+1, M), the
-forward-transformed data ghat and the frequency-domain solutions xhat.
+root:
+    python tests/golden/make_golden.py            # sphere1280_N64_T4
+    python tests/golden/make_golden.py --c3 -j 7  # sphere5120_N128_T6
+Outputs tests/golden/<workload>.npz with the density q (N+1, M) and the
+frequency-domain solutions xhat (distinct frequencies); the 1280-triangle file
+also holds the forward-transformed data ghat and the static near-field values.
+
+The 5120-triangle file is the same all-at-once oracle solve: its frequencies
+are independent (one dense assembly and LU each), so they are spread over
+worker processes, each running oracle.assemble_V and an LU solve for its
+frequencies; the transforms and near-field values are the oracle's own.
 """
+import argparse
+import multiprocessing as mp
 import os
 import sys
 import time
 
-import numpy as np
-
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-import cqm_workloads as W  # noqa: E402
-import oracle as O  # noqa: E402
 
-
-def main():
+def _c2():
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
     wl = W.C2
     V, T = wl.mesh()
     t = time.time()
@@ -26,6 +34,60 @@ def main():
     print(f"{wl.name}: oracle {time.time() - t:.1f}s, im_ratio {r['im_ratio']:.2e}")
     np.savez_compressed(os.path.join(HERE, f"{wl.name}.npz"), q=r["q"], ghat=r["ghat"],
                         xhat=r["xhat"], static=r["static"])
+
+
+_G = {}
+
+
+def _init(V, T, pairs, static):
+    _G.update(V=V, T=T, pairs=pairs, static=static)
+
+
+def _one(args):
+    import scipy.linalg as sla
+    import oracle as O
+    l, s, g = args
+    A = O.assemble_V(_G["V"], _G["T"], s, 5, _G["pairs"], _G["static"])
+    return l, sla.lu_solve(sla.lu_factor(A, overwrite_a=True), g)
+
+
+def _c3(workers):
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
+    wl = W.C3
+    V, T = wl.mesh()
+    t = time.time()
+    s, rho, dt = O.frequencies(wl.N, wl.T)
+    F = wl.N + 1
+    H = O.num_frequencies_half(F)
+    w = wl.wave
+    b = O.rhs(V, T, wl.N, wl.T, w.direction, w.sigma, w.t0, w.amplitude)
+    ghat = O.forward_dft(b, rho, H)
+    pairs = O.near_pairs(T)
+    static = O.near_static(V, T, pairs, 5)
+    xhat = np.empty((H, len(T)), dtype=np.complex128)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers, initializer=_init, initargs=(V, T, pairs, static)) as pool:
+        for l, x in pool.imap_unordered(_one, [(l, s[l], ghat[l]) for l in range(H)]):
+            xhat[l] = x
+            print(f"  frequency {l} done at {time.time() - t:.0f}s", flush=True)
+    q, im_ratio = O.inverse_dft(xhat, rho, F, conjugate_fill=True)
+    print(f"{wl.name}: oracle {time.time() - t:.1f}s, im_ratio {im_ratio:.2e}")
+    np.savez_compressed(os.path.join(HERE, f"{wl.name}.npz"), q=q, xhat=xhat)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--c3", action="store_true", help="the 5120-triangle workload")
+    ap.add_argument("-j", type=int, default=4, help="worker processes (--c3)")
+    a = ap.parse_args()
+    if a.c3:
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+        _c3(a.j)
+    else:
+        _c2()
 
 
 if __name__ == "__main__":

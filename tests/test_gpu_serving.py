@@ -160,3 +160,34 @@ def test_serving_is_deterministic(ctx):
         srv.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+
+def test_failed_lane_releases_and_refuses(ctx):
+    # lane 0 is stopped from the host after one restart cycle (the
+    # fail_after_cycles hook), as after a device error: its requests are
+    # rejected with CQM_EDEVICE, their arena regions are given back, later
+    # submits to it are refused at once, the other lane keeps serving, and
+    # drain/destroy return instead of waiting forever
+    say("serving: failed lane")
+    srv = Server(ctx, 256 << 20, max_active=4, cache_operators=0, large_lane=1,
+                 large_bytes=4 << 20, fail_after_cycles=1, mode=C.CQM_MIXED_PLAIN)
+    Vs, Ts = W.icosphere(1)   # 80 triangles, N = 8: lane 0
+    Vb, Tb = W.icosphere(2)   # 320 triangles, N = 16: above 4 MB dense, lane 1
+    rng = np.random.default_rng(11)
+    tickets = [srv.submit(Vs, Ts, 8, 2.0, W.random_direction(rng), 0.3, 1.6) for _ in range(3)]
+    res = wait_all(srv, tickets, timeout=60.0)
+    assert all(r[0] == -1 and r[1] == C.CQM_EDEVICE for r in res.values())
+    with pytest.raises(C.CqmError) as e:
+        srv.submit(Vs, Ts, 8, 2.0, (1.0, 0.0, 0.0), 0.3, 1.6)
+    assert e.value.code == C.CQM_EDEVICE
+    t = srv.submit(Vb, Tb, 16, 2.0, (0.0, 1.0, 0.0), 0.3, 1.6)
+    done, rc, q, d, lat = wait_all(srv, [t], timeout=60.0)[t]
+    assert done == 1 and rc == C.CQM_OK and np.all(np.isfinite(q))
+    with pytest.raises(C.CqmError) as e:
+        srv.drain()
+    assert e.value.code == C.CQM_EDEVICE
+    st = srv.stats()
+    assert st["rejected"] == 3 and st["completed"] == 1 and st["active"] == 0
+    assert st["arena_used"] == 0, st
+    srv.close()

@@ -98,3 +98,28 @@ def test_server_default_options_as_documented():
     assert o.solver.reuse_operator == 1
     with pytest.raises(C.CqmError):
         C._check(C.load_library().cqm_server_default_options(None))
+
+
+def test_every_declaration_names_its_passage():
+    # each function declaration (or a run of declarations with no blank line
+    # between them) is preceded by a comment naming the paper's section or
+    # equation it implements, or stating that it is plumbing with no passage
+    src = open(os.path.join(ROOT, "include", "cqm.h")).read()
+    body = src.split("extern \"C\" {", 1)[1]
+    last_comment, missing = "", []
+    for chunk in re.split(r"(/\*.*?\*/)", body, flags=re.S):
+        if chunk.startswith("/*"):
+            last_comment = chunk
+            continue
+        # a blank line ends the comment's scope
+        for k, seg in enumerate(re.split(r"\n[ \t]*\n", chunk)):
+            for name in re.findall(r"\b(?:int|const char\*)\s+(cqm_\w+)\s*\(", seg):
+                if k > 0 or not re.search(r"Section \d|Paper: no passage", last_comment):
+                    missing.append(name)
+    assert not missing, missing
+    # the computing entry points cite a section, not "no passage"
+    for name in ("cqm_frequencies", "cqm_apply_V", "cqm_near_entries", "cqm_solve",
+                 "cqm_set_plane_wave", "cqm_problem_create", "cqm_operator_stats"):
+        m = re.search(r"(/\*(?:(?!\*/).)*?\*/)\s*(?:(?:int|const char\*)\s+cqm_\w+\([^;]*;\s*)*"
+                      r"(?:int|const char\*)\s+" + name + r"\s*\(", body, flags=re.S)
+        assert m and re.search(r"Section \d", m.group(1)), name
