@@ -286,6 +286,21 @@ int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im)
 int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
                 const void* x, void* y, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): cqm_apply_V of the matrix-free
+ * plain form (CQM_FORM_MATRIX_FREE, plain modes) with no allocation.  The
+ * far product's split-K partial sums go to a fixed device array of 64 MiB
+ * inside the library (one per GPU, held until the process ends); near-field
+ * values go to the caller's workspace as in cqm_apply_V.  No hipMalloc,
+ * hipFree or allocating call is made (no autotuning: the cached tuned shape
+ * or the default one, its source split reduced to fit).  Arguments as for
+ * cqm_apply_V.  CQM_EINVAL for other forms; CQM_ENOMEM when
+ * nl x M x (8 or 16 bytes) exceeds 64 MiB, or without a workspace.  Every
+ * call on one GPU shares that array and leaves its partial sums there:
+ * calls that overlap on one GPU (other streams or threads) race. */
+int cqm_apply_V_noalloc(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
+                        const void* x, void* y, hipStream_t stream);
+
 /* Near-field (vertex-sharing) pairs and their static Duffy integrals: the
  * singular part of the Galerkin entries of Section 3.2 (kernel of
  * eq. fundsol at s = 0).  Host arrays, caller-owned; pass NULL to query

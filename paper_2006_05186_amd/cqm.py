@@ -21,7 +21,8 @@ __all__ = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
-    "cqm_frequencies", "cqm_apply_V", "cqm_near_entries", "cqm_operator_stats",
+    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_near_entries",
+    "cqm_operator_stats",
     "cqm_server_opts", "cqm_request", "cqm_server_stats_t", "cqm_server_default_options",
     "cqm_server_create", "cqm_server_submit", "cqm_server_poll", "cqm_server_drain",
     "cqm_server_stats", "cqm_server_destroy", "EXPORTED_SYMBOLS",
@@ -39,7 +40,8 @@ EXPORTED_SYMBOLS = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
-    "cqm_frequencies", "cqm_apply_V", "cqm_near_entries", "cqm_operator_stats",
+    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_near_entries",
+    "cqm_operator_stats",
     "cqm_server_default_options", "cqm_server_create", "cqm_server_submit", "cqm_server_poll",
     "cqm_server_drain", "cqm_server_stats", "cqm_server_destroy",
 ]
@@ -148,6 +150,7 @@ def load_library():
                                            ctypes.POINTER(cqm_diag), P]),
         "cqm_frequencies": (ctypes.c_int, [I32, D, D, P, P]),
         "cqm_apply_V": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
+        "cqm_apply_V_noalloc": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_near_entries": (ctypes.c_int, [P, ctypes.POINTER(I64), P, P, P]),
         "cqm_operator_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_diag)]),
         "cqm_server_default_options": (ctypes.c_int, [ctypes.POINTER(cqm_server_opts)]),
@@ -260,6 +263,12 @@ def cqm_frequencies(N, T, rho=0.0):
 def cqm_apply_V(p, l0, nl, precision, x_ptr, y_ptr, stream=0):
     return _check(load_library().cqm_apply_V(p, l0, nl, precision, ctypes.c_void_p(x_ptr),
                                              ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream)))
+
+
+def cqm_apply_V_noalloc(p, l0, nl, precision, x_ptr, y_ptr, stream=0):
+    return _check(load_library().cqm_apply_V_noalloc(p, l0, nl, precision, ctypes.c_void_p(x_ptr),
+                                                     ctypes.c_void_p(y_ptr),
+                                                     ctypes.c_void_p(stream)))
 
 
 def cqm_near_entries(p, with_static=True):

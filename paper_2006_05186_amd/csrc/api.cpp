@@ -142,6 +142,7 @@ int cqm_ctx_create(int device, cqm_ctx_t* out) {
     CQM_HIP(hipGetDeviceCount(&n));
     require(device >= 0 && device < n, CQM_EINVAL, "device index out of range");
     CQM_HIP(hipSetDevice(device));
+    far_scratch_init(device);  // device address of the fixed scratch array, once per device
     auto* c = new cqm_ctx_s();
     c->device = device;
     int cus = 0;
@@ -379,6 +380,39 @@ int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision, cons
       apply_op<float>(*p, l0, nl, (const cf32*)x, M, (cf32*)y, M, nullptr, stream);
     else
       apply_op<double>(*p, l0, nl, (const cf64*)x, M, (cf64*)y, M, nullptr, stream);
+    return CQM_OK;
+  });
+}
+
+int cqm_apply_V_noalloc(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision, const void* x,
+                        void* y, hipStream_t stream) {
+  return guarded([&] {
+    require(p && x && y, CQM_EINVAL, "NULL argument");
+    require(!mode_is_h2(p->opt.mode) && p->opt.form == CQM_FORM_MATRIX_FREE, CQM_EINVAL,
+            "the allocation-free product is for the matrix-free plain form");
+    require(l0 >= 0 && nl >= 1 && l0 + nl <= p->Fsys, CQM_EINVAL, "frequency range outside the solved band");
+    require(precision == 32 || precision == 64, CQM_EINVAL, "precision must be 32 or 64");
+    const size_t slot = (size_t)nl * p->M * (precision == 32 ? sizeof(cf32) : sizeof(cf64));
+    require(slot <= kFarScratchBytes, CQM_ENOMEM,
+            "nl x M x element size = " + std::to_string(slot) + " bytes exceeds the fixed scratch of " +
+                std::to_string(kFarScratchBytes) + " bytes");
+    require(p->ws != nullptr && p->ws_bytes >= p->lay.total, CQM_ENOMEM, "workspace missing");
+    CQM_HIP(hipSetDevice(p->ctx->device));
+    // near-field values into the caller's workspace (launches only)
+    if (!p->static_ready) {
+      launch_near_static(*p, stream);
+      p->static_ready = true;
+    }
+    cf64* nv = reinterpret_cast<cf64*>(p->ws + p->lay.near_val);
+    if (!p->near_ready) {
+      launch_near_values(*p, nv, stream);
+      p->near_ready = true;
+    }
+    const int M = (int)p->M;
+    if (precision == 32)
+      launch_far_apply_fixed<float>(*p, l0, nl, (const cf32*)x, M, (cf32*)y, M, nv, stream);
+    else
+      launch_far_apply_fixed<double>(*p, l0, nl, (const cf64*)x, M, (cf64*)y, M, nv, stream);
     return CQM_OK;
   });
 }

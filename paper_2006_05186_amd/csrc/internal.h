@@ -311,6 +311,14 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
 void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
                            unsigned long long* ctr, hipStream_t s);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
+// Allocation-free far product (matrix-free form): partial sums in the fixed
+// device array of kFarScratchBytes (k_far.hip), whose address is looked up
+// once per device by far_scratch_init (with that device current).
+constexpr size_t kFarScratchBytes = size_t(64) << 20;
+void far_scratch_init(int device);
+template <typename R>
+void launch_far_apply_fixed(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                            cplx<R>* y, int64_t ys, const cf64* near_vals, hipStream_t s);
 FarShape far_shape_of(const Problem& p, int nsys, int precision);  // shape in use (tuned or default)
 
 // dense products (k_dense.hip)

@@ -548,6 +548,63 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
   far_reduce_near_slots<R>(p, l0, nsys, partial, S, x, xs, y, ys, near_vals, active, s);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free far product.  Its split-K partial sums live in `scratch`, a
+// fixed device array of kFarScratchBytes in this code object: every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only stands for the
+// symbol); its device address is looked up once per device with
+// hipGetSymbolAddress while that device is current, and kept here.
+static __device__ __align__(256) unsigned char scratch[kFarScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+void far_scratch_init(int device) {
+  require(device >= 0 && device < kMaxScratchDevices, CQM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  int cur = -1;
+  CQM_HIP(hipGetDevice(&cur));
+  require(cur == device, CQM_EINVAL, "far_scratch_init: device is not current");
+  void* ptr = nullptr;
+  CQM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  require(ptr != nullptr, CQM_EDEVICE, "no device address for the fixed scratch array");
+  g_scratch_ptr[device] = ptr;
+}
+
+template <typename R>
+void launch_far_apply_fixed(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                            cplx<R>* y, int64_t ys, const cf64* near_vals, hipStream_t s) {
+  const int dev = p.ctx->device;
+  require(dev >= 0 && dev < kMaxScratchDevices, CQM_EINVAL, "device index out of range");
+  void* buf;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    buf = g_scratch_ptr[dev];
+  }
+  require(buf != nullptr, CQM_EDEVICE, "fixed scratch not set up on this device");
+  const int M = (int)p.M;
+  // the cached (tuned) or heuristic shape, its source split halved until the
+  // partial sums fit (one slot always fits: checked by the caller)
+  FarShape sh = far_shape_of(p, nsys, sizeof(R) == 4 ? 32 : 64);
+  const size_t slot = (size_t)nsys * M * sizeof(cplx<R>);
+  require(slot <= kFarScratchBytes, CQM_ENOMEM, "product exceeds the fixed scratch");
+  while (sh.waves > 1 && (size_t)far_splits(M, nsys, sh.ft, sh.waves) * slot > kFarScratchBytes)
+    sh.waves /= 2;
+  const int S = far_splits(M, nsys, sh.ft, sh.waves);
+  require((size_t)S * slot <= kFarScratchBytes, CQM_ENOMEM, "product exceeds the fixed scratch");
+  cplx<R>* partial = static_cast<cplx<R>*>(buf);
+  far_apply_shape<R>(p, l0, nsys, x, xs, partial, nullptr, nullptr, sh, s);
+  far_reduce_near_slots<R>(p, l0, nsys, partial, S, x, xs, y, ys, near_vals, nullptr, s);
+}
+template void launch_far_apply_fixed<float>(const Problem&, int, int, const cf32*, int64_t, cf32*,
+                                            int64_t, const cf64*, hipStream_t);
+template void launch_far_apply_fixed<double>(const Problem&, int, int, const cf64*, int64_t, cf64*,
+                                             int64_t, const cf64*, hipStream_t);
 
 template <int FT, bool kDiag = false>
 static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
