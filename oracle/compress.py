@@ -32,7 +32,7 @@ from .cqm import FOUR_PI, triangle_quadrature
 
 __all__ = ["cluster_tree", "block_tree", "cheb_nodes", "lagrange_1d", "cluster_basis",
            "transfer_matrix", "maca", "maca_norm2", "build_compressed", "compressed_matvec",
-           "dense_tensor", "compressed_dense", "solve_compressed"]
+           "dense_tensor", "block_tensor", "compressed_dense", "solve_compressed"]
 
 
 def cluster_tree(V, T, n_min):
@@ -187,14 +187,52 @@ def dense_tensor(V, T, s_list, q=5):
     return np.stack([assemble_V(V, T, s, q, pairs, static) for s in s_list], axis=-1)
 
 
+def block_tensor(V, T, ir, ic, s_list, near, q=5):
+    """Galerkin block tensor V[ir, ic, k] = V(s_k)[ir, ic] (eq. tensor) with its
+    entries formed on demand, as Algorithm 3 reads the entries of the block it
+    compresses: pairs sharing no vertex by the 6-point rule on both triangles,
+    pairs sharing a vertex by the static Duffy part plus the 6 x 6 rule of the
+    bounded remainder (Section 3.2).  `near` maps (i, j) to the static value of
+    every pair sharing a vertex."""
+    from .cqm import far_entries, near_dynamic
+    X, W, _ = triangle_quadrature(V, T)
+    ir, ic = np.asarray(ir), np.asarray(ic)
+    out = np.stack([far_entries(X[ir], W[ir], X[ic], W[ic], s) for s in s_list], axis=-1)
+    pos_c = {int(j): b for b, j in enumerate(ic)}
+    cols = set(pos_c)
+    ia, jb, gi, gj, st = [], [], [], [], []
+    for a, i in enumerate(ir):
+        for j in sorted(cols & near["by_row"][int(i)]):
+            ia.append(a)
+            jb.append(pos_c[j])
+            gi.append(int(i))
+            gj.append(j)
+            st.append(near["static"][(int(i), j)])
+    if ia:
+        gi, gj, st = np.asarray(gi), np.asarray(gj), np.asarray(st)
+        for k, s in enumerate(s_list):
+            out[ia, jb, k] = st + near_dynamic(X[gi], W[gi], X[gj], W[gj], s)
+    return out
+
+
+def _near_lookup(V, T, q=5):
+    from .cqm import near_pairs, near_static
+    pairs = near_pairs(T)
+    static = near_static(V, T, pairs, q)
+    by_row = [set() for _ in range(len(T))]
+    for i, j, _ in pairs:
+        by_row[i].add(j)
+    return dict(by_row=by_row, static={(i, j): v for (i, j, _), v in zip(pairs, static)})
+
+
 def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None):
-    """Algorithm 3: partition, bases, MACA of every block.  `dense` (M x M x F)
-    supplies the near-field entries (computed here if not given)."""
+    """Algorithm 3: partition, bases, MACA of every block.  The near-field
+    block tensors are taken from `dense` (M x M x F) when it is given, else
+    their entries are formed on demand (block_tensor), block by block."""
     clusters = cluster_tree(V, T, n_min)
     far, near = block_tree(clusters, eta)
     nodes = [cheb_nodes(c, m) for c in clusters]
-    if dense is None:
-        dense = dense_tensor(V, T, s_list)
+    lookup = _near_lookup(V, T) if dense is None else None
     s_list = np.asarray(s_list)
     blocks = []
     for (r, c) in far:
@@ -206,7 +244,8 @@ def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None):
         blocks.append(dict(kind="far", r=r, c=c, C=Cs, d=Ds, rank=info["rank"]))
     for (r, c) in near:
         ir, ic = clusters[r]["idx"], clusters[c]["idx"]
-        Cs, Ds, info = maca(dense[np.ix_(ir, ic)], eps, rcap)
+        G = dense[np.ix_(ir, ic)] if dense is not None else block_tensor(V, T, ir, ic, s_list, lookup)
+        Cs, Ds, info = maca(G, eps, rcap)
         blocks.append(dict(kind="near", r=r, c=c, C=Cs, d=Ds, rank=info["rank"]))
     U = {}
     for b in blocks:

@@ -98,9 +98,37 @@ def dunavant6():
 
 
 def gauss_legendre01(q: int):
-    """Gauss-Legendre nodes and weights mapped to [0, 1]."""
-    x, w = np.polynomial.legendre.leggauss(q)
-    return 0.5 * (x + 1.0), 0.5 * w
+    """Gauss-Legendre nodes and weights mapped to [0, 1], correctly rounded to
+    FP64: Newton's method on the Legendre polynomial P_q in 40-digit decimal
+    arithmetic (three-term recurrence; P_q'(t) = q (t P_q - P_{q-1})/(t^2 - 1)),
+    weights 2 / ((1 - t^2) P_q'(t)^2), both halved onto [0, 1].  (The FP64
+    routine of NumPy leaves weights off by up to about 1e-15 relative, which
+    the rho^-N amplification of the time-domain solution turns into 1e-8.)"""
+    from decimal import Decimal, localcontext
+    t0, _ = np.polynomial.legendre.leggauss(q)  # starting points only
+    xs, ws = [], []
+    with localcontext() as ctx:
+        ctx.prec = 40
+        one, two = Decimal(1), Decimal(2)
+        for guess in t0:
+            t = Decimal(float(guess))
+            for _ in range(100):
+                p0, p1 = one, t
+                for k in range(2, q + 1):
+                    p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+                dp = q * (t * p1 - p0) / (t * t - one)
+                step = p1 / dp
+                t -= step
+                if abs(step) < Decimal("1e-35"):
+                    break
+            p0, p1 = one, t
+            for k in range(2, q + 1):
+                p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+            dp = q * (t * p1 - p0) / (t * t - one)
+            xs.append(float((t + one) / two))
+            ws.append(float(one / ((one - t * t) * dp * dp)))
+    order = np.argsort(xs)
+    return np.asarray(xs)[order], np.asarray(ws)[order]
 
 
 def triangle_quadrature(V, T):

@@ -4,9 +4,14 @@ Calls only oracle/ and cqm_workloads/ (no GPU code).  Run from the repository
 root:
     python tests/golden/make_golden.py            # sphere1280_N64_T4
     python tests/golden/make_golden.py --c3 -j 7  # sphere5120_N128_T6
+    python tests/golden/make_golden.py --h2m4     # sphere1280_N16_T2_h2m4
 Outputs tests/golden/<workload>.npz with the density q (N+1, M) and the
 frequency-domain solutions xhat (distinct frequencies); the 1280-triangle file
 also holds the forward-transformed data ghat and the static near-field values.
+The h2m4 file holds the oracle's compressed operator (Algorithm 3: leaf size
+32, eta = 1, Chebyshev order m = 4, MACA tolerances 1e-6 and 1e-10, near
+blocks formed on demand) applied to a seeded input, with its block counts
+and ranks.
 
 The 5120-triangle file is the same all-at-once oracle solve: its frequencies
 are independent (one dense assembly and LU each), so they are spread over
@@ -77,12 +82,35 @@ def _c3(workers):
     np.savez_compressed(os.path.join(HERE, f"{wl.name}.npz"), q=q, xhat=xhat)
 
 
+def _h2m4():
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
+    V, T = W.icosphere(3)
+    N, Tend = 16, 2.0
+    s, _, _ = O.frequencies(N, Tend)
+    x = W.random_complex((len(s), len(T)), seed=31)
+    out = {"x": x}
+    for tag, eps in (("e6", 1e-6), ("e10", 1e-10)):
+        t = time.time()
+        op = O.build_compressed(V, T, s, 32, 1.0, 4, eps)
+        out[f"y_{tag}"] = O.compressed_matvec(op, x)
+        out[f"ranks_{tag}"] = np.asarray([b["rank"] for b in op["blocks"]])
+        out[f"kinds_{tag}"] = np.asarray([b["kind"] == "far" for b in op["blocks"]])
+        print(f"eps {eps}: {len(op['far'])} far / {len(op['near'])} near blocks, "
+              f"{time.time() - t:.0f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "sphere1280_N16_T2_h2m4.npz"), **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--c3", action="store_true", help="the 5120-triangle workload")
     ap.add_argument("-j", type=int, default=4, help="worker processes (--c3)")
+    ap.add_argument("--h2m4", action="store_true", help="compressed operator, m = 4")
     a = ap.parse_args()
-    if a.c3:
+    if a.h2m4:
+        _h2m4()
+    elif a.c3:
         for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
             os.environ[k] = "1"
         _c3(a.j)

@@ -141,3 +141,26 @@ def test_compressed_dense_matches_matvec(small_problem):
     y = O.compressed_matvec(op, x)
     for l in range(len(s)):
         assert np.linalg.norm(A[:, :, l] @ x[l] - y[l]) < 1e-13 * np.linalg.norm(y[l])
+
+
+def test_on_demand_near_blocks_equal_the_dense_tensor_slices():
+    # Algorithm 3 forms only the entries of the block it compresses; the
+    # oracle's on-demand block tensors equal the slices of the fully
+    # assembled tensor (to rounding: sums may be formed in another order),
+    # so both builds approximate the same tensor to the MACA tolerance
+    V, T = W.icosphere(1)
+    s, _, _ = O.frequencies(6, 2.0)
+    dense = O.dense_tensor(V, T, s)
+    a = O.build_compressed(V, T, s, 4, 1.0, 3, 1e-8, dense=dense)
+    assert len(a["near"]) > 0 and len(a["far"]) > 0
+    cl = a["clusters"]
+    lookup = O.compress._near_lookup(V, T)
+    for (r, c) in a["near"]:
+        ir, ic = cl[r]["idx"], cl[c]["idx"]
+        G = O.block_tensor(V, T, ir, ic, s, lookup)
+        ref = dense[np.ix_(ir, ic)]
+        assert np.max(np.abs(G - ref)) <= 1e-14 * np.max(np.abs(ref))
+    b = O.build_compressed(V, T, s, 4, 1.0, 3, 1e-8)
+    x = W.random_complex((len(s), len(T)), seed=4)
+    ya, yb = O.compressed_matvec(a, x), O.compressed_matvec(b, x)
+    assert np.linalg.norm(ya - yb) <= 1e-7 * np.linalg.norm(ya)

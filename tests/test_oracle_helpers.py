@@ -139,3 +139,22 @@ def test_compressed_solve_converges_to_the_plain_solve():
         errs.append(O.rel_error(qc, q, area))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-4
+
+
+def test_gauss_legendre_five_points_match_the_closed_form_to_rounding():
+    # the five-point Gauss-Legendre rule has the closed form
+    #   t = 0, +-(1/3) sqrt(5 -+ 2 sqrt(10/7)),  w = 128/225, (322 +- 13 sqrt 70)/900
+    # on [-1, 1]; the oracle's nodes and weights on [0, 1] must be these values
+    # correctly rounded (a 1e-15 weight error becomes 1e-8 in the time domain)
+    from decimal import Decimal as Dc, localcontext
+    x, w = O.gauss_legendre01(5)
+    with localcontext() as ctx:
+        ctx.prec = 40
+        s70, s107 = Dc(70).sqrt(), (Dc(10) / Dc(7)).sqrt()
+        t = [-(5 + 2 * s107).sqrt() / 3, -(5 - 2 * s107).sqrt() / 3, Dc(0),
+             (5 - 2 * s107).sqrt() / 3, (5 + 2 * s107).sqrt() / 3]
+        wt = [(322 - 13 * s70) / 900, (322 + 13 * s70) / 900, Dc(128) / 225,
+              (322 + 13 * s70) / 900, (322 - 13 * s70) / 900]
+        for k in range(5):
+            assert x[k] == float((t[k] + 1) / 2)
+            assert abs(Dc(w[k]) - wt[k] / 2) <= Dc(2) ** -53 * (wt[k] / 2)
