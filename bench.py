@@ -7,8 +7,10 @@ all frequency systems, right-hand side, forward scaled DFT, batched GMRES with
 FP64 refinement, inverse scaled DFT -- everything from the mesh to the
 time-domain density, with inputs already resident on the device.
 
-Prints ONE JSON line.  Default workload: unit-sphere icosphere with 1280
-triangles, N = 64 steps on T = 4 (33 frequency systems), Gaussian plane wave.
+Prints ONE JSON line.  Default workload: unit-sphere icosphere with 5120
+triangles, N = 128 steps on T = 6 (65 distinct frequency systems), Gaussian
+plane wave, solved in the mixed stored form; its error is measured against
+the stored oracle solution of the same workload.
 """
 import argparse
 import json
@@ -24,7 +26,11 @@ import numpy as np  # noqa: E402
 
 import cqm_workloads as W  # noqa: E402
 
+# MI355X published peaks: FP32 vector 157.3 TFLOP/s (packed FMA; 78.6 without
+# packed instructions, which this build does not emit), FP64 vector 78.6,
+# HBM3E 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # Algorithmic flops of one point-pair-frequency kernel value
@@ -32,20 +38,26 @@ PEAK_HBM_GBS = 8000.0
 # evaluations (exp, sin, cos; one flop each), three multiplies (sigma r,
 # omega r, weight) and two fused multiply-adds (4 flops).
 FLOPS_PER_UNIT = 10
-# Kernel-value ceilings from the chip's unit counts: 256 CUs x 64 lanes x
-# 2.4 GHz = 3.93e13 lane-cycles/s, divided by the lane-cycles one kernel
-# value costs.  FP32: 3 transcendentals at quarter rate plus ~6 full-rate
-# ops = ~18 lane-cycles.  FP64 (no hardware transcendentals; FP64 FMA is
-# full rate): VALU instructions per value counted in the ISA of the inner
-# loop, 32 for the dense assembly (table-driven exp and sincos on arguments
-# pre-scaled to table steps, index arithmetic, accumulation; 356 per 11
-# frequencies) and 36 for the FP64 matrix-free apply (the same math, which
-# also multiplies by x and accumulates per target; 328 per 9 frequencies).
-# Expressed in TFLOP/s with the 10-flop convention above.
+# Instruction-count ceilings (reported beside the vendor-peak fraction, not
+# as the roofline's peak): 256 CUs x 64 lanes x 2.4 GHz = 3.93e13
+# lane-cycles/s, divided by the lane-cycles one kernel value costs.  FP32:
+# 3 transcendentals (v_exp_f32, v_sin_f32, v_cos_f32) plus ~6 full-rate ops;
+# the transcendentals measure half the FP32 FMA rate on gfx950
+# (profiles/alu_rates_gfx950.txt: 29.5 vs 58.1 lane-ops per CU per cycle),
+# so 3 x 2.18 + 6 x 1.10 = 13.2 lane-cycles.  FP64 (no hardware
+# transcendentals): VALU instructions per value counted in the ISA of the
+# inner loop, 32 for the dense assembly (table-driven exp and sincos on
+# arguments pre-scaled to table steps, index arithmetic, accumulation; 356
+# per 11 frequencies) and 36 for the FP64 matrix-free apply (the same math,
+# which also multiplies by x and accumulates per target; 328 per 9
+# frequencies).  Expressed in TFLOP/s with the 10-flop convention above.
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
-ALU_PEAK_TFLOPS = {"far32": LANE_CYCLES_PER_S / 18 * FLOPS_PER_UNIT / 1e12,
+ALU_PEAK_TFLOPS = {"far32": LANE_CYCLES_PER_S / 13.2 * FLOPS_PER_UNIT / 1e12,
                    "far64": LANE_CYCLES_PER_S / 36 * FLOPS_PER_UNIT / 1e12,
                    "assemble": LANE_CYCLES_PER_S / 32 * FLOPS_PER_UNIT / 1e12}
+
+VENDOR_PEAK_TFLOPS = {"far32": PEAK_FP32_TFLOPS, "far64": PEAK_FP64_TFLOPS,
+                      "assemble": PEAK_FP64_TFLOPS}
 
 WORKLOADS = {"C1": W.C1, "C2": W.C2, "C3": W.C3}
 KCLS = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
@@ -94,7 +106,7 @@ def summarise_kernels(diags):
     return ms, calls
 
 
-def roofline(diags):
+def roofline(diags, tag):
     """Dominant kernel class over the timed steps and where it stands against
     its roofline.  Durations are the HIP-event times of every launch in the
     timed steps (recorded on the solve stream); the algorithmic work is what
@@ -114,27 +126,28 @@ def roofline(diags):
            "work_per_launch": work[k] / n}
     if name in ("far32", "far64", "assemble"):
         ach = work[k] / n * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
-        peak = ALU_PEAK_TFLOPS[name]
-        vendor = PEAK_FP32_TFLOPS if name == "far32" else PEAK_FP64_TFLOPS
+        peak = VENDOR_PEAK_TFLOPS[name]
+        isa = ALU_PEAK_TFLOPS[name]
         return out | {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                      "frac": ach / peak, "traffic": traffic_per_launch(name),
+                      "frac": ach / peak, "traffic": traffic_per_launch(name, tag),
                       "work_unit": "kernel values", "flops_per_unit": FLOPS_PER_UNIT,
-                      "frac_of_vendor_peak": ach / vendor}
+                      "isa_count_ceiling_tflops": isa, "frac_of_isa_count_ceiling": ach / isa}
     if name in ("gemv32", "gemv64", "arnoldi"):
         ach = work[k] / n / (avg_ms * 1e-3) / 1e9
         return out | {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                      "frac": ach / PEAK_HBM_GBS, "traffic": traffic_per_launch(name),
+                      "frac": ach / PEAK_HBM_GBS, "traffic": traffic_per_launch(name, tag),
                       "work_unit": "bytes"}
     return out | {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                   "frac": None, "traffic": None}
 
 
-def traffic_per_launch(cls):
+def traffic_per_launch(cls, tag):
     """HBM bytes per launch of the class's kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
-    or None when the summary is missing or the kernel source changed since."""
+    summary profiles/traffic_<cls>_<tag>.txt (FETCH_SIZE + WRITE_SIZE, scaled
+    by the plain-copy calibration), or None when the summary is missing or the
+    kernel source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{cls}_sphere1280_N64.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{cls}_{tag}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -151,52 +164,85 @@ def traffic_per_launch(cls):
         return None
 
 
-def cpu_baseline(wl, sample_freqs=2):
-    """The oracle on the host: near field, right-hand side, both DFTs, and the
-    dense assembly + LU of `sample_freqs` of the frequency systems; the
-    per-frequency part is scaled to all systems of one solve."""
+def golden_q(wl):
+    path = os.path.join(ROOT, "tests", "golden", f"{wl.name}.npz")
+    return np.load(path)["q"] if os.path.exists(path) else None
+
+
+def errors(q, ref, area):
+    """Area-weighted relative error over all steps and the largest per-step one."""
+    num = np.sqrt(np.sum(area[None, :] * (q - ref) ** 2, axis=1))
+    den = np.sqrt(np.sum(area[None, :] * ref ** 2, axis=1))
+    return rel_err(q, ref, area), float(np.max(num / np.maximum(den, 1e-300)))
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d["num_threads"] for d in threadpool_info() if d.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(wl, sample_rows=128):
+    """The oracle on the host, timed on a bounded sample of one solve of `wl`:
+    the frequency-independent parts run whole (right-hand side, forward
+    transform, near-field pairs and static integrals, inverse transform); of
+    the per-frequency part (dense assembly of V(s_l), LU, solve) the assembly
+    of `sample_rows` rows of V(s_0) is timed and scaled to all rows, and one
+    LU factorisation + solve of an M x M complex matrix is timed (its cost
+    does not depend on the values); the two are scaled to all distinct
+    frequencies."""
     import scipy.linalg as sla
 
     import oracle as O
     V, T = wl.mesh()
+    M = len(T)
     F = wl.N + 1
     H = O.num_frequencies_half(F)
+    w = wl.wave
     t0 = time.perf_counter()
     s, rho, dt = O.frequencies(wl.N, wl.T)
-    b = O.rhs(V, T, wl.N, wl.T)
+    b = O.rhs(V, T, wl.N, wl.T, w.direction, w.sigma, w.t0, w.amplitude)
     ghat = O.forward_dft(b, rho, H)
     pairs = O.near_pairs(T)
     static = O.near_static(V, T, pairs, 5)
+    O.inverse_dft(np.zeros((H, M), dtype=complex), rho, F)
     t_fixed = time.perf_counter() - t0
+    rows = np.linspace(0, M - 1, min(sample_rows, M)).astype(int)
     t1 = time.perf_counter()
-    xh = np.zeros((H, len(T)), dtype=complex)
-    for l in range(sample_freqs):
-        A = O.assemble_V(V, T, s[l], pairs=pairs, static=static)
-        xh[l] = sla.lu_solve(sla.lu_factor(A), ghat[l])
-    t_freq = (time.perf_counter() - t1) / sample_freqs
+    A_rows = O.assemble_V(V, T, s[0], pairs=pairs, static=static, rows=rows)
+    t_asm = (time.perf_counter() - t1) * M / len(rows)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M)) + M * np.eye(M)
+    A[rows] = A_rows
     t2 = time.perf_counter()
-    O.inverse_dft(xh, rho, F)
-    t_fixed += time.perf_counter() - t2
-    t_solve = t_fixed + H * t_freq
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_freqs} of {H} frequency systems (dense assembly + LU) plus the "
-                      f"near field, right-hand side and both DFTs; per-frequency time scaled "
-                      f"x{H}", "seconds_per_solve": t_solve}
+    sla.lu_solve(sla.lu_factor(A, overwrite_a=True), ghat[0])
+    t_lu = time.perf_counter() - t2
+    t_solve = t_fixed + H * (t_asm + t_lu)
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": f"{wl.name}: right-hand side, forward/inverse transforms and the near field "
+                      f"whole ({t_fixed:.1f} s); assembly of {len(rows)} of {M} rows of V(s_0) "
+                      f"scaled x{M / len(rows):.0f} ({t_asm:.1f} s per frequency) and one "
+                      f"{M} x {M} complex LU + solve ({t_lu:.1f} s), both scaled to the {H} "
+                      f"distinct frequencies; elementwise assembly single-threaded, LU on the "
+                      f"BLAS threads", "seconds_per_solve": t_solve}
 
 
-def run_compressed(C, torch, ctx):
+def run_compressed(C, torch, ctx, only=None):
     """The paper's compressed form (H2 in space x MACA across frequencies,
     cluster leaves 32, eta 1, Chebyshev m = 4, eps 1e-6, full band) on the
-    5120-triangle sphere, N = 128, T = 6, against the stored dense form (FP64
-    refined to 1e-15, itself within 1e-8 of the oracle at the sizes the oracle
-    reaches) and the matrix-free plain form."""
+    5120-triangle sphere, N = 128, T = 6, against the stored oracle solution
+    of the same workload, beside the stored dense and matrix-free plain forms."""
     from paper_2006_05186_amd.solver import Problem
     wl = W.C3
     V, T = wl.mesh()
     area = area_of(V, T)
+    ref = golden_q(wl)
     res = {}
-    ref = None
     # eta = 0.125: at this size no block is admissible, so every block is
     # compressed across frequencies only (MACA) and the time-domain error is
     # set by eps instead of the m = 4 spatial interpolation
@@ -204,6 +250,8 @@ def run_compressed(C, torch, ctx):
                                   ("compressed_mixed", C.CQM_MIXED_H2ACA, C.CQM_FORM_DENSE, None),
                                   ("compressed_mixed_eta0.125", C.CQM_MIXED_H2ACA, C.CQM_FORM_DENSE, 0.125),
                                   ("matrix_free_mixed", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE, None)):
+        if only and name not in only:
+            continue
         kw = {} if eta is None else {"eta": eta}
         p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, form=form, **kw)
         p.set_plane_wave()
@@ -219,27 +267,25 @@ def run_compressed(C, torch, ctx):
         if mode == C.CQM_MIXED_H2ACA:
             r |= {"max_rank": d.max_rank, "mean_rank": d.mean_rank, "far_blocks": d.n_far_blocks,
                   "near_blocks": d.n_near_blocks}
-        if ref is None:
-            ref = qn
-        else:
-            r["error_vs_dense"] = rel_err(qn, ref, area)
-            num = np.sqrt(np.sum(area[None, :] * (qn - ref) ** 2, axis=1))
-            den = np.sqrt(np.sum(area[None, :] * ref ** 2, axis=1))
-            r["max_step_error_vs_dense"] = float(np.max(num / np.maximum(den, 1e-300)))
+        if ref is not None:
+            r["error_vs_oracle"], r["max_step_error_vs_oracle"] = errors(qn, ref, area)
         res[name] = r
         p.close()
-    res["compressed_speedup_vs_dense"] = (res["dense_mixed"]["seconds_per_solve"] /
-                                          res["compressed_mixed"]["seconds_per_solve"])
-    res["compressed_speedup_vs_matrix_free"] = (res["matrix_free_mixed"]["seconds_per_solve"] /
-                                                res["compressed_mixed"]["seconds_per_solve"])
+    if only is None:
+        res["compressed_speedup_vs_dense"] = (res["dense_mixed"]["seconds_per_solve"] /
+                                              res["compressed_mixed"]["seconds_per_solve"])
+        res["compressed_speedup_vs_matrix_free"] = (res["matrix_free_mixed"]["seconds_per_solve"] /
+                                                    res["compressed_mixed"]["seconds_per_solve"])
     return {"workload": wl.name} | res
 
 
-def run_batch48(C, torch, ctx):
+def run_batch48(C, torch, ctx, sample=4):
     """Uneven batch: 48 seeded problems (spheres/ellipsoids of 80..5120
     triangles, N in {16,32,64,128}, random direction and pulse width) solved
     by one cqm_solve_batch call; dense stored operators up to 1280 triangles,
-    matrix-free products for 5120."""
+    matrix-free products for 5120.  The first `sample` problems of at most
+    320 triangles are compared with the oracle."""
+    import oracle as O
     from paper_2006_05186_amd.solver import Problem, solve_batch
     mix = W.problem_mix(48)
     probs = []
@@ -256,92 +302,84 @@ def run_batch48(C, torch, ctx):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     iters = sum(d.total_iters for _, d in res)
+    checked = []
+    for k, w in enumerate(mix):
+        if len(checked) >= sample:
+            break
+        if w.M > 320:
+            continue
+        V, T = w.mesh()
+        ref = O.solve(V, T, w.N, w.T, direction=w.wave.direction, sigma=w.wave.sigma,
+                      t0=w.wave.t0, amplitude=w.wave.amplitude)
+        e, emax = errors(res[k][0].cpu().numpy(), ref, area_of(V, T))
+        checked.append({"problem": w.name, "error_vs_oracle": e, "max_step_error_vs_oracle": emax})
     for p in probs:
         p.close()
     return {"problems": len(mix), "makespan_s": el, "solves_per_s": len(mix) / el, "rc": rc,
             "triangles": sorted({w.M for w in mix}), "steps": sorted({w.N for w in mix}),
-            "total_arnoldi_steps": iters}
+            "total_arnoldi_steps": iters, "sampled_errors": checked,
+            "max_sampled_error_vs_oracle": max(c["error_vs_oracle"] for c in checked)}
 
 
-def run_serving(C, torch, ctx, rate, duration):
-    """Poisson stream of solve requests on the 5120-triangle sphere (N = 128,
-    T = 6, random direction and pulse per request) served by the continuous-
-    batching loop with the operator cache (dense mixed form)."""
-    from paper_2006_05186_amd.solver import Server
-    wl = W.C3
-    V, T = wl.mesh()
-    arrivals = W.poisson_arrivals(rate, duration)
-    rng = np.random.default_rng(W.DEFAULT_SEED + 1)
-    srv = Server(ctx, 96 << 30, max_active=16, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
-    # the first request builds the cached operator; it is timed like the rest
-    tickets = []
-    t0 = time.perf_counter()
-    for a in arrivals:
-        now = time.perf_counter() - t0
-        if a > now:
-            time.sleep(a - now)
-        sigma = float(rng.uniform(0.2, 0.4))
-        tickets.append(srv.submit(V, T, wl.N, wl.T, W.random_direction(rng), sigma, 1.0 + 2 * sigma))
-    lat, rcs = {}, []
-    while len(lat) < len(tickets):
-        for t in tickets:
-            if t not in lat:
-                done, rc, _, d, l = srv.poll(t)
-                if done:
-                    lat[t] = l
-                    rcs.append(rc)
-        time.sleep(0.001)
-    el = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    L = np.asarray(list(lat.values()))
-    return {"workload": wl.name, "rate_per_s": rate, "duration_s": duration, "requests": len(tickets),
-            "solves_per_s": len(tickets) / el, "p50_ms": float(np.percentile(L, 50)),
-            "p99_ms": float(np.percentile(L, 99)), "max_ms": float(L.max()),
-            "all_ok": all(r == C.CQM_OK for r in rcs), "peak_active": st["peak_active"],
-            "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"]}
-
-
-def run_serving_mix(C, torch, ctx, rate, duration, large_frac=0.2):
-    """Poisson stream mixing sphere5120_N128_T6 requests with a fraction of
-    sphere20480_N256_T6 ones.  The large lane is on: requests whose stored
-    dense operator would exceed a quarter of the budget (the 20480-triangle
-    ones) are solved in the compressed form on a second stream; the others in
-    the dense mixed form.  Operators cached; latency per class."""
+def run_serving(C, torch, ctx, rate, duration, large_frac=0.2, check_every=8):
+    """Poisson stream of solve requests (seeded): sphere5120_N128_T6 requests
+    and, with probability `large_frac`, sphere20480_N256_T6 ones, each with a
+    random direction and pulse width, served by the continuous-batching loop
+    with the operator cache; the large lane (second stream) solves requests
+    whose stored dense operator would exceed a quarter of the budget -- the
+    20480-triangle ones -- in the compressed form.  Every `check_every`-th
+    5120-triangle request carries the stored oracle workload's pulse and is
+    compared with the oracle's solution."""
     from paper_2006_05186_amd.solver import Server
     small, large = W.C3, W.C5_LARGE
     meshes = {small.name: small.mesh(), large.name: large.mesh()}
+    ref = golden_q(small)
+    area = area_of(*meshes[small.name])
     arrivals = W.poisson_arrivals(rate, duration)
     rng = np.random.default_rng(W.DEFAULT_SEED + 2)
     kinds = [large if rng.uniform() < large_frac else small for _ in arrivals]
     srv = Server(ctx, 200 << 30, max_active=16, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
-                 large_lane=1)
+                 large_lane=int(large_frac > 0))
     tickets = []
+    nsmall = 0
     t0 = time.perf_counter()
     for a, wl in zip(arrivals, kinds):
         now = time.perf_counter() - t0
         if a > now:
             time.sleep(a - now)
         V, T = meshes[wl.name]
-        sigma = float(rng.uniform(0.2, 0.4))
-        tickets.append((srv.submit(V, T, wl.N, wl.T, W.random_direction(rng), sigma, 1.0 + 2 * sigma),
-                        wl.name))
-    lat, rcs = {}, []
+        checked = False
+        if wl is small:
+            checked = ref is not None and nsmall % check_every == 0
+            nsmall += 1
+        if checked:
+            w = small.wave
+            d, sigma, t0w = w.direction, w.sigma, w.t0
+        else:
+            d = W.random_direction(rng)
+            sigma = float(rng.uniform(0.2, 0.4))
+            t0w = 1.0 + 2 * sigma
+        tickets.append((srv.submit(V, T, wl.N, wl.T, d, sigma, t0w), wl.name, checked))
+    lat, rcs, errs = {}, [], []
     while len(lat) < len(tickets):
-        for t, name in tickets:
+        for t, name, checked in tickets:
             if t not in lat:
-                done, rc, _, d, l = srv.poll(t)
+                done, rc, q, dg, l = srv.poll(t)
                 if done:
                     lat[t] = (l, name)
                     rcs.append(rc)
-        time.sleep(0.005)
+                    if checked and done == 1:
+                        errs.append(errors(q, ref, area)[0])
+        time.sleep(0.002)
     el = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
     out = {"rate_per_s": rate, "duration_s": duration, "requests": len(tickets),
            "large_fraction": large_frac, "makespan_s": el, "solves_per_s": len(tickets) / el,
            "all_ok": all(r == C.CQM_OK for r in rcs), "lane_completed": st["lane_completed"],
-           "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"]}
+           "operators_built": st["operators_built"], "cache_hits": st["operator_cache_hits"],
+           "peak_active": st["peak_active"], "checked_requests": len(errs),
+           "max_error_vs_oracle_checked": max(errs) if errs else None}
     for name in (small.name, large.name):
         L = np.asarray([l for l, n in lat.values() if n == name])
         if len(L):
@@ -352,19 +390,159 @@ def run_serving_mix(C, torch, ctx, rate, duration, large_frac=0.2):
     return out
 
 
+def tag_of(wl):
+    return f"sphere{wl.M}_N{wl.N}"
+
+
+def far32_probe(C, torch, ctx, wl):
+    """Kernel evaluation rate of the matrix-free FP32 far product (all
+    distinct frequency systems active): one cqm_apply_V, timed by events."""
+    from paper_2006_05186_amd.solver import Problem
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE)
+    H = wl.N // 2 + 1
+    x = torch.as_tensor(W.random_complex((H, len(T)), seed=3), device="cuda").to(torch.complex64)
+    for _ in range(2):
+        p.apply(x, 0, 32)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(st)
+    for _ in range(reps):
+        p.apply(x, 0, 32)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_apply = e0.elapsed_time(e1) / reps * 1e-3
+    u = C.cqm_operator_stats(p.handle).far_units
+    p.close()
+    tf = u * FLOPS_PER_UNIT / t_apply / 1e12
+    return {"workload": wl.name, "ms": t_apply * 1e3, "units_per_s": u / t_apply,
+            "entries_per_s": u / 36 / t_apply, "tflops": tf,
+            "frac_fp32_peak": tf / PEAK_FP32_TFLOPS,
+            "frac_fp32_unpacked_peak": tf / PEAK_FP32_UNPACKED_TFLOPS,
+            "frac_of_measured_issue_ceiling": tf / ALU_PEAK_TFLOPS["far32"]}
+
+
+def run_marching(C, torch, ctx, wl, steps=3):
+    """The paper's time-marching solve (weights of eq. dft from the stored
+    FP64 operator, history sums, conjugate gradients on What_0) of `wl`,
+    against the stored all-at-once oracle solution (they agree to order
+    rho^(N+1))."""
+    from paper_2006_05186_amd.solver import Problem
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_FP64_PLAIN, marching=1)
+    p.set_plane_wave()
+    p.solve_marching()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        q, rc, d = p.solve_marching()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    out = {"workload": wl.name, "seconds_per_solve": el, "rc": rc, "cg_iterations": d.total_iters,
+           "max_cg_per_step": d.max_iters, "t_setup_ms": d.t_setup_ms, "t_steps_ms": d.t_solve_ms,
+           "weights_GB": d.operator_bytes / 1e9}
+    ref = golden_q(wl)
+    if ref is not None:
+        out["error_vs_oracle_all_at_once"], out["max_step_error"] = errors(
+            q.cpu().numpy(), ref, area_of(V, T))
+    p.close()
+    return out
+
+
+def tensor_error(C, torch, ctx, V, T, N, Tend, n_min, eta, m, eps):
+    """Section 7.1's relative error e = ||V - V~||_F / ||V||_F of the
+    compressed tensor over all (i, j, k), k = 0..N, formed exactly from the
+    products of both operators with every unit vector (FP64; the plain
+    operator without cut-off, its conjugate frequencies by reflection), with
+    the compressed operator's ranks and storage.  Returns a dict."""
+    from paper_2006_05186_amd.solver import Problem
+    M, F = len(T), N + 1
+    H = F // 2 + 1
+    pd = Problem(ctx, V, T, N, Tend, mode=C.CQM_FP64_PLAIN, form=C.CQM_FORM_DENSE,
+                 cutoff_inner=0.0, cutoff_outer=0.0)
+    pc = Problem(ctx, V, T, N, Tend, mode=C.CQM_FP64_H2ACA, n_min=n_min, eta=eta, cheb_m=m,
+                 eps_aca=eps)
+    x = torch.zeros((F, M), dtype=torch.complex128, device="cuda")
+    num = torch.zeros((), dtype=torch.float64, device="cuda")
+    den = torch.zeros((), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    for j in range(M):
+        x[:, j] = 1.0
+        yh = pd.apply(x[:H], 0, 64)
+        yd = torch.cat([yh, torch.conj(torch.flip(yh[1:F - H + 1], [0]))])
+        yc = pc.apply(x, 0, 64)
+        num += torch.sum(torch.abs(yc - yd) ** 2)
+        den += torch.sum(torch.abs(yd) ** 2)
+        x[:, j] = 0.0
+    torch.cuda.synchronize()
+    st = C.cqm_operator_stats(pc.handle)
+    out = {"m": m, "eps": eps, "eta": eta, "e": float(torch.sqrt(num / den)),
+           "max_rank": st.max_rank, "mean_rank": st.mean_rank, "far_blocks": st.n_far_blocks,
+           "near_blocks": st.n_near_blocks, "bytes": st.operator_bytes,
+           "storage_vs_dense": st.operator_bytes / (16.0 * M * M * F),
+           "storage_vs_plain_h2": st.operator_bytes / max(st.h2_plain_bytes, 1),
+           "seconds": time.perf_counter() - t0}
+    pd.close()
+    pc.close()
+    return out
+
+
+def run_study(C, torch, ctx):
+    """The tensor-approximation study of Section 7.1 at reduced size: the
+    unit-sphere polyhedron with 1280 triangles, N = 64 steps with
+    dt / h = 0.83 (T = 8, the paper's Courant number), leaf size 32, the
+    paper's eta = 2 and the configured eta = 1; e, ranks and storage against
+    eps for m = 2, 3, 4, and along eps = 10^-m."""
+    V, T = W.icosphere(3)
+    N, Tend = 64, 8.0
+    rows = []
+    for eta in (2.0, 1.0):
+        for m in (2, 3, 4):
+            for k in range(2, 9):
+                rows.append(tensor_error(C, torch, ctx, V, T, N, Tend, 32, eta, m, 10.0 ** -k))
+                print(f"study eta={eta} m={m} eps=1e-{k}: e={rows[-1]['e']:.3e}", file=sys.stderr,
+                      flush=True)
+    return {"mesh_triangles": len(T), "N": N, "T": Tend, "n_min": 32, "rows": rows}
+
+
+def alu_probe(blocks=256 * 16, iters=4096):
+    """Lane-op rates of single VALU instructions (probes/alu_rate.hip), as
+    operations per second and per compute unit per cycle (256 CUs, 2.4 GHz)."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2006_05186_amd", "lib", "libcqm_probe.so"))
+    rates = (ctypes.c_double * 6)()
+    rc = L.cqm_probe_alu_rates(0, blocks, iters, rates)
+    if rc != 0:
+        raise RuntimeError("ALU probe failed")
+    names = ["v_exp_f32", "v_sin_f32", "v_cos_f32", "v_rsq_f32", "v_fma_f32", "v_fma_f64"]
+    out = {"blocks": blocks, "threads": 256, "iters": iters, "chains": 8}
+    for n, r in zip(names, rates):
+        out[n] = {"lane_ops_per_s": r, "lane_ops_per_cu_cycle": r / (256 * 2.4e9)}
+    return {"alu_probe": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=10.0)
-    ap.add_argument("--serve-seconds", type=float, default=6.0)
-    ap.add_argument("--serve-mix", type=float, default=0.0, metavar="RATE",
-                    help="only run the mixed serving stream (5120- and 20% 20480-triangle "
-                         "requests) at RATE requests/s for --serve-seconds and exit")
+    ap.add_argument("--serve-rate", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-large", type=float, default=0.2,
+                    help="fraction of 20480-triangle requests in the serving stream")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving stream and print its record")
+    ap.add_argument("--alu-probe", action="store_true",
+                    help="only measure the lane-op rates of v_exp_f32, v_sin_f32, v_cos_f32, "
+                         "v_rsq_f32 and FP32/FP64 FMA (lib/libcqm_probe.so) and exit")
+    ap.add_argument("--part", choices=["far32", "compressed", "marching", "study"],
+                    help="only run one piece on the workload (for counter profiles) and print "
+                         "its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -389,12 +567,27 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
         return
+    if args.alu_probe:
+        print(json.dumps(alu_probe()), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     ctx = C.cqm_ctx_create(0)
-    if args.serve_mix > 0:
-        mix = run_serving_mix(C, torch, ctx, args.serve_mix, args.serve_seconds)
+    if args.part:
+        if args.part == "far32":
+            rec = far32_probe(C, torch, ctx, wl)
+        elif args.part == "study":
+            rec = run_study(C, torch, ctx)
+        elif args.part == "compressed":
+            rec = run_compressed(C, torch, ctx, only=("compressed_mixed",))
+        else:
+            rec = run_marching(C, torch, ctx, wl)
         C.cqm_ctx_destroy(ctx)
-        print(json.dumps({"serving_mix": mix}), flush=True)
+        print(json.dumps({args.part: rec}), flush=True)
+        return
+    if args.serve_only:
+        rec = run_serving(C, torch, ctx, args.serve_rate, args.serve_seconds, args.serve_large)
+        C.cqm_ctx_destroy(ctx)
+        print(json.dumps({"serving": rec}), flush=True)
         return
     main_mode, main_form = C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE
     r = run_variant(C, Problem, ctx, wl, main_mode, main_form, args.steps, args.warmup, torch)
@@ -402,13 +595,14 @@ def main():
     value = K / r["elapsed"]
     lat_ms = np.asarray(r["lat"]) * 1e3
     d0 = r["diags"][-1]
+    area = area_of(r["V"], r["T"])
     # Kernel durations come from HIP events recorded around every launch on
-    # the solve stream; the event records cost about a tenth of a step, so
-    # they run in a second pass of the same workload right after the timed
-    # steps rather than inside them.
+    # the solve stream; the event records cost part of a step, so they run
+    # in a second pass of the same workload right after the timed steps
+    # rather than inside them.
     KP = min(K, 10)
     rp = run_variant(C, Problem, ctx, wl, main_mode, main_form, KP, 1, torch, profile=1)
-    rl = roofline(rp["diags"])
+    rl = roofline(rp["diags"], tag_of(wl))
     out = {
         "metric": "time-domain CQM-BEM solves/s + p50/p99 latency; kernel entries/s vs VALU peak",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -430,55 +624,48 @@ def main():
                    "workspace_GB": r["workspace"] / 1e9},
         "kernel_ms_per_step": dict(zip(KCLS, (summarise_kernels(rp["diags"])[0] / KP).round(4).tolist())),
     }
-    golden = os.path.join(ROOT, "tests", "golden", f"{wl.name}.npz")
-    if os.path.exists(golden):
-        ref = np.load(golden)["q"]
-        out["error_vs_oracle"] = rel_err(r["q"], ref, area_of(r["V"], r["T"]))
+    ref = golden_q(wl)
+    if ref is not None:
+        out["error_vs_oracle"], out["max_step_error_vs_oracle"] = errors(r["q"], ref, area)
+    print(f"headline {wl.name}: {value:.2f} solves/s", file=sys.stderr, flush=True)
     if not args.no_variants:
         var = {}
-        for name, mode, form, steps in (("fp64_dense", C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE, 10),
-                                        ("mixed_matrix_free", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE, 5),
-                                        ("fp64_matrix_free", C.CQM_FP64_PLAIN, C.CQM_FORM_MATRIX_FREE, 3)):
+        for name, mode, form, steps in (("fp64_dense", C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE, 5),
+                                        ("mixed_matrix_free", C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE, 2),
+                                        ("fp64_matrix_free", C.CQM_FP64_PLAIN, C.CQM_FORM_MATRIX_FREE, 1)):
             rv = run_variant(C, Problem, ctx, wl, mode, form, steps, 1, torch, profile=1)
             ms, calls = summarise_kernels(rv["diags"])
             v = {"solves_per_s": steps / rv["elapsed"]}
-            for kn in ("far32", "far64"):
+            for kn in ("far32", "far64", "assemble"):
                 k = KCLS.index(kn)
                 if calls[k]:
                     v[f"{kn}_avg_ms"] = ms[k] / calls[k]
-            if os.path.exists(golden):
-                v["error_vs_oracle"] = rel_err(rv["q"], ref, area_of(rv["V"], rv["T"]))
+            if ref is not None:
+                v["error_vs_oracle"], v["max_step_error_vs_oracle"] = errors(rv["q"], ref, area)
             var[name] = v
-        # kernel evaluation rate of the matrix-free FP32 far product (all
-        # frequency systems active): one cqm_apply_V probe, timed by events
-        V, T = wl.mesh()
-        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE)
-        H = wl.N // 2 + 1
-        x = torch.as_tensor(W.random_complex((H, len(T)), seed=3), device="cuda").to(torch.complex64)
-        for _ in range(2):
-            p.apply(x, 0, 32)
-        torch.cuda.synchronize()
-        st = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 10
-        e0.record(st)
-        for _ in range(reps):
-            p.apply(x, 0, 32)
-        e1.record(st)
-        torch.cuda.synchronize()
-        t_apply = e0.elapsed_time(e1) / reps * 1e-3
-        u = C.cqm_operator_stats(p.handle).far_units
-        var["far32_apply_probe"] = {"ms": t_apply * 1e3, "units_per_s": u / t_apply,
-                                    "entries_per_s": u / 36 / t_apply,
-                                    "tflops": u * FLOPS_PER_UNIT / t_apply / 1e12,
-                                    "frac_fp32_peak": u * FLOPS_PER_UNIT / t_apply / 1e12 / PEAK_FP32_TFLOPS,
-                                    "frac_transcendental_ceiling": u / t_apply / (LANE_CYCLES_PER_S / 18)}
-        p.close()
+            print(f"variant {name} done", file=sys.stderr, flush=True)
+        var["far32_apply_probe"] = far32_probe(C, torch, ctx, wl)
         out["variants"] = var
-    if not args.no_variants:
+        # the smaller plain configuration (1280 triangles, N = 64) as a sub-record
+        c2 = W.C2
+        r2 = run_variant(C, Problem, ctx, c2, main_mode, main_form, 30, 3, torch)
+        rec2 = {"workload": c2.name, "solves_per_s": 30 / r2["elapsed"],
+                "p50_ms": float(np.percentile(np.asarray(r2["lat"]) * 1e3, 50)),
+                "p99_ms": float(np.percentile(np.asarray(r2["lat"]) * 1e3, 99))}
+        ref2 = golden_q(c2)
+        if ref2 is not None:
+            rec2["error_vs_oracle"], rec2["max_step_error_vs_oracle"] = errors(
+                r2["q"], ref2, area_of(r2["V"], r2["T"]))
+        out["C2"] = rec2
+        out["marching"] = [run_marching(C, torch, ctx, W.C2), run_marching(C, torch, ctx, wl, steps=1)]
+        print("marching done", file=sys.stderr, flush=True)
         out["compressed"] = run_compressed(C, torch, ctx)
+        print("compressed done", file=sys.stderr, flush=True)
         out["batch48"] = run_batch48(C, torch, ctx)
-        out["serving"] = run_serving(C, torch, ctx, rate=args.serve_rate, duration=args.serve_seconds)
+        print("batch48 done", file=sys.stderr, flush=True)
+        out["serving"] = run_serving(C, torch, ctx, args.serve_rate, args.serve_seconds,
+                                     args.serve_large)
+        print("serving done", file=sys.stderr, flush=True)
     C.cqm_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

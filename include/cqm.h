@@ -121,7 +121,23 @@ typedef struct cqm_options {
                             plain operator's diagonal blocks the same way
                             (the near-field values they need as well).
                                                                 (BLOCK_JACOBI) */
-  int32_t reserved[2];
+  int32_t marching;      /* nonzero: the workspace also holds the real
+                            integration weights What_n, n = 0..N, of the
+                            stored form (N+1 slices of the packed
+                            triangle, 8 B per entry) for
+                            cqm_solve_marching                        (0)   */
+  double cutoff_inner;   /* cut-off of the stored form's inner-iteration
+                            (FP32) operator: a 64 x 64 tile (16 x 16 in the
+                            assembly) is left out of frequency l when
+                            Re(s_l) r_min >= cutoff_inner, r_min the gap of
+                            the tiles' bounding boxes, so every entry left
+                            out is below e^-cutoff_inner of the kernel
+                            scale (introduction: cut-off strategies);
+                            0 = off                                   (18) */
+  double cutoff_outer;   /* the same for the FP64 operator (assembly and
+                            refinement residuals); 45 leaves out entries
+                            below 3e-20 of the kernel scale, far under FP64
+                            rounding; 0 = off                         (45) */
 } cqm_options;
 
 /* Inner preconditioners (cqm_options.precond). */
@@ -177,7 +193,11 @@ typedef struct cqm_diag {
                                values evaluated; GEMV32, GEMV64 and ARNOLDI
                                in bytes the algorithm must move (operator
                                rows once, Krylov vectors per pass); others 0 */
-  int32_t reserved[6];
+  int64_t h2_plain_bytes;   /* H2 x MACA: bytes of the same blocks without
+                               the frequency compression (every block's
+                               spatial factor per frequency, plus the
+                               bases): plain H2 storage, Section 7.1     */
+  int32_t reserved[4];
 } cqm_diag;
 
 typedef struct cqm_ctx_s* cqm_ctx_t;
@@ -265,6 +285,23 @@ int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream
  * must share precond; otherwise CQM_EINVAL before any work is queued. */
 int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
                     cqm_diag* diags, hipStream_t stream);
+
+/* Time-marching solve of the same discrete system (Section 3.2, eq. dft,
+ * eq. cqmgalapx with eq. cqmrhs): the real integration weights
+ * What_n = rho^-n/(N+1) sum_l V(s_l) zeta^nl, n = 0..N, are formed from the
+ * stored operator of the distinct frequencies, then for n = 0..N the history
+ * sum r_n = b_n - sum_{j=1}^{n} What_j q_{n-j} and What_0 q_n = r_n (real
+ * symmetric positive definite; conjugate gradients with the inverses of its
+ * 64 x 64 diagonal blocks, to outer_tol relative residual).  It agrees with
+ * cqm_solve up to terms of order rho^(N+1).  The problem must be created in
+ * a plain mode, form CQM_FORM_DENSE, with cqm_options.marching = 1
+ * (CQM_EINVAL otherwise).  q_out: device, (N+1) x M doubles, caller-owned,
+ * written step by step.  diag (host, may be NULL): total_iters / max_iters
+ * are conjugate-gradient iterations over / per step, max_rel_residual the
+ * largest final relative residual of a step.  CQM_ENOCONV if a step missed
+ * its tolerance (output written), CQM_ENAN on non-finite values.  The call
+ * waits for the stream (the host steers the iterations). */
+int cqm_solve_marching(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream);
 
 /* ------------------------------------------------------------ test hooks */
 /* BDF2 CQM frequencies s_l = delta(rho zeta^-l)/dt for N steps on (0,T]

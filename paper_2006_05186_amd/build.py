@@ -22,12 +22,19 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-
          "-I" + os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 LIBNAME = "libcqm.so"
+PROBENAME = "libcqm_probe.so"
+
+
+# Per-file flags: the near-field entries (largest of every row, amplified by
+# rho^-N in the time domain) are computed without fused multiply-adds.
+FILE_FLAGS = {"k_near.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj]
+    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    cmd = [HIPCC] + FLAGS + extra + lang + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -51,7 +58,20 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, os.path.join(OUT, LIBNAME))
+    build_probe()
     return os.path.join(OUT, LIBNAME)
+
+
+def build_probe():
+    """The ALU throughput probe (probes/alu_rate.hip) as its own library,
+    lib/libcqm_probe.so; bench.py --alu-probe loads it."""
+    src = os.path.join(HERE, "probes", "alu_rate.hip")
+    tmp = os.path.join(OUT, PROBENAME + ".tmp")
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-shared", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, os.path.join(OUT, PROBENAME))
 
 
 if __name__ == "__main__":

@@ -21,6 +21,8 @@ __all__ = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
+    "cqm_solve_marching",
+    "cqm_solve_marching",
     "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_near_entries",
     "cqm_operator_stats",
     "cqm_server_opts", "cqm_request", "cqm_server_stats_t", "cqm_server_default_options",
@@ -62,7 +64,8 @@ class cqm_options(ctypes.Structure):
         ("eps_aca", ctypes.c_double), ("aca_band", ctypes.c_int32), ("q_duffy", ctypes.c_int32),
         ("reuse_operator", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+        ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32), ("marching", ctypes.c_int32),
+        ("cutoff_inner", ctypes.c_double), ("cutoff_outer", ctypes.c_double),
     ]
 
 
@@ -78,7 +81,7 @@ class cqm_diag(ctypes.Structure):
         ("far_units", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 8),
         ("kernel_calls", ctypes.c_int32 * 8), ("far_tile", ctypes.c_int32),
         ("far_waves", ctypes.c_int32), ("kernel_work", ctypes.c_double * 8),
-        ("reserved", ctypes.c_int32 * 6),
+        ("h2_plain_bytes", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4),
     ]
 
     def as_dict(self):
@@ -146,6 +149,7 @@ def load_library():
         "cqm_set_plane_wave": (ctypes.c_int, [P, ctypes.POINTER(D), D, D, D]),
         "cqm_set_dirichlet_samples": (ctypes.c_int, [P, P]),
         "cqm_solve": (ctypes.c_int, [P, P, ctypes.POINTER(cqm_diag), P]),
+        "cqm_solve_marching": (ctypes.c_int, [P, P, ctypes.POINTER(cqm_diag), P]),
         "cqm_solve_batch": (ctypes.c_int, [ctypes.POINTER(P), I32, ctypes.POINTER(P),
                                            ctypes.POINTER(cqm_diag), P]),
         "cqm_frequencies": (ctypes.c_int, [I32, D, D, P, P]),
@@ -232,6 +236,15 @@ def cqm_set_plane_wave(p, direction, sigma, t0, amplitude=1.0):
 
 def cqm_set_dirichlet_samples(p, dev_ptr):
     return _check(load_library().cqm_set_dirichlet_samples(p, ctypes.c_void_p(dev_ptr)))
+
+
+def cqm_solve_marching(p, q_out_ptr, stream=0):
+    """Returns (rc, diag); rc is CQM_OK or CQM_ENOCONV, other codes raise."""
+    d = cqm_diag()
+    rc = load_library().cqm_solve_marching(p, ctypes.c_void_p(q_out_ptr), ctypes.byref(d),
+                                           ctypes.c_void_p(stream))
+    _check(rc, ok=(CQM_OK, CQM_ENOCONV))
+    return rc, d
 
 
 def cqm_solve(p, q_out_ptr, stream=0):

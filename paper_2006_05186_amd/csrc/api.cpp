@@ -132,6 +132,8 @@ int cqm_default_options(cqm_options* o) {
   o->autotune = 1;
   o->graphs = 0;
   o->precond = CQM_PRECOND_BLOCK_JACOBI;
+  o->cutoff_inner = 18.0;
+  o->cutoff_outer = 45.0;
   return CQM_OK;
 }
 
@@ -187,6 +189,9 @@ int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv, const 
             "arnoldi_layout");
     require(o.precond == CQM_PRECOND_NONE || o.precond == CQM_PRECOND_BLOCK_JACOBI, CQM_EINVAL,
             "precond");
+    require(o.cutoff_inner >= 0 && o.cutoff_outer >= 0 && std::isfinite(o.cutoff_inner) &&
+                std::isfinite(o.cutoff_outer),
+            CQM_EINVAL, "cut-off exponents must be finite and >= 0");
     for (int64_t k = 0; k < 3 * nv; ++k)
       require(std::isfinite(vertices[k]), CQM_EINVAL, "non-finite vertex coordinate");
     for (int64_t k = 0; k < 3 * M; ++k)
@@ -237,6 +242,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
   (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
   h2_release(*p);
   p->timer.release();
+  if (p->march_host) (void)hipHostFree(p->march_host);
   for (hipEvent_t e : p->setup_ev)
     if (e) (void)hipEventDestroy(e);
   delete p->engine;
@@ -246,7 +252,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
                   p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea64u, p->dev.pb64u, p->dev.ftab, p->dev.ea32,
-                  p->dev.pb32};
+                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -343,6 +349,14 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs, cqm_di
       if (rc != CQM_OK && (worst == CQM_OK || rc < worst)) worst = rc;
     }
     return finish(worst);
+  });
+}
+
+int cqm_solve_marching(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream) {
+  return guarded([&] {
+    require(p != nullptr, CQM_EINVAL, "NULL problem");
+    solve_marching(*p, q_out, diag, stream);
+    return CQM_OK;
   });
 }
 

@@ -32,6 +32,29 @@ template <typename T> void ensure(T*& ptr, size_t& cap, size_t n) {
   cap = c;
 }
 bool dense_form(const Problem& p) { return !mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE; }
+
+// Entries of the stored upper triangle a product reads per frequency under
+// the inner and the FP64 cut-off (from the host copy of the tile gaps),
+// once per problem.
+void cut_entries(Problem& p) {
+  if ((int)p.cut_entries32.size() == p.Fsys) return;
+  const int M = (int)p.M, nb = sym_blocks(M);
+  const std::vector<float>& gap = p.tile_gap_host;
+  p.cut_entries32.assign(p.Fsys, 0);
+  p.cut_entries64.assign(p.Fsys, 0);
+  for (int l = 0; l < p.Fsys; ++l) {
+    const float c32 = std::nextafter(cutoff_radius(p.opt.cutoff_inner, p.s_re[l]), 3.4e38f);
+    const float c64 = std::nextafter(cutoff_radius(p.opt.cutoff_outer, p.s_re[l]), 3.4e38f);
+    for (int J = 0; J < nb; ++J)
+      for (int I = 0; I <= J; ++I) {
+        const int64_t ri = std::min(kSymB, M - I * kSymB), cj = std::min(kSymB, M - J * kSymB);
+        const int64_t e = I == J ? ri * (ri + 1) / 2 : ri * cj;
+        const float g = gap[(size_t)J * (J + 1) / 2 + I];
+        if (!(g >= c32)) p.cut_entries32[l] += e;
+        if (!(g >= c64)) p.cut_entries64[l] += e;
+      }
+  }
+}
 }  // namespace
 
 template <typename R>
@@ -281,6 +304,14 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
           gl.V32 = d.V32;
           gl.V64 = d.V64;
           gl.M = M;
+          // cut-off radii of this frequency (rounded up: a skipped tile's
+          // entries were all left out by the assembly)
+          gl.gap = p.dev.tile_gap;
+          gl.cut32 = std::nextafter(cutoff_radius(p.opt.cutoff_inner, p.s_re[l]), 3.4e38f);
+          gl.cut64 = std::nextafter(cutoff_radius(p.opt.cutoff_outer, p.s_re[l]), 3.4e38f);
+          cut_entries(p);
+          gl.entries32 = p.cut_entries32[l];
+          gl.entries64 = p.cut_entries64[l];
           lite_.push_back(gl);
           it = slot.find(d.V64);
         }

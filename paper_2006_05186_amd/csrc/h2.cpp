@@ -184,16 +184,20 @@ void h2_prepare(Problem& p, hipStream_t s) {
   CQM_HIP(hipStreamSynchronize(s));
   h.max_rank = 0;
   double sum = 0.0;
-  int64_t bytes = 0;
+  int64_t bytes = 0, plain = 0;
   const size_t es = h.store_fp64 ? sizeof(cf64) : sizeof(cf32);
   for (size_t b = 0; b < h.blocks.size(); ++b) {
     h.max_rank = std::max(h.max_rank, h.ranks[b]);
     sum += h.ranks[b];
-    bytes += (int64_t)h.ranks[b] * ((int64_t)h.blocks[b].arows * h.blocks[b].acols * es + (int64_t)h.nsys * 16);
+    const int64_t slice = (int64_t)h.blocks[b].arows * h.blocks[b].acols * es;
+    bytes += (int64_t)h.ranks[b] * (slice + (int64_t)h.nsys * 16);
+    plain += (int64_t)h.nsys * slice;
   }
   bytes += (int64_t)(h.Uleaf.size() + h.E.size()) * 8;
+  plain += (int64_t)(h.Uleaf.size() + h.E.size()) * 8;
   h.mean_rank = h.blocks.empty() ? 0.0 : sum / h.blocks.size();
   h.bytes = bytes;
+  h.plain_bytes = plain;
 }
 
 template <typename R>
@@ -213,6 +217,7 @@ void h2_stats(const Problem& p, cqm_diag* d) {
   d->n_far_blocks = h.n_far;
   d->n_near_blocks = h.n_near;
   d->operator_bytes = h.bytes;
+  d->h2_plain_bytes = h.plain_bytes;
 }
 
 void h2_release(Problem& p) {

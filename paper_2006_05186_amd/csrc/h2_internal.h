@@ -66,6 +66,7 @@ struct H2Operator {
   int max_rank = 0;
   double mean_rank = 0;
   int64_t bytes = 0;
+  int64_t plain_bytes = 0;  // the same blocks per frequency (no MACA)
   // host FP64 data
   std::vector<double> nodes;   // per cluster 3*m Chebyshev nodes
   std::vector<double> Uleaf;   // per leaf #r x p (row-major)

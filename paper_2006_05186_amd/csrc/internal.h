@@ -121,7 +121,10 @@ struct GemvGroup {
 struct GroupLite {
   const void* V32;  // FP32 slice (mixed form) or null
   const void* V64;  // FP64 slice
-  int M, n, pad0, pad1;
+  int M, n;
+  float cut32, cut64;      // cut-off radii of the slice's frequency
+  const float* gap;        // tile box gaps (cut-off), or null
+  long long entries32, entries64;  // entries a product reads under each cut-off
   void* basis[kMaxGroup];  // members' Krylov bases (inner precision)
   cf64* x[kMaxGroup];      // members' FP64 iterates
   void* symp[kMaxGroup];   // members' partial-sum buffers
@@ -199,11 +202,26 @@ struct MeshDev {
   double* pb64u = nullptr;
   float* ea32 = nullptr;
   float* pb32 = nullptr;
+  // cut-off tables: per stored 64 x 64 tile (I, J), the gap between the
+  // bounding boxes of the two blocks' triangles (sym_tiles(M) floats, tile
+  // order of the packed triangle); per 16-triangle group of the assembly
+  // tiling, its box lo[3], hi[3]
+  float* tile_gap = nullptr;
+  double* sub_box = nullptr;
 };
+// Frequency-dependent cut-off radii of a system: tiles whose box gap is at
+// least cut32 (inner precision) or cut64 (FP64 operator) are left out.
+inline float cutoff_radius(double L, double re_s) {
+  return (L > 0.0 && re_s > 0.0) ? (float)(L / re_s) : 3.0e38f;
+}
 
 // Offsets (bytes) of the solve workspace.
 struct Layout {
   size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, pinv = 0, diag64 = 0, total = 0;
+  // time marching (cqm_options.marching): weights, What_0 block inverses and
+  // their complex staging, product partials, CG vectors and partial sums
+  size_t mw = 0, mpinv = 0, mdiag = 0, mpart = 0, mvec = 0;
+  int mchunks = 1;  // weight chunks of the history product (its partial slots)
 };
 
 struct H2Operator;  // compressed representation (h2.cpp)
@@ -281,6 +299,11 @@ struct Problem {
   class Engine* engine = nullptr;
   hipEvent_t setup_ev[2] = {nullptr, nullptr};  // brackets the operator setup of a solve
   EngineBufs engine_bufs;
+  int* march_host = nullptr;  // pinned: [0] converged flag, [1] step iterations
+  // stored-form entries a product reads per frequency under the inner and
+  // the FP64 cut-off (upper triangle; filled on first use)
+  std::vector<int64_t> cut_entries32, cut_entries64;
+  std::vector<float> tile_gap_host;  // host copy of dev.tile_gap
   bool full_band() const { return Fsys == F; }
 };
 
@@ -462,6 +485,30 @@ class Engine {
 };
 
 void release_engine_bufs(EngineBufs& b);
+
+// ------------------------------------------------------------ time marching
+// Vectors and partial sums of the conjugate gradients on What_0 (k_march.hip).
+struct CgVec {
+  double *x, *r, *z, *p, *w;
+  double *rz, *pw, *rr, *bb;  // per-workgroup partials (rz by iteration parity)
+  int* done;                  // device flag: converged
+  int* hdone;                 // pinned host flag (the host polls it)
+  int* iters;                 // pinned host counter: iterations of the step
+  const cf64* pinv;           // block inverses of What_0 (real parts used)
+  int M, nwg;
+};
+void launch_march_weights(const cf64* V, int M, int H, int F, const cf64* tw, const double* scale,
+                          double* W, hipStream_t s);
+int march_chunks(int M, int cnt);
+void launch_march_product(const double* W, int M, int j0, int cnt, const double* X, int xb,
+                          double* P, int S, const int* done, hipStream_t s);
+void launch_march_reduce(const double* P, int S, int M, double sign, const double* add, double* y,
+                         hipStream_t s);
+void launch_march_diag(const double* W0, int M, cf64* out, hipStream_t s);
+void launch_cg_init(const CgVec& v, hipStream_t s);
+void launch_cg_iteration(const CgVec& v, const double* W0, double* P, int par, double tol2,
+                         hipStream_t s);
+void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s);  // march.cpp
 
 // RAII helper: times the launches issued in its scope as one class.
 struct Timed {

@@ -198,11 +198,28 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
   }
   int I, J;
   decode_tile(t, I, J);
+  const int ntB = sym_blocks(M) * kB;
+  const int n = kGrouped ? G.n : 1;
+  // cut-off: a tile whose blocks' box gap reaches the slice's radius holds
+  // only zeros (the assembly left those entries out); its partial sums are
+  // zero and it is not read
+  if (G.gap && G.gap[t] >= (which == 0 && sizeof(R) == 4 ? G.cut32 : G.cut64)) {
+    if (threadIdx.x < kB) {
+      cplx<R> z;
+      z.re = R(0);
+      z.im = R(0);
+      for (int k = 0; k < n; ++k) {
+        if (!G.sysi[k][which == 0 ? 1 : 0]) continue;
+        cplx<R>* P = (cplx<R>*)G.symp[k];
+        P[(int64_t)J * ntB + I * kB + threadIdx.x] = z;
+        if (I != J) P[(int64_t)I * ntB + J * kB + threadIdx.x] = z;
+      }
+    }
+    return;
+  }
   const void* Vs = which == 0 ? (sizeof(R) == 4 ? G.V32 : G.V64) : G.V64;
   cplx<R> a[kRowsPerWave];
   masked_tile<R>((const cplx<R>*)Vs, t, M, I, J, a);
-  const int ntB = sym_blocks(M) * kB;
-  const int n = kGrouped ? G.n : 1;
   int done = 0;
   for (int k = 0; k < n; ++k) {
     if (!G.sysi[k][which == 0 ? 1 : 0]) continue;
@@ -212,10 +229,12 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
     ++done;
   }
   if (ctr && t == 0 && threadIdx.x == 0 && done) {
-    // algorithmic bytes, charged once per group by its first tile: the upper
-    // triangle of the slice once, each member's vectors once
-    const unsigned long long MM = (unsigned long long)M;
-    atomicAdd(ctr, (MM * (MM + 1) / 2 + (unsigned long long)done * 2 * MM) * sizeof(cplx<R>));
+    // algorithmic bytes, charged once per group by its first tile (never
+    // left out): the entries of the upper triangle a product reads under the
+    // slice's cut-off (counted by the host), each member's vectors once
+    const long long e = which == 0 && sizeof(R) == 4 ? G.entries32 : G.entries64;
+    atomicAdd(ctr, ((unsigned long long)e + (unsigned long long)done * 2 * (unsigned long long)M) *
+                       sizeof(cplx<R>));
   }
 }
 

@@ -61,15 +61,16 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     const typename Pt4<R>::T* __restrict__ pts, const int4* __restrict__ vid, int M,
     const R* __restrict__ ea, const R* __restrict__ pb, int nsys, const cplx<R>* __restrict__ x,
     int64_t xs, cplx<R>* __restrict__ partial, int chunk, const int* __restrict__ active,
-    unsigned long long* ctr, const double* __restrict__ ftab) {
+    unsigned long long* ctr, const double* __restrict__ ftab, const double* __restrict__ sbox,
+    double L) {
   using P4 = typename Pt4<R>::T;
   const int l0 = blockIdx.y * FT;
   const int nl = min(FT, nsys - l0);
-  int nact = nl;  // systems of the tile that asked for the product
+  unsigned amask = (1u << nl) - 1u;  // systems of the tile that asked for the product
   if (active) {
-    nact = 0;
-    for (int l = 0; l < nl; ++l) nact += active[(l0 + l) * kSysiStride] != 0;
-    if (!nact) return;
+    amask = 0;
+    for (int l = 0; l < nl; ++l) amask |= (active[(l0 + l) * kSysiStride] != 0 ? 1u : 0u) << l;
+    if (!amask) return;
   }
   __shared__ __align__(16) double stab[sizeof(R) == 8 ? 256 + kFp64Tab512Len : 2];
   if constexpr (sizeof(R) == 8) {
@@ -102,9 +103,42 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
   __shared__ cplx<R> sx[kTs * FT];
   const int j0 = blockIdx.z * chunk;
   const int j1 = min(M, j0 + chunk);
-  int pairs_done = 0;  // non-near source triangles of this target (work count)
+  // Re(s_l) of the tile's frequencies, from the exponent coefficients
+  // (FP32: -Re(s)/ln2; FP64: -Re(s) 256/ln2)
+  R res[FT];
+#pragma unroll
+  for (int l = 0; l < FT; ++l)
+    res[l] = -fe[l] * (sizeof(R) == 4 ? R(0.69314718055994531) : R(0.69314718055994531 / 256.0));
+  // work count: (non-near source triangle, active frequency not left out)
+  unsigned long long units_done = 0;
   for (int jt = j0; jt < j1; jt += kTs) {
     const int nt = min(kTs, j1 - jt);
+    // cut-off: the smallest gap between the boxes of the target block's four
+    // 16-groups and the source tile's two bounds every point distance;
+    // frequencies with Re(s_l) gap >= L are left out (uniform per workgroup)
+    // (padding frequencies past nl are never evaluated)
+    unsigned cut = ((1u << FT) - 1u) & ~((1u << nl) - 1u);
+    if (L < 1e300) {
+      double g2 = 1e300;
+      const int gt0 = blockIdx.x * (kTgt / 16), gs0 = jt / 16;
+      for (int a = gt0; a < min(gt0 + kTgt / 16, (M + 15) / 16); ++a)
+        for (int b = gs0; b < min(gs0 + kTs / 16, (M + 15) / 16); ++b) {
+          double h2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double gd = fmax(0.0, fmax(sbox[6 * a + d] - sbox[6 * b + 3 + d],
+                                             sbox[6 * b + d] - sbox[6 * a + 3 + d]));
+            h2 += gd * gd;
+          }
+          g2 = fmin(g2, h2);
+        }
+      const double gap = sqrt(g2);
+#pragma unroll
+      for (int l = 0; l < FT; ++l)
+        if ((double)res[l] * gap >= L) cut |= 1u << l;
+    }
+    if (cut == (1u << FT) - 1u) continue;  // every frequency left out
+    const int wunits = __popc(amask & ~cut);
     __syncthreads();
     for (int k = threadIdx.x; k < nt * kQ; k += kTgt) sp[k] = pts[jt * kQ + k];
     for (int k = threadIdx.x; k < nt; k += kTgt) sv[k] = vid[jt + k];
@@ -119,7 +153,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     __syncthreads();
     for (int jj = 0; jj < nt; ++jj) {
       if (share_vertex(tv, sv[jj])) continue;
-      ++pairs_done;
+      units_done += wunits;
       R vre[FT], vim[FT];
 #pragma unroll
       for (int l = 0; l < FT; ++l) {
@@ -136,6 +170,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
         const R w = tw[a] * q.w * ri;
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
+          if (cut & (1u << l)) continue;  // uniform per workgroup
           R e, c, sn;
           KMath<R>::eval(fe[l], fp[l], r, e, c, sn, stab);
           e *= w;
@@ -166,7 +201,7 @@ __global__ __launch_bounds__(kTgt) void k_far_apply(
     // point-pair-frequency kernel values of the far pairs handled here, for
     // the systems that asked for them (closed systems sharing the tile are
     // evaluated too but are not useful work)
-    unsigned long long u = i < M ? (unsigned long long)pairs_done * kQ * kQ * nact : 0ull;
+    unsigned long long u = i < M ? units_done * kQ * kQ : 0ull;
     u = wave_sum(u);
     if ((threadIdx.x & 63) == 0) atomicAdd(ctr, u);
   }
@@ -241,7 +276,9 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
                                                               const int32_t* __restrict__ nrp,
                                                               const int32_t* __restrict__ ncol,
                                                               const cf64* __restrict__ nval,
-                                                              int64_t nnz) {
+                                                              int64_t nnz,
+                                                              const double* __restrict__ sbox,
+                                                              double Lin, double Lout) {
   // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I (in
   // the diagonal mode, within block blockIdx.x / 10)
   constexpr int kSub = kSymB / kAt;
@@ -274,10 +311,38 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
   __syncthreads();
   const bool inb = i < M && j < M && (I != J || i <= j);
   const bool nearp = inb && share_vertex(vid[i], vid[j]);
-  const bool live = inb && !nearp;
+  // cut-off: with g the gap of the two 16-groups' boxes, every point pair
+  // of the tile has Re(s_l) r >= Re(s_l) g; frequencies with Re(s_l) g >= L
+  // are left out (zero) of the FP64 operator (Lout) or its FP32 copy (Lin)
+  // [uniform over the workgroup]
+  double gap = 0.0;
+  {
+    const double* bi = sbox + 6 * I;
+    const double* bj = sbox + 6 * J;
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double gd = fmax(0.0, fmax(bi[d] - bj[3 + d], bj[d] - bi[3 + d]));
+      g2 += gd * gd;
+    }
+    gap = sqrt(g2);
+  }
+  double fe[FT], fp[FT];
+  unsigned cut64 = 0, cut32 = 0;  // bit l: frequency l0 + l left out
+#pragma unroll
+  for (int l = 0; l < FT; ++l) {
+    fe[l] = l < nl ? ea[l0 + l] : 0.0;
+    fp[l] = l < nl ? pb[l0 + l] : 0.0;
+    // Re(s) from the exponent coefficient in table steps (-Re(s) 256/ln2)
+    const double rg = -fe[l] * (0.69314718055994531 / 256.0) * gap;
+    if (l >= nl || rg >= Lout) cut64 |= 1u << l;
+    if (l >= nl || rg >= Lin) cut32 |= 1u << l;
+  }
+  const bool all_cut = cut64 == (1u << FT) - 1u;
+  const bool live = inb && !nearp && !all_cut;
   if (ctr) {
     // point-pair-frequency kernel values evaluated by this tile
-    unsigned long long u = live ? (unsigned long long)kQ * kQ * nl : 0ull;
+    unsigned long long u = live ? (unsigned long long)kQ * kQ * (FT - __popc(cut64)) : 0ull;
     u = wave_sum(u);
     if ((threadIdx.x & 63) == 0) atomicAdd(ctr, u);
   }
@@ -285,12 +350,6 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
 #pragma unroll
   for (int l = 0; l < FT; ++l) vre[l] = vim[l] = 0.0;
   if (live) {
-    double fe[FT], fp[FT];
-#pragma unroll
-    for (int l = 0; l < FT; ++l) {
-      fe[l] = l < nl ? ea[l0 + l] : 0.0;
-      fp[l] = l < nl ? pb[l0 + l] : 0.0;
-    }
     for (int a = 0; a < kQ; ++a) {
       const double4 t = pts[i * kQ + a];
 #pragma unroll 1
@@ -301,6 +360,8 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
         const double w = t.w * q.w / r;
 #pragma unroll
         for (int l = 0; l < FT; ++l) {
+          // (left-out frequencies of a partly cut tile are evaluated anyway and
+          // stored as zero: a branch per frequency costs more than it saves)
           double e, c, sn;
           // arguments in table steps; the host has bounded -Re(s) r below
           // by -708 unless kClamp
@@ -324,7 +385,7 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
   // the mirrored entry (j, i) is stored too when both lie in one diagonal
   // block of the packed triangle (written directly: about 6 % of tiles)
   const bool mirpos = i != j && (kDiag || sym_stored(j, i));
-  const bool mir = live && mirpos;
+  const bool mir = inb && !nearp && mirpos;
   const int64_t oi = kDiag ? cidx(i, j) : sym_index(i, j);
   const int64_t om = mirpos ? (kDiag ? cidx(j, i) : sym_index(j, i)) : 0;
   if (nearp && nval) {
@@ -350,16 +411,19 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
       }
     }
   }
+  // far pairs (left-out frequencies stored as zero)
 #pragma unroll
   for (int l = 0; l < FT; ++l) {
-    if (!live || l >= nl) continue;
-    const double re = vre[l] * kInv4Pi, im = vim[l] * kInv4Pi;
+    if (!inb || nearp || l >= nl) continue;
+    const bool z64 = cut64 & (1u << l), z32 = cut32 & (1u << l);
+    const double re = z64 ? 0.0 : vre[l] * kInv4Pi, im = z64 ? 0.0 : vim[l] * kInv4Pi;
+    const cf32 v32 = z32 ? cf32{0.f, 0.f} : cf32{(float)re, (float)im};
     const int64_t base = (int64_t)(l0 + l) * SL;
     d64[base + oi] = cf64{re, im};
-    if (d32) d32[base + oi] = cf32{(float)re, (float)im};
+    if (d32) d32[base + oi] = v32;
     if (mir) {
       d64[base + om] = cf64{re, im};
-      if (d32) d32[base + om] = cf32{(float)re, (float)im};
+      if (d32) d32[base + om] = v32;
     }
   }
 }
@@ -423,8 +487,11 @@ static void far_apply_ft(const Problem& p, int l0, int nsys, const cplx<R>* x, i
     ea = p.dev.ea64u + l0;  // in table steps
     pb = p.dev.pb64u + l0;
   }
+  // cut-off exponent: the inner (FP32) operator or the FP64 one (0 = off)
+  const double Lc = sizeof(R) == 4 ? p.opt.cutoff_inner : p.opt.cutoff_outer;
   hipLaunchKernelGGL((k_far_apply<R, FT>), grid, dim3(kTgt), 0, s, pts, p.dev.vid, M, ea, pb,
-                     nsys, x, xs, partial, chunk, active, ctr, p.dev.ftab);
+                     nsys, x, xs, partial, chunk, active, ctr, p.dev.ftab, p.dev.sub_box,
+                     Lc > 0 ? Lc : HUGE_VAL);
   CQM_HIP(hipGetLastError());
 }
 
@@ -628,14 +695,19 @@ static void dense_assemble_ft(const Problem& p, cf64* d64, cf32* d32, const cf64
   double sr = 0.0;
   for (int l = 0; l < p.Fsys; ++l) sr = std::max(sr, p.s_re[l]);
   const bool clamp = !(sr * diag <= 700.0);
+  // cut-off exponents (0 = off)
+  const double Lin = p.opt.cutoff_inner > 0 ? p.opt.cutoff_inner : HUGE_VAL;
+  const double Lout = p.opt.cutoff_outer > 0 ? p.opt.cutoff_outer : HUGE_VAL;
   if (clamp)
     hipLaunchKernelGGL((k_dense_assemble<FT, true, kDiag>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
                        p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
-                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
+                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size(), p.dev.sub_box,
+                       Lin, Lout);
   else
     hipLaunchKernelGGL((k_dense_assemble<FT, false, kDiag>), grid, dim3(kAt * kAt), 0, s, p.dev.pts64,
                        p.dev.vid, M, p.dev.ea64u, p.dev.pb64u, p.Fsys, d64, d32, ctr, p.dev.ftab,
-                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size());
+                       p.dev.near_rowptr, p.dev.near_col, nv, (int64_t)p.col.size(), p.dev.sub_box,
+                       Lin, Lout);
   CQM_HIP(hipGetLastError());
 }
 

@@ -4,6 +4,10 @@
 //       sharing pattern), computed once per mesh in FP64;
 // D_ij(s) = sum_ab W_ia W_jb (exp(-s r) - 1)/(4 pi r): the bounded remainder by
 //       the 6-point rule, with its r = 0 value -s/(4 pi), per frequency, FP64.
+// These entries are the largest of every row and the time-domain solution
+// amplifies their rounding by up to rho^-N (1e8), so this file is compiled
+// without contraction into fused multiply-adds (each product and sum rounded
+// on its own) and exp(-s r) - 1 is formed without cancellation.
 #include "device_util.h"
 #include "fp64_math.h"
 
@@ -129,21 +133,17 @@ void launch_near_static(const Problem& p, hipStream_t s) {
 }
 
 // vals[l][k] = S_k + D_k(s_l) for near pair k (row kr[k]), system l: one
-// thread per pair and frequency.  exp(-s r) from the table-driven FP64
-// exponential and sine/cosine (tables staged in LDS); exp(-s r) - 1 is then
-// formed directly: its rounding error, about 2^-52 in absolute terms, stays
-// below that of the static part S_k, which is of order 1/r and dominates
-// the entry.
+// thread per pair and frequency.  With z = -s r = x + i y and the half
+// angle (sin y = 2 sh ch, cos y = 1 - 2 sh^2),
+//   exp(z) - 1 = (expm1(x) (1 - 2 sh^2) - 2 sh^2) + i (1 + expm1(x)) 2 sh ch,
+// free of the cancellation of exp(z) - 1 at small |s r| (library expm1 and
+// sincos).
 __global__ __launch_bounds__(128) void k_near_values(const double4* __restrict__ pts,
                                                      const int32_t* __restrict__ krow,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ stat,
                                                      const cf64* __restrict__ sfreq, int64_t nnz,
-                                                     cf64* __restrict__ vals,
-                                                     const double* __restrict__ ftab) {
-  __shared__ __align__(16) double stab[kFp64TabLen];
-  for (int t = threadIdx.x; t < kFp64TabLen; t += blockDim.x) stab[t] = ftab[t];
-  __syncthreads();
+                                                     cf64* __restrict__ vals) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y;
   if (k >= nnz) return;
@@ -159,13 +159,12 @@ __global__ __launch_bounds__(128) void k_near_values(const double4* __restrict__
       const double ww = tp.w * sp.w;
       double fr, fi;
       if (r > 0.0) {
-        // (exp(-s r) - 1) / r with exp(-s r) = e (cos(si r) - i sin(si r))
-        const double ir = 1.0 / r;
-        const double e = exp_tab(-sr * r, stab);
-        double sn, c;
-        sincos_tab(si * r, stab, &sn, &c);
-        fr = fma(e, c, -1.0) * ir;
-        fi = -(e * sn) * ir;
+        const double x = -sr * r, y = -si * r;
+        double sh, ch;
+        sincos(0.5 * y, &sh, &ch);
+        const double em1 = expm1(x), sh2 = 2.0 * sh * sh;
+        fr = (em1 * (1.0 - sh2) - sh2) / r;
+        fi = ((1.0 + em1) * (2.0 * sh * ch)) / r;
       } else {
         fr = -sr;
         fi = -si;
@@ -181,7 +180,7 @@ void launch_near_values(const Problem& p, cf64* vals, hipStream_t s) {
   const int64_t nnz = (int64_t)p.col.size();
   dim3 grid((unsigned)((nnz + 127) / 128), p.Fsys);
   hipLaunchKernelGGL(k_near_values, grid, dim3(128), 0, s, p.dev.pts64, p.dev.near_row,
-                     p.dev.near_col, p.dev.near_static, p.dev.s, nnz, vals, p.dev.ftab);
+                     p.dev.near_col, p.dev.near_static, p.dev.s, nnz, vals);
   CQM_HIP(hipGetLastError());
 }
 

@@ -12,33 +12,37 @@ namespace cqm {
 
 // Gauss-Legendre rule on [0,1] by Newton iteration on P_q.
 void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w) {
+  // Newton's method on P_q in extended precision (x86 long double, 64-bit
+  // mantissa), nodes and weights 2/((1-t^2) P_q'(t)^2) then rounded once to
+  // FP64: the Duffy rules' values are the largest entries of every row, and
+  // the time-domain solution amplifies their rounding by up to rho^-N
   x.assign(q, 0.0);
   w.assign(q, 0.0);
+  using L = long double;
+  const L pi_l = 3.141592653589793238462643383279502884L;
   for (int i = 0; i < q; ++i) {
-    double t = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    L t = std::cos(pi_l * (i + 0.75L) / (q + 0.5L));
     for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = t;
+      L p0 = 1.0L, p1 = t;
       for (int k = 2; k <= q; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        const L p2 = ((2.0L * k - 1.0L) * t * p1 - (k - 1.0L) * p0) / k;
         p0 = p1;
         p1 = p2;
       }
-      const double dp = q * (t * p1 - p0) / (t * t - 1.0);
-      const double dt = p1 / dp;
+      const L dp = q * (t * p1 - p0) / (t * t - 1.0L);
+      const L dt = p1 / dp;
       t -= dt;
-      if (std::fabs(dt) < 1e-16) {
-        double a0 = 1.0, a1 = t;
-        for (int k = 2; k <= q; ++k) {
-          const double a2 = ((2.0 * k - 1.0) * t * a1 - (k - 1.0) * a0) / k;
-          a0 = a1;
-          a1 = a2;
-        }
-        const double d = q * (t * a1 - a0) / (t * t - 1.0);
-        w[i] = 1.0 / ((1.0 - t * t) * d * d);  // weight on [0,1] = 2/((1-t^2)P'^2) / 2
-        break;
-      }
+      if (std::fabs(dt) < 1e-19L) break;
     }
-    x[i] = 0.5 * (1.0 - t);
+    L a0 = 1.0L, a1 = t;
+    for (int k = 2; k <= q; ++k) {
+      const L a2 = ((2.0L * k - 1.0L) * t * a1 - (k - 1.0L) * a0) / k;
+      a0 = a1;
+      a1 = a2;
+    }
+    const L d = q * (t * a1 - a0) / (t * t - 1.0L);
+    w[i] = (double)(1.0L / ((1.0L - t * t) * d * d));  // weight on [0,1] = 2/((1-t^2)P'^2) / 2
+    x[i] = (double)(0.5L * (1.0L - t));
   }
   // sort ascending
   std::vector<int> idx(q);
@@ -155,6 +159,43 @@ void upload_problem(Problem& p) {
   }
   p.dev.pts64 = upload(p64);
   p.dev.pts32 = upload(p32);
+  {
+    // bounding boxes of the triangles of each 64-block and 16-group (the
+    // vertex boxes contain every quadrature point), for the cut-off
+    auto boxes = [&](int g) {
+      const int64_t nb = (M + g - 1) / g;
+      std::vector<double> b(nb * 6);
+      for (int64_t k = 0; k < nb; ++k) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = k * g; i < std::min<int64_t>(M, (k + 1) * g); ++i)
+          for (int v = 0; v < 3; ++v)
+            for (int d = 0; d < 3; ++d) {
+              const double x = p.verts[3 * p.tris[3 * i + v] + d];
+              lo[d] = std::min(lo[d], x);
+              hi[d] = std::max(hi[d], x);
+            }
+        for (int d = 0; d < 3; ++d) b[6 * k + d] = lo[d], b[6 * k + 3 + d] = hi[d];
+      }
+      return b;
+    };
+    const std::vector<double> b64 = boxes(kSymB), b16 = boxes(16);
+    const int nb = sym_blocks((int)M);
+    std::vector<float> gap((size_t)sym_tiles((int)M));
+    for (int J = 0; J < nb; ++J)
+      for (int I = 0; I <= J; ++I) {
+        double g2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double gd = std::max(0.0, std::max(b64[6 * I + d] - b64[6 * J + 3 + d],
+                                                   b64[6 * J + d] - b64[6 * I + 3 + d]));
+          g2 += gd * gd;
+        }
+        // rounded down so the float never exceeds the true gap
+        gap[(size_t)J * (J + 1) / 2 + I] = std::nextafter((float)std::sqrt(g2), 0.0f);
+      }
+    p.dev.tile_gap = upload(gap);
+    p.tile_gap_host = gap;
+    p.dev.sub_box = upload(b16);
+  }
   p.dev.vid = upload(vid);
   p.dev.area = upload(area);
   p.dev.verts = upload(p.verts);
@@ -317,6 +358,19 @@ void compute_layout(Problem& p) {
                       block_inverse_elems((int)M));
       }
     }
+  }
+  if (p.opt.marching && !mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE) {
+    // time marching: N+1 real weight slices, the block inverses of What_0
+    // (and their complex staging), the history product's partial slots and
+    // the CG vectors with their per-workgroup partials
+    const int Mi = (int)M, nb = sym_blocks(Mi);
+    const size_t nwg = (M + 255) / 256;
+    L.mchunks = march_chunks(Mi, std::max(1, p.N));
+    L.mw = take(sizeof(double) * p.F * sym_slice(Mi));
+    L.mpinv = take(sizeof(cf64) * block_inverse_elems(Mi));
+    L.mdiag = take(sizeof(cf64) * block_inverse_elems(Mi));
+    L.mpart = take(sizeof(double) * L.mchunks * (size_t)nb * nb * kSymB);
+    L.mvec = take(sizeof(double) * (5 * M + 5 * nwg) + 256);
   }
   L.total = off;
   p.lay = L;

@@ -41,6 +41,15 @@ class Problem:
         rc, diag = C.cqm_solve(self.handle, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         return out, rc, diag
 
+    def solve_marching(self, out=None):
+        """Time-marching solve (needs marching=1 at construction)."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.N + 1, self.M), dtype=torch.float64, device=self.device)
+        rc, diag = C.cqm_solve_marching(self.handle, out.data_ptr(),
+                                        torch.cuda.current_stream().cuda_stream)
+        return out, rc, diag
+
     def apply(self, x, l0=0, precision=64):
         """x: complex torch tensor (nl, M) on device; returns V(s_l) x_l."""
         torch = self.torch

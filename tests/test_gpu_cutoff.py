@@ -1,0 +1,81 @@
+"""Cut-off of far pairs whose kernel factor e^{-Re(s_l) r} is negligible (the
+cut-off strategy named in the paper's introduction): left out of the FP32
+inner-iteration operator below e^-18 of the kernel scale and out of the FP64
+operator below e^-45.  The answer must not move beyond the FP64 floor of the
+plain solve, the products must agree with the full operator to their
+precision, and work must actually be skipped."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import cqm_workloads as W
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_05186_amd import cqm as C  # noqa: E402
+from paper_2006_05186_amd.solver import Problem  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = C.cqm_ctx_create(0)
+    yield c
+    C.cqm_ctx_destroy(c)
+
+
+@pytest.mark.parametrize("form", [C.CQM_FORM_DENSE, C.CQM_FORM_MATRIX_FREE])
+def test_cutoff_products_equal_full_operator(ctx, form):
+    wl = W.C3
+    V, T = wl.mesh()
+    H = wl.N // 2 + 1
+    x = torch.as_tensor(W.random_complex((H, len(T)), seed=41), device="cuda")
+    ys = {}
+    for on in (True, False):
+        kw = {} if on else {"cutoff_inner": 0.0, "cutoff_outer": 0.0}
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=form, **kw)
+        ys[on] = {prec: p.apply(x, 0, prec).cpu().numpy().astype(np.complex128) for prec in (32, 64)}
+        p.close()
+    for prec, tol in ((32, 1e-7), (64, 1e-15)):
+        worst = max(np.linalg.norm(ys[True][prec][l] - ys[False][prec][l]) /
+                    np.linalg.norm(ys[False][prec][l]) for l in range(H))
+        say(f"form={form} precision {prec}: cut-off vs full worst {worst:.2e}")
+        assert worst <= tol
+
+
+def test_cutoff_skips_work_and_keeps_the_answer(ctx):
+    wl = W.C3
+    V, T = wl.mesh()
+    g = np.load(os.path.join(GOLDEN, f"{wl.name}.npz"))
+    _, _, area = O.triangle_quadrature(V, T)
+    res = {}
+    for on in (True, False):
+        kw = {} if on else {"cutoff_inner": 0.0, "cutoff_outer": 0.0}
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE,
+                    profile=1, **kw)
+        p.set_plane_wave()
+        q, rc, d = p.solve()
+        assert rc == C.CQM_OK
+        err = O.rel_error(q.cpu().numpy(), g["q"], area)
+        w = d.as_dict()["kernel_work"]
+        res[on] = (q.cpu().numpy(), err, w[C.KERNEL_CLASSES.index("assemble")],
+                   w[C.KERNEL_CLASSES.index("gemv32")])
+        say(f"cut-off {on}: err vs oracle {err:.2e}, assembly values {res[on][2]:.3e}, "
+            f"inner product bytes {res[on][3]:.3e}, steps {d.total_iters}")
+        p.close()
+    # the two runs differ only below the FP64 floor of the plain solve
+    diff = O.rel_error(res[True][0], res[False][0], area)
+    say(f"cut-off on vs off: {diff:.2e}")
+    assert diff < 3e-8 and res[True][1] < 3e-8
+    assert res[True][2] < 0.9 * res[False][2]
+    assert res[True][3] < res[False][3]
