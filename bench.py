@@ -396,10 +396,14 @@ def tag_of(wl):
 
 def far32_probe(C, torch, ctx, wl):
     """Kernel evaluation rate of the matrix-free FP32 far product (all
-    distinct frequency systems active): one cqm_apply_V, timed by events."""
+    distinct frequency systems active, no cut-off): cqm_apply_V timed by
+    events."""
     from paper_2006_05186_amd.solver import Problem
     V, T = wl.mesh()
-    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE)
+    # no cut-off: every far point-pair-frequency value is evaluated, so the
+    # count of values per product is exactly far_units
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_MATRIX_FREE,
+                cutoff_inner=0.0, cutoff_outer=0.0)
     H = wl.N // 2 + 1
     x = torch.as_tensor(W.random_complex((H, len(T)), seed=3), device="cuda").to(torch.complex64)
     for _ in range(2):
@@ -422,6 +426,35 @@ def far32_probe(C, torch, ctx, wl):
             "frac_fp32_peak": tf / PEAK_FP32_TFLOPS,
             "frac_fp32_unpacked_peak": tf / PEAK_FP32_UNPACKED_TFLOPS,
             "frac_of_measured_issue_ceiling": tf / ALU_PEAK_TFLOPS["far32"]}
+
+
+def h2_apply_probe(C, torch, ctx, wl, reps=5):
+    """The compressed operator of `wl` (m = 4, leaf size 32, eta = 1, eps
+    1e-6, mixed) built once (MACA) and applied `reps` times in each
+    precision to all frequencies, timed by events: the compressed kernels
+    without a whole solve around them (for counter profiles)."""
+    from paper_2006_05186_amd.solver import Problem
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_H2ACA)
+    F = wl.N + 1
+    x = torch.as_tensor(W.random_complex((F, len(T)), seed=5), device="cuda")
+    p.apply(x, 0, 64)  # builds the operator
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    out = {"workload": wl.name}
+    for prec in (32, 64):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            p.apply(x, 0, prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out[f"apply{prec}_ms"] = e0.elapsed_time(e1) / reps
+    d = C.cqm_operator_stats(p.handle)
+    out |= {"max_rank": d.max_rank, "mean_rank": d.mean_rank, "far_blocks": d.n_far_blocks,
+            "near_blocks": d.n_near_blocks, "operator_GB": d.operator_bytes / 1e9}
+    p.close()
+    return out
 
 
 def run_marching(C, torch, ctx, wl, steps=3):
@@ -540,7 +573,7 @@ def main():
     ap.add_argument("--alu-probe", action="store_true",
                     help="only measure the lane-op rates of v_exp_f32, v_sin_f32, v_cos_f32, "
                          "v_rsq_f32 and FP32/FP64 FMA (lib/libcqm_probe.so) and exit")
-    ap.add_argument("--part", choices=["far32", "compressed", "marching", "study"],
+    ap.add_argument("--part", choices=["far32", "compressed", "h2apply", "marching", "study"],
                     help="only run one piece on the workload (for counter profiles) and print "
                          "its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -575,6 +608,8 @@ def main():
     if args.part:
         if args.part == "far32":
             rec = far32_probe(C, torch, ctx, wl)
+        elif args.part == "h2apply":
+            rec = h2_apply_probe(C, torch, ctx, wl)
         elif args.part == "study":
             rec = run_study(C, torch, ctx)
         elif args.part == "compressed":

@@ -70,6 +70,32 @@ __device__ __forceinline__ void wave_reduce_scatter_near(T* a, int lane) {
     wave_reduce_scatter_near<1, OFF * 2, T>(a, lane);
   }
 }
+// Double-double value hi + lo (|lo| <= ulp(hi)/2): sums of FP64 products
+// carried to about 106 bits (error-free product by fma, Knuth's two-sum).
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  const double p = a * b;
+  return dd{p, fma(a, b, -p)};
+}
+__device__ __forceinline__ dd operator+(dd a, dd b) {
+  const double s = a.hi + b.hi;
+  const double bb = s - a.hi;
+  double e = (a.hi - (s - bb)) + (b.hi - bb);  // two-sum error of a.hi + b.hi
+  e += a.lo + b.lo;
+  const double h = s + e;
+  return dd{h, e - (h - s)};
+}
+__device__ __forceinline__ dd operator-(dd a) { return dd{-a.hi, -a.lo}; }
+__device__ __forceinline__ dd& operator+=(dd& a, dd b) {
+  a = a + b;
+  return a;
+}
+template <int OFF> __device__ __forceinline__ dd xor_lane(dd v) {
+  return dd{xor_lane<OFF>(v.hi), xor_lane<OFF>(v.lo)};
+}
+
 template <typename T> __device__ __forceinline__ T wave_sum_near(T v) {
   T a[1] = {v};
   wave_reduce_scatter_near<1, 1, T>(a, 0);

@@ -287,7 +287,7 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
       if (dense_form(p)) {
         d.V64 = wsp<cf64>(p, p.lay.dense64) + (size_t)l * sym_slice(M);
         d.V32 = p.lay.dense32 ? (const void*)(wsp<cf32>(p, p.lay.dense32) + (size_t)l * sym_slice(M)) : nullptr;
-        d.symp = st->base + st->sym + sizeof(cf64) * (size_t)l * sym_partials(M);
+        d.symp = st->base + st->sym + 2 * sizeof(cf64) * (size_t)l * sym_partials(M);
         if (p.lay.pinv) {
           d.Pinv = mixed ? (const void*)(wsp<cf32>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M))
                          : (const void*)(wsp<cf64>(p, p.lay.pinv) + (size_t)l * block_inverse_elems(M));
@@ -643,9 +643,13 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     launch_cycle_finish<R>(sd, n, maxM_, s);
   }
   if (!lite_.empty()) {
-    // residuals of the systems that ran this cycle: the list from its start
+    // residuals of the systems that ran this cycle (the list from its start),
+    // in double-double arithmetic
     Timed t(p0, CQM_K_GEMV64, s);
-    dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
+    for (const GClass& c : cyc_cls_)
+      launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
+                             p0.timer.ctr(CQM_K_GEMV64), s);
+    if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
   }
   bool other_forms = false;  // stored-form residuals are complete already
   for (SolveState* st : S_) {

@@ -372,6 +372,12 @@ void launch_dense_gemv_groups(const GroupLite* gl, int ngroups, int M, bool grou
 template <typename R>
 void launch_dense_reduce_desc(const SysDesc* sd, int nsys, int maxM, int which, int j,
                               hipStream_t s);
+// FP64 refinement residuals r = ghat - V x of the stored form in
+// double-double arithmetic (partials as (hi, lo): 2 sym_partials cf64 per
+// system), for systems with an open outer iteration
+void launch_resid_dd_groups(const GroupLite* gl, int ngroups, int M, bool grouped,
+                            unsigned long long* ctr, hipStream_t s);
+void launch_resid_dd_reduce(const SysDesc* sd, int nsys, int maxM, hipStream_t s);
 // Block-Jacobi preconditioner (k_dense.hip): inverses of the kSymB x kSymB
 // diagonal blocks of every slice (elimination and storage in R), from the
 // packed slice's diagonal tiles or from a compact array of the blocks;

@@ -238,6 +238,138 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
   }
 }
 
+// FP64 refinement residual r = ghat - V x in double-double arithmetic:
+// every product exact (two_prod), every sum carried to ~106 bits, the
+// partial sums stored as (hi, lo) pairs (P_hi in the first sym_partials
+// slots of the member's buffer, P_lo in the next), r rounded once.  With the
+// residual formed in FP64 the refinement stalls where the rounding of V x
+// (about 1e-16 of |V||x|) hides the true residual, and the time-domain
+// solution, which amplifies per-frequency errors by up to rho^-N, inherits
+// that floor; formed in double-double, x converges to the solution of the
+// stored FP64 system.
+__global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restrict__ gl, int grouped,
+                                                       unsigned long long* ctr) {
+  __shared__ dd colred[4][kB][2];
+  const GroupLite& G = gl[blockIdx.y];
+  const int M = G.M;
+  const int t = blockIdx.x;
+  const int n = grouped ? G.n : 1;
+  {
+    bool any = false;
+    for (int k = 0; k < n; ++k) any |= G.sysi[k][0] != 0;
+    if (!any) return;
+  }
+  int I, J;
+  decode_tile(t, I, J);
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ntB = sym_blocks(M) * kB;
+  const int64_t np = sym_partials(M);
+  if (G.gap && G.gap[t] >= G.cut64) {
+    // a tile left out by the cut-off holds only zeros
+    if (threadIdx.x < kB) {
+      for (int k = 0; k < n; ++k) {
+        if (!G.sysi[k][0]) continue;
+        cf64* P = (cf64*)G.symp[k];
+        P[(int64_t)J * ntB + I * kB + threadIdx.x] = cf64{0.0, 0.0};
+        P[np + (int64_t)J * ntB + I * kB + threadIdx.x] = cf64{0.0, 0.0};
+        if (I != J) {
+          P[(int64_t)I * ntB + J * kB + threadIdx.x] = cf64{0.0, 0.0};
+          P[np + (int64_t)I * ntB + J * kB + threadIdx.x] = cf64{0.0, 0.0};
+        }
+      }
+    }
+    return;
+  }
+  cf64 a[kRowsPerWave];
+  masked_tile<double>((const cf64*)G.V64, t, M, I, J, a);
+  if (ctr && t == 0 && threadIdx.x == 0) {
+    // algorithmic bytes, once per group: the entries read under the FP64
+    // cut-off, each open member's vectors once
+    int open = 0;
+    for (int k = 0; k < n; ++k) open += G.sysi[k][0] != 0;
+    atomicAdd(ctr, ((unsigned long long)G.entries64 + (unsigned long long)open * 2 * M) * sizeof(cf64));
+  }
+  for (int k = 0; k < n; ++k) {
+    if (!G.sysi[k][0]) continue;
+    const cf64* x = G.x[k];
+    cf64* P = (cf64*)G.symp[k];
+    const cf64 xj = load_x<double>(x, J * kB + c, M);
+    // rows of I: V_IJ x_J, real and imaginary parts in two rounds
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      dd v[kRowsPerWave];
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q)
+        v[q] = part == 0 ? two_prod(a[q].re, xj.re) + (-two_prod(a[q].im, xj.im))
+                         : two_prod(a[q].re, xj.im) + two_prod(a[q].im, xj.re);
+      wave_reduce_scatter_near<kRowsPerWave>(v, c);
+      if (c < kRowsPerWave) {
+        const int64_t o = (int64_t)J * ntB + I * kB + w * kRowsPerWave + scatter_entry<kRowsPerWave>(c);
+        double* ph = reinterpret_cast<double*>(P + o);
+        double* pl = reinterpret_cast<double*>(P + np + o);
+        ph[part] = v[0].hi;
+        pl[part] = v[0].lo;
+      }
+    }
+    if (I != J) {
+      // rows of J: V_IJ^T x_I
+      const cf64 xi = load_x<double>(x, I * kB + c, M);
+      dd cre{0.0, 0.0}, cim{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < kRowsPerWave; ++q) {
+        const int r = w * kRowsPerWave + q;
+        const double xr = lane_bcast(xi.re, r), xm = lane_bcast(xi.im, r);
+        cre += two_prod(a[q].re, xr) + (-two_prod(a[q].im, xm));
+        cim += two_prod(a[q].re, xm) + two_prod(a[q].im, xr);
+      }
+      colred[w][c][0] = cre;
+      colred[w][c][1] = cim;
+      __syncthreads();
+      if (w == 0) {
+        const dd ore = (colred[0][c][0] + colred[1][c][0]) + (colred[2][c][0] + colred[3][c][0]);
+        const dd oim = (colred[0][c][1] + colred[1][c][1]) + (colred[2][c][1] + colred[3][c][1]);
+        const int64_t o = (int64_t)I * ntB + J * kB + c;
+        P[o] = cf64{ore.hi, oim.hi};
+        P[np + o] = cf64{ore.lo, oim.lo};
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// r = ghat - sum_Y P[Y][i] in double-double, rounded once (the systems with
+// an open outer iteration).
+__global__ __launch_bounds__(256) void k_symv_resid_dd_reduce(const SysDesc* __restrict__ sd) {
+  const SysDesc D = sd[blockIdx.y];
+  if (!D.symp || !D.sysi[0]) return;
+  const int M = D.M;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int nt = sym_blocks(M), ntB = nt * kB;
+  const int64_t np = sym_partials(M);
+  const cf64* P = (const cf64*)D.symp;
+  dd re{D.ghat[i].re, 0.0}, im{D.ghat[i].im, 0.0};
+  for (int Y = 0; Y < nt; ++Y) {
+    const cf64 h = P[(int64_t)Y * ntB + i], l = P[np + (int64_t)Y * ntB + i];
+    re += dd{-h.re, -l.re};
+    im += dd{-h.im, -l.im};
+  }
+  D.r[i] = cf64{re.hi + re.lo, im.hi + im.lo};
+}
+
+void launch_resid_dd_groups(const GroupLite* gl, int ngroups, int M, bool grouped,
+                            unsigned long long* ctr, hipStream_t s) {
+  if (ngroups <= 0) return;
+  hipLaunchKernelGGL(k_symv_resid_dd, dim3(sym_tiles(M), ngroups), dim3(256), 0, s, gl,
+                     grouped ? 1 : 0, ctr);
+  CQM_HIP(hipGetLastError());
+}
+
+void launch_resid_dd_reduce(const SysDesc* sd, int nsys, int maxM, hipStream_t s) {
+  hipLaunchKernelGGL(k_symv_resid_dd_reduce, dim3((maxM + 255) / 256, nsys), dim3(256), 0, s, sd);
+  CQM_HIP(hipGetLastError());
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_symv_reduce_desc(const SysDesc* __restrict__ sd, int which,
                                                           int j) {

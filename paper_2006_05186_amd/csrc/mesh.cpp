@@ -305,9 +305,10 @@ size_t state_layout(const Problem& p, SolveState& st) {
   st.sysd = take(sizeof(double) * 8 * Fs);
   st.sysi = take(sizeof(int) * kSysiStride * Fs);
   st.part = take(sizeof(double) * Fs * ((M + kArnRows - 1) / kArnRows) * (4 * (m + 1) + 2));
-  // tile partial sums of stored-operator products (sized for FP64)
+  // tile partial sums of stored-operator products (sized for the
+  // double-double residual: (hi, lo) pairs of FP64 complex values)
   const bool stored = !mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE;
-  st.sym = stored ? take(sizeof(cf64) * Fs * sym_partials((int)M)) : 0;
+  st.sym = stored ? take(2 * sizeof(cf64) * Fs * sym_partials((int)M)) : 0;
   st.scratch = take(4096);
   st.total = off;
   return off;
