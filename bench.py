@@ -282,17 +282,17 @@ def run_compressed(C, torch, ctx, only=None):
 def run_batch48(C, torch, ctx, sample=4):
     """Uneven batch: 48 seeded problems (spheres/ellipsoids of 80..5120
     triangles, N in {16,32,64,128}, random direction and pulse width) solved
-    by one cqm_solve_batch call; dense stored operators up to 1280 triangles,
-    matrix-free products for 5120.  The first `sample` problems of at most
-    320 triangles are compared with the oracle."""
+    by one cqm_solve_batch call, every problem in the stored form (about
+    130 GB of operators, assembled by one work-queue launch).  The first
+    `sample` problems of at most 320 triangles are compared with the
+    oracle."""
     import oracle as O
     from paper_2006_05186_amd.solver import Problem, solve_batch
     mix = W.problem_mix(48)
     probs = []
     for w in mix:
         V, T = w.mesh()
-        form = C.CQM_FORM_DENSE if len(T) <= 1280 else C.CQM_FORM_MATRIX_FREE
-        p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=form)
+        p = Problem(ctx, V, T, w.N, w.T, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
         p.set_plane_wave(w.wave.direction, w.wave.sigma, w.wave.t0)
         probs.append(p)
     solve_batch(probs)  # warm-up (kernels, descriptor buffers)
@@ -573,7 +573,8 @@ def main():
     ap.add_argument("--alu-probe", action="store_true",
                     help="only measure the lane-op rates of v_exp_f32, v_sin_f32, v_cos_f32, "
                          "v_rsq_f32 and FP32/FP64 FMA (lib/libcqm_probe.so) and exit")
-    ap.add_argument("--part", choices=["far32", "compressed", "h2apply", "marching", "study"],
+    ap.add_argument("--part", choices=["far32", "compressed", "h2apply", "marching", "study",
+                                       "batch48"],
                     help="only run one piece on the workload (for counter profiles) and print "
                          "its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -610,6 +611,8 @@ def main():
             rec = far32_probe(C, torch, ctx, wl)
         elif args.part == "h2apply":
             rec = h2_apply_probe(C, torch, ctx, wl)
+        elif args.part == "batch48":
+            rec = run_batch48(C, torch, ctx)
         elif args.part == "study":
             rec = run_study(C, torch, ctx)
         elif args.part == "compressed":

@@ -160,6 +160,9 @@ int cqm_ctx_destroy(cqm_ctx_t ctx) {
   if (!ctx) return CQM_OK;
   (void)hipSetDevice(ctx->device);
   release_engine_bufs(ctx->eb);
+  if (ctx->asm_jobs) (void)hipFree(ctx->asm_jobs);
+  if (ctx->asm_stage) (void)hipHostFree(ctx->asm_stage);
+  if (ctx->asm_counter) (void)hipFree(ctx->asm_counter);
   delete ctx;
   return CQM_OK;
 }

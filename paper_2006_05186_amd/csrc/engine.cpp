@@ -107,8 +107,24 @@ static void diag_block_inverses(Problem& p, const cf64* nv, hipStream_t s) {
   else launch_block_inverse<double>(dg, (int)p.M, p.Fsys, true, wsp<cf64>(p, p.lay.pinv), s);
 }
 
+// Block-Jacobi inverses of an assembled stored operator, and its ready flag.
+static void finish_dense(Problem& p, hipStream_t s) {
+  if (p.lay.pinv) {
+    cf64* d64 = wsp<cf64>(p, p.lay.dense64);
+    Timed t(p, CQM_K_OTHER, s);
+    if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(d64, (int)p.M, p.Fsys, false, wsp<cf32>(p, p.lay.pinv), s);
+    else launch_block_inverse<double>(d64, (int)p.M, p.Fsys, false, wsp<cf64>(p, p.lay.pinv), s);
+  }
+  p.dense_ready = true;
+}
+
 // Near field and (dense form) the assembled operator, or the compressed one.
-void prepare_operator(Problem& p, hipStream_t s) {
+// With defer_dense, a stored-form operator that needs assembling is left to
+// the caller (returns true: assemble, then finish_dense).
+static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense);
+void prepare_operator(Problem& p, hipStream_t s) { prepare_operator_impl(p, s, false); }
+
+static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense) {
   require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
   if (!p.static_ready) {
     Timed t(p, CQM_K_NEAR, s);
@@ -131,10 +147,10 @@ void prepare_operator(Problem& p, hipStream_t s) {
       }
     }
     p.near_ready = true;
-    return;
+    return false;
   }
   const bool have = p.near_ready && (p.opt.form != CQM_FORM_DENSE || p.dense_ready);
-  if (have && p.opt.reuse_operator) return;
+  if (have && p.opt.reuse_operator) return false;
   cf64* nv = wsp<cf64>(p, p.lay.near_val);
   {
     Timed t(p, CQM_K_NEAR, s);
@@ -143,19 +159,46 @@ void prepare_operator(Problem& p, hipStream_t s) {
   p.near_ready = true;
   if (p.opt.form == CQM_FORM_MATRIX_FREE && p.lay.pinv) diag_block_inverses(p, nv, s);
   if (p.opt.form == CQM_FORM_DENSE) {
+    p.dense_ready = false;
+    if (defer_dense) return true;
     cf64* d64 = wsp<cf64>(p, p.lay.dense64);
     cf32* d32 = p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr;
     {
       Timed t(p, CQM_K_ASSEMBLE, s);
       launch_dense_assemble(p, d64, d32, nv, p.timer.ctr(CQM_K_ASSEMBLE), s);
     }
-    if (p.lay.pinv) {
-      Timed t(p, CQM_K_OTHER, s);
-      if (mode_is_mixed(p.opt.mode)) launch_block_inverse<float>(d64, (int)p.M, p.Fsys, false, wsp<cf32>(p, p.lay.pinv), s);
-      else launch_block_inverse<double>(d64, (int)p.M, p.Fsys, false, wsp<cf64>(p, p.lay.pinv), s);
-    }
-    p.dense_ready = true;
+    finish_dense(p, s);
   }
+  return false;
+}
+
+// Operators of a batch: near fields per problem, then every stored operator
+// that needs assembling in one work-queue launch, then their block inverses.
+static void prepare_batch(std::vector<SolveState*>& G, hipStream_t s) {
+  std::vector<Problem*> ps;
+  std::vector<cf64*> d64;
+  std::vector<cf32*> d32;
+  std::vector<const cf64*> nv;
+  for (SolveState* st : G) {
+    Problem& p = *st->p;
+    CQM_HIP(hipSetDevice(p.ctx->device));
+    require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
+            "workspace missing or smaller than cqm_workspace_size");
+    if (std::find(ps.begin(), ps.end(), &p) != ps.end()) continue;
+    if (prepare_operator_impl(p, s, true)) {
+      ps.push_back(&p);
+      d64.push_back(wsp<cf64>(p, p.lay.dense64));
+      d32.push_back(p.lay.dense32 ? wsp<cf32>(p, p.lay.dense32) : nullptr);
+      nv.push_back(wsp<cf64>(p, p.lay.near_val));
+    }
+  }
+  if (ps.empty()) return;
+  Problem& p0 = *G[0]->p;
+  {
+    Timed t(p0, CQM_K_ASSEMBLE, s);
+    launch_dense_assemble_batch(ps, d64, d32, nv, p0.timer.ctr(CQM_K_ASSEMBLE), s);
+  }
+  for (Problem* p : ps) finish_dense(*p, s);
 }
 
 // Operator (optionally), right-hand side and forward transform of one state.
@@ -601,6 +644,16 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   }
   const int open = count(0);
   if (open == 0) return 0;
+  // the residual that closes this cycle is formed in double-double
+  // arithmetic, except the first one of an FP32 inner iteration (about 2e-7
+  // of the right-hand side: FP64 rounding of V x is far below it, and the
+  // next cycle corrects from a double-double residual); FP64 inner cycles
+  // reach 1e-8 in one cycle and the refinement may close after the next
+  bool resid_dd = sizeof(R) == 8;
+  for (int k = 0; k < n; ++k)
+    if (flags_[(size_t)kSysiStride * k] &&
+        !(eb.status_norms[3 * k + 1] > 1e-6 * eb.status_norms[3 * k]))
+      resid_dd = true;
   // systems open now are the ones whose cycle runs (and whose residual is
   // formed at its end)
   upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
@@ -643,13 +696,16 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     launch_cycle_finish<R>(sd, n, maxM_, s);
   }
   if (!lite_.empty()) {
-    // residuals of the systems that ran this cycle (the list from its start),
-    // in double-double arithmetic
+    // residuals of the systems that ran this cycle (the list from its start)
     Timed t(p0, CQM_K_GEMV64, s);
-    for (const GClass& c : cyc_cls_)
-      launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
-                             p0.timer.ctr(CQM_K_GEMV64), s);
-    if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
+    if (resid_dd) {
+      for (const GClass& c : cyc_cls_)
+        launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
+                               p0.timer.ctr(CQM_K_GEMV64), s);
+      if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
+    } else {
+      dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
+    }
   }
   bool other_forms = false;  // stored-form residuals are complete already
   for (SolveState* st : S_) {
@@ -736,7 +792,22 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s) {
               "batched stored-operator problems must share the preconditioner");
       pre = pk;
     }
-    for (SolveState* st : G) pre_solve(*st, s, true, true);
+    if (G.size() > 1) {
+      // several problems: one work-queue launch assembles their stored
+      // operators; the setup events of each bracket the whole batch setup
+      for (SolveState* st : G)
+        for (hipEvent_t& e : st->p->setup_ev)
+          if (!e) CQM_HIP(hipEventCreate(&e));
+      for (SolveState* st : G) CQM_HIP(hipEventRecord(st->p->setup_ev[0], s));
+      prepare_batch(G, s);
+      for (SolveState* st : G) CQM_HIP(hipEventRecord(st->p->setup_ev[1], s));
+      for (SolveState* st : G) {
+        pre_solve(*st, s, false);
+        st->diag.t_setup_ms = -1.0;  // pending: read from the events after the solve
+      }
+    } else {
+      for (SolveState* st : G) pre_solve(*st, s, true, true);
+    }
     auto t1 = std::chrono::steady_clock::now();
     // a problem's own solve keeps its engine (buffers, captured graphs)
     std::unique_ptr<Engine> local;

@@ -169,11 +169,35 @@ struct Tuner {
   std::map<uint64_t, int> assemble;  // (M, systems) -> frequency tile
 };
 
+// One problem of a work-queue assembly launch (k_far.hip): its tables and
+// outputs, cut-off exponents, and its items [item0, item0 + tiles nft).
+struct AsmJob {
+  const double4* pts;
+  const int4* vid;
+  const double* ea;
+  const double* pb;
+  cf64* d64;
+  cf32* d32;
+  const int32_t* nrp;
+  const int32_t* ncol;
+  const cf64* nval;
+  const double* sbox;
+  int64_t nnz;
+  long long item0;
+  int M, nsys, nft, pad;
+  double Lin, Lout;
+};
+
 struct Ctx {
   int device = 0;
   int cus = 256;  // compute units of the device
   EngineBufs eb;
   Tuner tune;
+  // work-queue assembly: job table and item counter (grow-only)
+  AsmJob* asm_jobs = nullptr;
+  AsmJob* asm_stage = nullptr;  // pinned host copy the table is uploaded from
+  size_t asm_cap = 0;
+  unsigned long long* asm_counter = nullptr;
 };
 
 // Device tables of one mesh (owned by the problem, uploaded at create).
@@ -390,6 +414,12 @@ void launch_block_inverse(const cf64* d64, int M, int nsys, bool compact, cplx<R
 // the diagonal kSymB-blocks of every V(s_l), FP64, compact [l][block][row][col]
 // (block-Jacobi preconditioner of the matrix-free form; k_far.hip)
 void launch_diag_blocks(const Problem& p, cf64* d, const cf64* nv, hipStream_t s);
+// the stored operators of several problems (same context) in one persistent
+// work-queue launch; each problem's d64 / d32 / near values as in
+// launch_dense_assemble
+void launch_dense_assemble_batch(const std::vector<Problem*>& ps, const std::vector<cf64*>& d64,
+                                 const std::vector<cf32*>& d32, const std::vector<const cf64*>& nv,
+                                 unsigned long long* ctr, hipStream_t s);
 template <typename R>
 void launch_block_apply(const SysDesc* sd, int n, int maxM, int j, hipStream_t s);
 inline int64_t block_inverse_elems(int M) { return (int64_t)sym_blocks(M) * kSymB * kSymB; }

@@ -264,45 +264,43 @@ constexpr int kAt = 16;
 // block), both triangles, FP64, into a compact array of full blocks
 // [frequency][block][kSymB x kSymB] (the block-Jacobi preconditioner of the
 // matrix-free form).
+// One work item of the assembly: tile pair kk of the 16 x 16 tiling (in the
+// diagonal mode: block kk / 10, pair kk % 10) and frequency tile ft.  stab:
+// the FP64 exp/sincos tables in LDS (staged by the caller); spt: LDS for the
+// tile's source points.
 template <int FT, bool kClamp, bool kDiag>
-__global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(const double4* __restrict__ pts,
-                                                              const int4* __restrict__ vid, int M,
-                                                              const double* __restrict__ ea,
-                                                              const double* __restrict__ pb,
-                                                              int nsys, cf64* __restrict__ d64,
-                                                              cf32* __restrict__ d32,
-                                                              unsigned long long* ctr,
-                                                              const double* __restrict__ ftab,
-                                                              const int32_t* __restrict__ nrp,
-                                                              const int32_t* __restrict__ ncol,
-                                                              const cf64* __restrict__ nval,
-                                                              int64_t nnz,
-                                                              const double* __restrict__ sbox,
-                                                              double Lin, double Lout) {
+__device__ __forceinline__ void assemble_tile(long long kk_in, int ft, const double4* __restrict__ pts,
+                                              const int4* __restrict__ vid, int M,
+                                              const double* __restrict__ ea,
+                                              const double* __restrict__ pb, int nsys,
+                                              cf64* __restrict__ d64, cf32* __restrict__ d32,
+                                              unsigned long long* ctr,
+                                              const int32_t* __restrict__ nrp,
+                                              const int32_t* __restrict__ ncol,
+                                              const cf64* __restrict__ nval, int64_t nnz,
+                                              const double* __restrict__ sbox, double Lin,
+                                              double Lout, const double* stab,
+                                              double4 (*spt)[kQ]) {
   // tile pair (I, J), I <= J, from the linear index k = J (J+1)/2 + I (in
   // the diagonal mode, within block blockIdx.x / 10)
   constexpr int kSub = kSymB / kAt;
-  const long long kk = kDiag ? blockIdx.x % (kSub * (kSub + 1) / 2) : blockIdx.x;
+  const long long kk = kDiag ? kk_in % (kSub * (kSub + 1) / 2) : kk_in;
   long long J = (long long)((sqrt(8.0 * (double)kk + 1.0) - 1.0) * 0.5);
   while (J * (J + 1) / 2 > kk) --J;
   while ((J + 1) * (J + 2) / 2 <= kk) ++J;
   int I = (int)(kk - J * (J + 1) / 2);
   if (kDiag) {
-    const int Bk = blockIdx.x / (kSub * (kSub + 1) / 2);
+    const int Bk = (int)(kk_in / (kSub * (kSub + 1) / 2));
     I += Bk * kSub;
     J += Bk * kSub;
   }
   const int tx = threadIdx.x % kAt, ty = threadIdx.x / kAt;
   const int i = I * kAt + ty, j = (int)J * kAt + tx;
-  const int l0 = blockIdx.y * FT;
+  const int l0 = ft * FT;
   const int nl = min(FT, nsys - l0);
-  // exponential table, then the 512-entry sine/cosine table
-  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
   // quadrature points of the tile's kAt source triangles (shared by the
   // threads of one column), staged once instead of held in registers
-  __shared__ double4 spt[kAt][kQ];
-  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kAt * kAt)
-    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
+  __syncthreads();  // the previous item's reads of spt are done
   if (threadIdx.x < kAt * kQ) {
     const int jt = (int)J * kAt + threadIdx.x / kQ;
     spt[threadIdx.x / kQ][threadIdx.x % kQ] =
@@ -425,6 +423,54 @@ __global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(c
       d64[base + om] = cf64{re, im};
       if (d32) d32[base + om] = v32;
     }
+  }
+}
+
+
+// Grid form: one workgroup per (tile pair, frequency tile).
+template <int FT, bool kClamp, bool kDiag>
+__global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble(
+    const double4* __restrict__ pts, const int4* __restrict__ vid, int M,
+    const double* __restrict__ ea, const double* __restrict__ pb, int nsys, cf64* __restrict__ d64,
+    cf32* __restrict__ d32, unsigned long long* ctr, const double* __restrict__ ftab,
+    const int32_t* __restrict__ nrp, const int32_t* __restrict__ ncol, const cf64* __restrict__ nval,
+    int64_t nnz, const double* __restrict__ sbox, double Lin, double Lout) {
+  // exponential table, then the 512-entry sine/cosine table
+  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
+  __shared__ double4 spt[kAt][kQ];
+  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kAt * kAt)
+    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
+  assemble_tile<FT, kClamp, kDiag>(blockIdx.x, blockIdx.y, pts, vid, M, ea, pb, nsys, d64, d32, ctr,
+                                   nrp, ncol, nval, nnz, sbox, Lin, Lout, stab, spt);
+}
+
+// Work-queue form (uneven batches): a persistent grid whose workgroups claim
+// (problem, tile pair, frequency tile) items from one atomic counter until
+// the items run out; they never wait on one another.  Items of problem k
+// are [item0_k, item0_k + tiles_k nft_k), frequency tiles of one tile pair
+// adjacent.
+template <int FT, bool kClamp>
+__global__ __launch_bounds__(kAt * kAt, FT <= 9 ? 6 : 5) void k_dense_assemble_queue(
+    const AsmJob* __restrict__ jobs, int njobs, long long total, unsigned long long* counter,
+    const double* __restrict__ ftab, unsigned long long* ctr) {
+  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
+  __shared__ double4 spt[kAt][kQ];
+  __shared__ long long item_s;
+  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kAt * kAt)
+    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
+  int jb = 0;  // claimed items only grow, so the job index only moves forward
+  for (;;) {
+    __syncthreads();  // item_s of the previous round has been read by all
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long item = item_s;
+    if (item >= total) break;
+    while (jb + 1 < njobs && jobs[jb + 1].item0 <= item) ++jb;
+    const AsmJob& A = jobs[jb];
+    const long long local = item - A.item0;
+    assemble_tile<FT, kClamp, false>(local / A.nft, (int)(local % A.nft), A.pts, A.vid, A.M, A.ea,
+                                     A.pb, A.nsys, A.d64, A.d32, ctr, A.nrp, A.ncol, A.nval, A.nnz,
+                                     A.sbox, A.Lin, A.Lout, stab, spt);
   }
 }
 
@@ -756,6 +802,89 @@ void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* n
     tn.assemble[key] = FT;
   }
   run(FT, ctr);
+}
+
+void launch_dense_assemble_batch(const std::vector<Problem*>& ps, const std::vector<cf64*>& d64,
+                                 const std::vector<cf32*>& d32, const std::vector<const cf64*>& nv,
+                                 unsigned long long* ctr, hipStream_t s) {
+  if (ps.empty()) return;
+  Ctx& ctx = *ps[0]->ctx;
+  // one frequency tile for the batch: the fewest padding slots summed over
+  // the problems (11 | 33, 13 | 65, 9 | 9); the exponential clamp if any
+  // problem needs it
+  const int opts[3] = {13, 11, 9};
+  int FT = 13;
+  long long waste = -1;
+  for (int f : opts) {
+    long long w = 0;
+    for (Problem* p : ps) w += ((p->Fsys + f - 1) / f) * f - p->Fsys;
+    if (waste < 0 || w < waste) waste = w, FT = f;
+  }
+  bool clamp = false;
+  std::vector<AsmJob> jobs;
+  long long item = 0;
+  for (size_t k = 0; k < ps.size(); ++k) {
+    const Problem& p = *ps[k];
+    const int M = (int)p.M, nt = (M + kAt - 1) / kAt;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (size_t v = 0; v < p.verts.size() / 3; ++v)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], p.verts[3 * v + d]);
+        hi[d] = std::max(hi[d], p.verts[3 * v + d]);
+      }
+    double diag = 0.0, sr = 0.0;
+    for (int d = 0; d < 3; ++d) diag += (hi[d] - lo[d]) * (hi[d] - lo[d]);
+    for (int l = 0; l < p.Fsys; ++l) sr = std::max(sr, p.s_re[l]);
+    clamp |= !(sr * std::sqrt(diag) <= 700.0);
+    AsmJob A{};
+    A.pts = p.dev.pts64;
+    A.vid = p.dev.vid;
+    A.ea = p.dev.ea64u;
+    A.pb = p.dev.pb64u;
+    A.d64 = d64[k];
+    A.d32 = d32[k];
+    A.nrp = p.dev.near_rowptr;
+    A.ncol = p.dev.near_col;
+    A.nval = nv[k];
+    A.sbox = p.dev.sub_box;
+    A.nnz = (int64_t)p.col.size();
+    A.item0 = item;
+    A.M = M;
+    A.nsys = p.Fsys;
+    A.nft = (p.Fsys + FT - 1) / FT;
+    A.Lin = p.opt.cutoff_inner > 0 ? p.opt.cutoff_inner : HUGE_VAL;
+    A.Lout = p.opt.cutoff_outer > 0 ? p.opt.cutoff_outer : HUGE_VAL;
+    jobs.push_back(A);
+    item += (long long)nt * (nt + 1) / 2 * A.nft;
+  }
+  if (jobs.size() > ctx.asm_cap) {
+    // the previous table's upload was ordered before any earlier solve
+    // finished; the stream is idle between the library's solve calls
+    CQM_HIP(hipStreamSynchronize(s));
+    if (ctx.asm_jobs) CQM_HIP(hipFree(ctx.asm_jobs));
+    if (ctx.asm_stage) CQM_HIP(hipHostFree(ctx.asm_stage));
+    ctx.asm_jobs = nullptr;
+    ctx.asm_stage = nullptr;
+    CQM_HIP(hipMalloc(&ctx.asm_jobs, sizeof(AsmJob) * jobs.size()));
+    CQM_HIP(hipHostMalloc((void**)&ctx.asm_stage, sizeof(AsmJob) * jobs.size(), hipHostMallocDefault));
+    ctx.asm_cap = jobs.size();
+  }
+  if (!ctx.asm_counter) CQM_HIP(hipMalloc(&ctx.asm_counter, sizeof(unsigned long long)));
+  std::copy(jobs.begin(), jobs.end(), ctx.asm_stage);
+  CQM_HIP(hipMemcpyAsync(ctx.asm_jobs, ctx.asm_stage, sizeof(AsmJob) * jobs.size(),
+                         hipMemcpyHostToDevice, s));
+  CQM_HIP(hipMemsetAsync(ctx.asm_counter, 0, sizeof(unsigned long long), s));
+  // persistent grid: as many workgroups as the occupancy hint keeps resident
+  const int wgs = ctx.cus * (FT <= 9 ? 6 : 5);
+  const double* ftab = ps[0]->dev.ftab;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(wgs), dim3(kAt * kAt), 0, s, ctx.asm_jobs, (int)jobs.size(),
+                       item, ctx.asm_counter, ftab, ctr);
+  };
+  if (FT == 13) clamp ? go(k_dense_assemble_queue<13, true>) : go(k_dense_assemble_queue<13, false>);
+  else if (FT == 11) clamp ? go(k_dense_assemble_queue<11, true>) : go(k_dense_assemble_queue<11, false>);
+  else clamp ? go(k_dense_assemble_queue<9, true>) : go(k_dense_assemble_queue<9, false>);
+  CQM_HIP(hipGetLastError());
 }
 
 void launch_diag_blocks(const Problem& p, cf64* d, const cf64* nv, hipStream_t s) {

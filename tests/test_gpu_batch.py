@@ -99,3 +99,28 @@ def test_batch_rejects_mixed_preconditioning(ctx):
         assert rc == C.CQM_OK and d.converged == 1
     a.close()
     b.close()
+
+
+def test_batch_work_queue_assembly_equals_single_assembly(ctx):
+    # a batch assembles its stored operators in one work-queue launch
+    # (workgroups claim (problem, tile pair, frequency tile) items); the
+    # entries must be exactly those of each problem's own assembly
+    say("work-queue assembly vs single assembly")
+    specs = [(W.icosphere(2), 16, 2.0), (W.ellipsoid(1, (1.3, 0.7, 1.0)), 8, 2.0),
+             (W.icosphere(3), 32, 4.0)]
+    probs = []
+    for (V, T), N, Tend in specs:
+        p = Problem(ctx, V, T, N, Tend, mode=C.CQM_FP64_PLAIN, form=C.CQM_FORM_DENSE)
+        p.set_plane_wave()
+        probs.append(p)
+    res, rc = solve_batch(probs)
+    assert rc == C.CQM_OK
+    for ((V, T), N, Tend), p in zip(specs, probs):
+        H = N // 2 + 1
+        x = torch.as_tensor(W.random_complex((H, len(T)), seed=17), device="cuda")
+        y_batch = p.apply(x, 0, 64).cpu().numpy()
+        q = Problem(ctx, V, T, N, Tend, mode=C.CQM_FP64_PLAIN, form=C.CQM_FORM_DENSE)
+        y_alone = q.apply(x, 0, 64).cpu().numpy()
+        assert np.array_equal(y_batch, y_alone), (len(T), N)
+        q.close()
+        p.close()
