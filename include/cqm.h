@@ -138,6 +138,16 @@ typedef struct cqm_options {
                             refinement residuals); 45 leaves out entries
                             below 3e-20 of the kernel scale, far under FP64
                             rounding; 0 = off                         (45) */
+  int32_t refine_plain;  /* compressed modes: nonzero forms every FP64
+                            refinement residual with the plain operator
+                            (the FP64 matrix-free product of Section 3.2's
+                            Galerkin entries plus the near-field values),
+                            so the answer is the plain method's to
+                            outer_tol and the compressed operator only
+                            carries the inner iterations; 0 forms it with
+                            the compressed operator, whose approximation
+                            error (Section 6.1: m, eta, eps_aca) then
+                            stays in the answer                        (1) */
 } cqm_options;
 
 /* Inner preconditioners (cqm_options.precond). */
@@ -371,7 +381,12 @@ typedef struct cqm_server_opts {
   int32_t fail_after_cycles; /* failure-path test hook: > 0 makes lane 0's
                               worker stop with CQM_EDEVICE after that many
                               restart cycles, as after a device error     (0) */
-  int32_t reserved[4];
+  int32_t large_cu_percent; /* share of the compute units the large lane's
+                              stream may use (a CU mask spread evenly over
+                              the chip), so the first lane always keeps the
+                              rest; 0 or >= 100: no mask.  If the runtime
+                              refuses the mask the stream is unmasked   (50) */
+  int32_t reserved[3];
   int64_t large_bytes;     /* size limit of the above; <= 0: budget / 4   (0) */
   cqm_options solver;      /* options of every request (mode, form, tolerances) */
 } cqm_server_opts;

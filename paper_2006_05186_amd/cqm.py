@@ -66,6 +66,7 @@ class cqm_options(ctypes.Structure):
         ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32), ("marching", ctypes.c_int32),
         ("cutoff_inner", ctypes.c_double), ("cutoff_outer", ctypes.c_double),
+        ("refine_plain", ctypes.c_int32),
     ]
 
 
@@ -95,7 +96,7 @@ class cqm_diag(ctypes.Structure):
 class cqm_server_opts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("cache_operators", ctypes.c_int32),
                 ("large_lane", ctypes.c_int32), ("fail_after_cycles", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4),
+                ("large_cu_percent", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
                 ("large_bytes", ctypes.c_int64), ("solver", cqm_options)]
 
 

@@ -70,6 +70,11 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+}  // namespace
+
+int cqm::fail_with(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
 
 template <typename F> int guarded(F&& f) {
   try {
@@ -134,6 +139,7 @@ int cqm_default_options(cqm_options* o) {
   o->precond = CQM_PRECOND_BLOCK_JACOBI;
   o->cutoff_inner = 18.0;
   o->cutoff_outer = 45.0;
+  o->refine_plain = 1;
   return CQM_OK;
 }
 

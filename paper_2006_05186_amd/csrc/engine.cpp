@@ -57,6 +57,27 @@ void cut_entries(Problem& p) {
 }
 }  // namespace
 
+// The plain operator without a stored copy: far-field kernel evaluation on
+// the fly plus the near-field values (Section 3.2).  The matrix-free form's
+// product, and the refinement residual of compressed problems with
+// refine_plain (their partial sums have a buffer of their own, the
+// compressed operator occupying the matrix-free form's).
+template <typename R>
+void apply_plain_free(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y,
+                      int64_t ys, const int* active, hipStream_t s) {
+  const size_t off = mode_is_h2(p.opt.mode) ? p.lay.mfpart : p.lay.partial;
+  require(off != 0 && p.lay.near_val != 0, CQM_EINVAL, "no buffers for the matrix-free product");
+  cplx<R>* partial = wsp<cplx<R>>(p, off);
+  {
+    const int c = sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64;
+    Timed t(p, c, s);
+    launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, p.timer.ctr(c), s);
+  }
+  Timed t(p, CQM_K_NEAR, s);
+  launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, wsp<cf64>(p, p.lay.near_val),
+                            active, s);
+}
+
 template <typename R>
 void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
               const int* active, hipStream_t s) {
@@ -65,30 +86,22 @@ void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R
     h2_apply<R>(p, l0, nsys, x, xs, y, ys, active, s);
     return;
   }
-  const int M = (int)p.M;
-  if (p.opt.form == CQM_FORM_DENSE) {
-    const cplx<R>* V;
-    if constexpr (sizeof(R) == 4) {
-      require(p.lay.dense32 != 0, CQM_EINVAL, "FP32 dense operator exists only in mixed mode");
-      V = wsp<cf32>(p, p.lay.dense32);
-    } else {
-      V = wsp<cf64>(p, p.lay.dense64);
-    }
-    require(p.own.sym != 0, CQM_EINVAL, "no partial-sum buffer for the stored operator");
-    Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
-    launch_dense_gemv<R>(V + (int64_t)l0 * sym_slice(M), M, nsys, x, xs, y, ys, active,
-                         p.own.at<cplx<R>>(p.own.sym), s);
-  } else {
-    cplx<R>* partial = wsp<cplx<R>>(p, p.lay.partial);
-    {
-      const int c = sizeof(R) == 4 ? CQM_K_FAR32 : CQM_K_FAR64;
-      Timed t(p, c, s);
-      launch_far_apply<R>(p, l0, nsys, x, xs, partial, active, p.timer.ctr(c), s);
-    }
-    Timed t(p, CQM_K_NEAR, s);
-    launch_far_reduce_near<R>(p, l0, nsys, partial, x, xs, y, ys, wsp<cf64>(p, p.lay.near_val),
-                              active, s);
+  if (p.opt.form != CQM_FORM_DENSE) {
+    apply_plain_free<R>(p, l0, nsys, x, xs, y, ys, active, s);
+    return;
   }
+  const int M = (int)p.M;
+  const cplx<R>* V;
+  if constexpr (sizeof(R) == 4) {
+    require(p.lay.dense32 != 0, CQM_EINVAL, "FP32 dense operator exists only in mixed mode");
+    V = wsp<cf32>(p, p.lay.dense32);
+  } else {
+    V = wsp<cf64>(p, p.lay.dense64);
+  }
+  require(p.own.sym != 0, CQM_EINVAL, "no partial-sum buffer for the stored operator");
+  Timed t(p, sizeof(R) == 4 ? CQM_K_GEMV32 : CQM_K_GEMV64, s);
+  launch_dense_gemv<R>(V + (int64_t)l0 * sym_slice(M), M, nsys, x, xs, y, ys, active,
+                       p.own.at<cplx<R>>(p.own.sym), s);
 }
 template void apply_op<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
 template void apply_op<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);
@@ -137,13 +150,13 @@ static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense) {
         Timed t(p, CQM_K_ASSEMBLE, s);
         h2_prepare(p, s);
       }
-      if (p.lay.pinv) {
+      if (p.lay.near_val) {
         cf64* nv = wsp<cf64>(p, p.lay.near_val);
         {
           Timed t(p, CQM_K_NEAR, s);
           launch_near_values(p, nv, s);
         }
-        diag_block_inverses(p, nv, s);
+        if (p.lay.pinv) diag_block_inverses(p, nv, s);
       }
     }
     p.near_ready = true;
@@ -713,8 +726,12 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     if (dense_form(p)) continue;
     other_forms = true;
     const int M = (int)p.M;
-    apply_op<double>(p, 0, p.Fsys, st->at<cf64>(st->x), M, st->at<cf64>(st->r), M,
-                     st->at<int>(st->sysi), s);
+    if (mode_is_h2(p.opt.mode) && p.opt.refine_plain)
+      apply_plain_free<double>(p, 0, p.Fsys, st->at<cf64>(st->x), M, st->at<cf64>(st->r), M,
+                               st->at<int>(st->sysi), s);
+    else
+      apply_op<double>(p, 0, p.Fsys, st->at<cf64>(st->x), M, st->at<cf64>(st->r), M,
+                       st->at<int>(st->sysi), s);
   }
   if (other_forms) {
     Timed t(p0, CQM_K_OTHER, s);

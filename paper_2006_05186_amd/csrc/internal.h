@@ -242,6 +242,9 @@ inline float cutoff_radius(double L, double re_s) {
 // Offsets (bytes) of the solve workspace.
 struct Layout {
   size_t partial = 0, near_val = 0, dense64 = 0, dense32 = 0, pinv = 0, diag64 = 0, total = 0;
+  // compressed modes with refine_plain: split-K partial sums of the FP64
+  // matrix-free product that forms the refinement residuals
+  size_t mfpart = 0;
   // time marching (cqm_options.marching): weights, What_0 block inverses and
   // their complex staging, product partials, CG vectors and partial sums
   size_t mw = 0, mpinv = 0, mdiag = 0, mpart = 0, mvec = 0;
@@ -357,6 +360,8 @@ void launch_far_reduce_near(const Problem& p, int l0, int nsys, const cplx<R>* p
 // ones (pairs sharing a vertex) copied from the near-field values nv
 void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* nv,
                            unsigned long long* ctr, hipStream_t s);
+// Records msg as the calling thread's cqm_last_error() and returns code.
+int fail_with(int code, const std::string& msg);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
 // Allocation-free far product (matrix-free form): partial sums in the fixed
 // device array of kFarScratchBytes (k_far.hip), whose address is looked up

@@ -576,7 +576,10 @@ uint64_t far_key(int M, int nsys, int precision) {
 // or tuning not possible here) the heuristic.  With `tune`, every candidate
 // is timed once on the real inputs (after one warm-up launch) and the fastest
 // kept; the candidates write only the partial-sum buffer, which the product
-// that follows overwrites.
+// that follows overwrites.  Products above kTuneMaxPairs panel-pair
+// frequencies are not tuned: the 2 x 9 (FP64) or 2 x 15 (FP32) candidate
+// launches would cost
+// seconds there, more than any shape could win back.
 template <typename R>
 FarShape far_shape(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs,
                    cplx<R>* partial, const int* active, bool tune, hipStream_t s) {
@@ -589,7 +592,8 @@ FarShape far_shape(const Problem& p, int l0, int nsys, const cplx<R>* x, int64_t
     if (it != tn.far.end()) return it->second;
   }
   FarShape best{pick_ft<R>(nsys), 4096};
-  if (!tune || !p.opt.autotune) return best;
+  constexpr double kTuneMaxPairs = 4e9;  // the 5120-triangle sphere, 129 frequencies
+  if (!tune || !p.opt.autotune || (double)p.M * (double)p.M * nsys > kTuneMaxPairs) return best;
   hipEvent_t e0, e1;
   CQM_HIP(hipEventCreate(&e0));
   CQM_HIP(hipEventCreate(&e1));

@@ -328,13 +328,24 @@ void compute_layout(Problem& p) {
   off = state_layout(p, p.own);
   if (mode_is_h2(p.opt.mode)) {
     L.partial = take(h2_workspace_bytes(p));
-    if (p.opt.precond == CQM_PRECOND_BLOCK_JACOBI) {
-      // block-Jacobi from the plain operator's diagonal blocks: near values,
-      // the blocks (FP64, compact) and their inverses
+    const bool bj = p.opt.precond == CQM_PRECOND_BLOCK_JACOBI;
+    // block-Jacobi and the plain refinement residual both need the plain
+    // operator's near-field values
+    if (bj || p.opt.refine_plain)
       L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
+    if (bj) {
+      // block-Jacobi from the plain operator's diagonal blocks (FP64,
+      // compact) and their inverses
       L.diag64 = take(sizeof(cf64) * Fs * block_inverse_elems((int)M));
       L.pinv = take((mode_is_mixed(p.opt.mode) ? sizeof(cf32) : sizeof(cf64)) * Fs *
                     block_inverse_elems((int)M));
+    }
+    if (p.opt.refine_plain) {
+      // partial sums of the FP64 matrix-free product (every system at once)
+      size_t worst = 0;
+      for (int nl = 1; nl <= (int)Fs; ++nl)
+        worst = std::max(worst, (size_t)far_partial_slots((int)M, nl, 64) * nl * sizeof(cf64));
+      L.mfpart = take(worst * M);
     }
   } else {
     L.near_val = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));

@@ -455,13 +455,15 @@ int cqm_server_default_options(cqm_server_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->max_active = 16;
   o->cache_operators = 1;
+  o->large_cu_percent = 50;
   cqm_default_options(&o->solver);
   o->solver.reuse_operator = 1;
   return CQM_OK;
 }
 
 int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* opts, cqm_server_t* out) {
-  if (!ctx || !out || hbm_budget < (1u << 20)) return CQM_EINVAL;
+  if (!ctx || !out || hbm_budget < (1u << 20))
+    return fail_with(CQM_EINVAL, "cqm_server_create: NULL argument or budget under 1 MiB");
   auto* s = new cqm_server_s();
   s->ctx = ctx;
   if (opts) s->opts = *opts;
@@ -474,14 +476,40 @@ int cqm_server_create(cqm_ctx_t ctx, size_t hbm_budget, const cqm_server_opts* o
   bool ok = hipSetDevice(ctx->device) == hipSuccess;
   for (int k = 0; ok && k < s->nlanes; ++k) {
     s->lanes[k].id = k;
-    ok = hipStreamCreateWithFlags(&s->lanes[k].stream, hipStreamNonBlocking) == hipSuccess;
+    const int pct = s->opts.large_cu_percent;
+    if (k == 1 && pct > 0 && pct < 100) {
+      // the large lane's long-running kernels would otherwise fill every CU
+      // and hold the first lane's launches back: confine them to every
+      // k-th CU (an even spread over the chip's dies and shader engines)
+      int cus = 0;
+      ok = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
+           hipSuccess;
+      if (ok && cus > 0) {
+        std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+        const int keep = std::max(1, cus * pct / 100);
+        for (int j = 0; j < keep; ++j) {
+          const int cu = (int)((int64_t)j * cus / keep);
+          mask[cu / 32] |= 1u << (cu % 32);
+        }
+        if (hipExtStreamCreateWithCUMask(&s->lanes[k].stream, (uint32_t)mask.size(),
+                                         mask.data()) == hipSuccess)
+          continue;
+        (void)hipGetLastError();
+      }
+    }
+    ok = ok && hipStreamCreateWithFlags(&s->lanes[k].stream, hipStreamNonBlocking) == hipSuccess;
   }
-  if (ok) ok = hipMalloc(&s->arena_mem, hbm_budget) == hipSuccess;
+  const char* what = ok ? nullptr : "cqm_server_create: device or stream set-up failed";
+  if (ok && hipMalloc(&s->arena_mem, hbm_budget) != hipSuccess) {
+    (void)hipGetLastError();  // clear the sticky allocation error for later checks
+    ok = false;
+    what = "cqm_server_create: the arena (hbm_budget bytes) could not be allocated";
+  }
   if (!ok) {
     for (int k = 0; k < s->nlanes; ++k)
       if (s->lanes[k].stream) (void)hipStreamDestroy(s->lanes[k].stream);
     delete s;
-    return CQM_ENOMEM;
+    return fail_with(CQM_ENOMEM, what);
   }
   s->arena.init(s->arena_mem, hbm_budget);
   for (int k = 0; k < s->nlanes; ++k) {

@@ -116,7 +116,8 @@ def test_large_lane_compressed_beside_plain(ctx):
     """With the large lane on, a request whose stored dense operator exceeds
     the limit is solved in the compressed form on its own stream while the
     others keep streaming on the first lane; every result equals the same
-    request solved alone in its form."""
+    request solved alone in its form, and the large one (refined with the
+    plain operator) equals the plain stored-form solution."""
     small = requests(4, seed=13)
     (VL, TL), NL, TLend = W.icosphere(3), 8, 2.0  # 1280 triangles: over the limit below
     nt = (len(TL) + 63) // 64
@@ -138,8 +139,13 @@ def test_large_lane_compressed_beside_plain(ctx):
     p.close()
     _, _, area = O.triangle_quadrature(VL, TL)
     e = O.rel_error(res[tl][2], qa, area)
-    say(f"  large request vs compressed alone {e:.1e}")
-    assert e < 1e-12
+    p = Problem(ctx, VL, TL, NL, TLend, mode=C.CQM_FP64_PLAIN, form=C.CQM_FORM_DENSE)
+    p.set_plane_wave((0.0, 0.6, 0.8), 0.3, 1.6)
+    qp = p.solve()[0].cpu().numpy()
+    p.close()
+    e_plain = O.rel_error(res[tl][2], qp, area)
+    say(f"  large request vs compressed alone {e:.1e}, vs plain stored form {e_plain:.1e}")
+    assert e < 1e-12 and e_plain < 1e-7
     for t, (V, T, N, Tend, d, s, t0) in zip(ts, small):
         p = Problem(ctx, V, T, N, Tend, mode=C.CQM_MIXED_PLAIN, form=C.CQM_FORM_DENSE)
         p.set_plane_wave(d, s, t0)
