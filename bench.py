@@ -106,9 +106,9 @@ def summarise_kernels(diags):
     return ms, calls
 
 
-def roofline(diags, tag):
-    """Dominant kernel class over the timed steps and where it stands against
-    its roofline.  Durations are the HIP-event times of every launch in the
+def roofline(diags, tag, cls=None):
+    """Dominant kernel class (or class `cls`) over the timed steps and where
+    it stands against its roofline.  Durations are the HIP-event times of every launch in the
     timed steps (recorded on the solve stream); the algorithmic work is what
     the kernels counted themselves: kernel values for the evaluation kernels
     (x FLOPS_PER_UNIT), bytes for the bandwidth-bound products and the
@@ -117,13 +117,16 @@ def roofline(diags, tag):
     work = np.zeros(len(KCLS))
     for d in diags:
         work += np.asarray(d["kernel_work"])
-    k = int(np.argmax(ms))
+    k = int(np.argmax(ms)) if cls is None else KCLS.index(cls)
     name = KCLS[k]
     n = max(int(calls[k]), 1)
     avg_ms = ms[k] / n
     out = {"kernel": name, "avg_launch_ms": avg_ms, "launches": int(calls[k]),
            "share_of_kernel_time": float(ms[k] / ms.sum()),
            "work_per_launch": work[k] / n}
+    if not (avg_ms > 0 and work[k] > 0):
+        return out | {"bound": None, "achieved": None, "peak": None, "unit": None,
+                      "frac": None, "traffic": None}
     if name in ("far32", "far64", "assemble"):
         ach = work[k] / n * FLOPS_PER_UNIT / (avg_ms * 1e-3) / 1e12
         peak = VENDOR_PEAK_TFLOPS[name]
@@ -682,6 +685,10 @@ def main():
                    "t_setup_ms": d0["t_setup_ms"], "t_solve_ms": d0["t_solve_ms"],
                    "workspace_GB": r["workspace"] / 1e9},
         "kernel_ms_per_step": dict(zip(KCLS, (summarise_kernels(rp["diags"])[0] / KP).round(4).tolist())),
+        # every class with GPU time against its own roofline
+        "rooflines": {c: {k: v for k, v in roofline(rp["diags"], tag_of(wl), c).items()
+                          if k not in ("kernel", "share_of_kernel_time")}
+                      for c in ("assemble", "gemv32", "gemv64", "arnoldi")},
     }
     ref = golden_q(wl)
     if ref is not None:
