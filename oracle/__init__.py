@@ -14,4 +14,5 @@ blocking or reordering beyond what the definitions state.
 from .cqm import *  # noqa: F401,F403
 from .compress import *  # noqa: F401,F403
 from .marching import *  # noqa: F401,F403
+from . import calderon  # noqa: F401
 from . import marching  # noqa: F401

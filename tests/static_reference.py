@@ -70,3 +70,24 @@ def static_reference(Ti, Tj, rtol=1e-11):
     f = lambda X: triangle_potential(X, *Tj)
     whole = _est(f, *Ti)
     return _adapt(f, *Ti, whole, rtol * abs(whole), 0) / (4.0 * math.pi)
+
+
+def solid_angle(P, A, B, C):
+    """Signed solid angle int_T (y - P).n / |y - P|^3 dS(y) of the flat triangle
+    T = (A,B,C) (n = (B-A) x (C-A) normalised) seen from points P (n,3): the
+    closed form of Van Oosterom and Strackee (IEEE TBME 1983)."""
+    P = np.atleast_2d(P)
+    R1, R2, R3 = A[None] - P, B[None] - P, C[None] - P
+    r1, r2, r3 = (np.linalg.norm(R, axis=1) for R in (R1, R2, R3))
+    num = np.einsum("ij,ij->i", R1, np.cross(R2, R3))
+    den = (r1 * r2 * r3 + np.einsum("ij,ij->i", R1, R2) * r3 + np.einsum("ij,ij->i", R1, R3) * r2
+           + np.einsum("ij,ij->i", R2, R3) * r1)
+    return 2.0 * np.arctan2(num, den)
+
+
+def double_layer_reference(Ti, Tj, rtol=1e-11):
+    """int_{Ti} int_{Tj} (x - y).n_j / (4 pi |x - y|^3) = int_{Ti} -Omega_j(x) / (4 pi):
+    the solid angle of Tj in closed form, the outer integral adaptive."""
+    f = lambda X: solid_angle(X, *Tj)
+    whole = _est(f, *Ti)
+    return -_adapt(f, *Ti, whole, rtol * max(abs(whole), 1e-300), 0) / (4.0 * math.pi)
