@@ -148,7 +148,19 @@ typedef struct cqm_options {
                             the compressed operator, whose approximation
                             error (Section 6.1: m, eta, eps_aca) then
                             stays in the answer                        (1) */
+  int32_t formulation;   /* CQM_FORMULATION_*: the boundary integral
+                            equation solved                     (INDIRECT) */
 } cqm_options;
+
+/* Formulations (cqm_options.formulation).  INDIRECT: V phi = g_D, phi a
+   single-layer density (q_out is phi).  DIRECT: the Galerkin equation of
+   Section 2.2 (eq. wavegalform) for a Dirichlet boundary, V q =
+   (-1/2 I + K) g_D with K the double-layer operator (eq. wavebio), q_out the
+   Neumann datum; g_D is represented by its L2 projection onto piecewise
+   constants (the paper uses piecewise linears), K is applied once per solve
+   (FP64, matrix-free).  The marching solve takes INDIRECT only. */
+#define CQM_FORMULATION_INDIRECT 0
+#define CQM_FORMULATION_DIRECT 1
 
 /* Inner preconditioners (cqm_options.precond). */
 #define CQM_PRECOND_NONE 0
@@ -332,6 +344,18 @@ int cqm_frequencies(int32_t N, double T, double rho, double* s_re, double* s_im)
  * workspace. */
 int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
                 const void* x, void* y, hipStream_t stream);
+
+/* y_l = K(s_l) x_l for l = l0 .. l0+nl-1: the piecewise-constant Galerkin
+ * matrices of the double-layer operator of Section 2.2 (eq. wavebio),
+ * K_l[m,i] = <phi_m, K(s_l) phi_i>, kernel d/dn_y exp(-s r)/(4 pi r) with
+ * n_y the unit normal of the source triangle in its vertex order; FP64,
+ * far field matrix-free.  x, y: device complex128 arrays nl x M
+ * (caller-owned, must not overlap).  Needs a problem created with
+ * formulation = CQM_FORMULATION_DIRECT (the workspace holds K's near values
+ * and partial sums), else CQM_EINVAL; CQM_EINVAL for a frequency range
+ * outside the solved band; CQM_ENOMEM without a workspace. */
+int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y,
+                hipStream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, serving
  * loops or harnesses that forbid hipMalloc): cqm_apply_V of the matrix-free

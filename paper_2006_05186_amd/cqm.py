@@ -21,9 +21,8 @@ __all__ = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
-    "cqm_solve_marching",
-    "cqm_solve_marching",
-    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_near_entries",
+    "cqm_solve_marching", "CQM_FORMULATION_INDIRECT", "CQM_FORMULATION_DIRECT",
+    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_apply_K", "cqm_near_entries",
     "cqm_operator_stats",
     "cqm_server_opts", "cqm_request", "cqm_server_stats_t", "cqm_server_default_options",
     "cqm_server_create", "cqm_server_submit", "cqm_server_poll", "cqm_server_drain",
@@ -36,14 +35,15 @@ CQM_FORM_MATRIX_FREE, CQM_FORM_DENSE = 0, 1
 CQM_BAND_FULL, CQM_BAND_HALF = 0, 1
 CQM_ARNOLDI_AUTO, CQM_ARNOLDI_GROUP, CQM_ARNOLDI_SPLIT = 0, 1, 2
 CQM_PRECOND_NONE, CQM_PRECOND_BLOCK_JACOBI = 0, 1
+CQM_FORMULATION_INDIRECT, CQM_FORMULATION_DIRECT = 0, 1
 KERNEL_CLASSES = ["far32", "far64", "assemble", "gemv32", "gemv64", "near", "arnoldi", "other"]
 
 EXPORTED_SYMBOLS = [
     "cqm_last_error", "cqm_default_options", "cqm_ctx_create", "cqm_ctx_destroy",
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
-    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_near_entries",
-    "cqm_operator_stats",
+    "cqm_solve_marching", "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_apply_K",
+    "cqm_near_entries", "cqm_operator_stats",
     "cqm_server_default_options", "cqm_server_create", "cqm_server_submit", "cqm_server_poll",
     "cqm_server_drain", "cqm_server_stats", "cqm_server_destroy",
 ]
@@ -66,7 +66,7 @@ class cqm_options(ctypes.Structure):
         ("arnoldi_layout", ctypes.c_int32), ("autotune", ctypes.c_int32),
         ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32), ("marching", ctypes.c_int32),
         ("cutoff_inner", ctypes.c_double), ("cutoff_outer", ctypes.c_double),
-        ("refine_plain", ctypes.c_int32),
+        ("refine_plain", ctypes.c_int32), ("formulation", ctypes.c_int32),
     ]
 
 
@@ -156,6 +156,7 @@ def load_library():
         "cqm_frequencies": (ctypes.c_int, [I32, D, D, P, P]),
         "cqm_apply_V": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_apply_V_noalloc": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
+        "cqm_apply_K": (ctypes.c_int, [P, I32, I32, P, P, P]),
         "cqm_near_entries": (ctypes.c_int, [P, ctypes.POINTER(I64), P, P, P]),
         "cqm_operator_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_diag)]),
         "cqm_server_default_options": (ctypes.c_int, [ctypes.POINTER(cqm_server_opts)]),
@@ -283,6 +284,11 @@ def cqm_apply_V_noalloc(p, l0, nl, precision, x_ptr, y_ptr, stream=0):
     return _check(load_library().cqm_apply_V_noalloc(p, l0, nl, precision, ctypes.c_void_p(x_ptr),
                                                      ctypes.c_void_p(y_ptr),
                                                      ctypes.c_void_p(stream)))
+
+
+def cqm_apply_K(p, l0, nl, x_ptr, y_ptr, stream=0):
+    return _check(load_library().cqm_apply_K(p, l0, nl, ctypes.c_void_p(x_ptr),
+                                             ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream)))
 
 
 def cqm_near_entries(p, with_static=True):

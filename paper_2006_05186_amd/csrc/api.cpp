@@ -140,6 +140,7 @@ int cqm_default_options(cqm_options* o) {
   o->cutoff_inner = 18.0;
   o->cutoff_outer = 45.0;
   o->refine_plain = 1;
+  o->formulation = CQM_FORMULATION_INDIRECT;
   return CQM_OK;
 }
 
@@ -201,6 +202,8 @@ int cqm_problem_create(cqm_ctx_t ctx, const double* vertices, int64_t nv, const 
     require(o.cutoff_inner >= 0 && o.cutoff_outer >= 0 && std::isfinite(o.cutoff_inner) &&
                 std::isfinite(o.cutoff_outer),
             CQM_EINVAL, "cut-off exponents must be finite and >= 0");
+    require(o.formulation == CQM_FORMULATION_INDIRECT || o.formulation == CQM_FORMULATION_DIRECT,
+            CQM_EINVAL, "unknown formulation");
     for (int64_t k = 0; k < 3 * nv; ++k)
       require(std::isfinite(vertices[k]), CQM_EINVAL, "non-finite vertex coordinate");
     for (int64_t k = 0; k < 3 * M; ++k)
@@ -261,7 +264,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
                   p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea64u, p->dev.pb64u, p->dev.ftab, p->dev.ea32,
-                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box};
+                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box, p->dev.nrm64, p->dev.nearK_static};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -403,6 +406,24 @@ int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision, cons
       apply_op<float>(*p, l0, nl, (const cf32*)x, M, (cf32*)y, M, nullptr, stream);
     else
       apply_op<double>(*p, l0, nl, (const cf64*)x, M, (cf64*)y, M, nullptr, stream);
+    return CQM_OK;
+  });
+}
+
+int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y,
+                hipStream_t stream) {
+  return guarded([&] {
+    require(p && x && y, CQM_EINVAL, "NULL argument");
+    require(p->opt.formulation == CQM_FORMULATION_DIRECT, CQM_EINVAL,
+            "create the problem with formulation = CQM_FORMULATION_DIRECT");
+    require(l0 >= 0 && nl >= 1 && l0 + nl <= p->Fsys, CQM_EINVAL, "frequency range outside the solved band");
+    require(p->ws != nullptr && p->ws_bytes >= p->lay.total, CQM_ENOMEM, "workspace missing");
+    CQM_HIP(hipSetDevice(p->ctx->device));
+    prepare_double_layer(*p, stream);
+    const int M = (int)p->M;
+    launch_apply_K(*p, l0, nl, (const cf64*)x, M, nullptr, 0.0, (cf64*)y, M,
+                   reinterpret_cast<const cf64*>(p->ws + p->lay.nearK),
+                   reinterpret_cast<cf64*>(p->ws + p->lay.kpart), stream);
     return CQM_OK;
   });
 }

@@ -137,8 +137,24 @@ static void finish_dense(Problem& p, hipStream_t s) {
 static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense);
 void prepare_operator(Problem& p, hipStream_t s) { prepare_operator_impl(p, s, false); }
 
+// Near values of the double-layer operator (direct formulation): the static
+// part once per mesh, the per-frequency values once per operator.
+void prepare_double_layer(Problem& p, hipStream_t s) {
+  require(p.lay.nearK != 0, CQM_EINVAL, "no double-layer buffers (formulation is not DIRECT)");
+  Timed t(p, CQM_K_NEAR, s);
+  if (!p.nearK_static_ready) {
+    launch_nearK_static(p, s);
+    p.nearK_static_ready = true;
+  }
+  if (!(p.nearK_ready && p.opt.reuse_operator)) {
+    launch_nearK_values(p, wsp<cf64>(p, p.lay.nearK), s);
+    p.nearK_ready = true;
+  }
+}
+
 static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense) {
   require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
+  if (p.opt.formulation == CQM_FORMULATION_DIRECT) prepare_double_layer(p, s);
   if (!p.static_ready) {
     Timed t(p, CQM_K_NEAR, s);
     launch_near_static(p, s);
@@ -237,9 +253,24 @@ void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed) {
     CQM_HIP(hipStreamSynchronize(s));
     st.diag.t_setup_ms = ms_since(t0);
   }
-  Timed t(p, CQM_K_OTHER, s);
-  launch_rhs(p, st.inc, st.at<double>(st.b), s);
-  launch_dft_forward(p, st.at<double>(st.b), st.at<cf64>(st.ghat), st.at<double>(st.scratch), s);
+  {
+    Timed t(p, CQM_K_OTHER, s);
+    launch_rhs(p, st.inc, st.at<double>(st.b), s);
+    launch_dft_forward(p, st.at<double>(st.b), st.at<cf64>(st.ghat), st.at<double>(st.scratch), s);
+  }
+  if (p.opt.formulation == CQM_FORMULATION_DIRECT) {
+    // direct formulation: ghat_l = -1/2 ghat_l + K_l (ghat_l / area), the
+    // transforms of <phi_i, (-1/2 I + K) g_D> with g_D's piecewise-constant
+    // coefficients b_n / area
+    if (!p.nearK_ready) prepare_double_layer(p, s);
+    const int M = (int)p.M;
+    cf64* g = st.at<cf64>(st.ghat);
+    cf64* c = wsp<cf64>(p, p.lay.kin);
+    Timed t(p, CQM_K_FAR64, s);
+    launch_div_area(p, p.Fsys, g, M, c, s);
+    launch_apply_K(p, 0, p.Fsys, c, M, g, -0.5, g, M, wsp<cf64>(p, p.lay.nearK),
+                   wsp<cf64>(p, p.lay.kpart), s);
+  }
 }
 
 // Inverse transform and operator diagnostics of one state.

@@ -232,6 +232,10 @@ struct MeshDev {
   // tiling, its box lo[3], hi[3]
   float* tile_gap = nullptr;
   double* sub_box = nullptr;
+  // double-layer operator (direct formulation): unit normals of the
+  // triangles (vertex order), the static near part of K (nnz)
+  double4* nrm64 = nullptr;
+  double* nearK_static = nullptr;
 };
 // Frequency-dependent cut-off radii of a system: tiles whose box gap is at
 // least cut32 (inner precision) or cut64 (FP64 operator) are left out.
@@ -245,6 +249,9 @@ struct Layout {
   // compressed modes with refine_plain: split-K partial sums of the FP64
   // matrix-free product that forms the refinement residuals
   size_t mfpart = 0;
+  // direct formulation: near values of K (nnz x Fsys), the coefficient
+  // vectors it is applied to (Fsys x M) and its split-K partial sums
+  size_t nearK = 0, kin = 0, kpart = 0;
   // time marching (cqm_options.marching): weights, What_0 block inverses and
   // their complex staging, product partials, CG vectors and partial sums
   size_t mw = 0, mpinv = 0, mdiag = 0, mpart = 0, mvec = 0;
@@ -317,6 +324,7 @@ struct Problem {
   size_t ws_bytes = 0;
   Layout lay;
   bool static_ready = false, near_ready = false, dense_ready = false;
+  bool nearK_static_ready = false, nearK_ready = false;
   H2Operator* h2 = nullptr;
   cqm_diag last{};
   int64_t far_units = 0;
@@ -362,6 +370,16 @@ void launch_dense_assemble(const Problem& p, cf64* d64, cf32* d32, const cf64* n
                            unsigned long long* ctr, hipStream_t s);
 // Records msg as the calling thread's cqm_last_error() and returns code.
 int fail_with(int code, const std::string& msg);
+// Double-layer operator K(s) (k_dlayer.hip): static near part, near values
+// per frequency, y = alpha z + K x (z may be y; FP64, matrix-free far field),
+// and c = g / area.
+void launch_nearK_static(const Problem& p, hipStream_t s);
+void launch_nearK_values(const Problem& p, cf64* vals, hipStream_t s);
+void launch_apply_K(const Problem& p, int l0, int nsys, const cf64* x, int64_t xs, const cf64* z,
+                    double alpha, cf64* y, int64_t ys, const cf64* nvals, cf64* partial,
+                    hipStream_t s);
+void launch_div_area(const Problem& p, int nsys, const cf64* g, int64_t gs, cf64* c, hipStream_t s);
+size_t dl_partial_bytes(int M, int Fs);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
 // Allocation-free far product (matrix-free form): partial sums in the fixed
 // device array of kFarScratchBytes (k_far.hip), whose address is looked up
@@ -444,6 +462,7 @@ template <typename R>
 void apply_op(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys,
               const int* active, hipStream_t s);
 void prepare_operator(Problem& p, hipStream_t s);
+void prepare_double_layer(Problem& p, hipStream_t s);  // near values of K (direct formulation)
 // timed: measure the setup with the problem's events instead of a stream
 // synchronisation (one caller per problem at a time)
 void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed = false);

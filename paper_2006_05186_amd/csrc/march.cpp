@@ -21,6 +21,8 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
   require(!mode_is_h2(p.opt.mode) && p.opt.form == CQM_FORM_DENSE, CQM_EINVAL,
           "time marching needs the stored plain form (CQM_FORM_DENSE, plain mode)");
+  require(p.opt.formulation == CQM_FORMULATION_INDIRECT, CQM_EINVAL,
+          "the marching solve takes the indirect formulation");
   require(p.opt.marching != 0 && p.lay.mw != 0, CQM_EINVAL,
           "create the problem with cqm_options.marching = 1 (the workspace holds the weights)");
   require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM, "workspace missing");

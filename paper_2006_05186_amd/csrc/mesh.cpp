@@ -160,6 +160,22 @@ void upload_problem(Problem& p) {
   p.dev.pts64 = upload(p64);
   p.dev.pts32 = upload(p32);
   {
+    // unit normals in the triangles' vertex order (the double-layer kernel)
+    std::vector<double4> nrm(M);
+    for (int64_t i = 0; i < M; ++i) {
+      const double* A = &p.verts[3 * p.tris[3 * i]];
+      const double* B = &p.verts[3 * p.tris[3 * i + 1]];
+      const double* C = &p.verts[3 * p.tris[3 * i + 2]];
+      const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+      const double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+      const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2],
+                           u[0] * v[1] - u[1] * v[0]};
+      const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      nrm[i] = double4{n[0] / nn, n[1] / nn, n[2] / nn, 0.0};
+    }
+    p.dev.nrm64 = upload(nrm);
+  }
+  {
     // bounding boxes of the triangles of each 64-block and 16-group (the
     // vertex boxes contain every quadrature point), for the cut-off
     auto boxes = [&](int g) {
@@ -208,6 +224,7 @@ void upload_problem(Problem& p) {
   p.dev.near_kind = upload(p.kind);
   p.dev.near_vtx = upload(p.nvtx);
   CQM_HIP(hipMalloc(&p.dev.near_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
+  CQM_HIP(hipMalloc(&p.dev.nearK_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
   std::vector<double> gx, gw;
   gauss_legendre01(p.opt.q_duffy, gx, gw);
   std::vector<double> gl(gx);
@@ -383,6 +400,12 @@ void compute_layout(Problem& p) {
     L.mdiag = take(sizeof(cf64) * block_inverse_elems(Mi));
     L.mpart = take(sizeof(double) * L.mchunks * (size_t)nb * nb * kSymB);
     L.mvec = take(sizeof(double) * (5 * M + 5 * nwg) + 256);
+  }
+  if (p.opt.formulation == CQM_FORMULATION_DIRECT) {
+    // double-layer operator for the direct right-hand side
+    L.nearK = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
+    L.kin = take(sizeof(cf64) * Fs * M);
+    L.kpart = take(dl_partial_bytes((int)M, (int)Fs));
   }
   L.total = off;
   p.lay = L;

@@ -1,0 +1,155 @@
+"""The double-layer operator K(s) and the direct Dirichlet formulation on the
+GPU (cqm_apply_K, cqm_options.formulation = CQM_FORMULATION_DIRECT) against
+the oracle (oracle/calderon.py): products with K(s_l) entry for entry, and
+whole direct solves V q = (-1/2 I + K) g_D of Section 2.2 (eq. wavegalform
+with a Dirichlet boundary) in every form and precision."""
+import sys
+
+import numpy as np
+import pytest
+
+import cqm_workloads as W
+import oracle as O
+import oracle.calderon as OK
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_05186_amd import cqm as C  # noqa: E402
+from paper_2006_05186_amd.solver import Problem, solve_batch  # noqa: E402
+
+DIRECT = C.CQM_FORMULATION_DIRECT
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = C.cqm_ctx_create(0)
+    yield c
+    C.cqm_ctx_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def ell():
+    """A 320-triangle ellipsoid (K is not symmetric there), N = 16, T = 2."""
+    V, T = W.ellipsoid(2, (1.3, 0.8, 1.0))
+    return V, T, 16, 2.0
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_apply_K_matches_oracle(ctx, ell, full):
+    V, T, N, Tend = ell
+    kw = {"mode": C.CQM_MIXED_H2ACA} if full else {}
+    p = Problem(ctx, V, T, N, Tend, formulation=DIRECT, **kw)
+    s, _, _ = O.frequencies(N, Tend)
+    nl = len(s) if full else N // 2 + 1  # the compressed modes solve the full band
+    x = W.random_complex((nl, len(T)), seed=21)
+    y = p.apply_K(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    worst = 0.0
+    for l in range(nl):
+        ref = OK.assemble_K(V, T, s[l]) @ x[l]
+        e = np.linalg.norm(y[l] - ref) / np.linalg.norm(ref)
+        worst = max(worst, e)
+    say(f"apply_K M={len(T)} frequencies {nl}: worst relative error {worst:.1e}")
+    assert worst < 1e-13
+    # a frequency sub-range addresses the same matrices
+    y2 = p.apply_K(torch.as_tensor(x[3:7], device="cuda"), l0=3).cpu().numpy()
+    assert np.abs(y2 - y[3:7]).max() <= 1e-14 * np.abs(y).max()
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_direct(ell):
+    V, T, N, Tend = ell
+    say("oracle: direct solve of the 320-triangle ellipsoid")
+    q = OK.solve_direct(V, T, N, Tend)
+    _, _, area = O.triangle_quadrature(V, T)
+    return q, area
+
+
+@pytest.mark.parametrize("mode,form", [(C.CQM_FP64_PLAIN, C.CQM_FORM_DENSE),
+                                       (C.CQM_MIXED_PLAIN, C.CQM_FORM_DENSE),
+                                       (C.CQM_MIXED_PLAIN, C.CQM_FORM_MATRIX_FREE),
+                                       (C.CQM_MIXED_H2ACA, C.CQM_FORM_DENSE)])
+def test_direct_solve_matches_oracle(ctx, ell, oracle_direct, mode, form):
+    V, T, N, Tend = ell
+    qref, area = oracle_direct
+    p = Problem(ctx, V, T, N, Tend, mode=mode, form=form, formulation=DIRECT)
+    p.set_plane_wave()
+    q, rc, d = p.solve()
+    err = O.rel_error(q.cpu().numpy(), qref, area)
+    say(f"direct solve mode={mode} form={form}: rc={rc} err vs oracle {err:.2e}, "
+        f"residual {d.max_rel_residual:.1e}")
+    assert rc == C.CQM_OK and d.converged == 1 and err < 1e-8
+    p.close()
+
+
+def test_direct_differs_from_indirect_and_batches(ctx, ell, oracle_direct):
+    """The two formulations answer different questions (a Neumann datum, a
+    single-layer density); direct problems in one batch equal each alone."""
+    V, T, N, Tend = ell
+    qref, area = oracle_direct
+    pi = Problem(ctx, V, T, N, Tend)
+    pi.set_plane_wave()
+    qi = pi.solve()[0].cpu().numpy()
+    pi.close()
+    assert O.rel_error(qi, qref, area) > 1e-2
+    V2, T2 = W.icosphere(2)
+    probs = [Problem(ctx, V, T, N, Tend, formulation=DIRECT),
+             Problem(ctx, V2, T2, 8, 2.0, formulation=DIRECT)]
+    for k, p in enumerate(probs):
+        p.set_plane_wave((0.0, 0.6, 0.8) if k else (1.0, 0.0, 0.0))
+    res, rc = solve_batch(probs)
+    assert rc == C.CQM_OK
+    e = O.rel_error(res[0][0].cpu().numpy(), qref, area)
+    q2 = OK.solve_direct(V2, T2, 8, 2.0, direction=(0.0, 0.6, 0.8))
+    e2 = O.rel_error(res[1][0].cpu().numpy(), q2, O.triangle_quadrature(V2, T2)[2])
+    say(f"batch of two direct problems: errors vs oracle {e:.1e}, {e2:.1e}")
+    assert e < 1e-8 and e2 < 1e-8
+    for p in probs:
+        p.close()
+
+
+def test_apply_K_large_sampled_rows(ctx):
+    """5120-triangle sphere, N = 128: sampled rows of K(s_l) x for the lowest,
+    a middle and the highest distinct frequency against the oracle's rows."""
+    wl = W.C3
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, formulation=DIRECT)
+    s, _, _ = O.frequencies(wl.N, wl.T)
+    H = wl.N // 2 + 1
+    x = W.random_complex((H, len(T)), seed=22)
+    y = p.apply_K(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    rows = np.random.default_rng(5).choice(len(T), 24, replace=False)
+    for l in (0, H // 2, H - 1):
+        ref = OK.assemble_K(V, T, s[l], rows=rows) @ x[l]
+        e = np.linalg.norm(y[l][rows] - ref) / np.linalg.norm(ref)
+        say(f"apply_K M=5120 l={l}: sampled rows relative error {e:.1e}")
+        assert e < 1e-13
+    p.close()
+
+
+def test_direct_argument_checks(ctx, ell):
+    V, T, N, Tend = ell
+    p = Problem(ctx, V, T, N, Tend)
+    x = torch.zeros((1, len(T)), dtype=torch.complex128, device="cuda")
+    with pytest.raises(C.CqmError) as e:
+        p.apply_K(x)
+    assert e.value.code == C.CQM_EINVAL
+    p.close()
+    p = Problem(ctx, V, T, N, Tend, formulation=DIRECT, marching=1)
+    p.set_plane_wave()
+    with pytest.raises(C.CqmError) as e:
+        p.solve_marching()
+    assert e.value.code == C.CQM_EINVAL
+    with pytest.raises(C.CqmError) as e:
+        p.apply_K(torch.zeros((2, len(T)), dtype=torch.complex128, device="cuda"), l0=N // 2)
+    assert e.value.code == C.CQM_EINVAL
+    p.close()
+    with pytest.raises(C.CqmError) as e:
+        Problem(ctx, V, T, N, Tend, formulation=7)
+    assert e.value.code == C.CQM_EINVAL

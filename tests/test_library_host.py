@@ -85,7 +85,7 @@ def test_host_argument_errors():
     assert o.autotune == 1 and o.arnoldi_layout == C.CQM_ARNOLDI_AUTO and o.graphs == 0
     assert o.precond == C.CQM_PRECOND_BLOCK_JACOBI
     assert (o.cutoff_inner, o.cutoff_outer) == (18.0, 45.0)
-    assert o.refine_plain == 1
+    assert o.refine_plain == 1 and o.formulation == C.CQM_FORMULATION_INDIRECT
 
 
 def test_server_default_options_as_documented():
