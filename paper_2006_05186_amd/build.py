@@ -54,7 +54,9 @@ def build(verbose=False):
             if err.strip():
                 print(os.path.basename(s), err, file=sys.stderr)
     tmp = os.path.join(OUT, LIBNAME + ".tmp")
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    # roctx: named stage ranges for rocprofv3 --marker-trace
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

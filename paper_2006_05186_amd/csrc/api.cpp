@@ -325,6 +325,7 @@ int cqm_set_dirichlet_samples(cqm_problem_t p, const double* g) {
 
 int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream) {
   return guarded([&] {
+    Stage stage("cqm_solve");
     require(p != nullptr, CQM_EINVAL, "NULL problem");
     p->own.p = p;
     p->own.base = p->ws;
@@ -340,6 +341,7 @@ int cqm_solve(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream
 int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs, cqm_diag* diags,
                     hipStream_t stream) {
   return guarded([&] {
+    Stage stage("cqm_solve_batch");
     require(probs && q_outs && count >= 0, CQM_EINVAL, "NULL argument");
     std::vector<SolveState*> S;
     for (int k = 0; k < count; ++k) {
@@ -366,6 +368,7 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs, cqm_di
 
 int cqm_solve_marching(cqm_problem_t p, double* q_out, cqm_diag* diag, hipStream_t stream) {
   return guarded([&] {
+    Stage stage("cqm_solve_marching");
     require(p != nullptr, CQM_EINVAL, "NULL problem");
     solve_marching(*p, q_out, diag, stream);
     return CQM_OK;

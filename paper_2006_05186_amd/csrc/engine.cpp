@@ -153,6 +153,7 @@ void prepare_double_layer(Problem& p, hipStream_t s) {
 }
 
 static bool prepare_operator_impl(Problem& p, hipStream_t s, bool defer_dense) {
+  Stage stage("prepare_operator");
   require(p.ws != nullptr, CQM_ENOMEM, "no workspace attached (cqm_set_workspace)");
   if (p.opt.formulation == CQM_FORMULATION_DIRECT) prepare_double_layer(p, s);
   if (!p.static_ready) {
@@ -232,6 +233,7 @@ static void prepare_batch(std::vector<SolveState*>& G, hipStream_t s) {
 
 // Operator (optionally), right-hand side and forward transform of one state.
 void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed) {
+  Stage stage("operator_and_right_hand_side");
   Problem& p = *st.p;
   CQM_HIP(hipSetDevice(p.ctx->device));
   require(p.ws != nullptr && p.ws_bytes >= p.lay.total, CQM_ENOMEM,
@@ -275,6 +277,7 @@ void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed) {
 
 // Inverse transform and operator diagnostics of one state.
 void post_solve(SolveState& st, hipStream_t s) {
+  Stage stage("inverse_transform");
   Problem& p = *st.p;
   cqm_diag& dg = st.diag;
   double* sums = st.at<double>(st.scratch);  // cleared by the forward transform
@@ -670,6 +673,7 @@ template <typename R> void Engine::step_graph(int j, hipStream_t s) {
 }
 
 template <typename R> int Engine::cycle_t(hipStream_t s) {
+  Stage stage(sizeof(R) == 4 ? "restart_cycle_fp32" : "restart_cycle_fp64");
   const int n = (int)hd_.size();
   if (!n) return 0;
   Problem& p0 = *S_[0]->p;

@@ -10,6 +10,8 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/cqm.h"
 
 namespace cqm {
@@ -569,6 +571,15 @@ void launch_cg_init(const CgVec& v, hipStream_t s);
 void launch_cg_iteration(const CgVec& v, const double* W0, double* P, int par, double tol2,
                          hipStream_t s);
 void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s);  // march.cpp
+
+// RAII helper: a named host range around a stage (rocprofv3 --marker-trace
+// records it; without a profiler the calls return at once).
+struct Stage {
+  explicit Stage(const char* name) { roctxRangePushA(name); }
+  ~Stage() { roctxRangePop(); }
+  Stage(const Stage&) = delete;
+  Stage& operator=(const Stage&) = delete;
+};
 
 // RAII helper: times the launches issued in its scope as one class.
 struct Timed {

@@ -6,6 +6,7 @@
 // definite; the paper factorises it once, this build iterates on it).
 #include <chrono>
 #include <cmath>
+#include <optional>
 
 #include "internal.h"
 
@@ -37,6 +38,8 @@ void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   // operator (near field, FP64 assembly), right-hand sides b_n
   prepare_operator(p, s);
+  std::optional<Stage> setup;
+  setup.emplace("marching_weights");
   SolveState& st = p.own;
   st.p = &p;
   st.base = p.ws;
@@ -50,6 +53,7 @@ void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
   launch_march_diag(W, M, dg, s);
   launch_block_inverse<double>(dg, M, 1, true, pinv, s);
   CQM_HIP(hipStreamSynchronize(s));
+  setup.reset();
   const double t_setup = ms_since(t0);
   auto t1 = std::chrono::steady_clock::now();
   // CG vectors
@@ -78,6 +82,7 @@ void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s) {
   bool converged = true, finite = true;
   double max_res = 0.0;
   std::vector<double> rr(nwg), bb(nwg);
+  Stage steps("marching_steps");
   for (int n = 0; n <= N; ++n) {
     // r_n = b_n - sum_{j=1}^{n} What_j q_{n-j}
     if (n == 0) {

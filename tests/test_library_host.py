@@ -125,3 +125,15 @@ def test_every_declaration_names_its_passage():
         m = re.search(r"(/\*(?:(?!\*/).)*?\*/)\s*(?:(?:int|const char\*)\s+cqm_\w+\([^;]*;\s*)*"
                       r"(?:int|const char\*)\s+" + name + r"\s*\(", body, flags=re.S)
         assert m and re.search(r"Section \d", m.group(1)), name
+
+
+def test_library_marks_its_stages_for_the_profiler():
+    """Named stage ranges (roctx) around the solve's stages: the library
+    imports the range calls, so rocprofv3 --marker-trace records them."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm missing")
+    out = subprocess.run([nm, "-D", C.library_path()], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
