@@ -174,7 +174,10 @@ size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
 // frequencies; each rank term is a complex 16 x acols x 16 product done as
 // four real MFMA chains (re re, im im, re im, im re), then scaled by d_t[l]
 // and accumulated.  Columns are taken 32 at a time so the input block stays
-// in registers across the rank terms.
+// in registers across the rank terms.  A workgroup holds as many waves as
+// its frequencies need (up to kRankWaves<R>), so the slices of a row tile
+// are read from memory by one workgroup and shared by its waves through the
+// caches, instead of once per group of four waves.
 namespace {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
@@ -197,10 +200,14 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int L, int v) { return (L >> 4) + 4 * v; }
 };
 constexpr int kKC = 32;  // columns per register block
+// waves per workgroup: 12 for FP32 (under 170 VGPRs: three waves per SIMD;
+// one workgroup covers 192 frequencies), 4 for FP64 (8 measured slower: the
+// FP64 product is bound by its rank loop, not by re-reads)
+template <typename R> constexpr int kRankWaves = sizeof(R) == 4 ? 12 : 4;
 }  // namespace
 
 template <typename R, typename S, int NF, bool kAccum>
-__global__ __launch_bounds__(256) void k_h2_rank_mfma(const RankTile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankTile* __restrict__ tiles,
                                                       const RankTask* __restrict__ tasks,
                                                       const int* __restrict__ ranks,
                                                       const cplx<S>* __restrict__ cstore,
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(256) void k_h2_rank_mfma(const RankTile* __restrict
   using A4 = typename MF::acc;
   const RankTile tl = tiles[blockIdx.x];
   const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int fb = (blockIdx.y * 4 + w) * 16 * NF;  // first frequency of this wave
+  const int fb = (blockIdx.y * (blockDim.x >> 6) + w) * 16 * NF;  // first frequency of this wave
   if (fb >= nsys) return;                         // no barrier follows
   const int arow = L & 15, kq = L >> 4, col = L & 15;
   A4 accr[NF], acci[NF];
@@ -319,8 +326,13 @@ static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* 
                              int l0, int nsys, const cplx<R>* x, cplx<R>* out, hipStream_t s) {
   if (ntiles <= 0) return;
   constexpr int NF = 1;
-  const dim3 grid(ntiles, (nsys + 64 * NF - 1) / (64 * NF));
-  hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(256), 0, s, tiles, tasks, ranks,
+  // 16 NF frequencies per wave; the fewest workgroups per row tile, with the
+  // waves spread evenly over them
+  const int ftiles = (nsys + 16 * NF - 1) / (16 * NF);
+  const int gy = (ftiles + kRankWaves<R> - 1) / kRankWaves<R>;
+  const int nw = (ftiles + gy - 1) / gy;
+  const dim3 grid(ntiles, gy);
+  hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(64 * nw), 0, s, tiles, tasks, ranks,
                      (const cplx<S>*)cstore, dvec, dstride, l0, nsys, x, out);
   CQM_HIP(hipGetLastError());
 }
