@@ -294,23 +294,31 @@ __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restri
     const cf64* x = G.x[k];
     cf64* P = (cf64*)G.symp[k];
     const cf64 xj = load_x<double>(x, J * kB + c, M);
-    // rows of I: V_IJ x_J, real and imaginary parts in two rounds
+    // rows of I: V_IJ x_J, real and imaginary parts and the two halves of
+    // the wave's rows in separate rounds (register budget: four waves per
+    // SIMD)
+    constexpr int kH = kRowsPerWave / 2;
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-      dd v[kRowsPerWave];
+    for (int part = 0; part < 2; ++part)
 #pragma unroll
-      for (int q = 0; q < kRowsPerWave; ++q)
-        v[q] = part == 0 ? two_prod(a[q].re, xj.re) + (-two_prod(a[q].im, xj.im))
-                         : two_prod(a[q].re, xj.im) + two_prod(a[q].im, xj.re);
-      wave_reduce_scatter_near<kRowsPerWave>(v, c);
-      if (c < kRowsPerWave) {
-        const int64_t o = (int64_t)J * ntB + I * kB + w * kRowsPerWave + scatter_entry<kRowsPerWave>(c);
-        double* ph = reinterpret_cast<double*>(P + o);
-        double* pl = reinterpret_cast<double*>(P + np + o);
-        ph[part] = v[0].hi;
-        pl[part] = v[0].lo;
+      for (int half = 0; half < 2; ++half) {
+        dd v[kH];
+#pragma unroll
+        for (int q = 0; q < kH; ++q) {
+          const cf64 e = a[half * kH + q];
+          v[q] = part == 0 ? two_prod(e.re, xj.re) + (-two_prod(e.im, xj.im))
+                           : two_prod(e.re, xj.im) + two_prod(e.im, xj.re);
+        }
+        wave_reduce_scatter_near<kH>(v, c);
+        if (c < kH) {
+          const int64_t o = (int64_t)J * ntB + I * kB + w * kRowsPerWave + half * kH +
+                            scatter_entry<kH>(c);
+          double* ph = reinterpret_cast<double*>(P + o);
+          double* pl = reinterpret_cast<double*>(P + np + o);
+          ph[part] = v[0].hi;
+          pl[part] = v[0].lo;
+        }
       }
-    }
     if (I != J) {
       // rows of J: V_IJ^T x_I
       const cf64 xi = load_x<double>(x, I * kB + c, M);
