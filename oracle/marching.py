@@ -29,7 +29,7 @@ import scipy.linalg as sla
 from .cqm import (assemble_V, frequencies, near_pairs, near_static, num_frequencies_half, rhs,
                   twiddles)
 
-__all__ = ["cqm_weights", "march", "solve_marching"]
+__all__ = ["cqm_weights", "march", "solve_marching", "compressed_weights", "solve_marching_compressed"]
 
 
 def cqm_weights(V, T, N, Tend, rho=None, q=5):
@@ -77,6 +77,52 @@ def solve_marching(V, T, N, Tend, rho=None, q=5, direction=(1.0, 0.0, 0.0), sigm
     cqm.solve up to the aliasing of the weights, of order rho^F)."""
     W, ratio, rho = cqm_weights(V, T, N, Tend, rho, q)
     b = rhs(V, T, N, Tend, direction, sigma, t0, amplitude, samples)
+    qn = march(W, b)
+    if return_weights:
+        return qn, W, ratio
+    return qn
+
+
+def compressed_weights(op, rho, M):
+    """Integration weights of the compressed tensor (Section 6.2, eq. fastdft):
+    the slices C_t of every block are frequency-independent, so the scaled
+    DFT of eq. dft acts on the fibres alone,
+        dhat_t[n] = rho^-n / F sum_l d_t[l] zeta^(n l mod F),
+    and What_n = sum_blocks sum_t dhat_t[n] C_t (far blocks expanded with
+    their cluster bases).  Returns (W real (F, M, M), ||Im W|| / ||Re W||)."""
+    from .compress import compressed_dense
+    F = op["F"]
+    tw = twiddles(F, +1)
+    scale = np.array([rho ** (-n) / F for n in range(F)])
+    blocks = []
+    for b in op["blocks"]:
+        bb = dict(b)
+        if b["C"]:
+            D = np.asarray(b["d"])  # (rank, F)
+            Dh = np.zeros_like(D)
+            for n in range(F):
+                acc = np.zeros(D.shape[0], dtype=np.complex128)
+                for l in range(F):
+                    acc += D[:, l] * tw[(n * l) % F]
+                Dh[:, n] = acc * scale[n]
+            bb["d"] = list(Dh)
+        blocks.append(bb)
+    Wc = compressed_dense(dict(op, blocks=blocks), M)  # (M, M, F)
+    W = np.moveaxis(Wc, 2, 0)
+    ratio = np.linalg.norm(W.imag) / max(np.linalg.norm(W.real), 1e-300)
+    return W.real.copy(), ratio
+
+
+def solve_marching_compressed(V, T, N, Tend, n_min, eta, m, eps, rho=None,
+                              direction=(1.0, 0.0, 0.0), sigma=0.25, t0=1.5, amplitude=1.0,
+                              return_weights=False):
+    """Time-marching solve with the weights of the compressed tensor (the
+    H2 x MACA operator of Algorithm 3 over all F = N + 1 frequencies)."""
+    from .compress import build_compressed
+    s, rho, dt = frequencies(N, Tend, rho)
+    op = build_compressed(V, T, s, n_min, eta, m, eps)
+    W, ratio = compressed_weights(op, rho, len(T))
+    b = rhs(V, T, N, Tend, direction, sigma, t0, amplitude)
     qn = march(W, b)
     if return_weights:
         return qn, W, ratio

@@ -67,3 +67,43 @@ def test_march_recovers_a_known_history_for_scalar_weights():
     bad = b.copy()
     bad[5] -= w[1] * qs[4]
     assert np.max(np.abs(O.march(w[:, None, None], bad) - qs)) > 1e-3
+
+
+def test_compressed_weights_reduce_to_the_plain_ones(tiny):
+    # no admissible block (eta = 0) and MACA to full rank (eps = 0): the
+    # compressed tensor is the plain one, so the fibre transform of eq.
+    # fastdft must give the plain weights of eq. dft
+    wl, V, T, qm, Wt, ratio, rho, dt, area = tiny
+    s, _, _ = O.frequencies(wl.N, wl.T)
+    op = O.build_compressed(V, T, s, 8, 0.0, 2, 0.0)
+    Wc, r = O.compressed_weights(op, rho, len(T))
+    assert np.linalg.norm(Wc - Wt) <= 1e-7 * np.linalg.norm(Wt)
+
+
+def test_fibre_transform_equals_the_transform_of_the_tensor(tiny):
+    # the slices do not depend on frequency, so transforming the fibres and
+    # transforming the expanded tensor give the same weights (with far blocks)
+    wl, V, T, qm, Wt, ratio, rho, dt, area = tiny
+    s, _, _ = O.frequencies(wl.N, wl.T)
+    op = O.build_compressed(V, T, s, 4, 1.0, 2, 1e-6)
+    assert len(op["far"]) > 0
+    Wc, r = O.compressed_weights(op, rho, len(T))
+    A = O.compressed_dense(op, len(T))  # (M, M, F)
+    F = wl.N + 1
+    direct = np.stack([(rho ** -n / F) * sum(A[:, :, l] * np.exp(2j * np.pi * n * l / F)
+                                              for l in range(F)) for n in range(F)])
+    # equal up to rounding, which rho^-n (up to 1e8) amplifies: 4e-8 measured
+    assert np.linalg.norm(Wc - direct.real) <= 1e-6 * np.linalg.norm(direct.real)
+
+
+def test_compressed_marching_approaches_the_plain_one(tiny):
+    # the error against the plain marching solve falls with the MACA
+    # tolerance until the interpolation error of the far field is left
+    # (Corollary combierr), which falls with the order m (Theorem h2err)
+    wl, V, T, qm, Wt, ratio, rho, dt, area = tiny
+    err = lambda m, eps: O.rel_error(O.solve_marching_compressed(V, T, wl.N, wl.T, 4, 1.0, m, eps),
+                                     qm, area)
+    e_eps = [err(3, eps) for eps in (1e-2, 1e-4, 1e-6)]
+    assert e_eps[0] > e_eps[1] > e_eps[2]
+    e_m = [err(m, 1e-12) for m in (2, 3, 4)]
+    assert e_m[0] > e_m[1] > e_m[2] and e_m[2] < 1e-5
