@@ -146,6 +146,7 @@ void set_views(Problem& p) {
   h.yhat_d = base + h.off_yhat;
   h.xp_d = base + h.off_xp;
   h.yp_d = base + h.off_yp;
+  h.dhat_d = h.off_dhat ? (cf64*)(base + h.off_dhat) : nullptr;
 }
 }  // namespace
 
@@ -166,6 +167,8 @@ size_t h2_workspace_bytes(const Problem& pc) {
   h.off_yhat = take(h2_apply_scratch_bytes(h, p.Fsys));
   h.off_xp = take(h2_perm_scratch_bytes(h, p.Fsys));
   h.off_yp = take(h2_perm_scratch_bytes(h, p.Fsys));
+  // time marching: the fibres' transforms beside the fibres
+  h.off_dhat = p.opt.marching ? take((size_t)h.dvec_elems * sizeof(cf64)) : 0;
   h.total = off;
   return off;
 }
@@ -205,6 +208,23 @@ void h2_apply(Problem& p, int l0, int nsys, const cplx<R>* x, int64_t xs, cplx<R
               const int* /*active*/, hipStream_t s) {
   set_views(p);
   launch_h2_apply<R>(p, *p.h2, l0, nsys, x, xs, y, ys, nullptr, s);
+}
+
+// y_k = What_k x_k for k = k0 .. k0+nsys-1 (compressed time-marching
+// weights: the fibres' transforms, after h2_marching_weights)
+void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, cf64* y, int64_t ys,
+                      hipStream_t s) {
+  set_views(p);
+  H2Operator& h = *p.h2;
+  require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
+  launch_h2_apply<double>(p, h, k0, nsys, x, xs, y, ys, h.dhat_d, s);
+}
+
+void h2_marching_weights(Problem& p, hipStream_t s) {
+  set_views(p);
+  H2Operator& h = *p.h2;
+  require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
+  launch_fibre_dft(p, h, h.dvec_d, h.dhat_d, s);
 }
 template void h2_apply<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
 template void h2_apply<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);

@@ -105,6 +105,7 @@ struct H2Operator {
   // workspace regions (byte offsets from the problem's H2 region)
   size_t off_cstore = 0, off_dvec = 0, off_stage = 0, off_xhat = 0, off_yhat = 0, total = 0;
   size_t off_xp = 0, off_yp = 0;
+  size_t off_dhat = 0;  // marching: the fibres' transforms (integration weights)
   int64_t cstore_elems = 0, dvec_elems = 0, stage_elems = 0;
   int64_t stage_budget = 0;       // cf64 elements per MACA batch
   std::vector<std::pair<int, int>> batches;  // [b0, b1) per MACA launch
@@ -112,6 +113,7 @@ struct H2Operator {
   // per-problem views into the workspace (set before use)
   cf64* stage_d = nullptr;
   cf64* dvec_d = nullptr;
+  cf64* dhat_d = nullptr;
   void* cstore_d = nullptr;
   void* xhat_d = nullptr;
   void* yhat_d = nullptr;
@@ -128,7 +130,10 @@ void launch_maca(const Problem& p, H2Operator& h, int b0, int nb, hipStream_t s)
 void launch_maca_finalize_batch(const Problem& p, H2Operator& h, int b0, int nb, hipStream_t s);
 template <typename R>
 void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                     cplx<R>* y, int64_t ys, void* scratch, hipStream_t s);
+                     cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s);
+// scaled inverse DFT of every fibre slot (eq. fastdft): dhat[n] =
+// rho^-n / F sum_l d[l] zeta^(n l mod F); full band only
+void launch_fibre_dft(const Problem& p, const H2Operator& h, const cf64* d, cf64* dhat, hipStream_t s);
 size_t h2_apply_scratch_bytes(const H2Operator& h, int nsys);
 size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys);
 

@@ -257,6 +257,9 @@ struct Layout {
   // time marching (cqm_options.marching): weights, What_0 block inverses and
   // their complex staging, product partials, CG vectors and partial sums
   size_t mw = 0, mpinv = 0, mdiag = 0, mpart = 0, mvec = 0;
+  // compressed time marching: past densities as complex rows (newest last),
+  // the history product's outputs, the CG product's input and output
+  size_t mz = 0, my = 0, mpc = 0;
   int mchunks = 1;  // weight chunks of the history product (its partial slots)
 };
 
@@ -571,6 +574,20 @@ void launch_cg_init(const CgVec& v, hipStream_t s);
 void launch_cg_iteration(const CgVec& v, const double* W0, double* P, int par, double tol2,
                          hipStream_t s);
 void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s);  // march.cpp
+// compressed time marching (h2.cpp): the weights What_n from the fibres, and
+// y_k = What_k x_k for k = k0 .. k0+nsys-1 (complex in and out)
+void h2_marching_weights(Problem& p, hipStream_t s);
+void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, cf64* y, int64_t ys,
+                      hipStream_t s);
+// compressed marching helpers (k_march.hip): r = b - Re sum_{k<n} Y[k];
+// Z = x as complex; w = Re Y with the partial p.w (CG product); the mean
+// over the frequencies of the plain diagonal blocks (real part)
+void launch_hist_reduce(const cf64* Y, int n, int M, const double* b, double* r, hipStream_t s);
+void launch_to_complex(const double* x, int M, cf64* z, const int* done, hipStream_t s);
+void launch_cg_reduce_complex(const CgVec& v, const cf64* y, hipStream_t s);
+void launch_freq_mean_blocks(const cf64* blocks, int F, int64_t nel, cf64* out, hipStream_t s);
+void launch_cg_check(const CgVec& v, double tol2, hipStream_t s);
+void launch_cg_finish(const CgVec& v, int par, hipStream_t s);
 
 // RAII helper: a named host range around a stage (rocprofv3 --marker-trace
 // records it; without a profiler the calls return at once).

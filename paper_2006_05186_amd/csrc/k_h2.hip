@@ -175,9 +175,7 @@ size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
 // four real MFMA chains (re re, im im, re im, im re), then scaled by d_t[l]
 // and accumulated.  Columns are taken 32 at a time so the input block stays
 // in registers across the rank terms.  A workgroup holds as many waves as
-// its frequencies need (up to kRankWaves<R>), so the slices of a row tile
-// are read from memory by one workgroup and shared by its waves through the
-// caches, instead of once per group of four waves.
+// its frequencies need, up to kRankWaves<R>.
 namespace {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
@@ -200,10 +198,10 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int L, int v) { return (L >> 4) + 4 * v; }
 };
 constexpr int kKC = 32;  // columns per register block
-// waves per workgroup: 12 for FP32 (under 170 VGPRs: three waves per SIMD;
-// one workgroup covers 192 frequencies), 4 for FP64 (8 measured slower: the
-// FP64 product is bound by its rank loop, not by re-reads)
-template <typename R> constexpr int kRankWaves = sizeof(R) == 4 ? 12 : 4;
+// waves per workgroup: 4.  Wider workgroups (12 waves for FP32, 8 for FP64)
+// cut the FP32 far products' fetched bytes by half but measured no faster:
+// the products are bound by their rank loops, not by re-reads
+template <typename R> constexpr int kRankWaves = 4;
 }  // namespace
 
 template <typename R, typename S, int NF, bool kAccum>
@@ -339,7 +337,9 @@ static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* 
 
 template <typename R>
 void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                     cplx<R>* y, int64_t ys, void* /*scratch*/, hipStream_t s) {
+                     cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s) {
+  // the frequency fibres d_t[l], or their transforms (time-marching weights)
+  const cf64* dv = fibres ? fibres : h.dvec_d;
   const int P = h.p;
   cplx<R>* xh = (cplx<R>*)h.xhat_d;
   cplx<R>* yh = (cplx<R>*)h.yhat_d;
@@ -373,10 +373,10 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
   // 2. couplings: every cluster's coefficient rows (zero where no core block)
   if (h.store_fp64)
     launch_rank_mfma<R, double, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
-                                       h.cstore_d, h.dvec_d, dstride, l0, nsys, xh, yh, s);
+                                       h.cstore_d, dv, dstride, l0, nsys, xh, yh, s);
   else
     launch_rank_mfma<R, float, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
-                                      h.cstore_d, h.dvec_d, dstride, l0, nsys, xh, yh, s);
+                                      h.cstore_d, dv, dstride, l0, nsys, xh, yh, s);
   // 3. downward pass
   for (int lv = 1; lv < h.nlevels; ++lv) {
     const int cnt = h.level_off[lv + 1] - h.level_off[lv];
@@ -399,17 +399,51 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
   CQM_HIP(hipGetLastError());
   if (h.store_fp64)
     launch_rank_mfma<R, double, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                      h.cstore_d, h.dvec_d, dstride, l0, nsys, xp, yp, s);
+                                      h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
   else
     launch_rank_mfma<R, float, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                     h.cstore_d, h.dvec_d, dstride, l0, nsys, xp, yp, s);
+                                     h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
   hipLaunchKernelGGL((k_h2_scatter<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, yp, y, ys);
   CQM_HIP(hipGetLastError());
 }
 
 template void launch_h2_apply<float>(const Problem&, H2Operator&, int, int, const cf32*, int64_t, cf32*,
-                                     int64_t, void*, hipStream_t);
+                                     int64_t, const cf64*, hipStream_t);
 template void launch_h2_apply<double>(const Problem&, H2Operator&, int, int, const cf64*, int64_t, cf64*,
-                                      int64_t, void*, hipStream_t);
+                                      int64_t, const cf64*, hipStream_t);
+
+// One thread per (fibre slot, n): dhat[n] = rho^-n / F sum_l d[l] zeta^(n l mod F)
+// (twiddles and scales from the problem's tables; the index n l mod F is
+// carried incrementally).
+__global__ __launch_bounds__(256) void k_fibre_dft(const cf64* __restrict__ d, int64_t slots, int F,
+                                                   const cf64* __restrict__ tw,
+                                                   const double* __restrict__ scale,
+                                                   cf64* __restrict__ dhat) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= slots * F) return;
+  const int64_t slot = g / F;
+  const int n = (int)(g - slot * F);
+  const cf64* ds = d + slot * F;
+  double re = 0.0, im = 0.0;
+  int k = 0;
+  for (int l = 0; l < F; ++l) {
+    const cf64 a = ds[l], t = tw[k];
+    re += a.re * t.re - a.im * t.im;
+    im += a.re * t.im + a.im * t.re;
+    k += n;
+    if (k >= F) k -= F;
+  }
+  dhat[g] = cf64{re * scale[n], im * scale[n]};
+}
+
+void launch_fibre_dft(const Problem& p, const H2Operator& h, const cf64* d, cf64* dhat, hipStream_t s) {
+  require(h.nsys == p.F, CQM_EINVAL, "the fibre transform needs the full band of frequencies");
+  const int64_t slots = h.dvec_elems / p.F;
+  const int64_t n = slots * p.F;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fibre_dft, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, slots, p.F,
+                     p.dev.tw_inv, p.dev.rho_ipow, dhat);
+  CQM_HIP(hipGetLastError());
+}
 
 }  // namespace cqm

@@ -285,6 +285,73 @@ __global__ __launch_bounds__(256) void k_cg_direction(CgVec v, int par) {
   if (i < v.M) v.p[i] = fma(beta, v.p[i], v.z[i]);
 }
 
+// ------------------------------------------------------------------ compressed marching
+// r = b - sum_{k < n} Re Y[k] (the history sum of eq. cqmrhs from the
+// compressed weights' products, one row per lag)
+__global__ __launch_bounds__(256) void k_hist_reduce(const cf64* __restrict__ Y, int n, int M,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ r) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc += Y[(int64_t)k * M + i].re;
+  r[i] = b[i] - acc;
+}
+
+// z = x + 0 i (skipped once the CG has converged)
+__global__ __launch_bounds__(256) void k_to_complex(const double* __restrict__ x, int M,
+                                                    cf64* __restrict__ z, const int* done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < M) z[i] = cf64{x[i], 0.0};
+}
+
+// w = Re y (the real weight's product with the real direction) and the
+// partial p.w of the workgroup's rows
+__global__ __launch_bounds__(256) void k_cg_reduce_complex(CgVec v, const cf64* __restrict__ y) {
+  if (*v.done) return;
+  __shared__ double red[16];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double wi = 0.0, pi = 0.0;
+  if (i < v.M) {
+    wi = y[i].re;
+    pi = v.p[i];
+    v.w[i] = wi;
+  }
+  const double pw = block_sum(pi * wi, red);
+  if (threadIdx.x == 0) v.pw[blockIdx.x] = pw;
+}
+
+// out = Re (1/F) sum_l blocks[l] (the plain operator's diagonal blocks at
+// every frequency: their mean is the diagonal block of What_0, eq. dft at
+// n = 0)
+__global__ __launch_bounds__(256) void k_freq_mean_blocks(const cf64* __restrict__ blocks, int F,
+                                                          int64_t nel, cf64* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nel) return;
+  double acc = 0.0;
+  for (int l = 0; l < F; ++l) acc += blocks[(int64_t)l * nel + e].re;
+  out[e] = cf64{acc / F, 0.0};
+}
+
+void launch_hist_reduce(const cf64* Y, int n, int M, const double* b, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_hist_reduce, dim3((M + 255) / 256), dim3(256), 0, s, Y, n, M, b, r);
+  CQM_HIP(hipGetLastError());
+}
+void launch_to_complex(const double* x, int M, cf64* z, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_complex, dim3((M + 255) / 256), dim3(256), 0, s, x, M, z, done);
+  CQM_HIP(hipGetLastError());
+}
+void launch_cg_reduce_complex(const CgVec& v, const cf64* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_reduce_complex, dim3(v.nwg), dim3(256), 0, s, v, y);
+  CQM_HIP(hipGetLastError());
+}
+void launch_freq_mean_blocks(const cf64* blocks, int F, int64_t nel, cf64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_freq_mean_blocks, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, blocks,
+                     F, nel, out);
+  CQM_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ launchers
 void launch_march_weights(const cf64* V, int M, int H, int F, const cf64* tw, const double* scale,
                           double* W, hipStream_t s) {
@@ -340,6 +407,19 @@ void launch_cg_iteration(const CgVec& v, const double* W0, double* P, int par, d
   hipLaunchKernelGGL(k_march_gemv, dim3(sym_tiles(M), 1), dim3(256), 0, s, W0, sym_slice(M), M, 0, 1,
                      1, (const double*)v.p, 0, P, (const int*)v.done);
   hipLaunchKernelGGL(k_cg_reduce, dim3(v.nwg), dim3(256), 0, s, v, (const double*)P);
+  hipLaunchKernelGGL(k_cg_update, dim3(v.nwg), dim3(256), 0, s, v, par);
+  hipLaunchKernelGGL(k_cg_direction, dim3(v.nwg), dim3(256), 0, s, v, par);
+  CQM_HIP(hipGetLastError());
+}
+
+// The CG iteration's parts around an external product (the compressed
+// marching): the convergence test, then, after w = What_0 p, the update and
+// the new direction.
+void launch_cg_check(const CgVec& v, double tol2, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(1), 0, s, v, tol2);
+  CQM_HIP(hipGetLastError());
+}
+void launch_cg_finish(const CgVec& v, int par, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update, dim3(v.nwg), dim3(256), 0, s, v, par);
   hipLaunchKernelGGL(k_cg_direction, dim3(v.nwg), dim3(256), 0, s, v, par);
   CQM_HIP(hipGetLastError());

@@ -291,6 +291,18 @@ void compute_layout(Problem& p) {
     L.mpart = take(sizeof(double) * L.mchunks * (size_t)nb * nb * kSymB);
     L.mvec = take(sizeof(double) * (5 * M + 5 * nwg) + 256);
   }
+  if (p.opt.marching && mode_is_h2(p.opt.mode)) {
+    // compressed time marching (weights from the fibres, in the compressed
+    // operator's own workspace): history rows, product outputs, the CG
+    // product's vectors and vectors/partials, the block inverses of What_0
+    const size_t nwg = (M + 255) / 256;
+    L.mz = take(sizeof(cf64) * p.F * M);
+    L.my = take(sizeof(cf64) * p.F * M);
+    L.mpc = take(sizeof(cf64) * 2 * M);
+    L.mpinv = take(sizeof(cf64) * block_inverse_elems((int)M));
+    L.mdiag = take(sizeof(cf64) * block_inverse_elems((int)M));
+    L.mvec = take(sizeof(double) * (5 * M + 5 * nwg) + 256);
+  }
   if (p.opt.formulation == CQM_FORMULATION_DIRECT) {
     // double-layer operator for the direct right-hand side
     L.nearK = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));

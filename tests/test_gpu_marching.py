@@ -79,11 +79,55 @@ def test_marching_C2_against_stored_all_at_once(ctx):
     p.close()
 
 
+@pytest.mark.parametrize("mode", [C.CQM_FP64_H2ACA, C.CQM_MIXED_H2ACA])
+def test_compressed_marching_matches_oracle(ctx, mode):
+    """Weights from the transformed MACA fibres (eq. fastdft) on the
+    80-triangle sphere with admissible blocks (leaf size 4, eta 1, m = 3)
+    against the oracle's compressed marching (same partition, order and
+    tolerance); pivots of near-ties may differ, so the bar is that of the
+    compressed all-at-once comparison."""
+    wl = W.C0_TINY
+    V, T = wl.mesh()
+    kw = dict(n_min=4, eta=1.0, cheb_m=3, eps_aca=1e-10)
+    say("oracle: compressed marching of the 80-triangle sphere")
+    qref = O.solve_marching_compressed(V, T, wl.N, wl.T, 4, 1.0, 3, 1e-10)
+    qplain = O.solve_marching(V, T, wl.N, wl.T)
+    _, _, area = O.triangle_quadrature(V, T)
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, marching=1, **kw)
+    p.set_plane_wave()
+    q, rc, d = p.solve_marching()
+    q = q.cpu().numpy()
+    e = O.rel_error(q, qref, area)
+    e_plain = O.rel_error(q, qplain, area)
+    say(f"compressed marching mode={mode}: rc={rc} err vs oracle compressed marching {e:.2e}, "
+        f"vs plain marching {e_plain:.2e} (oracle's own {O.rel_error(qref, qplain, area):.2e}); "
+        f"far/near blocks {d.n_far_blocks}/{d.n_near_blocks}, CG iterations {d.total_iters}")
+    assert rc == C.CQM_OK and d.converged == 1 and d.n_far_blocks > 0
+    assert e < (1e-6 if mode == C.CQM_FP64_H2ACA else 1e-4)
+    p.close()
+
+
+def test_compressed_marching_C1_against_plain(ctx, c1):
+    """320 triangles, N = 32, the configured compressed form with a tight MACA
+    tolerance: the compressed weights give the plain marching solution to
+    the approximation level."""
+    wl, V, T, qm, qa, area = c1
+    p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_FP64_H2ACA, marching=1, eps_aca=1e-10)
+    p.set_plane_wave()
+    q, rc, d = p.solve_marching()
+    e = O.rel_error(q.cpu().numpy(), qm, area)
+    say(f"compressed marching M=320 N=32: rc={rc} err vs oracle marching {e:.2e}, CG iterations "
+        f"{d.total_iters}, setup {d.t_setup_ms:.1f} ms, steps {d.t_solve_ms:.1f} ms")
+    assert rc == C.CQM_OK and e < 1e-6
+    p.close()
+
+
 def test_marching_argument_checks(ctx):
     wl = W.C0_TINY
     V, T = wl.mesh()
     for kw in ({"marching": 0}, {"marching": 1, "form": C.CQM_FORM_MATRIX_FREE},
-               {"marching": 1, "mode": C.CQM_MIXED_H2ACA}):
+               {"marching": 1, "mode": C.CQM_MIXED_H2ACA, "aca_band": C.CQM_BAND_HALF},
+               {"marching": 1, "mode": C.CQM_MIXED_H2ACA, "precond": C.CQM_PRECOND_NONE}):
         p = Problem(ctx, V, T, wl.N, wl.T, **kw)
         p.set_plane_wave()
         with pytest.raises(C.CqmError) as e:
