@@ -747,6 +747,10 @@ def main():
         out["serving"] = run_serving(C, torch, ctx, args.serve_rate, args.serve_seconds,
                                      args.serve_large)
         print("serving done", file=sys.stderr, flush=True)
+        # the 5120-triangle requests alone at 20 per second (C5's rate): the
+        # continuously batched requests share one cached operator
+        out["serving_5120_20per_s"] = run_serving(C, torch, ctx, 20.0, 10.0, large_frac=0.0)
+        print("serving at 20/s done", file=sys.stderr, flush=True)
     C.cqm_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
