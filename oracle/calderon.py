@@ -49,7 +49,8 @@ from .cqm import (classify_pairs, forward_dft, frequencies, gauss_legendre01, in
                   assemble_V)
 
 __all__ = ["normals", "static_K_edge", "static_K_vertex", "near_static_K", "remainder_K",
-           "near_dynamic_K", "far_entries_K", "assemble_K", "solve_direct"]
+           "near_dynamic_K", "far_entries_K", "assemble_K", "solve_direct", "static_Kp_edge",
+           "static_Kp_vertex", "near_static_Kp", "assemble_Kp"]
 
 FOUR_PI = 4.0 * math.pi
 
@@ -229,3 +230,98 @@ def solve_direct(V, T, N, Tend, rho=None, q=5, direction=(1.0, 0.0, 0.0), sigma=
         return dict(q=qn, s=s, rho=rho, dt=dt, b=b, bhat=bhat, ghat=ghat, xhat=xhat,
                     im_ratio=im_ratio)
     return qn
+
+
+def static_Kp_edge(A, B, C, D, ni, q):
+    """Integral of -(x - y).n_i / (4 pi |x - y|^3) over tau x t, tau = (A,B,C)
+    (target, unit normal ni), t = (A,B,D) (source): the adjoint double
+    layer's kernel d/dn_x 1/(4 pi r).  n_i is orthogonal to e and c, so
+    -(x - y).n_i = beta (d.n_i), and the radial integral is 1/2 as for K."""
+    e, c, d = B - A, C - A, D - A
+    at = 0.5 * np.linalg.norm(np.cross(e, c), axis=-1)
+    bt = 0.5 * np.linalg.norm(np.cross(e, d), axis=-1)
+    dn = np.sum(d * ni, axis=-1)
+    x, w = gauss_legendre01(q)
+    acc = np.zeros(at.shape)
+    for p, wp in zip(x, w):
+        for r, wr in zip(x, w):
+            pieces = [
+                ((1 - p), p, r, 1.0),
+                (p * (1 - r), p * r, 1.0, p),
+                (-p * (1 - r), 1.0, p * r, p),
+                (-p, r, 1 - p, 1.0),
+            ]
+            for dl, al, be, jac in pieces:
+                v = dl * e + al * c - be * d
+                nv = np.linalg.norm(v, axis=-1)
+                acc += wp * wr * jac * be / (nv * nv * nv)
+    return at * bt / (2.0 * math.pi) * dn * acc
+
+
+def static_Kp_vertex(P, A1, A2, B1, B2, ni, q):
+    """The adjoint double layer for a vertex pair, tau = (P,A1,A2) (target,
+    normal ni), t = (P,B1,B2): a lies in the target plane, so
+    -(x - y).n_i = zeta b.n_i, with zeta = w xi in the first half and the
+    radial variable zeta in the second; the radial integral is 1/2 in both:
+        K' = |tau||t| / (2 pi) int_[0,1]^3 ( w^2 b.n_i / |a - w b|^3
+                                             + w b.n_i / |w a - b|^3 )."""
+    a1, a2, b1, b2 = A1 - P, A2 - P, B1 - P, B2 - P
+    at = 0.5 * np.linalg.norm(np.cross(a1, a2), axis=-1)
+    bt = 0.5 * np.linalg.norm(np.cross(b1, b2), axis=-1)
+    x, w = gauss_legendre01(q)
+    acc = np.zeros(at.shape)
+    for th, wt in zip(x, w):
+        b = b1 + th * (b2 - b1)
+        bn = np.sum(b * ni, axis=-1)
+        for eta, we in zip(x, w):
+            a = a1 + eta * (a2 - a1)
+            for u, wu in zip(x, w):
+                d1 = np.linalg.norm(a - u * b, axis=-1)
+                d2 = np.linalg.norm(u * a - b, axis=-1)
+                acc += we * wt * wu * bn * (u * u / (d1 * d1 * d1) + u / (d2 * d2 * d2))
+    return at * bt / (2.0 * math.pi) * acc
+
+
+def near_static_Kp(V, T, pairs, q=5):
+    """Static part of the adjoint double layer K' (normal derivative at the
+    target, eq. wavebio) for every near pair."""
+    n = normals(V, T)
+    out = np.zeros(len(pairs))
+    ident, edge, vert = classify_pairs(T, pairs)
+    pi = np.asarray([p[0] for p in pairs])
+    if len(edge):
+        k = edge[:, 0]
+        out[k] = static_Kp_edge(V[edge[:, 1]], V[edge[:, 2]], V[edge[:, 3]], V[edge[:, 4]],
+                                n[pi[k]], q)
+    if len(vert):
+        k = vert[:, 0]
+        out[k] = static_Kp_vertex(V[vert[:, 1]], V[vert[:, 2]], V[vert[:, 3]], V[vert[:, 4]],
+                                  V[vert[:, 5]], n[pi[k]], q)
+    return out
+
+
+def assemble_Kp(V, T, s, q=5, pairs=None, static=None):
+    """Dense piecewise-constant Galerkin matrix of the adjoint double layer,
+    K'(s)[i,j] = int_tau_i int_tau_j d/dn_x G(x - y, s), kernel
+    -(1 + s r) exp(-s r)(x - y).n_x / (4 pi r^3) with n_x the target's normal."""
+    X, W, _ = triangle_quadrature(V, T)
+    n = normals(V, T)
+    M = len(T)
+    if pairs is None:
+        pairs = near_pairs(T)
+    if static is None:
+        static = near_static_Kp(V, T, pairs, q)
+    d = X[:, :, None, None, :] - X[None, None, :, :, :]
+    r = np.linalg.norm(d, axis=-1)
+    dn = np.einsum("iajbk,ik->iajb", d, n)
+    safe = np.where(r > 0.0, r, 1.0)
+    kf = np.where(r > 0.0, -(1.0 + s * safe) * np.exp(-s * safe) * dn / (FOUR_PI * safe ** 3), 0.0)
+    out = np.einsum("ia,iajb,jb->ij", W, kf, W).astype(np.complex128)
+    for k, (i, j, _) in enumerate(pairs):
+        dd = X[i][:, None, :] - X[j][None, :, :]
+        rr = np.linalg.norm(dd, axis=-1)
+        dni = dd @ n[i]
+        sr = np.where(rr > 0.0, rr, 1.0)
+        val = np.where(rr > 0.0, -remainder_K(s * sr) * dni / (FOUR_PI * sr ** 3), 0.0)
+        out[i, j] = static[k] + W[i] @ val @ W[j]
+    return out

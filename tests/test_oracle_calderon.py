@@ -185,3 +185,47 @@ def test_direct_solve_radial_data_gives_sphere_transfer_function():
         mean = (q * area).sum(1) / area.sum()
         errs.append(np.linalg.norm(mean - scalar[:, 0]) / np.linalg.norm(scalar))
     assert errs[1] < 0.03 and errs[0] / errs[1] > 2.5
+
+
+def test_adjoint_static_rules_against_solid_angle():
+    """K'[tau, t] is K[t, tau]: the adjoint rules (target normal) against the
+    solid-angle reference with the roles of the triangles exchanged."""
+    A, B, C = np.array([0., 0, 0]), np.array([1., 0, 0]), np.array([0.4, 0.9, 0.0])
+    D = np.array([0.5, 0.0, 0.8])
+    ni = _unit(np.cross(B - A, C - A))
+    ref = double_layer_reference((A, B, D), (A, B, C))
+    assert abs(K.static_Kp_edge(A, B, C, D, ni, 12) - ref) < 1e-10 * abs(ref)
+    B1, B2 = np.array([-0.8, 0.1, 0.2]), np.array([-0.3, -0.9, 0.1])
+    ref = double_layer_reference((A, B1, B2), (A, B, C))
+    assert abs(K.static_Kp_vertex(A, B, C, B1, B2, ni, 12) - ref) < 1e-10 * abs(ref)
+
+
+@pytest.mark.parametrize("s", [0.0, 1.0 + 2.0j])
+def test_adjoint_is_the_transpose(s):
+    """For piecewise constants on both sides the Galerkin matrix of K' (normal
+    derivative at the target) is the transpose of K's; the two are coded
+    separately (other normal, other sign, other Duffy rules)."""
+    V, T = W.ellipsoid(1, (1.3, 0.8, 1.0))
+    A, B = K.assemble_K(V, T, s), K.assemble_Kp(V, T, s)
+    assert np.linalg.norm(B - A.T) <= 1e-13 * np.linalg.norm(A)
+
+
+def test_neumann_trace_of_the_single_layer_potential():
+    """Exterior jump relation (eq. wavebio): the single-layer potential of the
+    indirect density phi (V phi = g) has the Neumann trace (-1/2 + K') phi,
+    which the direct formulation computes as q from the same g; the two
+    Galerkin answers approach each other as h falls."""
+    s = 1.0 + 1.5j
+    x0 = np.array([0.1, 0.05, -0.1])
+    errs = []
+    for level in (1, 2, 3):
+        V, T = W.ellipsoid(level, (1.3, 0.8, 1.0))
+        X, Wt, area = O.triangle_quadrature(V, T)
+        u, _ = _point_source(X, K.normals(V, T)[:, None, :], x0, s)
+        g = (Wt * u).sum(1) / area
+        A = O.assemble_V(V, T, s)
+        phi = sla.solve(A, area * g)
+        q = sla.solve(A, -0.5 * area * g + K.assemble_K(V, T, s) @ g)
+        lhs = -0.5 * area * phi + K.assemble_Kp(V, T, s) @ phi
+        errs.append(np.linalg.norm(lhs - area * q) / np.linalg.norm(area * q))
+    assert errs[2] < 0.05 and errs[0] / errs[1] > 1.5 and errs[1] / errs[2] > 1.5
