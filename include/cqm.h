@@ -348,13 +348,15 @@ int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
 /* y_l = K(s_l) x_l for l = l0 .. l0+nl-1: the piecewise-constant Galerkin
  * matrices of the double-layer operator of Section 2.2 (eq. wavebio),
  * K_l[m,i] = <phi_m, K(s_l) phi_i>, kernel d/dn_y exp(-s r)/(4 pi r) with
- * n_y the unit normal of the source triangle in its vertex order; FP64,
- * far field matrix-free.  x, y: device complex128 arrays nl x M
- * (caller-owned, must not overlap).  Needs a problem created with
- * formulation = CQM_FORMULATION_DIRECT (the workspace holds K's near values
- * and partial sums), else CQM_EINVAL; CQM_EINVAL for a frequency range
- * outside the solved band; CQM_ENOMEM without a workspace. */
-int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y,
+ * n_y the unit normal of the source triangle in its vertex order; with
+ * adjoint != 0 the adjoint double layer K' of the same equation (kernel
+ * d/dn_x, the target's normal; for piecewise constants its matrix is K's
+ * transpose).  FP64, far field matrix-free.  x, y: device complex128
+ * arrays nl x M (caller-owned, must not overlap).  Needs a problem created
+ * with formulation = CQM_FORMULATION_DIRECT (the workspace holds K's near
+ * values and partial sums), else CQM_EINVAL; CQM_EINVAL for a frequency
+ * range outside the solved band; CQM_ENOMEM without a workspace. */
+int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, int32_t adjoint, const void* x, void* y,
                 hipStream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, serving

@@ -156,7 +156,7 @@ def load_library():
         "cqm_frequencies": (ctypes.c_int, [I32, D, D, P, P]),
         "cqm_apply_V": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_apply_V_noalloc": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
-        "cqm_apply_K": (ctypes.c_int, [P, I32, I32, P, P, P]),
+        "cqm_apply_K": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_near_entries": (ctypes.c_int, [P, ctypes.POINTER(I64), P, P, P]),
         "cqm_operator_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_diag)]),
         "cqm_server_default_options": (ctypes.c_int, [ctypes.POINTER(cqm_server_opts)]),
@@ -286,8 +286,8 @@ def cqm_apply_V_noalloc(p, l0, nl, precision, x_ptr, y_ptr, stream=0):
                                                      ctypes.c_void_p(stream)))
 
 
-def cqm_apply_K(p, l0, nl, x_ptr, y_ptr, stream=0):
-    return _check(load_library().cqm_apply_K(p, l0, nl, ctypes.c_void_p(x_ptr),
+def cqm_apply_K(p, l0, nl, x_ptr, y_ptr, stream=0, adjoint=0):
+    return _check(load_library().cqm_apply_K(p, l0, nl, int(adjoint), ctypes.c_void_p(x_ptr),
                                              ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream)))
 
 

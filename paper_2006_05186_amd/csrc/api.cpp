@@ -264,7 +264,7 @@ int cqm_problem_destroy(cqm_problem_t p) {
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
                   p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea64u, p->dev.pb64u, p->dev.ftab, p->dev.ea32,
-                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box, p->dev.nrm64, p->dev.nearK_static};
+                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box, p->dev.nrm64, p->dev.nearK_static, p->dev.near_tpos};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -413,7 +413,7 @@ int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision, cons
   });
 }
 
-int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y,
+int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, int32_t adjoint, const void* x, void* y,
                 hipStream_t stream) {
   return guarded([&] {
     require(p && x && y, CQM_EINVAL, "NULL argument");
@@ -426,7 +426,7 @@ int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y,
     const int M = (int)p->M;
     launch_apply_K(*p, l0, nl, (const cf64*)x, M, nullptr, 0.0, (cf64*)y, M,
                    reinterpret_cast<const cf64*>(p->ws + p->lay.nearK),
-                   reinterpret_cast<cf64*>(p->ws + p->lay.kpart), stream);
+                   reinterpret_cast<cf64*>(p->ws + p->lay.kpart), adjoint != 0, stream);
     return CQM_OK;
   });
 }

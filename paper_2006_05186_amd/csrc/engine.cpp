@@ -271,7 +271,7 @@ void pre_solve(SolveState& st, hipStream_t s, bool prepare, bool timed) {
     Timed t(p, CQM_K_FAR64, s);
     launch_div_area(p, p.Fsys, g, M, c, s);
     launch_apply_K(p, 0, p.Fsys, c, M, g, -0.5, g, M, wsp<cf64>(p, p.lay.nearK),
-                   wsp<cf64>(p, p.lay.kpart), s);
+                   wsp<cf64>(p, p.lay.kpart), false, s);
   }
 }
 

@@ -238,6 +238,7 @@ struct MeshDev {
   // triangles (vertex order), the static near part of K (nnz)
   double4* nrm64 = nullptr;
   double* nearK_static = nullptr;
+  int32_t* near_tpos = nullptr;   // nnz: position of pair (j, i) for pair (i, j)
 };
 // Frequency-dependent cut-off radii of a system: tiles whose box gap is at
 // least cut32 (inner precision) or cut64 (FP64 operator) are left out.
@@ -382,7 +383,7 @@ void launch_nearK_static(const Problem& p, hipStream_t s);
 void launch_nearK_values(const Problem& p, cf64* vals, hipStream_t s);
 void launch_apply_K(const Problem& p, int l0, int nsys, const cf64* x, int64_t xs, const cf64* z,
                     double alpha, cf64* y, int64_t ys, const cf64* nvals, cf64* partial,
-                    hipStream_t s);
+                    bool adjoint, hipStream_t s);
 void launch_div_area(const Problem& p, int nsys, const cf64* g, int64_t gs, cf64* c, hipStream_t s);
 size_t dl_partial_bytes(int M, int Fs);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)

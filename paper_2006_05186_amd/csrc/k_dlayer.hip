@@ -178,7 +178,10 @@ __global__ __launch_bounds__(128) void k_nearK_values(const double4* __restrict_
 // Far pairs, matrix-free: one thread per target triangle and kDlFT
 // frequencies; source triangles staged through LDS (points, vertex ids,
 // normals, coefficients); the source range split over blockIdx.z, partial
-// sums reduced in a fixed order by k_dl_reduce_near.
+// sums reduced in a fixed order by k_dl_reduce_near.  kAdj: the adjoint
+// double layer K' (normal derivative at the target, eq. wavebio), kernel
+// -(1 + s r) exp(-s r)(x - y).n_x / (4 pi r^3) with the target's normal.
+template <bool kAdj>
 __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ pts,
                                                    const int4* __restrict__ vid,
                                                    const double4* __restrict__ nrm, int M,
@@ -199,6 +202,7 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
     tw[a] = q.w;
   }
   const int4 tv = vid[ic];
+  const double4 ni = nrm[ic];
   double sr[kDlFT], si[kDlFT], are[kDlFT], aim[kDlFT];
 #pragma unroll
   for (int l = 0; l < kDlFT; ++l) {
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
       if ((tv.x == w4.x) | (tv.x == w4.y) | (tv.x == w4.z) | (tv.y == w4.x) | (tv.y == w4.y) |
           (tv.y == w4.z) | (tv.z == w4.x) | (tv.z == w4.y) | (tv.z == w4.z))
         continue;
-      const double4 nj = sn[jj];
+      const double4 nj = kAdj ? double4{-ni.x, -ni.y, -ni.z, 0.0} : sn[jj];
       double vre[kDlFT], vim[kDlFT];
 #pragma unroll
       for (int l = 0; l < kDlFT; ++l) vre[l] = vim[l] = 0.0;
@@ -273,12 +277,14 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
 }
 
 // y_l[i] = alpha z_l[i] + sum_q partial[q][l][i] + sum_{k in near row i}
-// Knear_l[k] x_l[col k]; z may be y itself (read before the write).
+// Knear_l[k] x_l[col k]; z may be y itself (read before the write).  With
+// tpos (the adjoint) the near value of pair (i, j) is K's value of (j, i):
+// the same integral with the roles exchanged.
 __global__ __launch_bounds__(256) void k_dl_reduce_near(
     const cf64* __restrict__ partial, int S, int nsys, int M, const cf64* __restrict__ x,
     int64_t xs, const cf64* z, double alpha, cf64* y, int64_t ys,
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const cf64* __restrict__ nvals, int64_t nnz) {
+    const int32_t* __restrict__ tpos, const cf64* __restrict__ nvals, int64_t nnz) {
   const int l = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(256) void k_dl_reduce_near(
   const cf64* xl = x + (int64_t)l * xs;
   const cf64* nv = nvals + (int64_t)l * nnz;
   for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const cf64 a = nv[k], b = xl[col[k]];
+    const cf64 a = nv[tpos ? tpos[k] : k], b = xl[col[k]];
     re += a.re * b.re - a.im * b.im;
     im += a.re * b.im + a.im * b.re;
   }
@@ -352,18 +358,22 @@ void launch_nearK_values(const Problem& p, cf64* vals, hipStream_t s) {
 
 void launch_apply_K(const Problem& p, int l0, int nsys, const cf64* x, int64_t xs, const cf64* z,
                     double alpha, cf64* y, int64_t ys, const cf64* nvals, cf64* partial,
-                    hipStream_t s) {
+                    bool adjoint, hipStream_t s) {
   const int M = (int)p.M;
   int chunk = 0;
   const int S = dl_splits(M, nsys, &chunk);
   dim3 grid((M + kDlTgt - 1) / kDlTgt, (nsys + kDlFT - 1) / kDlFT, S);
-  hipLaunchKernelGGL(k_dl_far, grid, dim3(kDlTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64, M,
-                     p.dev.s, l0, nsys, x, xs, partial, chunk);
+  if (adjoint)
+    hipLaunchKernelGGL(k_dl_far<true>, grid, dim3(kDlTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64,
+                       M, p.dev.s, l0, nsys, x, xs, partial, chunk);
+  else
+    hipLaunchKernelGGL(k_dl_far<false>, grid, dim3(kDlTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64,
+                       M, p.dev.s, l0, nsys, x, xs, partial, chunk);
   CQM_HIP(hipGetLastError());
   const int64_t nnz = (int64_t)p.col.size();
   hipLaunchKernelGGL(k_dl_reduce_near, dim3((M + 255) / 256, nsys), dim3(256), 0, s, partial, S,
                      nsys, M, x, xs, z, alpha, y, ys, p.dev.near_rowptr, p.dev.near_col,
-                     nvals + (int64_t)l0 * nnz, nnz);
+                     adjoint ? p.dev.near_tpos : nullptr, nvals + (int64_t)l0 * nnz, nnz);
   CQM_HIP(hipGetLastError());
 }
 

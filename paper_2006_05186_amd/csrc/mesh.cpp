@@ -113,6 +113,21 @@ void upload_problem(Problem& p) {
   p.dev.near_row = upload(krow);
   p.dev.near_kind = upload(p.kind);
   p.dev.near_vtx = upload(p.nvtx);
+  {
+    // position of pair (j, i) for every pair (i, j) (the pattern is
+    // symmetric: sharing a vertex is)
+    std::vector<int32_t> tpos(p.col.size());
+    for (int64_t i = 0; i < M; ++i)
+      for (int k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k) {
+        const int j = p.col[k];
+        const int32_t* b = p.col.data() + p.rowptr[j];
+        const int32_t* e = p.col.data() + p.rowptr[j + 1];
+        const int32_t* f = std::lower_bound(b, e, (int32_t)i);
+        require(f != e && *f == i, CQM_EINVAL, "near-field pattern is not symmetric");
+        tpos[k] = (int32_t)(f - p.col.data());
+      }
+    p.dev.near_tpos = upload(tpos);
+  }
   CQM_HIP(hipMalloc(&p.dev.near_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
   CQM_HIP(hipMalloc(&p.dev.nearK_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
   std::vector<double> gx, gw;

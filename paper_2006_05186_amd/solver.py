@@ -60,14 +60,15 @@ class Problem:
                       torch.cuda.current_stream().cuda_stream)
         return y
 
-    def apply_K(self, x, l0=0):
-        """x: complex torch tensor (nl, M) on device; returns K(s_l) x_l (FP64;
-        needs formulation=CQM_FORMULATION_DIRECT at construction)."""
+    def apply_K(self, x, l0=0, adjoint=False):
+        """x: complex torch tensor (nl, M) on device; returns K(s_l) x_l, or
+        K'(s_l) x_l with adjoint (FP64; needs formulation=CQM_FORMULATION_DIRECT
+        at construction)."""
         torch = self.torch
         x = x.to(torch.complex128).contiguous()
         y = torch.empty_like(x)
         C.cqm_apply_K(self.handle, l0, x.shape[0], x.data_ptr(), y.data_ptr(),
-                      torch.cuda.current_stream().cuda_stream)
+                      torch.cuda.current_stream().cuda_stream, adjoint)
         return y
 
     def close(self):

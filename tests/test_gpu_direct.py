@@ -62,6 +62,31 @@ def test_apply_K_matches_oracle(ctx, ell, full):
     p.close()
 
 
+@pytest.mark.parametrize("full", [False, True])
+def test_apply_adjoint_K_matches_oracle(ctx, ell, full):
+    """K'(s_l) x_l (the adjoint double layer, target normal) against the
+    oracle's assemble_Kp, and the adjoint identity y.(K' x) = (K y).x."""
+    V, T, N, Tend = ell
+    kw = {"mode": C.CQM_MIXED_H2ACA} if full else {}
+    p = Problem(ctx, V, T, N, Tend, formulation=DIRECT, **kw)
+    s, _, _ = O.frequencies(N, Tend)
+    nl = len(s) if full else N // 2 + 1
+    x = W.random_complex((nl, len(T)), seed=23)
+    yv = W.random_complex((nl, len(T)), seed=24)
+    ka = p.apply_K(torch.as_tensor(x, device="cuda"), adjoint=True).cpu().numpy()
+    ky = p.apply_K(torch.as_tensor(yv, device="cuda")).cpu().numpy()
+    worst = 0.0
+    for l in (0, 1, nl // 2, nl - 1):
+        ref = OK.assemble_Kp(V, T, s[l]) @ x[l]
+        worst = max(worst, np.linalg.norm(ka[l] - ref) / np.linalg.norm(ref))
+    say(f"apply_K adjoint M={len(T)} frequencies {nl}: worst relative error {worst:.1e}")
+    assert worst < 1e-13
+    for l in range(nl):
+        lhs, rhs = yv[l] @ ka[l], ky[l] @ x[l]
+        assert abs(lhs - rhs) <= 1e-13 * (np.linalg.norm(yv[l]) * np.linalg.norm(ka[l]))
+    p.close()
+
+
 @pytest.fixture(scope="module")
 def oracle_direct(ell):
     V, T, N, Tend = ell
@@ -130,6 +155,15 @@ def test_apply_K_large_sampled_rows(ctx):
         e = np.linalg.norm(y[l][rows] - ref) / np.linalg.norm(ref)
         say(f"apply_K M=5120 l={l}: sampled rows relative error {e:.1e}")
         assert e < 1e-13
+    # the adjoint at full size: y.(K' x) = (K y).x for every frequency, K
+    # itself pinned by the sampled rows above
+    yv = W.random_complex((H, len(T)), seed=25)
+    ka = p.apply_K(torch.as_tensor(x, device="cuda"), adjoint=True).cpu().numpy()
+    ky = p.apply_K(torch.as_tensor(yv, device="cuda")).cpu().numpy()
+    worst = max(abs(yv[l] @ ka[l] - ky[l] @ x[l]) / (np.linalg.norm(yv[l]) * np.linalg.norm(ka[l]))
+                for l in range(H))
+    say(f"apply_K adjoint M=5120: worst adjoint-identity defect {worst:.1e}")
+    assert worst < 1e-13
     p.close()
 
 
