@@ -82,6 +82,14 @@ def ellipsoid(level: int, axes):
     return V * np.asarray(axes, dtype=np.float64)[None, :], T
 
 
+def two_spheres(level: int, distance: float = 6.0):
+    """Two unit icospheres with centres `distance` apart on the x axis (two
+    scatterers; far apart, their clusters form large admissible blocks)."""
+    V, T = icosphere(level)
+    V2 = V + np.asarray([distance, 0.0, 0.0])[None, :]
+    return np.concatenate([V, V2]), np.concatenate([T, T + len(V)]).astype(np.int32)
+
+
 def level_for_triangles(M: int) -> int:
     for k in range(0, 8):
         if 20 * 4 ** k == M:

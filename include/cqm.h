@@ -89,7 +89,7 @@ typedef struct cqm_options {
                             already below 1e-13 also ends the system     */
   int32_t n_min;         /* cluster leaf size                        (32)   */
   double eta;            /* box admissibility parameter              (1.0)  */
-  int32_t cheb_m;        /* Chebyshev points per axis, rank m^3      (4)    */
+  int32_t cheb_m;        /* Chebyshev points per axis, rank m^3, 2..8 (4)   */
   double eps_aca;        /* MACA stopping tolerance                  (1e-6) */
   int32_t aca_band;      /* CQM_BAND_*                               (FULL) */
   int32_t q_duffy;       /* Gauss points per Duffy dimension (<= 16) (5)    */

@@ -28,7 +28,7 @@ void setup_structure(Problem& p) {
   if (!p.h2) p.h2 = new H2Operator();
   H2Operator& h = *p.h2;
   if (h.built) return;
-  require(p.opt.cheb_m <= 4, CQM_EINVAL, "compressed modes support cheb_m <= 4 (rank <= 64)");
+  require(p.opt.cheb_m >= 2 && p.opt.cheb_m <= 8, CQM_EINVAL, "compressed modes support cheb_m in [2, 8]");
   h2_build_structure(p, h);
   h.store_fp64 = mode_is_mixed(p.opt.mode) ? 0 : 1;
   const int ncl = (int)h.cl.size(), nleaf = (int)h.leaves.size();

@@ -84,7 +84,6 @@ __global__ __launch_bounds__(kMB) void k_maca(MacaArgs A) {
   __shared__ double redm[NW];
   __shared__ int redi[NW];
   __shared__ unsigned char used[kMaxSys];
-  __shared__ double cc_s[2 * 64], dd_s[2 * 64];
   for (int k = tid; k < F; k += kMB) used[k] = 0;
   int kpiv = 0, rank = R;
   double G2 = 0.0;
@@ -199,8 +198,6 @@ __global__ __launch_bounds__(kMB) void k_maca(MacaArgs A) {
         cross += cr * dr - ci * di;  // Re(<C_l,C_t><d_l,d_t>)
       }
     }
-    (void)cc_s;
-    (void)dd_s;
     G2 += nrm * dn + 2.0 * cross;
     if (tid == 0) used[kpiv] = 1;
     if (sqrt(nrm * dn) <= A.eps * sqrt(fmax(G2, 0.0))) {
@@ -292,12 +289,15 @@ __global__ __launch_bounds__(256) void k_maca_finalize(const BlockDesc* __restri
     }
     return;
   }
-  // expanded far block: O = U_r C_t U_c^T, 16 rows of T = U_r C_t at a time
-  __shared__ cf64 Tsh[16 * 64];
+  // expanded far block: O = U_r C_t U_c^T, kTsh / P rows of T = U_r C_t at
+  // a time (16 rows for p <= 64, 2 for p = 512)
+  constexpr int kTsh = 1024;
+  __shared__ cf64 Tsh[kTsh];
+  const int rows_per = max(1, kTsh / P);
   const double* Ur = Ufull + uoff[B.r];
   const double* Uc = Ufull + uoff[B.c];
-  for (int i0 = 0; i0 < B.arows; i0 += 16) {
-    const int nr = min(16, B.arows - i0);
+  for (int i0 = 0; i0 < B.arows; i0 += rows_per) {
+    const int nr = min(rows_per, B.arows - i0);
     for (int e = threadIdx.x; e < nr * P; e += blockDim.x) {
       const int i = i0 + e / P, nu = e % P;
       double re = 0.0, im = 0.0;
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_maca_finalize(const BlockDesc* __restri
 }
 
 void launch_maca_finalize_batch(const Problem& p, H2Operator& h, int b0, int nb, hipStream_t s) {
-  require(h.p <= 64, CQM_EINVAL, "interpolation rank above 64 is not supported");
+  require(h.p <= 1024, CQM_EINVAL, "interpolation rank above 1024 is not supported");
   const size_t lds = 0;
   dim3 grid(nb, h.Rcap);
   if (h.store_fp64)

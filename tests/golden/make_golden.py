@@ -5,13 +5,17 @@ root:
     python tests/golden/make_golden.py            # sphere1280_N64_T4
     python tests/golden/make_golden.py --c3 -j 7  # sphere5120_N128_T6
     python tests/golden/make_golden.py --h2m4     # sphere1280_N16_T2_h2m4
+    python tests/golden/make_golden.py --h2order  # two_spheres640_N16_T2_h2
 Outputs tests/golden/<workload>.npz with the density q (N+1, M) and the
 frequency-domain solutions xhat (distinct frequencies); the 1280-triangle file
 also holds the forward-transformed data ghat and the static near-field values.
 The h2m4 file holds the oracle's compressed operator (Algorithm 3: leaf size
 32, eta = 1, Chebyshev order m = 4, MACA tolerances 1e-6 and 1e-10, near
 blocks formed on demand) applied to a seeded input, with its block counts
-and ranks.
+and ranks.  The h2 file of two 320-triangle spheres six radii apart holds the
+same for Chebyshev orders m = 4 .. 8 (leaf size 16, eta = 1, tolerance 1e-10,
+near blocks from the dense tensor) and the plain product: the two spheres' clusters form admissible
+blocks of 320 x 320, stored as Tucker cores for m <= 6 and expanded for m >= 7.
 
 The 5120-triangle file is the same all-at-once oracle solve: its frequencies
 are independent (one dense assembly and LU each), so they are spread over
@@ -102,13 +106,43 @@ def _h2m4():
     np.savez_compressed(os.path.join(HERE, "sphere1280_N16_T2_h2m4.npz"), **out)
 
 
+ORDERS = (4, 5, 6, 7, 8)
+
+
+def _h2order():
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
+    V, T = W.two_spheres(2)
+    N, Tend = 16, 2.0
+    s, _, _ = O.frequencies(N, Tend)
+    x = W.random_complex((len(s), len(T)), seed=32)
+    t = time.time()
+    dense = O.dense_tensor(V, T, s)
+    print(f"dense tensor {time.time() - t:.0f}s", flush=True)
+    out = {"x": x, "y_plain": np.einsum("ijl,lj->li", dense, x)}
+    for m in ORDERS:
+        t = time.time()
+        op = O.build_compressed(V, T, s, 16, 1.0, m, 1e-10, dense=dense)
+        out[f"y_m{m}"] = O.compressed_matvec(op, x)
+        out[f"ranks_m{m}"] = np.asarray([b["rank"] for b in op["blocks"]])
+        out[f"kinds_m{m}"] = np.asarray([b["kind"] == "far" for b in op["blocks"]])
+        print(f"m {m}: {len(op['far'])} far / {len(op['near'])} near blocks, "
+              f"{time.time() - t:.0f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "two_spheres640_N16_T2_h2.npz"), **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--c3", action="store_true", help="the 5120-triangle workload")
     ap.add_argument("-j", type=int, default=4, help="worker processes (--c3)")
     ap.add_argument("--h2m4", action="store_true", help="compressed operator, m = 4")
+    ap.add_argument("--h2order", action="store_true",
+                    help="compressed operator of two spheres, m = 4 .. 8")
     a = ap.parse_args()
-    if a.h2m4:
+    if a.h2order:
+        _h2order()
+    elif a.h2m4:
         _h2m4()
     elif a.c3:
         for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):

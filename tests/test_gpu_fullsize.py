@@ -183,9 +183,49 @@ def test_compressed_C3_against_stored_oracle(ctx):
 
 
 @pytest.fixture(scope="module")
+def ordercase():
+    """Two 320-triangle spheres six radii apart, N = 16: the spheres' clusters
+    form two admissible 320 x 320 blocks (Tucker cores for m <= 6, expanded
+    for m >= 7) beside small far and near blocks within each sphere.  The
+    oracle's compressed operators for m = 4 .. 8 applied to a seeded input
+    are stored (tests/golden/two_spheres640_N16_T2_h2.npz,
+    make_golden.py --h2order), with the plain product."""
+    V, T = W.two_spheres(2)
+    return V, T, 16, 2.0, _golden("two_spheres640_N16_T2_h2")
+
+
+@pytest.mark.parametrize("m", [4, 5, 6, 7, 8])
+def test_compressed_orders_match_oracle(ctx, ordercase, m):
+    """Chebyshev orders m = 4 .. 8 (p = 64 .. 512): cores, transfers and the
+    expansion of far blocks against the oracle's operator; the interpolation
+    error against the plain product falls with m (Section 4.2)."""
+    V, T, N, Tend, g = ordercase
+    x, ref, plain = g["x"], g[f"y_m{m}"], g["y_plain"]
+    oranks, far = g[f"ranks_m{m}"], g[f"kinds_m{m}"]
+    nfar, nnear = int(far.sum()), int((~far).sum())
+    for mode, tol in ((C.CQM_FP64_H2ACA, 1e-12), (C.CQM_MIXED_H2ACA, 1e-6)):
+        say(f"compressed m={m} two spheres mode={mode}")
+        p = Problem(ctx, V, T, N, Tend, mode=mode, n_min=16, eta=1.0, cheb_m=m, eps_aca=1e-10)
+        y = p.apply(torch.as_tensor(x, device="cuda"), 0, 64).cpu().numpy()
+        st = C.cqm_operator_stats(p.handle)
+        same_pivots = (st.max_rank == int(oranks.max()) and
+                       abs(st.mean_rank - float(np.mean(oranks))) < 1e-12)
+        worst = max(np.linalg.norm(y[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(len(x)))
+        interp = max(np.linalg.norm(y[l] - plain[l]) / np.linalg.norm(plain[l]) for l in range(len(x)))
+        say(f"  far/near {st.n_far_blocks}/{st.n_near_blocks}, ranks max {st.max_rank} mean "
+            f"{st.mean_rank:.4f} (oracle {int(oranks.max())} {float(np.mean(oranks)):.4f}); "
+            f"error vs oracle {worst:.2e}, vs plain {interp:.2e}")
+        assert (st.n_far_blocks, st.n_near_blocks) == (nfar, nnear)
+        bound = tol if (same_pivots or mode == C.CQM_MIXED_H2ACA) else 1e-9
+        assert worst < bound, (mode, worst, bound)
+        p.close()
+
+
+@pytest.fixture(scope="module")
 def m4case():
     """1280-triangle sphere, N = 16: leaf size 32 and eta = 1 give admissible
-    blocks, so the p = 64 Tucker cores and transfers are exercised.  The
+    blocks (all small enough to be expanded; the p = 64 Tucker cores and
+    transfers are exercised by the two-sphere case above).  The
     oracle's compressed operator applied to a seeded input is stored
     (tests/golden/sphere1280_N16_T2_h2m4.npz, make_golden.py --h2m4): its
     build takes minutes on the CPU."""
