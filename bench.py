@@ -13,6 +13,7 @@ plane wave, solved in the mixed stored form; its error is measured against
 the stored oracle solution of the same workload.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -289,6 +290,48 @@ def run_compressed(C, torch, ctx, only=None):
     return {"workload": wl.name} | res
 
 
+def run_orders(C, torch, ctx, orders=(4, 5, 6), etas=(1.0, 0.5)):
+    """The compressed approximation itself (refined with the compressed
+    operator, as the paper solves) on the 5120-triangle sphere, N = 128, T = 6
+    for Chebyshev orders m and admissibility parameters eta (Section 4.2's
+    trade: the interpolation error falls with m and with eta), against the
+    stored oracle solution: error, ranks, storage, set-up and solve time."""
+    from paper_2006_05186_amd.solver import Problem
+    wl = W.C3
+    V, T = wl.mesh()
+    area = area_of(V, T)
+    ref = golden_q(wl)
+    res = {"workload": wl.name, "eps_aca": 1e-6, "n_min": 32}
+    for eta in etas:
+        for m in orders:
+            p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_H2ACA, form=C.CQM_FORM_DENSE,
+                        cheb_m=m, eta=eta, refine_plain=0)
+            p.set_plane_wave()
+            t0 = time.perf_counter()
+            p.solve()  # includes the set-up (MACA of every block)
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            q, rc, d = p.solve()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            r = {"m": m, "eta": eta, "rc": rc, "seconds_per_solve": el,
+                 "first_solve_s": first, "t_setup_ms": d.t_setup_ms,
+                 "operator_GB": d.operator_bytes / 1e9, "max_rank": d.max_rank,
+                 "mean_rank": d.mean_rank, "far_blocks": d.n_far_blocks,
+                 "near_blocks": d.n_near_blocks, "iters": d.total_iters}
+            if ref is not None:
+                r["error_vs_oracle"], r["max_step_error_vs_oracle"] = errors(q.cpu().numpy(), ref, area)
+            res[f"m{m}_eta{eta:g}"] = r
+            print(f"orders: m={m} eta={eta} done ({el:.2f} s, error "
+                  f"{r.get('error_vs_oracle', float('nan')):.2e})", file=sys.stderr, flush=True)
+            p.close()
+            del q
+            gc.collect()
+            torch.cuda.empty_cache()
+    return res
+
+
 def run_batch48(C, torch, ctx, sample=4):
     """Uneven batch: 48 seeded problems (spheres/ellipsoids of 80..5120
     triangles, N in {16,32,64,128}, random direction and pulse width) solved
@@ -341,7 +384,6 @@ def run_serving(C, torch, ctx, rate, duration, large_frac=0.2, check_every=8):
     the plain operator, on half of the compute units.  Every `check_every`-th
     5120-triangle request carries the stored oracle workload's pulse and is
     compared with the oracle's solution."""
-    import gc
     from paper_2006_05186_amd.solver import Server
     # the server takes its arena with one device allocation: hand back what
     # torch's caching allocator still holds from earlier records
@@ -612,7 +654,7 @@ def main():
                     help="only measure the lane-op rates of v_exp_f32, v_sin_f32, v_cos_f32, "
                          "v_rsq_f32 and FP32/FP64 FMA (lib/libcqm_probe.so) and exit")
     ap.add_argument("--part", choices=["far32", "compressed", "h2apply", "marching", "study",
-                                       "batch48"],
+                                       "batch48", "orders"],
                     help="only run one piece on the workload (for counter profiles) and print "
                          "its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -653,6 +695,8 @@ def main():
             rec = run_batch48(C, torch, ctx)
         elif args.part == "study":
             rec = run_study(C, torch, ctx)
+        elif args.part == "orders":
+            rec = run_orders(C, torch, ctx)
         elif args.part == "compressed":
             rec = run_compressed(C, torch, ctx, only=("compressed_mixed", "compressed_mixed_approx"))
         else:
@@ -742,6 +786,7 @@ def main():
         print("marching done", file=sys.stderr, flush=True)
         out["compressed"] = run_compressed(C, torch, ctx)
         print("compressed done", file=sys.stderr, flush=True)
+        out["compressed_orders"] = run_orders(C, torch, ctx)
         out["batch48"] = run_batch48(C, torch, ctx)
         print("batch48 done", file=sys.stderr, flush=True)
         out["serving"] = run_serving(C, torch, ctx, args.serve_rate, args.serve_seconds,

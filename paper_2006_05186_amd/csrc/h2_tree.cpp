@@ -241,10 +241,13 @@ void h2_build_structure(Problem& p, H2Operator& h) {
   }
   h.cstore_elems = coff;
   h.dvec_elems = doff;
-  // MACA batches bounded by a staging budget (cf64 elements)
+  // MACA batches bounded by a staging budget (cf64 elements): room for 512
+  // of the largest block tensors at once (two workgroups per compute unit),
+  // at least 2 GiB and at most 16 GiB unless one block needs more
   int64_t biggest = 0;
   for (auto& b : h.blocks) biggest = std::max<int64_t>(biggest, (int64_t)R * b.rows * b.cols);
-  h.stage_budget = std::max<int64_t>(biggest, (int64_t)1 << 27);  // 2 GiB of cf64
+  h.stage_budget = std::max<int64_t>(
+      biggest, std::min<int64_t>((int64_t)1 << 30, std::max<int64_t>((int64_t)1 << 27, 512 * biggest)));
   h.batches.clear();
   int64_t acc = 0;
   int b0 = 0;

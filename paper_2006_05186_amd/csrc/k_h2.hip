@@ -168,14 +168,20 @@ size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
 // ------------------------------------------------------------------
 // Block-rank products on the matrix cores: for every output row tile
 // (16 rows) and its task list,
-//   out[row, l] (+)= sum_tasks sum_t d_t[l] sum_j C_t[row, j] x[x_row0 + j, l],
-// the contraction of the MACA slices C_t with the cluster vectors, scaled by
+//   out[row, l] (+)= sum_tasks sum_t sum_j C_t[row, j] (d_t[l] x[x_row0 + j, l]),
+// the contraction of the MACA slices C_t with the cluster vectors scaled by
 // the frequency fibres d_t (eq. lrfinal).  One wave owns NF tiles of 16
-// frequencies; each rank term is a complex 16 x acols x 16 product done as
-// four real MFMA chains (re re, im im, re im, im re), then scaled by d_t[l]
-// and accumulated.  Columns are taken 32 at a time so the input block stays
-// in registers across the rank terms.  A workgroup holds as many waves as
-// its frequencies need, up to kRankWaves<R>.
+// frequencies.  The fibre value of the lane's frequency scales the B operand
+// (the input block) before each rank term, so consecutive terms accumulate
+// into the same four real MFMA chains (re re, im im, re im, im re) with no
+// dependence of one term on the result of the last; every kFlush terms the
+// chains are added into FP-R accumulators by the vector unit (long MFMA
+// chains lose accuracy: over all terms of a row tile the FP32 product's
+// error grows sevenfold).  Columns
+// are taken 32 at a time so the input block stays in registers across the
+// rank terms; the next term's slice entries and fibre values are loaded one
+// term ahead.  A workgroup holds as many waves as its frequencies need, up
+// to kRankWaves<R>.
 namespace {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
@@ -198,9 +204,9 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int L, int v) { return (L >> 4) + 4 * v; }
 };
 constexpr int kKC = 32;  // columns per register block
+constexpr int kFlush = 4;  // rank terms per MFMA chain
 // waves per workgroup: 4.  Wider workgroups (12 waves for FP32, 8 for FP64)
-// cut the FP32 far products' fetched bytes by half but measured no faster:
-// the products are bound by their rank loops, not by re-reads
+// cut the FP32 far products' fetched bytes by half but measured no faster
 template <typename R> constexpr int kRankWaves = 4;
 }  // namespace
 
@@ -210,19 +216,40 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
                                                       const int* __restrict__ ranks,
                                                       const cplx<S>* __restrict__ cstore,
                                                       const cf64* __restrict__ dvec, int dstride,
-                                                      int l0, int nsys,
+                                                      int l0, int nsys, int ntiles, int gy,
                                                       const cplx<R>* __restrict__ x,
                                                       cplx<R>* __restrict__ out) {
   using MF = Mfma<R>;
   using A4 = typename MF::acc;
-  const RankTile tl = tiles[blockIdx.x];
+  // Workgroups are dealt to the eight dies in turn, so the gy frequency
+  // workgroups of one row tile get ids eight apart: they run on one die and
+  // read the tile's slices through its L2 once.
+  const int grp = blockIdx.x / (8 * gy), rem = blockIdx.x % (8 * gy);
+  const int fy = rem >> 3, tile = grp * 8 + (rem & 7);
+  if (tile >= ntiles) return;  // padding of the last group; no barrier follows
+  const RankTile tl = tiles[tile];
   const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int fb = (blockIdx.y * (blockDim.x >> 6) + w) * 16 * NF;  // first frequency of this wave
+  const int fb = (fy * (blockDim.x >> 6) + w) * 16 * NF;  // first frequency of this wave
   if (fb >= nsys) return;                         // no barrier follows
   const int arow = L & 15, kq = L >> 4, col = L & 15;
-  A4 accr[NF], acci[NF];
+  const bool rowin = arow < tl.nrows;
+  // sums of Cr Br, Ci Bi, Cr Bi, Ci Br over the last terms; acc: the rest
+  A4 p1[NF], p2[NF], p3[NF], p4[NF], accr[NF], acci[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) accr[f] = acci[f] = MF::zero();
+  for (int f = 0; f < NF; ++f) p1[f] = p2[f] = p3[f] = p4[f] = accr[f] = acci[f] = MF::zero();
+  int chain = 0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        accr[f][v] += p1[f][v] - p2[f][v];
+        acci[f][v] += p3[f][v] + p4[f][v];
+      }
+      p1[f] = p2[f] = p3[f] = p4[f] = MF::zero();
+    }
+    chain = 0;
+  };
   for (int q = tl.t0; q < tl.t1; ++q) {
     const RankTask T = tasks[q];
     const int rk = ranks[T.block];
@@ -244,12 +271,13 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
           xr[s][f] = in ? v.re : R(0);
           xi[s][f] = in ? v.im : R(0);
         }
-      // slice entries of rank term t, loaded one term ahead of their use
-      const bool rowin = arow < tl.nrows;
+      // slice entries and fibre values of rank term t
       const cplx<S>* C0 = cstore + T.c_off + (int64_t)min(arow, tl.nrows - 1) * T.ldc + j0;
-      R ar[kKC / 4], ai[kKC / 4];
-      auto load_a = [&](int t, R* re, R* im) {
-        const cplx<S>* Cr = C0 + (int64_t)min(t, max(rk - 1, 0)) * T.cstride;
+      const cf64* D0 = dvec + T.d_off + l0;
+      R ar[kKC / 4], ai[kKC / 4], dr[NF], di[NF];
+      auto load_term = [&](int t, R* re, R* im, R* fr, R* fi) {
+        const int tc = min(t, max(rk - 1, 0));
+        const cplx<S>* Cr = C0 + (int64_t)tc * T.cstride;
 #pragma unroll
         for (int s = 0; s < kKC / 4; ++s) {
           const int j = 4 * s + kq;
@@ -258,36 +286,30 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
           re[s] = in ? (R)c.re : R(0);
           im[s] = in ? (R)c.im : R(0);
         }
-      };
-      load_a(0, ar, ai);
-      for (int t = 0; t < rk; ++t) {
-        R br[kKC / 4], bi[kKC / 4];
-        load_a(t + 1, br, bi);
-        A4 p1[NF], p2[NF], p3[NF], p4[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) p1[f] = p2[f] = p3[f] = p4[f] = MF::zero();
+        for (int f = 0; f < NF; ++f) {
+          const int l = fb + 16 * f + col;
+          const cf64 d = D0[(int64_t)tc * dstride + min(l, nsys - 1)];
+          fr[f] = (R)d.re;
+          fi[f] = (R)d.im;
+        }
+      };
+      load_term(0, ar, ai, dr, di);
+      for (int t = 0; t < rk; ++t) {
+        R br[kKC / 4], bi[kKC / 4], er[NF], ei[NF];
+        load_term(t + 1, br, bi, er, ei);
 #pragma unroll
         for (int s = 0; s < kKC / 4; ++s) {
           if (s < ks) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-              p1[f] = MF::mac(ar[s], xr[s][f], p1[f]);
-              p2[f] = MF::mac(ai[s], xi[s][f], p2[f]);
-              p3[f] = MF::mac(ar[s], xi[s][f], p3[f]);
-              p4[f] = MF::mac(ai[s], xr[s][f], p4[f]);
+              const R yr = dr[f] * xr[s][f] - di[f] * xi[s][f];
+              const R yi = dr[f] * xi[s][f] + di[f] * xr[s][f];
+              p1[f] = MF::mac(ar[s], yr, p1[f]);
+              p2[f] = MF::mac(ai[s], yi, p2[f]);
+              p3[f] = MF::mac(ar[s], yi, p3[f]);
+              p4[f] = MF::mac(ai[s], yr, p4[f]);
             }
-          }
-        }
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int l = fb + 16 * f + col;
-          const cf64 d = dvec[T.d_off + (int64_t)t * dstride + l0 + min(l, nsys - 1)];
-          const R dr = l < nsys ? (R)d.re : R(0), di = l < nsys ? (R)d.im : R(0);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const R zr = p1[f][v] - p2[f][v], zi = p3[f][v] + p4[f][v];
-            accr[f][v] += dr * zr - di * zi;
-            acci[f][v] += dr * zi + di * zr;
           }
         }
 #pragma unroll
@@ -295,9 +317,16 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
           ar[s] = br[s];
           ai[s] = bi[s];
         }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          dr[f] = er[f];
+          di[f] = ei[f];
+        }
+        if (++chain == kFlush) flush();
       }
     }
   }
+  flush();
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -329,9 +358,9 @@ static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* 
   const int ftiles = (nsys + 16 * NF - 1) / (16 * NF);
   const int gy = (ftiles + kRankWaves<R> - 1) / kRankWaves<R>;
   const int nw = (ftiles + gy - 1) / gy;
-  const dim3 grid(ntiles, gy);
+  const dim3 grid((unsigned)(((ntiles + 7) / 8) * 8 * gy));
   hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(64 * nw), 0, s, tiles, tasks, ranks,
-                     (const cplx<S>*)cstore, dvec, dstride, l0, nsys, x, out);
+                     (const cplx<S>*)cstore, dvec, dstride, l0, nsys, ntiles, gy, x, out);
   CQM_HIP(hipGetLastError());
 }
 
@@ -352,6 +381,19 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
   const unsigned gblk = (unsigned)(((int64_t)M * nsys + kHB - 1) / kHB);
   const int nch = (nsys + kLC - 1) / kLC;
   hipLaunchKernelGGL((k_h2_gather<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, x, xs, xp);
+  if (h.n_core == 0) {
+    // no block kept as a Tucker core (every admissible block small enough
+    // to be expanded): no cluster coefficients, the leaf products write y
+    if (h.store_fp64)
+      launch_rank_mfma<R, double, false>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
+                                         h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+    else
+      launch_rank_mfma<R, float, false>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
+                                        h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+    hipLaunchKernelGGL((k_h2_scatter<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, yp, y, ys);
+    CQM_HIP(hipGetLastError());
+    return;
+  }
   // 1. upward pass
   if (f32)
     hipLaunchKernelGGL((k_h2_up_leaf<R, float>), dim3(nleaf, nch), dim3(kHB), 0, s, h.cl_d, h.level_cl_d + h.level_off[h.nlevels],
