@@ -151,10 +151,11 @@ def test_compressed_C3_against_stored_oracle(ctx):
     oracle.  Refined with the compressed operator itself (refine_plain = 0)
     at the configured order (m = 4, eta = 1) the error is the Chebyshev
     interpolation error of the far field (about 5e-2 measured; Theorem
-    h2err: it falls with m and with stricter admissibility); with eta =
-    0.125 no block is admissible at this size and every block is compressed
-    across frequencies only, which must meet the 1e-5 bound of the mixed
-    compressed path.  With refinement residuals from the plain operator (the
+    h2err: it falls with m and with stricter admissibility); at m = 6 with
+    eta = 0.25 (1962 admissible blocks) and with eta = 0.125 (no admissible
+    block at this size: every block compressed across frequencies only) it
+    must meet the 1e-5 bound of the mixed compressed path.  With refinement
+    residuals from the plain operator (the
     default) the configured compressed form must give the plain solution,
     to the bar of solves with plain FP64 residuals."""
     wl = W.C3
@@ -162,14 +163,16 @@ def test_compressed_C3_against_stored_oracle(ctx):
     g = _golden(wl.name)
     _, _, area = O.triangle_quadrature(V, T)
     errs = {}
-    for eta, rp in ((1.0, 0), (0.125, 0), (1.0, 1)):
-        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_H2ACA, eta=eta, refine_plain=rp)
+    for m, eta, rp in ((4, 1.0, 0), (6, 0.25, 0), (4, 0.125, 0), (4, 1.0, 1)):
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=C.CQM_MIXED_H2ACA, eta=eta, refine_plain=rp,
+                    cheb_m=m)
         p.set_plane_wave()
         q, rc, d = p.solve()
         q = q.cpu().numpy()
         errs[eta, rp] = O.rel_error(q, g["q"], area)
+        assert d.n_far_blocks > 0 or eta < 0.25
         early = float(np.max(O.step_errors(q, g["q"], area)[: wl.N // 2 + 1]))
-        say(f"  compressed eta={eta} refine_plain={rp}: rc={rc} err vs oracle {errs[eta, rp]:.2e} "
+        say(f"  compressed m={m} eta={eta} refine_plain={rp}: rc={rc} err vs oracle {errs[eta, rp]:.2e} "
             f"(n <= N/2: {early:.1e}) "
             f"far/near blocks {d.n_far_blocks}/{d.n_near_blocks} max rank {d.max_rank} op "
             f"{d.operator_bytes / 1e9:.2f} GB, cycles {d.cycles}, solve {d.t_solve_ms:.0f} ms")
@@ -178,6 +181,7 @@ def test_compressed_C3_against_stored_oracle(ctx):
             assert early < C3_EARLY_TOL
         p.close()
     assert errs[1.0, 0] < 0.1
+    assert errs[0.25, 0] < 1e-5
     assert errs[0.125, 0] < 1e-5
     assert errs[1.0, 1] < C3_TOL_FP64_RESIDUAL
 
