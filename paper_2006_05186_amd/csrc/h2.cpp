@@ -96,6 +96,22 @@ void setup_structure(Problem& p) {
     }
     if (ck.empty()) ck.push_back(RankTask{});
     if (lk.empty()) lk.push_back(RankTask{});
+    // lag-0 tables: the same tasks over the compact collapsed slices (the
+    // slice store holds Rcap slices per block, c_off = Rcap x the compact
+    // offset; within a block the row offset is unchanged)
+    auto compact = [&](std::vector<RankTask> v) {
+      for (RankTask& t : v) {
+        if (t.acols == 0) continue;
+        const BlockDesc& B = h.blocks[t.block];
+        t.c_off = B.c_off / h.Rcap + (t.c_off - B.c_off);
+        t.d_off = 0;
+      }
+      return v;
+    };
+    h.core_tasks0_d = up(compact(ck));
+    h.leaf_tasks0_d = up(compact(lk));
+    h.ones_d = up(std::vector<int>(std::max<size_t>(h.blocks.size(), 1), 1));
+    h.one_d = up(std::vector<cf64>{cf64{1.0, 0.0}});
     h.core_tiles_d = up(ct);
     h.core_tasks_d = up(ck);
     h.leaf_tiles_d = up(lt);
@@ -147,6 +163,7 @@ void set_views(Problem& p) {
   h.xp_d = base + h.off_xp;
   h.yp_d = base + h.off_yp;
   h.dhat_d = h.off_dhat ? (cf64*)(base + h.off_dhat) : nullptr;
+  h.w0_d = h.off_w0 ? (void*)(base + h.off_w0) : nullptr;
 }
 }  // namespace
 
@@ -169,6 +186,9 @@ size_t h2_workspace_bytes(const Problem& pc) {
   h.off_yp = take(h2_perm_scratch_bytes(h, p.Fsys));
   // time marching: the fibres' transforms beside the fibres
   h.off_dhat = p.opt.marching ? take((size_t)h.dvec_elems * sizeof(cf64)) : 0;
+  h.off_w0 = p.opt.marching
+                 ? take((size_t)(h.cstore_elems / h.Rcap) * (h.store_fp64 ? sizeof(cf64) : sizeof(cf32)))
+                 : 0;
   h.total = off;
   return off;
 }
@@ -177,6 +197,7 @@ void h2_prepare(Problem& p, hipStream_t s) {
   setup_structure(p);
   set_views(p);
   H2Operator& h = *p.h2;
+  h.w0_ready = false;  // the slices change: collapse again before use
   for (auto& bt : h.batches) {
     const int nb = bt.second - bt.first;
     if (nb <= 0) continue;
@@ -217,7 +238,10 @@ void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, c
   set_views(p);
   H2Operator& h = *p.h2;
   require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
-  launch_h2_apply<double>(p, h, k0, nsys, x, xs, y, ys, h.dhat_d, s);
+  if (k0 == 0 && nsys == 1 && h.w0_ready)
+    launch_h2_apply_lag0(p, h, x, xs, y, ys, s);
+  else
+    launch_h2_apply<double>(p, h, k0, nsys, x, xs, y, ys, h.dhat_d, s);
 }
 
 void h2_marching_weights(Problem& p, hipStream_t s) {
@@ -225,6 +249,11 @@ void h2_marching_weights(Problem& p, hipStream_t s) {
   H2Operator& h = *p.h2;
   require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
   launch_fibre_dft(p, h, h.dvec_d, h.dhat_d, s);
+  // What_0 is applied in every conjugate-gradient iteration: collapse its
+  // rank terms once
+  require(h.w0_d != nullptr, CQM_EINVAL, "no lag-0 slices in the workspace");
+  launch_collapse_lag0(p, h, s);
+  h.w0_ready = true;
 }
 template void h2_apply<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
 template void h2_apply<double>(Problem&, int, int, const cf64*, int64_t, cf64*, int64_t, const int*, hipStream_t);
@@ -264,6 +293,10 @@ void h2_release(Problem& p) {
   release(h.core_tasks_d);
   release(h.leaf_tiles_d);
   release(h.leaf_tasks_d);
+  release(h.core_tasks0_d);
+  release(h.leaf_tasks0_d);
+  release(h.ones_d);
+  release(h.one_d);
   delete p.h2;
   p.h2 = nullptr;
 }

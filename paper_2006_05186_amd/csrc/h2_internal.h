@@ -101,11 +101,19 @@ struct H2Operator {
   RankTile* leaf_tiles_d = nullptr;
   RankTask* leaf_tasks_d = nullptr;
   int n_core_tiles = 0, n_leaf_tiles = 0;
+  // time marching, lag 0: the same tables over one collapsed slice per
+  // block (W0_b = sum_t dhat_t[0] C_t, compact: block b at c_off / Rcap),
+  // with rank 1 and fibre value 1
+  RankTask* core_tasks0_d = nullptr;
+  RankTask* leaf_tasks0_d = nullptr;
+  int* ones_d = nullptr;    // one entry per block, each 1
+  cf64* one_d = nullptr;    // a single 1 + 0i
   std::vector<int> level_off;
   // workspace regions (byte offsets from the problem's H2 region)
   size_t off_cstore = 0, off_dvec = 0, off_stage = 0, off_xhat = 0, off_yhat = 0, total = 0;
   size_t off_xp = 0, off_yp = 0;
   size_t off_dhat = 0;  // marching: the fibres' transforms (integration weights)
+  size_t off_w0 = 0;    // marching: collapsed lag-0 slices (storage precision)
   int64_t cstore_elems = 0, dvec_elems = 0, stage_elems = 0;
   int64_t stage_budget = 0;       // cf64 elements per MACA batch
   std::vector<std::pair<int, int>> batches;  // [b0, b1) per MACA launch
@@ -114,6 +122,8 @@ struct H2Operator {
   cf64* stage_d = nullptr;
   cf64* dvec_d = nullptr;
   cf64* dhat_d = nullptr;
+  void* w0_d = nullptr;
+  bool w0_ready = false;
   void* cstore_d = nullptr;
   void* xhat_d = nullptr;
   void* yhat_d = nullptr;
@@ -131,6 +141,12 @@ void launch_maca_finalize_batch(const Problem& p, H2Operator& h, int b0, int nb,
 template <typename R>
 void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
                      cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s);
+// one system through the collapsed lag-0 slices (after launch_collapse_lag0)
+void launch_h2_apply_lag0(const Problem& p, H2Operator& h, const cf64* x, int64_t xs, cf64* y,
+                          int64_t ys, hipStream_t s);
+// W0_b = sum_{t < rank_b} dhat_t[0] C_t for every block, in FP64, stored in
+// the storage precision at the compact offsets
+void launch_collapse_lag0(const Problem& p, H2Operator& h, hipStream_t s);
 // scaled inverse DFT of every fibre slot (eq. fastdft): dhat[n] =
 // rho^-n / F sum_l d[l] zeta^(n l mod F); full band only
 void launch_fibre_dft(const Problem& p, const H2Operator& h, const cf64* d, cf64* dhat, hipStream_t s);

@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kHB) void k_h2_up_leaf(const int* __restrict__ cl, 
   for (int e = threadIdx.x; e < P * ln; e += kHB) {
     const int mu = e / ln, l = lb + e % ln;
     R re = R(0), im = R(0);
+#pragma unroll 8
     for (int i = 0; i < n; ++i) {
       const R u = (R)Ul[(int64_t)i * P + mu];
       const cplx<R> v = xp[(int64_t)(beg + i) * nsys + l];
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(kHB) void k_h2_up(const int* __restrict__ list, con
       const int s = q ? s1 : s0;
       const U* Es = E + (int64_t)s * P * P;
       const cplx<R>* xs_ = xhat + (int64_t)s * P * nsys;
+#pragma unroll 8
       for (int lam = 0; lam < P; ++lam) {
         const R w = (R)Es[(int64_t)lam * P + mu];
         const cplx<R> v = xs_[(int64_t)lam * nsys + l];
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(kHB) void k_h2_down(const int* __restrict__ list, c
     const int lam = e / ln, l = lb + e % ln;
     const int64_t o = (int64_t)lam * nsys + l;
     R re = out[o].re, im = out[o].im;
+#pragma unroll 8
     for (int mu = 0; mu < P; ++mu) {
       const R w = (R)Ec[(int64_t)lam * P + mu];
       const cplx<R> v = yp[(int64_t)mu * nsys + l];
@@ -145,6 +148,7 @@ __global__ __launch_bounds__(kHB) void k_h2_leaf_out(const int* __restrict__ cl,
   for (int e = threadIdx.x; e < n * ln; e += kHB) {
     const int i = e / ln, l = lb + e % ln;
     R re = R(0), im = R(0);
+#pragma unroll 8
     for (int mu = 0; mu < P; ++mu) {
       const R u = (R)Ul[(int64_t)i * P + mu];
       const cplx<R> v = yh[(int64_t)mu * nsys + l];
@@ -181,7 +185,9 @@ size_t h2_perm_scratch_bytes(const H2Operator& h, int nsys) {
 // are taken 32 at a time so the input block stays in registers across the
 // rank terms; the next term's slice entries and fibre values are loaded one
 // term ahead.  A workgroup holds as many waves as its frequencies need, up
-// to kRankWaves<R>.
+// to kRankWaves<R>; with a single tile of frequencies (KS > 1) its KS waves
+// share the row tile instead, each taking every KS-th task, and their sums
+// are added in wave order through LDS.
 namespace {
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
@@ -210,7 +216,7 @@ constexpr int kFlush = 4;  // rank terms per MFMA chain
 template <typename R> constexpr int kRankWaves = 4;
 }  // namespace
 
-template <typename R, typename S, int NF, bool kAccum>
+template <typename R, typename S, int NF, bool kAccum, int KS>
 __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankTile* __restrict__ tiles,
                                                       const RankTask* __restrict__ tasks,
                                                       const int* __restrict__ ranks,
@@ -229,8 +235,9 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
   if (tile >= ntiles) return;  // padding of the last group; no barrier follows
   const RankTile tl = tiles[tile];
   const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int fb = (fy * (blockDim.x >> 6) + w) * 16 * NF;  // first frequency of this wave
-  if (fb >= nsys) return;                         // no barrier follows
+  // first frequency of this wave
+  const int fb = KS > 1 ? 0 : (fy * (blockDim.x >> 6) + w) * 16 * NF;
+  if (fb >= nsys) return;  // KS == 1 only: no barrier follows
   const int arow = L & 15, kq = L >> 4, col = L & 15;
   const bool rowin = arow < tl.nrows;
   // sums of Cr Br, Ci Bi, Cr Bi, Ci Br over the last terms; acc: the rest
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
     }
     chain = 0;
   };
-  for (int q = tl.t0; q < tl.t1; ++q) {
+  for (int q = tl.t0 + (KS > 1 ? w : 0); q < tl.t1; q += KS) {
     const RankTask T = tasks[q];
     const int rk = ranks[T.block];
     for (int j0 = 0; j0 < T.acols; j0 += kKC) {
@@ -327,6 +334,28 @@ __global__ __launch_bounds__(64 * kRankWaves<R>) void k_h2_rank_mfma(const RankT
     }
   }
   flush();
+  if constexpr (KS > 1) {
+    // waves 1 .. KS-1 hand their sums to wave 0, which adds them in order
+    __shared__ R red[KS - 1][2 * 4 * NF][64];
+    if (w > 0)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          red[w - 1][8 * f + v][L] = accr[f][v];
+          red[w - 1][8 * f + 4 + v][L] = acci[f][v];
+        }
+    __syncthreads();
+    if (w > 0) return;
+    for (int u = 0; u < KS - 1; ++u)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          accr[f][v] += red[u][8 * f + v][L];
+          acci[f][v] += red[u][8 * f + 4 + v][L];
+        }
+  }
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -354,27 +383,46 @@ static void launch_rank_mfma(const RankTile* tiles, int ntiles, const RankTask* 
   if (ntiles <= 0) return;
   constexpr int NF = 1;
   // 16 NF frequencies per wave; the fewest workgroups per row tile, with the
-  // waves spread evenly over them
+  // waves spread evenly over them.  One tile of frequencies: the row tile's
+  // tasks split over kRankWaves<R> waves of one workgroup.
   const int ftiles = (nsys + 16 * NF - 1) / (16 * NF);
+  if (ftiles == 1) {
+    constexpr int KS = kRankWaves<R>;
+    const dim3 grid((unsigned)(((ntiles + 7) / 8) * 8));
+    hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum, KS>), grid, dim3(64 * KS), 0, s, tiles, tasks,
+                       ranks, (const cplx<S>*)cstore, dvec, dstride, l0, nsys, ntiles, 1, x, out);
+    CQM_HIP(hipGetLastError());
+    return;
+  }
   const int gy = (ftiles + kRankWaves<R> - 1) / kRankWaves<R>;
   const int nw = (ftiles + gy - 1) / gy;
   const dim3 grid((unsigned)(((ntiles + 7) / 8) * 8 * gy));
-  hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum>), grid, dim3(64 * nw), 0, s, tiles, tasks, ranks,
+  hipLaunchKernelGGL((k_h2_rank_mfma<R, S, NF, kAccum, 1>), grid, dim3(64 * nw), 0, s, tiles, tasks, ranks,
                      (const cplx<S>*)cstore, dvec, dstride, l0, nsys, ntiles, gy, x, out);
   CQM_HIP(hipGetLastError());
 }
 
+// The slices, ranks and fibres a product contracts: the operator's own, or
+// the collapsed lag-0 slices of the time-marching weights.
+struct RankOperands {
+  const RankTask* core_tasks;
+  const RankTask* leaf_tasks;
+  const int* ranks;
+  const void* cstore;
+  const cf64* dvec;
+  int dstride;
+};
+
 template <typename R>
-void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
-                     cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s) {
-  // the frequency fibres d_t[l], or their transforms (time-marching weights)
-  const cf64* dv = fibres ? fibres : h.dvec_d;
+static void h2_apply_with(const Problem& p, H2Operator& h, const RankOperands& op, int l0, int nsys,
+                          const cplx<R>* x, int64_t xs, cplx<R>* y, int64_t ys, hipStream_t s) {
+  const cf64* dv = op.dvec;
   const int P = h.p;
   cplx<R>* xh = (cplx<R>*)h.xhat_d;
   cplx<R>* yh = (cplx<R>*)h.yhat_d;
   const int nleaf = (int)h.leaves.size();
   const bool f32 = sizeof(R) == 4;
-  const int dstride = h.nsys;
+  const int dstride = op.dstride;
   const int M = (int)h.perm.size();
   cplx<R>* xp = (cplx<R>*)h.xp_d;
   cplx<R>* yp = (cplx<R>*)h.yp_d;
@@ -385,11 +433,11 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
     // no block kept as a Tucker core (every admissible block small enough
     // to be expanded): no cluster coefficients, the leaf products write y
     if (h.store_fp64)
-      launch_rank_mfma<R, double, false>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                         h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+      launch_rank_mfma<R, double, false>(h.leaf_tiles_d, h.n_leaf_tiles, op.leaf_tasks, op.ranks,
+                                         op.cstore, dv, dstride, l0, nsys, xp, yp, s);
     else
-      launch_rank_mfma<R, float, false>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                        h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+      launch_rank_mfma<R, float, false>(h.leaf_tiles_d, h.n_leaf_tiles, op.leaf_tasks, op.ranks,
+                                        op.cstore, dv, dstride, l0, nsys, xp, yp, s);
     hipLaunchKernelGGL((k_h2_scatter<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, yp, y, ys);
     CQM_HIP(hipGetLastError());
     return;
@@ -414,11 +462,11 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
   }
   // 2. couplings: every cluster's coefficient rows (zero where no core block)
   if (h.store_fp64)
-    launch_rank_mfma<R, double, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
-                                       h.cstore_d, dv, dstride, l0, nsys, xh, yh, s);
+    launch_rank_mfma<R, double, false>(h.core_tiles_d, h.n_core_tiles, op.core_tasks, op.ranks,
+                                       op.cstore, dv, dstride, l0, nsys, xh, yh, s);
   else
-    launch_rank_mfma<R, float, false>(h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, h.ranks_d,
-                                      h.cstore_d, dv, dstride, l0, nsys, xh, yh, s);
+    launch_rank_mfma<R, float, false>(h.core_tiles_d, h.n_core_tiles, op.core_tasks, op.ranks,
+                                      op.cstore, dv, dstride, l0, nsys, xh, yh, s);
   // 3. downward pass
   for (int lv = 1; lv < h.nlevels; ++lv) {
     const int cnt = h.level_off[lv + 1] - h.level_off[lv];
@@ -440,12 +488,73 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
                        h.U_d, h.uleaf_off_d, P, nsys, yh, yp);
   CQM_HIP(hipGetLastError());
   if (h.store_fp64)
-    launch_rank_mfma<R, double, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                      h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+    launch_rank_mfma<R, double, true>(h.leaf_tiles_d, h.n_leaf_tiles, op.leaf_tasks, op.ranks,
+                                      op.cstore, dv, dstride, l0, nsys, xp, yp, s);
   else
-    launch_rank_mfma<R, float, true>(h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, h.ranks_d,
-                                     h.cstore_d, dv, dstride, l0, nsys, xp, yp, s);
+    launch_rank_mfma<R, float, true>(h.leaf_tiles_d, h.n_leaf_tiles, op.leaf_tasks, op.ranks,
+                                     op.cstore, dv, dstride, l0, nsys, xp, yp, s);
   hipLaunchKernelGGL((k_h2_scatter<R>), dim3(gblk), dim3(kHB), 0, s, h.perm_d, M, nsys, yp, y, ys);
+  CQM_HIP(hipGetLastError());
+}
+
+template <typename R>
+void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
+                     cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s) {
+  // the frequency fibres d_t[l], or their transforms (time-marching weights)
+  const RankOperands op{h.core_tasks_d, h.leaf_tasks_d, h.ranks_d, h.cstore_d,
+                        fibres ? fibres : h.dvec_d, h.nsys};
+  h2_apply_with<R>(p, h, op, l0, nsys, x, xs, y, ys, s);
+}
+
+void launch_h2_apply_lag0(const Problem& p, H2Operator& h, const cf64* x, int64_t xs, cf64* y,
+                          int64_t ys, hipStream_t s) {
+  require(h.w0_ready && h.w0_d, CQM_EINVAL, "lag-0 slices not formed");
+  const RankOperands op{h.core_tasks0_d, h.leaf_tasks0_d, h.ones_d, h.w0_d, h.one_d, 0};
+  h2_apply_with<double>(p, h, op, 0, 1, x, xs, y, ys, s);
+}
+
+// W0_b[e] = sum_{t < rank_b} dhat_t[0] C_t[e]: one workgroup per block, the
+// block's lag-0 fibre values staged in LDS, FP64 sums rounded once.
+constexpr int kCollapseMaxR = 128;
+template <typename S>
+__global__ __launch_bounds__(256) void k_collapse_lag0(const BlockDesc* __restrict__ blocks,
+                                                       const int* __restrict__ ranks,
+                                                       const cplx<S>* __restrict__ cstore,
+                                                       const cf64* __restrict__ dhat, int nsys,
+                                                       int Rcap, cplx<S>* __restrict__ w0) {
+  __shared__ cf64 d0[kCollapseMaxR];
+  const BlockDesc B = blocks[blockIdx.x];
+  const int rk = ranks[blockIdx.x];
+  for (int t = threadIdx.x; t < rk; t += 256) d0[t] = dhat[B.d_off + (int64_t)t * nsys];
+  __syncthreads();
+  const int64_t n = (int64_t)B.arows * B.acols;
+  const cplx<S>* C = cstore + B.c_off;
+  cplx<S>* W = w0 + B.c_off / Rcap;
+  for (int64_t e = threadIdx.x; e < n; e += 256) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < rk; ++t) {
+      const cplx<S> c = C[(int64_t)t * n + e];
+      const cf64 d = d0[t];
+      re += d.re * (double)c.re - d.im * (double)c.im;
+      im += d.re * (double)c.im + d.im * (double)c.re;
+    }
+    cplx<S> v;
+    v.re = (S)re;
+    v.im = (S)im;
+    W[e] = v;
+  }
+}
+
+void launch_collapse_lag0(const Problem& p, H2Operator& h, hipStream_t s) {
+  require(h.Rcap <= kCollapseMaxR, CQM_EINVAL, "rank cap above the lag-0 collapse limit");
+  const unsigned nb = (unsigned)h.blocks.size();
+  if (nb == 0) return;
+  if (h.store_fp64)
+    hipLaunchKernelGGL((k_collapse_lag0<double>), dim3(nb), dim3(256), 0, s, h.blocks_d, h.ranks_d,
+                       (const cf64*)h.cstore_d, h.dhat_d, h.nsys, h.Rcap, (cf64*)h.w0_d);
+  else
+    hipLaunchKernelGGL((k_collapse_lag0<float>), dim3(nb), dim3(256), 0, s, h.blocks_d, h.ranks_d,
+                       (const cf32*)h.cstore_d, h.dhat_d, h.nsys, h.Rcap, (cf32*)h.w0_d);
   CQM_HIP(hipGetLastError());
 }
 

@@ -225,6 +225,24 @@ def test_compressed_orders_match_oracle(ctx, ordercase, m):
         p.close()
 
 
+def test_compressed_few_systems_match_full_band(ctx, ordercase):
+    """Products over at most 16 systems split each row tile's tasks over the
+    waves of a workgroup (a different summation order from the full band):
+    a frequency sub-range equals the same rows of the full-band product."""
+    V, T, N, Tend, g = ordercase
+    x = g["x"]
+    for mode, tol in ((C.CQM_FP64_H2ACA, 1e-13), (C.CQM_MIXED_H2ACA, 1e-6)):
+        p = Problem(ctx, V, T, N, Tend, mode=mode, n_min=16, eta=1.0, cheb_m=5, eps_aca=1e-10)
+        full = p.apply(torch.as_tensor(x, device="cuda"), 0, 64).cpu().numpy()
+        for l0, nl in ((0, 1), (3, 5), (1, 16)):
+            part = p.apply(torch.as_tensor(x[l0:l0 + nl], device="cuda"), l0, 64).cpu().numpy()
+            e = max(np.linalg.norm(part[k] - full[l0 + k]) / np.linalg.norm(full[l0 + k])
+                    for k in range(nl))
+            say(f"  mode={mode} systems {l0}..{l0 + nl - 1}: relative difference {e:.1e}")
+            assert e < tol
+        p.close()
+
+
 @pytest.fixture(scope="module")
 def m4case():
     """1280-triangle sphere, N = 16: leaf size 32 and eta = 1 give admissible
