@@ -111,6 +111,15 @@ void setup_structure(Problem& p) {
     h.core_tasks0_d = up(compact(ck));
     h.leaf_tasks0_d = up(compact(lk));
     h.ones_d = up(std::vector<int>(std::max<size_t>(h.blocks.size(), 1), 1));
+    // fast right-hand side: z_{b,t} slots, Rcap x acols per block
+    std::vector<int64_t> zoff(std::max<size_t>(h.blocks.size(), 1), 0);
+    int64_t zo = 0;
+    for (size_t b = 0; b < h.blocks.size(); ++b) {
+      zoff[b] = zo;
+      zo += (int64_t)h.Rcap * h.blocks[b].acols;
+    }
+    h.z_elems = zo;
+    h.zoff_d = up(zoff);
     h.one_d = up(std::vector<cf64>{cf64{1.0, 0.0}});
     h.core_tiles_d = up(ct);
     h.core_tasks_d = up(ck);
@@ -164,6 +173,9 @@ void set_views(Problem& p) {
   h.yp_d = base + h.off_yp;
   h.dhat_d = h.off_dhat ? (cf64*)(base + h.off_dhat) : nullptr;
   h.w0_d = h.off_w0 ? (void*)(base + h.off_w0) : nullptr;
+  h.z_d = h.off_z ? (cf64*)(base + h.off_z) : nullptr;
+  h.hxh_d = h.off_hxh ? (cf64*)(base + h.off_hxh) : nullptr;
+  h.rpart_d = h.off_rpart ? (cf64*)(base + h.off_rpart) : nullptr;
 }
 }  // namespace
 
@@ -189,6 +201,14 @@ size_t h2_workspace_bytes(const Problem& pc) {
   h.off_w0 = p.opt.marching
                  ? take((size_t)(h.cstore_elems / h.Rcap) * (h.store_fp64 ? sizeof(cf64) : sizeof(cf32)))
                  : 0;
+  if (p.opt.marching) {
+    const size_t coef = h.cl.size() * (size_t)h.p;
+    h.off_z = take((size_t)std::max<int64_t>(h.z_elems, 1) * sizeof(cf64));
+    h.off_hxh = take((size_t)p.F * coef * sizeof(cf64));
+    h.off_rpart = take((size_t)kConvSplit * std::max(coef, h.perm.size()) * sizeof(cf64));
+  } else {
+    h.off_z = h.off_hxh = h.off_rpart = 0;
+  }
   h.total = off;
   return off;
 }
@@ -244,6 +264,20 @@ void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, c
     launch_h2_apply<double>(p, h, k0, nsys, x, xs, y, ys, h.dhat_d, s);
 }
 
+void h2_history_push(Problem& p, int m, const cf64* x, cf64* hx, hipStream_t s) {
+  set_views(p);
+  H2Operator& h = *p.h2;
+  require(h.hxh_d != nullptr, CQM_EINVAL, "no marching history in the workspace");
+  launch_h2_push_history(p, h, m, x, hx, s);
+}
+
+void h2_history_sum(Problem& p, int n, const cf64* hx, cf64* y, hipStream_t s) {
+  set_views(p);
+  H2Operator& h = *p.h2;
+  require(h.z_d != nullptr && h.dhat_d != nullptr, CQM_EINVAL, "no marching history in the workspace");
+  launch_h2_fast_history(p, h, n, hx, y, s);
+}
+
 void h2_marching_weights(Problem& p, hipStream_t s) {
   set_views(p);
   H2Operator& h = *p.h2;
@@ -297,6 +331,7 @@ void h2_release(Problem& p) {
   release(h.leaf_tasks0_d);
   release(h.ones_d);
   release(h.one_d);
+  release(h.zoff_d);
   delete p.h2;
   p.h2 = nullptr;
 }

@@ -108,12 +108,19 @@ struct H2Operator {
   RankTask* leaf_tasks0_d = nullptr;
   int* ones_d = nullptr;    // one entry per block, each 1
   cf64* one_d = nullptr;    // a single 1 + 0i
+  // time marching, fast right-hand side (eq. fastrhs): per block the rank
+  // terms' fibre-convolved column histories z_{b,t} (Rcap x acols, from
+  // zoff[b]), the cluster coefficients of every past step and the split-K
+  // partial rows of the one-system products
+  int64_t* zoff_d = nullptr;
+  int64_t z_elems = 0;
   std::vector<int> level_off;
   // workspace regions (byte offsets from the problem's H2 region)
   size_t off_cstore = 0, off_dvec = 0, off_stage = 0, off_xhat = 0, off_yhat = 0, total = 0;
   size_t off_xp = 0, off_yp = 0;
   size_t off_dhat = 0;  // marching: the fibres' transforms (integration weights)
   size_t off_w0 = 0;    // marching: collapsed lag-0 slices (storage precision)
+  size_t off_z = 0, off_hxh = 0, off_rpart = 0;  // marching: fast right-hand side
   int64_t cstore_elems = 0, dvec_elems = 0, stage_elems = 0;
   int64_t stage_budget = 0;       // cf64 elements per MACA batch
   std::vector<std::pair<int, int>> batches;  // [b0, b1) per MACA launch
@@ -124,6 +131,9 @@ struct H2Operator {
   cf64* dhat_d = nullptr;
   void* w0_d = nullptr;
   bool w0_ready = false;
+  cf64* z_d = nullptr;
+  cf64* hxh_d = nullptr;
+  cf64* rpart_d = nullptr;
   void* cstore_d = nullptr;
   void* xhat_d = nullptr;
   void* yhat_d = nullptr;
@@ -147,6 +157,15 @@ void launch_h2_apply_lag0(const Problem& p, H2Operator& h, const cf64* x, int64_
 // W0_b = sum_{t < rank_b} dhat_t[0] C_t for every block, in FP64, stored in
 // the storage precision at the compact offsets
 void launch_collapse_lag0(const Problem& p, H2Operator& h, hipStream_t s);
+// fast right-hand side of the compressed marching (eq. fastrhs), FP64:
+// push: hx = step m's input x (triangle order) in cluster order, and its
+// cluster coefficients into history slot m; sum: y = sum_{k=1}^{n}
+// What_k x_{n-k} from the histories hx (rows m = 0 .. n-1, M each)
+constexpr int kConvSplit = 8;  // split-K factor of the one-system products
+void launch_h2_push_history(const Problem& p, H2Operator& h, int m, const cf64* x, cf64* hx,
+                            hipStream_t s);
+void launch_h2_fast_history(const Problem& p, H2Operator& h, int n, const cf64* hx, cf64* y,
+                            hipStream_t s);
 // scaled inverse DFT of every fibre slot (eq. fastdft): dhat[n] =
 // rho^-n / F sum_l d[l] zeta^(n l mod F); full band only
 void launch_fibre_dft(const Problem& p, const H2Operator& h, const cf64* d, cf64* dhat, hipStream_t s);

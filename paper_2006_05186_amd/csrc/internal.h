@@ -580,6 +580,11 @@ void solve_marching(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s);  
 void h2_marching_weights(Problem& p, hipStream_t s);
 void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, cf64* y, int64_t ys,
                       hipStream_t s);
+// fast right-hand side (eq. fastrhs): record step m's input x (complex,
+// triangle order) as history row hx (cluster order) with its cluster
+// coefficients; y = sum_{k=1}^{n} What_k x_{n-k} from rows 0 .. n-1
+void h2_history_push(Problem& p, int m, const cf64* x, cf64* hx, hipStream_t s);
+void h2_history_sum(Problem& p, int n, const cf64* hx, cf64* y, hipStream_t s);
 // compressed marching helpers (k_march.hip): r = b - Re sum_{k<n} Y[k];
 // Z = x as complex; w = Re Y with the partial p.w (CG product); the mean
 // over the frequencies of the plain diagonal blocks (real part)

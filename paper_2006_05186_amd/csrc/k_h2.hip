@@ -558,6 +558,180 @@ void launch_collapse_lag0(const Problem& p, H2Operator& h, hipStream_t s) {
   CQM_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------------
+// Fast right-hand side of the compressed marching (eq. fastrhs):
+//   sum_{k=1}^{n} What_k x_{n-k} = sum_b sum_t C_bt (sum_k dhat_bt[k] x_{n-k}|cols b)
+// The inner sums (the fibres convolved with the block's column history) are
+// formed first, then one product per block and rank term: one pass over
+// the slices per step instead of one per lag.
+
+// z_{b,t}[j] = sum_{k=1}^{n} dhat_bt[k] h_{n-k}[col_b + j]; h: past inputs in
+// cluster order (expanded far and near blocks) or their cluster
+// coefficients (cores).  One workgroup per block.
+__global__ __launch_bounds__(256) void k_fast_conv(const BlockDesc* __restrict__ blocks,
+                                                   const int* __restrict__ ranks,
+                                                   const int64_t* __restrict__ zoff,
+                                                   const int* __restrict__ cl, int P,
+                                                   const cf64* __restrict__ dhat, int F, int n,
+                                                   const cf64* __restrict__ hx, int64_t sx,
+                                                   const cf64* __restrict__ hxh, int64_t sxh,
+                                                   cf64* __restrict__ z) {
+  const int b = blockIdx.x;
+  const BlockDesc B = blocks[b];
+  const int rk = ranks[b], nc = B.acols;
+  const bool core = B.kind == kFarCore;
+  const cf64* H = core ? hxh + (int64_t)B.c * P : hx + cl[4 * B.c];
+  const int64_t sh = core ? sxh : sx;
+  cf64* zb = z + zoff[b];
+  for (int e = threadIdx.x; e < rk * nc; e += 256) {
+    const int t = e / nc, j = e - t * nc;
+    const cf64* d = dhat + B.d_off + (int64_t)t * F;
+    double re = 0.0, im = 0.0;
+#pragma unroll 4
+    for (int k = 1; k <= n; ++k) {
+      const cf64 a = d[k], v = H[(int64_t)(n - k) * sh + j];
+      re += a.re * v.re - a.im * v.im;
+      im += a.re * v.im + a.im * v.re;
+    }
+    zb[e] = cf64{re, im};
+  }
+}
+
+// One system, split K: part[y][out_row0 + row] = sum over the tasks
+// q = t0 + y, t0 + y + kConvSplit, .. of the row tile and their rank terms of
+// C_t[row, :] . z_{b,t}.  Sixteen lanes per row take every sixteenth column;
+// their sums are combined by a fixed butterfly.
+template <typename S>
+__global__ __launch_bounds__(256) void k_h2_rank_conv(const RankTile* __restrict__ tiles,
+                                                      const RankTask* __restrict__ tasks,
+                                                      const int* __restrict__ ranks,
+                                                      const int64_t* __restrict__ zoff,
+                                                      const cplx<S>* __restrict__ cstore,
+                                                      const cf64* __restrict__ z, int64_t pstride,
+                                                      cf64* __restrict__ part) {
+  const RankTile tl = tiles[blockIdx.x];
+  const int y = blockIdx.y;
+  const int row = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  double re = 0.0, im = 0.0;
+  if (row < tl.nrows) {
+    for (int q = tl.t0 + y; q < tl.t1; q += kConvSplit) {
+      const RankTask T = tasks[q];
+      const int rk = ranks[T.block];
+      const cplx<S>* Crow = cstore + T.c_off + (int64_t)row * T.ldc;
+      const cf64* zt = z + zoff[T.block];
+      for (int t = 0; t < rk; ++t) {
+        const cplx<S>* Ct = Crow + (int64_t)t * T.cstride;
+        const cf64* zz = zt + (int64_t)t * T.acols;
+        for (int j = lane; j < T.acols; j += 16) {
+          const cplx<S> c = Ct[j];
+          const cf64 v = zz[j];
+          re += (double)c.re * v.re - (double)c.im * v.im;
+          im += (double)c.re * v.im + (double)c.im * v.re;
+        }
+      }
+    }
+  }
+  for (int off = 8; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 16);
+    im += __shfl_xor(im, off, 16);
+  }
+  if (lane == 0 && row < tl.nrows) part[(int64_t)y * pstride + tl.out_row0 + row] = cf64{re, im};
+}
+
+// out[i] (+)= sum_{y < kConvSplit} part[y][i], in order of y
+template <bool kAccum>
+__global__ __launch_bounds__(256) void k_conv_reduce(const cf64* __restrict__ part, int64_t pstride,
+                                                     int64_t n, cf64* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int y = 0; y < kConvSplit; ++y) {
+    const cf64 v = part[(int64_t)y * pstride + i];
+    re += v.re;
+    im += v.im;
+  }
+  if (kAccum) {
+    out[i].re += re;
+    out[i].im += im;
+  } else {
+    out[i] = cf64{re, im};
+  }
+}
+
+static void conv_products(const H2Operator& h, const RankTile* tiles, int ntiles,
+                          const RankTask* tasks, int64_t rows, bool accum, cf64* out,
+                          hipStream_t s) {
+  if (ntiles <= 0) return;
+  const int64_t ps = (int64_t)std::max(h.cl.size() * (size_t)h.p, h.perm.size());
+  const dim3 grid((unsigned)ntiles, kConvSplit);
+  if (h.store_fp64)
+    hipLaunchKernelGGL((k_h2_rank_conv<double>), grid, dim3(256), 0, s, tiles, tasks, h.ranks_d,
+                       h.zoff_d, (const cf64*)h.cstore_d, h.z_d, ps, h.rpart_d);
+  else
+    hipLaunchKernelGGL((k_h2_rank_conv<float>), grid, dim3(256), 0, s, tiles, tasks, h.ranks_d,
+                       h.zoff_d, (const cf32*)h.cstore_d, h.z_d, ps, h.rpart_d);
+  CQM_HIP(hipGetLastError());
+  const unsigned g = (unsigned)((rows + 255) / 256);
+  if (accum)
+    hipLaunchKernelGGL((k_conv_reduce<true>), dim3(g), dim3(256), 0, s, h.rpart_d, ps, rows, out);
+  else
+    hipLaunchKernelGGL((k_conv_reduce<false>), dim3(g), dim3(256), 0, s, h.rpart_d, ps, rows, out);
+  CQM_HIP(hipGetLastError());
+}
+
+void launch_h2_push_history(const Problem& p, H2Operator& h, int m, const cf64* x, cf64* hx,
+                            hipStream_t s) {
+  const int M = (int)h.perm.size(), P = h.p, nleaf = (int)h.leaves.size();
+  require(m >= 0 && m < p.F, CQM_EINVAL, "history slot out of range");
+  hipLaunchKernelGGL((k_h2_gather<double>), dim3((M + kHB - 1) / kHB), dim3(kHB), 0, s, h.perm_d, M, 1,
+                     x, (int64_t)M, hx);
+  CQM_HIP(hipGetLastError());
+  if (h.n_core == 0) return;
+  cf64* xh = h.hxh_d + (int64_t)m * h.cl.size() * P;
+  hipLaunchKernelGGL((k_h2_up_leaf<double, double>), dim3(nleaf, 1), dim3(kHB), 0, s, h.cl_d,
+                     h.level_cl_d + h.level_off[h.nlevels], h.perm_d, h.U_d, h.uleaf_off_d, P, 1, hx, xh);
+  CQM_HIP(hipGetLastError());
+  for (int lv = h.nlevels - 2; lv >= 0; --lv) {
+    const int cnt = h.level_off[lv + 1] - h.level_off[lv];
+    hipLaunchKernelGGL((k_h2_up<double, double>), dim3(cnt, 1), dim3(kHB), 0, s,
+                       h.level_cl_d + h.level_off[lv], h.cl_d + 4 * (int)h.cl.size(), h.E_d, P, 1, xh);
+    CQM_HIP(hipGetLastError());
+  }
+}
+
+void launch_h2_fast_history(const Problem& p, H2Operator& h, int n, const cf64* hx, cf64* y,
+                            hipStream_t s) {
+  const int M = (int)h.perm.size(), P = h.p, nleaf = (int)h.leaves.size();
+  require(n >= 1 && n < p.F && h.nsys == p.F, CQM_EINVAL, "history length out of range");
+  const int nb = (int)h.blocks.size();
+  const int64_t coef = (int64_t)h.cl.size() * P;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_fast_conv, dim3(nb), dim3(256), 0, s, h.blocks_d, h.ranks_d, h.zoff_d, h.cl_d, P,
+                       h.dhat_d, h.nsys, n, hx, (int64_t)M, h.hxh_d, coef, h.z_d);
+    CQM_HIP(hipGetLastError());
+  }
+  cf64* yh = (cf64*)h.yhat_d;
+  cf64* yp = (cf64*)h.yp_d;
+  if (h.n_core > 0) {
+    conv_products(h, h.core_tiles_d, h.n_core_tiles, h.core_tasks_d, coef, false, yh, s);
+    for (int lv = 1; lv < h.nlevels; ++lv) {
+      const int cnt = h.level_off[lv + 1] - h.level_off[lv];
+      hipLaunchKernelGGL((k_h2_down<double, double>), dim3(cnt, 1), dim3(kHB), 0, s,
+                         h.level_cl_d + h.level_off[lv], h.cl_d, h.E_d, P, 1, yh);
+      CQM_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((k_h2_leaf_out<double, double>), dim3(nleaf, 1), dim3(kHB), 0, s, h.cl_d,
+                       h.level_cl_d + h.level_off[h.nlevels], h.U_d, h.uleaf_off_d, P, 1, yh, yp);
+    CQM_HIP(hipGetLastError());
+    conv_products(h, h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, M, true, yp, s);
+  } else {
+    conv_products(h, h.leaf_tiles_d, h.n_leaf_tiles, h.leaf_tasks_d, M, false, yp, s);
+  }
+  hipLaunchKernelGGL((k_h2_scatter<double>), dim3((M + kHB - 1) / kHB), dim3(kHB), 0, s, h.perm_d, M, 1,
+                     yp, y, (int64_t)M);
+  CQM_HIP(hipGetLastError());
+}
+
 template void launch_h2_apply<float>(const Problem&, H2Operator&, int, int, const cf32*, int64_t, cf32*,
                                      int64_t, const cf64*, hipStream_t);
 template void launch_h2_apply<double>(const Problem&, H2Operator&, int, int, const cf64*, int64_t, cf64*,

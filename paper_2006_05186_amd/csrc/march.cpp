@@ -87,8 +87,8 @@ void solve_marching_h2(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s)
   const double t_setup = ms_since(t0);
   auto t1 = std::chrono::steady_clock::now();
   CgVec v = cg_vectors(p, pinv);
-  cf64* Z = wsp<cf64>(p, p.lay.mz);  // row N - m: q_m as complex
-  cf64* Y = wsp<cf64>(p, p.lay.my);  // the history product, one row per lag
+  cf64* HX = wsp<cf64>(p, p.lay.mz);  // row m: q_m as complex, cluster order
+  cf64* Y = wsp<cf64>(p, p.lay.my);   // the history sum of the current step
   cf64* pc = wsp<cf64>(p, p.lay.mpc);
   cf64* wc = pc + M;
   // the weights carry the compressed operator's approximation error, far
@@ -104,9 +104,9 @@ void solve_marching_h2(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s)
     if (n == 0) {
       CQM_HIP(hipMemcpyAsync(v.r, b, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
     } else {
-      // lags k = 1..n against q_{n-k}: rows N-n+1 .. N of Z
-      h2_apply_weights(p, 1, n, Z + (size_t)(N - n + 1) * M, M, Y, M, s);
-      launch_hist_reduce(Y, n, M, b + (size_t)n * M, v.r, s);
+      // sum_{k=1}^{n} What_k q_{n-k} by the fast right-hand side (eq. fastrhs)
+      h2_history_sum(p, n, HX, Y, s);
+      launch_hist_reduce(Y, 1, M, b + (size_t)n * M, v.r, s);
     }
     v.x = q_out + (size_t)n * M;
     p.march_host[0] = 0;
@@ -131,7 +131,10 @@ void solve_marching_h2(Problem& p, double* q_out, cqm_diag* diag, hipStream_t s)
     if (!std::isfinite(res)) finite = false;
     if (!(res <= tol) && !(srr == 0.0)) converged = false;
     max_res = std::max(max_res, res);
-    launch_to_complex(v.x, M, Z + (size_t)(N - n) * M, nullptr, s);
+    if (n < N) {
+      launch_to_complex(v.x, M, pc, nullptr, s);
+      h2_history_push(p, n, pc, HX + (size_t)n * M, s);
+    }
   }
   cqm_diag d{};
   d.n_systems = N + 1;

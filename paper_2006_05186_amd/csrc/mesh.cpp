@@ -308,11 +308,12 @@ void compute_layout(Problem& p) {
   }
   if (p.opt.marching && mode_is_h2(p.opt.mode)) {
     // compressed time marching (weights from the fibres, in the compressed
-    // operator's own workspace): history rows, product outputs, the CG
-    // product's vectors and vectors/partials, the block inverses of What_0
+    // operator's own workspace): the past densities in cluster order, the
+    // history sum, the CG product's vectors and vectors/partials, the block
+    // inverses of What_0
     const size_t nwg = (M + 255) / 256;
     L.mz = take(sizeof(cf64) * p.F * M);
-    L.my = take(sizeof(cf64) * p.F * M);
+    L.my = take(sizeof(cf64) * M);
     L.mpc = take(sizeof(cf64) * 2 * M);
     L.mpinv = take(sizeof(cf64) * block_inverse_elems((int)M));
     L.mdiag = take(sizeof(cf64) * block_inverse_elems((int)M));
