@@ -315,9 +315,13 @@ int cqm_solve_batch(cqm_problem_t* probs, int32_t count, double** q_outs,
  * sum r_n = b_n - sum_{j=1}^{n} What_j q_{n-j} and What_0 q_n = r_n (real
  * symmetric positive definite; conjugate gradients with the inverses of its
  * 64 x 64 diagonal blocks, to outer_tol relative residual).  It agrees with
- * cqm_solve up to terms of order rho^(N+1).  The problem must be created in
- * a plain mode, form CQM_FORM_DENSE, with cqm_options.marching = 1
- * (CQM_EINVAL otherwise).  q_out: device, (N+1) x M doubles, caller-owned,
+ * cqm_solve up to terms of order rho^(N+1).  The problem must be created
+ * with cqm_options.marching = 1 and the indirect formulation, either in a
+ * plain mode with form CQM_FORM_DENSE, or in a compressed mode (Section 6.2:
+ * the weights are the compressed operator with its fibres transformed,
+ * eq. fastdft; the history sums use eq. fastrhs; needs aca_band
+ * CQM_BAND_FULL and precond CQM_PRECOND_BLOCK_JACOBI); CQM_EINVAL
+ * otherwise.  q_out: device, (N+1) x M doubles, caller-owned,
  * written step by step.  diag (host, may be NULL): total_iters / max_iters
  * are conjugate-gradient iterations over / per step, max_rel_residual the
  * largest final relative residual of a step.  CQM_ENOCONV if a step missed
