@@ -225,17 +225,28 @@ def _near_lookup(V, T, q=5):
     return dict(by_row=by_row, static={(i, j): v for (i, j, _), v in zip(pairs, static)})
 
 
-def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None):
+def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None, rows=None):
     """Algorithm 3: partition, bases, MACA of every block.  The near-field
     block tensors are taken from `dense` (M x M x F) when it is given, else
-    their entries are formed on demand (block_tensor), block by block."""
+    their entries are formed on demand (block_tensor), block by block.  With
+    `rows` only the blocks whose row cluster holds one of those triangles are
+    compressed: the operator's rows `rows` are then complete (the others
+    are not), which reaches sampled rows of meshes whose whole compressed
+    operator would take hours here."""
     clusters = cluster_tree(V, T, n_min)
     far, near = block_tree(clusters, eta)
     nodes = [cheb_nodes(c, m) for c in clusters]
     lookup = _near_lookup(V, T) if dense is None else None
     s_list = np.asarray(s_list)
+    rowset = None if rows is None else set(int(i) for i in rows)
+
+    def kept(r):
+        return rowset is None or not rowset.isdisjoint(clusters[r]["idx"].tolist())
+
     blocks = []
     for (r, c) in far:
+        if not kept(r):
+            continue
         gr = np.stack(np.meshgrid(*nodes[r], indexing="ij"), -1).reshape(-1, 3)
         gc = np.stack(np.meshgrid(*nodes[c], indexing="ij"), -1).reshape(-1, 3)
         dist = np.linalg.norm(gr[:, None, :] - gc[None, :, :], axis=-1)
@@ -243,6 +254,8 @@ def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None):
         Cs, Ds, info = maca(S, eps, rcap)
         blocks.append(dict(kind="far", r=r, c=c, C=Cs, d=Ds, rank=info["rank"]))
     for (r, c) in near:
+        if not kept(r):
+            continue
         ir, ic = clusters[r]["idx"], clusters[c]["idx"]
         G = dense[np.ix_(ir, ic)] if dense is not None else block_tensor(V, T, ir, ic, s_list, lookup)
         Cs, Ds, info = maca(G, eps, rcap)
@@ -254,7 +267,7 @@ def build_compressed(V, T, s_list, n_min, eta, m, eps, dense=None, rcap=None):
                 if cid not in U:
                     U[cid] = cluster_basis(V, T, clusters[cid], nodes[cid])
     return dict(clusters=clusters, far=far, near=near, nodes=nodes, blocks=blocks, U=U,
-                F=len(s_list))
+                F=len(s_list), rows=rows)
 
 
 def compressed_matvec(op, x):

@@ -6,6 +6,7 @@ root:
     python tests/golden/make_golden.py --c3 -j 7  # sphere5120_N128_T6
     python tests/golden/make_golden.py --h2m4     # sphere1280_N16_T2_h2m4
     python tests/golden/make_golden.py --h2order  # two_spheres640_N16_T2_h2
+    python tests/golden/make_golden.py --h2rows   # sphere5120_N128_T6_h2rows
 Outputs tests/golden/<workload>.npz with the density q (N+1, M) and the
 frequency-domain solutions xhat (distinct frequencies); the 1280-triangle file
 also holds the forward-transformed data ghat and the static near-field values.
@@ -16,6 +17,11 @@ and ranks.  The h2 file of two 320-triangle spheres six radii apart holds the
 same for Chebyshev orders m = 4 .. 8 (leaf size 16, eta = 1, tolerance 1e-10,
 near blocks from the dense tensor) and the plain product: the two spheres' clusters form admissible
 blocks of 320 x 320, stored as Tucker cores for m <= 6 and expanded for m >= 7.
+The h2rows file holds rows of the 5120-triangle workload's compressed
+operator (leaf size 32, eta = 1, m = 4, MACA tolerances 1e-6 and 1e-10: the
+configured setting) applied to a seeded input: the triangles of four leaf
+clusters, with only the blocks of their block rows compressed (entries on
+demand).
 
 The 5120-triangle file is the same all-at-once oracle solve: its frequencies
 are independent (one dense assembly and LU each), so they are spread over
@@ -106,6 +112,29 @@ def _h2m4():
     np.savez_compressed(os.path.join(HERE, "sphere1280_N16_T2_h2m4.npz"), **out)
 
 
+def _h2rows():
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
+    wl = W.C3
+    V, T = wl.mesh()
+    s, _, _ = O.frequencies(wl.N, wl.T)
+    cl = O.compress.cluster_tree(V, T, 32)
+    leaves = [c for c in cl if not c["sons"]]
+    pick = [leaves[k * len(leaves) // 4]["idx"] for k in range(4)]
+    rows = np.sort(np.concatenate(pick))
+    x = W.random_complex((len(s), len(T)), seed=33)  # regenerated by the test from the seed
+    out = {"rows": rows, "seed": np.asarray(33)}
+    for tag, eps in (("e6", 1e-6), ("e10", 1e-10)):
+        t = time.time()
+        op = O.build_compressed(V, T, s, 32, 1.0, 4, eps, rows=rows)
+        out[f"y_{tag}"] = O.compressed_matvec(op, x)[:, rows]
+        out[f"nblocks_{tag}"] = np.asarray(len(op["blocks"]))
+        print(f"eps {eps}: {len(op['blocks'])} blocks for {len(rows)} rows, {time.time() - t:.0f}s",
+              flush=True)
+    np.savez_compressed(os.path.join(HERE, "sphere5120_N128_T6_h2rows.npz"), **out)
+
+
 ORDERS = (4, 5, 6, 7, 8)
 
 
@@ -139,8 +168,12 @@ def main():
     ap.add_argument("--h2m4", action="store_true", help="compressed operator, m = 4")
     ap.add_argument("--h2order", action="store_true",
                     help="compressed operator of two spheres, m = 4 .. 8")
+    ap.add_argument("--h2rows", action="store_true",
+                    help="sampled rows of the 5120-triangle compressed operator")
     a = ap.parse_args()
-    if a.h2order:
+    if a.h2rows:
+        _h2rows()
+    elif a.h2order:
         _h2order()
     elif a.h2m4:
         _h2m4()

@@ -186,6 +186,35 @@ def test_compressed_C3_against_stored_oracle(ctx):
     assert errs[1.0, 1] < C3_TOL_FP64_RESIDUAL
 
 
+@pytest.mark.parametrize("eps,tag", [(1e-6, "e6"), (1e-10, "e10")])
+def test_compressed_C3_rows_match_oracle(ctx, eps, tag):
+    """The configured compressed operator of the 5120-triangle workload (leaf
+    size 32, eta = 1, m = 4: 1612 Tucker cores of p = 64 with their
+    transfers, expanded far and near blocks, full band of 129 frequencies)
+    against the oracle's compressed operator on the rows of four leaf
+    clusters (tests/golden/sphere5120_N128_T6_h2rows.npz, make_golden.py
+    --h2rows: only the blocks of those block rows are compressed there).
+    FP64 slices: with the oracle's pivots the rows agree to rounding; a MACA
+    pivot that flips on a floating-point near-tie changes that block's
+    approximant within the tolerance eps, so the bar is 10 eps (1e-9 for
+    eps = 1e-10); FP32 slices: max(1e-6, 10 eps)."""
+    wl = W.C3
+    V, T = wl.mesh()
+    g = _golden("sphere5120_N128_T6_h2rows")
+    rows, ref = g["rows"], g[f"y_{tag}"]
+    s, _, _ = O.frequencies(wl.N, wl.T)
+    x = W.random_complex((len(s), len(T)), seed=int(g["seed"]))
+    for mode, tol in ((C.CQM_FP64_H2ACA, 10 * eps if eps > 1e-8 else 1e-9),
+                      (C.CQM_MIXED_H2ACA, max(1e-6, 10 * eps))):
+        p = Problem(ctx, V, T, wl.N, wl.T, mode=mode, n_min=32, eta=1.0, cheb_m=4, eps_aca=eps)
+        y = p.apply(torch.as_tensor(x, device="cuda"), 0, 64).cpu().numpy()[:, rows]
+        worst = max(np.linalg.norm(y[l] - ref[l]) / np.linalg.norm(ref[l]) for l in range(len(s)))
+        say(f"  compressed C3 rows ({len(rows)}) eps={eps} mode={mode}: worst relative error "
+            f"{worst:.2e} over {len(s)} frequencies")
+        assert worst < tol
+        p.close()
+
+
 @pytest.fixture(scope="module")
 def ordercase():
     """Two 320-triangle spheres six radii apart, N = 16: the spheres' clusters

@@ -164,3 +164,18 @@ def test_on_demand_near_blocks_equal_the_dense_tensor_slices():
     x = W.random_complex((len(s), len(T)), seed=4)
     ya, yb = O.compressed_matvec(a, x), O.compressed_matvec(b, x)
     assert np.linalg.norm(ya - yb) <= 1e-7 * np.linalg.norm(ya)
+
+
+def test_sampled_rows_equal_the_whole_operator_rows(small_problem):
+    # compressing only the blocks whose row cluster holds a sampled triangle
+    # leaves those rows of the product unchanged: every other block adds
+    # nothing to them, and the kept blocks are compressed the same way
+    V, T, s, dense = small_problem
+    x = W.random_complex((len(s), len(T)), seed=6)
+    full = O.build_compressed(V, T, s, 8, 1.0, 3, 1e-8, dense=dense)
+    rows = np.asarray(sorted(set(full["clusters"][5]["idx"].tolist()) | {0, 17, 250}))
+    part = O.build_compressed(V, T, s, 8, 1.0, 3, 1e-8, dense=dense, rows=rows)
+    assert 0 < len(part["blocks"]) < len(full["blocks"])
+    yf = O.compressed_matvec(full, x)[:, rows]
+    yp = O.compressed_matvec(part, x)[:, rows]
+    assert np.array_equal(yf, yp)
