@@ -7,6 +7,7 @@ root:
     python tests/golden/make_golden.py --h2m4     # sphere1280_N16_T2_h2m4
     python tests/golden/make_golden.py --h2order  # two_spheres640_N16_T2_h2
     python tests/golden/make_golden.py --h2rows   # sphere5120_N128_T6_h2rows
+    python tests/golden/make_golden.py --h2march  # two_spheres640_N16_T2_h2march
 Outputs tests/golden/<workload>.npz with the density q (N+1, M) and the
 frequency-domain solutions xhat (distinct frequencies); the 1280-triangle file
 also holds the forward-transformed data ghat and the static near-field values.
@@ -21,7 +22,10 @@ The h2rows file holds rows of the 5120-triangle workload's compressed
 operator (leaf size 32, eta = 1, m = 4, MACA tolerances 1e-6 and 1e-10: the
 configured setting) applied to a seeded input: the triangles of four leaf
 clusters, with only the blocks of their block rows compressed (entries on
-demand).
+demand).  The h2march file holds the oracle's compressed time-marching
+solution (weights from the transformed fibres) of the two spheres, N = 16,
+T = 2, leaf size 16, eta = 1, tolerance 1e-10, m = 4 and 6 (the 320 x 320
+blocks are Tucker cores), with the plain marching solution.
 
 The 5120-triangle file is the same all-at-once oracle solve: its frequencies
 are independent (one dense assembly and LU each), so they are spread over
@@ -135,6 +139,21 @@ def _h2rows():
     np.savez_compressed(os.path.join(HERE, "sphere5120_N128_T6_h2rows.npz"), **out)
 
 
+def _h2march():
+    import numpy as np
+    import cqm_workloads as W
+    import oracle as O
+    V, T = W.two_spheres(2)
+    N, Tend = 16, 2.0
+    out = {}
+    for m in (4, 6):
+        t = time.time()
+        out[f"q_m{m}"] = O.solve_marching_compressed(V, T, N, Tend, 16, 1.0, m, 1e-10)
+        print(f"compressed marching m {m}: {time.time() - t:.0f}s", flush=True)
+    out["q_plain"] = O.solve_marching(V, T, N, Tend)
+    np.savez_compressed(os.path.join(HERE, "two_spheres640_N16_T2_h2march.npz"), **out)
+
+
 ORDERS = (4, 5, 6, 7, 8)
 
 
@@ -170,8 +189,12 @@ def main():
                     help="compressed operator of two spheres, m = 4 .. 8")
     ap.add_argument("--h2rows", action="store_true",
                     help="sampled rows of the 5120-triangle compressed operator")
+    ap.add_argument("--h2march", action="store_true",
+                    help="compressed marching of two spheres, m = 4 and 6")
     a = ap.parse_args()
-    if a.h2rows:
+    if a.h2march:
+        _h2march()
+    elif a.h2rows:
         _h2rows()
     elif a.h2order:
         _h2order()

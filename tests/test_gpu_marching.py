@@ -122,6 +122,34 @@ def test_compressed_marching_C1_against_plain(ctx, c1):
     p.close()
 
 
+@pytest.mark.parametrize("m", [4, 6])
+def test_compressed_marching_with_cores_matches_oracle(ctx, m):
+    """Two 320-triangle spheres six radii apart (their clusters form 320 x 320
+    admissible blocks kept as Tucker cores, so the fast right-hand side
+    convolves cluster coefficients and the lag-0 collapse covers cores),
+    N = 16, leaf size 16, eta = 1, m = 4 and 6, tolerance 1e-10, against the
+    oracle's compressed marching (tests/golden/two_spheres640_N16_T2_h2march.npz,
+    make_golden.py --h2march)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "two_spheres640_N16_T2_h2march.npz"))
+    V, T = W.two_spheres(2)
+    N, Tend = 16, 2.0
+    _, _, area = O.triangle_quadrature(V, T)
+    for mode, tol in ((C.CQM_FP64_H2ACA, 1e-6), (C.CQM_MIXED_H2ACA, 1e-4)):
+        p = Problem(ctx, V, T, N, Tend, mode=mode, marching=1, n_min=16, eta=1.0, cheb_m=m,
+                    eps_aca=1e-10)
+        p.set_plane_wave()
+        q, rc, d = p.solve_marching()
+        q = q.cpu().numpy()
+        e = O.rel_error(q, g[f"q_m{m}"], area)
+        e_plain = O.rel_error(q, g["q_plain"], area)
+        say(f"compressed marching, two spheres, m={m} mode={mode}: rc={rc} err vs oracle "
+            f"{e:.2e}, vs plain marching {e_plain:.2e}; far/near blocks "
+            f"{d.n_far_blocks}/{d.n_near_blocks}, CG iterations {d.total_iters}")
+        assert rc == C.CQM_OK and d.converged == 1 and e < tol
+        p.close()
+
+
 def test_marching_argument_checks(ctx):
     wl = W.C0_TINY
     V, T = wl.mesh()
