@@ -686,22 +686,15 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     for (int k = 0; k < n; ++k) c += flags_[(size_t)kSysiStride * k + which] != 0;
     return c;
   };
+  // compressed inner operator with plain residuals: each cycle gains about
+  // the approximation error, so the inner target follows the last gain
+  const double relax = mode_is_h2(p0.opt.mode) && p0.opt.refine_plain ? 0.1 : 0.0;
   {
     Timed t(p0, CQM_K_OTHER, s);
-    launch_cycle_start<R>(sd, n, outer_tol, inner_tol, s);
+    launch_cycle_start<R>(sd, n, outer_tol, inner_tol, relax, s);
   }
   const int open = count(0);
   if (open == 0) return 0;
-  // the residual that closes this cycle is formed in double-double
-  // arithmetic, except the first one of an FP32 inner iteration (about 2e-7
-  // of the right-hand side: FP64 rounding of V x is far below it, and the
-  // next cycle corrects from a double-double residual); FP64 inner cycles
-  // reach 1e-8 in one cycle and the refinement may close after the next
-  bool resid_dd = sizeof(R) == 8;
-  for (int k = 0; k < n; ++k)
-    if (flags_[(size_t)kSysiStride * k] &&
-        !(eb.status_norms[3 * k + 1] > 1e-6 * eb.status_norms[3 * k]))
-      resid_dd = true;
   // systems open now are the ones whose cycle runs (and whose residual is
   // formed at its end)
   upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
@@ -746,14 +739,14 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   if (!lite_.empty()) {
     // residuals of the systems that ran this cycle (the list from its start)
     Timed t(p0, CQM_K_GEMV64, s);
-    if (resid_dd) {
-      for (const GClass& c : cyc_cls_)
-        launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
-                               p0.timer.ctr(CQM_K_GEMV64), s);
-      if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
-    } else {
-      dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
-    }
+    // the residual that closes the cycle, per system in double-double or
+    // FP64 as its cycle start chose (status flag 4); each launch takes its
+    // own systems and the others leave at once
+    for (const GClass& c : cyc_cls_)
+      launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
+                             p0.timer.ctr(CQM_K_GEMV64), s);
+    if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
+    dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
   }
   bool other_forms = false;  // stored-form residuals are complete already
   for (SolveState* st : S_) {
@@ -795,8 +788,8 @@ void Engine::finish_diag(int k, hipStream_t s, bool refresh) {
   if (refresh) {
     // residual norms of the last cycle, then the status of every system
     const SysDesc* sd = eb.desc + st->first;
-    if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), s);
-    else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, s);
+    if (mixed) launch_cycle_start<float>(sd, p.Fsys, outer_tol, std::max(p.opt.inner_tol, 2e-7), 0.0, s);
+    else launch_cycle_start<double>(sd, p.Fsys, outer_tol, p.opt.inner_tol, 0.0, s);
     status(s);
   }
   // else the status read that found every system closed is still current

@@ -52,7 +52,7 @@ template <> struct Pt4<double> { using T = double4; };
 
 constexpr int kQ = 6;          // Dunavant points per triangle
 constexpr int kMaxDuffy = 16;  // max Gauss points per Duffy dimension
-constexpr int kSysiStride = 4; // ints per system in the GMRES status array
+constexpr int kSysiStride = 8; // ints per system in the GMRES status array
 
 // Per-frequency constants of the factor exp(-s r) = 2^(ea r) e^{-2 pi i pb r}:
 // ea = -Re(s) log2(e), pb = Im(s) / (2 pi).  Padded with zero-work entries.
@@ -408,8 +408,11 @@ void launch_residual_combine(const SysDesc* sd, int n, hipStream_t s);
 // flags (kSysiStride ints) and ||ghat||, last residual norm, non-finite flag
 // (3 doubles) of n systems, into host-visible memory
 void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hipStream_t s);
+// relax > 0: inexact refinement (the inner target follows the reduction of
+// the last cycle, for inner operators that approximate the outer one)
 template <typename R>
-void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s);
+void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, double relax,
+                        hipStream_t s);
 // split: three launches over row slices; fused (split only): the first one
 // also sums the stored-operator partials of w = A v_j (no separate reduction)
 template <typename R>

@@ -181,7 +181,11 @@ void launch_dense_gemv(const cplx<R>* V, int M, int nsys, const cplx<R>* x, int6
 // members' flags and vectors all hang off that one load.  The group lists
 // are rebuilt by the host at its status checks; members closed since are
 // skipped.  which = 0: basis[j] -> basis[j+1] of systems with an open cycle
-// (inner precision); which = 1: x -> r = ghat - V x of open systems (FP64).
+// (inner precision); which = 1: x -> r = ghat - V x of open systems whose
+// residual is not formed in double-double this cycle (FP64).
+__device__ __forceinline__ bool member_on(const int* sysi, int which) {
+  return which == 0 ? sysi[1] != 0 : (sysi[0] != 0 && sysi[4] == 0);
+}
 template <typename R, bool kGrouped>
 __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict__ gl, int which,
                                                      int j, unsigned long long* ctr) {
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
     // groups with no open member leave at once (the full list is used by
     // graph-captured steps)
     bool any = false;
-    for (int k = 0; k < (kGrouped ? G.n : 1); ++k) any |= G.sysi[k][which == 0 ? 1 : 0] != 0;
+    for (int k = 0; k < (kGrouped ? G.n : 1); ++k) any |= member_on(G.sysi[k], which);
     if (!any) return;
   }
   int I, J;
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
       z.re = R(0);
       z.im = R(0);
       for (int k = 0; k < n; ++k) {
-        if (!G.sysi[k][which == 0 ? 1 : 0]) continue;
+        if (!member_on(G.sysi[k], which)) continue;
         cplx<R>* P = (cplx<R>*)G.symp[k];
         P[(int64_t)J * ntB + I * kB + threadIdx.x] = z;
         if (I != J) P[(int64_t)I * ntB + J * kB + threadIdx.x] = z;
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
   masked_tile<R>((const cplx<R>*)Vs, t, M, I, J, a);
   int done = 0;
   for (int k = 0; k < n; ++k) {
-    if (!G.sysi[k][which == 0 ? 1 : 0]) continue;
+    if (!member_on(G.sysi[k], which)) continue;
     const cplx<R>* x = which == 0 ? (const cplx<R>*)G.basis[k] + (int64_t)j * M
                                   : (const cplx<R>*)(const void*)G.x[k];
     tile_products<R>(a, M, I, J, x, (cplx<R>*)G.symp[k], ntB, colred);
@@ -247,6 +251,9 @@ __global__ __launch_bounds__(256) void k_symv_groups(const GroupLite* __restrict
 // solution, which amplifies per-frequency errors by up to rho^-N, inherits
 // that floor; formed in double-double, x converges to the solution of the
 // stored FP64 system.
+// open systems whose closing residual is formed in double-double
+__device__ __forceinline__ bool dd_on(const int* sysi) { return sysi[0] != 0 && sysi[4] != 0; }
+
 __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restrict__ gl, int grouped,
                                                        unsigned long long* ctr) {
   __shared__ dd colred[4][kB][2];
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restri
   const int n = grouped ? G.n : 1;
   {
     bool any = false;
-    for (int k = 0; k < n; ++k) any |= G.sysi[k][0] != 0;
+    for (int k = 0; k < n; ++k) any |= dd_on(G.sysi[k]);
     if (!any) return;
   }
   int I, J;
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restri
     // a tile left out by the cut-off holds only zeros
     if (threadIdx.x < kB) {
       for (int k = 0; k < n; ++k) {
-        if (!G.sysi[k][0]) continue;
+        if (!dd_on(G.sysi[k])) continue;
         cf64* P = (cf64*)G.symp[k];
         P[(int64_t)J * ntB + I * kB + threadIdx.x] = cf64{0.0, 0.0};
         P[np + (int64_t)J * ntB + I * kB + threadIdx.x] = cf64{0.0, 0.0};
@@ -286,11 +293,11 @@ __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restri
     // algorithmic bytes, once per group: the entries read under the FP64
     // cut-off, each open member's vectors once
     int open = 0;
-    for (int k = 0; k < n; ++k) open += G.sysi[k][0] != 0;
+    for (int k = 0; k < n; ++k) open += dd_on(G.sysi[k]);
     atomicAdd(ctr, ((unsigned long long)G.entries64 + (unsigned long long)open * 2 * M) * sizeof(cf64));
   }
   for (int k = 0; k < n; ++k) {
-    if (!G.sysi[k][0]) continue;
+    if (!dd_on(G.sysi[k])) continue;
     const cf64* x = G.x[k];
     cf64* P = (cf64*)G.symp[k];
     const cf64 xj = load_x<double>(x, J * kB + c, M);
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(256) void k_symv_resid_dd(const GroupLite* __restri
 // an open outer iteration).
 __global__ __launch_bounds__(256) void k_symv_resid_dd_reduce(const SysDesc* __restrict__ sd) {
   const SysDesc D = sd[blockIdx.y];
-  if (!D.symp || !D.sysi[0]) return;
+  if (!D.symp || !dd_on(D.sysi)) return;
   const int M = D.M;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(256) void k_symv_reduce_desc(const SysDesc* __restr
                                                           int j) {
   const SysDesc D = sd[blockIdx.y];
   if (!D.symp) return;  // not a stored-operator system (matrix-free in a mixed batch)
-  if (which == 0 ? !D.sysi[1] : !D.sysi[0]) return;
+  if (!member_on(D.sysi, which)) return;
   const int M = D.M;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= M) return;

@@ -16,7 +16,10 @@ constexpr double kFloorTol = 1e-13;  // stagnation below this counts as converge
 
 // sysd per system (8 doubles): 0 beta, 1 cycle tolerance, 2 ||ghat||,
 // 3 last true residual norm, 4 non-finite flag.  sysi (kSysiStride ints):
-// 0 system active, 1 cycle active, 2 Arnoldi steps in cycle, 3 total steps.
+// 0 system active, 1 cycle active, 2 Arnoldi steps in cycle, 3 total steps,
+// 4 the residual closing this cycle is formed in double-double (set per
+// system at the cycle's start, so a system's arithmetic never depends on
+// the others it shares a batch with).
 // Every kernel takes the system descriptors; workgroup k serves system k, so
 // systems of different lengths and problems share the launches.
 __global__ __launch_bounds__(256) void k_gmres_init(const SysDesc* __restrict__ sd) {
@@ -38,12 +41,18 @@ __global__ __launch_bounds__(256) void k_gmres_init(const SysDesc* __restrict__ 
     D.sysi[1] = 0;
     D.sysi[2] = 0;
     D.sysi[3] = 0;
+    D.sysi[4] = 0;
   }
 }
 
+// relax > 0 (inexact refinement): once a cycle has reduced the true
+// residual by q = rn / previous, the next cycle's inner target is relaxed to
+// relax * q of its start (at most 1e-3, never tighter than inner_tol): when
+// the inner operator only approximates the one of the residual, each cycle
+// gains about q, and solving the inner system further gains nothing.
 template <typename R>
 __global__ __launch_bounds__(256) void k_cycle_start(const SysDesc* __restrict__ sd, double outer_tol,
-                                                     double inner_tol) {
+                                                     double inner_tol, double relax) {
   __shared__ double red[16];
   const SysDesc D = sd[blockIdx.x];
   int* st = D.sysi;
@@ -76,11 +85,17 @@ __global__ __launch_bounds__(256) void k_cycle_start(const SysDesc* __restrict__
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    double itol = inner_tol;
+    if (relax > 0.0 && rn < prev) itol = fmax(inner_tol, fmin(relax * rn / prev, 1e-3));
     d[0] = rn;
-    d[1] = fmax(inner_tol * rn, 0.5 * outer_tol * bn);
+    d[1] = fmax(itol * rn, 0.5 * outer_tol * bn);
     d[3] = rn;
     st[1] = 1;
     st[2] = 0;
+    // double-double closing residual: FP64 inner cycles, and FP32 ones whose
+    // residual is already below 1e-6 (before that, FP64 rounding of V x is
+    // far below the cycle's gain and the next cycle corrects it)
+    st[4] = (sizeof(R) == 8 || rn <= 1e-6 * bn) ? 1 : 0;
   }
   for (int k = threadIdx.x; k <= m; k += 256) D.g[k] = cf64{k == 0 ? rn : 0.0, 0.0};
   cplx<R>* v0 = (cplx<R>*)D.basis;
@@ -792,8 +807,9 @@ void launch_gather_diag(const SysDesc* sd, int n, int* flags, double* norms, hip
   CQM_HIP(hipGetLastError());
 }
 template <typename R>
-void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, hipStream_t s) {
-  hipLaunchKernelGGL((k_cycle_start<R>), dim3(n), dim3(256), 0, s, sd, outer_tol, inner_tol);
+void launch_cycle_start(const SysDesc* sd, int n, double outer_tol, double inner_tol, double relax,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_cycle_start<R>), dim3(n), dim3(256), 0, s, sd, outer_tol, inner_tol, relax);
   CQM_HIP(hipGetLastError());
 }
 // One workgroup per system, or the three launches over row slices (the
@@ -827,8 +843,8 @@ template <typename R> void launch_cycle_finish(const SysDesc* sd, int n, int max
   CQM_HIP(hipGetLastError());
 }
 
-template void launch_cycle_start<float>(const SysDesc*, int, double, double, hipStream_t);
-template void launch_cycle_start<double>(const SysDesc*, int, double, double, hipStream_t);
+template void launch_cycle_start<float>(const SysDesc*, int, double, double, double, hipStream_t);
+template void launch_cycle_start<double>(const SysDesc*, int, double, double, double, hipStream_t);
 template void launch_arnoldi<float>(const SysDesc*, int, int, int, bool, bool, bool,
                                     unsigned long long*, int*, hipStream_t);
 template void launch_arnoldi<double>(const SysDesc*, int, int, int, bool, bool, bool,
