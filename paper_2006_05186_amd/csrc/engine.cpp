@@ -438,6 +438,18 @@ void Engine::set(const std::vector<SolveState*>& S, hipStream_t s) {
     CQM_HIP(hipHostMalloc((void**)&eb.staging, sizeof(GroupLite) * c, hipHostMallocDefault));
     eb.staging_cap = c;
   }
+  ensure(eb.arn_desc, eb.arn_cap, std::max<size_t>(1, hd_.size()));
+  if (eb.arn_staging_cap < 2 * (size_t)n) {
+    if (eb.arn_staging) {
+      CQM_HIP(hipStreamSynchronize(s));
+      CQM_HIP(hipHostFree(eb.arn_staging));
+    }
+    eb.arn_staging = nullptr;
+    eb.arn_staging_cap = 0;
+    const size_t c = std::max<size_t>(2 * (size_t)n, 256);
+    CQM_HIP(hipHostMalloc((void**)&eb.arn_staging, sizeof(SysDesc) * c, hipHostMallocDefault));
+    eb.arn_staging_cap = c;
+  }
   if (eb.status_host_cap < (size_t)n) {
     if (eb.status_host) {
       CQM_HIP(hipStreamSynchronize(s));
@@ -566,6 +578,16 @@ void Engine::status(hipStream_t s) {
 // set in the host copy of the flags, sorted by mesh size, uploaded through
 // the pinned staging area.  The stream was synchronised by the status read,
 // so the previous upload from the same staging area is complete.
+void Engine::upload_arnoldi(int slot, hipStream_t s) {
+  const int n = (int)hd_.size();
+  SysDesc* st = eb.arn_staging + (size_t)slot * n;
+  int c = 0;
+  for (int k = 0; k < n; ++k)
+    if (flags_[(size_t)kSysiStride * k + 1]) st[c++] = hd_[k];
+  arn_n_ = c;
+  if (c) CQM_HIP(hipMemcpyAsync(eb.arn_desc, st, sizeof(SysDesc) * c, hipMemcpyHostToDevice, s));
+}
+
 void Engine::upload_open(int which, GroupLite* dst, size_t stage, std::vector<GClass>& cls,
                          hipStream_t s) {
   cls.clear();
@@ -646,8 +668,11 @@ void Engine::step_eager(int j, const GroupLite* list, const std::vector<GClass>&
     }
   }
   Timed t(p0, CQM_K_ARNOLDI, s);
-  launch_arnoldi<R>(eb.desc, n, maxM_, j, split_, split_, fuse_pre<R>(),
-                    p0.timer.ctr(CQM_K_ARNOLDI), eb.cyc_host_dev, s);
+  // the systems open when the list was built (the others issue no loads;
+  // one closed since then leaves at its flag)
+  const bool listed = arn_n_ > 0;
+  launch_arnoldi<R>(listed ? eb.arn_desc : eb.desc, listed ? arn_n_ : n, maxM_, j, split_, split_,
+                    fuse_pre<R>(), p0.timer.ctr(CQM_K_ARNOLDI), eb.cyc_host_dev, s);
 }
 
 // The same step from its captured graph (captured on first use).
@@ -698,6 +723,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   // systems open now are the ones whose cycle runs (and whose residual is
   // formed at its end)
   upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
+  if (!graphs_) upload_arnoldi(0, s);
   const GroupLite* step_list = eb.open_cycle;
   step_cls_ = cyc_cls_;
   // host copies of the cycle-open flags: set here for the systems whose
@@ -726,6 +752,7 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     // queued before step j - kAhead + 1, whose last kernel has started
     if (!graphs_ && j - kAhead > upload_j && 4 * c <= 3 * listed) {
       upload_open(1, eb.open_step, lite_.size(), step_cls_, s);
+      upload_arnoldi(1, s);
       step_list = eb.open_step;
       listed = c;
       upload_j = j;

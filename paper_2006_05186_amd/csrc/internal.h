@@ -144,6 +144,10 @@ struct EngineBufs {
   size_t step_cap = 0;
   GroupLite* staging = nullptr;     // pinned host copies of the two lists
   size_t staging_cap = 0;
+  SysDesc* arn_desc = nullptr;      // descriptors of the systems an eager
+  size_t arn_cap = 0;               // Arnoldi step runs (open at the last
+  SysDesc* arn_staging = nullptr;   // list build), and their pinned staging
+  size_t arn_staging_cap = 0;       // (two slots: cycle start, step lists)
   GroupLite* all_groups = nullptr;  // every group (graph-captured steps)
   size_t all_cap = 0;
   GemvGroup* groups = nullptr;
@@ -511,6 +515,11 @@ class Engine {
   std::vector<GClass> cyc_cls_, step_cls_;
   // groups with a member whose flag `which` is set (host flags), by mesh
   // size, uploaded to dst from the pinned staging area at `stage`
+  // descriptors of the systems with an open cycle into eb.arn_desc (staging
+  // slot 0 at a cycle start, 1 at later list builds); the eager Arnoldi
+  // steps run over them only, so closed systems issue no loads
+  void upload_arnoldi(int slot, hipStream_t s);
+  int arn_n_ = 0;
   void upload_open(int which, GroupLite* dst, size_t stage, std::vector<GClass>& cls,
                    hipStream_t s);
   // reduce = false leaves the partial sums for the Arnoldi step to add up

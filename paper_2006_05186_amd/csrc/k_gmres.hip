@@ -519,8 +519,10 @@ __global__ __launch_bounds__(kArnRows) void k_arn_dots(const SysDesc* __restrict
   if (!wr) return;
   if (sum && valid) as_global((cplx<R>*)D.basis)[(int64_t)(j + 1) * M + i] = x;
   if (ctr && threadIdx.x == 0) {
+    // inner products: v_0 .. v_j and w; with the stored product's tile
+    // partials reduced here, their nt slots per row and the sum's write
     const unsigned long long rows = min(kArnRows, M - s * kArnRows);
-    atomicAdd(ctr, rows * (j + 2) * sizeof(cplx<R>));
+    atomicAdd(ctr, rows * ((j + 2) + (sum ? nt + 1 : 0)) * sizeof(cplx<R>));
   }
 }
 
@@ -711,7 +713,9 @@ __global__ __launch_bounds__(kArnRows) void k_arn_finish(const SysDesc* __restri
   }
   if (ctr && tid == 0) {
     const unsigned long long rows = min(kArnRows, M - s * kArnRows);
-    atomicAdd(ctr, rows * (second ? j + 3 : 2) * sizeof(cplx<R>));
+    // second pass and normalisation; with the next step's preconditioner
+    // applied here, the rows of the diagonal-block inverse and the write
+    atomicAdd(ctr, rows * ((second ? j + 3 : 2) + (fuse ? kSymB + 1 : 0)) * sizeof(cplx<R>));
   }
 }
 
