@@ -724,6 +724,13 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
   // formed at its end)
   upload_open(0, eb.open_cycle, 0, cyc_cls_, s);
   if (!graphs_) upload_arnoldi(0, s);
+  // which closing-residual launches this cycle needs: each system's choice
+  // (status flag 4, set by its cycle start) came with the status read
+  bool any_dd = false, any_64 = false;
+  for (int k = 0; k < n; ++k) {
+    if (!flags_[(size_t)kSysiStride * k + 1]) continue;
+    (flags_[(size_t)kSysiStride * k + 4] ? any_dd : any_64) = true;
+  }
   const GroupLite* step_list = eb.open_cycle;
   step_cls_ = cyc_cls_;
   // host copies of the cycle-open flags: set here for the systems whose
@@ -769,11 +776,14 @@ template <typename R> int Engine::cycle_t(hipStream_t s) {
     // the residual that closes the cycle, per system in double-double or
     // FP64 as its cycle start chose (status flag 4); each launch takes its
     // own systems and the others leave at once
-    for (const GClass& c : cyc_cls_)
-      launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
-                             p0.timer.ctr(CQM_K_GEMV64), s);
-    if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
-    dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
+    if (any_dd) {
+      for (const GClass& c : cyc_cls_)
+        launch_resid_dd_groups(eb.open_cycle + c.off, c.count, c.M, c.grouped,
+                               p0.timer.ctr(CQM_K_GEMV64), s);
+      if (!cyc_cls_.empty()) launch_resid_dd_reduce(eb.desc, (int)hd_.size(), maxM_, s);
+    }
+    if (any_64)
+      dense_product<double>(eb.open_cycle, cyc_cls_, 1, 0, true, p0.timer.ctr(CQM_K_GEMV64), s);
   }
   bool other_forms = false;  // stored-form residuals are complete already
   for (SolveState* st : S_) {
