@@ -26,9 +26,16 @@ constexpr int kRowsPerWave = kB / 4;  // 4 waves per tile, 16 rows each
 // lane (each row read by a wave is 64 contiguous entries).
 template <typename R>
 __device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ Vt, cplx<R>* a) {
+  // each operator entry is read once per product: non-temporal loads keep
+  // the stream from evicting the vectors and partial sums
   const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  typedef R v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) a[q] = as_global(Vt)[(w * kRowsPerWave + q) * kB + c];
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(Vt) + (w * kRowsPerWave + q) * kB + c);
+    a[q].re = v.x;
+    a[q].im = v.y;
+  }
 }
 
 template <typename R>
