@@ -96,21 +96,6 @@ void setup_structure(Problem& p) {
     }
     if (ck.empty()) ck.push_back(RankTask{});
     if (lk.empty()) lk.push_back(RankTask{});
-    // lag-0 tables: the same tasks over the compact collapsed slices (the
-    // slice store holds Rcap slices per block, c_off = Rcap x the compact
-    // offset; within a block the row offset is unchanged)
-    auto compact = [&](std::vector<RankTask> v) {
-      for (RankTask& t : v) {
-        if (t.acols == 0) continue;
-        const BlockDesc& B = h.blocks[t.block];
-        t.c_off = B.c_off / h.Rcap + (t.c_off - B.c_off);
-        t.d_off = 0;
-      }
-      return v;
-    };
-    h.core_tasks0_d = up(compact(ck));
-    h.leaf_tasks0_d = up(compact(lk));
-    h.ones_d = up(std::vector<int>(std::max<size_t>(h.blocks.size(), 1), 1));
     // fast right-hand side: z_{b,t} slots, Rcap x acols per block
     std::vector<int64_t> zoff(std::max<size_t>(h.blocks.size(), 1), 0);
     int64_t zo = 0;
@@ -120,7 +105,6 @@ void setup_structure(Problem& p) {
     }
     h.z_elems = zo;
     h.zoff_d = up(zoff);
-    h.one_d = up(std::vector<cf64>{cf64{1.0, 0.0}});
     h.core_tiles_d = up(ct);
     h.core_tasks_d = up(ck);
     h.leaf_tiles_d = up(lt);
@@ -173,6 +157,7 @@ void set_views(Problem& p) {
   h.yp_d = base + h.off_yp;
   h.dhat_d = h.off_dhat ? (cf64*)(base + h.off_dhat) : nullptr;
   h.w0_d = h.off_w0 ? (void*)(base + h.off_w0) : nullptr;
+  h.w0dense_d = h.off_w0dense ? (double*)(base + h.off_w0dense) : nullptr;
   h.z_d = h.off_z ? (cf64*)(base + h.off_z) : nullptr;
   h.hxh_d = h.off_hxh ? (cf64*)(base + h.off_hxh) : nullptr;
   h.rpart_d = h.off_rpart ? (cf64*)(base + h.off_rpart) : nullptr;
@@ -201,6 +186,7 @@ size_t h2_workspace_bytes(const Problem& pc) {
   h.off_w0 = p.opt.marching
                  ? take((size_t)(h.cstore_elems / h.Rcap) * (h.store_fp64 ? sizeof(cf64) : sizeof(cf32)))
                  : 0;
+  h.off_w0dense = p.opt.marching ? take(h.perm.size() * h.perm.size() * sizeof(double)) : 0;
   if (p.opt.marching) {
     const size_t coef = h.cl.size() * (size_t)h.p;
     h.off_z = take((size_t)std::max<int64_t>(h.z_elems, 1) * sizeof(cf64));
@@ -259,7 +245,7 @@ void h2_apply_weights(Problem& p, int k0, int nsys, const cf64* x, int64_t xs, c
   H2Operator& h = *p.h2;
   require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
   if (k0 == 0 && nsys == 1 && h.w0_ready)
-    launch_h2_apply_lag0(p, h, x, xs, y, ys, s);
+    launch_lag0_dense_product(h, x, y, s);
   else
     launch_h2_apply<double>(p, h, k0, nsys, x, xs, y, ys, h.dhat_d, s);
 }
@@ -284,9 +270,11 @@ void h2_marching_weights(Problem& p, hipStream_t s) {
   require(h.dhat_d != nullptr, CQM_EINVAL, "no marching weights in the workspace");
   launch_fibre_dft(p, h, h.dvec_d, h.dhat_d, s);
   // What_0 is applied in every conjugate-gradient iteration: collapse its
-  // rank terms once
-  require(h.w0_d != nullptr, CQM_EINVAL, "no lag-0 slices in the workspace");
+  // rank terms once and hold it densely, as the solve stage of the method
+  // holds What_0 for its factorisation
+  require(h.w0_d != nullptr && h.w0dense_d != nullptr, CQM_EINVAL, "no lag-0 weights in the workspace");
   launch_collapse_lag0(p, h, s);
+  launch_expand_lag0(p, h, s);
   h.w0_ready = true;
 }
 template void h2_apply<float>(Problem&, int, int, const cf32*, int64_t, cf32*, int64_t, const int*, hipStream_t);
@@ -327,10 +315,6 @@ void h2_release(Problem& p) {
   release(h.core_tasks_d);
   release(h.leaf_tiles_d);
   release(h.leaf_tasks_d);
-  release(h.core_tasks0_d);
-  release(h.leaf_tasks0_d);
-  release(h.ones_d);
-  release(h.one_d);
   release(h.zoff_d);
   delete p.h2;
   p.h2 = nullptr;

@@ -101,13 +101,6 @@ struct H2Operator {
   RankTile* leaf_tiles_d = nullptr;
   RankTask* leaf_tasks_d = nullptr;
   int n_core_tiles = 0, n_leaf_tiles = 0;
-  // time marching, lag 0: the same tables over one collapsed slice per
-  // block (W0_b = sum_t dhat_t[0] C_t, compact: block b at c_off / Rcap),
-  // with rank 1 and fibre value 1
-  RankTask* core_tasks0_d = nullptr;
-  RankTask* leaf_tasks0_d = nullptr;
-  int* ones_d = nullptr;    // one entry per block, each 1
-  cf64* one_d = nullptr;    // a single 1 + 0i
   // time marching, fast right-hand side (eq. fastrhs): per block the rank
   // terms' fibre-convolved column histories z_{b,t} (Rcap x acols, from
   // zoff[b]), the cluster coefficients of every past step and the split-K
@@ -120,6 +113,7 @@ struct H2Operator {
   size_t off_xp = 0, off_yp = 0;
   size_t off_dhat = 0;  // marching: the fibres' transforms (integration weights)
   size_t off_w0 = 0;    // marching: collapsed lag-0 slices (storage precision)
+  size_t off_w0dense = 0;  // marching: What_0 = Re W0, dense M x M (FP64)
   size_t off_z = 0, off_hxh = 0, off_rpart = 0;  // marching: fast right-hand side
   int64_t cstore_elems = 0, dvec_elems = 0, stage_elems = 0;
   int64_t stage_budget = 0;       // cf64 elements per MACA batch
@@ -129,8 +123,9 @@ struct H2Operator {
   cf64* stage_d = nullptr;
   cf64* dvec_d = nullptr;
   cf64* dhat_d = nullptr;
-  void* w0_d = nullptr;
-  bool w0_ready = false;
+  void* w0_d = nullptr;   // W0_b = sum_t dhat_t[0] C_t per block, at c_off / Rcap
+  double* w0dense_d = nullptr;
+  bool w0_ready = false;  // both formed for the current slices
   cf64* z_d = nullptr;
   cf64* hxh_d = nullptr;
   cf64* rpart_d = nullptr;
@@ -151,12 +146,14 @@ void launch_maca_finalize_batch(const Problem& p, H2Operator& h, int b0, int nb,
 template <typename R>
 void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cplx<R>* x, int64_t xs,
                      cplx<R>* y, int64_t ys, const cf64* fibres, hipStream_t s);
-// one system through the collapsed lag-0 slices (after launch_collapse_lag0)
-void launch_h2_apply_lag0(const Problem& p, H2Operator& h, const cf64* x, int64_t xs, cf64* y,
-                          int64_t ys, hipStream_t s);
 // W0_b = sum_{t < rank_b} dhat_t[0] C_t for every block, in FP64, stored in
 // the storage precision at the compact offsets
 void launch_collapse_lag0(const Problem& p, H2Operator& h, hipStream_t s);
+// What_0 = Re W0 written densely (M x M, triangle order, FP64): near and
+// expanded far blocks copy their slice, cores add U_r Re(W0_b) U_c^T
+void launch_expand_lag0(const Problem& p, H2Operator& h, hipStream_t s);
+// y = What_0 q (q complex with zero imaginary part; y likewise)
+void launch_lag0_dense_product(const H2Operator& h, const cf64* q, cf64* y, hipStream_t s);
 // fast right-hand side of the compressed marching (eq. fastrhs), FP64:
 // push: hx = step m's input x (triangle order) in cluster order, and its
 // cluster coefficients into history slot m; sum: y = sum_{k=1}^{n}

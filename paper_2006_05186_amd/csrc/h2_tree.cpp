@@ -228,6 +228,8 @@ void h2_build_structure(Problem& p, H2Operator& h) {
       if (b.kind == kFarCore) {
         b.arows = b.acols = P;
         ++h.n_core;
+        // time marching expands What_0 densely, cores through full bases
+        if (p.opt.marching) need_full[b.r] = need_full[b.c] = 1;
       } else {
         b.arows = h.cl[b.r].size();
         b.acols = h.cl[b.c].size();

@@ -8,6 +8,7 @@
 // wave reads one matrix entry as a broadcast and consecutive systems as
 // coalesced vectors.  R: arithmetic precision; S: storage of the slices.
 #include "h2_internal.h"
+#include "device_util.h"
 
 namespace cqm {
 
@@ -506,11 +507,90 @@ void launch_h2_apply(const Problem& p, H2Operator& h, int l0, int nsys, const cp
   h2_apply_with<R>(p, h, op, l0, nsys, x, xs, y, ys, s);
 }
 
-void launch_h2_apply_lag0(const Problem& p, H2Operator& h, const cf64* x, int64_t xs, cf64* y,
-                          int64_t ys, hipStream_t s) {
-  require(h.w0_ready && h.w0_d, CQM_EINVAL, "lag-0 slices not formed");
-  const RankOperands op{h.core_tasks0_d, h.leaf_tasks0_d, h.ones_d, h.w0_d, h.one_d, 0};
-  h2_apply_with<double>(p, h, op, 0, 1, x, xs, y, ys, s);
+// What_0 = Re W0 written densely (triangle order, row-major M x M, FP64).
+// One workgroup per block: near and expanded far blocks copy the real part
+// of their collapsed slice; a core forms T = U_r Re(W0_b) a few rows at a
+// time in LDS, then T U_c^T (full cluster bases).  The blocks partition the
+// matrix, so every entry is written once.
+constexpr int kExpandLds = 2048;
+template <typename S>
+__global__ __launch_bounds__(256) void k_expand_lag0(const BlockDesc* __restrict__ blocks, int Rcap,
+                                                     const cplx<S>* __restrict__ w0,
+                                                     const int* __restrict__ cl,
+                                                     const int* __restrict__ perm,
+                                                     const double* __restrict__ Ufull,
+                                                     const int64_t* __restrict__ uoff, int P, int M,
+                                                     double* __restrict__ W) {
+  const BlockDesc B = blocks[blockIdx.x];
+  const int rb = cl[4 * B.r], cb = cl[4 * B.c];
+  const cplx<S>* C = w0 + B.c_off / Rcap;
+  if (B.kind != kFarCore) {
+    const int n = B.arows * B.acols;
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int i = e / B.acols, j = e - i * B.acols;
+      W[(int64_t)perm[rb + i] * M + perm[cb + j]] = (double)C[e].re;
+    }
+    return;
+  }
+  __shared__ double Tsh[kExpandLds];
+  const int rows = cl[4 * B.r + 1] - rb, cols = cl[4 * B.c + 1] - cb;
+  const double* Ur = Ufull + uoff[B.r];
+  const double* Uc = Ufull + uoff[B.c];
+  const int rows_per = max(1, kExpandLds / P);
+  for (int i0 = 0; i0 < rows; i0 += rows_per) {
+    const int nr = min(rows_per, rows - i0);
+    for (int e = threadIdx.x; e < nr * P; e += 256) {
+      const int i = i0 + e / P, nu = e % P;
+      double acc = 0.0;
+      for (int mu = 0; mu < P; ++mu) acc += Ur[(int64_t)i * P + mu] * (double)C[(int64_t)mu * P + nu].re;
+      Tsh[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * cols; e += 256) {
+      const int ii = e / cols, j = e - ii * cols;
+      double acc = 0.0;
+      for (int nu = 0; nu < P; ++nu) acc += Tsh[ii * P + nu] * Uc[(int64_t)j * P + nu];
+      W[(int64_t)perm[rb + i0 + ii] * M + perm[cb + j]] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_expand_lag0(const Problem& p, H2Operator& h, hipStream_t s) {
+  require(h.p <= kExpandLds, CQM_EINVAL, "interpolation rank above the expansion tile");
+  const unsigned nb = (unsigned)h.blocks.size();
+  const int M = (int)h.perm.size();
+  if (nb == 0) return;
+  if (h.store_fp64)
+    hipLaunchKernelGGL((k_expand_lag0<double>), dim3(nb), dim3(256), 0, s, h.blocks_d, h.Rcap,
+                       (const cf64*)h.w0_d, h.cl_d, h.perm_d, h.Ufull_d, h.ufull_off_d, h.p, M,
+                       h.w0dense_d);
+  else
+    hipLaunchKernelGGL((k_expand_lag0<float>), dim3(nb), dim3(256), 0, s, h.blocks_d, h.Rcap,
+                       (const cf32*)h.w0_d, h.cl_d, h.perm_d, h.Ufull_d, h.ufull_off_d, h.p, M,
+                       h.w0dense_d);
+  CQM_HIP(hipGetLastError());
+}
+
+// y = What_0 q for the real parts of q: one wave per row, lanes along the
+// row (coalesced), the row sum in a fixed order; y's imaginary part is 0.
+__global__ __launch_bounds__(256) void k_lag0_dense_product(const double* __restrict__ W, int M,
+                                                            const cf64* __restrict__ q,
+                                                            cf64* __restrict__ y) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= M) return;  // whole waves leave: no barrier follows
+  const double* w = W + (int64_t)row * M;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < M; j += 64) acc += w[j] * q[j].re;
+  acc = wave_sum(acc);
+  if (lane == 0) y[row] = cf64{acc, 0.0};
+}
+
+void launch_lag0_dense_product(const H2Operator& h, const cf64* q, cf64* y, hipStream_t s) {
+  const int M = (int)h.perm.size();
+  hipLaunchKernelGGL(k_lag0_dense_product, dim3((M + 3) / 4), dim3(256), 0, s, h.w0dense_d, M, q, y);
+  CQM_HIP(hipGetLastError());
 }
 
 // W0_b[e] = sum_{t < rank_b} dhat_t[0] C_t[e]: one workgroup per block, the
