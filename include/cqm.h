@@ -124,8 +124,10 @@ typedef struct cqm_options {
   int32_t marching;      /* nonzero: the workspace also holds the real
                             integration weights What_n, n = 0..N, of the
                             stored form (N+1 slices of the packed
-                            triangle, 8 B per entry) for
-                            cqm_solve_marching                        (0)   */
+                            triangle, 8 B per entry), or for a compressed
+                            mode the transformed fibres, What_0 densely
+                            (8 M^2 B) and the history of past densities,
+                            for cqm_solve_marching                    (0)   */
   double cutoff_inner;   /* cut-off of the stored form's inner-iteration
                             (FP32) operator: a 64 x 64 tile (16 x 16 in the
                             assembly) is left out of frequency l when
