@@ -149,7 +149,10 @@ typedef struct cqm_options {
                             carries the inner iterations; 0 forms it with
                             the compressed operator, whose approximation
                             error (Section 6.1: m, eta, eps_aca) then
-                            stays in the answer                        (1) */
+                            stays in the answer.  With refine_plain the
+                            inner target of a cycle after the first is
+                            0.1 x the previous cycle's residual reduction
+                            (at most 1e-3, never below inner_tol)      (1) */
   int32_t formulation;   /* CQM_FORMULATION_*: the boundary integral
                             equation solved                     (INDIRECT) */
 } cqm_options;
