@@ -487,8 +487,8 @@ void solve_states(std::vector<SolveState*>& S, hipStream_t s);  // full solves, 
 // precision): used by the batch solve and by the serving loop.
 class Engine {
  public:
-  explicit Engine(Ctx& c) : ctx(c), eb(c.eb) {}
-  Engine(Ctx& c, EngineBufs& b) : ctx(c), eb(b) {}  // own descriptor/status buffers
+  explicit Engine(Ctx& c) : eb(c.eb) {}
+  Engine(Ctx&, EngineBufs& b) : eb(b) {}  // own descriptor/status buffers
   ~Engine();
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
@@ -503,7 +503,6 @@ class Engine {
   bool mixed = true;
  private:
   template <typename R> int cycle_t(hipStream_t s);
-  Ctx& ctx;
   EngineBufs& eb;
   std::vector<SolveState*> S_;
   std::vector<SysDesc> hd_;
