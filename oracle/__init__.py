@@ -16,3 +16,4 @@ from .compress import *  # noqa: F401,F403
 from .marching import *  # noqa: F401,F403
 from . import calderon  # noqa: F401
 from . import marching  # noqa: F401
+from . import hypersingular  # noqa: F401

@@ -91,3 +91,55 @@ def double_layer_reference(Ti, Tj, rtol=1e-11):
     f = lambda X: solid_angle(X, *Tj)
     whole = _est(f, *Ti)
     return -_adapt(f, *Ti, whole, rtol * max(abs(whole), 1e-300), 0) / (4.0 * math.pi)
+
+
+def _barycentric_gradient(T, b):
+    """lambda_b(y) = 1 + g . (y - T[b]) on the flat triangle T: g = n x e_b / (2|T|),
+    e_b the edge opposite vertex b taken in the vertex order."""
+    A, B, C = T
+    c = np.cross(B - A, C - A)
+    n = c / np.linalg.norm(c)
+    e = T[(b + 2) % 3] - T[(b + 1) % 3]
+    return np.cross(n, e) / np.linalg.norm(c), n
+
+
+def weighted_triangle_potential(P, T, b):
+    """int_T lambda_b(y) dy / |P - y| for points P (n,3): lambda_b is linear, so
+    lambda_b(y) = lambda_b(P') + g.(y - P') with P' the projection of P on the
+    plane; the first part is the uniform potential, and the in-plane moment
+    int_T (y - P')/|P - y| dy is the surface gradient of |P - y| integrated,
+    i.e. by the divergence theorem the boundary integral of |P - y| times the
+    outward edge normal, each edge in closed form."""
+    P = np.atleast_2d(P)
+    g, n = _barycentric_gradient(T, b)
+    w = (P - T[0]) @ n
+    Pp = P - w[:, None] * n
+    lam = 1.0 + (Pp - T[b]) @ g
+    mom = np.zeros(len(P))
+    for k in range(3):
+        Q1, Q2 = T[k], T[(k + 1) % 3]
+        L = np.linalg.norm(Q2 - Q1)
+        u = (Q2 - Q1) / L
+        nu = np.cross(u, n)  # outward in-plane normal for the vertex order
+        t0 = (P - Q1) @ u
+        rho2 = np.maximum(np.sum((P - Q1) ** 2, axis=1) - t0 * t0, 0.0)
+        rho = np.sqrt(rho2)
+
+        def F(tau):
+            sq = np.sqrt(tau * tau + rho2)
+            safe = np.where(rho > 0.0, rho, 1.0)
+            return 0.5 * (tau * sq + np.where(rho > 0.0, rho2 * np.arcsinh(tau / safe), 0.0))
+
+        mom += (F(L - t0) - F(-t0)) * (nu @ g)
+    return lam * triangle_potential(P, *T) + mom
+
+
+def weighted_static_reference(Ti, Tj, a, b, rtol=1e-11):
+    """int_{Ti} int_{Tj} lambda_a(x) lambda_b(y) / (4 pi |x-y|), lambda the
+    barycentric coordinates of vertex a of Ti and vertex b of Tj."""
+    Ti = [np.asarray(v, float) for v in Ti]
+    Tj = [np.asarray(v, float) for v in Tj]
+    ga, _ = _barycentric_gradient(Ti, a)
+    f = lambda X: (1.0 + (X - Ti[a]) @ ga) * weighted_triangle_potential(X, Tj, b)
+    whole = _est(f, *Ti)
+    return _adapt(f, *Ti, whole, rtol * abs(whole), 0) / (4.0 * math.pi)
