@@ -468,6 +468,42 @@ def tag_of(wl):
     return f"sphere{wl.M}_N{wl.N}"
 
 
+def run_hypersingular(C, torch, ctx, wl, reps=5):
+    """The hypersingular product D(s_l) x_l on the piecewise-linear space
+    (cqm_apply_D, FP64) over every frequency of the band, timed by events
+    after the once-per-mesh static parts; the far rate counts the 6 x 6
+    point pairs of every ordered far pair of triangles per frequency."""
+    from paper_2006_05186_amd.solver import Problem
+    V, T = wl.mesh()
+    p = Problem(ctx, V, T, wl.N, wl.T, formulation=C.CQM_FORMULATION_DIRECT)
+    H = wl.N // 2 + 1
+    x = torch.as_tensor(W.random_complex((H, len(V)), seed=5), device="cuda")
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    p.apply_D(x)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_first = e0.elapsed_time(e1) * 1e-3
+    e0.record(st)
+    for _ in range(reps):
+        p.apply_D(x)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_apply = e0.elapsed_time(e1) / reps * 1e-3
+    p.close()
+    # ordered pairs of triangles sharing a vertex (the near field)
+    by_vertex = {}
+    for i, tri in enumerate(T):
+        for v in tri:
+            by_vertex.setdefault(int(v), set()).add(i)
+    near = sum(len(set().union(*(by_vertex[int(v)] for v in tri))) for tri in T)
+    far_pairs = len(T) * len(T) - near
+    return {"workload": wl.name, "vertices": len(V), "frequencies": H, "ms": t_apply * 1e3,
+            "first_call_ms": t_first * 1e3, "far_point_pairs_per_s": far_pairs * 36 * H / t_apply,
+            "near_pairs": near}
+
+
 def far32_probe(C, torch, ctx, wl):
     """Kernel evaluation rate of the matrix-free FP32 far product (all
     distinct frequency systems active, no cut-off): cqm_apply_V timed by
@@ -662,7 +698,7 @@ def main():
                     help="only measure the lane-op rates of v_exp_f32, v_sin_f32, v_cos_f32, "
                          "v_rsq_f32 and FP32/FP64 FMA (lib/libcqm_probe.so) and exit")
     ap.add_argument("--part", choices=["far32", "compressed", "h2apply", "marching", "study",
-                                       "batch48", "orders"],
+                                       "batch48", "orders", "hypersingular"],
                     help="only run one piece on the workload (for counter profiles) and print "
                          "its record")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -707,6 +743,8 @@ def main():
             rec = run_orders(C, torch, ctx)
         elif args.part == "compressed":
             rec = run_compressed(C, torch, ctx)
+        elif args.part == "hypersingular":
+            rec = run_hypersingular(C, torch, ctx, wl)
         else:
             rec = [run_marching(C, torch, ctx, wl), marching_compressed(C, torch, ctx, wl)]
         C.cqm_ctx_destroy(ctx)
@@ -795,6 +833,7 @@ def main():
         out["compressed"] = run_compressed(C, torch, ctx)
         print("compressed done", file=sys.stderr, flush=True)
         out["compressed_orders"] = run_orders(C, torch, ctx)
+        out["hypersingular"] = run_hypersingular(C, torch, ctx, wl)
         out["batch48"] = run_batch48(C, torch, ctx)
         print("batch48 done", file=sys.stderr, flush=True)
         out["serving"] = run_serving(C, torch, ctx, args.serve_rate, args.serve_seconds,

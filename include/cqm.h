@@ -368,6 +368,24 @@ int cqm_apply_V(cqm_problem_t p, int32_t l0, int32_t nl, int32_t precision,
 int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, int32_t adjoint, const void* x, void* y,
                 hipStream_t stream);
 
+/* y_l = D(s_l) x_l for l = l0 .. l0+nl-1: the Galerkin matrices of the
+ * hypersingular operator of Section 2.2 (eq. wavebio) on the continuous
+ * piecewise-linear space S_h^1 of Section 3.2, D_l[p,j] = <phi_p, D(s_l) phi_j>
+ * over the hat functions of the mesh vertices.  The entries are those of the
+ * integration by parts on the closed surface,
+ *   int int G [curl phi_j(y) . curl phi_p(x) + s^2 n_x.n_y phi_j(y) phi_p(x)],
+ * G = exp(-s r)/(4 pi r), the sign with which D_l is elliptic (Section 3.1);
+ * pairs of triangles sharing a vertex take the static part 1/(4 pi r) by
+ * Sauter-Schwab quadrature (q_duffy points per axis), once per mesh, the
+ * rest by the 6-point rule; the far field matrix-free.  FP64.
+ * x, y: device complex128 arrays nl x nv (vertex order of the mesh given to
+ * cqm_problem_create; caller-owned, must not overlap).  Needs a problem
+ * created with formulation = CQM_FORMULATION_DIRECT (the workspace holds the
+ * product's per-triangle sources and partial sums), else CQM_EINVAL;
+ * CQM_EINVAL for a frequency range outside the solved band; CQM_ENOMEM
+ * without a workspace. */
+int cqm_apply_D(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y, hipStream_t stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, serving
  * loops or harnesses that forbid hipMalloc): cqm_apply_V of the matrix-free
  * plain form (CQM_FORM_MATRIX_FREE, plain modes) with no allocation.  The

@@ -28,7 +28,8 @@ PROBENAME = "libcqm_probe.so"
 # Per-file flags: the near-field entries (largest of every row, amplified by
 # rho^-N in the time domain) and the double-layer operator are computed
 # without fused multiply-adds.
-FILE_FLAGS = {"k_near.hip": ["-ffp-contract=off"], "k_dlayer.hip": ["-ffp-contract=off"]}
+FILE_FLAGS = {"k_near.hip": ["-ffp-contract=off"], "k_dlayer.hip": ["-ffp-contract=off"],
+              "k_hsing.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):

@@ -22,8 +22,8 @@ __all__ = [
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
     "cqm_solve_marching", "CQM_FORMULATION_INDIRECT", "CQM_FORMULATION_DIRECT",
-    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_apply_K", "cqm_near_entries",
-    "cqm_operator_stats",
+    "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_apply_K", "cqm_apply_D",
+    "cqm_near_entries", "cqm_operator_stats",
     "cqm_server_opts", "cqm_request", "cqm_server_stats_t", "cqm_server_default_options",
     "cqm_server_create", "cqm_server_submit", "cqm_server_poll", "cqm_server_drain",
     "cqm_server_stats", "cqm_server_destroy", "EXPORTED_SYMBOLS",
@@ -43,7 +43,7 @@ EXPORTED_SYMBOLS = [
     "cqm_problem_create", "cqm_problem_destroy", "cqm_workspace_size", "cqm_set_workspace",
     "cqm_set_plane_wave", "cqm_set_dirichlet_samples", "cqm_solve", "cqm_solve_batch",
     "cqm_solve_marching", "cqm_frequencies", "cqm_apply_V", "cqm_apply_V_noalloc", "cqm_apply_K",
-    "cqm_near_entries", "cqm_operator_stats",
+    "cqm_apply_D", "cqm_near_entries", "cqm_operator_stats",
     "cqm_server_default_options", "cqm_server_create", "cqm_server_submit", "cqm_server_poll",
     "cqm_server_drain", "cqm_server_stats", "cqm_server_destroy",
 ]
@@ -157,6 +157,7 @@ def load_library():
         "cqm_apply_V": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_apply_V_noalloc": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
         "cqm_apply_K": (ctypes.c_int, [P, I32, I32, I32, P, P, P]),
+        "cqm_apply_D": (ctypes.c_int, [P, I32, I32, P, P, P]),
         "cqm_near_entries": (ctypes.c_int, [P, ctypes.POINTER(I64), P, P, P]),
         "cqm_operator_stats": (ctypes.c_int, [P, ctypes.POINTER(cqm_diag)]),
         "cqm_server_default_options": (ctypes.c_int, [ctypes.POINTER(cqm_server_opts)]),
@@ -289,6 +290,11 @@ def cqm_apply_V_noalloc(p, l0, nl, precision, x_ptr, y_ptr, stream=0):
 def cqm_apply_K(p, l0, nl, x_ptr, y_ptr, stream=0, adjoint=0):
     return _check(load_library().cqm_apply_K(p, l0, nl, int(adjoint), ctypes.c_void_p(x_ptr),
                                              ctypes.c_void_p(y_ptr), ctypes.c_void_p(stream)))
+
+
+def cqm_apply_D(p, l0, nl, x_ptr, y_ptr, stream=0):
+    return _check(load_library().cqm_apply_D(p, l0, nl, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr),
+                                             ctypes.c_void_p(stream)))
 
 
 def cqm_near_entries(p, with_static=True):

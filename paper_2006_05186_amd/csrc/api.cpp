@@ -264,7 +264,8 @@ int cqm_problem_destroy(cqm_problem_t p) {
                   p->dev.near_rowptr, p->dev.near_col, p->dev.near_row, p->dev.near_kind, p->dev.near_vtx,
                   p->dev.near_static, p->dev.gl, p->dev.s, p->dev.tw_fwd, p->dev.tw_inv,
                   p->dev.rho_pow, p->dev.rho_ipow, p->dev.ea64, p->dev.pb64, p->dev.ea64u, p->dev.pb64u, p->dev.ftab, p->dev.ea32,
-                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box, p->dev.nrm64, p->dev.nearK_static, p->dev.near_tpos};
+                  p->dev.pb32, p->dev.tile_gap, p->dev.sub_box, p->dev.nrm64, p->dev.nearK_static, p->dev.near_tpos,
+                  p->dev.nearD_static, p->dev.v2t_ptr, p->dev.v2t};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -427,6 +428,32 @@ int cqm_apply_K(cqm_problem_t p, int32_t l0, int32_t nl, int32_t adjoint, const 
     launch_apply_K(*p, l0, nl, (const cf64*)x, M, nullptr, 0.0, (cf64*)y, M,
                    reinterpret_cast<const cf64*>(p->ws + p->lay.nearK),
                    reinterpret_cast<cf64*>(p->ws + p->lay.kpart), adjoint != 0, stream);
+    return CQM_OK;
+  });
+}
+
+int cqm_apply_D(cqm_problem_t p, int32_t l0, int32_t nl, const void* x, void* y, hipStream_t stream) {
+  return guarded([&] {
+    require(p && x && y, CQM_EINVAL, "NULL argument");
+    require(p->opt.formulation == CQM_FORMULATION_DIRECT, CQM_EINVAL,
+            "create the problem with formulation = CQM_FORMULATION_DIRECT");
+    require(l0 >= 0 && nl >= 1 && l0 + nl <= p->Fsys, CQM_EINVAL, "frequency range outside the solved band");
+    require(p->ws != nullptr && p->ws_bytes >= p->lay.total, CQM_ENOMEM, "workspace missing");
+    CQM_HIP(hipSetDevice(p->ctx->device));
+    // static parts, once per mesh: the single layer's (curl term) and the
+    // weighted ones (s^2 term)
+    if (!p->static_ready) {
+      launch_near_static(*p, stream);
+      p->static_ready = true;
+    }
+    if (!p->nearD_static_ready) {
+      launch_nearD_static(*p, stream);
+      p->nearD_static_ready = true;
+    }
+    launch_apply_D(*p, l0, nl, (const cf64*)x, p->nv, (cf64*)y, p->nv,
+                   reinterpret_cast<cf64*>(p->ws + p->lay.dsrc),
+                   reinterpret_cast<cf64*>(p->ws + p->lay.dpart),
+                   reinterpret_cast<cf64*>(p->ws + p->lay.dz), stream);
     return CQM_OK;
   });
 }

@@ -242,6 +242,9 @@ struct MeshDev {
   // triangles (vertex order), the static near part of K (nnz)
   double4* nrm64 = nullptr;
   double* nearK_static = nullptr;
+  double* nearD_static = nullptr;  // nnz*9: hypersingular static weights [a][b] (direct formulation)
+  int32_t* v2t_ptr = nullptr;      // nv+1: vertex -> (triangle, local vertex) slots
+  int32_t* v2t = nullptr;          // 3M slots 3*i + a, ascending per vertex
   int32_t* near_tpos = nullptr;   // nnz: position of pair (j, i) for pair (i, j)
 };
 // Frequency-dependent cut-off radii of a system: tiles whose box gap is at
@@ -258,7 +261,7 @@ struct Layout {
   size_t mfpart = 0;
   // direct formulation: near values of K (nnz x Fsys), the coefficient
   // vectors it is applied to (Fsys x M) and its split-K partial sums
-  size_t nearK = 0, kin = 0, kpart = 0;
+  size_t nearK = 0, kin = 0, kpart = 0, dsrc = 0, dz = 0, dpart = 0;
   // time marching (cqm_options.marching): weights, What_0 block inverses and
   // their complex staging, product partials, CG vectors and partial sums
   size_t mw = 0, mpinv = 0, mdiag = 0, mpart = 0, mvec = 0;
@@ -334,7 +337,7 @@ struct Problem {
   size_t ws_bytes = 0;
   Layout lay;
   bool static_ready = false, near_ready = false, dense_ready = false;
-  bool nearK_static_ready = false, nearK_ready = false;
+  bool nearK_static_ready = false, nearK_ready = false, nearD_static_ready = false;
   H2Operator* h2 = nullptr;
   cqm_diag last{};
   int64_t far_units = 0;
@@ -390,6 +393,15 @@ void launch_apply_K(const Problem& p, int l0, int nsys, const cf64* x, int64_t x
                     bool adjoint, hipStream_t s);
 void launch_div_area(const Problem& p, int nsys, const cf64* g, int64_t gs, cf64* c, hipStream_t s);
 size_t dl_partial_bytes(int M, int Fs);
+// hypersingular operator (k_hsing.hip): the barycentric coordinates of the
+// 6-point rule's points, passed by value to the kernels
+struct HsRule {
+  double bary[6][3];
+};
+size_t hs_partial_bytes(int M, int Fs);
+void launch_nearD_static(const Problem& p, hipStream_t s);
+void launch_apply_D(const Problem& p, int l0, int nsys, const cf64* x, int64_t xs, cf64* y,
+                    int64_t ys, cf64* src, cf64* partial, cf64* z, hipStream_t s);
 int far_partial_slots(int M, int nsys, int precision);  // split-K slots of the far product (any shape)
 // Allocation-free far product (matrix-free form): partial sums in the fixed
 // device array of kFarScratchBytes (k_far.hip), whose address is looked up

@@ -130,6 +130,19 @@ void upload_problem(Problem& p) {
   }
   CQM_HIP(hipMalloc(&p.dev.near_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
   CQM_HIP(hipMalloc(&p.dev.nearK_static, sizeof(double) * std::max<size_t>(1, p.col.size())));
+  if (p.opt.formulation == CQM_FORMULATION_DIRECT)
+    CQM_HIP(hipMalloc(&p.dev.nearD_static, sizeof(double) * 9 * std::max<size_t>(1, p.col.size())));
+  {
+    // vertex -> (triangle, local vertex) slots, ascending: the fixed order
+    // in which the hypersingular product sums a vertex's contributions
+    std::vector<int32_t> ptr(p.nv + 1, 0), slot(3 * M);
+    for (int64_t k = 0; k < 3 * M; ++k) ++ptr[p.tris[k] + 1];
+    for (int64_t v = 0; v < p.nv; ++v) ptr[v + 1] += ptr[v];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t k = 0; k < 3 * M; ++k) slot[fill[p.tris[k]]++] = (int32_t)k;
+    p.dev.v2t_ptr = upload(ptr);
+    p.dev.v2t = upload(slot);
+  }
   std::vector<double> gx, gw;
   gauss_legendre01(p.opt.q_duffy, gx, gw);
   std::vector<double> gl(gx);
@@ -324,6 +337,10 @@ void compute_layout(Problem& p) {
     L.nearK = take(sizeof(cf64) * Fs * std::max<size_t>(1, p.col.size()));
     L.kin = take(sizeof(cf64) * Fs * M);
     L.kpart = take(dl_partial_bytes((int)M, (int)Fs));
+    // hypersingular product: per-triangle sources, partial sums, slots
+    L.dsrc = take(sizeof(cf64) * 9 * Fs * M);
+    L.dpart = take(hs_partial_bytes((int)M, (int)Fs));
+    L.dz = take(sizeof(cf64) * 3 * Fs * M);
   }
   L.total = off;
   p.lay = L;

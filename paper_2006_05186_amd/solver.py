@@ -14,6 +14,7 @@ class Problem:
         import torch
         self.torch = torch
         self.M = int(np.asarray(tris).shape[0])
+        self.nv = int(np.asarray(vertices).shape[0])
         self.N = int(N)
         self.options = C.cqm_default_options(**opts)
         self.handle = C.cqm_problem_create(ctx, vertices, tris, N, T, self.options)
@@ -69,6 +70,18 @@ class Problem:
         y = torch.empty_like(x)
         C.cqm_apply_K(self.handle, l0, x.shape[0], x.data_ptr(), y.data_ptr(),
                       torch.cuda.current_stream().cuda_stream, adjoint)
+        return y
+
+    def apply_D(self, x, l0=0):
+        """x: complex torch tensor (nl, nv) of vertex coefficients on device;
+        returns D(s_l) x_l, the hypersingular operator on the piecewise-linear
+        space (FP64; needs formulation=CQM_FORMULATION_DIRECT at
+        construction)."""
+        torch = self.torch
+        x = x.to(torch.complex128).contiguous()
+        y = torch.empty_like(x)
+        C.cqm_apply_D(self.handle, l0, x.shape[0], x.data_ptr(), y.data_ptr(),
+                      torch.cuda.current_stream().cuda_stream)
         return y
 
     def close(self):
