@@ -36,7 +36,7 @@ namespace {
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr int kHsTgt = 64;  // target triangles (threads) per workgroup
 constexpr int kHsTs = 16;   // source triangles per LDS tile
-constexpr int kHsFT = 2;    // frequencies per workgroup
+constexpr int kHsFT = 3;    // frequencies per workgroup
 constexpr int kHsWaves = 4096;
 
 struct w3 {
@@ -200,9 +200,10 @@ __global__ __launch_bounds__(256) void k_hs_source(const cf64* __restrict__ x, i
 
 // Far pairs, matrix-free: one thread per target triangle and kHsFT
 // frequencies; source triangles through LDS; the source range split over
-// blockIdx.z.  Per target: A = sum_t V_tau,t u_t (curl term) and, per target
-// point k, m_k = sum_t (n_tau.n_t) sum_l G(x_k - y_l) g_t,l; the partial
-// result per local vertex a is c_a.A + s^2 sum_k W_k lambda_a(k) m_k.
+// blockIdx.z.  Per target: A = sum_t V_tau,t u_t (curl term) and, per local
+// vertex a, Z_a = sum_k W_k lambda_a(k) sum_t (n_tau.n_t) sum_l G(x_k - y_l)
+// g_t,l (mass term, folded over the target points as they are visited); the
+// partial result per local vertex a is c_a.A + s^2 Z_a.
 __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ pts,
                                                    const int4* __restrict__ vid,
                                                    const double4* __restrict__ nrm,
@@ -226,16 +227,14 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
   const int4 tv = vid[ic];
   const double4 ni = nrm[ic];
   double sr[kHsFT], si[kHsFT];
-  double Are[kHsFT][3], Aim[kHsFT][3], mre[kHsFT][kQ], mim[kHsFT][kQ];
+  double Are[kHsFT][3], Aim[kHsFT][3], Zre[kHsFT][3], Zim[kHsFT][3];
 #pragma unroll
   for (int l = 0; l < kHsFT; ++l) {
     const cf64 sv = l < nl ? sfreq[l0 + lt + l] : cf64{0.0, 0.0};
     sr[l] = sv.re;
     si[l] = sv.im;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) Are[l][d] = Aim[l][d] = 0.0;
-#pragma unroll
-    for (int k = 0; k < kQ; ++k) mre[l][k] = mim[l][k] = 0.0;
+    for (int d = 0; d < 3; ++d) Are[l][d] = Aim[l][d] = Zre[l][d] = Zim[l][d] = 0.0;
   }
   __shared__ double4 sp[kHsTs * kQ];
   __shared__ double4 sn[kHsTs];
@@ -275,8 +274,9 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
         for (int b = 0; b < kQ; ++b) {
           const double4 q = sp[jj * kQ + b];
           const double dx = tx[a] - q.x, dy = ty[a] - q.y, dz = tz[a] - q.z;
-          const double r = sqrt(dx * dx + dy * dy + dz * dz);
-          const double ir = 1.0 / r;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double ir = rsqrt(r2);  // far pairs: r > 0
+          const double r = r2 * ir;
 #pragma unroll
           for (int l = 0; l < kHsFT; ++l) {
             double s, c;
@@ -290,20 +290,20 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
             gim[l] += Gr * g.im + Gi * g.re;
           }
         }
+        const double twa = tw[a];
+        const double f0 = twa * nn * rule.bary[a][0], f1 = twa * nn * rule.bary[a][1],
+                     f2 = twa * nn * rule.bary[a][2];
 #pragma unroll
         for (int l = 0; l < kHsFT; ++l) {
-          vre[l] += tw[a] * hre[l];
-          vim[l] += tw[a] * him[l];
+          vre[l] += twa * hre[l];
+          vim[l] += twa * him[l];
+          Zre[l][0] += f0 * gre[l];
+          Zim[l][0] += f0 * gim[l];
+          Zre[l][1] += f1 * gre[l];
+          Zim[l][1] += f1 * gim[l];
+          Zre[l][2] += f2 * gre[l];
+          Zim[l][2] += f2 * gim[l];
         }
-        // m_a += nn * g  (a runtime index into a register array: unrolled select)
-#pragma unroll
-        for (int k = 0; k < kQ; ++k)
-          if (k == a)
-#pragma unroll
-            for (int l = 0; l < kHsFT; ++l) {
-              mre[l][k] += nn * gre[l];
-              mim[l][k] += nn * gim[l];
-            }
       }
 #pragma unroll
       for (int l = 0; l < kHsFT; ++l)
@@ -328,13 +328,7 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
         const double cx = e[a].x * inv, cy = e[a].y * inv, cz = e[a].z * inv;
         double re = cx * Are[l][0] + cy * Are[l][1] + cz * Are[l][2];
         double im = cx * Aim[l][0] + cy * Aim[l][1] + cz * Aim[l][2];
-        double wr = 0.0, wi = 0.0;
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) {
-          const double f = tw[k] * rule.bary[k][a];
-          wr += f * mre[l][k];
-          wi += f * mim[l][k];
-        }
+        const double wr = Zre[l][a], wi = Zim[l][a];
         re += s2r * wr - s2i * wi;
         im += s2r * wi + s2i * wr;
         o[a] = cf64{re * kInv4Pi, im * kInv4Pi};
