@@ -210,7 +210,10 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
                                                    const double* __restrict__ verts, int M,
                                                    const cf64* __restrict__ sfreq, int l0, int nsys,
                                                    const cf64* __restrict__ src, HsRule rule,
-                                                   cf64* __restrict__ partial, int chunk) {
+                                                   cf64* __restrict__ partial, int chunk,
+                                                   const double* __restrict__ ftab,
+                                                   const double* __restrict__ eau,
+                                                   const double* __restrict__ pbu) {
   const int lt = blockIdx.y * kHsFT;
   const int nl = min(kHsFT, nsys - lt);
   const int i = blockIdx.x * kHsTgt + threadIdx.x;
@@ -226,13 +229,14 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
   }
   const int4 tv = vid[ic];
   const double4 ni = nrm[ic];
-  double sr[kHsFT], si[kHsFT];
+  // -Re(s) and Im(s) in the steps of the exponential and the fine
+  // sine/cosine tables (staged in LDS below)
+  double fe[kHsFT], fp[kHsFT];
   double Are[kHsFT][3], Aim[kHsFT][3], Zre[kHsFT][3], Zim[kHsFT][3];
 #pragma unroll
   for (int l = 0; l < kHsFT; ++l) {
-    const cf64 sv = l < nl ? sfreq[l0 + lt + l] : cf64{0.0, 0.0};
-    sr[l] = sv.re;
-    si[l] = sv.im;
+    fe[l] = l < nl ? eau[l0 + lt + l] : 0.0;
+    fp[l] = l < nl ? pbu[l0 + lt + l] : 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) Are[l][d] = Aim[l][d] = Zre[l][d] = Zim[l][d] = 0.0;
   }
@@ -240,6 +244,9 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
   __shared__ double4 sn[kHsTs];
   __shared__ int4 sv[kHsTs];
   __shared__ cf64 sx[kHsTs * kHsFT * 9];
+  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
+  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kHsTgt)
+    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
   const int j0 = blockIdx.z * chunk;
   const int j1 = min(M, j0 + chunk);
   for (int jt = j0; jt < j1; jt += kHsTs) {
@@ -279,10 +286,10 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
           const double r = r2 * ir;
 #pragma unroll
           for (int l = 0; l < kHsFT; ++l) {
-            double s, c;
-            sincos_bounded(si[l] * r, &s, &c);
-            const double e = ir * exp_nonpos(-sr[l] * r);
-            const double Gr = e * c, Gi = -e * s;  // exp(-s r)/r
+            double sn, c;
+            sincos_tabu512(fp[l] * r, stab + 256, &sn, &c);
+            const double e = ir * exp_tabu(fmax(fe[l] * r, -261474.0), stab);
+            const double Gr = e * c, Gi = -e * sn;  // exp(-s r)/r
             hre[l] += Gr * q.w;
             him[l] += Gi * q.w;
             const cf64 g = xs[l * 9 + 3 + b];
@@ -322,7 +329,8 @@ __global__ __launch_bounds__(kHsTgt) void k_hs_far(const double4* __restrict__ p
 #pragma unroll
     for (int l = 0; l < kHsFT; ++l) {
       if (l >= nl) continue;
-      const double s2r = sr[l] * sr[l] - si[l] * si[l], s2i = 2.0 * sr[l] * si[l];
+      const cf64 sv = sfreq[l0 + lt + l];
+      const double s2r = sv.re * sv.re - sv.im * sv.im, s2i = 2.0 * sv.re * sv.im;
       cf64* o = partial + (((int64_t)blockIdx.z * nsys + lt + l) * M + i) * 3;
       for (int a = 0; a < 3; ++a) {
         const double cx = e[a].x * inv, cy = e[a].y * inv, cz = e[a].z * inv;
@@ -498,7 +506,8 @@ void launch_apply_D(const Problem& p, int l0, int nsys, const cf64* x, int64_t x
   const int S = hs_splits(M, nsys, &chunk);
   dim3 grid((M + kHsTgt - 1) / kHsTgt, (nsys + kHsFT - 1) / kHsFT, S);
   hipLaunchKernelGGL(k_hs_far, grid, dim3(kHsTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64,
-                     p.dev.verts, M, p.dev.s, l0, nsys, src, rule, partial, chunk);
+                     p.dev.verts, M, p.dev.s, l0, nsys, src, rule, partial, chunk, p.dev.ftab,
+                     p.dev.ea64u, p.dev.pb64u);
   CQM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_hs_near, dim3((M + 127) / 128, nsys), dim3(128), 0, s, partial, S, nsys, M,
                      p.dev.pts64, p.dev.vid, p.dev.nrm64, p.dev.verts, p.dev.near_rowptr,
