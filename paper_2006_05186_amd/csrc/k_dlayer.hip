@@ -187,7 +187,10 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
                                                    const double4* __restrict__ nrm, int M,
                                                    const cf64* __restrict__ sfreq, int l0,
                                                    int nsys, const cf64* __restrict__ x, int64_t xs,
-                                                   cf64* __restrict__ partial, int chunk) {
+                                                   cf64* __restrict__ partial, int chunk,
+                                                   const double* __restrict__ ftab,
+                                                   const double* __restrict__ eau,
+                                                   const double* __restrict__ pbu) {
   const int lt = blockIdx.y * kDlFT;
   const int nl = min(kDlFT, nsys - lt);
   const int i = blockIdx.x * kDlTgt + threadIdx.x;
@@ -203,12 +206,16 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
   }
   const int4 tv = vid[ic];
   const double4 ni = nrm[ic];
-  double sr[kDlFT], si[kDlFT], are[kDlFT], aim[kDlFT];
+  // s_l itself (for 1 + s r) and -Re(s), Im(s) in the steps of the
+  // exponential and the fine sine/cosine tables (staged in LDS below)
+  double sr[kDlFT], si[kDlFT], fe[kDlFT], fp[kDlFT], are[kDlFT], aim[kDlFT];
 #pragma unroll
   for (int l = 0; l < kDlFT; ++l) {
     const cf64 sv = l < nl ? sfreq[l0 + lt + l] : cf64{0.0, 0.0};
     sr[l] = sv.re;
     si[l] = sv.im;
+    fe[l] = l < nl ? eau[l0 + lt + l] : 0.0;
+    fp[l] = l < nl ? pbu[l0 + lt + l] : 0.0;
     are[l] = 0.0;
     aim[l] = 0.0;
   }
@@ -216,6 +223,9 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
   __shared__ double4 sn[kDlTs];
   __shared__ int4 sv[kDlTs];
   __shared__ cf64 sx[kDlTs * kDlFT];
+  __shared__ __align__(16) double stab[256 + kFp64Tab512Len];
+  for (int k = threadIdx.x; k < 256 + kFp64Tab512Len; k += kDlTgt)
+    stab[k] = ftab[k < 256 ? k : kFp64Tab512Off + (k - 256)];
   const int j0 = blockIdx.z * chunk;
   const int j1 = min(M, j0 + chunk);
   for (int jt = j0; jt < j1; jt += kDlTs) {
@@ -250,8 +260,8 @@ __global__ __launch_bounds__(kDlTgt) void k_dl_far(const double4* __restrict__ p
 #pragma unroll
           for (int l = 0; l < kDlFT; ++l) {
             double s, c;
-            sincos_bounded(si[l] * r, &s, &c);
-            const double e = g * exp_nonpos(-sr[l] * r);
+            sincos_tabu512(fp[l] * r, stab + 256, &s, &c);
+            const double e = g * exp_tabu(fmax(fe[l] * r, -261474.0), stab);
             // (1 + s r) exp(-s r) = e-scaled ((1 + sr r) + i si r)(c - i s)
             const double a1 = 1.0 + sr[l] * r, b1 = si[l] * r;
             vre[l] += e * (a1 * c + b1 * s);
@@ -365,10 +375,12 @@ void launch_apply_K(const Problem& p, int l0, int nsys, const cf64* x, int64_t x
   dim3 grid((M + kDlTgt - 1) / kDlTgt, (nsys + kDlFT - 1) / kDlFT, S);
   if (adjoint)
     hipLaunchKernelGGL(k_dl_far<true>, grid, dim3(kDlTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64,
-                       M, p.dev.s, l0, nsys, x, xs, partial, chunk);
+                       M, p.dev.s, l0, nsys, x, xs, partial, chunk, p.dev.ftab, p.dev.ea64u,
+                       p.dev.pb64u);
   else
     hipLaunchKernelGGL(k_dl_far<false>, grid, dim3(kDlTgt), 0, s, p.dev.pts64, p.dev.vid, p.dev.nrm64,
-                       M, p.dev.s, l0, nsys, x, xs, partial, chunk);
+                       M, p.dev.s, l0, nsys, x, xs, partial, chunk, p.dev.ftab, p.dev.ea64u,
+                       p.dev.pb64u);
   CQM_HIP(hipGetLastError());
   const int64_t nnz = (int64_t)p.col.size();
   hipLaunchKernelGGL(k_dl_reduce_near, dim3((M + 255) / 256, nsys), dim3(256), 0, s, partial, S,
