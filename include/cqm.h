@@ -13,6 +13,10 @@
  *     time steps by scaled DFTs                       (remark ending Section 6.2)
  *   - optional compression: H2 in space (Section 4, Algorithm 1) and
  *     multivariate ACA across frequencies (Section 5, Algorithms 2 and 3).
+ *   - the other operators of the Calderon system (Section 2.2, eq. wavebio)
+ *     per frequency: the double layer K and its adjoint K' on
+ *     piecewise-constant elements, the hypersingular D on piecewise-linear
+ *     ones, and the direct Dirichlet formulation (eq. wavegalform).
  *
  * Conventions
  *   - Every function returns int: 0 on success or a negative CQM_E* code.

@@ -1,4 +1,5 @@
-"""Plain FP64 CPU oracle for the all-at-once CQM Galerkin BEM single-layer solve.
+"""Plain FP64 CPU oracle for the all-at-once CQM Galerkin BEM single-layer solve,
+its compressed form and time marching, and the Calderon operators K, K' and D.
 
 TEST INFRASTRUCTURE ONLY. This package exists to check the GPU library. Only
 the test suite, the smoke check and the CPU-baseline leg of the benchmark may
