@@ -75,7 +75,8 @@ extern "C" {
 #define CQM_FORM_MATRIX_FREE 0 /* kernel evaluated on the fly in every product */
 #define CQM_FORM_DENSE 1       /* all V(s_l) assembled once in HBM           */
 
-/* Frequency band handled by MACA (conjugate symmetry, see DESIGN). */
+/* Frequency band handled by MACA (V(conj s) = conj V(s): the half band
+   and conjugation give the rest). */
 #define CQM_BAND_FULL 0 /* all N+1 frequencies compressed and solved */
 #define CQM_BAND_HALF 1 /* l = 0..N/2 solved, the rest by conjugation */
 
