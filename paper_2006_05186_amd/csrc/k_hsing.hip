@@ -34,7 +34,7 @@ namespace cqm {
 
 namespace {
 constexpr double kInv4Pi = 0.07957747154594767;
-constexpr int kHsTgt = 64;  // target triangles (threads) per workgroup
+constexpr int kHsTgt = 128; // target triangles (threads) per workgroup
 constexpr int kHsTs = 16;   // source triangles per LDS tile
 constexpr int kHsFT = 3;    // frequencies per workgroup
 constexpr int kHsWaves = 4096;
